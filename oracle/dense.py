@@ -1,0 +1,169 @@
+"""Python side of the dense FP64 oracle (ctypes wrapper around dense.c).
+
+TEST INFRASTRUCTURE ONLY: only tests, the smoke check and the benchmark's CPU
+baseline leg use this module.  It shares no code with the GPU library.
+
+The discretisation (Section 2.1 "Numerics"; operator form in Appendix A):
+forward-Euler upwind streaming, then the backward-Euler operator-split source
+update with zero scattering, density 1 and fixed temperature,
+I^{m+1} = (I* + c dt kappa eps) / (1 + c dt kappa).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+from . import planck
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO = os.path.join(HERE, "_dense.so")
+SRC = os.path.join(HERE, "dense.c")
+
+FACE_VACUUM, FACE_INFLOW_PLANCK, FACE_PERIODIC, FACE_INFLOW_VALUES = 0, 1, 2, 3
+
+
+def build(force: bool = False) -> str:
+    """Compile dense.c with gcc + OpenMP into oracle/_dense.so."""
+    if force or not os.path.exists(SO) or os.path.getmtime(SO) < os.path.getmtime(SRC):
+        cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", SRC, "-o", SO + ".tmp", "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(SO + ".tmp", SO)
+    return SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO):
+            build()
+        L = ctypes.CDLL(SO)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.oracle_dense_march.argtypes = [
+            ctypes.c_int, ip, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ip, dp,
+            ctypes.c_double, ctypes.c_double, dp, dp, ctypes.c_int, ctypes.c_int]
+        L.oracle_dense_march.restype = ctypes.c_int
+        L.oracle_dense_transport.argtypes = [
+            ctypes.c_int, ip, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, ip, dp,
+            ctypes.c_double, ctypes.c_double, dp, dp, ctypes.c_int]
+        L.oracle_dense_transport.restype = ctypes.c_int
+        L.oracle_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+# ---------------------------------------------------------------------------
+# problem-derived quantities (independent of the GPU library's own setup)
+# ---------------------------------------------------------------------------
+
+def time_step(prob) -> float:
+    """dt = CFL / (c * sum_d 1/dx_d) over the active axes."""
+    inv = 0.0
+    for d in range(prob.dim):
+        inv += prob.n_cells[d] / prob.extent[d]
+    return prob.cfl / (prob.c * inv)
+
+
+def kappa_field(prob) -> np.ndarray:
+    """(N_X, N_nu) opacity kappa0(x) * scale(g)."""
+    return np.outer(np.asarray(prob.kappa0, float), np.asarray(prob.kappa_scale, float))
+
+
+def emission(prob) -> np.ndarray:
+    return planck.emission_field(prob.edges, prob.T_cell)
+
+
+def ghost_values(prob) -> np.ndarray:
+    """(6, N_nu) isotropic ghost intensities of each face (zero where unused)."""
+    G = prob.n_groups
+    out = np.zeros((6, G))
+    for f in range(6):
+        kind = prob.bc[f]
+        if kind == FACE_INFLOW_PLANCK:
+            out[f] = planck.group_emission(prob.edges, float(prob.bc_T[f]))
+        elif kind == FACE_INFLOW_VALUES:
+            out[f] = np.asarray(prob.bc_values)[f]
+    return out
+
+
+def initial_dense(prob) -> np.ndarray:
+    """Isotropic Planck state at the medium temperature, shape (N_X*N_nu, N_theta, N_phi)."""
+    eps = emission(prob).reshape(-1)
+    return np.broadcast_to(eps[:, None, None], (prob.M, prob.n_theta, prob.n_phi)).copy()
+
+
+def march(prob, I0: np.ndarray, n_steps: int, n_threads: int = 0, dt: float = None) -> np.ndarray:
+    """n_steps full steps (transport + source) of the dense FP64 scheme."""
+    I = np.ascontiguousarray(I0, dtype=np.float64).copy()
+    work = np.empty_like(I)
+    nc = np.ascontiguousarray(np.asarray(prob.n_cells, dtype=np.int32))
+    ext = np.ascontiguousarray(np.asarray(prob.extent, dtype=np.float64))
+    bc = np.ascontiguousarray(np.asarray(prob.bc, dtype=np.int32))
+    ghost = np.ascontiguousarray(ghost_values(prob))
+    kap = np.ascontiguousarray(kappa_field(prob))
+    eps = np.ascontiguousarray(emission(prob))
+    mu = np.ascontiguousarray(np.asarray(prob.mu, float))
+    phi = np.ascontiguousarray(np.asarray(prob.phi, float))
+    if dt is None:
+        dt = time_step(prob)
+    rc = lib().oracle_dense_march(prob.dim, _ip(nc), _dp(ext), prob.n_groups, prob.n_theta,
+                                  prob.n_phi, _dp(mu), _dp(phi), _dp(kap), _dp(eps), _ip(bc),
+                                  _dp(ghost), float(prob.c), float(dt), _dp(I), _dp(work),
+                                  int(n_steps), int(n_threads))
+    if rc != 0:
+        raise RuntimeError("oracle_dense_march failed")
+    return I
+
+
+def transport(prob, I: np.ndarray, n_threads: int = 0) -> np.ndarray:
+    """Transport half-step only (no source update)."""
+    I = np.ascontiguousarray(I, dtype=np.float64)
+    out = np.empty_like(I)
+    nc = np.ascontiguousarray(np.asarray(prob.n_cells, dtype=np.int32))
+    ext = np.ascontiguousarray(np.asarray(prob.extent, dtype=np.float64))
+    bc = np.ascontiguousarray(np.asarray(prob.bc, dtype=np.int32))
+    ghost = np.ascontiguousarray(ghost_values(prob))
+    mu = np.ascontiguousarray(np.asarray(prob.mu, float))
+    phi = np.ascontiguousarray(np.asarray(prob.phi, float))
+    rc = lib().oracle_dense_transport(
+        prob.dim, _ip(nc), _dp(ext), prob.n_groups, prob.n_theta, prob.n_phi, _dp(mu), _dp(phi),
+        _ip(bc), _dp(ghost), float(prob.c), float(time_step(prob)), _dp(I), _dp(out),
+        int(n_threads))
+    if rc != 0:
+        raise RuntimeError("oracle_dense_transport failed")
+    return out
+
+
+def source(prob, I: np.ndarray) -> np.ndarray:
+    """Implicit absorption/emission update at fixed T (scattering zero, rho = 1)."""
+    dt = time_step(prob)
+    kap = kappa_field(prob).reshape(-1)
+    eps = emission(prob).reshape(-1)
+    a = prob.c * dt * kap
+    return (I + (a * eps)[:, None, None]) / (1.0 + a)[:, None, None]
+
+
+def energy(prob, I: np.ndarray) -> float:
+    """Quadrature-weighted radiation content sum_cells dV sum_g sum_lp w_l w_p I."""
+    dV = float(np.prod([prob.extent[d] / prob.n_cells[d] for d in range(prob.dim)]))
+    w = np.outer(prob.w_theta, prob.w_phi)
+    return dV * float(np.einsum("klp,lp->", I, w))
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())

@@ -1,0 +1,269 @@
+"""Tensor-train (TT) algebra of the multigroup transport step, in plain numpy FP64.
+
+TEST INFRASTRUCTURE ONLY: the oracle the GPU path is compared with.  It shares
+no code with the GPU library.
+
+Format (Section 3.1, the merged spatio-spectral decomposition):
+    I[k, l, p] = sum_{a,b} Z[k, a] Theta[a, l, b] Phi[b, p],
+with k = cell*N_nu + g, Z of shape (N_X N_nu, r1), Theta (r1, N_theta, r2),
+Phi (r2, N_phi).
+
+Transport operator (Appendix A, "Value of n"): the upwind update is the
+identity plus n = 2 d_X rank-1 TT operators, one per (axis, sign of n_d).  The
+operator for (d, +) acts on Z as -lambda_d (I - O_{d-}) and multiplies the
+angular cores by the positive part of n_d; (d, -) acts as -lambda_d (O_{d+} - I)
+with the negative part.  Boundary ghost values enter as a rank-1 Dirichlet TT
+(the blue TT of the Appendix A figure), one per inflow face.  The source update
+(Section 2.1, backward Euler at fixed T, no scattering) is a Hadamard product
+with the rank-1 field d = 1/(1 + c dt kappa) plus the rank-1 emission term
+c dt kappa eps d (Section 3.1: rank-1 TT lift of spatio-spectral fields).
+
+The sum is formed explicitly: Z_new is the block row [Z, S_1 Z, ..., S_n Z,
+bc..., emission], Theta_new is block diagonal and Phi_new is stacked, so the
+ranks after the update are (n+1) r + n_bc + 1 (Appendix A, ranks of the
+green TT plus the source's rank growth).
+
+Rounding: TT-SVD rounding of Oseledets (2011), which the paper cites for its
+SVD rounding method: right-to-left orthogonalisation by QR, then a
+left-to-right sweep of truncated SVDs, each bond truncated at
+delta = tol * ||X||_F / sqrt(d - 1) with d = 3 cores.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import dense
+
+
+# ---------------------------------------------------------------------------
+# the operator terms
+# ---------------------------------------------------------------------------
+
+def direction_factors(prob):
+    """For each (axis, sign) term a pair (g[N_theta], h[N_phi]) with
+    g(l) h(p) = n_d^{+/-}(l, p), the positive / negative part of the direction
+    component.  Returned as a list of (axis, sign, g, h)."""
+    mu = np.asarray(prob.mu, float)
+    phi = np.asarray(prob.phi, float)
+    terms = []
+    if prob.dim == 1:
+        one = np.ones(prob.n_phi)
+        terms.append((0, +1, np.maximum(mu, 0.0), one))
+        terms.append((0, -1, np.minimum(mu, 0.0), one))
+        return terms
+    st = np.sqrt(np.maximum(0.0, 1.0 - mu * mu))
+    cp, sp = np.cos(phi), np.sin(phi)
+    terms.append((0, +1, st, np.maximum(cp, 0.0)))
+    terms.append((0, -1, st, np.minimum(cp, 0.0)))
+    terms.append((1, +1, st, np.maximum(sp, 0.0)))
+    terms.append((1, -1, st, np.minimum(sp, 0.0)))
+    if prob.dim == 3:
+        one = np.ones(prob.n_phi)
+        terms.append((2, +1, np.maximum(mu, 0.0), one))
+        terms.append((2, -1, np.minimum(mu, 0.0), one))
+    return terms
+
+
+def _cell_index(prob):
+    nx = int(prob.n_cells[0])
+    ny = int(prob.n_cells[1]) if prob.dim > 1 else 1
+    nz = int(prob.n_cells[2]) if prob.dim > 2 else 1
+    cell = np.arange(nx * ny * nz)
+    return np.stack([cell % nx, (cell // nx) % ny, cell // (nx * ny)], axis=1), (nx, ny, nz)
+
+
+def shift(prob, Z: np.ndarray, axis: int, s: int) -> np.ndarray:
+    """(O Z)[cell] = Z[cell + s e_axis]; zero outside the domain unless the axis is
+    periodic, in which case the index wraps."""
+    G = prob.n_groups
+    idx, N = _cell_index(prob)
+    r = Z.shape[1]
+    Zc = Z.reshape(-1, G, r)
+    j = idx.copy()
+    j[:, axis] += s
+    periodic = prob.bc[2 * axis] == dense.FACE_PERIODIC
+    inside = (j[:, axis] >= 0) & (j[:, axis] < N[axis])
+    if periodic:
+        j[:, axis] %= N[axis]
+        inside[:] = True
+    src = j[:, 0] + N[0] * (j[:, 1] + N[1] * j[:, 2])
+    out = np.zeros_like(Zc)
+    out[inside] = Zc[src[inside]]
+    return out.reshape(-1, r)
+
+
+def bc_columns(prob):
+    """Rank-1 Dirichlet terms: list of (z[M], g[N_theta], h[N_phi]) for every
+    inflow face.  Low face of axis d: value +lambda_d * ghost_g on the first cell
+    layer with the (d, +) angular factors; high face: -lambda_d * ghost_g on the
+    last layer with the (d, -) factors."""
+    dt = dense.time_step(prob)
+    ghost = dense.ghost_values(prob)
+    idx, N = _cell_index(prob)
+    terms = {(a, s): (g, h) for a, s, g, h in direction_factors(prob)}
+    G = prob.n_groups
+    cols = []
+    for face in range(2 * prob.dim):
+        kind = prob.bc[face]
+        if kind not in (dense.FACE_INFLOW_PLANCK, dense.FACE_INFLOW_VALUES):
+            continue
+        axis, high = face // 2, face % 2
+        lam = prob.c * dt / (prob.extent[axis] / prob.n_cells[axis])
+        layer = (idx[:, axis] == (N[axis] - 1 if high else 0)).astype(float)
+        sign = -1.0 if high else 1.0
+        z = (sign * lam * layer[:, None] * ghost[face][None, :]).reshape(-1)
+        g, h = terms[(axis, -1 if high else +1)]
+        cols.append((z, g, h))
+    return cols
+
+
+def n_bc(prob) -> int:
+    return sum(1 for f in range(2 * prob.dim) if prob.bc[f] in (dense.FACE_INFLOW_PLANCK,
+                                                                 dense.FACE_INFLOW_VALUES))
+
+
+def _assemble(blocksZ, blocksTh, blocksPh, n_theta):
+    """Explicit TT sum: Z concatenated, Theta block diagonal, Phi stacked."""
+    Z = np.concatenate(blocksZ, axis=1)
+    R1 = sum(t.shape[0] for t in blocksTh)
+    R2 = sum(t.shape[2] for t in blocksTh)
+    Th = np.zeros((R1, n_theta, R2))
+    a = b = 0
+    for t in blocksTh:
+        Th[a:a + t.shape[0], :, b:b + t.shape[2]] = t
+        a += t.shape[0]
+        b += t.shape[2]
+    Ph = np.concatenate(blocksPh, axis=0)
+    return Z, Th, Ph
+
+
+def apply_transport(prob, Z, Th, Ph):
+    """I* = (identity + sum of the n rank-1 upwind operators) I + Dirichlet terms."""
+    dt = dense.time_step(prob)
+    bZ, bT, bP = [Z], [Th], [Ph]
+    for axis, s, g, h in direction_factors(prob):
+        lam = prob.c * dt / (prob.extent[axis] / prob.n_cells[axis])
+        if s > 0:
+            SZ = -lam * (Z - shift(prob, Z, axis, -1))
+        else:
+            SZ = -lam * (shift(prob, Z, axis, +1) - Z)
+        bZ.append(SZ)
+        bT.append(Th * g[None, :, None])
+        bP.append(Ph * h[None, :])
+    for z, g, h in bc_columns(prob):
+        bZ.append(z[:, None])
+        bT.append(g[None, :, None].copy())
+        bP.append(h[None, :].copy())
+    return _assemble(bZ, bT, bP, prob.n_theta)
+
+
+def apply_source(prob, Z, Th, Ph):
+    """Backward-Euler absorption/emission at fixed T: d * I + c dt kappa eps d."""
+    dt = dense.time_step(prob)
+    kap = dense.kappa_field(prob).reshape(-1)
+    eps = dense.emission(prob).reshape(-1)
+    a = prob.c * dt * kap
+    d = 1.0 / (1.0 + a)
+    bZ = [Z * d[:, None], (a * eps * d)[:, None]]
+    bT = [Th, np.ones((1, prob.n_theta, 1))]
+    bP = [Ph, np.ones((1, prob.n_phi))]
+    return _assemble(bZ, bT, bP, prob.n_theta)
+
+
+def apply_step(prob, Z, Th, Ph):
+    """Transport followed by the source update, as one explicit TT sum."""
+    return apply_source(prob, *apply_transport(prob, Z, Th, Ph))
+
+
+def full(Z, Th, Ph) -> np.ndarray:
+    return np.einsum("ka,alb,bp->klp", Z, Th, Ph, optimize=True)
+
+
+def initial_tt(prob):
+    """Rank-1 isotropic Planck state at the medium temperature."""
+    eps = dense.emission(prob).reshape(-1)
+    return eps[:, None].copy(), np.ones((1, prob.n_theta, 1)), np.ones((1, prob.n_phi))
+
+
+# ---------------------------------------------------------------------------
+# TT-SVD rounding
+# ---------------------------------------------------------------------------
+
+def delta_rank(s: np.ndarray, delta: float, cap: int) -> int:
+    """Smallest r >= 1 with ||s[r:]||_2 <= delta, then capped."""
+    n = len(s)
+    tail = np.sqrt(np.cumsum((s[::-1] ** 2))[::-1])    # tail[i] = ||s[i:]||
+    r = n
+    for i in range(1, n):
+        if tail[i] <= delta:
+            r = i
+            break
+    return max(1, min(r, cap, n))
+
+
+def round_tt(Z, Th, Ph, tol: float, cap: int):
+    """TT-SVD rounding (Oseledets 2011): orthogonalise right-to-left with QR of
+    the row-unfolded cores, then truncate left-to-right with delta-truncated
+    SVDs.  Returns (Z, Theta, Phi, info); cores are in Oseledets' gauge
+    (Z and Theta left-orthonormal, the norm carried by Phi)."""
+    R1, nt, R2 = Th.shape
+    # right-to-left orthogonalisation
+    q, r = np.linalg.qr(Ph.T)                 # Ph = r^T q^T
+    Ph_o = q.T
+    Th1 = np.einsum("alb,bc->alc", Th, r.T)   # absorb the triangular factor
+    k2 = Th1.shape[2]
+    q, r = np.linalg.qr(Th1.reshape(R1, nt * k2).T)
+    Th_o = q.T.reshape(-1, nt, k2)
+    Z1 = Z @ r.T
+    # left-to-right compression
+    U, s, Vt = np.linalg.svd(Z1, full_matrices=False)
+    norm = float(np.sqrt(np.sum(s ** 2)))
+    delta = tol * norm / math.sqrt(2.0)
+    r1 = delta_rank(s, delta, cap)
+    Zo = U[:, :r1]
+    C2 = np.einsum("ja,alb->jlb", s[:r1, None] * Vt[:r1], Th_o)
+    U2, s2, Vt2 = np.linalg.svd(C2.reshape(r1 * nt, k2), full_matrices=False)
+    r2 = delta_rank(s2, delta, cap)
+    Tho = U2[:, :r2].reshape(r1, nt, r2)
+    Pho = (s2[:r2, None] * Vt2[:r2]) @ Ph_o
+    info = dict(norm=norm, r1=r1, r2=r2, sv1=s, sv2=s2,
+                discarded=float(math.sqrt(np.sum(s[r1:] ** 2) + np.sum(s2[r2:] ** 2))),
+                R1=R1, R2=R2)
+    return Zo, Tho, Pho, info
+
+
+def step(prob, Z, Th, Ph, tol=None, cap=None):
+    """One step then truncate.  step_order 0: one rounding after transport and
+    source; step_order 1: round after the transport and again after the source
+    (the paper's order, Section 3.1 closing paragraph)."""
+    tol = prob.tol if tol is None else tol
+    cap = prob.rank_cap if cap is None else cap
+    if prob.step_order == 1:
+        Z, Th, Ph, _ = round_tt(*apply_transport(prob, Z, Th, Ph), tol, cap)
+        return round_tt(*apply_source(prob, Z, Th, Ph), tol, cap)
+    return round_tt(*apply_step(prob, Z, Th, Ph), tol, cap)
+
+
+def solve(prob, n_steps=None, cores=None, tol=None, cap=None):
+    Z, Th, Ph = initial_tt(prob) if cores is None else cores
+    n_steps = prob.n_steps if n_steps is None else n_steps
+    infos = []
+    for _ in range(n_steps):
+        Z, Th, Ph, info = step(prob, Z, Th, Ph, tol, cap)
+        infos.append(info)
+    return (Z, Th, Ph), infos
+
+
+def compression(prob, r1: int, r2: int) -> float:
+    """Section 3.2: dense entries over TT entries."""
+    n_tt = prob.M * r1 + prob.n_theta * r1 * r2 + prob.n_phi * r2
+    return prob.dense_entries / n_tt
+
+
+def tt_energy(prob, Z, Th, Ph) -> float:
+    """Quadrature-weighted content computed on the cores (TT integration)."""
+    dV = float(np.prod([prob.extent[d] / prob.n_cells[d] for d in range(prob.dim)]))
+    a = np.einsum("alb,l,bp,p->a", Th, np.asarray(prob.w_theta), Ph, np.asarray(prob.w_phi))
+    return dV * float(Z.sum(axis=0) @ a)

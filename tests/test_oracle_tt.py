@@ -1,0 +1,202 @@
+"""Pins of the oracle's TT algebra.
+
+* The explicit TT-sum apply (Appendix A) reconstructs to exactly one step of
+  the dense march, which is itself pinned by closed forms.
+* Ranks after the apply are (n+1) r + n_bc + 1 (Appendix A plus the source's
+  emission term).
+* TT-SVD rounding equals its plain definition: sequential delta-truncated
+  Eckart-Young projections of the dense unfoldings, bond 1 then bond 2, each
+  with delta = tol ||X|| / sqrt(2) (numpy SVD of the dense tensor, a
+  computation independent of the core-wise algorithm).  With N_phi = 1 it is
+  the truncated matrix SVD.  Its error is bounded by tol ||X||.
+* The paper's structural claims: a uniform isotropic state stays rank 1
+  (thermal relaxation), and a group-scaled vacuum inflow gives identical ranks
+  for any group scaling (multigroup hohlraum).
+* A TT solve at tol 1e-14 without a binding cap equals the dense march.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import tt_inputs as ti
+from oracle import dense, tt
+
+
+def _prob(dim, n, G=3, nt=4, nphi=4, bc=(1, 0, 0, 0, 0, 0), seed=0, T=0.3, periodic=False):
+    nc = tuple(list(n) + [1] * (3 - len(n)))
+    nx = int(np.prod(nc))
+    rng = np.random.default_rng(seed)
+    edges = np.array([0.0] + list(np.geomspace(0.2, 3.0, G - 1)) + [np.inf])
+    if dim == 1:
+        mu, wt = ti.gauss_legendre_mu(nt)
+        phi, wp = np.zeros(1), np.full(1, 2 * math.pi)
+    else:
+        mu, wt = ti.midpoint_mu(nt)
+        phi, wp = ti.midpoint_phi(nphi)
+    if periodic:
+        bc = (2,) * 6
+    return ti.Problem(name="t", dim=dim, n_cells=nc, extent=(1.0, 0.8, 1.2), edges=edges,
+                      kappa0=rng.uniform(0.2, 4.0, nx), kappa_scale=np.geomspace(3.0, 0.5, G),
+                      T_cell=np.full(nx, T), mu=mu, w_theta=wt, phi=phi, w_phi=wp, bc=bc,
+                      bc_T=(1.0, 0.7, 0.0, 0.5, 0.0, 0.0), tol=1e-8, rank_cap=64)
+
+
+CASES = [(1, (9,), 1, 4, (1, 0, 0, 0, 0, 0)), (1, (6,), 1, 6, (1, 1, 0, 0, 0, 0)),
+         (2, (5, 4), 4, 4, (1, 0, 0, 1, 0, 0)), (3, (3, 4, 3), 2, 4, (1, 0, 0, 0, 0, 1)),
+         (2, (4, 5), 4, 6, (2, 2, 2, 2, 0, 0))]
+
+
+@pytest.mark.parametrize("dim,n,nphi,nt,bc", CASES)
+def test_apply_equals_dense_step(dim, n, nphi, nt, bc):
+    p = _prob(dim, n, nt=nt, nphi=nphi, bc=bc)
+    r1, r2 = 3, min(2, p.n_phi)
+    Z, Th, Ph = ti.random_tt(p.M, p.n_theta, p.n_phi, r1, r2, seed=1)
+    X = tt.full(Z, Th, Ph)
+    ref = dense.march(p, X, 1)
+    Zn, Tn, Pn = tt.apply_step(p, Z, Th, Ph)
+    np.testing.assert_allclose(tt.full(Zn, Tn, Pn), ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+    # halves separately
+    Xs = tt.full(*tt.apply_transport(p, Z, Th, Ph))
+    np.testing.assert_allclose(Xs, dense.transport(p, X), rtol=1e-12, atol=1e-14 * np.abs(Xs).max())
+    nterm = 2 * dim
+    assert Zn.shape[1] == (nterm + 1) * r1 + tt.n_bc(p) + 1
+    assert Pn.shape[0] == (nterm + 1) * r2 + tt.n_bc(p) + 1
+
+
+def _dense_definition(X, tol, cap):
+    """Sequential delta-truncated SVD projections of the unfoldings (bond 1 then
+    bond 2), delta = tol ||X|| / sqrt(2)."""
+    M, nt, nphi = X.shape
+    norm = np.linalg.norm(X)
+    delta = tol * norm / math.sqrt(2)
+    U, s, Vt = np.linalg.svd(X.reshape(M, nt * nphi), full_matrices=False)
+    r1 = _rank(s, delta, cap)
+    X1 = (U[:, :r1] * s[:r1]) @ Vt[:r1]
+    U2, s2, Vt2 = np.linalg.svd(X1.reshape(M * nt, nphi), full_matrices=False)
+    r2 = _rank(s2, delta, cap)
+    X2 = (U2[:, :r2] * s2[:r2]) @ Vt2[:r2]
+    return X2.reshape(M, nt, nphi), r1, r2, s
+
+
+def _rank(s, delta, cap):
+    for r in range(1, len(s) + 1):
+        if np.sqrt(np.sum(s[r:] ** 2)) <= delta:
+            return min(r, cap)
+    return min(len(s), cap)
+
+
+@pytest.mark.parametrize("tol,cap", [(1e-3, 64), (1e-2, 64), (1e-6, 3), (0.0, 64)])
+def test_round_equals_sequential_svd_definition(tol, cap):
+    p = _prob(2, (4, 3), nt=4, nphi=6)
+    Z, Th, Ph = ti.random_tt(p.M, p.n_theta, p.n_phi, 5, 4, seed=2, decay=0.3)
+    Zn, Tn, Pn = tt.apply_step(p, Z, Th, Ph)
+    X = tt.full(Zn, Tn, Pn)
+    ref, r1, r2, s = _dense_definition(X, tol, cap)
+    Zo, To, Po, info = tt.round_tt(Zn, Tn, Pn, tol, cap)
+    assert (info["r1"], info["r2"]) == (r1, r2)
+    Xo = tt.full(Zo, To, Po)
+    np.testing.assert_allclose(Xo, ref, rtol=0, atol=1e-12 * np.linalg.norm(X))
+    np.testing.assert_allclose(info["sv1"][:len(s)], s[:len(info["sv1"])], rtol=1e-10,
+                               atol=1e-13 * s[0])
+    assert info["norm"] == pytest.approx(np.linalg.norm(X), rel=1e-13)
+    if cap >= 64:
+        assert np.linalg.norm(Xo - X) <= tol * np.linalg.norm(X) * (1 + 1e-12) + 1e-13
+
+
+def test_round_nphi1_is_truncated_matrix_svd():
+    p = _prob(1, (8,), nt=6)
+    Z, Th, Ph = ti.random_tt(p.M, p.n_theta, 1, 4, 1, seed=3, decay=0.2)
+    Zn, Tn, Pn = tt.apply_step(p, Z, Th, Ph)
+    X = tt.full(Zn, Tn, Pn)[:, :, 0]
+    tol = 1e-3
+    U, s, Vt = np.linalg.svd(X, full_matrices=False)
+    delta = tol * np.linalg.norm(s) / math.sqrt(2)
+    r = _rank(s, delta, 100)
+    ref = (U[:, :r] * s[:r]) @ Vt[:r]
+    Zo, To, Po, info = tt.round_tt(Zn, Tn, Pn, tol, 100)
+    assert info["r1"] == r and info["r2"] == 1
+    np.testing.assert_allclose(tt.full(Zo, To, Po)[:, :, 0], ref, atol=1e-13 * s[0])
+
+
+def test_round_idempotent_and_orthonormal():
+    p = _prob(2, (3, 3), nt=4, nphi=4)
+    Z, Th, Ph = ti.random_tt(p.M, 4, 4, 4, 3, seed=4, decay=0.4)
+    Zn, Tn, Pn = tt.apply_step(p, Z, Th, Ph)
+    a = tt.round_tt(Zn, Tn, Pn, 1e-3, 64)
+    b = tt.round_tt(*a[:3], 1e-3, 64)
+    assert (a[3]["r1"], a[3]["r2"]) == (b[3]["r1"], b[3]["r2"])
+    np.testing.assert_allclose(tt.full(*b[:3]), tt.full(*a[:3]), atol=1e-12 * a[3]["norm"])
+    Zo, To, _, _ = a
+    np.testing.assert_allclose(Zo.T @ Zo, np.eye(Zo.shape[1]), atol=1e-12)
+    T2 = To.reshape(-1, To.shape[2])
+    np.testing.assert_allclose(T2.T @ T2, np.eye(T2.shape[1]), atol=1e-12)
+
+
+def test_exact_low_rank_recovered():
+    # a TT with exact ranks (2, 2) padded with zero blocks rounds back to (2, 2)
+    rng = np.random.default_rng(9)
+    M, nt, nphi = 40, 5, 6
+    Z = rng.standard_normal((M, 2)); Th = rng.standard_normal((2, nt, 2)); Ph = rng.standard_normal((2, nphi))
+    Zp = np.concatenate([Z, Z @ rng.standard_normal((2, 3))], axis=1)
+    Thp = np.zeros((5, nt, 4)); Thp[:2, :, :2] = Th; Thp[2:, :, 2:] = rng.standard_normal((3, nt, 2)) * 0
+    Php = np.concatenate([Ph, rng.standard_normal((2, nphi))])
+    Zo, To, Po, info = tt.round_tt(Zp, Thp, Php, 1e-12, 64)
+    assert (info["r1"], info["r2"]) == (2, 2)
+    np.testing.assert_allclose(tt.full(Zo, To, Po), tt.full(Z, Th, Ph), atol=1e-11)
+
+
+def test_uniform_state_stays_rank_one():
+    # thermal-relaxation structure: isotropic, spatially uniform state with
+    # periodic faces stays rank 1 under transport + source
+    p = _prob(2, (4, 4), nt=4, nphi=8, periodic=True)
+    p.kappa0 = np.full(p.n_x, 2.0)
+    Z = np.tile(np.array([0.3, 0.1, 0.05]), p.n_x)[:, None]
+    cores = (Z, np.ones((1, 4, 1)), np.ones((1, 8)))
+    (Zo, To, Po), infos = tt.solve(p, 5, cores=cores, tol=1e-10)
+    assert all(i["r1"] == 1 and i["r2"] == 1 for i in infos)
+
+
+def test_group_scaled_vacuum_inflow_rank_invariance():
+    # multigroup hohlraum: with vacuum transport and spatially uniform,
+    # group-scaled inflow, the rank history does not depend on the scaling
+    hist = []
+    for scale in (np.array([1.0, 1.0, 1.0, 1.0]), np.array([0.2, 3.0, 0.7, 1.9])):
+        p = _prob(2, (6, 6), G=4, nt=4, nphi=8, bc=(3, 0, 3, 0, 0, 0), T=0.0)
+        p.kappa0 = np.zeros(p.n_x)
+        vals = np.zeros((6, 4)); vals[0] = scale; vals[2] = scale
+        p.bc_values = vals
+        (_, _, _), infos = tt.solve(p, 8, tol=1e-6)
+        hist.append([(i["r1"], i["r2"]) for i in infos])
+    assert hist[0] == hist[1]
+
+
+@pytest.mark.parametrize("dim,n,nphi,nt", [(1, (10,), 1, 6), (2, (5, 4), 4, 4)])
+def test_tt_solve_matches_dense_march(dim, n, nphi, nt):
+    p = _prob(dim, n, nt=nt, nphi=nphi)
+    K = 6
+    (Z, Th, Ph), infos = tt.solve(p, K, tol=1e-14, cap=10 ** 6)
+    ref = dense.march(p, dense.initial_dense(p), K)
+    err = np.linalg.norm(tt.full(Z, Th, Ph) - ref) / np.linalg.norm(ref)
+    assert err <= 1e-10
+    # paper's step order (round after transport and after source) gives the same tensor
+    p.step_order = 1
+    (Z1, T1, P1), _ = tt.solve(p, K, tol=1e-14, cap=10 ** 6)
+    assert np.linalg.norm(tt.full(Z1, T1, P1) - ref) / np.linalg.norm(ref) <= 1e-10
+
+
+def test_tt_energy_matches_dense_energy():
+    p = _prob(2, (4, 5), nt=4, nphi=6)
+    Z, Th, Ph = ti.random_tt(p.M, 4, 6, 3, 2, seed=6)
+    assert tt.tt_energy(p, Z, Th, Ph) == pytest.approx(dense.energy(p, tt.full(Z, Th, Ph)), rel=1e-12)
+
+
+def test_compression_formula_paper_values():
+    # thermal relaxation: 4 x 3 x 512 x 1024 at rank 1 prints C ~ 4000;
+    # N_nu = 100 prints 1e5 (table) / 1.2e5 (text)
+    p = ti.Problem(name="c", dim=1, n_cells=(4, 1, 1), extent=(4, 1, 1),
+                   edges=np.zeros(4), kappa0=np.ones(4), kappa_scale=np.ones(3), T_cell=np.ones(4),
+                   mu=np.zeros(512), w_theta=np.zeros(512), phi=np.zeros(1024), w_phi=np.zeros(1024))
+    assert round(tt.compression(p, 1, 1), -2) == 4100.0
+    p100 = p.copy(edges=np.zeros(101), kappa_scale=np.ones(100))
+    assert 0.9e5 < tt.compression(p100, 1, 1) < 1.25e5
