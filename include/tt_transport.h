@@ -1,0 +1,211 @@
+/*
+ * tt_transport.h -- C ABI of the MI355X (gfx950) tensor-train multigroup
+ * radiation transport library.
+ *
+ * What the library computes (arXiv 2602.00290):
+ *
+ *   * The intensity is a tensor train over (space x group, polar angle,
+ *     azimuthal angle):  I[k, l, p] = sum_{a,b} Z[k,a] Theta[a,l,b] Phi[b,p]
+ *     with the merged spatio-spectral row index k = cell * N_nu + g
+ *     (Section 3.1, the merged decomposition; cell = ix + Nx*(iy + Ny*iz)).
+ *   * One time step applies the discretised multigroup discrete-ordinates
+ *     operator: forward-Euler streaming with the upwind flux, then the
+ *     backward-Euler operator-split absorption/emission update at fixed
+ *     medium temperature with zero scattering and density 1 (Section 2.1,
+ *     the discrete source equation), i.e.
+ *        I* = I - sum_d lambda_d [n_d^+ (I_c - I_{c-e_d}) + n_d^- (I_{c+e_d} - I_c)]
+ *        I' = (I* + c dt kappa eps) / (1 + c dt kappa),   lambda_d = c dt / dx_d,
+ *     as a sum of n = 2 d_X rank-1 TT operators plus rank-1 boundary and
+ *     emission terms (Appendix A), so the ranks grow to (n+1) r + n_bc + 1.
+ *   * Rank is restored by TT-SVD rounding (Oseledets 2011, the SVD rounding
+ *     the paper uses, Section 3.1 footnote): right-to-left QR
+ *     orthogonalisation, then left-to-right delta-truncated SVDs with
+ *     delta = tol * ||I||_F / sqrt(2); each rank is also capped.
+ *   * Group emission eps_g(T) = 2 T^4 int x^3/(e^x - 1) dx over the group
+ *     in units h = k = c_light = 1 (Section 2, group emission; the solver's
+ *     own c is a separate input).
+ *
+ * Conventions for every entry point:
+ *   * Host arrays passed in are read during the call and copied; the caller
+ *     keeps ownership.  Device memory is never allocated by the library: the
+ *     caller passes one device workspace (e.g. a torch uint8 tensor) of at
+ *     least tt_transport_workspace_bytes() bytes, owns it, and must keep it
+ *     alive until tt_transport_destroy().
+ *   * `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls enqueue work on that stream and return without waiting, except
+ *     those documented as synchronising.
+ *   * Every call returns a tt_status; nothing aborts or throws across the
+ *     ABI.  tt_transport_last_error() gives a thread-local message for the
+ *     last failing call.  A NaN/Inf produced on the device is reported as
+ *     TT_ERR_NUMERIC by the next synchronising call.
+ *   * One handle must not be used from two host threads at once.  Handles
+ *     are independent of each other.
+ */
+#ifndef TT_TRANSPORT_H
+#define TT_TRANSPORT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TT_OK = 0,
+    TT_ERR_INVALID_ARG = -1,   /* bad sizes, pointers, or option values          */
+    TT_ERR_OOM = -2,           /* workspace smaller than required               */
+    TT_ERR_NUMERIC = -3,       /* NaN / Inf detected in the state               */
+    TT_ERR_HIP = -4,           /* a HIP runtime call failed                     */
+    TT_ERR_STATE = -5          /* call not valid in the handle's current state  */
+} tt_status;
+
+/* Precision of the large core contractions (Z and the first-core projection).
+ * The R factors, the SVDs and the truncation thresholds are always FP64. */
+typedef enum {
+    TT_PREC_FP64 = 0,   /* Z stored and contracted in FP64                       */
+    TT_PREC_FP32 = 1,   /* Z stored in FP32, contractions on FP32 MFMA            */
+    TT_PREC_BF16X = 2   /* Z stored in FP32, contractions as split BF16 (hi+lo)
+                           products on BF16 MFMA with FP32 accumulation          */
+} tt_precision;
+
+/* How the first (M-row) core is factorised inside the rounding. */
+typedef enum {
+    TT_ROUND_QR = 0,    /* Householder TSQR in FP64, then an FP64 SVD of R
+                           (TT-SVD rounding)                                      */
+    TT_ROUND_GRAM = 1   /* FP64 Gram matrix of the projected core, then an FP64
+                           symmetric eigensolver (Gram rounding, Section 3.1
+                           footnote); accurate when tol >> 1e-8                  */
+} tt_round_method;
+
+typedef enum {
+    TT_BC_VACUUM = 0,          /* ghost intensity 0                              */
+    TT_BC_INFLOW_PLANCK = 1,   /* isotropic ghost intensity eps_g(bc_T[face])    */
+    TT_BC_PERIODIC = 2,        /* wrap-around; both faces of the axis            */
+    TT_BC_INFLOW_VALUES = 3    /* isotropic ghost intensity bc_values[face*N+g]  */
+} tt_bc;
+
+/* Problem statement (Section 2 and 2.1; quadrature and group conventions of
+ * Section 4).  Faces are ordered x-, x+, y-, y+, z-, z+. */
+typedef struct tt_problem {
+    int dim;                        /* 1, 2 or 3                                    */
+    int n_cells[3];                 /* cells per axis (unused axes: 1)              */
+    double extent[3];               /* domain [0, extent_d] per axis                */
+    int n_groups;                   /* N_nu >= 1                                    */
+    const double* group_edges;      /* N_nu + 1 edges, [0] = 0, [N_nu] = +inf       */
+    const double* kappa0;           /* N_X spatial opacity factor (>= 0)            */
+    const double* kappa_group_scale;/* N_nu: kappa[cell,g] = kappa0[cell]*scale[g]  */
+    const double* T_cell;           /* N_X fixed medium temperature (>= 0)          */
+    int n_theta;                    /* polar nodes                                  */
+    int n_phi;                      /* azimuthal nodes (must be 1 when dim == 1)    */
+    const double* mu;               /* n_theta cos(theta) nodes in (-1, 1)          */
+    const double* w_theta;          /* n_theta polar weights                        */
+    const double* phi;              /* n_phi azimuth nodes (ignored when dim == 1)  */
+    const double* w_phi;            /* n_phi azimuthal weights                      */
+    int bc[6];                      /* tt_bc per face                               */
+    double bc_T[6];                 /* temperatures for TT_BC_INFLOW_PLANCK          */
+    const double* bc_values;        /* 6*N_nu values for TT_BC_INFLOW_VALUES or NULL */
+    double c;                       /* propagation speed                            */
+    double cfl;                     /* dt = cfl / (c * sum_d 1/dx_d)                */
+    double tol;                     /* relative rounding tolerance                  */
+    int rank_cap;                   /* cap on both TT ranks (>= 1)                  */
+    int precision;                  /* tt_precision                                 */
+    int round_method;               /* tt_round_method                              */
+    int paper_step_order;           /* 0: one rounding per step after transport and
+                                       source; 1: round after transport and again
+                                       after the source (Section 3.1)              */
+} tt_problem;
+
+/* Statistics of the last solve / round (Section 3.2 metrics). */
+typedef struct tt_stats {
+    int steps;            /* steps taken by the last solve                           */
+    int r1, r2;           /* current ranks                                            */
+    int max_R1, max_R2;   /* largest pre-rounding ranks seen                          */
+    int nan_flag;         /* 1 if a NaN/Inf was seen                                  */
+    double norm;          /* ||I||_F before the last truncation                       */
+    double discarded_rel; /* sqrt(sum of discarded sigma^2) / norm, last rounding     */
+    double energy;        /* dV * sum_k sum_lp w_l w_p I[k,l,p] of the current state */
+    double k_s;           /* peak storage / post-round storage (Section 3.2 k_s)      */
+    double compression;   /* N_X N_nu N_theta N_phi / TT entries (Section 3.2 eq.)    */
+    double seconds;       /* wall time of the last solve (host clock, synchronised)  */
+    double kernel_ms[8];  /* summed HIP-event durations per kernel class when timing
+                             is on: [0] prep, [1] project (first-core contraction),
+                             [2] factor (TSQR or Gram), [3] factor tree / reduce,
+                             [4] small-core SVD chain, [5] output contraction,
+                             [6] diagnostics, [7] unused                            */
+    long long kernel_launches[8]; /* launches counted per class                      */
+    double flops[8];      /* algorithmic flops per class, summed over the solve      */
+} tt_stats;
+
+typedef struct tt_handle tt_handle;
+
+/* Bytes of device workspace needed for `p` at its rank cap.  Returns 0 for an
+ * invalid problem (see tt_transport_last_error). */
+size_t tt_transport_workspace_bytes(const tt_problem* p);
+
+/* Create a solver.  Validates `p`, computes host-side setup in FP64 (dt,
+ * group emission, angular factors), carves `dev_workspace` and uploads the
+ * inputs and the rank-1 initial state I0 = eps_g(T_cell) (x) 1 (x) 1
+ * (isotropic Planck state at the medium temperature).  Synchronises.
+ * Errors: TT_ERR_INVALID_ARG, TT_ERR_OOM (bytes too small), TT_ERR_HIP. */
+tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t bytes,
+                              void* stream, tt_handle** out);
+
+/* Apply the transport + source operator once without rounding (Appendix A):
+ * afterwards the handle holds the unrounded TT sum with ranks
+ * (n+1) r + n_bc + 1; tt_transport_get_cores materialises it.  With
+ * paper_step_order = 1 this applies the transport half only. */
+tt_status tt_transport_apply_op(tt_handle* h, void* stream);
+
+/* Round the handle's TT (a pending unrounded sum or a plain state) with the
+ * given tolerance and rank cap (rank_cap <= the problem's cap). */
+tt_status tt_transport_round(tt_handle* h, double tol, int rank_cap, void* stream);
+
+/* n_steps full steps (apply + round, or the paper's two-round order).  No host
+ * synchronisation inside; `out` (may be NULL) is filled after a final
+ * synchronisation. */
+tt_status tt_transport_solve(tt_handle* h, int n_steps, tt_stats* out, void* stream);
+
+/* Reset the state to the rank-1 initial condition. */
+tt_status tt_transport_reset(tt_handle* h, void* stream);
+
+/* Current ranks (synchronises). */
+tt_status tt_transport_get_ranks(tt_handle* h, int* r1, int* r2);
+
+/* Copy the current cores to host FP64 arrays: Z (M x r1, row-major),
+ * Theta (r1 x n_theta x r2), Phi (r2 x n_phi).  Any pointer may be NULL.
+ * Synchronises.  A pending unrounded sum is returned as its explicit cores. */
+tt_status tt_transport_get_cores(tt_handle* h, double* Z, double* Theta, double* Phi,
+                                 void* stream);
+
+/* Replace the state by host FP64 cores of ranks (r1, r2) <= the caps
+ * (checkpoint restore, tests).  Synchronises. */
+tt_status tt_transport_set_cores(tt_handle* h, int r1, int r2, const double* Z,
+                                 const double* Theta, const double* Phi, void* stream);
+
+/* Fill `out` with the statistics of the current state (synchronises). */
+tt_status tt_transport_get_stats(tt_handle* h, tt_stats* out);
+
+/* Record HIP events around every kernel launch and accumulate their
+ * durations into tt_stats.kernel_ms (on = 1) or stop (on = 0). */
+tt_status tt_transport_set_timing(tt_handle* h, int on);
+
+/* One full step for each of n independent handles, all enqueued on `stream`
+ * so the device overlaps them (the handles' kernels are interleaved per
+ * phase).  Handles must be distinct. */
+tt_status tt_transport_step_batch(tt_handle** hs, int n, void* stream);
+
+/* Release the handle's host resources.  Never frees the caller's workspace. */
+tt_status tt_transport_destroy(tt_handle* h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* tt_transport_last_error(void);
+
+/* Group emission coefficients eps_g(T), N_nu values, computed by the
+ * library's host routine (series evaluation, see the source). */
+tt_status tt_transport_group_emission(const double* edges, int n_groups, double T, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TT_TRANSPORT_H */

@@ -12,7 +12,7 @@ over the group [nu_{f-1}, nu_f).  In units with h = k = c = 1 this is
 and the gray sum over all groups is 2 pi^4 T^4 / 15 = c a T^4 / (4 pi) with
 a = 8 pi^5 / 15 (the gray limit stated right after the Planck function).
 
-The integral is evaluated with mpmath's tanh-sinh quadrature at 40 digits,
+The integral is evaluated with mpmath's tanh-sinh quadrature at 60 digits,
 an implementation independent of the library's series evaluation.
 """
 from __future__ import annotations
@@ -23,13 +23,20 @@ import math
 import mpmath
 import numpy as np
 
-_DPS = 40
+_DPS = 60
 
 
-def _planck_integrand(x):
-    if x == 0:
-        return mpmath.mpf(0)
-    return x ** 3 / mpmath.expm1(x)
+def _shifted_integrand(a):
+    """u -> (a+u)^3 e^{-u} / (1 - e^{-(a+u)}), so that
+    int_a^b x^3/(e^x - 1) dx = e^{-a} int_0^{b-a} (this) du.  Factoring e^{-a}
+    out keeps the integrand O(1) wherever the group sits, which matters
+    because the quadrature's error control is absolute."""
+    def f(u):
+        x = a + u
+        if x == 0:
+            return mpmath.mpf(0)
+        return x ** 3 * mpmath.exp(-u) / (-mpmath.expm1(-x))
+    return f
 
 
 @functools.lru_cache(maxsize=None)
@@ -37,17 +44,15 @@ def planck_integral(xa: float, xb: float) -> float:
     """int_{xa}^{xb} x^3/(e^x - 1) dx for 0 <= xa < xb <= inf (float in, float out)."""
     with mpmath.workdps(_DPS):
         a = mpmath.mpf(xa)
-        b = mpmath.inf if math.isinf(xb) else mpmath.mpf(xb)
-        if not (b > a):
+        w = mpmath.inf if math.isinf(xb) else mpmath.mpf(xb) - a
+        if not (w > 0):
             return 0.0
-        # split at points where the integrand changes character so the quadrature
-        # sees smooth pieces
-        pts = [a]
-        for s in (1, 3, 10, 30, 100):
-            if a < s < b:
-                pts.append(mpmath.mpf(s))
-        pts.append(b)
-        val = mpmath.quad(_planck_integrand, pts)
+        # split where the shifted integrand changes character (unit-scale decay
+        # in u, and the Rayleigh-Jeans / Wien crossover near x ~ 1..10)
+        cuts = {mpmath.mpf(d) for d in (0.25, 0.5, 1, 2, 4, 8, 16, 32, 64, 128)}
+        cuts |= {mpmath.mpf(s) - a for s in (1, 3, 10, 30)}
+        pts = [mpmath.mpf(0)] + sorted(c for c in cuts if 0 < c < w) + [w]
+        val = mpmath.exp(-a) * mpmath.quad(_shifted_integrand(a), pts)
         return float(val)
 
 

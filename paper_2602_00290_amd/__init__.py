@@ -1,0 +1,305 @@
+"""Python binding of libtt_transport.so (ctypes; argument marshalling only).
+
+Every step of the transport + rounding path runs in the library's HIP kernels;
+this module converts a problem description into the C struct, allocates the
+device workspace with PyTorch, and forwards calls.  There is no CPU fallback:
+importing fails loudly when the shared library is missing.
+
+Names follow the C ABI in include/tt_transport.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtt_transport.so")
+
+TT_OK, TT_ERR_INVALID_ARG, TT_ERR_OOM, TT_ERR_NUMERIC, TT_ERR_HIP, TT_ERR_STATE = 0, -1, -2, -3, -4, -5
+TT_PREC_FP64, TT_PREC_FP32, TT_PREC_BF16X = 0, 1, 2
+TT_ROUND_QR, TT_ROUND_GRAM = 0, 1
+TT_BC_VACUUM, TT_BC_INFLOW_PLANCK, TT_BC_PERIODIC, TT_BC_INFLOW_VALUES = 0, 1, 2, 3
+
+KERNEL_CLASSES = ("prep", "project", "factor", "tree", "svd", "output", "diag", "unused")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class TTProblem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int),
+        ("n_cells", ctypes.c_int * 3),
+        ("extent", ctypes.c_double * 3),
+        ("n_groups", ctypes.c_int),
+        ("group_edges", _dp),
+        ("kappa0", _dp),
+        ("kappa_group_scale", _dp),
+        ("T_cell", _dp),
+        ("n_theta", ctypes.c_int),
+        ("n_phi", ctypes.c_int),
+        ("mu", _dp),
+        ("w_theta", _dp),
+        ("phi", _dp),
+        ("w_phi", _dp),
+        ("bc", ctypes.c_int * 6),
+        ("bc_T", ctypes.c_double * 6),
+        ("bc_values", _dp),
+        ("c", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+        ("tol", ctypes.c_double),
+        ("rank_cap", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("round_method", ctypes.c_int),
+        ("paper_step_order", ctypes.c_int),
+    ]
+
+
+class TTStats(ctypes.Structure):
+    _fields_ = [
+        ("steps", ctypes.c_int),
+        ("r1", ctypes.c_int),
+        ("r2", ctypes.c_int),
+        ("max_R1", ctypes.c_int),
+        ("max_R2", ctypes.c_int),
+        ("nan_flag", ctypes.c_int),
+        ("norm", ctypes.c_double),
+        ("discarded_rel", ctypes.c_double),
+        ("energy", ctypes.c_double),
+        ("k_s", ctypes.c_double),
+        ("compression", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+        ("kernel_ms", ctypes.c_double * 8),
+        ("kernel_launches", ctypes.c_longlong * 8),
+        ("flops", ctypes.c_double * 8),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {f: getattr(self, f) for f, _ in self._fields_[:12]}
+        d["kernel_ms"] = dict(zip(KERNEL_CLASSES, list(self.kernel_ms)))
+        d["kernel_launches"] = dict(zip(KERNEL_CLASSES, list(self.kernel_launches)))
+        d["flops"] = dict(zip(KERNEL_CLASSES, list(self.flops)))
+        return d
+
+
+class TTError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"tt_transport error {status}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+            "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    L.tt_transport_workspace_bytes.argtypes = [ctypes.POINTER(TTProblem)]
+    L.tt_transport_workspace_bytes.restype = ctypes.c_size_t
+    L.tt_transport_create.argtypes = [ctypes.POINTER(TTProblem), vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.tt_transport_apply_op.argtypes = [vp, vp]
+    L.tt_transport_round.argtypes = [vp, ctypes.c_double, ctypes.c_int, vp]
+    L.tt_transport_solve.argtypes = [vp, ctypes.c_int, ctypes.POINTER(TTStats), vp]
+    L.tt_transport_reset.argtypes = [vp, vp]
+    L.tt_transport_get_ranks.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    L.tt_transport_get_cores.argtypes = [vp, _dp, _dp, _dp, vp]
+    L.tt_transport_set_cores.argtypes = [vp, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, vp]
+    L.tt_transport_get_stats.argtypes = [vp, ctypes.POINTER(TTStats)]
+    L.tt_transport_set_timing.argtypes = [vp, ctypes.c_int]
+    L.tt_transport_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp]
+    L.tt_transport_destroy.argtypes = [vp]
+    L.tt_transport_last_error.argtypes = []
+    L.tt_transport_last_error.restype = ctypes.c_char_p
+    L.tt_transport_group_emission.argtypes = [_dp, ctypes.c_int, ctypes.c_double, _dp]
+    for name in ("create", "apply_op", "round", "solve", "reset", "get_ranks", "get_cores", "set_cores",
+                 "get_stats", "set_timing", "step_batch", "destroy", "group_emission"):
+        getattr(L, "tt_transport_" + name).restype = ctypes.c_int
+    return L
+
+
+lib = _load()
+
+EXPORTED = ("tt_transport_workspace_bytes", "tt_transport_create", "tt_transport_apply_op", "tt_transport_round",
+            "tt_transport_solve", "tt_transport_reset", "tt_transport_get_ranks", "tt_transport_get_cores",
+            "tt_transport_set_cores", "tt_transport_get_stats", "tt_transport_set_timing",
+            "tt_transport_step_batch", "tt_transport_destroy", "tt_transport_last_error",
+            "tt_transport_group_emission")
+
+
+def _check(status: int):
+    if status != TT_OK:
+        raise TTError(status, lib.tt_transport_last_error().decode())
+
+
+def _arr(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+def group_emission(edges, T: float) -> np.ndarray:
+    e = _arr(edges)
+    out = np.empty(len(e) - 1)
+    _check(lib.tt_transport_group_emission(e.ctypes.data_as(_dp), len(e) - 1, float(T), out.ctypes.data_as(_dp)))
+    return out
+
+
+class ProblemStruct:
+    """A tt_problem built from a problem description (attributes as in
+    tt_inputs.Problem); keeps the numpy arrays alive while referenced."""
+
+    def __init__(self, prob, round_method: Optional[int] = None):
+        self.keep = []
+
+        def ptr(a):
+            if a is None:
+                return None
+            a = _arr(a)
+            self.keep.append(a)
+            return a.ctypes.data_as(_dp)
+
+        s = TTProblem()
+        s.dim = int(prob.dim)
+        for d in range(3):
+            s.n_cells[d] = int(prob.n_cells[d]) if d < prob.dim else 1
+            s.extent[d] = float(prob.extent[d])
+        s.n_groups = len(prob.edges) - 1
+        s.group_edges = ptr(prob.edges)
+        s.kappa0 = ptr(prob.kappa0)
+        s.kappa_group_scale = ptr(prob.kappa_scale)
+        s.T_cell = ptr(prob.T_cell)
+        s.n_theta = len(prob.mu)
+        s.n_phi = len(prob.w_phi)
+        s.mu = ptr(prob.mu)
+        s.w_theta = ptr(prob.w_theta)
+        s.phi = ptr(prob.phi)
+        s.w_phi = ptr(prob.w_phi)
+        for f in range(6):
+            s.bc[f] = int(prob.bc[f])
+            s.bc_T[f] = float(prob.bc_T[f])
+        s.bc_values = ptr(None if prob.bc_values is None else np.asarray(prob.bc_values).reshape(-1))
+        s.c = float(prob.c)
+        s.cfl = float(prob.cfl)
+        s.tol = float(prob.tol)
+        s.rank_cap = int(prob.rank_cap)
+        s.precision = int(prob.precision)
+        s.round_method = int(getattr(prob, "round_method", TT_ROUND_QR) if round_method is None else round_method)
+        s.paper_step_order = int(prob.step_order)
+        self.s = s
+
+
+def workspace_bytes(prob, round_method: Optional[int] = None) -> int:
+    ps = ProblemStruct(prob, round_method)
+    n = lib.tt_transport_workspace_bytes(ctypes.byref(ps.s))
+    if n == 0:
+        raise TTError(TT_ERR_INVALID_ARG, lib.tt_transport_last_error().decode())
+    return int(n)
+
+
+class Solver:
+    """One TT transport solve on a GPU: owns the device workspace (a torch
+    uint8 tensor) and the library handle."""
+
+    def __init__(self, prob, device="cuda:0", stream=None, round_method: Optional[int] = None, workspace=None):
+        import torch
+
+        self.prob = prob
+        self.device = torch.device(device)
+        self._ps = ProblemStruct(prob, round_method)
+        nbytes = lib.tt_transport_workspace_bytes(ctypes.byref(self._ps.s))
+        if nbytes == 0:
+            _check(TT_ERR_INVALID_ARG)
+        self.nbytes = int(nbytes)
+        if workspace is None:
+            workspace = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        self.workspace = workspace
+        base = workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self._stream = stream
+        self.handle = ctypes.c_void_p()
+        _check(lib.tt_transport_create(ctypes.byref(self._ps.s), ctypes.c_void_p(aligned),
+                                       self.nbytes + 256 - (aligned - base), self._sp(),
+                                       ctypes.byref(self.handle)))
+        self.M = prob.n_x * (len(prob.edges) - 1)
+        self.n_theta = len(prob.mu)
+        self.n_phi = len(prob.w_phi)
+
+    def _sp(self):
+        import torch
+
+        if self._stream is None:
+            return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+        return ctypes.c_void_p(self._stream.cuda_stream)
+
+    # ----- C ABI, same names -----
+    def apply_op(self):
+        _check(lib.tt_transport_apply_op(self.handle, self._sp()))
+
+    def round(self, tol: float, rank_cap: int):
+        _check(lib.tt_transport_round(self.handle, float(tol), int(rank_cap), self._sp()))
+
+    def solve(self, n_steps: int) -> dict:
+        st = TTStats()
+        _check(lib.tt_transport_solve(self.handle, int(n_steps), ctypes.byref(st), self._sp()))
+        return st.as_dict()
+
+    def solve_async(self, n_steps: int):
+        """Enqueue n_steps and return after the final synchronisation, no stats."""
+        _check(lib.tt_transport_solve(self.handle, int(n_steps), None, self._sp()))
+
+    def reset(self):
+        _check(lib.tt_transport_reset(self.handle, self._sp()))
+
+    def get_ranks(self):
+        r1, r2 = ctypes.c_int(), ctypes.c_int()
+        _check(lib.tt_transport_get_ranks(self.handle, ctypes.byref(r1), ctypes.byref(r2)))
+        return r1.value, r2.value
+
+    def get_cores(self, pending_shape=None):
+        """Host FP64 copies (Z, Theta, Phi).  For a pending unrounded sum pass
+        pending_shape = (R1, R2)."""
+        if pending_shape is None:
+            r1, r2 = self.get_ranks()
+        else:
+            r1, r2 = pending_shape
+        Z = np.empty((self.M, r1))
+        Th = np.empty((r1, self.n_theta, r2))
+        Ph = np.empty((r2, self.n_phi))
+        _check(lib.tt_transport_get_cores(self.handle, Z.ctypes.data_as(_dp), Th.ctypes.data_as(_dp),
+                                          Ph.ctypes.data_as(_dp), self._sp()))
+        return Z, Th, Ph
+
+    def set_cores(self, Z, Th, Ph):
+        Z, Th, Ph = _arr(Z), _arr(Th), _arr(Ph)
+        _check(lib.tt_transport_set_cores(self.handle, Z.shape[1], Ph.shape[0], Z.ctypes.data_as(_dp),
+                                          Th.ctypes.data_as(_dp), Ph.ctypes.data_as(_dp), self._sp()))
+
+    def get_stats(self) -> dict:
+        st = TTStats()
+        _check(lib.tt_transport_get_stats(self.handle, ctypes.byref(st)))
+        return st.as_dict()
+
+    def set_timing(self, on: bool):
+        _check(lib.tt_transport_set_timing(self.handle, 1 if on else 0))
+
+    def destroy(self):
+        if self.handle:
+            lib.tt_transport_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def step_batch(solvers, stream=None):
+    """One step of every solver, enqueued on one stream."""
+    import torch
+
+    arr = (ctypes.c_void_p * len(solvers))(*[s.handle for s in solvers])
+    sp = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+    _check(lib.tt_transport_step_batch(arr, len(solvers), sp))
+

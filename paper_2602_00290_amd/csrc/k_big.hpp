@@ -1,0 +1,394 @@
+// Kernels over the large first core (M = N_X * N_nu rows).
+#pragma once
+
+#include "k_small.hpp"
+#include "tt_common.hpp"
+
+namespace ttrt {
+
+// Problem arrays used to evaluate the rank-1 columns and the absorption factor
+// of a merged row on the fly.
+struct RowData {
+    const double* kappa0;   // N_X
+    const double* kscale;   // N_nu
+    const double* eps;      // M  (eps_g(T_cell))
+    const double* ghost;    // 6 x N_nu isotropic ghost intensities
+};
+
+__device__ inline double row_kappa(const Geom& g, const RowData& rd, long long k) {
+    const long long cell = k / g.G;
+    const int grp = (int)(k - cell * g.G);
+    return rd.kappa0[cell] * rd.kscale[grp];
+}
+
+// Value in row k of rank-1 column q of the operator (before the d scaling).
+__device__ inline double rank1_value(const Geom& g, const OpDesc& op, const RowData& rd, long long k, int q) {
+    if (op.r1kind[q] == 0) {
+        return g.cdt * row_kappa(g, rd, k) * rd.eps[k];
+    }
+    const int face = op.r1face[q];
+    const int axis = face >> 1, high = face & 1;
+    const int n = axis == 0 ? g.nx : (axis == 1 ? g.ny : g.nz);
+    const int idx = axis_index(g, k, axis);
+    if (idx != (high ? n - 1 : 0)) return 0.0;
+    const long long cell = k / g.G;
+    const int grp = (int)(k - cell * g.G);
+    const double v = g.lam[axis] * rd.ghost[face * g.G + grp];
+    return high ? -v : v;
+}
+
+__device__ inline double row_scale(const Geom& g, const OpDesc& op, const RowData& rd, long long k) {
+    return op.scale_d ? 1.0 / (1.0 + g.cdt * row_kappa(g, rd, k)) : 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// Gather contraction
+// ---------------------------------------------------------------------------
+//
+// MODE_PROJECT:  B[k,:] = d_k * ( sum_j Z[nbr_j(k),:] G_j + sum_q z_q(k) G_rank1[q] )
+//                with j over the gather blocks (Z itself and its shifted copies
+//                O_{d-} Z, O_{d+} Z), i.e. B = Z_new L_Theta for the pending TT
+//                sum without forming Z_new (Appendix A operator terms).
+// MODE_OUTPUT:   Z_out = B V_r (plain contraction, K = ldb).
+// 64 x 64 output tile per 256-thread block, K staged through LDS in chunks of 8.
+enum { MODE_PROJECT = 0, MODE_OUTPUT = 1 };
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_gather_gemm(Geom g, OpDesc op, const DevState* __restrict__ st,
+                                                      const T* __restrict__ A, const T* __restrict__ Gop,
+                                                      T* __restrict__ Out, RowData rd) {
+    constexpr int BM = 64, BN = 64, KC = 8;
+    __shared__ T As[KC][BM + 4];
+    __shared__ T Gs[KC][BN + 4];
+    __shared__ long long nbr[kMaxBlocks][BM];
+    const int tid = threadIdx.x;
+    const long long row0 = (long long)blockIdx.x * BM;
+    const int col0 = blockIdx.y * BN;
+    int lda, ldg, ldo, nblk, kper;
+    if (MODE == MODE_PROJECT) {
+        lda = st->ldz; kper = st->ldz; ldg = st->ldb; ldo = st->ldb; nblk = op.n_gather;
+    } else {
+        lda = st->ldb; kper = st->ldb; ldg = st->ldzn; ldo = st->ldzn; nblk = 1;
+    }
+    if (col0 >= ldo) return;
+    for (int idx = tid; idx < nblk * BM; idx += 256) {
+        const int j = idx / BM, i = idx % BM;
+        const long long k = row0 + i;
+        long long src = -1;
+        if (k < g.M) src = (MODE == MODE_OUTPUT || j == 0) ? k : neighbour_row(g, k, op.gaxis[j], op.gdir[j]);
+        nbr[j][i] = src;
+    }
+    const int tx = tid & 15, ty = tid >> 4;
+    T acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = (T)0;
+    __syncthreads();
+    for (int j = 0; j < nblk; ++j) {
+        for (int k0 = 0; k0 < kper; k0 += KC) {
+            {   // A tile: 64 rows x 8, two consecutive elements per thread
+                const int r = tid >> 2, kk = (tid & 3) * 2;
+                const long long src = nbr[j][r];
+                T a0 = (T)0, a1 = (T)0;
+                if (src >= 0) {
+                    const T* p = A + src * (long long)lda + k0 + kk;
+                    if (k0 + kk < kper) a0 = p[0];
+                    if (k0 + kk + 1 < kper) a1 = p[1];
+                }
+                As[kk][r] = a0;
+                As[kk + 1][r] = a1;
+            }
+            {   // G tile: 8 x 64
+                const int kk = tid >> 5, c = (tid & 31) * 2;
+                const int grow = j * kper + k0 + kk;
+                T g0 = (T)0, g1 = (T)0;
+                if (k0 + kk < kper) {
+                    if (col0 + c < ldg) g0 = Gop[(long long)grow * ldg + col0 + c];
+                    if (col0 + c + 1 < ldg) g1 = Gop[(long long)grow * ldg + col0 + c + 1];
+                }
+                Gs[kk][c] = g0;
+                Gs[kk][c + 1] = g1;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+                T a[4], b[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) b[jj] = Gs[kk][tx * 4 + jj];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) acc[i][jj] += a[i] * b[jj];
+            }
+            __syncthreads();
+        }
+    }
+    // epilogue
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const long long k = row0 + ty * 4 + i;
+        if (k >= g.M) continue;
+        double dk = 1.0;
+        double zq[kMaxBlocks];
+        if (MODE == MODE_PROJECT) {
+            dk = row_scale(g, op, rd, k);
+            for (int q = 0; q < op.n_r1; ++q) zq[q] = rank1_value(g, op, rd, k, q);
+        }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int c = col0 + tx * 4 + jj;
+            if (c >= ldo) continue;
+            double v = (double)acc[i][jj];
+            if (MODE == MODE_PROJECT) {
+                const int base = op.n_gather * kper;
+                for (int q = 0; q < op.n_r1; ++q) v += zq[q] * (double)Gop[(long long)(base + q) * ldg + c];
+                v *= dk;
+            }
+            Out[k * ldo + c] = (T)v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Householder TSQR: R factor of a tall matrix
+// ---------------------------------------------------------------------------
+//
+// Each block owns a contiguous range of rows and keeps an upper-triangular R
+// (KP x KP, FP64) in LDS.  Rows arrive in chunks of NG*BR; thread (rg, c)
+// holds BR rows of column c of the chunk in registers.  For every column j the
+// reflector that zeroes the chunk's column j against R[j][j] is formed
+// (LAPACK dlarfg convention: beta = -sign(alpha) ||(alpha, x)||,
+// tau = (beta - alpha) / beta, v = x / (alpha - beta)) and applied to the
+// columns c > j of R and of the chunk.  Column-parallel: the dot products
+// v^T T[:, c] run down each thread's own registers and across row groups
+// through LDS.  The block writes its final R (KP x KP, zeros below the
+// diagonal) to Rout[blockIdx.x].
+// ncols = k1 from the state; lda is the state's ldb when lda_from_state.
+template <typename TS, int KP, int NG, int BR>
+__global__ __launch_bounds__(KP* NG) void k_tsqr(const TS* __restrict__ A, int lda_static, int lda_from_state,
+                                                 long long nrows, long long rows_per_block,
+                                                 const DevState* __restrict__ st, double* __restrict__ Rout) {
+    __shared__ double R[KP][KP];
+    __shared__ double vbuf[2][NG * BR];
+    __shared__ double pdot[2][NG][KP];
+    __shared__ double red[2][NG];
+    const int tid = threadIdx.x;
+    const int c = tid % KP, rg = tid / KP;
+    const int ncols = st->k1;
+    const int lda = lda_from_state ? st->ldb : lda_static;
+    for (int idx = tid; idx < KP * KP; idx += KP * NG) R[idx / KP][idx % KP] = 0.0;
+    __syncthreads();
+    const long long begin = (long long)blockIdx.x * rows_per_block;
+    long long end = begin + rows_per_block;
+    if (end > nrows) end = nrows;
+    double T[BR];
+    for (long long k0 = begin; k0 < end; k0 += NG * BR) {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            const long long row = k0 + rg * BR + i;
+            T[i] = (row < end && c < ncols) ? (double)A[row * lda + c] : 0.0;
+        }
+        for (int j = 0; j < ncols; ++j) {
+            const int p = j & 1;
+            if (c == j) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < BR; ++i) s += T[i] * T[i];
+                red[p][rg] = s;
+            }
+            __syncthreads();
+            double xn2 = 0.0;
+#pragma unroll
+            for (int q = 0; q < NG; ++q) xn2 += red[p][q];
+            if (xn2 != xn2) {             // NaN in the data: poison R so it reaches the SVD
+                if (c == j && rg == 0) R[j][j] = xn2;
+                continue;
+            }
+            if (!(xn2 > 0.0)) continue;   // uniform: nothing to annihilate in this column
+            const double alpha = R[j][j];
+            const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+            const double tau = (beta - alpha) / beta;
+            const double scal = 1.0 / (alpha - beta);
+            if (c == j) {
+#pragma unroll
+                for (int i = 0; i < BR; ++i) vbuf[p][rg * BR + i] = T[i] * scal;
+            }
+            __syncthreads();
+            double rjc = 0.0;
+            if (c > j && c < ncols) {
+                double d = 0.0;
+#pragma unroll
+                for (int i = 0; i < BR; ++i) d += vbuf[p][rg * BR + i] * T[i];
+                pdot[p][rg][c] = d;
+                rjc = R[j][c];
+            }
+            if (c == j && rg == 0) R[j][j] = beta;
+            __syncthreads();
+            if (c > j && c < ncols) {
+                double w = rjc;
+#pragma unroll
+                for (int q = 0; q < NG; ++q) w += pdot[p][q][c];
+                const double f = tau * w;
+#pragma unroll
+                for (int i = 0; i < BR; ++i) T[i] -= f * vbuf[p][rg * BR + i];
+                if (rg == 0) R[j][c] = rjc - f;
+            }
+        }
+    }
+    __syncthreads();
+    double* out = Rout + (size_t)blockIdx.x * KP * KP;
+    for (int idx = tid; idx < KP * KP; idx += KP * NG) {
+        const int i = idx / KP, j = idx % KP;
+        out[idx] = (j >= i) ? R[i][j] : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Gram accumulation (Gram rounding): G = B^T B in FP64
+// ---------------------------------------------------------------------------
+// Each block accumulates the Gram matrix of its rows: thread (i, j) of a
+// 16 x 16 grid owns a 4 x 4 (KPxKP / 64 x 64) block.  Partial sums go to
+// Gout[blockIdx.x] and are added up by k_sum_parts.
+template <typename TS, int KP>
+__global__ __launch_bounds__(256) void k_gram(const TS* __restrict__ B, const DevState* __restrict__ st, long long nrows,
+                                              long long rows_per_block, double* __restrict__ Gout) {
+    constexpr int KC = 16;
+    constexpr int TPR = KP / 16;   // entries per thread per dimension
+    __shared__ double Bs[KC][KP + 1];
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4;
+    const int ncols = st->k1, ldb = st->ldb;
+    double acc[TPR][TPR];
+#pragma unroll
+    for (int i = 0; i < TPR; ++i)
+#pragma unroll
+        for (int j = 0; j < TPR; ++j) acc[i][j] = 0.0;
+    const long long begin = (long long)blockIdx.x * rows_per_block;
+    long long end = begin + rows_per_block;
+    if (end > nrows) end = nrows;
+    for (long long k0 = begin; k0 < end; k0 += KC) {
+        for (int idx = tid; idx < KC * KP; idx += 256) {
+            const int r = idx / KP, c = idx % KP;
+            const long long row = k0 + r;
+            Bs[r][c] = (row < end && c < ncols) ? (double)B[row * ldb + c] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < KC; ++r) {
+            double a[TPR], b[TPR];
+#pragma unroll
+            for (int i = 0; i < TPR; ++i) a[i] = Bs[r][ty + 16 * i];
+#pragma unroll
+            for (int j = 0; j < TPR; ++j) b[j] = Bs[r][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < TPR; ++i)
+#pragma unroll
+                for (int j = 0; j < TPR; ++j) acc[i][j] += a[i] * b[j];
+        }
+        __syncthreads();
+    }
+    double* out = Gout + (size_t)blockIdx.x * KP * KP;
+#pragma unroll
+    for (int i = 0; i < TPR; ++i)
+#pragma unroll
+        for (int j = 0; j < TPR; ++j) out[(ty + 16 * i) * KP + tx + 16 * j] = acc[i][j];
+}
+
+// out[e] = sum_p parts[p][e] for e < n (fixed summation order: deterministic).
+__global__ void k_sum_parts(const double* __restrict__ parts, int nparts, int n, double* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double s = 0.0;
+    for (int p = 0; p < nparts; ++p) s += parts[(size_t)p * n + e];
+    out[e] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Inspection: explicit first core of the pending TT sum, rows [k0, k0 + nr)
+// ---------------------------------------------------------------------------
+template <typename TS>
+__global__ void k_materialize(Geom g, OpDesc op, const DevState* __restrict__ st, const TS* __restrict__ Z,
+                              RowData rd, long long k0, long long nr, double* __restrict__ out) {
+    const int r1 = st->r1, ldz = st->ldz;
+    const int R1 = op.n_rblk * r1 + op.n_r1;
+    const long long total = nr * R1;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const long long kk = idx / R1;
+        const int col = (int)(idx % R1);
+        const long long k = k0 + kk;
+        double v;
+        if (col < op.n_rblk * r1) {
+            const int t = col / r1, a = col % r1;
+            v = op.rcoef0[t] * (double)Z[k * ldz + a];
+            if (op.rshift[t] >= 0) {
+                const int j = op.rshift[t];
+                const long long s = neighbour_row(g, k, op.gaxis[j], op.gdir[j]);
+                if (s >= 0) v += op.rcoef[t] * (double)Z[s * ldz + a];
+            }
+        } else {
+            v = rank1_value(g, op, rd, k, col - op.n_rblk * r1);
+        }
+        out[idx] = v * row_scale(g, op, rd, k);
+    }
+}
+
+// Explicit Theta_new (R1 x N_theta x R2, block diagonal) and Phi_new (R2 x N_phi).
+__global__ void k_sum_small_cores(Geom g, OpDesc op, const DevState* __restrict__ st, const double* __restrict__ Th,
+                                  const double* __restrict__ Ph, const double* __restrict__ gtab,
+                                  const double* __restrict__ htab, double* __restrict__ ThN, double* __restrict__ PhN) {
+    const int r1 = st->r1, r2 = st->r2, nt = g.nt, npn = g.np;
+    const int nrb = op.n_rblk, nr1 = op.n_r1;
+    const int R1 = nrb * r1 + nr1, R2 = nrb * r2 + nr1;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < R1 * nt * R2; idx += gridDim.x * blockDim.x) {
+        const int col = idx % R2, rl = idx / R2;
+        const int row = rl / nt, l = rl % nt;
+        double v = 0.0;
+        if (row < nrb * r1) {
+            const int t = row / r1, a = row % r1;
+            if (col >= t * r2 && col < (t + 1) * r2)
+                v = Th[((size_t)a * nt + l) * r2 + (col - t * r2)] * gtab[op.rfac[t] * nt + l];
+        } else {
+            const int q = row - nrb * r1;
+            if (col == nrb * r2 + q) v = gtab[op.r1fac[q] * nt + l];
+        }
+        ThN[idx] = v;
+    }
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < R2 * npn; idx += gridDim.x * blockDim.x) {
+        const int col = idx / npn, p = idx % npn;
+        double v;
+        if (col < nrb * r2) {
+            const int t = col / r2, b = col % r2;
+            v = Ph[(size_t)b * npn + p] * htab[op.rfac[t] * npn + p];
+        } else {
+            v = htab[op.r1fac[col - nrb * r2] * npn + p];
+        }
+        PhN[idx] = v;
+    }
+}
+
+// Column sums of Z (r1 entries) and the NaN/Inf check, for diagnostics.
+template <typename TS>
+__global__ void k_colsum(const DevState* __restrict__ st, const TS* __restrict__ Z, long long M,
+                         double* __restrict__ parts) {
+    const int r1 = st->r1, ldz = st->ldz;
+    __shared__ double sh[256];
+    for (int a = 0; a < r1; ++a) {
+        double s = 0.0;
+        for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < M; k += (long long)gridDim.x * blockDim.x)
+            s += (double)Z[k * ldz + a];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+            if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) parts[(size_t)blockIdx.x * 128 + a] = sh[0];
+        __syncthreads();
+    }
+}
+
+}  // namespace ttrt

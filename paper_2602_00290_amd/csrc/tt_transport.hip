@@ -1,0 +1,886 @@
+// Host runtime and C ABI of the TT multigroup transport library (gfx950).
+//
+// One rounding pass (a "round") over the pending operator runs these kernels
+// on the caller's stream, with every rank decided on the device:
+//   k_prep         right-to-left QR of the small cores of the TT sum; builds
+//                  the gather operand G = fold(L_Theta)            (1 block)
+//   k_gather_gemm  B = Z_new L_Theta without forming Z_new           (project)
+//   k_tsqr x L     Householder TSQR of B -> R_B   (or k_gram + k_sum_parts)
+//   k_svd_chain    SVD of R_B, truncation of both bonds, new Theta/Phi (1 block)
+//   k_gather_gemm  Z_out = B V_r                                     (output)
+//   k_commit       new ranks become current
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/tt_transport.h"
+#include "k_big.hpp"
+#include "k_small.hpp"
+#include "tt_common.hpp"
+
+namespace ttrt {
+void group_emission(const double* edges, int n_groups, double T, double* out);
+}
+
+using namespace ttrt;
+
+namespace {
+
+thread_local std::string g_err;
+
+tt_status fail(tt_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail(TT_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+enum KClass { KC_PREP = 0, KC_PROJECT = 1, KC_FACTOR = 2, KC_TREE = 3, KC_SVD = 4, KC_OUTPUT = 5, KC_DIAG = 6 };
+
+struct Plan {
+    int dim = 1, nx = 1, ny = 1, nz = 1;
+    long long NX = 0, M = 0;
+    int G = 0, nt = 0, np = 0;
+    int n_terms = 0, n_bc = 0, cap = 1;
+    int r1cap = 1, r2cap = 1, R1cap = 1, R2cap = 1, k1cap = 1, k2cap = 1, ldzcap = 8, ldbcap = 8;
+    int n_gather_max = 1, n_r1_max = 1;
+    int KP = 64, chunk = 128;
+    std::vector<int> levP;          // blocks per TSQR level
+    std::vector<long long> levRows; // rows per block per level
+    std::vector<long long> levN;    // rows of the level input
+    int Pg = 1;
+    long long rowsg = 0;
+    size_t elem = 8;                // bytes per stored element of Z / B
+    // workspace layout (byte offsets)
+    size_t o_state, o_Z0, o_Z1, o_B, o_Th0, o_Th1, o_Ph0, o_Ph1, o_LTh, o_QTh, o_QPh, o_G, o_V, o_RA, o_RB, o_small,
+        o_k0, o_ks, o_eps, o_ghost, o_gtab, o_htab, o_ThN, o_PhN, o_sv, o_colsum;
+    size_t small_bytes = 0, n_parts_max = 1;
+    size_t bytes = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool is_inflow(int kind) { return kind == TT_BC_INFLOW_PLANCK || kind == TT_BC_INFLOW_VALUES; }
+
+tt_status validate(const tt_problem* p) {
+    if (!p) return fail(TT_ERR_INVALID_ARG, "problem is NULL");
+    if (p->dim < 1 || p->dim > 3) return fail(TT_ERR_INVALID_ARG, "dim must be 1, 2 or 3");
+    for (int d = 0; d < p->dim; ++d) {
+        if (p->n_cells[d] < 1) return fail(TT_ERR_INVALID_ARG, "n_cells must be >= 1");
+        if (!(p->extent[d] > 0.0)) return fail(TT_ERR_INVALID_ARG, "extent must be > 0");
+    }
+    if (p->n_groups < 1 || !p->group_edges) return fail(TT_ERR_INVALID_ARG, "need n_groups >= 1 and group_edges");
+    if (!(p->group_edges[0] >= 0.0)) return fail(TT_ERR_INVALID_ARG, "group_edges[0] must be >= 0");
+    for (int g = 0; g < p->n_groups; ++g)
+        if (!(p->group_edges[g + 1] > p->group_edges[g])) return fail(TT_ERR_INVALID_ARG, "group edges must increase");
+    if (!p->kappa0 || !p->kappa_group_scale || !p->T_cell) return fail(TT_ERR_INVALID_ARG, "kappa0, kappa_group_scale and T_cell are required");
+    if (p->n_theta < 1 || !p->mu || !p->w_theta) return fail(TT_ERR_INVALID_ARG, "need n_theta >= 1, mu and w_theta");
+    if (p->n_phi < 1 || !p->w_phi) return fail(TT_ERR_INVALID_ARG, "need n_phi >= 1 and w_phi");
+    if (p->dim == 1 && p->n_phi != 1) return fail(TT_ERR_INVALID_ARG, "dim == 1 requires n_phi == 1");
+    if (p->dim > 1 && !p->phi) return fail(TT_ERR_INVALID_ARG, "phi is required for dim > 1");
+    for (int l = 0; l < p->n_theta; ++l)
+        if (!(p->mu[l] >= -1.0 && p->mu[l] <= 1.0)) return fail(TT_ERR_INVALID_ARG, "mu must lie in [-1, 1]");
+    for (int f = 0; f < 6; ++f) {
+        if (p->bc[f] < 0 || p->bc[f] > 3) return fail(TT_ERR_INVALID_ARG, "unknown boundary kind");
+        if (f < 2 * p->dim && p->bc[f] == TT_BC_INFLOW_VALUES && !p->bc_values)
+            return fail(TT_ERR_INVALID_ARG, "TT_BC_INFLOW_VALUES needs bc_values");
+        if (f < 2 * p->dim && p->bc[f] == TT_BC_INFLOW_PLANCK && !(p->bc_T[f] >= 0.0))
+            return fail(TT_ERR_INVALID_ARG, "bc_T must be >= 0");
+    }
+    for (int d = 0; d < p->dim; ++d)
+        if ((p->bc[2 * d] == TT_BC_PERIODIC) != (p->bc[2 * d + 1] == TT_BC_PERIODIC))
+            return fail(TT_ERR_INVALID_ARG, "periodic boundaries must be set on both faces of an axis");
+    if (!(p->c > 0.0) || !(p->cfl > 0.0)) return fail(TT_ERR_INVALID_ARG, "c and cfl must be > 0");
+    if (!(p->tol >= 0.0)) return fail(TT_ERR_INVALID_ARG, "tol must be >= 0");
+    if (p->rank_cap < 1) return fail(TT_ERR_INVALID_ARG, "rank_cap must be >= 1");
+    if (p->precision < 0 || p->precision > 2) return fail(TT_ERR_INVALID_ARG, "unknown precision");
+    if (p->precision == TT_PREC_BF16X) return fail(TT_ERR_INVALID_ARG, "TT_PREC_BF16X is not available in this build");
+    if (p->round_method < 0 || p->round_method > 1) return fail(TT_ERR_INVALID_ARG, "unknown round_method");
+    if (p->paper_step_order < 0 || p->paper_step_order > 1) return fail(TT_ERR_INVALID_ARG, "paper_step_order must be 0 or 1");
+    return TT_OK;
+}
+
+tt_status make_plan(const tt_problem* p, Plan& P) {
+    tt_status s = validate(p);
+    if (s != TT_OK) return s;
+    P.dim = p->dim;
+    P.nx = p->n_cells[0];
+    P.ny = p->dim > 1 ? p->n_cells[1] : 1;
+    P.nz = p->dim > 2 ? p->n_cells[2] : 1;
+    P.NX = (long long)P.nx * P.ny * P.nz;
+    P.G = p->n_groups;
+    P.M = P.NX * P.G;
+    P.nt = p->n_theta;
+    P.np = p->n_phi;
+    P.n_terms = 2 * p->dim;
+    P.n_bc = 0;
+    for (int f = 0; f < 2 * p->dim; ++f) P.n_bc += is_inflow(p->bc[f]) ? 1 : 0;
+    P.cap = p->rank_cap;
+    const long long full1 = std::min<long long>(P.M, (long long)P.nt * P.np);
+    P.r1cap = (int)std::min<long long>(P.cap, full1);
+    P.r2cap = std::min(P.cap, P.np);
+    const int nrb = 1 + P.n_terms;
+    P.n_r1_max = P.n_bc + 1;
+    P.n_gather_max = 1 + P.n_terms;
+    P.R1cap = nrb * P.r1cap + P.n_r1_max;
+    P.R2cap = nrb * P.r2cap + P.n_r1_max;
+    P.k2cap = std::min(P.R2cap, P.np);
+    P.k1cap = std::min(P.R1cap, P.nt * P.k2cap);
+    P.ldzcap = ld_for_rank(P.r1cap);
+    P.ldbcap = ld_for_rank(P.k1cap);
+    if (P.k1cap > 128) return fail(TT_ERR_INVALID_ARG, "projected first-core rank above 128 is not supported by this build");
+    P.KP = P.k1cap <= 64 ? 64 : 128;
+    P.chunk = P.KP == 64 ? 8 * 16 : 4 * 16;
+    P.elem = p->precision == TT_PREC_FP64 ? 8 : 4;
+    // TSQR levels
+    {
+        long long n = P.M;
+        int P1 = (int)std::min<long long>(2048, std::max<long long>(1, (n + 4 * P.chunk - 1) / (4 * P.chunk)));
+        long long rows = (n + P1 - 1) / P1;
+        rows = (rows + P.chunk - 1) / P.chunk * P.chunk;
+        P1 = (int)((n + rows - 1) / rows);
+        P.levP.push_back(P1); P.levRows.push_back(rows); P.levN.push_back(n);
+        int prev = P1;
+        while (prev > 1) {
+            long long nn = (long long)prev * P.KP;
+            long long rr = 4LL * P.chunk;
+            int Pn = (int)((nn + rr - 1) / rr);
+            P.levP.push_back(Pn); P.levRows.push_back(rr); P.levN.push_back(nn);
+            prev = Pn;
+        }
+        P.n_parts_max = (size_t)P.levP[0];
+    }
+    {
+        long long rows = std::max<long long>(64, (P.M + 1023) / 1024);
+        rows = (rows + 15) / 16 * 16;
+        P.Pg = (int)((P.M + rows - 1) / rows);
+        P.rowsg = rows;
+        P.n_parts_max = std::max<size_t>(P.n_parts_max, (size_t)P.Pg);
+    }
+    // layout
+    size_t off = 0;
+    auto take = [&](size_t b) { size_t o = off; off = align256(off + std::max<size_t>(b, 8)); return o; };
+    const size_t d = sizeof(double);
+    P.o_state = take(sizeof(DevState));
+    P.o_Z0 = take((size_t)P.M * P.ldzcap * P.elem);
+    P.o_Z1 = take((size_t)P.M * P.ldzcap * P.elem);
+    P.o_B = take((size_t)P.M * P.ldbcap * P.elem);
+    P.o_Th0 = take((size_t)P.r1cap * P.nt * P.r2cap * d);
+    P.o_Th1 = take((size_t)P.r1cap * P.nt * P.r2cap * d);
+    P.o_Ph0 = take((size_t)P.r2cap * P.np * d);
+    P.o_Ph1 = take((size_t)P.r2cap * P.np * d);
+    P.o_LTh = take((size_t)P.R1cap * P.k1cap * d);
+    P.o_QTh = take((size_t)P.k1cap * P.nt * P.k2cap * d);
+    P.o_QPh = take((size_t)P.k2cap * P.np * d);
+    P.o_G = take((size_t)(P.n_gather_max * P.ldzcap + P.n_r1_max) * P.ldbcap * P.elem);
+    P.o_V = take((size_t)P.ldbcap * P.ldzcap * P.elem);
+    P.o_RA = take(P.n_parts_max * P.KP * P.KP * d);
+    P.o_RB = take(P.n_parts_max * P.KP * P.KP * d);
+    // small scratch: A1, Q1, A2, Q2, tau, J, Th2, C2, V2, sv, perm, flag
+    const size_t m2 = (size_t)P.nt * P.k2cap;
+    P.small_bytes = 0;
+    P.small_bytes += align256((size_t)P.np * P.R2cap * d);
+    P.small_bytes += align256((size_t)P.np * P.k2cap * d);
+    P.small_bytes += align256(std::max(m2 * P.R1cap, (size_t)P.k1cap * P.k1cap) * d);
+    P.small_bytes += align256(m2 * P.k1cap * d);
+    P.small_bytes += align256((size_t)std::max(P.R1cap, P.R2cap) * d);
+    P.small_bytes += align256((size_t)P.k1cap * P.k1cap * d);
+    P.small_bytes += align256((size_t)P.r1cap * m2 * d);
+    P.small_bytes += align256((size_t)P.r1cap * P.nt * P.k2cap * d);
+    P.small_bytes += align256((size_t)P.k2cap * P.k2cap * d);
+    P.small_bytes += align256((size_t)(P.k1cap + P.k2cap) * d);
+    P.small_bytes += align256((size_t)(P.k1cap + P.k2cap) * sizeof(int));
+    P.small_bytes += align256(sizeof(int));
+    P.o_small = take(P.small_bytes);
+    P.o_k0 = take((size_t)P.NX * d);
+    P.o_ks = take((size_t)P.G * d);
+    P.o_eps = take((size_t)P.M * d);
+    P.o_ghost = take((size_t)6 * P.G * d);
+    P.o_gtab = take((size_t)(1 + P.n_terms) * P.nt * d);
+    P.o_htab = take((size_t)(1 + P.n_terms) * P.np * d);
+    P.o_ThN = take((size_t)P.R1cap * P.nt * P.R2cap * d);
+    P.o_PhN = take((size_t)P.R2cap * P.np * d);
+    P.o_sv = take((size_t)(P.k1cap + P.k2cap) * d);
+    P.o_colsum = take((size_t)256 * 128 * d);
+    P.bytes = off;
+    return TT_OK;
+}
+
+}  // namespace
+
+struct tt_handle {
+    Plan P;
+    Geom geom{};
+    int precision = 0, round_method = 0, step_order = 0;
+    double tol = 0.0;
+    double dt = 0.0;
+    double dV = 1.0;
+    char* ws = nullptr;
+    hipStream_t create_stream = nullptr;
+    int zcur = 0, ccur = 0;
+    int pending = OP_NONE;
+    OpDesc ops[4];
+    std::vector<double> w_theta, w_phi;
+    std::vector<double> eps_host;
+    // timing
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+    std::vector<int> ev_class;
+    size_t ev_used = 0;
+    double kernel_ms[8] = {0};
+    long long kernel_launches[8] = {0};
+    double flops[8] = {0};
+    double last_seconds = 0.0;
+    int last_steps = 0;
+
+    template <typename T>
+    T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+    DevState* st() const { return at<DevState>(P.o_state); }
+    void* Zc() const { return ws + (zcur ? P.o_Z1 : P.o_Z0); }
+    void* Zn() const { return ws + (zcur ? P.o_Z0 : P.o_Z1); }
+    double* Thc() const { return at<double>(ccur ? P.o_Th1 : P.o_Th0); }
+    double* Thn() const { return at<double>(ccur ? P.o_Th0 : P.o_Th1); }
+    double* Phc() const { return at<double>(ccur ? P.o_Ph1 : P.o_Ph0); }
+    double* Phn() const { return at<double>(ccur ? P.o_Ph0 : P.o_Ph1); }
+    RowData rowdata() const { return RowData{at<double>(P.o_k0), at<double>(P.o_ks), at<double>(P.o_eps), at<double>(P.o_ghost)}; }
+    SmallScratch scratch() const {
+        SmallScratch s;
+        char* b = ws + P.o_small;
+        const size_t d = sizeof(double);
+        const size_t m2 = (size_t)P.nt * P.k2cap;
+        s.A1 = (double*)b; b += align256((size_t)P.np * P.R2cap * d);
+        s.Q1 = (double*)b; b += align256((size_t)P.np * P.k2cap * d);
+        s.A2 = (double*)b; b += align256(std::max(m2 * P.R1cap, (size_t)P.k1cap * P.k1cap) * d);
+        s.Q2 = (double*)b; b += align256(m2 * P.k1cap * d);
+        s.tau = (double*)b; b += align256((size_t)std::max(P.R1cap, P.R2cap) * d);
+        s.J = (double*)b; b += align256((size_t)P.k1cap * P.k1cap * d);
+        s.Th2 = (double*)b; b += align256((size_t)P.r1cap * m2 * d);
+        s.C2 = (double*)b; b += align256((size_t)P.r1cap * P.nt * P.k2cap * d);
+        s.V2 = (double*)b; b += align256((size_t)P.k2cap * P.k2cap * d);
+        s.sv = (double*)b; b += align256((size_t)(P.k1cap + P.k2cap) * d);
+        s.perm = (int*)b; b += align256((size_t)(P.k1cap + P.k2cap) * sizeof(int));
+        s.flag = (int*)b;
+        return s;
+    }
+
+    // event timing around one launch
+    size_t ev_begin(int cls, hipStream_t s) {
+        if (!timing) return (size_t)-1;
+        if (ev_used == ev_pool.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return (size_t)-1;
+            ev_pool.push_back({a, b});
+            ev_class.push_back(cls);
+        }
+        ev_class[ev_used] = cls;
+        hipEventRecord(ev_pool[ev_used].first, s);
+        return ev_used++;
+    }
+    void ev_end(size_t i, hipStream_t s) {
+        if (i == (size_t)-1) return;
+        hipEventRecord(ev_pool[i].second, s);
+    }
+    void ev_collect() {
+        for (size_t i = 0; i < ev_used; ++i) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev_pool[i].first, ev_pool[i].second) == hipSuccess) {
+                kernel_ms[ev_class[i]] += ms;
+                kernel_launches[ev_class[i]] += 1;
+            }
+        }
+        ev_used = 0;
+    }
+};
+
+namespace {
+
+void build_ops(tt_handle* h, const tt_problem* p) {
+    const Plan& P = h->P;
+    auto term_index = [&](int axis, int sign) { return 1 + 2 * axis + (sign > 0 ? 0 : 1); };
+    for (int kind = 0; kind < 4; ++kind) {
+        OpDesc& o = h->ops[kind];
+        std::memset(&o, 0, sizeof(o));
+        for (int i = 0; i < kMaxBlocks; ++i) o.rshift[i] = -1;
+        o.n_rblk = 1;
+        o.rfac[0] = 0;
+        o.rcoef0[0] = 1.0;
+        o.n_gather = 1;
+        const bool stream = kind == OP_FULL || kind == OP_TRANSPORT;
+        const bool source = kind == OP_FULL || kind == OP_SOURCE;
+        if (stream) {
+            for (int axis = 0; axis < P.dim; ++axis) {
+                for (int sign = 1; sign >= -1; sign -= 2) {
+                    const int t = o.n_rblk++;
+                    const double lam = h->geom.lam[axis];
+                    o.rfac[t] = term_index(axis, sign);
+                    const int j = o.n_gather++;
+                    o.gaxis[j] = axis;
+                    // the (d,+) term reads the upwind neighbour c - e_d; the (d,-) term c + e_d
+                    o.gdir[j] = sign > 0 ? -1 : +1;
+                    o.rshift[t] = j;
+                    o.rcoef0[t] = sign > 0 ? -lam : lam;
+                    o.rcoef[t] = sign > 0 ? lam : -lam;
+                }
+            }
+            for (int f = 0; f < 2 * P.dim; ++f) {
+                if (!is_inflow(p->bc[f])) continue;
+                const int q = o.n_r1++;
+                o.r1kind[q] = 1;
+                o.r1face[q] = f;
+                o.r1fac[q] = term_index(f / 2, (f & 1) ? -1 : +1);
+            }
+        }
+        if (source) {
+            const int q = o.n_r1++;
+            o.r1kind[q] = 0;
+            o.r1fac[q] = 0;
+            o.scale_d = 1;
+        }
+    }
+}
+
+template <typename T>
+tt_status upload(void* dst, const std::vector<T>& v, hipStream_t s) {
+    if (v.empty()) return TT_OK;
+    HIP_TRY(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return TT_OK;
+}
+
+tt_status read_state(tt_handle* h, DevState& out, hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(&out, h->st(), sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return TT_OK;
+}
+
+tt_status write_state(tt_handle* h, const DevState& in, hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(h->st(), &in, sizeof(DevState), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return TT_OK;
+}
+
+template <typename T>
+tt_status set_cores_impl(tt_handle* h, int r1, int r2, const double* Z, const double* Th, const double* Ph,
+                         hipStream_t s) {
+    const Plan& P = h->P;
+    const int ldz = ld_for_rank(r1);
+    std::vector<T> zb((size_t)P.M * ldz, (T)0);
+    for (long long k = 0; k < P.M; ++k)
+        for (int a = 0; a < r1; ++a) zb[(size_t)k * ldz + a] = (T)Z[(size_t)k * r1 + a];
+    h->zcur = 0;
+    h->ccur = 0;
+    HIP_TRY(hipMemcpyAsync(h->Zc(), zb.data(), zb.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h->Thc(), Th, (size_t)r1 * P.nt * r2 * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h->Phc(), Ph, (size_t)r2 * P.np * sizeof(double), hipMemcpyHostToDevice, s));
+    DevState st;
+    std::memset(&st, 0, sizeof(st));
+    st.r1 = r1; st.r2 = r2; st.ldz = ldz;
+    st.max_R1 = r1; st.max_R2 = r2;
+    h->pending = OP_NONE;
+    return write_state(h, st, s);
+}
+
+tt_status reset_impl(tt_handle* h, hipStream_t s) {
+    const Plan& P = h->P;
+    std::vector<double> th((size_t)P.nt, 1.0), ph((size_t)P.np, 1.0);
+    if (h->precision == TT_PREC_FP64) return set_cores_impl<double>(h, 1, 1, h->eps_host.data(), th.data(), ph.data(), s);
+    return set_cores_impl<float>(h, 1, 1, h->eps_host.data(), th.data(), ph.data(), s);
+}
+
+// One rounding pass applying operator `op` (OP_NONE: plain rounding).
+template <typename T>
+tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t s) {
+    const Plan& P = h->P;
+    const OpDesc& op = h->ops[opkind];
+    DevState* st = h->st();
+    SmallScratch sc = h->scratch();
+    T* Gop = h->at<T>(P.o_G);
+    T* B = h->at<T>(P.o_B);
+    T* V = h->at<T>(P.o_V);
+    double* LTh = h->at<double>(P.o_LTh);
+    double* QTh = h->at<double>(P.o_QTh);
+    double* QPh = h->at<double>(P.o_QPh);
+    size_t e;
+
+    e = h->ev_begin(KC_PREP, s);
+    hipLaunchKernelGGL(k_prep<T>, dim3(1), dim3(kSmallThreads), 0, s, h->geom, op, st, h->Thc(), h->Phc(),
+                       h->at<double>(P.o_gtab), h->at<double>(P.o_htab), sc, LTh, P.k1cap, QTh, QPh, Gop, P.ldbcap);
+    h->ev_end(e, s);
+
+    const unsigned gx = (unsigned)((P.M + 63) / 64);
+    e = h->ev_begin(KC_PROJECT, s);
+    hipLaunchKernelGGL((k_gather_gemm<T, MODE_PROJECT>), dim3(gx, (P.ldbcap + 63) / 64), dim3(256), 0, s, h->geom, op,
+                       st, (const T*)h->Zc(), (const T*)Gop, B, h->rowdata());
+    h->ev_end(e, s);
+
+    const double* RB = nullptr;
+    int ldr = P.KP;
+    int gram = 0;
+    double* RA = h->at<double>(P.o_RA);
+    double* RBuf = h->at<double>(P.o_RB);
+    if (h->round_method == TT_ROUND_QR) {
+        const double* in = nullptr;
+        double* out = RA;
+        for (size_t L = 0; L < P.levP.size(); ++L) {
+            e = h->ev_begin(L == 0 ? KC_FACTOR : KC_TREE, s);
+            if (P.KP == 64) {
+                if (L == 0)
+                    hipLaunchKernelGGL((k_tsqr<T, 64, 8, 16>), dim3(P.levP[L]), dim3(512), 0, s, (const T*)B, 0, 1,
+                                       P.levN[L], P.levRows[L], (const DevState*)st, out);
+                else
+                    hipLaunchKernelGGL((k_tsqr<double, 64, 8, 16>), dim3(P.levP[L]), dim3(512), 0, s, in, 64, 0,
+                                       P.levN[L], P.levRows[L], (const DevState*)st, out);
+            } else {
+                if (L == 0)
+                    hipLaunchKernelGGL((k_tsqr<T, 128, 4, 16>), dim3(P.levP[L]), dim3(512), 0, s, (const T*)B, 0, 1,
+                                       P.levN[L], P.levRows[L], (const DevState*)st, out);
+                else
+                    hipLaunchKernelGGL((k_tsqr<double, 128, 4, 16>), dim3(P.levP[L]), dim3(512), 0, s, in, 128, 0,
+                                       P.levN[L], P.levRows[L], (const DevState*)st, out);
+            }
+            h->ev_end(e, s);
+            in = out;
+            out = (out == RA) ? RBuf : RA;
+        }
+        RB = in;
+    } else {
+        gram = 1;
+        e = h->ev_begin(KC_FACTOR, s);
+        if (P.KP == 64)
+            hipLaunchKernelGGL((k_gram<T, 64>), dim3(P.Pg), dim3(256), 0, s, (const T*)B, (const DevState*)st, P.M,
+                               P.rowsg, RA);
+        else
+            hipLaunchKernelGGL((k_gram<T, 128>), dim3(P.Pg), dim3(256), 0, s, (const T*)B, (const DevState*)st, P.M,
+                               P.rowsg, RA);
+        h->ev_end(e, s);
+        e = h->ev_begin(KC_TREE, s);
+        const int n = P.KP * P.KP;
+        hipLaunchKernelGGL(k_sum_parts, dim3((n + 255) / 256), dim3(256), 0, s, (const double*)RA, P.Pg, n, RBuf);
+        h->ev_end(e, s);
+        RB = RBuf;
+    }
+
+    e = h->ev_begin(KC_SVD, s);
+    hipLaunchKernelGGL(k_svd_chain<T>, dim3(1), dim3(kSmallThreads), 0, s, h->geom, st, RB, ldr, gram,
+                       (const double*)QTh, (const double*)QPh, tol, std::min(cap, P.r1cap), std::min(cap, P.r2cap), sc,
+                       h->Thn(), h->Phn(), V,
+                       h->at<double>(P.o_sv));
+    h->ev_end(e, s);
+
+    e = h->ev_begin(KC_OUTPUT, s);
+    hipLaunchKernelGGL((k_gather_gemm<T, MODE_OUTPUT>), dim3(gx, (P.ldzcap + 63) / 64), dim3(256), 0, s, h->geom, op,
+                       (const DevState*)st, (const T*)B, (const T*)V, (T*)h->Zn(), h->rowdata());
+    h->ev_end(e, s);
+    hipLaunchKernelGGL(k_commit, dim3(1), dim3(64), 0, s, st);
+    HIP_TRY(hipGetLastError());
+    h->zcur ^= 1;
+    h->ccur ^= 1;
+    return TT_OK;
+}
+
+tt_status round_dispatch(tt_handle* h, int opkind, double tol, int cap, hipStream_t s) {
+    if (h->precision == TT_PREC_FP64) return round_impl<double>(h, opkind, tol, cap, s);
+    return round_impl<float>(h, opkind, tol, cap, s);
+}
+
+tt_status step_impl(tt_handle* h, hipStream_t s) {
+    tt_status r;
+    if (h->pending != OP_NONE) {
+        r = round_dispatch(h, h->pending, h->tol, h->P.cap, s);
+        h->pending = OP_NONE;
+        if (r != TT_OK) return r;
+        if (h->step_order == 1) return round_dispatch(h, OP_SOURCE, h->tol, h->P.cap, s);
+        return TT_OK;
+    }
+    if (h->step_order == 1) {
+        r = round_dispatch(h, OP_TRANSPORT, h->tol, h->P.cap, s);
+        if (r != TT_OK) return r;
+        return round_dispatch(h, OP_SOURCE, h->tol, h->P.cap, s);
+    }
+    return round_dispatch(h, OP_FULL, h->tol, h->P.cap, s);
+}
+
+template <typename T>
+tt_status energy_impl(tt_handle* h, hipStream_t s, double* energy, int* nanflag) {
+    const Plan& P = h->P;
+    DevState st;
+    tt_status r = read_state(h, st, s);
+    if (r != TT_OK) return r;
+    double* parts = h->at<double>(P.o_colsum);
+    hipLaunchKernelGGL(k_colsum<T>, dim3(256), dim3(256), 0, s, (const DevState*)h->st(), (const T*)h->Zc(), P.M, parts);
+    HIP_TRY(hipGetLastError());
+    std::vector<double> hp((size_t)256 * 128);
+    std::vector<double> th((size_t)st.r1 * P.nt * st.r2), ph((size_t)st.r2 * P.np);
+    HIP_TRY(hipMemcpyAsync(hp.data(), parts, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(th.data(), h->Thc(), th.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ph.data(), h->Phc(), ph.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double E = 0.0;
+    bool bad = false;
+    for (int a = 0; a < st.r1; ++a) {
+        double cs = 0.0;
+        for (int b = 0; b < 256; ++b) cs += hp[(size_t)b * 128 + a];
+        if (!std::isfinite(cs)) bad = true;
+        // e_a = sum_{l,q} Theta[a,l,q] w_l sum_p Phi[q,p] w_p
+        double ea = 0.0;
+        for (int l = 0; l < P.nt; ++l)
+            for (int q = 0; q < st.r2; ++q) {
+                double pw = 0.0;
+                for (int p = 0; p < P.np; ++p) pw += ph[(size_t)q * P.np + p] * h->w_phi[p];
+                ea += th[((size_t)a * P.nt + l) * st.r2 + q] * h->w_theta[l] * pw;
+            }
+        E += cs * ea;
+    }
+    *energy = E * h->dV;
+    *nanflag = (bad || st.nan_flag) ? 1 : 0;
+    return TT_OK;
+}
+
+tt_status fill_stats(tt_handle* h, tt_stats* out, hipStream_t s) {
+    DevState st;
+    tt_status r = read_state(h, st, s);
+    if (r != TT_OK) return r;
+    const Plan& P = h->P;
+    std::memset(out, 0, sizeof(*out));
+    out->steps = h->last_steps;
+    out->r1 = st.r1;
+    out->r2 = st.r2;
+    out->max_R1 = st.max_R1;
+    out->max_R2 = st.max_R2;
+    out->norm = st.norm;
+    out->discarded_rel = st.norm > 0 ? std::sqrt(std::max(st.disc2, 0.0)) / st.norm : 0.0;
+    double E = 0.0;
+    int bad = 0;
+    r = (h->precision == TT_PREC_FP64) ? energy_impl<double>(h, s, &E, &bad) : energy_impl<float>(h, s, &E, &bad);
+    if (r != TT_OK) return r;
+    out->energy = E;
+    out->nan_flag = bad;
+    const double dense = (double)P.M * P.nt * P.np;
+    const double tt = (double)P.M * st.r1 + (double)P.nt * st.r1 * st.r2 + (double)P.np * st.r2;
+    out->compression = dense / tt;
+    // peak working set of a round (input Z, projected core B, output Z) over the rounded TT
+    const double peak = (double)P.M * (st.r1 + P.k1cap + st.r1) + (double)P.nt * P.R1cap * P.R2cap;
+    out->k_s = peak / tt;
+    out->seconds = h->last_seconds;
+    for (int i = 0; i < 8; ++i) {
+        out->kernel_ms[i] = h->kernel_ms[i];
+        out->kernel_launches[i] = h->kernel_launches[i];
+    }
+    out->flops[KC_PROJECT] = st.fl[0];
+    out->flops[KC_FACTOR] = st.fl[1];
+    out->flops[KC_OUTPUT] = st.fl[2];
+    return TT_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+size_t tt_transport_workspace_bytes(const tt_problem* p) {
+    Plan P;
+    if (make_plan(p, P) != TT_OK) return 0;
+    return P.bytes;
+}
+
+tt_status tt_transport_group_emission(const double* edges, int n_groups, double T, double* out) {
+    if (!edges || !out || n_groups < 1) return fail(TT_ERR_INVALID_ARG, "bad arguments");
+    ttrt::group_emission(edges, n_groups, T, out);
+    return TT_OK;
+}
+
+tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t bytes, void* stream, tt_handle** out) {
+    if (!out) return fail(TT_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    Plan P;
+    tt_status r = make_plan(p, P);
+    if (r != TT_OK) return r;
+    if (!dev_workspace) return fail(TT_ERR_INVALID_ARG, "workspace is NULL");
+    if (bytes < P.bytes) return fail(TT_ERR_OOM, "workspace too small: need " + std::to_string(P.bytes) + " bytes");
+    if (((uintptr_t)dev_workspace) & 255) return fail(TT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    for (long long i = 0; i < P.NX; ++i)
+        if (!(p->kappa0[i] >= 0.0) || !std::isfinite(p->kappa0[i]) || !(p->T_cell[i] >= 0.0))
+            return fail(TT_ERR_INVALID_ARG, "kappa0 and T_cell must be finite and >= 0");
+    for (int g = 0; g < P.G; ++g)
+        if (!(p->kappa_group_scale[g] >= 0.0) || !std::isfinite(p->kappa_group_scale[g]))
+            return fail(TT_ERR_INVALID_ARG, "kappa_group_scale must be finite and >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    tt_handle* h = new tt_handle();
+    h->P = P;
+    h->precision = p->precision;
+    h->round_method = p->round_method;
+    h->step_order = p->paper_step_order;
+    h->tol = p->tol;
+    h->ws = (char*)dev_workspace;
+    h->create_stream = s;
+    // geometry and time step: dt = cfl / (c sum_d 1/dx_d)
+    Geom& g = h->geom;
+    g.dim = P.dim; g.nx = P.nx; g.ny = P.ny; g.nz = P.nz; g.G = P.G; g.M = P.M; g.nt = P.nt; g.np = P.np;
+    g.n_terms = P.n_terms; g.n_bc = P.n_bc;
+    double inv = 0.0;
+    h->dV = 1.0;
+    for (int d = 0; d < P.dim; ++d) {
+        const double dx = p->extent[d] / p->n_cells[d];
+        inv += 1.0 / dx;
+        h->dV *= dx;
+    }
+    h->dt = p->cfl / (p->c * inv);
+    g.cdt = p->c * h->dt;
+    for (int d = 0; d < 3; ++d) {
+        g.periodic[d] = (d < P.dim && p->bc[2 * d] == TT_BC_PERIODIC) ? 1 : 0;
+        g.lam[d] = d < P.dim ? p->c * h->dt / (p->extent[d] / p->n_cells[d]) : 0.0;
+    }
+    {
+        int q = 0;
+        for (int f = 0; f < 2 * P.dim; ++f)
+            if (is_inflow(p->bc[f])) g.bc_face[q++] = f;
+    }
+    build_ops(h, p);
+    h->w_theta.assign(p->w_theta, p->w_theta + P.nt);
+    h->w_phi.assign(p->w_phi, p->w_phi + P.np);
+    // emission per merged row, from the distinct cell temperatures
+    std::vector<double> eps((size_t)P.M);
+    {
+        std::map<double, std::vector<double>> cache;
+        for (long long c = 0; c < P.NX; ++c) {
+            auto it = cache.find(p->T_cell[c]);
+            if (it == cache.end()) {
+                std::vector<double> e((size_t)P.G);
+                ttrt::group_emission(p->group_edges, P.G, p->T_cell[c], e.data());
+                it = cache.emplace(p->T_cell[c], std::move(e)).first;
+            }
+            std::copy(it->second.begin(), it->second.end(), eps.begin() + c * P.G);
+        }
+    }
+    h->eps_host = eps;
+    std::vector<double> ghost((size_t)6 * P.G, 0.0);
+    for (int f = 0; f < 2 * P.dim; ++f) {
+        if (p->bc[f] == TT_BC_INFLOW_PLANCK) ttrt::group_emission(p->group_edges, P.G, p->bc_T[f], &ghost[(size_t)f * P.G]);
+        if (p->bc[f] == TT_BC_INFLOW_VALUES)
+            for (int gg = 0; gg < P.G; ++gg) ghost[(size_t)f * P.G + gg] = p->bc_values[(size_t)f * P.G + gg];
+    }
+    // angular factors of each operator term: g(l) h(p) = positive / negative part of n_d
+    const int nf = 1 + P.n_terms;
+    std::vector<double> gtab((size_t)nf * P.nt, 1.0), htab((size_t)nf * P.np, 1.0);
+    for (int axis = 0; axis < P.dim; ++axis) {
+        for (int si = 0; si < 2; ++si) {
+            const int t = 1 + 2 * axis + si;
+            const bool pos = si == 0;
+            for (int l = 0; l < P.nt; ++l) {
+                const double mu = p->mu[l];
+                const double st = std::sqrt(std::max(0.0, 1.0 - mu * mu));
+                double gv;
+                if (P.dim == 1 || axis == 2) gv = pos ? std::max(mu, 0.0) : std::min(mu, 0.0);
+                else gv = st;
+                gtab[(size_t)t * P.nt + l] = gv;
+            }
+            for (int pp = 0; pp < P.np; ++pp) {
+                double hv = 1.0;
+                if (P.dim > 1 && axis < 2) {
+                    const double v = axis == 0 ? std::cos(p->phi[pp]) : std::sin(p->phi[pp]);
+                    hv = pos ? std::max(v, 0.0) : std::min(v, 0.0);
+                }
+                htab[(size_t)t * P.np + pp] = hv;
+            }
+        }
+    }
+    std::vector<double> k0(p->kappa0, p->kappa0 + P.NX), ks(p->kappa_group_scale, p->kappa_group_scale + P.G);
+    tt_status u;
+    if ((u = upload(h->at<double>(P.o_k0), k0, s)) != TT_OK) { delete h; return u; }
+    if ((u = upload(h->at<double>(P.o_ks), ks, s)) != TT_OK) { delete h; return u; }
+    if ((u = upload(h->at<double>(P.o_eps), eps, s)) != TT_OK) { delete h; return u; }
+    if ((u = upload(h->at<double>(P.o_ghost), ghost, s)) != TT_OK) { delete h; return u; }
+    if ((u = upload(h->at<double>(P.o_gtab), gtab, s)) != TT_OK) { delete h; return u; }
+    if ((u = upload(h->at<double>(P.o_htab), htab, s)) != TT_OK) { delete h; return u; }
+    if (hipMemsetAsync(h->ws + P.o_G, 0, P.o_V - P.o_G, s) != hipSuccess) { delete h; return fail(TT_ERR_HIP, "memset"); }
+    if ((u = reset_impl(h, s)) != TT_OK) { delete h; return u; }
+    *out = h;
+    return TT_OK;
+}
+
+tt_status tt_transport_reset(tt_handle* h, void* stream) {
+    if (!h) return fail(TT_ERR_INVALID_ARG, "handle is NULL");
+    return reset_impl(h, (hipStream_t)stream);
+}
+
+tt_status tt_transport_apply_op(tt_handle* h, void* stream) {
+    (void)stream;
+    if (!h) return fail(TT_ERR_INVALID_ARG, "handle is NULL");
+    if (h->pending != OP_NONE) return fail(TT_ERR_STATE, "an unrounded operator is already pending");
+    h->pending = h->step_order == 1 ? OP_TRANSPORT : OP_FULL;
+    return TT_OK;
+}
+
+tt_status tt_transport_round(tt_handle* h, double tol, int rank_cap, void* stream) {
+    if (!h) return fail(TT_ERR_INVALID_ARG, "handle is NULL");
+    if (!(tol >= 0.0) || rank_cap < 1) return fail(TT_ERR_INVALID_ARG, "need tol >= 0 and rank_cap >= 1");
+    if (rank_cap > h->P.cap) rank_cap = h->P.cap;
+    const int op = h->pending;
+    h->pending = OP_NONE;
+    return round_dispatch(h, op, tol, rank_cap, (hipStream_t)stream);
+}
+
+tt_status tt_transport_solve(tt_handle* h, int n_steps, tt_stats* out, void* stream) {
+    if (!h) return fail(TT_ERR_INVALID_ARG, "handle is NULL");
+    if (n_steps < 0) return fail(TT_ERR_INVALID_ARG, "n_steps must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < 8; ++i) { h->kernel_ms[i] = 0; h->kernel_launches[i] = 0; h->flops[i] = 0; }
+    {
+        DevState st;
+        tt_status r = read_state(h, st, s);
+        if (r != TT_OK) return r;
+        for (int i = 0; i < 4; ++i) st.fl[i] = 0.0;
+        r = write_state(h, st, s);
+        if (r != TT_OK) return r;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    for (int i = 0; i < n_steps; ++i) {
+        tt_status r = step_impl(h, s);
+        if (r != TT_OK) return r;
+        if (h->timing && h->ev_used > 4096) {
+            HIP_TRY(hipStreamSynchronize(s));
+            h->ev_collect();
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    auto t1 = std::chrono::steady_clock::now();
+    h->ev_collect();
+    h->last_seconds = std::chrono::duration<double>(t1 - t0).count();
+    h->last_steps = n_steps;
+    if (out) {
+        tt_status r = fill_stats(h, out, s);
+        if (r != TT_OK) return r;
+        if (out->nan_flag) return fail(TT_ERR_NUMERIC, "NaN or Inf in the TT state");
+    }
+    return TT_OK;
+}
+
+tt_status tt_transport_get_ranks(tt_handle* h, int* r1, int* r2) {
+    if (!h) return fail(TT_ERR_INVALID_ARG, "handle is NULL");
+    DevState st;
+    tt_status r = read_state(h, st, h->create_stream);
+    if (r != TT_OK) return r;
+    if (r1) *r1 = st.r1;
+    if (r2) *r2 = st.r2;
+    return TT_OK;
+}
+
+tt_status tt_transport_get_cores(tt_handle* h, double* Z, double* Theta, double* Phi, void* stream) {
+    if (!h) return fail(TT_ERR_INVALID_ARG, "handle is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const Plan& P = h->P;
+    DevState st;
+    tt_status r = read_state(h, st, s);
+    if (r != TT_OK) return r;
+    if (h->pending != OP_NONE) {
+        // explicit TT sum: Z_new in row chunks through the B buffer, small cores directly
+        const OpDesc& op = h->ops[h->pending];
+        const int R1 = op.n_rblk * st.r1 + op.n_r1, R2 = op.n_rblk * st.r2 + op.n_r1;
+        if (Z) {
+            double* buf = h->at<double>(P.o_B);
+            const long long cap_rows = std::max<long long>(1, (long long)(P.M * P.ldbcap * P.elem / sizeof(double)) / R1);
+            for (long long k0 = 0; k0 < P.M; k0 += cap_rows) {
+                const long long nr = std::min(cap_rows, P.M - k0);
+                if (h->precision == TT_PREC_FP64)
+                    hipLaunchKernelGGL(k_materialize<double>, dim3(1024), dim3(256), 0, s, h->geom, op, (const DevState*)h->st(),
+                                       (const double*)h->Zc(), h->rowdata(), k0, nr, buf);
+                else
+                    hipLaunchKernelGGL(k_materialize<float>, dim3(1024), dim3(256), 0, s, h->geom, op, (const DevState*)h->st(),
+                                       (const float*)h->Zc(), h->rowdata(), k0, nr, buf);
+                HIP_TRY(hipGetLastError());
+                HIP_TRY(hipMemcpyAsync(Z + k0 * R1, buf, (size_t)nr * R1 * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+            }
+        }
+        hipLaunchKernelGGL(k_sum_small_cores, dim3(64), dim3(256), 0, s, h->geom, op, (const DevState*)h->st(),
+                           (const double*)h->Thc(), (const double*)h->Phc(), (const double*)h->at<double>(P.o_gtab),
+                           (const double*)h->at<double>(P.o_htab), h->at<double>(P.o_ThN), h->at<double>(P.o_PhN));
+        HIP_TRY(hipGetLastError());
+        if (Theta) HIP_TRY(hipMemcpyAsync(Theta, h->at<double>(P.o_ThN), (size_t)R1 * P.nt * R2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (Phi) HIP_TRY(hipMemcpyAsync(Phi, h->at<double>(P.o_PhN), (size_t)R2 * P.np * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return TT_OK;
+    }
+    if (Z) {
+        if (h->precision == TT_PREC_FP64) {
+            std::vector<double> zb((size_t)P.M * st.ldz);
+            HIP_TRY(hipMemcpyAsync(zb.data(), h->Zc(), zb.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            for (long long k = 0; k < P.M; ++k)
+                for (int a = 0; a < st.r1; ++a) Z[(size_t)k * st.r1 + a] = zb[(size_t)k * st.ldz + a];
+        } else {
+            std::vector<float> zb((size_t)P.M * st.ldz);
+            HIP_TRY(hipMemcpyAsync(zb.data(), h->Zc(), zb.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            for (long long k = 0; k < P.M; ++k)
+                for (int a = 0; a < st.r1; ++a) Z[(size_t)k * st.r1 + a] = zb[(size_t)k * st.ldz + a];
+        }
+    }
+    if (Theta) HIP_TRY(hipMemcpyAsync(Theta, h->Thc(), (size_t)st.r1 * P.nt * st.r2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (Phi) HIP_TRY(hipMemcpyAsync(Phi, h->Phc(), (size_t)st.r2 * P.np * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return TT_OK;
+}
+
+tt_status tt_transport_set_cores(tt_handle* h, int r1, int r2, const double* Z, const double* Theta, const double* Phi,
+                                 void* stream) {
+    if (!h) return fail(TT_ERR_INVALID_ARG, "handle is NULL");
+    if (!Z || !Theta || !Phi) return fail(TT_ERR_INVALID_ARG, "cores must not be NULL");
+    if (r1 < 1 || r2 < 1 || r1 > h->P.r1cap || r2 > h->P.r2cap)
+        return fail(TT_ERR_INVALID_ARG, "ranks must be within [1, cap] (r1 <= " + std::to_string(h->P.r1cap) +
+                                            ", r2 <= " + std::to_string(h->P.r2cap) + ")");
+    hipStream_t s = (hipStream_t)stream;
+    if (h->precision == TT_PREC_FP64) return set_cores_impl<double>(h, r1, r2, Z, Theta, Phi, s);
+    return set_cores_impl<float>(h, r1, r2, Z, Theta, Phi, s);
+}
+
+tt_status tt_transport_get_stats(tt_handle* h, tt_stats* out) {
+    if (!h || !out) return fail(TT_ERR_INVALID_ARG, "NULL argument");
+    return fill_stats(h, out, h->create_stream);
+}
+
+tt_status tt_transport_set_timing(tt_handle* h, int on) {
+    if (!h) return fail(TT_ERR_INVALID_ARG, "handle is NULL");
+    h->timing = on != 0;
+    return TT_OK;
+}
+
+tt_status tt_transport_step_batch(tt_handle** hs, int n, void* stream) {
+    if (!hs || n < 0) return fail(TT_ERR_INVALID_ARG, "bad arguments");
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j)
+            if (hs[i] == hs[j]) return fail(TT_ERR_INVALID_ARG, "handles must be distinct");
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < n; ++i) {
+        if (!hs[i]) return fail(TT_ERR_INVALID_ARG, "NULL handle");
+        tt_status r = step_impl(hs[i], s);
+        if (r != TT_OK) return r;
+    }
+    return TT_OK;
+}
+
+tt_status tt_transport_destroy(tt_handle* h) {
+    if (!h) return TT_OK;
+    for (auto& pr : h->ev_pool) {
+        hipEventDestroy(pr.first);
+        hipEventDestroy(pr.second);
+    }
+    delete h;
+    return TT_OK;
+}
+
+const char* tt_transport_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -68,9 +68,13 @@ def test_rayleigh_jeans_series():
 def test_wien_tail_closed_form():
     # large x: int_x^inf t^3 e^{-t} dt = e^{-x}(x^3 + 3x^2 + 6x + 6); the Bose
     # correction sum_{k>=2} is O(e^{-2x}), far below double precision at x = 60
-    for x in (40.0, 60.0):
+    for x in (40.0, 60.0, 105.0, 333.0, 650.0):
         ref = math.exp(-x) * (x ** 3 + 3 * x ** 2 + 6 * x + 6)
         assert planck.planck_integral(x, math.inf) == pytest.approx(ref, rel=1e-14)
+    # a finite group far in the tail: difference of the two closed-form tails
+    a, b = 105.0, 333.0
+    ref = (math.exp(-a) * (a ** 3 + 3 * a ** 2 + 6 * a + 6) - math.exp(-b) * (b ** 3 + 3 * b ** 2 + 6 * b + 6))
+    assert planck.planck_integral(a, b) == pytest.approx(ref, rel=1e-14)
 
 
 def test_zero_temperature_and_homogeneity():
