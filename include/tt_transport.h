@@ -72,9 +72,12 @@ typedef enum {
 typedef enum {
     TT_ROUND_QR = 0,    /* Householder TSQR in FP64, then an FP64 SVD of R
                            (TT-SVD rounding)                                      */
-    TT_ROUND_GRAM = 1   /* FP64 Gram matrix of the projected core, then an FP64
+    TT_ROUND_GRAM = 1,  /* FP64 Gram matrix of the projected core, then an FP64
                            symmetric eigensolver (Gram rounding, Section 3.1
                            footnote); accurate when tol >> 1e-8                  */
+    TT_ROUND_AUTO = 2   /* QR for TT_PREC_FP64; Gram for FP32 / split-BF16 data,
+                           whose own rounding (>= 6e-8) is above the Gram's
+                           FP64 accuracy floor (~1.5e-8 relative)                */
 } tt_round_method;
 
 typedef enum {

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libtt_transport.so")
 
 TT_OK, TT_ERR_INVALID_ARG, TT_ERR_OOM, TT_ERR_NUMERIC, TT_ERR_HIP, TT_ERR_STATE = 0, -1, -2, -3, -4, -5
 TT_PREC_FP64, TT_PREC_FP32, TT_PREC_BF16X = 0, 1, 2
-TT_ROUND_QR, TT_ROUND_GRAM = 0, 1
+TT_ROUND_QR, TT_ROUND_GRAM, TT_ROUND_AUTO = 0, 1, 2
 TT_BC_VACUUM, TT_BC_INFLOW_PLANCK, TT_BC_PERIODIC, TT_BC_INFLOW_VALUES = 0, 1, 2, 3
 
 KERNEL_CLASSES = ("prep", "project", "factor", "tree", "svd", "output", "diag", "unused")
@@ -184,7 +184,7 @@ class ProblemStruct:
         s.tol = float(prob.tol)
         s.rank_cap = int(prob.rank_cap)
         s.precision = int(prob.precision)
-        s.round_method = int(getattr(prob, "round_method", TT_ROUND_QR) if round_method is None else round_method)
+        s.round_method = int(getattr(prob, "round_method", TT_ROUND_AUTO) if round_method is None else round_method)
         s.paper_step_order = int(prob.step_order)
         self.s = s
 

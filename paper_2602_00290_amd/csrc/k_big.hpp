@@ -297,13 +297,33 @@ __global__ __launch_bounds__(256) void k_gram(const TS* __restrict__ B, const De
         for (int j = 0; j < TPR; ++j) out[(ty + 16 * i) * KP + tx + 16 * j] = acc[i][j];
 }
 
-// out[e] = sum_p parts[p][e] for e < n (fixed summation order: deterministic).
-__global__ void k_sum_parts(const double* __restrict__ parts, int nparts, int n, double* __restrict__ out) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += parts[(size_t)p * n + e];
-    out[e] = s;
+// out[e] = sum_p parts[p][e] for e < n.  Each block owns 32 consecutive
+// entries; its 8 waves-groups of 32 threads take every 8th part (coalesced
+// 256-byte rows), then the 8 partial sums are added in a fixed order, so the
+// result is deterministic.
+__global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ parts, int nparts, int n,
+                                                   double* __restrict__ out) {
+    __shared__ double sh[8][32];
+    const int e = blockIdx.x * 32 + (threadIdx.x & 31);
+    const int q = threadIdx.x >> 5;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (e < n) {
+        int p = q;
+        for (; p + 24 < nparts; p += 32) {
+            s0 += parts[(size_t)p * n + e];
+            s1 += parts[(size_t)(p + 8) * n + e];
+            s2 += parts[(size_t)(p + 16) * n + e];
+            s3 += parts[(size_t)(p + 24) * n + e];
+        }
+        for (; p < nparts; p += 8) s0 += parts[(size_t)p * n + e];
+    }
+    sh[q][threadIdx.x & 31] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (q == 0 && e < n) {
+        double t = 0.0;
+        for (int k = 0; k < 8; ++k) t += sh[k][threadIdx.x];
+        out[e] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -1,7 +1,6 @@
 // Single-workgroup FP64 kernels on the small cores (Theta, Phi and the R factor
-// of the first core).  All matrices here are at most a few hundred rows and
-// columns; they live in global scratch (L2 resident) and are processed by one
-// workgroup with block-level reductions.
+// or Gram matrix of the projected first core).  Working matrices live in LDS
+// when they fit (dynamic shared memory), otherwise in global scratch.
 #pragma once
 
 #include "tt_common.hpp"
@@ -9,6 +8,7 @@
 namespace ttrt {
 
 constexpr int kSmallThreads = 1024;
+constexpr int kSmallLdsBytes = 150 * 1024;
 
 // Operator description shared by the prep, projection and materialise kernels.
 struct OpDesc {
@@ -27,11 +27,44 @@ struct OpDesc {
     int scale_d;                // rows scaled by d = 1/(1 + c dt kappa)
 };
 
+// Global fallbacks and persistent small buffers of the rounding.
+struct SmallScratch {
+    double* A1;    // N_phi x R2cap
+    double* Q1;    // N_phi x N_phi + R2cap x k2cap
+    double* A2;    // (N_theta k2cap) x R1cap
+    double* Q2;    // (N_theta k2cap) x k1cap
+    double* tau;   // max(R1cap, R2cap)
+    double* J;     // k1cap x k1cap
+    double* Th2;   // r1cap x N_theta k2cap
+    double* C2;    // r1cap N_theta x k2cap
+    double* V2;    // k2cap x k2cap
+    double* sv;    // 3 k1cap + k2cap
+    int* perm;     // k1cap + k2cap
+    int* flag;
+    double* W;     // k1cap x k1cap rotations of the first-bond Jacobi
+    double* Wkeep; // k1cap x k1cap right singular vectors of the previous round
+};
+
+// Bump allocator over the dynamic LDS block, falling back to global memory.
+struct LdsCarver {
+    double* base;
+    size_t used, cap;   // in doubles
+    __device__ double* take(size_t n, double* fallback) {
+        n = (n + 1) & ~(size_t)1;
+        if (used + n <= cap) {
+            double* p = base + used;
+            used += n;
+            return p;
+        }
+        return fallback;
+    }
+};
+
 // ---------------------------------------------------------------------------
 // block-level helpers
 // ---------------------------------------------------------------------------
 
-__device__ inline double block_sum(double v, double* red) {
+__device__ __forceinline__ double block_sum(double v, double* red) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
     v = wave_sum(v);
     __syncthreads();
@@ -44,11 +77,10 @@ __device__ inline double block_sum(double v, double* red) {
 }
 
 // Householder QR of the m x n column-major matrix A (A[i + j*lda]) by the
-// whole block.  k = min(m, n) reflectors; on return the upper triangle holds
-// R (k x n) and the strict lower part of the first k columns holds the
-// reflector tails (unit leading entry implied).  tau receives k scalars.
-// Each column of the trailing matrix is handled by a group of `gs` threads.
-__device__ void block_householder_qr(double* A, int lda, int m, int n, double* tau, double* red) {
+// whole block.  k = min(m, n) reflectors (LAPACK dlarfg convention); on return
+// the upper triangle holds R (k x n) and the strict lower part of the first k
+// columns holds the reflector tails (unit leading entry implied).
+__device__ __forceinline__ void block_householder_qr(double* A, int lda, int m, int n, double* tau, double* red) {
     const int k = m < n ? m : n;
     const int nt = blockDim.x;
     for (int j = 0; j < k; ++j) {
@@ -72,7 +104,6 @@ __device__ void block_householder_qr(double* A, int lda, int m, int n, double* t
             tau[j] = t;
         }
         if (t != 0.0) {
-            // trailing columns c = j+1..n-1; groups of gs threads per column
             const int ncol = n - j - 1;
             int gs = 1;
             while (gs < 32 && gs * 2 * ncol <= nt) gs *= 2;
@@ -97,7 +128,7 @@ __device__ void block_householder_qr(double* A, int lda, int m, int n, double* t
 }
 
 // Explicit Q (m x k, column-major, Q[i + c*ldq]) from the reflectors left in A.
-__device__ void block_form_q(const double* A, int lda, int m, int k, const double* tau, double* Q, int ldq) {
+__device__ __forceinline__ void block_form_q(const double* A, int lda, int m, int k, const double* tau, double* Q, int ldq) {
     const int nt = blockDim.x;
     for (int idx = threadIdx.x; idx < m * k; idx += nt) {
         const int i = idx % m, c = idx / m;
@@ -130,85 +161,376 @@ __device__ void block_form_q(const double* A, int lda, int m, int k, const doubl
     }
 }
 
-// One-sided (Hestenes) Jacobi on the n columns of the m x n column-major
-// matrix A: rotates column pairs until all are orthogonal, so that A V = U S.
-// When V is non-null the rotations are accumulated into the n x n matrix V
-// (column-major, V[i + j*n], initialised to I here).  Pairs are scheduled by
-// the round-robin tournament so each round touches disjoint columns.
-__device__ void block_jacobi(double* A, int lda, int m, int n, double* V, int* flag, double* red) {
-    const int nt = blockDim.x;
-    if (V) {
-        for (int idx = threadIdx.x; idx < n * n; idx += nt) V[idx] = (idx % n == idx / n) ? 1.0 : 0.0;
+// Lane exchange within groups of 2..16 consecutive lanes by DPP (VALU
+// latency instead of an LDS crossbar round trip).  CTRL: 0xB1 quad xor 1,
+// 0x4E quad xor 2, 0x141 mirror within 8 lanes, 0x140 mirror within 16 lanes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_swap(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over aligned groups of gs in {1, 2, 4, 8, 16, 32} consecutive lanes;
+// every lane of a group receives the group total.
+__device__ __forceinline__ double group_sum(double v, int gs) {
+    if (gs >= 2) v += dpp_swap<0xB1>(v);
+    if (gs >= 4) v += dpp_swap<0x4E>(v);
+    if (gs >= 8) v += dpp_swap<0x141>(v);
+    if (gs >= 16) v += dpp_swap<0x140>(v);
+    if (gs >= 32) v += __shfl_xor(v, 16, 64);
+    return v;
+}
+
+// 1/x and 1/sqrt(x) from the hardware estimates refined by two Newton steps
+// (x finite and positive where used).
+__device__ __forceinline__ double rcp_refined(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ double rsq_refined(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
+// Jacobi rotation annihilating the off-diagonal g of [[a, g], [g, b]]:
+// zeta = (b - a) / 2g, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) (the smaller
+// root of t^2 + 2 zeta t - 1 = 0), c = 1/sqrt(1 + t^2), s = c t.  Applied as
+// x' = c x - s y, y' = s x + c y on the column pair.
+__device__ __forceinline__ void jacobi_rotation(double a, double b, double g, double* c, double* s, double* t) {
+    const double zeta = (b - a) * rcp_refined(2.0 * g);
+    double tt;
+    if (fabs(zeta) > 1e150) {
+        tt = 0.5 * rcp_refined(zeta);
+    } else {
+        const double q = fma(zeta, zeta, 1.0);
+        const double root = q * rsq_refined(q);
+        tt = copysign(rcp_refined(fabs(zeta) + root), zeta);
     }
+    const double cc = rsq_refined(fma(tt, tt, 1.0));
+    *c = cc;
+    *s = cc * tt;
+    *t = tt;
+}
+
+// Pair (a, b) of round `round` in the round-robin tournament over np players
+// (player 0 fixed, the others rotating); a < b.
+__device__ __forceinline__ void tournament_pair(int pp, int round, int np, int* a, int* b) {
+    const int pa = pp, pb = np - 1 - pp;
+    int x = pa == 0 ? 0 : ((pa - 1 + round) % (np - 1)) + 1;
+    int y = pb == 0 ? 0 : ((pb - 1 + round) % (np - 1)) + 1;
+    if (x > y) { const int t = x; x = y; y = t; }
+    *a = x;
+    *b = y;
+}
+
+// One-sided (Hestenes) Jacobi on the n columns of the m x n column-major A,
+// accumulating the rotations into W (n x n column-major, caller-initialised):
+// A W converges to U S with orthogonal columns, W to the right singular
+// vectors.  Column norms are tracked through the rotations
+// (alpha' = alpha - t gamma, beta' = beta + t gamma) and refreshed every sweep,
+// so each pair needs one reduction.  A rotation is applied when
+// |gamma| > 1e-15 sqrt(alpha beta) and gamma is above an absolute floor set by
+// the matrix norm.  Convergence is quadratic, so the sweeps end after one
+// whose largest rotation tangent is below 1e-8 (the next would move the
+// columns by ~1e-16); at most 40 sweeps.  Returns the number of sweeps.
+__device__ __forceinline__ int block_jacobi_1s(double* A, int lda, int m, int n, double* W, int ldw, double* nrm, int* flag,
+                                                double* red) {
     if (n < 2) {
         __syncthreads();
-        return;
+        return 0;
     }
-    const int np = (n + 1) & ~1;          // players (a dummy when n is odd)
-    const int npairs = np / 2;
-    int gs = 64;                          // threads per pair (power of two, <= 64)
+    const int nt = blockDim.x;
+    const int np = (n + 1) & ~1, npairs = np / 2;
+    int gs = 1;
+    while (gs < 16 && gs * 8 < m) gs *= 2;      // ~8 rows per thread
     while (gs > 1 && gs * npairs > nt) gs >>= 1;
     const int pair = threadIdx.x / gs, gl = threadIdx.x % gs;
-    const double eps = 1e-15;
-    for (int sweep = 0; sweep < 60; ++sweep) {
+    const int ngroups = nt / gs;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        double part = 0.0;
+        for (int j = threadIdx.x; j < n; j += nt) {
+            double acc = 0.0;
+            for (int i = 0; i < m; ++i) acc += A[i + (size_t)j * lda] * A[i + (size_t)j * lda];
+            nrm[j] = acc;
+            part += acc;
+        }
+        const double tot = block_sum(part, red);   // contains barriers
+        const double floor_abs = 1e-30 * tot;
         if (threadIdx.x == 0) *flag = 0;
         __syncthreads();
         for (int round = 0; round < np - 1; ++round) {
-            for (int pp = pair; pp < npairs; pp += nt / gs) {
-                // positions pp and np-1-pp; position 0 is fixed
-                int pa = pp, pb = np - 1 - pp;
-                int a = pa == 0 ? 0 : ((pa - 1 + round) % (np - 1)) + 1;
-                int b = pb == 0 ? 0 : ((pb - 1 + round) % (np - 1)) + 1;
-                if (a > b) { int t = a; a = b; b = t; }
-                const bool real = b < n;
-                double al = 0.0, be = 0.0, ga = 0.0;
+            for (int pp0 = 0; pp0 < npairs; pp0 += ngroups) {
+                const int pp = pp0 + pair;
+                int a = 0, b = 0;
+                bool real = false;
+                if (pp < npairs) {
+                    tournament_pair(pp, round, np, &a, &b);
+                    real = b < n;
+                }
+                double ga = 0.0;
+                if (real)
+                    for (int i = gl; i < m; i += gs) ga += A[i + (size_t)a * lda] * A[i + (size_t)b * lda];
+                ga = group_sum(ga, gs);
                 if (real) {
-                    for (int i = gl; i < m; i += gs) {
-                        const double x = A[i + (size_t)a * lda], y = A[i + (size_t)b * lda];
-                        al += x * x; be += y * y; ga += x * y;
-                    }
-                }
-                for (int off = gs >> 1; off >= 1; off >>= 1) {
-                    al += __shfl_xor(al, off, 64);
-                    be += __shfl_xor(be, off, 64);
-                    ga += __shfl_xor(ga, off, 64);
-                }
-                if (real && ga != 0.0 && fabs(ga) > eps * sqrt(al * be)) {
-                    const double zeta = (be - al) / (2.0 * ga);
-                    const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-                    for (int i = gl; i < m; i += gs) {
-                        const double x = A[i + (size_t)a * lda], y = A[i + (size_t)b * lda];
-                        A[i + (size_t)a * lda] = c * x - s * y;
-                        A[i + (size_t)b * lda] = s * x + c * y;
-                    }
-                    if (V) {
+                    const double al = nrm[a], be = nrm[b];
+                    if (fabs(ga) > 1e-15 * sqrt(al * be) && fabs(ga) > floor_abs) {
+                        double c, s, t;
+                        jacobi_rotation(al, be, ga, &c, &s, &t);
+                        for (int i = gl; i < m; i += gs) {
+                            const double x = A[i + (size_t)a * lda], y = A[i + (size_t)b * lda];
+                            A[i + (size_t)a * lda] = c * x - s * y;
+                            A[i + (size_t)b * lda] = s * x + c * y;
+                        }
                         for (int i = gl; i < n; i += gs) {
-                            const double x = V[i + (size_t)a * n], y = V[i + (size_t)b * n];
-                            V[i + (size_t)a * n] = c * x - s * y;
-                            V[i + (size_t)b * n] = s * x + c * y;
+                            const double x = W[i + (size_t)a * ldw], y = W[i + (size_t)b * ldw];
+                            W[i + (size_t)a * ldw] = c * x - s * y;
+                            W[i + (size_t)b * ldw] = s * x + c * y;
+                        }
+                        if (gl == 0) {
+                            nrm[a] = al - t * ga;
+                            nrm[b] = be + t * ga;
+                            if (fabs(t) > 1e-8) *flag = 1;
                         }
                     }
-                    if (gl == 0) *flag = 1;
                 }
             }
             __syncthreads();
         }
         const int f = *flag;
         __syncthreads();
-        if (!f) break;
+        if (!f) return sweep + 1;
     }
+    return 40;
 }
 
-// Column norms of A (m x n) into s[0..n), then a descending order in perm
-// (ties by index).
-__device__ void block_colnorms_sorted(const double* A, int lda, int m, int n, double* s, int* perm) {
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        double acc = 0.0;
-        for (int i = 0; i < m; ++i) acc += A[i + (size_t)j * lda] * A[i + (size_t)j * lda];
-        s[j] = sqrt(acc);
+// One-sided Jacobi with a compile-time layout: m = RPT * GS rows (rows beyond
+// the data must be zero), n <= nt / GS * 2 columns, W n x n (rows beyond n
+// unused).  Each pair of columns is owned by GS consecutive lanes holding RPT
+// rows each, so a round issues all its LDS loads at once, forms
+// alpha = |a|^2, beta = |b|^2, gamma = a.b by DPP group sums, and updates the
+// two columns of A and of W from registers.  Same rotation rule and stopping
+// rule as block_jacobi_1s.
+template <int RPT, int GS, int WPT>
+__device__ __forceinline__ int block_jacobi_1s_fixed(double* A, int lda, int n, double* W, int ldw, int* flag, double* red) {
+    if (n < 2) {
+        __syncthreads();
+        return 0;
     }
-    __syncthreads();
+    const int np = (n + 1) & ~1, npairs = np / 2;
+    const int pair = threadIdx.x / GS, gl = threadIdx.x % GS;
+    const bool active = pair < npairs;
+    // absolute floor: pairs whose inner product is below 1e-30 ||A||_F^2 are noise
+    double part = 0.0;
+    for (int idx = threadIdx.x; idx < RPT * GS * n; idx += blockDim.x) {
+        const double v = A[(idx % (RPT * GS)) + (size_t)(idx / (RPT * GS)) * lda];
+        part += v * v;
+    }
+    const double floor_abs = 1e-30 * block_sum(part, red);
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (threadIdx.x == 0) *flag = 0;
+        __syncthreads();
+        for (int round = 0; round < np - 1; ++round) {
+            if (active) {
+                int a, b;
+                tournament_pair(pair, round, np, &a, &b);
+                if (b < n) {
+                    double x[RPT], y[RPT], u[WPT], v[WPT];
+                    double* pa = A + (size_t)a * lda + gl;
+                    double* pb = A + (size_t)b * lda + gl;
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) { x[k] = pa[k * GS]; y[k] = pb[k * GS]; }
+                    double* wa = W + (size_t)a * ldw + gl;
+                    double* wb = W + (size_t)b * ldw + gl;
+#pragma unroll
+                    for (int k = 0; k < WPT; ++k) {
+                        const bool in = gl + k * GS < n;
+                        u[k] = in ? wa[k * GS] : 0.0;
+                        v[k] = in ? wb[k * GS] : 0.0;
+                    }
+                    double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) {
+                        al = fma(x[k], x[k], al);
+                        be = fma(y[k], y[k], be);
+                        ga = fma(x[k], y[k], ga);
+                    }
+                    al = group_sum(al, GS);
+                    be = group_sum(be, GS);
+                    ga = group_sum(ga, GS);
+                    if (fabs(ga) > 1e-15 * sqrt(al * be) && fabs(ga) > floor_abs) {
+                        double c, s, t;
+                        jacobi_rotation(al, be, ga, &c, &s, &t);
+#pragma unroll
+                        for (int k = 0; k < RPT; ++k) {
+                            pa[k * GS] = c * x[k] - s * y[k];
+                            pb[k * GS] = s * x[k] + c * y[k];
+                        }
+#pragma unroll
+                        for (int k = 0; k < WPT; ++k) {
+                            if (gl + k * GS < n) {
+                                wa[k * GS] = c * u[k] - s * v[k];
+                                wb[k * GS] = s * u[k] + c * v[k];
+                            }
+                        }
+                        if (gl == 0 && fabs(t) > 1e-8) *flag = 1;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        const int f = *flag;
+        __syncthreads();
+        if (!f) return sweep + 1;
+    }
+    return 40;
+}
+
+// Two-sided cyclic Jacobi on the symmetric n x n column-major S, accumulating
+// the rotations into W: W^T S W converges to diag(eigenvalues); sweeps end as
+// in block_jacobi_1s.  S is a Gram
+// matrix known to ~u tr(S) absolute, so off-diagonals below 1e-15 tr(S) are
+// noise and are not rotated (rotations inside the negligible block would
+// neither converge nor change its trace, i.e. the truncated tail norm).
+__device__ __forceinline__ int block_jacobi_sym(double* S, int n, int ld, double* W, double* cs, int* pa_, int* pb_, int* flag) {
+    if (n < 2) {
+        __syncthreads();
+        return 0;
+    }
+    const int nt = blockDim.x;
+    const int np = (n + 1) & ~1, npairs = np / 2;
+    double tr = 0.0;
+    for (int i = 0; i < n; ++i) tr += fabs(S[i + (size_t)i * ld]);
+    const double floor_abs = 1e-15 * tr;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (threadIdx.x == 0) *flag = 0;
+        __syncthreads();
+        for (int round = 0; round < np - 1; ++round) {
+            for (int pp = threadIdx.x; pp < npairs; pp += nt) {
+                int a, b;
+                tournament_pair(pp, round, np, &a, &b);
+                double c = 1.0, s = 0.0;
+                if (b < n) {
+                    const double app = S[a + (size_t)a * ld], aqq = S[b + (size_t)b * ld], apq = S[a + (size_t)b * ld];
+                    if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs) {
+                        double t;
+                        jacobi_rotation(app, aqq, apq, &c, &s, &t);
+                        if (fabs(t) > 1e-8) *flag = 1;
+                    }
+                }
+                cs[2 * pp] = c;
+                cs[2 * pp + 1] = s;
+                pa_[pp] = a;
+                pb_[pp] = b;
+            }
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < npairs * n; idx += nt) {   // columns: S <- S R, W <- W R
+                const int pp = idx / n, i = idx % n;
+                const int a = pa_[pp], b = pb_[pp];
+                const double c = cs[2 * pp], s = cs[2 * pp + 1];
+                if (b >= n || s == 0.0) continue;
+                const double x = S[i + (size_t)a * ld], y = S[i + (size_t)b * ld];
+                S[i + (size_t)a * ld] = c * x - s * y;
+                S[i + (size_t)b * ld] = s * x + c * y;
+                const double u = W[i + (size_t)a * ld], w = W[i + (size_t)b * ld];
+                W[i + (size_t)a * ld] = c * u - s * w;
+                W[i + (size_t)b * ld] = s * u + c * w;
+            }
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < npairs * n; idx += nt) {   // rows: S <- R^T S
+                const int pp = idx / n, i = idx % n;
+                const int a = pa_[pp], b = pb_[pp];
+                const double c = cs[2 * pp], s = cs[2 * pp + 1];
+                if (b >= n || s == 0.0) continue;
+                const double x = S[a + (size_t)i * ld], y = S[b + (size_t)i * ld];
+                S[a + (size_t)i * ld] = c * x - s * y;
+                S[b + (size_t)i * ld] = s * x + c * y;
+            }
+            __syncthreads();
+        }
+        const int f = *flag;
+        __syncthreads();
+        if (!f) return sweep + 1;
+    }
+    return 40;
+}
+
+// Two-sided Jacobi on a 64 x 64 symmetric S (zero-padded beyond n) with 1024
+// threads and one update phase per round: thread (p, q) maps the 2 x 2 block
+// of S on the rows of pair p and the columns of pair q to R_p^T B R_q, and
+// W <- W R is updated per (row, pair).  Same rotation and stopping rules as
+// block_jacobi_sym.
+__device__ __forceinline__ int block_jacobi_sym64(double* S, int ld, double* W, double* cs, int* pa_, int* pb_,
+                                                  int* flag) {
+    const int np = 64, npairs = 32;
+    double tr = 0.0;
+    for (int i = 0; i < 64; ++i) tr += fabs(S[i + (size_t)i * ld]);
+    const double floor_abs = 1e-15 * tr;
+    const int p = threadIdx.x >> 5, q = threadIdx.x & 31;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (threadIdx.x == 0) *flag = 0;
+        __syncthreads();
+        for (int round = 0; round < np - 1; ++round) {
+            if (threadIdx.x < npairs) {
+                int a, b;
+                tournament_pair(threadIdx.x, round, np, &a, &b);
+                double c = 1.0, sn = 0.0;
+                const double app = S[a + (size_t)a * ld], aqq = S[b + (size_t)b * ld], apq = S[a + (size_t)b * ld];
+                if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs) {
+                    double t;
+                    jacobi_rotation(app, aqq, apq, &c, &sn, &t);
+                    if (fabs(t) > 1e-8) *flag = 1;
+                }
+                cs[2 * threadIdx.x] = c;
+                cs[2 * threadIdx.x + 1] = sn;
+                pa_[threadIdx.x] = a;
+                pb_[threadIdx.x] = b;
+            }
+            __syncthreads();
+            {
+                const int ap = pa_[p], bp = pb_[p], aq = pa_[q], bq = pb_[q];
+                const double cp = cs[2 * p], sp = cs[2 * p + 1], cq = cs[2 * q], sq = cs[2 * q + 1];
+                double* s00 = S + ap + (size_t)aq * ld;
+                double* s01 = S + ap + (size_t)bq * ld;
+                double* s10 = S + bp + (size_t)aq * ld;
+                double* s11 = S + bp + (size_t)bq * ld;
+                const double b00 = *s00, b01 = *s01, b10 = *s10, b11 = *s11;
+                const double c00 = cq * b00 - sq * b01, c01 = sq * b00 + cq * b01;
+                const double c10 = cq * b10 - sq * b11, c11 = sq * b10 + cq * b11;
+                const int i0 = threadIdx.x >> 5, i1 = i0 + 32;     // W rows handled by this thread
+                double* w0a = W + i0 + (size_t)aq * ld;
+                double* w0b = W + i0 + (size_t)bq * ld;
+                double* w1a = W + i1 + (size_t)aq * ld;
+                double* w1b = W + i1 + (size_t)bq * ld;
+                const double u0 = *w0a, v0 = *w0b, u1 = *w1a, v1 = *w1b;
+                __syncthreads();
+                *s00 = cp * c00 - sp * c10;
+                *s01 = cp * c01 - sp * c11;
+                *s10 = sp * c00 + cp * c10;
+                *s11 = sp * c01 + cp * c11;
+                *w0a = cq * u0 - sq * v0;
+                *w0b = sq * u0 + cq * v0;
+                *w1a = cq * u1 - sq * v1;
+                *w1b = sq * u1 + cq * v1;
+            }
+            __syncthreads();
+        }
+        const int f = *flag;
+        __syncthreads();
+        if (!f) return sweep + 1;
+    }
+    return 40;
+}
+
+// Descending order of s[0..n) into perm (ties by index).
+__device__ __forceinline__ void block_sort_desc(const double* s, int n, int* perm) {
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
         const double v = s[j];
         int rank = 0;
@@ -222,7 +544,7 @@ __device__ void block_colnorms_sorted(const double* A, int lda, int m, int n, do
 }
 
 // Smallest r >= 1 with sqrt(sum_{i>=r} s_sorted[i]^2) <= delta, capped.
-__device__ inline int delta_rank(const double* s, const int* perm, int n, double delta, int cap) {
+__device__ __forceinline__ int delta_rank(const double* s, const int* perm, int n, double delta, int cap) {
     double tail = 0.0;
     int r = n;
     for (int i = n - 1; i >= 1; --i) {
@@ -241,97 +563,119 @@ __device__ inline int delta_rank(const double* s, const int* perm, int n, double
 //
 // The pending TT sum has Phi_new (R2 x N_phi, stacked), Theta_new (R1 x N_theta
 // x R2, block diagonal) and the virtual first core Z_new.  This kernel
-//  1. forms Phi_new^T and its QR:   Phi_new = L_Phi Q_Phi,
-//  2. forms Theta' = Theta_new x_3 L_Phi and the QR of its row unfolding:
-//     Theta'_(1) = L_Theta Q_Theta,
+//  1. factors Phi_new = L_Phi Q_Phi with orthonormal rows Q_Phi: by Householder
+//     QR of Phi_new^T when R2 < N_phi; when R2 >= N_phi any orthogonal Q_Phi
+//     works and Q_Phi = I, L_Phi = Phi_new (no arithmetic);
+//  2. forms Theta' = Theta_new x_3 L_Phi and factors its row unfolding
+//     Theta'_(1) = L_Theta Q_Theta the same way (QR of its transpose when
+//     R1 < N_theta k2, else Q_Theta = I and L_Theta = Theta'_(1));
 //  3. folds L_Theta with the streaming coefficients into the operand G of the
 //     gather contraction B = d .* (sum_j (O_j Z) G_j + rank-1 terms), so that
-//     B = Z_new L_Theta (the projected first core).
-// Writes Q_Theta, Q_Phi, L_Theta and G; R1, R2, k1, k2 and ldb go to the state.
-struct SmallScratch {
-    double* A1;    // N_phi x R2cap
-    double* Q1;    // N_phi x k2cap
-    double* A2;    // (N_theta k2cap) x R1cap
-    double* Q2;    // (N_theta k2cap) x k1cap
-    double* tau;   // max(R1cap, R2cap)
-    double* J;     // Jacobi matrix, k1cap x k1cap
-    double* Th2;   // r1cap x N_theta k2cap
-    double* C2;    // r1cap N_theta x k2cap
-    double* V2;    // k2cap x k2cap
-    double* sv;    // k1cap + k2cap singular values
-    int* perm;     // k1cap + k2cap
-    int* flag;
-};
-
+//     B = Z_new L_Theta (the projected first core; X_(1) = B Q_Theta (I x Q_Phi)).
+// The state gets R1, R2, k1, k2, ldb, and whether both Q's are identities
+// (the projected basis is then the canonical angular basis, so the previous
+// round's singular vectors are a valid warm start).
 template <typename TC>
 __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevState* st, const double* __restrict__ Th,
                                                         const double* __restrict__ Ph, const double* __restrict__ gtab,
                                                         const double* __restrict__ htab, SmallScratch sc,
                                                         double* __restrict__ LTh, int ldl, double* __restrict__ QTh,
-                                                        double* __restrict__ QPh, TC* __restrict__ Gop, int ldgcap) {
+                                                        double* __restrict__ QPh, TC* __restrict__ Gop) {
+    extern __shared__ double lds[];
     __shared__ double red[16];
+    LdsCarver cv{lds, 0, (size_t)kSmallLdsBytes / sizeof(double)};
     const int nt = g.nt, npn = g.np;
     const int r1 = st->r1, r2 = st->r2, ldz = st->ldz;
     const int nrb = op.n_rblk, nr1 = op.n_r1;
     const int R1 = nrb * r1 + nr1, R2 = nrb * r2 + nr1;
-    const int k2 = R2 < npn ? R2 : npn;
+    const bool phi_id = R2 >= npn;
+    const int k2 = phi_id ? npn : R2;
     const int m2 = nt * k2;
-    const int k1 = R1 < m2 ? R1 : m2;
+    const bool th_id = R1 >= m2;
+    const int k1 = th_id ? m2 : R1;
     const int ldb = ld_for_rank(k1);
 
-    // 1. A1 = Phi_new^T (N_phi x R2, column-major)
-    for (int idx = threadIdx.x; idx < npn * R2; idx += blockDim.x) {
-        const int p = idx % npn, col = idx / npn;
-        double v;
-        if (col < nrb * r2) {
-            const int t = col / r2, b = col % r2;
-            v = Ph[(size_t)b * npn + p] * htab[op.rfac[t] * npn + p];
-        } else {
-            v = htab[op.r1fac[col - nrb * r2] * npn + p];
+    // 1. L_Phi (R2 x k2, row-major) and Q_Phi (k2 x N_phi)
+    double* Lphi = cv.take((size_t)R2 * k2, sc.Q1 + (size_t)npn * npn);
+    if (phi_id) {
+        for (int idx = threadIdx.x; idx < R2 * npn; idx += blockDim.x) {
+            const int col = idx / npn, p = idx % npn;
+            double v;
+            if (col < nrb * r2) {
+                const int t = col / r2, b = col % r2;
+                v = Ph[(size_t)b * npn + p] * htab[op.rfac[t] * npn + p];
+            } else {
+                v = htab[op.r1fac[col - nrb * r2] * npn + p];
+            }
+            Lphi[idx] = v;
         }
-        sc.A1[p + (size_t)col * npn] = v;
+        for (int idx = threadIdx.x; idx < npn * npn; idx += blockDim.x) QPh[idx] = (idx / npn == idx % npn) ? 1.0 : 0.0;
+    } else {
+        double* A1 = cv.take((size_t)npn * R2, sc.A1);
+        double* Q1 = cv.take((size_t)npn * k2, sc.Q1);
+        for (int idx = threadIdx.x; idx < npn * R2; idx += blockDim.x) {
+            const int p = idx % npn, col = idx / npn;
+            double v;
+            if (col < nrb * r2) {
+                const int t = col / r2, b = col % r2;
+                v = Ph[(size_t)b * npn + p] * htab[op.rfac[t] * npn + p];
+            } else {
+                v = htab[op.r1fac[col - nrb * r2] * npn + p];
+            }
+            A1[p + (size_t)col * npn] = v;
+        }
+        __syncthreads();
+        block_householder_qr(A1, npn, npn, R2, sc.tau, red);
+        block_form_q(A1, npn, npn, k2, sc.tau, Q1, npn);
+        for (int idx = threadIdx.x; idx < k2 * npn; idx += blockDim.x) {
+            const int c = idx / npn, p = idx % npn;
+            QPh[(size_t)c * npn + p] = Q1[p + (size_t)c * npn];
+        }
+        for (int idx = threadIdx.x; idx < R2 * k2; idx += blockDim.x) {
+            const int col = idx / k2, c = idx % k2;
+            Lphi[idx] = (c <= col) ? A1[c + (size_t)col * npn] : 0.0;
+        }
     }
     __syncthreads();
-    block_householder_qr(sc.A1, npn, npn, R2, sc.tau, red);
-    block_form_q(sc.A1, npn, npn, k2, sc.tau, sc.Q1, npn);
-    // Q_Phi = Q1^T (k2 x N_phi)
-    for (int idx = threadIdx.x; idx < k2 * npn; idx += blockDim.x) {
-        const int c = idx / npn, p = idx % npn;
-        QPh[(size_t)c * npn + p] = sc.Q1[p + (size_t)c * npn];
-    }
-    // 2. A2 = Theta'^T ((N_theta k2) x R1, column-major); L_Phi[col][c] = R_Phi[c][col]
-    for (int idx = threadIdx.x; idx < m2 * R1; idx += blockDim.x) {
-        const int rowA = idx % m2, row = idx / m2;
-        const int l = rowA / k2, c = rowA % k2;
+    // 2. Theta' (R1 x N_theta x k2): value of element (row, l, c)
+    auto theta_p = [&](int row, int l, int c) -> double {
         double v = 0.0;
         if (row < nrb * r1) {
             const int t = row / r1, a = row % r1;
             const double* th = Th + ((size_t)a * nt + l) * r2;
-            for (int b = 0; b < r2; ++b) {
-                const int col = t * r2 + b;
-                const double lphi = (c <= col) ? sc.A1[c + (size_t)col * npn] : 0.0;
-                v += th[b] * lphi;
-            }
+            const double* lp = Lphi + (size_t)(t * r2) * k2 + c;
+            for (int b = 0; b < r2; ++b) v += th[b] * lp[(size_t)b * k2];
             v *= gtab[op.rfac[t] * nt + l];
         } else {
             const int q = row - nrb * r1;
-            const int col = nrb * r2 + q;
-            const double lphi = (c <= col) ? sc.A1[c + (size_t)col * npn] : 0.0;
-            v = gtab[op.r1fac[q] * nt + l] * lphi;
+            v = gtab[op.r1fac[q] * nt + l] * Lphi[(size_t)(nrb * r2 + q) * k2 + c];
         }
-        sc.A2[rowA + (size_t)row * m2] = v;
-    }
-    __syncthreads();
-    block_householder_qr(sc.A2, m2, m2, R1, sc.tau, red);
-    block_form_q(sc.A2, m2, m2, k1, sc.tau, sc.Q2, m2);
-    // Q_Theta = Q2^T (k1 x N_theta k2), L_Theta = R^T (R1 x k1)
-    for (int idx = threadIdx.x; idx < k1 * m2; idx += blockDim.x) {
-        const int i = idx / m2, rowA = idx % m2;
-        QTh[(size_t)i * m2 + rowA] = sc.Q2[rowA + (size_t)i * m2];
-    }
-    for (int idx = threadIdx.x; idx < R1 * k1; idx += blockDim.x) {
-        const int row = idx / k1, i = idx % k1;
-        LTh[(size_t)row * ldl + i] = (i <= row) ? sc.A2[i + (size_t)row * m2] : 0.0;
+        return v;
+    };
+    if (th_id) {
+        for (int idx = threadIdx.x; idx < R1 * m2; idx += blockDim.x) {
+            const int row = idx / m2, i = idx % m2;
+            LTh[(size_t)row * ldl + i] = theta_p(row, i / k2, i % k2);
+        }
+        for (int idx = threadIdx.x; idx < m2 * m2; idx += blockDim.x) QTh[idx] = (idx / m2 == idx % m2) ? 1.0 : 0.0;
+    } else {
+        double* A2 = cv.take((size_t)m2 * R1, sc.A2);
+        double* Q2 = cv.take((size_t)m2 * k1, sc.Q2);
+        for (int idx = threadIdx.x; idx < m2 * R1; idx += blockDim.x) {
+            const int rowA = idx % m2, row = idx / m2;
+            A2[rowA + (size_t)row * m2] = theta_p(row, rowA / k2, rowA % k2);
+        }
+        __syncthreads();
+        block_householder_qr(A2, m2, m2, R1, sc.tau, red);
+        block_form_q(A2, m2, m2, k1, sc.tau, Q2, m2);
+        for (int idx = threadIdx.x; idx < k1 * m2; idx += blockDim.x) {
+            const int i = idx / m2, rowA = idx % m2;
+            QTh[(size_t)i * m2 + rowA] = Q2[rowA + (size_t)i * m2];
+        }
+        for (int idx = threadIdx.x; idx < R1 * k1; idx += blockDim.x) {
+            const int row = idx / k1, i = idx % k1;
+            LTh[(size_t)row * ldl + i] = (i <= row) ? A2[i + (size_t)row * m2] : 0.0;
+        }
     }
     __syncthreads();
     // 3. gather operand G: rows (gather block j, a < ldz), then rank-1 rows; ldb columns
@@ -360,130 +704,125 @@ __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevSt
         st->R1 = R1; st->R2 = R2; st->k1 = k1; st->k2 = k2; st->ldb = ldb;
         if (R1 > st->max_R1) st->max_R1 = R1;
         if (R2 > st->max_R2) st->max_R2 = R2;
+        st->canon_prev = st->canon;
+        st->canon = (phi_id && th_id) ? 1 : 0;
     }
 }
 
 // ---------------------------------------------------------------------------
-// SVD chain: truncated SVDs of both bonds from the R factor of B = Z_new L_Theta
+// SVD chain: truncated SVDs of both bonds from the R factor (or Gram matrix)
+// of B = Z_new L_Theta
 // ---------------------------------------------------------------------------
 //
-// Input: R_B (k1 x k1, upper triangular, row-major with leading dim ldr) with
-// B = Q_B R_B.  The bond-1 SVD of the right-orthogonalised TT is the SVD of B:
-// one-sided Jacobi on R_B^T gives R_B^T W = U S, whose normalised columns are
-// the right singular vectors V of R_B (and of B).  The rest follows the
-// left-to-right sweep of TT-SVD rounding with the norm kept in Z:
-//   Z_out = B V_r, Theta'' = V_r^T Q_Theta, SVD of diag(S_r) Theta''
-//   ((r1 N_theta) x k2) -> V2, S2; Theta_out = Theta'' x_3 V2_r,
-//   Phi_out = V2_r^T Q_Phi.
-// gram != 0: the input is the Gram matrix G = B^T B (k1 x k1, symmetric)
-// instead; a two-sided Jacobi eigensolver gives V and S = sqrt(eig).
-template <typename TC>
+// QR input: R_B (k1 x k1, upper triangular, row-major, leading dim ldr) with
+// B = Q_B R_B; one-sided Jacobi on the columns of R_B W gives W = right
+// singular vectors of R_B (= those of B) and the column norms give S.
+// Gram input (gram != 0): G = B^T B; two-sided Jacobi W^T G W -> diag(S^2).
+// When this round and the previous one both project onto the canonical
+// angular basis, W starts from the previous round's singular vectors.
+// The rest is the left-to-right sweep of TT-SVD rounding with the norm kept
+// in Z:  Z_out = B V_r;  Theta'' = V_r^T Q_Theta;  SVD of diag(S_r) Theta''
+// ((r1 N_theta) x k2) -> V2, S2;  Theta_out = Theta'' x_3 V2_r;
+// Phi_out = V2_r^T Q_Phi.  Truncation: delta = tol ||X||_F / sqrt(2) per bond.
+template <typename TC, bool FAST>
 __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* st, const double* __restrict__ RB, int ldr,
                                                              int gram, const double* __restrict__ QTh,
                                                              const double* __restrict__ QPh, double tol, int cap1,
                                                              int cap2, SmallScratch sc, double* __restrict__ ThOut,
                                                              double* __restrict__ PhOut, TC* __restrict__ Vout,
                                                              double* __restrict__ sv_out) {
+    extern __shared__ double lds[];
     __shared__ double red[16];
     __shared__ int sh_r[2];
+    __shared__ int sh_flag;
+    __shared__ double cs[2 * 128];
+    __shared__ int pa_[128], pb_[128];
+    LdsCarver cv{lds, 0, (size_t)kSmallLdsBytes / sizeof(double)};
     const int nt = g.nt, npn = g.np;
     const int k1 = st->k1, k2 = st->k2;
     const int m2 = nt * k2;
-    double* J = sc.J;
-    // J = R_B^T, column-major k1 x k1: column j holds row j of R_B
-    for (int idx = threadIdx.x; idx < k1 * k1; idx += blockDim.x) {
-        const int i = idx % k1, j = idx / k1;
-        J[i + (size_t)j * k1] = RB[(size_t)j * ldr + i];
+    const bool warm = st->canon && st->canon_prev && st->k1_prev == k1;
+    // FAST (k1 <= 64, r1 N_theta <= 256, k2 <= 16): working matrices at fixed
+    // LDS offsets, 64 x 64 with leading dimension 65 (columns on different
+    // banks), zero / identity padded beyond k1.  Otherwise LDS where it fits
+    // and global scratch beyond.
+    const int kp = FAST ? 64 : k1;                       // padded order
+    const int ld = FAST ? 65 : k1;
+    const size_t reg0 = FAST ? (size_t)(64 * 65 > 257 * 16 ? 64 * 65 : 257 * 16) : 0;
+    double* J = FAST ? lds : cv.take((size_t)k1 * ld, sc.J);
+    double* W = FAST ? lds + reg0 : cv.take((size_t)k1 * ld, sc.W);
+    double* T = FAST ? W + (size_t)kp * ld : cv.take((size_t)k1 * ld, sc.A2);
+    double* nrm = FAST ? T + (size_t)kp * ld : cv.take((size_t)k1, sc.sv + 2 * k1);
+    double* s1 = FAST ? nrm + kp : cv.take((size_t)k1, sc.sv);
+    int* p1 = sc.perm;
+    long long tph[8];
+    int sw1 = 0, sw2 = 0;
+    tph[0] = wall_clock64();
+    // stage the input (R_B or G, row-major in global) column-major into T; W0
+    for (int idx = threadIdx.x; idx < kp * kp; idx += blockDim.x) {
+        const int j = idx % kp, i = idx / kp;      // coalesced along rows of the input
+        T[i + (size_t)j * ld] = (i < k1 && j < k1) ? RB[(size_t)i * ldr + j] : 0.0;
+        W[j + (size_t)i * ld] = (i < k1 && j < k1) ? (warm ? sc.Wkeep[j + (size_t)i * k1] : (i == j ? 1.0 : 0.0))
+                                                   : (i == j ? 1.0 : 0.0);
     }
     __syncthreads();
-    double* s1 = sc.sv;
-    int* p1 = sc.perm;
     if (!gram) {
-        block_jacobi(J, k1, k1, k1, nullptr, sc.flag, red);
-        block_colnorms_sorted(J, k1, k1, k1, s1, p1);
-    } else {
-        // G symmetric: cyclic two-sided Jacobi G <- W^T G W, W accumulated in A2
-        double* W = sc.A2;
-        for (int idx = threadIdx.x; idx < k1 * k1; idx += blockDim.x) W[idx] = (idx % k1 == idx / k1) ? 1.0 : 0.0;
-        __syncthreads();
-        const int np_ = (k1 + 1) & ~1, npairs = np_ / 2;
-        for (int sweep = 0; sweep < 60 && k1 > 1; ++sweep) {
-            if (threadIdx.x == 0) *sc.flag = 0;
-            __syncthreads();
-            for (int round = 0; round < np_ - 1; ++round) {
-                // one thread per pair decides its rotation; rotations of disjoint pairs commute
-                __shared__ double cs[2 * 128];
-                __shared__ int pa_[128], pb_[128];
-                for (int pp = threadIdx.x; pp < npairs; pp += blockDim.x) {
-                    int pa = pp, pb = np_ - 1 - pp;
-                    int a = pa == 0 ? 0 : ((pa - 1 + round) % (np_ - 1)) + 1;
-                    int b = pb == 0 ? 0 : ((pb - 1 + round) % (np_ - 1)) + 1;
-                    if (a > b) { int t = a; a = b; b = t; }
-                    double c = 1.0, s = 0.0;
-                    if (b < k1) {
-                        const double app = J[a + (size_t)a * k1], aqq = J[b + (size_t)b * k1], apq = J[a + (size_t)b * k1];
-                        if (apq != 0.0 && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
-                            const double zeta = (aqq - app) / (2.0 * apq);
-                            const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                            c = 1.0 / sqrt(1.0 + t * t);
-                            s = c * t;
-                            *sc.flag = 1;
-                        }
-                    }
-                    cs[2 * pp] = c; cs[2 * pp + 1] = s; pa_[pp] = a; pb_[pp] = b;
-                }
-                __syncthreads();
-                // columns: J <- J R, W <- W R
-                for (int idx = threadIdx.x; idx < npairs * k1; idx += blockDim.x) {
-                    const int pp = idx / k1, i = idx % k1;
-                    const int a = pa_[pp], b = pb_[pp];
-                    if (b >= k1) continue;
-                    const double c = cs[2 * pp], s = cs[2 * pp + 1];
-                    const double x = J[i + (size_t)a * k1], y = J[i + (size_t)b * k1];
-                    J[i + (size_t)a * k1] = c * x - s * y;
-                    J[i + (size_t)b * k1] = s * x + c * y;
-                    const double u = W[i + (size_t)a * k1], w = W[i + (size_t)b * k1];
-                    W[i + (size_t)a * k1] = c * u - s * w;
-                    W[i + (size_t)b * k1] = s * u + c * w;
-                }
-                __syncthreads();
-                // rows: J <- R^T J
-                for (int idx = threadIdx.x; idx < npairs * k1; idx += blockDim.x) {
-                    const int pp = idx / k1, i = idx % k1;
-                    const int a = pa_[pp], b = pb_[pp];
-                    if (b >= k1) continue;
-                    const double c = cs[2 * pp], s = cs[2 * pp + 1];
-                    const double x = J[a + (size_t)i * k1], y = J[b + (size_t)i * k1];
-                    J[a + (size_t)i * k1] = c * x - s * y;
-                    J[b + (size_t)i * k1] = s * x + c * y;
-                }
-                __syncthreads();
+        // J = R_B W (R_B upper triangular)
+        for (int idx = threadIdx.x; idx < kp * kp; idx += blockDim.x) {
+            const int i = idx % kp, j = idx / kp;
+            double acc = 0.0;
+            if (warm) {
+                for (int k = i; k < k1; ++k) acc += T[i + (size_t)k * ld] * W[k + (size_t)j * ld];
+            } else {
+                acc = T[i + (size_t)j * ld];
             }
-            const int f = *sc.flag;
-            __syncthreads();
-            if (!f) break;
+            J[i + (size_t)j * ld] = acc;
         }
-        for (int j = threadIdx.x; j < k1; j += blockDim.x) s1[j] = sqrt(fmax(J[j + (size_t)j * k1], 0.0));
         __syncthreads();
+        tph[1] = wall_clock64();
+        if (FAST)
+            sw1 = block_jacobi_1s_fixed<8, 8, 8>(J, ld, k1, W, ld, &sh_flag, red);
+        else
+            sw1 = block_jacobi_1s(J, ld, k1, k1, W, ld, nrm, &sh_flag, red);
+        tph[2] = wall_clock64();
         for (int j = threadIdx.x; j < k1; j += blockDim.x) {
-            const double v = s1[j];
-            int rank = 0;
-            for (int i = 0; i < k1; ++i) {
-                const double u = s1[i];
-                if (u > v || (u == v && i < j)) ++rank;
+            double acc = 0.0;
+            for (int i = 0; i < kp; ++i) acc += J[i + (size_t)j * ld] * J[i + (size_t)j * ld];
+            s1[j] = sqrt(acc);
+        }
+    } else {
+        if (warm) {
+            // J = W^T G W: J <- G W, then T <- W^T J
+            for (int idx = threadIdx.x; idx < kp * kp; idx += blockDim.x) {
+                const int i = idx % kp, j = idx / kp;
+                double acc = 0.0;
+                for (int k = 0; k < k1; ++k) acc += T[i + (size_t)k * ld] * W[k + (size_t)j * ld];
+                J[i + (size_t)j * ld] = acc;
             }
-            p1[rank] = j;
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < kp * kp; idx += blockDim.x) {
+                const int i = idx % kp, j = idx / kp;
+                double acc = 0.0;
+                for (int k = 0; k < k1; ++k) acc += W[k + (size_t)i * ld] * J[k + (size_t)j * ld];
+                T[i + (size_t)j * ld] = acc;
+            }
+            __syncthreads();
+        }
+        for (int idx = threadIdx.x; idx < kp * kp; idx += blockDim.x) {
+            const int i = idx % kp, j = idx / kp;
+            J[i + (size_t)j * ld] = T[i + (size_t)j * ld];
         }
         __syncthreads();
-        // right singular vectors are the eigenvectors: copy W into J scaled by s so the
-        // normalisation below is shared with the QR path
-        for (int idx = threadIdx.x; idx < k1 * k1; idx += blockDim.x) {
-            const int j = idx / k1;
-            J[idx] = W[idx] * s1[j];
-        }
-        __syncthreads();
+        tph[1] = wall_clock64();
+        if (FAST)
+            sw1 = block_jacobi_sym64(J, ld, W, cs, pa_, pb_, &sh_flag);
+        else
+            sw1 = block_jacobi_sym(J, k1, ld, W, cs, pa_, pb_, &sh_flag);
+        tph[2] = wall_clock64();
+        for (int j = threadIdx.x; j < k1; j += blockDim.x) s1[j] = sqrt(fmax(J[j + (size_t)j * ld], 0.0));
     }
-    // norm, threshold, bond-1 rank
+    __syncthreads();
+    block_sort_desc(s1, k1, p1);
     double part = 0.0;
     for (int j = threadIdx.x; j < k1; j += blockDim.x) part += s1[j] * s1[j];
     const double norm2 = block_sum(part, red);
@@ -494,71 +833,89 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
     const int r1n = sh_r[0];
     const int ldzn = ld_for_rank(r1n);
     const int ldb = st->ldb;
-    // V_r (k1 x r1n): normalised columns of J in descending order
+    // sorted V -> Wkeep (next warm start); V_r -> Vout in the contraction precision
+    for (int idx = threadIdx.x; idx < k1 * k1; idx += blockDim.x) {
+        const int i = idx % k1, a = idx / k1;
+        sc.Wkeep[idx] = W[i + (size_t)p1[a] * ld];
+    }
     for (int idx = threadIdx.x; idx < ldb * ldzn; idx += blockDim.x) {
         const int i = idx / ldzn, a = idx % ldzn;
         double v = 0.0;
-        if (i < k1 && a < r1n) {
-            const int j = p1[a];
-            const double s = s1[j];
-            v = (s > 0.0) ? J[i + (size_t)j * k1] / s : (i == j ? 1.0 : 0.0);
-        }
+        if (i < k1 && a < r1n) v = W[i + (size_t)p1[a] * ld];
         Vout[(size_t)i * ldzn + a] = (TC)v;
     }
-    // Theta'' = V_r^T Q_Theta (r1n x N_theta k2), and C2 = diag(S_r) Theta''
-    // reshaped ((r1n N_theta) x k2) column-major
+    // Theta'' = V_r^T Q_Theta (r1n x m2) and C2 = diag(S_r) Theta'' as ((r1n N_theta) x k2)
+    const int mC = r1n * nt;
+    const int mpad = FAST ? (mC <= 128 ? 128 : 256) : mC;   // fixed-layout row count (zero rows beyond mC)
+    const int ldc = FAST ? mpad + 1 : mC;                    // padded column stride of C2
+    double* C2 = FAST ? lds : cv.take((size_t)ldc * k2, sc.C2);
+    if (FAST)
+        for (int idx = threadIdx.x; idx < ldc * k2; idx += blockDim.x) C2[idx] = 0.0;
+    __syncthreads();
+    double* V2 = FAST ? s1 + k1 : cv.take((size_t)k2 * k2, sc.V2);
+    double* nrm2 = FAST ? V2 + (size_t)k2 * k2 : cv.take((size_t)k2, sc.sv + k1);
     for (int idx = threadIdx.x; idx < r1n * m2; idx += blockDim.x) {
         const int a = idx / m2, col = idx % m2;
-        const int j = p1[a];
-        const double s = s1[j];
+        const double* w = W + (size_t)p1[a] * ld;
         double acc = 0.0;
-        for (int i = 0; i < k1; ++i) {
-            const double v = (s > 0.0) ? J[i + (size_t)j * k1] / s : (i == j ? 1.0 : 0.0);
-            acc += v * QTh[(size_t)i * m2 + col];
-        }
+        for (int i = 0; i < k1; ++i) acc += w[i] * QTh[(size_t)i * m2 + col];
         sc.Th2[(size_t)a * m2 + col] = acc;
         const int l = col / k2, c = col % k2;
-        sc.C2[(a * nt + l) + (size_t)c * (r1n * nt)] = s * acc;
+        C2[(a * nt + l) + (size_t)c * ldc] = s1[p1[a]] * acc;
     }
+    for (int idx = threadIdx.x; idx < k2 * k2; idx += blockDim.x) V2[idx] = (idx % k2 == idx / k2) ? 1.0 : 0.0;
     __syncthreads();
-    const int mC = r1n * nt;
-    block_jacobi(sc.C2, mC, mC, k2, sc.V2, sc.flag, red);
+    tph[3] = wall_clock64();
+    if (FAST && mpad == 128)
+        sw2 = block_jacobi_1s_fixed<8, 16, 1>(C2, ldc, k2, V2, k2, &sh_flag, red);
+    else if (FAST)
+        sw2 = block_jacobi_1s_fixed<16, 16, 1>(C2, ldc, k2, V2, k2, &sh_flag, red);
+    else
+        sw2 = block_jacobi_1s(C2, ldc, mC, k2, V2, k2, nrm2, &sh_flag, red);
+    tph[4] = wall_clock64();
     double* s2 = sc.sv + k1;
     int* p2 = sc.perm + k1;
-    block_colnorms_sorted(sc.C2, mC, mC, k2, s2, p2);
-    if (threadIdx.x == 0) {
-        sh_r[1] = delta_rank(s2, p2, k2, delta, cap2 < k2 ? cap2 : k2);
+    for (int j = threadIdx.x; j < k2; j += blockDim.x) {
+        double acc = 0.0;
+        for (int i = 0; i < mC; ++i) acc += C2[i + (size_t)j * ldc] * C2[i + (size_t)j * ldc];
+        s2[j] = sqrt(acc);
     }
     __syncthreads();
+    block_sort_desc(s2, k2, p2);
+    if (threadIdx.x == 0) sh_r[1] = delta_rank(s2, p2, k2, delta, cap2 < k2 ? cap2 : k2);
+    __syncthreads();
     const int r2n = sh_r[1];
-    // Theta_out[a][l][q] = sum_c Theta''[a][l][c] V2[c][p2[q]];  Phi_out[q][p] = sum_c V2[c][p2[q]] Q_Phi[c][p]
     for (int idx = threadIdx.x; idx < r1n * nt * r2n; idx += blockDim.x) {
         const int q = idx % r2n, al = idx / r2n;
         const int a = al / nt, l = al % nt;
         const int jq = p2[q];
         double acc = 0.0;
-        for (int c = 0; c < k2; ++c) acc += sc.Th2[(size_t)a * m2 + l * k2 + c] * sc.V2[c + (size_t)jq * k2];
+        for (int c = 0; c < k2; ++c) acc += sc.Th2[(size_t)a * m2 + l * k2 + c] * V2[c + (size_t)jq * k2];
         ThOut[idx] = acc;
     }
     for (int idx = threadIdx.x; idx < r2n * npn; idx += blockDim.x) {
         const int q = idx / npn, p = idx % npn;
         const int jq = p2[q];
         double acc = 0.0;
-        for (int c = 0; c < k2; ++c) acc += sc.V2[c + (size_t)jq * k2] * QPh[(size_t)c * npn + p];
+        for (int c = 0; c < k2; ++c) acc += V2[c + (size_t)jq * k2] * QPh[(size_t)c * npn + p];
         PhOut[idx] = acc;
     }
-    // discarded tail and statistics
     double d1 = 0.0;
     for (int a = r1n + threadIdx.x; a < k1; a += blockDim.x) d1 += s1[p1[a]] * s1[p1[a]];
     for (int q = r2n + threadIdx.x; q < k2; q += blockDim.x) d1 += s2[p2[q]] * s2[p2[q]];
     const double disc2 = block_sum(d1, red);
     for (int j = threadIdx.x; j < k1; j += blockDim.x) sv_out[j] = s1[p1[j]];
+    tph[5] = wall_clock64();
     if (threadIdx.x == 0) {
+        for (int i = 0; i < 6; ++i) st->tph[i] = tph[i];
+        st->sweeps[0] = sw1;
+        st->sweeps[1] = sw2;
         st->r1n = r1n;
         st->r2n = r2n;
         st->ldzn = ldzn;
         st->norm = norm;
         st->disc2 = disc2;
+        st->k1_prev = k1;
         if (!(norm2 < 1e300) || norm2 != norm2) st->nan_flag = 1;
         st->rounds += 1;
         const double M = (double)g.M, R1 = (double)st->R1, kk = (double)k1;

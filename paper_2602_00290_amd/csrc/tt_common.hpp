@@ -32,12 +32,15 @@ struct DevState {
     int nan_flag;
     int max_R1, max_R2;
     int rounds;
-    int pad0;
+    int canon, canon_prev;  // projection used the canonical angular basis (this / previous round)
+    int k1_prev;            // k1 of the previous round (warm start validity)
     double norm;       // ||X||_F before truncation
     double disc2;      // squared discarded singular values (both bonds)
     double energy;
     double pad1;
     double fl[4];      // algorithmic flops accumulated: project, factor, output, small cores
+    int sweeps[2];     // Jacobi sweeps of the last round (bond 1, bond 2)
+    long long tph[8];  // wall_clock64 stamps at phase boundaries of the last SVD chain
 };
 
 // Static description of the problem shared by all kernels (passed by value).

@@ -17,11 +17,13 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <type_traits>
 #include <string>
 #include <vector>
 
 #include "../../include/tt_transport.h"
 #include "k_big.hpp"
+#include "k_mfma.hpp"
 #include "k_small.hpp"
 #include "tt_common.hpp"
 
@@ -61,6 +63,7 @@ struct Plan {
     std::vector<long long> levN;    // rows of the level input
     int Pg = 1;
     long long rowsg = 0;
+    bool svd_fast = false;          // all SVD-chain matrices fit the LDS layout
     size_t elem = 8;                // bytes per stored element of Z / B
     // workspace layout (byte offsets)
     size_t o_state, o_Z0, o_Z1, o_B, o_Th0, o_Th1, o_Ph0, o_Ph1, o_LTh, o_QTh, o_QPh, o_G, o_V, o_RA, o_RB, o_small,
@@ -106,7 +109,7 @@ tt_status validate(const tt_problem* p) {
     if (p->rank_cap < 1) return fail(TT_ERR_INVALID_ARG, "rank_cap must be >= 1");
     if (p->precision < 0 || p->precision > 2) return fail(TT_ERR_INVALID_ARG, "unknown precision");
     if (p->precision == TT_PREC_BF16X) return fail(TT_ERR_INVALID_ARG, "TT_PREC_BF16X is not available in this build");
-    if (p->round_method < 0 || p->round_method > 1) return fail(TT_ERR_INVALID_ARG, "unknown round_method");
+    if (p->round_method < 0 || p->round_method > 2) return fail(TT_ERR_INVALID_ARG, "unknown round_method");
     if (p->paper_step_order < 0 || p->paper_step_order > 1) return fail(TT_ERR_INVALID_ARG, "paper_step_order must be 0 or 1");
     return TT_OK;
 }
@@ -141,6 +144,14 @@ tt_status make_plan(const tt_problem* p, Plan& P) {
     P.ldbcap = ld_for_rank(P.k1cap);
     if (P.k1cap > 128) return fail(TT_ERR_INVALID_ARG, "projected first-core rank above 128 is not supported by this build");
     P.KP = P.k1cap <= 64 ? 64 : 128;
+    {
+        // fixed LDS layout of the SVD chain: 64 x 64 matrices (ld 65) and a
+        // bond-2 matrix of at most 256 rows x 16 columns
+        const size_t reg0 = std::max<size_t>(64 * 65, 257 * 16);
+        const size_t need = reg0 + 2 * 64 * 65 + 2 * 64 + (size_t)P.k2cap * P.k2cap + P.k2cap;
+        P.svd_fast = P.k1cap <= 64 && (long long)P.r1cap * P.nt <= 256 && P.k2cap <= 16 &&
+                     need * sizeof(double) <= (size_t)kSmallLdsBytes;
+    }
     P.chunk = P.KP == 64 ? 8 * 16 : 4 * 16;
     P.elem = p->precision == TT_PREC_FP64 ? 8 : 4;
     // TSQR levels
@@ -191,7 +202,7 @@ tt_status make_plan(const tt_problem* p, Plan& P) {
     const size_t m2 = (size_t)P.nt * P.k2cap;
     P.small_bytes = 0;
     P.small_bytes += align256((size_t)P.np * P.R2cap * d);
-    P.small_bytes += align256((size_t)P.np * P.k2cap * d);
+    P.small_bytes += align256(((size_t)P.np * P.np + (size_t)P.R2cap * P.k2cap) * d);
     P.small_bytes += align256(std::max(m2 * P.R1cap, (size_t)P.k1cap * P.k1cap) * d);
     P.small_bytes += align256(m2 * P.k1cap * d);
     P.small_bytes += align256((size_t)std::max(P.R1cap, P.R2cap) * d);
@@ -199,9 +210,11 @@ tt_status make_plan(const tt_problem* p, Plan& P) {
     P.small_bytes += align256((size_t)P.r1cap * m2 * d);
     P.small_bytes += align256((size_t)P.r1cap * P.nt * P.k2cap * d);
     P.small_bytes += align256((size_t)P.k2cap * P.k2cap * d);
-    P.small_bytes += align256((size_t)(P.k1cap + P.k2cap) * d);
+    P.small_bytes += align256((size_t)(3 * P.k1cap + P.k2cap) * d);
     P.small_bytes += align256((size_t)(P.k1cap + P.k2cap) * sizeof(int));
     P.small_bytes += align256(sizeof(int));
+    P.small_bytes += align256((size_t)P.k1cap * P.k1cap * d);
+    P.small_bytes += align256((size_t)P.k1cap * P.k1cap * d);
     P.o_small = take(P.small_bytes);
     P.o_k0 = take((size_t)P.NX * d);
     P.o_ks = take((size_t)P.G * d);
@@ -260,7 +273,7 @@ struct tt_handle {
         const size_t d = sizeof(double);
         const size_t m2 = (size_t)P.nt * P.k2cap;
         s.A1 = (double*)b; b += align256((size_t)P.np * P.R2cap * d);
-        s.Q1 = (double*)b; b += align256((size_t)P.np * P.k2cap * d);
+        s.Q1 = (double*)b; b += align256(((size_t)P.np * P.np + (size_t)P.R2cap * P.k2cap) * d);
         s.A2 = (double*)b; b += align256(std::max(m2 * P.R1cap, (size_t)P.k1cap * P.k1cap) * d);
         s.Q2 = (double*)b; b += align256(m2 * P.k1cap * d);
         s.tau = (double*)b; b += align256((size_t)std::max(P.R1cap, P.R2cap) * d);
@@ -268,9 +281,11 @@ struct tt_handle {
         s.Th2 = (double*)b; b += align256((size_t)P.r1cap * m2 * d);
         s.C2 = (double*)b; b += align256((size_t)P.r1cap * P.nt * P.k2cap * d);
         s.V2 = (double*)b; b += align256((size_t)P.k2cap * P.k2cap * d);
-        s.sv = (double*)b; b += align256((size_t)(P.k1cap + P.k2cap) * d);
+        s.sv = (double*)b; b += align256((size_t)(3 * P.k1cap + P.k2cap) * d);
         s.perm = (int*)b; b += align256((size_t)(P.k1cap + P.k2cap) * sizeof(int));
-        s.flag = (int*)b;
+        s.flag = (int*)b; b += align256(sizeof(int));
+        s.W = (double*)b; b += align256((size_t)P.k1cap * P.k1cap * d);
+        s.Wkeep = (double*)b;
         return s;
     }
 
@@ -284,12 +299,12 @@ struct tt_handle {
             ev_class.push_back(cls);
         }
         ev_class[ev_used] = cls;
-        hipEventRecord(ev_pool[ev_used].first, s);
+        (void)hipEventRecord(ev_pool[ev_used].first, s);
         return ev_used++;
     }
     void ev_end(size_t i, hipStream_t s) {
         if (i == (size_t)-1) return;
-        hipEventRecord(ev_pool[i].second, s);
+        (void)hipEventRecord(ev_pool[i].second, s);
     }
     void ev_collect() {
         for (size_t i = 0; i < ev_used; ++i) {
@@ -413,14 +428,21 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
     size_t e;
 
     e = h->ev_begin(KC_PREP, s);
-    hipLaunchKernelGGL(k_prep<T>, dim3(1), dim3(kSmallThreads), 0, s, h->geom, op, st, h->Thc(), h->Phc(),
-                       h->at<double>(P.o_gtab), h->at<double>(P.o_htab), sc, LTh, P.k1cap, QTh, QPh, Gop, P.ldbcap);
+    hipLaunchKernelGGL(k_prep<T>, dim3(1), dim3(kSmallThreads), kSmallLdsBytes, s, h->geom, op, st, h->Thc(), h->Phc(),
+                       h->at<double>(P.o_gtab), h->at<double>(P.o_htab), sc, LTh, P.k1cap, QTh, QPh, Gop);
     h->ev_end(e, s);
 
     const unsigned gx = (unsigned)((P.M + 63) / 64);
+    const unsigned gx128 = (unsigned)((P.M + 127) / 128);
+    constexpr bool f32 = std::is_same<T, float>::value;
     e = h->ev_begin(KC_PROJECT, s);
-    hipLaunchKernelGGL((k_gather_gemm<T, MODE_PROJECT>), dim3(gx, (P.ldbcap + 63) / 64), dim3(256), 0, s, h->geom, op,
-                       st, (const T*)h->Zc(), (const T*)Gop, B, h->rowdata());
+    if constexpr (f32)
+        hipLaunchKernelGGL((k_gemm_f32_mfma<MODE_PROJECT, 64>), dim3(gx128, (P.ldbcap + 63) / 64), dim3(256), 0, s,
+                           h->geom, op, (const DevState*)st, (const float*)h->Zc(), (const float*)Gop, (float*)B,
+                           h->rowdata());
+    else
+        hipLaunchKernelGGL((k_gather_gemm<T, MODE_PROJECT>), dim3(gx, (P.ldbcap + 63) / 64), dim3(256), 0, s, h->geom,
+                           op, st, (const T*)h->Zc(), (const T*)Gop, B, h->rowdata());
     h->ev_end(e, s);
 
     const double* RB = nullptr;
@@ -456,7 +478,10 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
     } else {
         gram = 1;
         e = h->ev_begin(KC_FACTOR, s);
-        if (P.KP == 64)
+        if (f32 && P.KP == 64)
+            hipLaunchKernelGGL(k_gram_f64_mfma, dim3(P.Pg), dim3(256), 0, s, (const float*)B, (const DevState*)st, P.M,
+                               P.rowsg, RA);
+        else if (P.KP == 64)
             hipLaunchKernelGGL((k_gram<T, 64>), dim3(P.Pg), dim3(256), 0, s, (const T*)B, (const DevState*)st, P.M,
                                P.rowsg, RA);
         else
@@ -465,21 +490,35 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
         h->ev_end(e, s);
         e = h->ev_begin(KC_TREE, s);
         const int n = P.KP * P.KP;
-        hipLaunchKernelGGL(k_sum_parts, dim3((n + 255) / 256), dim3(256), 0, s, (const double*)RA, P.Pg, n, RBuf);
+        hipLaunchKernelGGL(k_sum_parts, dim3((n + 31) / 32), dim3(256), 0, s, (const double*)RA, P.Pg, n, RBuf);
         h->ev_end(e, s);
         RB = RBuf;
     }
 
     e = h->ev_begin(KC_SVD, s);
-    hipLaunchKernelGGL(k_svd_chain<T>, dim3(1), dim3(kSmallThreads), 0, s, h->geom, st, RB, ldr, gram,
-                       (const double*)QTh, (const double*)QPh, tol, std::min(cap, P.r1cap), std::min(cap, P.r2cap), sc,
-                       h->Thn(), h->Phn(), V,
-                       h->at<double>(P.o_sv));
+    if (P.svd_fast)
+        hipLaunchKernelGGL((k_svd_chain<T, true>), dim3(1), dim3(kSmallThreads), kSmallLdsBytes, s, h->geom, st, RB, ldr,
+                           gram, (const double*)QTh, (const double*)QPh, tol, std::min(cap, P.r1cap),
+                           std::min(cap, P.r2cap), sc, h->Thn(), h->Phn(), V, h->at<double>(P.o_sv));
+    else
+        hipLaunchKernelGGL((k_svd_chain<T, false>), dim3(1), dim3(kSmallThreads), kSmallLdsBytes, s, h->geom, st, RB, ldr,
+                           gram, (const double*)QTh, (const double*)QPh, tol, std::min(cap, P.r1cap),
+                           std::min(cap, P.r2cap), sc, h->Thn(), h->Phn(), V, h->at<double>(P.o_sv));
     h->ev_end(e, s);
 
     e = h->ev_begin(KC_OUTPUT, s);
-    hipLaunchKernelGGL((k_gather_gemm<T, MODE_OUTPUT>), dim3(gx, (P.ldzcap + 63) / 64), dim3(256), 0, s, h->geom, op,
-                       (const DevState*)st, (const T*)B, (const T*)V, (T*)h->Zn(), h->rowdata());
+    if constexpr (f32) {
+        if (P.ldzcap <= 32)
+            hipLaunchKernelGGL((k_gemm_f32_mfma<MODE_OUTPUT, 32>), dim3(gx128, 1), dim3(256), 0, s, h->geom, op,
+                               (const DevState*)st, (const float*)B, (const float*)V, (float*)h->Zn(), h->rowdata());
+        else
+            hipLaunchKernelGGL((k_gemm_f32_mfma<MODE_OUTPUT, 64>), dim3(gx128, (P.ldzcap + 63) / 64), dim3(256), 0, s,
+                               h->geom, op, (const DevState*)st, (const float*)B, (const float*)V, (float*)h->Zn(),
+                               h->rowdata());
+    } else {
+        hipLaunchKernelGGL((k_gather_gemm<T, MODE_OUTPUT>), dim3(gx, (P.ldzcap + 63) / 64), dim3(256), 0, s, h->geom,
+                           op, (const DevState*)st, (const T*)B, (const T*)V, (T*)h->Zn(), h->rowdata());
+    }
     h->ev_end(e, s);
     hipLaunchKernelGGL(k_commit, dim3(1), dim3(64), 0, s, st);
     HIP_TRY(hipGetLastError());
@@ -616,11 +655,25 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
     for (int g = 0; g < P.G; ++g)
         if (!(p->kappa_group_scale[g] >= 0.0) || !std::isfinite(p->kappa_group_scale[g]))
             return fail(TT_ERR_INVALID_ARG, "kappa_group_scale must be finite and >= 0");
+    {
+        static bool attrs_set = false;
+        if (!attrs_set) {
+            HIP_TRY(hipFuncSetAttribute((const void*)k_prep<double>, hipFuncAttributeMaxDynamicSharedMemorySize, kSmallLdsBytes));
+            HIP_TRY(hipFuncSetAttribute((const void*)k_prep<float>, hipFuncAttributeMaxDynamicSharedMemorySize, kSmallLdsBytes));
+            HIP_TRY(hipFuncSetAttribute((const void*)k_svd_chain<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, kSmallLdsBytes));
+            HIP_TRY(hipFuncSetAttribute((const void*)k_svd_chain<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, kSmallLdsBytes));
+            HIP_TRY(hipFuncSetAttribute((const void*)k_svd_chain<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, kSmallLdsBytes));
+            HIP_TRY(hipFuncSetAttribute((const void*)k_svd_chain<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, kSmallLdsBytes));
+            attrs_set = true;
+        }
+    }
     hipStream_t s = (hipStream_t)stream;
     tt_handle* h = new tt_handle();
     h->P = P;
     h->precision = p->precision;
-    h->round_method = p->round_method;
+    h->round_method = p->round_method == TT_ROUND_AUTO
+                          ? (p->precision == TT_PREC_FP64 ? TT_ROUND_QR : TT_ROUND_GRAM)
+                          : p->round_method;
     h->step_order = p->paper_step_order;
     h->tol = p->tol;
     h->ws = (char*)dev_workspace;
@@ -874,8 +927,8 @@ tt_status tt_transport_step_batch(tt_handle** hs, int n, void* stream) {
 tt_status tt_transport_destroy(tt_handle* h) {
     if (!h) return TT_OK;
     for (auto& pr : h->ev_pool) {
-        hipEventDestroy(pr.first);
-        hipEventDestroy(pr.second);
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
     }
     delete h;
     return TT_OK;

@@ -140,10 +140,11 @@ def test_one_step_fp32(tt, dim):
     assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 2e-6 + 2 * p.tol * (r1 != info["r1"] or r2 != info["r2"])
 
 
-def test_solve_fp32_2d(tt):
+@pytest.mark.parametrize("method", ["qr", "auto"])
+def test_solve_fp32_2d(tt, method):
     p = _small(2, prec=ti.PREC_FP32, tol=1e-6, cap=12)
     K = 20
-    s = tt.Solver(p)
+    s = tt.Solver(p, round_method=tt.TT_ROUND_QR if method == "qr" else tt.TT_ROUND_AUTO)
     s.solve(K)
     (Zo, To, Po), _ = ott.solve(p, K)
     assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 1e-4
@@ -151,6 +152,7 @@ def test_solve_fp32_2d(tt):
 
 @pytest.mark.parametrize("prec", [ti.PREC_FP64, ti.PREC_FP32])
 def test_gram_rounding_one_step(tt, prec):
+    # Gram rounding of the first core: FP64 data keeps ~1e-8, FP32 data its own 1e-7
     p = _small(2, prec=prec, tol=1e-6, cap=16)
     s = tt.Solver(p, round_method=tt.TT_ROUND_GRAM)
     Z, Th, Ph = _random_state(p, 4, 3, seed=5)
@@ -159,6 +161,20 @@ def test_gram_rounding_one_step(tt, prec):
     Zo, To, Po, info = ott.step(p, Z, Th, Ph)
     assert s.get_ranks() == (info["r1"], info["r2"])
     assert rel(full(*s.get_cores()), full(Zo, To, Po)) < (1e-8 if prec == ti.PREC_FP64 else 2e-6)
+
+
+@pytest.mark.parametrize("method", ["qr", "gram"])
+def test_solve_2d_fp64_warm_started_jacobi(tt, method):
+    # 2D with N_theta N_phi = 24 directions: from step ~3 on both small-core
+    # factors are identities and the first-bond Jacobi starts from the previous
+    # round's singular vectors; the solve must still equal the oracle
+    p = _small(2, tol=1e-7, cap=16)
+    K = 30
+    s = tt.Solver(p, round_method=tt.TT_ROUND_QR if method == "qr" else tt.TT_ROUND_GRAM)
+    st = s.solve(K)
+    (Zo, To, Po), infos = ott.solve(p, K)
+    assert st["max_R1"] >= 24
+    assert rel(full(*s.get_cores()), full(Zo, To, Po)) < (1e-10 if method == "qr" else 1e-7)
 
 
 def test_paper_step_order(tt):

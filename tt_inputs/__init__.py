@@ -63,6 +63,7 @@ class Problem:
     rank_cap: int = 8
     precision: int = PREC_FP64
     step_order: int = 0          # 0: one rounding per step; 1: round after transport and after source
+    round_method: int = 2        # 0: Householder QR, 1: Gram, 2: QR for FP64 data, Gram otherwise
     n_steps: int = 1
     seed: int = 0
 
