@@ -192,10 +192,17 @@ tt_status tt_transport_get_stats(tt_handle* h, tt_stats* out);
  * durations into tt_stats.kernel_ms (on = 1) or stop (on = 0). */
 tt_status tt_transport_set_timing(tt_handle* h, int on);
 
-/* One full step for each of n independent handles, all enqueued on `stream`
- * so the device overlaps them (the handles' kernels are interleaved per
- * phase).  Handles must be distinct. */
-tt_status tt_transport_step_batch(tt_handle** hs, int n, void* stream);
+/* One full step for each of n independent handles (batched solves).  Handle i
+ * runs on streams[i % n_streams] (hipStream_t values), and the host enqueues
+ * the handles' steps interleaved, so requests on different streams overlap on
+ * the device (the single-workgroup SVD kernels of different handles run on
+ * different compute units).  Handles must be distinct.  Asynchronous. */
+tt_status tt_transport_step_batch(tt_handle** hs, int n, void** streams, int n_streams);
+
+/* n_steps steps of every handle as in tt_transport_step_batch, then a
+ * synchronisation of all streams; out (may be NULL) receives n stats. */
+tt_status tt_transport_solve_batch(tt_handle** hs, int n, int n_steps, void** streams, int n_streams,
+                                   tt_stats* out);
 
 /* Release the handle's host resources.  Never frees the caller's workspace. */
 tt_status tt_transport_destroy(tt_handle* h);

@@ -109,13 +109,15 @@ def _load():
     L.tt_transport_set_cores.argtypes = [vp, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, vp]
     L.tt_transport_get_stats.argtypes = [vp, ctypes.POINTER(TTStats)]
     L.tt_transport_set_timing.argtypes = [vp, ctypes.c_int]
-    L.tt_transport_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp]
+    L.tt_transport_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int]
+    L.tt_transport_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp),
+                                           ctypes.c_int, ctypes.POINTER(TTStats)]
     L.tt_transport_destroy.argtypes = [vp]
     L.tt_transport_last_error.argtypes = []
     L.tt_transport_last_error.restype = ctypes.c_char_p
     L.tt_transport_group_emission.argtypes = [_dp, ctypes.c_int, ctypes.c_double, _dp]
     for name in ("create", "apply_op", "round", "solve", "reset", "get_ranks", "get_cores", "set_cores",
-                 "get_stats", "set_timing", "step_batch", "destroy", "group_emission"):
+                 "get_stats", "set_timing", "step_batch", "solve_batch", "destroy", "group_emission"):
         getattr(L, "tt_transport_" + name).restype = ctypes.c_int
     return L
 
@@ -125,7 +127,7 @@ lib = _load()
 EXPORTED = ("tt_transport_workspace_bytes", "tt_transport_create", "tt_transport_apply_op", "tt_transport_round",
             "tt_transport_solve", "tt_transport_reset", "tt_transport_get_ranks", "tt_transport_get_cores",
             "tt_transport_set_cores", "tt_transport_get_stats", "tt_transport_set_timing",
-            "tt_transport_step_batch", "tt_transport_destroy", "tt_transport_last_error",
+            "tt_transport_step_batch", "tt_transport_solve_batch", "tt_transport_destroy", "tt_transport_last_error",
             "tt_transport_group_emission")
 
 
@@ -295,11 +297,20 @@ class Solver:
             pass
 
 
-def step_batch(solvers, stream=None):
-    """One step of every solver, enqueued on one stream."""
-    import torch
+def _stream_array(streams):
+    return (ctypes.c_void_p * len(streams))(*[ctypes.c_void_p(st.cuda_stream) for st in streams])
 
+
+def step_batch(solvers, streams):
+    """One step of every solver; solver i runs on streams[i % len(streams)]."""
     arr = (ctypes.c_void_p * len(solvers))(*[s.handle for s in solvers])
-    sp = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
-    _check(lib.tt_transport_step_batch(arr, len(solvers), sp))
+    _check(lib.tt_transport_step_batch(arr, len(solvers), _stream_array(streams), len(streams)))
 
+
+def solve_batch(solvers, n_steps, streams):
+    """n_steps steps of every solver, interleaved across the streams, then a
+    synchronisation; returns one stats dict per solver."""
+    arr = (ctypes.c_void_p * len(solvers))(*[s.handle for s in solvers])
+    stats = (TTStats * len(solvers))()
+    _check(lib.tt_transport_solve_batch(arr, len(solvers), int(n_steps), _stream_array(streams), len(streams), stats))
+    return [st.as_dict() for st in stats]

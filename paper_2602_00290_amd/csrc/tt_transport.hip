@@ -910,16 +910,38 @@ tt_status tt_transport_set_timing(tt_handle* h, int on) {
     return TT_OK;
 }
 
-tt_status tt_transport_step_batch(tt_handle** hs, int n, void* stream) {
-    if (!hs || n < 0) return fail(TT_ERR_INVALID_ARG, "bad arguments");
-    for (int i = 0; i < n; ++i)
-        for (int j = i + 1; j < n; ++j)
-            if (hs[i] == hs[j]) return fail(TT_ERR_INVALID_ARG, "handles must be distinct");
-    hipStream_t s = (hipStream_t)stream;
+tt_status tt_transport_step_batch(tt_handle** hs, int n, void** streams, int n_streams) {
+    if (!hs || n < 0 || !streams || n_streams < 1) return fail(TT_ERR_INVALID_ARG, "bad arguments");
     for (int i = 0; i < n; ++i) {
         if (!hs[i]) return fail(TT_ERR_INVALID_ARG, "NULL handle");
-        tt_status r = step_impl(hs[i], s);
+        for (int j = i + 1; j < n; ++j)
+            if (hs[i] == hs[j]) return fail(TT_ERR_INVALID_ARG, "handles must be distinct");
+    }
+    for (int i = 0; i < n; ++i) {
+        tt_status r = step_impl(hs[i], (hipStream_t)streams[i % n_streams]);
         if (r != TT_OK) return r;
+    }
+    return TT_OK;
+}
+
+tt_status tt_transport_solve_batch(tt_handle** hs, int n, int n_steps, void** streams, int n_streams, tt_stats* out) {
+    if (n_steps < 0) return fail(TT_ERR_INVALID_ARG, "n_steps must be >= 0");
+    auto t0 = std::chrono::steady_clock::now();
+    for (int k = 0; k < n_steps; ++k) {
+        tt_status r = tt_transport_step_batch(hs, n, streams, n_streams);
+        if (r != TT_OK) return r;
+    }
+    for (int i = 0; i < n_streams; ++i) HIP_TRY(hipStreamSynchronize((hipStream_t)streams[i]));
+    auto t1 = std::chrono::steady_clock::now();
+    const double sec = std::chrono::duration<double>(t1 - t0).count();
+    for (int i = 0; i < n; ++i) {
+        hs[i]->last_seconds = sec;
+        hs[i]->last_steps = n_steps;
+        hs[i]->ev_collect();
+        if (out) {
+            tt_status r = fill_stats(hs[i], &out[i], (hipStream_t)streams[i % n_streams]);
+            if (r != TT_OK) return r;
+        }
     }
     return TT_OK;
 }

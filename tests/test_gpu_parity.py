@@ -247,3 +247,27 @@ def test_plane2d_full_size_one_step_fp32(tt):
     r1, r2 = s.get_ranks()
     assert (r1, r2) == (info["r1"], info["r2"])
     assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 2e-6
+
+
+def test_batch_results_equal_alone_and_in_the_mix(tt):
+    # independent requests of different shapes and precisions: solved one by one,
+    # then together on two streams with interleaved enqueue; results must be
+    # bitwise identical (no cross-request reductions)
+    import torch
+    probs = [_small(1, tol=1e-7, cap=8, seed=1), _small(2, prec=ti.PREC_FP32, tol=1e-6, cap=12, seed=2),
+             _small(3, tol=1e-6, cap=8, seed=3), _small(2, tol=1e-7, cap=10, seed=4)]
+    K = 12
+    alone = []
+    for p in probs:
+        s = tt.Solver(p)
+        s.solve(K)
+        alone.append(s.get_cores())
+    solvers = [tt.Solver(p) for p in probs]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    stats = tt.solve_batch(solvers, K, streams)
+    assert len(stats) == len(probs)
+    for s, ref, st in zip(solvers, alone, stats):
+        got = s.get_cores()
+        for a, b in zip(got, ref):
+            np.testing.assert_array_equal(a, b)
+        assert (st["r1"], st["r2"]) == (ref[0].shape[1], ref[2].shape[0])
