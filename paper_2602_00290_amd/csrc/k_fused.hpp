@@ -1,0 +1,348 @@
+// Fused gather contraction over the first core on gfx950 MFMA (FP32 state).
+//
+// One persistent kernel walks 32-row tiles of the merged (cell, group) rows:
+//
+//   B[k,:] = d_k ( sum_j Z[nbr_j(k),:] G_j + sum_q z_q(k) g_q )       (projection)
+//
+// with the K dimension laid out as [gather block 0 | block 1 | ... | rank-1
+// columns] (n_gather * ldz + n_r1 rows of the operand).  The d_k row factor
+// and the rank-1 column values are applied to the A operand as it is loaded,
+// so the MFMA result is B itself.
+//
+//   GRAM = true:  B stays in registers and its FP64 Gram matrix B^T B is
+//                 accumulated on FP64 MFMA (products of FP32 values are exact
+//                 in FP64); B is never written.  Each block writes the upper
+//                 16 x 16 blocks of its partial Gram matrix.
+//   GRAM = false: the operand is G' = G V_r and the tile is stored: this is
+//                 Z_out = B V_r evaluated from Z without B in memory.
+//
+// Lane layouts (v_mfma_f32_16x16x4f32 and v_mfma_f64_16x16x4f64, 64 lanes):
+//   A[i][k] from lane i + 16 k,  B[k][j] from lane j + 16 k,
+//   D[i][j] in lane j + 16 (i / 4), register i % 4.
+// The K index of a lane's slot is permuted: in group t (16 K values) lane l
+// supplies K = 16 t + 4 (l / 16) + e to the e-th MFMA of the group, so that
+// one 16-byte load per lane feeds four MFMAs.  The f32 output tile then sits
+// in exactly the FP64 A/B operand layout the Gram MFMA needs (rows of B are
+// summed over, so any row-to-slot assignment that both operands share works).
+#pragma once
+
+#include "k_mfma.hpp"
+
+namespace ttrt {
+
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+constexpr int kFusedWaves = 8;
+constexpr int kFusedThreads = 64 * kFusedWaves;
+
+__host__ __device__ constexpr int gram_blocks(int nct) { return nct * (nct + 1) / 2; }
+
+// Neighbour structure of the gather blocks of one operator (host-computed).
+// Block j of a row k reads row k + delta[j] inside the domain; across a
+// domain edge (boundary-mask bit ebit[j] of the row set) it reads
+// k + wdelta[j] if bit j of wok is set (periodic axis), else nothing.  The
+// rank-1 columns of the operator are a dense block of rw columns per row,
+// stored roff elements after the start of the current Z.
+struct FusedNbr {
+    int delta[kMaxTerms + 1];
+    int wdelta[kMaxTerms + 1];
+    int ebit[kMaxTerms + 1];
+    int wok;
+    int n_gather;
+    int rw;
+    long long roff;
+    int scale_d;
+};
+
+constexpr int kOffSlots = 9;   // gather blocks 0..6, 7: rank-1 block, 8: always empty
+
+// Bytes of dynamic LDS for k_fused_f32<NCT, GRAM> with `ngroups` K groups:
+// operand, per-wave row-offset tables, slot table (and the Gram reduction,
+// which reuses the space).
+__host__ __device__ inline size_t fused_lds_bytes(int nct, bool gram, int ngroups) {
+    const size_t op = (size_t)ngroups * nct * 64 * 16;
+    const size_t offs = (size_t)kFusedWaves * 2 * kOffSlots * 16 * sizeof(int);
+    const size_t sel = (size_t)ngroups * 4 * sizeof(int);
+    const size_t main = op + offs + sel;
+    const size_t red = gram ? (size_t)(kFusedWaves / 2) * gram_blocks(nct) * 256 * sizeof(double) : 0;
+    return main > red ? main : red;
+}
+
+// Per-row constants of the fused kernels, computed once per problem (T is
+// fixed): d_k = 1 / (1 + c dt kappa_k) in FP32 and the boundary mask of the
+// row's cell (bit 2a: first cell along axis a, bit 2a + 1: last cell).
+__global__ __launch_bounds__(256) void k_row_aux(Geom g, RowData rd, float2* __restrict__ aux) {
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= g.M) return;
+    int mask = 0;
+    for (int a = 0; a < g.dim; ++a) {
+        const int idx = axis_index(g, k, a);
+        const int n = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
+        if (idx == 0) mask |= 1 << (2 * a);
+        if (idx == n - 1) mask |= 1 << (2 * a + 1);
+    }
+    float2 v;
+    v.x = (float)(1.0 / (1.0 + g.cdt * row_kappa(g, rd, k)));
+    v.y = __int_as_float(mask);
+    aux[k] = v;
+}
+
+// Rank-1 columns of operator `op` as a dense M x rw block (zero beyond
+// n_r1), already scaled by d_k when the operator scales rows.
+__global__ __launch_bounds__(256) void k_rank1_rows(Geom g, OpDesc op, RowData rd, int rw, float* __restrict__ R) {
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= g.M) return;
+    const float d = (float)row_scale(g, op, rd, k);
+    for (int q = 0; q < rw; ++q) {
+        float v = 0.0f;
+        if (q < op.n_r1) v = (float)rank1_value(g, op, rd, k, q) * d;
+        R[k * rw + q] = v;
+    }
+}
+
+template <int NCT, bool GRAM>
+__global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn, const DevState* __restrict__ st,
+                                                              const float* __restrict__ Z,
+                                                              const float* __restrict__ Gsw,
+                                                              float* __restrict__ Out, const float2* __restrict__ aux,
+                                                              double* __restrict__ Gpart, long long ntiles) {
+    constexpr int NB = gram_blocks(NCT);
+    extern __shared__ __align__(16) unsigned char fused_lds[];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int m = l & 15, q = l >> 4;
+    const int ldz = st->ldz;
+    const int KG = fn.n_gather * ldz;
+    const int K = KG + fn.rw;
+    const int T = (K + 15) >> 4;
+    const int ldo = GRAM ? 0 : st->ldzn;
+
+    f32x4v* Gs = reinterpret_cast<f32x4v*>(fused_lds);
+    int* offs_all = reinterpret_cast<int*>(fused_lds + (size_t)T * NCT * 64 * 16);
+    int* offs = offs_all + w * (2 * kOffSlots * 16);                 // [rt][slot][m] of this wave
+    int* sel = offs_all + kFusedWaves * 2 * kOffSlots * 16;          // [t][q]: slot | column << 8
+
+    {   // operand, already in lane order
+        const f32x4v* src = reinterpret_cast<const f32x4v*>(Gsw);
+        const int nvec = T * NCT * 64;
+        for (int idx = tid; idx < nvec; idx += kFusedThreads) Gs[idx] = src[idx];
+    }
+    for (int idx = tid; idx < T * 4; idx += kFusedThreads) {
+        const int t = idx >> 2, qq = idx & 3;
+        const int k0 = 16 * t + 4 * qq;
+        int slot = 8, cc = 0;
+        if (k0 < KG) {
+            slot = k0 / ldz;
+            cc = k0 - slot * ldz;
+        } else if (k0 < K) {
+            slot = 7;
+            cc = k0 - KG;
+        }
+        sel[idx] = slot | (cc << 8);
+    }
+    if (l < 32) offs[(l >> 4) * kOffSlots * 16 + 8 * 16 + (l & 15)] = -1;   // slot 8 of both row tiles
+    __syncthreads();
+
+    // contiguous tile ranges per wave; consecutive ranges on one XCD (blocks
+    // are dealt to the 8 XCDs round robin)
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int lb = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+    const long long gw = (long long)lb * kFusedWaves + w;
+    const long long nw = (long long)nb * kFusedWaves;
+    const int t_begin = (int)(gw * ntiles / nw), t_end = (int)((gw + 1) * ntiles / nw);
+
+    // Row data of a tile into this wave's offset table; returns d of the
+    // lane's two A rows.  Lane (m, q) writes slots q and q + 4 of row m.
+    auto tile_rows = [&](int tile, float& d0, float& d1) {
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            const int row = 32 * tile + 16 * rt + m;
+            const bool valid = row < g.M;
+            float2 a = make_float2(0.f, 0.f);
+            if (valid) a = aux[row];
+            const int mask = __float_as_int(a.y);
+            const float d = fn.scale_d ? a.x : 1.0f;
+            if (rt == 0) d0 = d; else d1 = d;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                int o = -1;
+                if (j < 7) {
+                    if (valid && j < fn.n_gather) {
+                        const bool edge = (mask >> fn.ebit[j]) & 1;
+                        if (!edge) o = row + fn.delta[j];
+                        else if ((fn.wok >> j) & 1) o = row + fn.wdelta[j];
+                        o = o < 0 ? -1 : o * ldz;
+                    }
+                } else if (valid && fn.rw > 0) {
+                    o = (int)(fn.roff + (long long)row * fn.rw);
+                }
+                if ((j & 3) == q) offs[(rt * kOffSlots + j) * 16 + m] = o;
+            }
+        }
+    };
+    // A operand of K group t for both row tiles (one 16-byte load each)
+    auto load_a = [&](int t, float d0, float d1, f32x4v& a0, f32x4v& a1) {
+        const int sc = sel[t * 4 + q];
+        const int slot = sc & 255, cc = sc >> 8;
+        const int o0 = offs[slot * 16 + m];
+        const int o1 = offs[(kOffSlots + slot) * 16 + m];
+        a0 = (f32x4v){0.f, 0.f, 0.f, 0.f};
+        a1 = a0;
+        if (o0 >= 0) a0 = *reinterpret_cast<const f32x4v*>(Z + o0 + cc);
+        if (o1 >= 0) a1 = *reinterpret_cast<const f32x4v*>(Z + o1 + cc);
+        if (slot < 7) {
+            a0 *= d0;
+            a1 *= d1;
+        }
+    };
+
+    f64x4 gacc[GRAM ? NB : 1];
+#pragma unroll
+    for (int i = 0; i < (GRAM ? NB : 1); ++i) gacc[i] = (f64x4){0.0, 0.0, 0.0, 0.0};
+
+    // Software pipeline over the flat sequence of (tile, group): loads run two
+    // groups ahead, and the next tile's first two groups are issued before this
+    // tile's epilogue.
+    const f32x4v zero4 = (f32x4v){0.f, 0.f, 0.f, 0.f};
+    float d0 = 0.f, d1 = 0.f, nd0 = 0.f, nd1 = 0.f;
+    f32x4v p00 = zero4, p01 = zero4, p10 = zero4, p11 = zero4;   // group t (p0x), t + 1 (p1x); x = row tile
+    if (t_begin < t_end) {
+        tile_rows(t_begin, d0, d1);
+        load_a(0, d0, d1, p00, p01);
+        if (T > 1) load_a(1, d0, d1, p10, p11);
+    }
+    for (int tile = t_begin; tile < t_end; ++tile) {
+        f32x4v acc[2][NCT];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) acc[rt][c] = zero4;
+
+        for (int t = 0; t < T; ++t) {
+            f32x4v n0 = zero4, n1 = zero4;
+            if (t + 2 < T) load_a(t + 2, d0, d1, n0, n1);
+            f32x4v bv[NCT];
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) bv[c] = Gs[(t * NCT + c) * 64 + l];
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int c = 0; c < NCT; ++c) {
+                    acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(p00[e], bv[c][e], acc[0][c], 0, 0, 0);
+                    acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(p01[e], bv[c][e], acc[1][c], 0, 0, 0);
+                }
+            p00 = p10; p01 = p11;
+            p10 = n0; p11 = n1;
+        }
+        const int R0 = 32 * tile;
+        if (tile + 1 < t_end) {
+            tile_rows(tile + 1, nd0, nd1);
+            load_a(0, nd0, nd1, p00, p01);
+            if (T > 1) load_a(1, nd0, nd1, p10, p11);
+        }
+
+        if constexpr (GRAM) {
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double v[NCT];
+#pragma unroll
+                    for (int c = 0; c < NCT; ++c) v[c] = (double)acc[rt][c][r];
+                    int bi = 0;
+#pragma unroll
+                    for (int ga = 0; ga < NCT; ++ga)
+#pragma unroll
+                        for (int gb = ga; gb < NCT; ++gb) {
+                            gacc[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[ga], v[gb], gacc[bi], 0, 0, 0);
+                            ++bi;
+                        }
+                }
+        } else {
+            // D[i][j] of row tile rt: row R0 + 16 rt + 4 q + r, column 16 c + m
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = R0 + 16 * rt + 4 * q + r;
+                    if (row >= g.M) continue;
+#pragma unroll
+                    for (int c = 0; c < NCT; ++c) {
+                        const int col = 16 * c + m;
+                        if (col < ldo) Out[(size_t)row * ldo + col] = acc[rt][c][r];
+                    }
+                }
+        }
+        d0 = nd0;
+        d1 = nd1;
+    }
+
+    if constexpr (GRAM) {
+        // fixed-order reduction of the 8 waves' partial Gram blocks through LDS
+        double* red = reinterpret_cast<double*>(fused_lds);
+        constexpr int PER = NB * 256;   // doubles per wave
+        __syncthreads();
+        for (int half = kFusedWaves / 2; half >= 1; half >>= 1) {
+            if (w >= half && w < 2 * half) {
+#pragma unroll
+                for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) red[(size_t)(w - half) * PER + (bi * 4 + r) * 64 + l] = gacc[bi][r];
+            }
+            __syncthreads();
+            if (w < half) {
+#pragma unroll
+                for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) gacc[bi][r] += red[(size_t)w * PER + (bi * 4 + r) * 64 + l];
+            }
+            __syncthreads();
+        }
+        if (w == 0) {
+            double* outp = Gpart + (size_t)b * PER;
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) outp[(bi * 4 + r) * 64 + l] = gacc[bi][r];
+        }
+    }
+}
+
+// Sum the per-block partial Gram blocks of k_fused_f32<NCT, true> in a fixed
+// order and expand them into the full symmetric (16 NCT) x (16 NCT) matrix
+// (row-major, leading dimension ldg).  Partial entry (bi, r, lane) is element
+// (16 ga + 4 r + lane / 16, 16 gb + lane % 16) of upper block bi = (ga, gb).
+template <int NCT>
+__global__ __launch_bounds__(256) void k_sum_gram(const double* __restrict__ parts, int nparts,
+                                                  double* __restrict__ out, int ldg) {
+    constexpr int NB = gram_blocks(NCT);
+    constexpr int n = NB * 256;
+    __shared__ double sh[8][32];
+    const int e = blockIdx.x * 32 + (threadIdx.x & 31);
+    const int qg = threadIdx.x >> 5;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (e < n) {
+        int p = qg;
+        for (; p + 24 < nparts; p += 32) {
+            s0 += parts[(size_t)p * n + e];
+            s1 += parts[(size_t)(p + 8) * n + e];
+            s2 += parts[(size_t)(p + 16) * n + e];
+            s3 += parts[(size_t)(p + 24) * n + e];
+        }
+        for (; p < nparts; p += 8) s0 += parts[(size_t)p * n + e];
+    }
+    sh[qg][threadIdx.x & 31] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (qg == 0 && e < n) {
+        double t = 0.0;
+        for (int k = 0; k < 8; ++k) t += sh[k][threadIdx.x];
+        const int bi = e >> 8, r = (e >> 6) & 3, ln = e & 63;
+        int ga = 0, rem = bi;
+        while (rem >= NCT - ga) { rem -= NCT - ga; ++ga; }
+        const int gb = ga + rem;
+        const int i = 16 * ga + 4 * r + (ln >> 4), j = 16 * gb + (ln & 15);
+        out[(size_t)i * ldg + j] = t;
+        if (ga != gb) out[(size_t)j * ldg + i] = t;
+    }
+}
+
+}  // namespace ttrt

@@ -580,7 +580,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevSt
                                                         const double* __restrict__ Ph, const double* __restrict__ gtab,
                                                         const double* __restrict__ htab, SmallScratch sc,
                                                         double* __restrict__ LTh, int ldl, double* __restrict__ QTh,
-                                                        double* __restrict__ QPh, TC* __restrict__ Gop) {
+                                                        double* __restrict__ QPh, TC* __restrict__ Gop,
+                                                        TC* __restrict__ Gsw, int nct) {
     extern __shared__ double lds[];
     __shared__ double red[16];
     LdsCarver cv{lds, 0, (size_t)kSmallLdsBytes / sizeof(double)};
@@ -680,8 +681,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevSt
     __syncthreads();
     // 3. gather operand G: rows (gather block j, a < ldz), then rank-1 rows; ldb columns
     const int grows = op.n_gather * ldz + nr1;
-    for (int idx = threadIdx.x; idx < grows * ldb; idx += blockDim.x) {
-        const int row = idx / ldb, col = idx % ldb;
+    auto gval = [&](int row, int col) -> double {
         double v = 0.0;
         if (col < k1) {
             if (row < op.n_gather * ldz) {
@@ -698,9 +698,25 @@ __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevSt
                 v = LTh[(size_t)(nrb * r1 + q) * ldl + col];
             }
         }
-        Gop[(size_t)row * ldb + col] = (TC)v;
+        return v;
+    };
+    for (int idx = threadIdx.x; idx < grows * ldb; idx += blockDim.x) {
+        const int row = idx / ldb, col = idx % ldb;
+        Gop[(size_t)row * ldb + col] = (TC)gval(row, col);
+    }
+    if (Gsw) {
+        // the same operand in the lane order of the fused MFMA contraction:
+        // slot ((t * nct + c) * 64 + lane) * 4 + e holds G[16 t + 4 (lane / 16) + e][16 c + lane % 16]
+        const int ng = (grows + 15) / 16;
+        for (int idx = threadIdx.x; idx < ng * nct * 256; idx += blockDim.x) {
+            const int e = idx & 3, ln = (idx >> 2) & 63, tc = idx >> 8;
+            const int c = tc % nct, t = tc / nct;
+            const int row = 16 * t + 4 * (ln >> 4) + e, col = 16 * c + (ln & 15);
+            Gsw[idx] = (row < grows && col < ldb) ? (TC)gval(row, col) : (TC)0;
+        }
     }
     if (threadIdx.x == 0) {
+        st->kall = grows;
         st->R1 = R1; st->R2 = R2; st->k1 = k1; st->k2 = k2; st->ldb = ldb;
         if (R1 > st->max_R1) st->max_R1 = R1;
         if (R2 > st->max_R2) st->max_R2 = R2;
@@ -730,7 +746,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
                                                              const double* __restrict__ QPh, double tol, int cap1,
                                                              int cap2, SmallScratch sc, double* __restrict__ ThOut,
                                                              double* __restrict__ PhOut, TC* __restrict__ Vout,
-                                                             double* __restrict__ sv_out) {
+                                                             double* __restrict__ sv_out, const TC* __restrict__ Gop,
+                                                             TC* __restrict__ Gfold, int nct_o) {
     extern __shared__ double lds[];
     __shared__ double red[16];
     __shared__ int sh_r[2];
@@ -844,6 +861,25 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
         if (i < k1 && a < r1n) v = W[i + (size_t)p1[a] * ld];
         Vout[(size_t)i * ldzn + a] = (TC)v;
     }
+    if (Gfold) {
+        // operand of the fused output contraction, G' = G V_r, in the lane
+        // order of the fused MFMA kernel (see k_prep)
+        const int kall = st->kall;
+        const int ng = (kall + 15) / 16;
+        for (int idx = threadIdx.x; idx < ng * nct_o * 256; idx += blockDim.x) {
+            const int e = idx & 3, ln = (idx >> 2) & 63, tc = idx >> 8;
+            const int c = tc % nct_o, t = tc / nct_o;
+            const int row = 16 * t + 4 * (ln >> 4) + e, a = 16 * c + (ln & 15);
+            double v = 0.0;
+            if (row < kall && a < r1n) {
+                const TC* gr = Gop + (size_t)row * ldb;
+                const double* wc = W + (size_t)p1[a] * ld;
+#pragma unroll 8
+                for (int i = 0; i < k1; ++i) v += (double)gr[i] * wc[i];
+            }
+            Gfold[idx] = (TC)v;
+        }
+    }
     // Theta'' = V_r^T Q_Theta (r1n x m2) and C2 = diag(S_r) Theta'' as ((r1n N_theta) x k2)
     const int mC = r1n * nt;
     const int mpad = FAST ? (mC <= 128 ? 128 : 256) : mC;   // fixed-layout row count (zero rows beyond mC)
@@ -919,9 +955,16 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
         if (!(norm2 < 1e300) || norm2 != norm2) st->nan_flag = 1;
         st->rounds += 1;
         const double M = (double)g.M, R1 = (double)st->R1, kk = (double)k1;
-        st->fl[0] += 2.0 * M * R1 * kk;
-        st->fl[1] += gram ? 2.0 * M * kk * kk : 2.0 * M * kk * kk - 2.0 / 3.0 * kk * kk * kk;
-        st->fl[2] += 2.0 * M * kk * (double)r1n;
+        if (Gfold) {
+            // fused path: projection + symmetric Gram in one kernel; the
+            // output contraction re-reads Z with K = R1
+            st->fl[0] += 2.0 * M * R1 * kk + M * kk * (kk + 1.0);
+            st->fl[2] += 2.0 * M * R1 * (double)r1n;
+        } else {
+            st->fl[0] += 2.0 * M * R1 * kk;
+            st->fl[1] += gram ? M * kk * (kk + 1.0) : 2.0 * M * kk * kk - 2.0 / 3.0 * kk * kk * kk;
+            st->fl[2] += 2.0 * M * kk * (double)r1n;
+        }
     }
 }
 

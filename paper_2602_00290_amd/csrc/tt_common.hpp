@@ -41,6 +41,8 @@ struct DevState {
     double fl[4];      // algorithmic flops accumulated: project, factor, output, small cores
     int sweeps[2];     // Jacobi sweeps of the last round (bond 1, bond 2)
     long long tph[8];  // wall_clock64 stamps at phase boundaries of the last SVD chain
+    int kall;          // rows of the gather operand: n_gather * ldz + n_r1
+    int pad2;
 };
 
 // Static description of the problem shared by all kernels (passed by value).

@@ -23,6 +23,7 @@
 
 #include "../../include/tt_transport.h"
 #include "k_big.hpp"
+#include "k_fused.hpp"
 #include "k_mfma.hpp"
 #include "k_small.hpp"
 #include "tt_common.hpp"
@@ -65,7 +66,20 @@ struct Plan {
     long long rowsg = 0;
     bool svd_fast = false;          // all SVD-chain matrices fit the LDS layout
     size_t elem = 8;                // bytes per stored element of Z / B
+    // fused FP32 Gram path: projection + FP64 Gram in one kernel, output
+    // contraction from Z with V_r folded into the operand (B never stored)
+    bool fused = false;
+    int nct_p = 4, nct_o = 2;       // 16-column MFMA tiles of B / of Z_out
+    int fused_T = 1;                // K groups of 16 at the rank caps
+    int fused_blocks = 1;           // blocks of the projection + Gram kernel (one partial each)
+    int fused_blocks_o = 1;         // blocks of the output kernel
+    long long fused_tiles = 0;      // 32-row tiles
+    size_t lds_p = 0, lds_o = 0;
+    size_t B_bytes = 0;
     // workspace layout (byte offsets)
+    size_t o_Gsw = 0, o_Gfold = 0, o_GP = 0, o_aux = 0, o_R1 = 0, o_R2 = 0;
+    int rw1 = 0, rw2 = 0;           // widths of the rank-1 row blocks (transport / source operators)
+    bool fused_overflow = false;
     size_t o_state, o_Z0, o_Z1, o_B, o_Th0, o_Th1, o_Ph0, o_Ph1, o_LTh, o_QTh, o_QPh, o_G, o_V, o_RA, o_RB, o_small,
         o_k0, o_ks, o_eps, o_ghost, o_gtab, o_htab, o_ThN, o_PhN, o_sv, o_colsum;
     size_t small_bytes = 0, n_parts_max = 1;
@@ -114,7 +128,7 @@ tt_status validate(const tt_problem* p) {
     return TT_OK;
 }
 
-tt_status make_plan(const tt_problem* p, Plan& P) {
+tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
     tt_status s = validate(p);
     if (s != TT_OK) return s;
     P.dim = p->dim;
@@ -154,6 +168,24 @@ tt_status make_plan(const tt_problem* p, Plan& P) {
     }
     P.chunk = P.KP == 64 ? 8 * 16 : 4 * 16;
     P.elem = p->precision == TT_PREC_FP64 ? 8 : 4;
+    {
+        const int method = p->round_method == TT_ROUND_AUTO
+                               ? (p->precision == TT_PREC_FP64 ? TT_ROUND_QR : TT_ROUND_GRAM)
+                               : p->round_method;
+        P.fused_T = (P.n_gather_max * P.ldzcap + P.n_r1_max + 15) / 16;
+        P.nct_p = P.ldbcap <= 32 ? 2 : 4;
+        P.nct_o = P.ldzcap <= 32 ? 2 : 4;
+        P.lds_p = fused_lds_bytes(P.nct_p, true, P.fused_T);
+        P.lds_o = fused_lds_bytes(P.nct_o, false, P.fused_T);
+        P.fused = allow_fused && p->precision == TT_PREC_FP32 && method == TT_ROUND_GRAM && P.k1cap <= 64 && P.ldzcap <= 64 &&
+                  (long long)(P.M + 64) * P.ldzcap < (1LL << 31) && std::max(P.lds_p, P.lds_o) <= 160 * 1024;
+        P.fused_tiles = (P.M + 31) / 32;
+        const long long want = (P.fused_tiles + kFusedWaves - 1) / kFusedWaves;
+        P.fused_blocks = (int)std::max<long long>(1, std::min<long long>(256, want));
+        if (P.fused_blocks > 8) P.fused_blocks = P.fused_blocks / 8 * 8;
+        P.fused_blocks_o = (int)std::max<long long>(1, std::min<long long>(512, want));
+        if (P.fused_blocks_o > 8) P.fused_blocks_o = P.fused_blocks_o / 8 * 8;
+    }
     // TSQR levels
     {
         long long n = P.M;
@@ -186,7 +218,23 @@ tt_status make_plan(const tt_problem* p, Plan& P) {
     P.o_state = take(sizeof(DevState));
     P.o_Z0 = take((size_t)P.M * P.ldzcap * P.elem);
     P.o_Z1 = take((size_t)P.M * P.ldzcap * P.elem);
-    P.o_B = take((size_t)P.M * P.ldbcap * P.elem);
+    P.B_bytes = (size_t)P.M * P.ldbcap * P.elem;
+    if (P.fused)   // B is not stored; keep a staging buffer for explicit TT-sum reads
+        P.B_bytes = std::min<size_t>(P.B_bytes, std::max<size_t>((size_t)16 << 20, (size_t)P.R1cap * sizeof(double)));
+    P.o_B = take(P.B_bytes);
+    if (P.fused) {
+        P.o_Gsw = take((size_t)P.fused_T * P.nct_p * 256 * sizeof(float));
+        P.o_Gfold = take((size_t)P.fused_T * P.nct_o * 256 * sizeof(float));
+        P.o_GP = take((size_t)P.fused_blocks * gram_blocks(P.nct_p) * 256 * d);
+        P.o_aux = take((size_t)P.M * sizeof(float2));
+        // rank-1 columns as dense row blocks: the full (or transport) operator, and
+        // the source operator when the paper's step order is used
+        const int nr1_t = p->paper_step_order ? P.n_bc : P.n_bc + 1;
+        P.rw1 = nr1_t > 0 ? round_up(nr1_t, 4) : 0;
+        P.rw2 = p->paper_step_order ? 4 : 0;
+        P.o_R1 = take((size_t)P.M * std::max(P.rw1, 1) * sizeof(float));
+        P.o_R2 = take((size_t)P.M * std::max(P.rw2, 1) * sizeof(float));
+    }
     P.o_Th0 = take((size_t)P.r1cap * P.nt * P.r2cap * d);
     P.o_Th1 = take((size_t)P.r1cap * P.nt * P.r2cap * d);
     P.o_Ph0 = take((size_t)P.r2cap * P.np * d);
@@ -227,7 +275,18 @@ tt_status make_plan(const tt_problem* p, Plan& P) {
     P.o_sv = take((size_t)(P.k1cap + P.k2cap) * d);
     P.o_colsum = take((size_t)256 * 128 * d);
     P.bytes = off;
+    // element offsets of the rank-1 blocks from Z must fit 32 bits
+    P.fused_overflow = P.fused && (long long)(P.o_R2 - P.o_Z0) / 4 + (long long)P.M * 8 >= (1LL << 31);
     return TT_OK;
+}
+
+tt_status make_plan(const tt_problem* p, Plan& P) {
+    tt_status s = make_plan_impl(p, P, true);
+    if (s == TT_OK && P.fused_overflow) {
+        P = Plan();
+        s = make_plan_impl(p, P, false);
+    }
+    return s;
 }
 
 }  // namespace
@@ -412,6 +471,92 @@ tt_status reset_impl(tt_handle* h, hipStream_t s) {
     return set_cores_impl<float>(h, 1, 1, h->eps_host.data(), th.data(), ph.data(), s);
 }
 
+// Neighbour structure and rank-1 block of operator `opkind` for the fused
+// kernels (offsets relative to the current Z buffer).
+FusedNbr fused_nbr(const tt_handle* h, int opkind) {
+    const Plan& P = h->P;
+    const OpDesc& op = h->ops[opkind];
+    FusedNbr f;
+    std::memset(&f, 0, sizeof(f));
+    f.n_gather = op.n_gather;
+    f.scale_d = op.scale_d;
+    for (int j = 0; j < kMaxTerms + 1; ++j) f.ebit[j] = 31;
+    for (int j = 1; j < op.n_gather; ++j) {
+        const int a = op.gaxis[j], sg = op.gdir[j];
+        const int n = a == 0 ? P.nx : (a == 1 ? P.ny : P.nz);
+        const int stride = a == 0 ? P.G : (a == 1 ? P.nx * P.G : P.nx * P.ny * P.G);
+        f.delta[j] = sg * stride;
+        f.ebit[j] = 2 * a + (sg > 0 ? 1 : 0);
+        if (h->geom.periodic[a]) {
+            f.wok |= 1 << j;
+            f.wdelta[j] = -sg * (n - 1) * stride;
+        }
+    }
+    const size_t zoff = h->zcur ? P.o_Z1 : P.o_Z0;
+    if (op.n_r1 > 0) {
+        const bool src = opkind == OP_SOURCE;
+        f.rw = src ? P.rw2 : P.rw1;
+        f.roff = ((long long)(src ? P.o_R2 : P.o_R1) - (long long)zoff) / (long long)sizeof(float);
+    }
+    return f;
+}
+
+// Fused FP32 Gram rounding pass (after k_prep): projection + FP64 Gram in one
+// persistent MFMA kernel, fixed-order sum of the block partials, SVD chain
+// (which also folds V_r into the gather operand), then Z_out straight from Z.
+template <int NP, int NO>
+tt_status round_fused_t(tt_handle* h, int opkind, double tol, int cap, hipStream_t s) {
+    const Plan& P = h->P;
+    DevState* st = h->st();
+    SmallScratch sc = h->scratch();
+    float* Gop = h->at<float>(P.o_G);
+    float* V = h->at<float>(P.o_V);
+    double* GP = h->at<double>(P.o_GP);
+    double* RB = h->at<double>(P.o_RB);
+    const FusedNbr fn = fused_nbr(h, opkind);
+    const float2* aux = h->at<float2>(P.o_aux);
+    size_t e = h->ev_begin(KC_PROJECT, s);
+    hipLaunchKernelGGL((k_fused_f32<NP, true>), dim3(P.fused_blocks), dim3(kFusedThreads), P.lds_p, s, h->geom, fn,
+                       (const DevState*)st, (const float*)h->Zc(), (const float*)h->at<float>(P.o_Gsw), (float*)nullptr,
+                       aux, GP, P.fused_tiles);
+    h->ev_end(e, s);
+    e = h->ev_begin(KC_TREE, s);
+    hipLaunchKernelGGL((k_sum_gram<NP>), dim3((gram_blocks(NP) * 256 + 31) / 32), dim3(256), 0, s, (const double*)GP,
+                       P.fused_blocks, RB, P.KP);
+    h->ev_end(e, s);
+    e = h->ev_begin(KC_SVD, s);
+    if (P.svd_fast)
+        hipLaunchKernelGGL((k_svd_chain<float, true>), dim3(1), dim3(kSmallThreads), kSmallLdsBytes, s, h->geom, st,
+                           (const double*)RB, P.KP, 1, (const double*)h->at<double>(P.o_QTh),
+                           (const double*)h->at<double>(P.o_QPh), tol, std::min(cap, P.r1cap), std::min(cap, P.r2cap),
+                           sc, h->Thn(), h->Phn(), V, h->at<double>(P.o_sv), (const float*)Gop,
+                           h->at<float>(P.o_Gfold), NO);
+    else
+        hipLaunchKernelGGL((k_svd_chain<float, false>), dim3(1), dim3(kSmallThreads), kSmallLdsBytes, s, h->geom, st,
+                           (const double*)RB, P.KP, 1, (const double*)h->at<double>(P.o_QTh),
+                           (const double*)h->at<double>(P.o_QPh), tol, std::min(cap, P.r1cap), std::min(cap, P.r2cap),
+                           sc, h->Thn(), h->Phn(), V, h->at<double>(P.o_sv), (const float*)Gop,
+                           h->at<float>(P.o_Gfold), NO);
+    h->ev_end(e, s);
+    e = h->ev_begin(KC_OUTPUT, s);
+    hipLaunchKernelGGL((k_fused_f32<NO, false>), dim3(P.fused_blocks_o), dim3(kFusedThreads), P.lds_o, s, h->geom, fn,
+                       (const DevState*)st, (const float*)h->Zc(), (const float*)h->at<float>(P.o_Gfold),
+                       (float*)h->Zn(), aux, (double*)nullptr, P.fused_tiles);
+    h->ev_end(e, s);
+    hipLaunchKernelGGL(k_commit, dim3(1), dim3(64), 0, s, st);
+    HIP_TRY(hipGetLastError());
+    h->zcur ^= 1;
+    h->ccur ^= 1;
+    return TT_OK;
+}
+
+tt_status round_fused(tt_handle* h, int opkind, double tol, int cap, hipStream_t s) {
+    const Plan& P = h->P;
+    if (P.nct_p == 4)
+        return P.nct_o == 4 ? round_fused_t<4, 4>(h, opkind, tol, cap, s) : round_fused_t<4, 2>(h, opkind, tol, cap, s);
+    return P.nct_o == 4 ? round_fused_t<2, 4>(h, opkind, tol, cap, s) : round_fused_t<2, 2>(h, opkind, tol, cap, s);
+}
+
 // One rounding pass applying operator `op` (OP_NONE: plain rounding).
 template <typename T>
 tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t s) {
@@ -427,14 +572,20 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
     double* QPh = h->at<double>(P.o_QPh);
     size_t e;
 
+    constexpr bool f32 = std::is_same<T, float>::value;
+    const bool fused = f32 && P.fused;
+    T* Gsw = fused ? h->at<T>(P.o_Gsw) : nullptr;
+    T* Gfold = fused ? h->at<T>(P.o_Gfold) : nullptr;
     e = h->ev_begin(KC_PREP, s);
     hipLaunchKernelGGL(k_prep<T>, dim3(1), dim3(kSmallThreads), kSmallLdsBytes, s, h->geom, op, st, h->Thc(), h->Phc(),
-                       h->at<double>(P.o_gtab), h->at<double>(P.o_htab), sc, LTh, P.k1cap, QTh, QPh, Gop);
+                       h->at<double>(P.o_gtab), h->at<double>(P.o_htab), sc, LTh, P.k1cap, QTh, QPh, Gop, Gsw, P.nct_p);
     h->ev_end(e, s);
+    if constexpr (f32) {
+        if (fused) return round_fused(h, opkind, tol, cap, s);
+    }
 
     const unsigned gx = (unsigned)((P.M + 63) / 64);
     const unsigned gx128 = (unsigned)((P.M + 127) / 128);
-    constexpr bool f32 = std::is_same<T, float>::value;
     e = h->ev_begin(KC_PROJECT, s);
     if constexpr (f32)
         hipLaunchKernelGGL((k_gemm_f32_mfma<MODE_PROJECT, 64>), dim3(gx128, (P.ldbcap + 63) / 64), dim3(256), 0, s,
@@ -499,11 +650,13 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
     if (P.svd_fast)
         hipLaunchKernelGGL((k_svd_chain<T, true>), dim3(1), dim3(kSmallThreads), kSmallLdsBytes, s, h->geom, st, RB, ldr,
                            gram, (const double*)QTh, (const double*)QPh, tol, std::min(cap, P.r1cap),
-                           std::min(cap, P.r2cap), sc, h->Thn(), h->Phn(), V, h->at<double>(P.o_sv));
+                           std::min(cap, P.r2cap), sc, h->Thn(), h->Phn(), V, h->at<double>(P.o_sv),
+                           (const T*)nullptr, (T*)nullptr, 0);
     else
         hipLaunchKernelGGL((k_svd_chain<T, false>), dim3(1), dim3(kSmallThreads), kSmallLdsBytes, s, h->geom, st, RB, ldr,
                            gram, (const double*)QTh, (const double*)QPh, tol, std::min(cap, P.r1cap),
-                           std::min(cap, P.r2cap), sc, h->Thn(), h->Phn(), V, h->at<double>(P.o_sv));
+                           std::min(cap, P.r2cap), sc, h->Thn(), h->Phn(), V, h->at<double>(P.o_sv),
+                           (const T*)nullptr, (T*)nullptr, 0);
     h->ev_end(e, s);
 
     e = h->ev_begin(KC_OUTPUT, s);
@@ -664,6 +817,10 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
             HIP_TRY(hipFuncSetAttribute((const void*)k_svd_chain<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, kSmallLdsBytes));
             HIP_TRY(hipFuncSetAttribute((const void*)k_svd_chain<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, kSmallLdsBytes));
             HIP_TRY(hipFuncSetAttribute((const void*)k_svd_chain<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, kSmallLdsBytes));
+            HIP_TRY(hipFuncSetAttribute((const void*)k_fused_f32<2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+            HIP_TRY(hipFuncSetAttribute((const void*)k_fused_f32<4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+            HIP_TRY(hipFuncSetAttribute((const void*)k_fused_f32<2, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+            HIP_TRY(hipFuncSetAttribute((const void*)k_fused_f32<4, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
             attrs_set = true;
         }
     }
@@ -758,6 +915,17 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
     if ((u = upload(h->at<double>(P.o_gtab), gtab, s)) != TT_OK) { delete h; return u; }
     if ((u = upload(h->at<double>(P.o_htab), htab, s)) != TT_OK) { delete h; return u; }
     if (hipMemsetAsync(h->ws + P.o_G, 0, P.o_V - P.o_G, s) != hipSuccess) { delete h; return fail(TT_ERR_HIP, "memset"); }
+    if (P.fused) {
+        const dim3 gr((unsigned)((P.M + 255) / 256));
+        hipLaunchKernelGGL(k_row_aux, gr, dim3(256), 0, s, h->geom, h->rowdata(), h->at<float2>(P.o_aux));
+        if (P.rw1 > 0)
+            hipLaunchKernelGGL(k_rank1_rows, gr, dim3(256), 0, s, h->geom, h->ops[h->step_order ? OP_TRANSPORT : OP_FULL],
+                               h->rowdata(), P.rw1, h->at<float>(P.o_R1));
+        if (P.rw2 > 0)
+            hipLaunchKernelGGL(k_rank1_rows, gr, dim3(256), 0, s, h->geom, h->ops[OP_SOURCE], h->rowdata(), P.rw2,
+                               h->at<float>(P.o_R2));
+        if (hipGetLastError() != hipSuccess) { delete h; return fail(TT_ERR_HIP, "row table launch"); }
+    }
     if ((u = reset_impl(h, s)) != TT_OK) { delete h; return u; }
     *out = h;
     return TT_OK;
@@ -843,7 +1011,7 @@ tt_status tt_transport_get_cores(tt_handle* h, double* Z, double* Theta, double*
         const int R1 = op.n_rblk * st.r1 + op.n_r1, R2 = op.n_rblk * st.r2 + op.n_r1;
         if (Z) {
             double* buf = h->at<double>(P.o_B);
-            const long long cap_rows = std::max<long long>(1, (long long)(P.M * P.ldbcap * P.elem / sizeof(double)) / R1);
+            const long long cap_rows = std::max<long long>(1, (long long)(P.B_bytes / sizeof(double)) / R1);
             for (long long k0 = 0; k0 < P.M; k0 += cap_rows) {
                 const long long nr = std::min(cap_rows, P.M - k0);
                 if (h->precision == TT_PREC_FP64)
