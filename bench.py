@@ -67,12 +67,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--round-method", default="auto", choices=["qr", "gram", "auto"])
     ap.add_argument("--timing", type=int, default=1, help="HIP-event timing of kernel classes")
-    ap.add_argument("--batch", type=int, default=8, help="independent solves advanced together")
-    ap.add_argument("--streams", type=int, default=8, help="HIP streams for the batch")
+    ap.add_argument("--batch", type=int, default=16, help="independent solves advanced together")
+    ap.add_argument("--streams", type=int, default=16, help="HIP streams for the batch")
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="GPU_MAX_HW_QUEUES for this process (0: keep the environment's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    # one hardware queue per stream: with fewer queues than streams, independent
+    # solves wait behind each other's latency-bound small-core kernels.  Must be
+    # set before the HIP runtime initialises.
+    if args.hw_queues > 0:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, args.hw_queues))
 
     import numpy as np
     import torch

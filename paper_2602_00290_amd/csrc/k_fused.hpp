@@ -42,7 +42,10 @@ __host__ __device__ constexpr int gram_blocks(int nct) { return nct * (nct + 1) 
 // domain edge (boundary-mask bit ebit[j] of the row set) it reads
 // k + wdelta[j] if bit j of wok is set (periodic axis), else nothing.  The
 // rank-1 columns of the operator are a dense block of rw columns per row,
-// stored roff elements after the start of the current Z.
+// stored roff elements after the start of the current Z.  Every load of the
+// fused kernels is unconditional: a slot with nothing to read points at a
+// zero region (zoff), which keeps the loads branch-free so that they stay in
+// flight across the pipeline.
 struct FusedNbr {
     int delta[kMaxTerms + 1];
     int wdelta[kMaxTerms + 1];
@@ -51,19 +54,19 @@ struct FusedNbr {
     int n_gather;
     int rw;
     long long roff;
+    long long zoff;   // offset of a zero region of at least 64 elements (loads with nothing to read go there)
     int scale_d;
 };
 
 constexpr int kOffSlots = 9;   // gather blocks 0..6, 7: rank-1 block, 8: always empty
 
 // Bytes of dynamic LDS for k_fused_f32<NCT, GRAM> with `ngroups` K groups:
-// operand, per-wave row-offset tables, slot table (and the Gram reduction,
-// which reuses the space).
+// operand and per-wave row-offset tables (the Gram reduction reuses the
+// space).
 __host__ __device__ inline size_t fused_lds_bytes(int nct, bool gram, int ngroups) {
-    const size_t op = (size_t)ngroups * nct * 64 * 16;
+    const size_t op = (size_t)((ngroups + 1) & ~1) * nct * 64 * 16;   // group count padded to even
     const size_t offs = (size_t)kFusedWaves * 2 * kOffSlots * 16 * sizeof(int);
-    const size_t sel = (size_t)ngroups * 4 * sizeof(int);
-    const size_t main = op + offs + sel;
+    const size_t main = op + offs;
     const size_t red = gram ? (size_t)(kFusedWaves / 2) * gram_blocks(nct) * 256 * sizeof(double) : 0;
     return main > red ? main : red;
 }
@@ -88,16 +91,11 @@ __global__ __launch_bounds__(256) void k_row_aux(Geom g, RowData rd, float2* __r
 }
 
 // Rank-1 columns of operator `op` as a dense M x rw block (zero beyond
-// n_r1), already scaled by d_k when the operator scales rows.
+// n_r1); the fused kernels scale them by d_k with the rest of the row.
 __global__ __launch_bounds__(256) void k_rank1_rows(Geom g, OpDesc op, RowData rd, int rw, float* __restrict__ R) {
     const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
     if (k >= g.M) return;
-    const float d = (float)row_scale(g, op, rd, k);
-    for (int q = 0; q < rw; ++q) {
-        float v = 0.0f;
-        if (q < op.n_r1) v = (float)rank1_value(g, op, rd, k, q) * d;
-        R[k * rw + q] = v;
-    }
+    for (int q = 0; q < rw; ++q) R[k * rw + q] = q < op.n_r1 ? (float)rank1_value(g, op, rd, k, q) : 0.0f;
 }
 
 template <int NCT, bool GRAM>
@@ -114,32 +112,22 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
     const int KG = fn.n_gather * ldz;
     const int K = KG + fn.rw;
     const int T = (K + 15) >> 4;
+    const int T2 = (T + 1) & ~1;   // groups padded to even (the padding group has a zero operand)
     const int ldo = GRAM ? 0 : st->ldzn;
+    const float rldz = 1.0f / (float)ldz;
 
     f32x4v* Gs = reinterpret_cast<f32x4v*>(fused_lds);
-    int* offs_all = reinterpret_cast<int*>(fused_lds + (size_t)T * NCT * 64 * 16);
+    int* offs_all = reinterpret_cast<int*>(fused_lds + (size_t)T2 * NCT * 64 * 16);
     int* offs = offs_all + w * (2 * kOffSlots * 16);                 // [rt][slot][m] of this wave
-    int* sel = offs_all + kFusedWaves * 2 * kOffSlots * 16;          // [t][q]: slot | column << 8
 
     {   // operand, already in lane order
         const f32x4v* src = reinterpret_cast<const f32x4v*>(Gsw);
         const int nvec = T * NCT * 64;
-        for (int idx = tid; idx < nvec; idx += kFusedThreads) Gs[idx] = src[idx];
+        for (int idx = tid; idx < T2 * NCT * 64; idx += kFusedThreads)
+            Gs[idx] = idx < nvec ? src[idx] : (f32x4v){0.f, 0.f, 0.f, 0.f};
     }
-    for (int idx = tid; idx < T * 4; idx += kFusedThreads) {
-        const int t = idx >> 2, qq = idx & 3;
-        const int k0 = 16 * t + 4 * qq;
-        int slot = 8, cc = 0;
-        if (k0 < KG) {
-            slot = k0 / ldz;
-            cc = k0 - slot * ldz;
-        } else if (k0 < K) {
-            slot = 7;
-            cc = k0 - KG;
-        }
-        sel[idx] = slot | (cc << 8);
-    }
-    if (l < 32) offs[(l >> 4) * kOffSlots * 16 + 8 * 16 + (l & 15)] = -1;   // slot 8 of both row tiles
+    const int zoff = (int)fn.zoff;
+    if (l < 32) offs[(l >> 4) * kOffSlots * 16 + 8 * 16 + (l & 15)] = zoff;   // slot 8 of both row tiles
     __syncthreads();
 
     // contiguous tile ranges per wave; consecutive ranges on one XCD (blocks
@@ -150,27 +138,33 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
     const long long nw = (long long)nb * kFusedWaves;
     const int t_begin = (int)(gw * ntiles / nw), t_end = (int)((gw + 1) * ntiles / nw);
 
-    // Row data of a tile into this wave's offset table; returns d of the
-    // lane's two A rows.  Lane (m, q) writes slots q and q + 4 of row m.
-    auto tile_rows = [&](int tile, float& d0, float& d1) {
+    // Row data of a tile (from its prefetched row-table entries a0, a1) into
+    // this wave's offset table; returns d of the lane's two A rows.  Lane
+    // (m, q) writes slots q and q + 4 of row m.
+    const int last = (int)g.M - 1;
+    auto aux_of = [&](int tile, int rt) -> float2 {
+        const int row = 32 * tile + 16 * rt + m;
+        return aux[row < last ? row : last];   // rows past the end are never used
+    };
+    auto tile_rows = [&](int tile, float2 a0, float2 a1, float& d0, float& d1) {
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
             const int row = 32 * tile + 16 * rt + m;
             const bool valid = row < g.M;
-            float2 a = make_float2(0.f, 0.f);
-            if (valid) a = aux[row];
+            const float2 a = rt == 0 ? a0 : a1;
             const int mask = __float_as_int(a.y);
             const float d = fn.scale_d ? a.x : 1.0f;
             if (rt == 0) d0 = d; else d1 = d;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                int o = -1;
+                int o = zoff;
                 if (j < 7) {
                     if (valid && j < fn.n_gather) {
                         const bool edge = (mask >> fn.ebit[j]) & 1;
-                        if (!edge) o = row + fn.delta[j];
-                        else if ((fn.wok >> j) & 1) o = row + fn.wdelta[j];
-                        o = o < 0 ? -1 : o * ldz;
+                        int nr = -1;
+                        if (!edge) nr = row + fn.delta[j];
+                        else if ((fn.wok >> j) & 1) nr = row + fn.wdelta[j];
+                        if (nr >= 0) o = nr * ldz;
                     }
                 } else if (valid && fn.rw > 0) {
                     o = (int)(fn.roff + (long long)row * fn.rw);
@@ -179,66 +173,76 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
             }
         }
     };
-    // A operand of K group t for both row tiles (one 16-byte load each)
-    auto load_a = [&](int t, float d0, float d1, f32x4v& a0, f32x4v& a1) {
-        const int sc = sel[t * 4 + q];
-        const int slot = sc & 255, cc = sc >> 8;
+    // A operand of K group t for both row tiles (one 16-byte load each, not
+    // yet scaled by d: the scale is applied when the group is consumed, so
+    // the load stays in flight)
+    auto load_a = [&](int t, f32x4v& a0, f32x4v& a1) {
+        // slot of this lane's 4 K values: gather block k0 / ldz, the rank-1
+        // block (7) or nothing (8)
+        const int k0 = 16 * t + 4 * q;
+        const int jj = (int)(((float)k0 + 0.5f) * rldz);   // k0 / ldz, exact for these small integers
+        const int slot = k0 < KG ? jj : (k0 < K ? 7 : 8);
+        const int cc = k0 < KG ? k0 - jj * ldz : (k0 < K ? k0 - KG : 0);
         const int o0 = offs[slot * 16 + m];
         const int o1 = offs[(kOffSlots + slot) * 16 + m];
-        a0 = (f32x4v){0.f, 0.f, 0.f, 0.f};
-        a1 = a0;
-        if (o0 >= 0) a0 = *reinterpret_cast<const f32x4v*>(Z + o0 + cc);
-        if (o1 >= 0) a1 = *reinterpret_cast<const f32x4v*>(Z + o1 + cc);
-        if (slot < 7) {
-            a0 *= d0;
-            a1 *= d1;
-        }
+        a0 = *reinterpret_cast<const f32x4v*>(Z + o0 + cc);
+        a1 = *reinterpret_cast<const f32x4v*>(Z + o1 + cc);
     };
 
     f64x4 gacc[GRAM ? NB : 1];
 #pragma unroll
     for (int i = 0; i < (GRAM ? NB : 1); ++i) gacc[i] = (f64x4){0.0, 0.0, 0.0, 0.0};
 
-    // Software pipeline over the flat sequence of (tile, group): loads run two
-    // groups ahead, and the next tile's first two groups are issued before this
-    // tile's epilogue.
+    // Software pipeline over the flat sequence of (tile, group).  Two register
+    // stages X and Y alternate (the K loop is unrolled by two, so no stage is
+    // ever copied: a copy would wait for its load): group t computes from
+    // one stage and refills it with group t + 2; the B operand of group t + 1
+    // is read from LDS while group t computes.  The next tile's first two
+    // groups are issued before this tile's epilogue, and its row-table
+    // entries a whole tile ahead.
     const f32x4v zero4 = (f32x4v){0.f, 0.f, 0.f, 0.f};
     float d0 = 0.f, d1 = 0.f, nd0 = 0.f, nd1 = 0.f;
-    f32x4v p00 = zero4, p01 = zero4, p10 = zero4, p11 = zero4;   // group t (p0x), t + 1 (p1x); x = row tile
+    f32x4v x0 = zero4, x1 = zero4, y0 = zero4, y1 = zero4;
     if (t_begin < t_end) {
-        tile_rows(t_begin, d0, d1);
-        load_a(0, d0, d1, p00, p01);
-        if (T > 1) load_a(1, d0, d1, p10, p11);
+        tile_rows(t_begin, aux_of(t_begin, 0), aux_of(t_begin, 1), d0, d1);
+        load_a(0, x0, x1);
+        load_a(1, y0, y1);
     }
+    f32x4v acc[2][NCT];
+    // (group t + 1 = T2 reads past the operand into the offset tables and
+    // groups t + 2 >= T load from the zero region: both unused, both in bounds)
+    auto stage = [&](int t, f32x4v& s0, f32x4v& s1, f32x4v (&bc)[NCT], f32x4v (&bn)[NCT]) {
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) bn[c] = Gs[((t + 1) * NCT + c) * 64 + l];
+        const f32x4v a0 = s0 * d0, a1 = s1 * d1;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) {
+                acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[e], bc[c][e], acc[0][c], 0, 0, 0);
+                acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[e], bc[c][e], acc[1][c], 0, 0, 0);
+            }
+        load_a(t + 2, s0, s1);
+    };
     for (int tile = t_begin; tile < t_end; ++tile) {
-        f32x4v acc[2][NCT];
+        const bool more = tile + 1 < t_end;
+        const float2 na0 = aux_of(tile + 1, 0), na1 = aux_of(tile + 1, 1);
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
             for (int c = 0; c < NCT; ++c) acc[rt][c] = zero4;
 
-        for (int t = 0; t < T; ++t) {
-            f32x4v n0 = zero4, n1 = zero4;
-            if (t + 2 < T) load_a(t + 2, d0, d1, n0, n1);
-            f32x4v bv[NCT];
+        f32x4v bA[NCT], bB[NCT];
 #pragma unroll
-            for (int c = 0; c < NCT; ++c) bv[c] = Gs[(t * NCT + c) * 64 + l];
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-#pragma unroll
-                for (int c = 0; c < NCT; ++c) {
-                    acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(p00[e], bv[c][e], acc[0][c], 0, 0, 0);
-                    acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(p01[e], bv[c][e], acc[1][c], 0, 0, 0);
-                }
-            p00 = p10; p01 = p11;
-            p10 = n0; p11 = n1;
+        for (int c = 0; c < NCT; ++c) bA[c] = Gs[c * 64 + l];
+        for (int t = 0; t < T2; t += 2) {
+            stage(t, x0, x1, bA, bB);
+            stage(t + 1, y0, y1, bB, bA);
         }
         const int R0 = 32 * tile;
-        if (tile + 1 < t_end) {
-            tile_rows(tile + 1, nd0, nd1);
-            load_a(0, nd0, nd1, p00, p01);
-            if (T > 1) load_a(1, nd0, nd1, p10, p11);
-        }
+        if (more) tile_rows(tile + 1, na0, na1, nd0, nd1);
+        load_a(0, x0, x1);
+        load_a(1, y0, y1);
 
         if constexpr (GRAM) {
 #pragma unroll

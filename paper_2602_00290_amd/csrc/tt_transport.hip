@@ -77,7 +77,7 @@ struct Plan {
     size_t lds_p = 0, lds_o = 0;
     size_t B_bytes = 0;
     // workspace layout (byte offsets)
-    size_t o_Gsw = 0, o_Gfold = 0, o_GP = 0, o_aux = 0, o_R1 = 0, o_R2 = 0;
+    size_t o_Gsw = 0, o_Gfold = 0, o_GP = 0, o_aux = 0, o_R1 = 0, o_R2 = 0, o_zero = 0;
     int rw1 = 0, rw2 = 0;           // widths of the rank-1 row blocks (transport / source operators)
     bool fused_overflow = false;
     size_t o_state, o_Z0, o_Z1, o_B, o_Th0, o_Th1, o_Ph0, o_Ph1, o_LTh, o_QTh, o_QPh, o_G, o_V, o_RA, o_RB, o_small,
@@ -234,6 +234,7 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         P.rw2 = p->paper_step_order ? 4 : 0;
         P.o_R1 = take((size_t)P.M * std::max(P.rw1, 1) * sizeof(float));
         P.o_R2 = take((size_t)P.M * std::max(P.rw2, 1) * sizeof(float));
+        P.o_zero = take(1024);   // zero region for loads with nothing to read
     }
     P.o_Th0 = take((size_t)P.r1cap * P.nt * P.r2cap * d);
     P.o_Th1 = take((size_t)P.r1cap * P.nt * P.r2cap * d);
@@ -276,7 +277,7 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
     P.o_colsum = take((size_t)256 * 128 * d);
     P.bytes = off;
     // element offsets of the rank-1 blocks from Z must fit 32 bits
-    P.fused_overflow = P.fused && (long long)(P.o_R2 - P.o_Z0) / 4 + (long long)P.M * 8 >= (1LL << 31);
+    P.fused_overflow = P.fused && (long long)(P.o_zero - P.o_Z0) / 4 + 256 >= (1LL << 31);
     return TT_OK;
 }
 
@@ -498,6 +499,7 @@ FusedNbr fused_nbr(const tt_handle* h, int opkind) {
         f.rw = src ? P.rw2 : P.rw1;
         f.roff = ((long long)(src ? P.o_R2 : P.o_R1) - (long long)zoff) / (long long)sizeof(float);
     }
+    f.zoff = ((long long)P.o_zero - (long long)zoff) / (long long)sizeof(float);
     return f;
 }
 
@@ -916,6 +918,7 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
     if ((u = upload(h->at<double>(P.o_htab), htab, s)) != TT_OK) { delete h; return u; }
     if (hipMemsetAsync(h->ws + P.o_G, 0, P.o_V - P.o_G, s) != hipSuccess) { delete h; return fail(TT_ERR_HIP, "memset"); }
     if (P.fused) {
+        if (hipMemsetAsync(h->ws + P.o_zero, 0, 1024, s) != hipSuccess) { delete h; return fail(TT_ERR_HIP, "memset"); }
         const dim3 gr((unsigned)((P.M + 255) / 256));
         hipLaunchKernelGGL(k_row_aux, gr, dim3(256), 0, s, h->geom, h->rowdata(), h->at<float2>(P.o_aux));
         if (P.rw1 > 0)
