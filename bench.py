@@ -4,19 +4,31 @@ Workload (the 2D configuration): 128 x 128 cells on [0,1]^2, 32 groups with
 log-spaced edges on [0.01, 10], 8 polar x 8 azimuthal product quadrature,
 seeded lognormal kappa0 (sigma 1, correlation length 0.1), kappa_g = kappa0 nu_g^-3,
 medium T = 0.1, Planck T = 1 inflow on x = 0; FP32 contractions with FP64
-QR / SVD / truncation, rank cap 32, tol 1e-6; one solve = 512 steps (t = L/c
-at CFL 0.5) from the rank-1 Planck state.  A benchmark step is one full solve of a batch of B independent requests
-of this workload (seeds 0..B-1) advanced together on B streams.
+Gram / SVD / truncation, rank cap 32, tol 1e-6; one solve = 512 steps (t = L/c
+at CFL 0.5) from the rank-1 Planck state.  A benchmark step is one full solve
+of a batch of B independent requests of this workload (seeds 0..B-1)
+advanced together on B streams.
 
 Prints one JSON line.  `value` = aggregate solves/s of the batch with inputs
 resident on the device.  A second timed phase runs one solve alone with
 HIP-event timing of every kernel class on the library's stream; `roofline`
-reports the dominant class from it.  `cpu_baseline` times the dense FP64 CPU
-oracle on this host for a bounded sample of the same workload.
+reports the kernel that bounds the batched throughput (the fused projection +
+FP64 Gram contraction) from it, and `traffic` its HBM bytes per launch from the
+committed counter summary (null when the kernel source has changed since).
+`cpu_baseline` times the dense FP64 CPU oracle on this host for a bounded
+sample of the same workload.
+
+Other modes (for profiling runs; they print one line and exit):
+  --mode probe        one solve of the workload for `--probe-steps` steps
+  --mode copy         a plain device-to-device copy of `--copy-mb` MiB (counter calibration)
+  --mode pmc-summary  turn rocprofv3 counter CSVs (--pmc-dir) into profiles/traffic_plane2d.json
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -31,6 +43,18 @@ PEAKS = {  # MI355X published dense peaks, TFLOP/s
 HBM_PEAK_GBS = 8000.0
 
 METRIC = "TT solves/s & TT apply+round GFLOP/s (% MFMA peak); p50/p99 solve latency"
+FUSED_KERNEL = "k_fused_f32<4, true>"
+KERNEL_SOURCES = ["paper_2602_00290_amd/csrc/k_fused.hpp", "paper_2602_00290_amd/csrc/k_mfma.hpp",
+                  "paper_2602_00290_amd/csrc/tt_common.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plane2d.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(prob, budget_s: float = 12.0):
@@ -59,6 +83,116 @@ def cpu_baseline(prob, budget_s: float = 12.0):
     }
 
 
+def stored_traffic():
+    """HBM bytes per launch of the fused kernel from the committed counter
+    summary, or None if it is missing or was taken on different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    return t
+
+
+def roofline(st1):
+    """Roofline of the fused projection + FP64 Gram kernel from the single-solve
+    event timing.  Its flops are FP32 MFMA (projection, 2 M R1 k1 per launch)
+    plus FP64 MFMA (symmetric Gram, M k1 (k1 + 1)); the peak is the rate of
+    that mix at the published dense peaks: (F32 + F64) / (F32 / P32 + F64 / P64)."""
+    ms, n, fl = st1["kernel_ms"], st1["kernel_launches"], st1["flops"]
+    if not n["project"] or not ms["project"]:
+        return None
+    f32, f64 = fl["project"], (fl["factor"] if n["factor"] == 0 else 0.0)
+    sec = ms["project"] * 1e-3
+    achieved = (f32 + f64) / sec / 1e12
+    peak = (f32 + f64) / (f32 / PEAKS["fp32"] + f64 / PEAKS["fp64"]) if (f32 + f64) > 0 else PEAKS["fp32"]
+    t = stored_traffic()
+    out = {"bound": "mfma", "kernel": FUSED_KERNEL, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+           "frac": achieved / peak, "traffic": (t["fetch_bytes"] + t["write_bytes"]) if t else None,
+           "avg_launch_ms": ms["project"] / n["project"], "launches": n["project"],
+           "flops_per_launch": {"fp32": f32 / n["project"], "fp64": f64 / n["project"]}}
+    if t:
+        out["traffic_detail"] = {k: t[k] for k in ("fetch_bytes", "write_bytes", "algorithmic_bytes")}
+    return out
+
+
+def mode_copy(args):
+    import torch
+    n = args.copy_mb * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(8):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copy", "bytes_per_copy": n * 4, "copies": 8}), flush=True)
+
+
+def mode_probe(args):
+    import torch
+    import paper_2602_00290_amd as tt
+    import tt_inputs as ti
+    s = tt.Solver(ti.plane2d())
+    st = s.solve(args.probe_steps)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "probe", "steps": args.probe_steps, "ranks": [st["r1"], st["r2"]]}), flush=True)
+
+
+def _pmc_rows(path, counter):
+    rows = []
+    for fn in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
+        with open(fn) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter:
+                    rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    rows.sort()
+    return rows
+
+
+def mode_pmc_summary(args):
+    """profiles/traffic_plane2d.json from four counter runs under --pmc-dir:
+    fetch/ and write/ (FETCH_SIZE, WRITE_SIZE of `--mode probe`), copy_fetch/ and
+    copy_write/ (the same counters of `--mode copy`).  Counter values are KiB per
+    dispatch; each is scaled by copy bytes / counter of the copy kernel."""
+    d = args.pmc_dir
+    nbytes = args.copy_mb * (1 << 20)
+
+    def copy_factor(sub, counter):
+        rows = _pmc_rows(os.path.join(d, sub), counter)
+        vals = sorted(v for _, _, v in rows)[-4:]          # the large copies
+        return nbytes / (sum(vals) / len(vals) * 1024.0)
+
+    def fused(sub, counter):
+        key = FUSED_KERNEL.replace(" ", "")
+        rows = [v for _, k, v in _pmc_rows(os.path.join(d, sub), counter) if key in k.replace(" ", "")]
+        steady = rows[len(rows) // 2:]                      # second half: ranks at their steady values
+        return sum(steady) / len(steady) * 1024.0, len(steady)
+
+    ff, fw = copy_factor("copy_fetch", "FETCH_SIZE"), copy_factor("copy_write", "WRITE_SIZE")
+    fetch, nf = fused("fetch", "FETCH_SIZE")
+    write, nw = fused("write", "WRITE_SIZE")
+    import tt_inputs as ti
+    p = ti.plane2d()
+    out = {
+        "kernel": FUSED_KERNEL,
+        "workload": "plane2d steady state (second half of a 64-step probe)",
+        "source_hash": kernel_source_hash(),
+        "fetch_bytes": fetch * ff,
+        "write_bytes": write * fw,
+        "raw_fetch_bytes": fetch, "raw_write_bytes": write, "dispatches": [nf, nw],
+        "calibration": {"copy_bytes": nbytes, "fetch_factor": ff, "write_factor": fw},
+        # Z read once (ld 24 floats) + row table (8 B) + rank-1 block (4 floats) + Gram partials
+        "algorithmic_bytes": p.M * (24 * 4 + 8 + 16) + 256 * 10 * 256 * 8,
+        "commands": [f"rocprofv3 --pmc {c} --output-format csv -d <dir>/{s} -o {s} -- python3 bench.py --mode {m}"
+                     for c, s, m in (("FETCH_SIZE", "fetch", "probe"), ("WRITE_SIZE", "write", "probe"),
+                                     ("FETCH_SIZE", "copy_fetch", "copy"), ("WRITE_SIZE", "copy_write", "copy"))],
+    }
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps({"mode": "pmc-summary", **{k: out[k] for k in ("fetch_bytes", "write_bytes")}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,15 +205,25 @@ def main():
     ap.add_argument("--streams", type=int, default=16, help="HIP streams for the batch")
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="GPU_MAX_HW_QUEUES for this process (0: keep the environment's)")
+    ap.add_argument("--mode", default="bench", choices=["bench", "probe", "copy", "pmc-summary"])
+    ap.add_argument("--probe-steps", type=int, default=64)
+    ap.add_argument("--copy-mb", type=int, default=512)
+    ap.add_argument("--pmc-dir", default=os.path.join(ROOT, "gpurun_out", "traffic"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.mode == "pmc-summary":
+        return mode_pmc_summary(args)
     # one hardware queue per stream: with fewer queues than streams, independent
     # solves wait behind each other's latency-bound small-core kernels.  Must be
     # set before the HIP runtime initialises.
     if args.hw_queues > 0:
         os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, args.hw_queues))
+    if args.mode == "copy":
+        return mode_copy(args)
+    if args.mode == "probe":
+        return mode_probe(args)
 
     import numpy as np
     import torch
@@ -127,19 +271,6 @@ def main():
     single.set_timing(False)
     agg_ms, agg_n, agg_fl = st1["kernel_ms"], st1["kernel_launches"], st1["flops"]
 
-    # dominant kernel class by measured time
-    dom = max(agg_ms, key=lambda c: agg_ms[c])
-    prec_of = {"project": "fp32", "output": "fp32", "factor": "fp64", "tree": "fp64", "svd": "fp64", "prep": "fp64"}
-    bound_of = {"project": "mfma", "output": "mfma", "factor": "mfma", "tree": "hbm", "svd": "alu", "prep": "alu"}
-    roof = None
-    if agg_ms[dom] > 0 and agg_n[dom] > 0:
-        fl = agg_fl.get(dom, 0.0)
-        avg_ms = agg_ms[dom] / agg_n[dom]
-        achieved = (fl / agg_n[dom]) / (avg_ms * 1e-3) / 1e12 if fl > 0 else None
-        peak = PEAKS[prec_of.get(dom, "fp64")]
-        roof = {"bound": bound_of.get(dom, "alu"), "kernel_class": dom, "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": (achieved / peak) if achieved else None, "traffic": None,
-                "avg_launch_ms": avg_ms, "launches": agg_n[dom]}
     lat_ms = np.array(lat) * 1e3
     out = {
         "metric": METRIC,
@@ -155,7 +286,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "plane2d: 128x128 cells, 32 groups [0.01,10], 8x8 angles, lognormal kappa0 "
-                               "(sigma 1, l 0.1), FP32 contractions + FP64 factorisation/SVD, rank cap 32, tol 1e-6, "
+                               "(sigma 1, l 0.1), FP32 contractions + FP64 Gram/SVD, rank cap 32, tol 1e-6, "
                                "512 steps per solve",
                    "batch": B, "streams": len(streams), "seeds": f"0..{B - 1}",
                    "round_method": args.round_method, "timesteps_per_solve": K},
@@ -168,7 +299,8 @@ def main():
         "max_R": [last["max_R1"], last["max_R2"]],
         "compression": last["compression"],
         "kernel_ms_per_solve": {c: agg_ms[c] for c in tt.KERNEL_CLASSES if agg_n[c]},
-        "roofline": roof,
+        "kernel_us_per_launch": {c: agg_ms[c] / agg_n[c] * 1e3 for c in tt.KERNEL_CLASSES if agg_n[c]},
+        "roofline": roofline(st1),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)

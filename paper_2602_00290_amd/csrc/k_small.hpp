@@ -956,9 +956,11 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
         st->rounds += 1;
         const double M = (double)g.M, R1 = (double)st->R1, kk = (double)k1;
         if (Gfold) {
-            // fused path: projection + symmetric Gram in one kernel; the
-            // output contraction re-reads Z with K = R1
-            st->fl[0] += 2.0 * M * R1 * kk + M * kk * (kk + 1.0);
+            // fused path: projection (FP32, fl[0]) and symmetric Gram (FP64,
+            // fl[1]) run in one kernel; the output contraction re-reads Z
+            // with K = R1
+            st->fl[0] += 2.0 * M * R1 * kk;
+            st->fl[1] += M * kk * (kk + 1.0);
             st->fl[2] += 2.0 * M * R1 * (double)r1n;
         } else {
             st->fl[0] += 2.0 * M * R1 * kk;
