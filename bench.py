@@ -21,6 +21,7 @@ sample of the same workload.
 Other modes (for profiling runs; they print one line and exit):
   --mode probe        one solve of the workload for `--probe-steps` steps
   --mode copy         a plain device-to-device copy of `--copy-mb` MiB (counter calibration)
+  --mode served       only the served request mix (capacity, then Poisson arrivals)
   --mode pmc-summary  turn rocprofv3 counter CSVs (--pmc-dir) into profiles/traffic_plane2d.json
 """
 from __future__ import annotations
@@ -118,6 +119,30 @@ def roofline(st1):
     return out
 
 
+def served_phase(args):
+    """The served request mix: 50/50 1D (16 GL mu) / 2D (8 x 8), cells per
+    dimension U{64..256}, groups U{16..64}, rank caps U{4..48}, FP32/FP64 split,
+    64 steps each.  First all requests arrive at once (capacity = completed
+    requests/s); then Poisson arrivals at 0.8 x capacity give p50/p99 latency."""
+    import tt_inputs as ti
+    from paper_2602_00290_amd.serve import Server, make_requests
+
+    probs = ti.served_requests(args.served, seed=0, steps=64)
+    srv = Server(budget_bytes=int(args.served_budget_gb * (1 << 30)), max_active=args.served_slots,
+                 n_streams=min(16, args.served_slots), chunk=4)
+    cap = srv.run(make_requests(probs))
+    rate = 0.8 * cap["throughput_rps"]
+    arr = ti.poisson_arrivals(len(probs), rate, seed=0)
+    live = srv.run(make_requests(probs, arr))
+    keep = ("p50_ms", "p99_ms", "mean_ms", "throughput_rps", "makespan_s", "max_active", "peak_workspace_bytes")
+    return {"requests": len(probs), "steps_per_request": 64,
+            "mix": "1D (16 GL mu) / 2D (8x8) 50/50, cells/dim U{64..256}, groups U{16..64}, caps U{4..48}, "
+                   "FP32 (Gram) / FP64 (QR) 50/50, seed 0",
+            "budget_gb": args.served_budget_gb, "slots": args.served_slots,
+            "capacity_rps": cap["throughput_rps"], "capacity_run": {k: cap[k] for k in keep},
+            "arrival_rate_rps": rate, **{k: live[k] for k in keep}}
+
+
 def mode_copy(args):
     import torch
     n = args.copy_mb * (1 << 20) // 4
@@ -205,10 +230,14 @@ def main():
     ap.add_argument("--streams", type=int, default=16, help="HIP streams for the batch")
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="GPU_MAX_HW_QUEUES for this process (0: keep the environment's)")
-    ap.add_argument("--mode", default="bench", choices=["bench", "probe", "copy", "pmc-summary"])
+    ap.add_argument("--mode", default="bench", choices=["bench", "probe", "copy", "pmc-summary", "served"])
     ap.add_argument("--probe-steps", type=int, default=64)
     ap.add_argument("--copy-mb", type=int, default=512)
     ap.add_argument("--pmc-dir", default=os.path.join(ROOT, "gpurun_out", "traffic"))
+    ap.add_argument("--served", type=int, default=256,
+                    help="requests of the served mix (0: skip the serving phase)")
+    ap.add_argument("--served-budget-gb", type=float, default=64.0)
+    ap.add_argument("--served-slots", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -224,6 +253,9 @@ def main():
         return mode_copy(args)
     if args.mode == "probe":
         return mode_probe(args)
+    if args.mode == "served":
+        print(json.dumps({"mode": "served", **served_phase(args)}), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -302,6 +334,8 @@ def main():
         "kernel_us_per_launch": {c: agg_ms[c] / agg_n[c] * 1e3 for c in tt.KERNEL_CLASSES if agg_n[c]},
         "roofline": roofline(st1),
     }
+    if args.served > 0:
+        out["served"] = served_phase(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
