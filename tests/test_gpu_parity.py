@@ -271,3 +271,54 @@ def test_batch_results_equal_alone_and_in_the_mix(tt):
         for a, b in zip(got, ref):
             np.testing.assert_array_equal(a, b)
         assert (st["r1"], st["r2"]) == (ref[0].shape[1], ref[2].shape[0])
+
+
+def _small3d(n_theta, n_phi, prec, bc, tol=1e-6, cap=32, seed=0, T=0.1):
+    p = ti.clumps3d(n=5, n_groups=3, n_theta=n_theta, n_phi=n_phi, tol=tol, rank_cap=cap, precision=prec,
+                    seed=seed, T=T)
+    p.n_cells = (5, 4, 3)
+    p.kappa0 = ti.lognormal_kappa0(p.n_cells, p.extent, 3, seed=seed)
+    p.T_cell = np.full(60, T)
+    p.bc = bc
+    p.bc_T = tuple(1.0 if b == ti.BC_INFLOW_PLANCK else 0.0 for b in bc)
+    return p
+
+
+@pytest.mark.parametrize("prec", [ti.PREC_FP64, ti.PREC_FP32])
+def test_one_step_k1_128(tt, prec):
+    # 8 x 16 directions: the projected first core has k1 = 128 columns (the 3D
+    # configuration's angular size); FP64 uses Householder TSQR, FP32 the Gram path
+    p = _small3d(8, 16, prec, bc=(1, 0, 0, 0, 0, 0), tol=1e-7, cap=40)
+    s = tt.Solver(p)
+    Z, Th, Ph = ti.random_tt(p.M, p.n_theta, p.n_phi, 20, 8, seed=7, decay=0.7)
+    s.set_cores(Z, Th, Ph)
+    s.solve(1)
+    Zo, To, Po, info = ott.step(p, Z, Th, Ph)
+    assert info["R1"] >= 128
+    r1, r2 = s.get_ranks()
+    if prec == ti.PREC_FP64:
+        assert (r1, r2) == (info["r1"], info["r2"])
+        assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 1e-12
+    else:
+        assert abs(r1 - info["r1"]) <= 1 and abs(r2 - info["r2"]) <= 1
+        assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 2e-6 + 2 * p.tol * (r1 != info["r1"] or r2 != info["r2"])
+
+
+@pytest.mark.parametrize("bc", [(1, 1, 2, 2, 1, 0), (1, 1, 1, 1, 1, 1), (2, 2, 2, 2, 2, 2)])
+def test_fused_fp32_3d_boundaries(tt, bc):
+    # fused FP32 kernels in 3D (7 gather blocks, 4 x 16 directions so k1 = 64):
+    # periodic wrap offsets, up to six inflow faces (rank-1 block of width 8)
+    p = _small3d(4, 16, ti.PREC_FP32, bc=bc, tol=1e-6, cap=32)
+    s = tt.Solver(p)
+    Z, Th, Ph = ti.random_tt(p.M, p.n_theta, p.n_phi, 24, 8, seed=11, decay=0.75)
+    s.set_cores(Z, Th, Ph)
+    s.solve(1)
+    Zo, To, Po, info = ott.step(p, Z, Th, Ph)
+    r1, r2 = s.get_ranks()
+    assert abs(r1 - info["r1"]) <= 1 and abs(r2 - info["r2"]) <= 1
+    assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 2e-6 + 2 * p.tol * (r1 != info["r1"] or r2 != info["r2"])
+    # a few more steps stay with the oracle
+    s.solve(3)
+    for _ in range(3):
+        Zo, To, Po, _ = ott.step(p, Zo, To, Po)
+    assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 1e-5
