@@ -631,20 +631,30 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
     } else {
         gram = 1;
         e = h->ev_begin(KC_FACTOR, s);
-        if (f32 && P.KP == 64)
-            hipLaunchKernelGGL(k_gram_f64_mfma, dim3(P.Pg), dim3(256), 0, s, (const float*)B, (const DevState*)st, P.M,
-                               P.rowsg, RA);
-        else if (P.KP == 64)
-            hipLaunchKernelGGL((k_gram<T, 64>), dim3(P.Pg), dim3(256), 0, s, (const T*)B, (const DevState*)st, P.M,
-                               P.rowsg, RA);
-        else
-            hipLaunchKernelGGL((k_gram<T, 128>), dim3(P.Pg), dim3(256), 0, s, (const T*)B, (const DevState*)st, P.M,
-                               P.rowsg, RA);
-        h->ev_end(e, s);
-        e = h->ev_begin(KC_TREE, s);
-        const int n = P.KP * P.KP;
-        hipLaunchKernelGGL(k_sum_parts, dim3((n + 31) / 32), dim3(256), 0, s, (const double*)RA, P.Pg, n, RBuf);
-        h->ev_end(e, s);
+        if (f32 && P.KP == 128) {
+            hipLaunchKernelGGL(k_gram_f64_mfma_w8, dim3(P.Pg), dim3(256), 0, s, (const float*)B, (const DevState*)st,
+                               P.M, P.rowsg, RA);
+            h->ev_end(e, s);
+            e = h->ev_begin(KC_TREE, s);
+            hipLaunchKernelGGL(k_sum_gram<8>, dim3((gram_blocks(8) * 256 + 31) / 32), dim3(256), 0, s,
+                               (const double*)RA, P.Pg, RBuf, P.KP);
+            h->ev_end(e, s);
+        } else {
+            if (f32 && P.KP == 64)
+                hipLaunchKernelGGL(k_gram_f64_mfma, dim3(P.Pg), dim3(256), 0, s, (const float*)B, (const DevState*)st,
+                                   P.M, P.rowsg, RA);
+            else if (P.KP == 64)
+                hipLaunchKernelGGL((k_gram<T, 64>), dim3(P.Pg), dim3(256), 0, s, (const T*)B, (const DevState*)st, P.M,
+                                   P.rowsg, RA);
+            else
+                hipLaunchKernelGGL((k_gram<T, 128>), dim3(P.Pg), dim3(256), 0, s, (const T*)B, (const DevState*)st, P.M,
+                                   P.rowsg, RA);
+            h->ev_end(e, s);
+            e = h->ev_begin(KC_TREE, s);
+            const int n = P.KP * P.KP;
+            hipLaunchKernelGGL(k_sum_parts, dim3((n + 31) / 32), dim3(256), 0, s, (const double*)RA, P.Pg, n, RBuf);
+            h->ev_end(e, s);
+        }
         RB = RBuf;
     }
 
