@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/tt_transport.h"
+#include "k_bf16x.hpp"
 #include "k_big.hpp"
 #include "k_fused.hpp"
 #include "k_mfma.hpp"
@@ -78,6 +79,10 @@ struct Plan {
     size_t B_bytes = 0;
     // workspace layout (byte offsets)
     size_t o_Gsw = 0, o_Gfold = 0, o_GP = 0, o_aux = 0, o_R1 = 0, o_R2 = 0, o_zero = 0;
+    // split-BF16 operands (precision TT_PREC_BF16X): chunked, column-major hi / lo
+    bool bf16x = false;
+    int nct_b = 4, nct_bo = 2, kc_g = 1, kc_v = 1;
+    size_t o_Gh = 0, o_Gl = 0, o_Vh = 0, o_Vl = 0;
     int rw1 = 0, rw2 = 0;           // widths of the rank-1 row blocks (transport / source operators)
     bool fused_overflow = false;
     size_t o_state, o_Z0, o_Z1, o_B, o_Th0, o_Th1, o_Ph0, o_Ph1, o_LTh, o_QTh, o_QPh, o_G, o_V, o_RA, o_RB, o_small,
@@ -122,7 +127,6 @@ tt_status validate(const tt_problem* p) {
     if (!(p->tol >= 0.0)) return fail(TT_ERR_INVALID_ARG, "tol must be >= 0");
     if (p->rank_cap < 1) return fail(TT_ERR_INVALID_ARG, "rank_cap must be >= 1");
     if (p->precision < 0 || p->precision > 2) return fail(TT_ERR_INVALID_ARG, "unknown precision");
-    if (p->precision == TT_PREC_BF16X) return fail(TT_ERR_INVALID_ARG, "TT_PREC_BF16X is not available in this build");
     if (p->round_method < 0 || p->round_method > 2) return fail(TT_ERR_INVALID_ARG, "unknown round_method");
     if (p->paper_step_order < 0 || p->paper_step_order > 1) return fail(TT_ERR_INVALID_ARG, "paper_step_order must be 0 or 1");
     return TT_OK;
@@ -222,6 +226,18 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
     if (P.fused)   // B is not stored; keep a staging buffer for explicit TT-sum reads
         P.B_bytes = std::min<size_t>(P.B_bytes, std::max<size_t>((size_t)16 << 20, (size_t)P.R1cap * sizeof(double)));
     P.o_B = take(P.B_bytes);
+    P.bf16x = p->precision == TT_PREC_BF16X;
+    if (P.bf16x) {
+        P.nct_b = P.ldbcap <= 64 ? 4 : 8;
+        P.nct_bo = P.ldzcap <= 32 ? 2 : 4;
+        P.kc_g = (P.n_gather_max * P.ldzcap + P.n_r1_max + kBxKC - 1) / kBxKC;
+        P.kc_v = (P.ldbcap + kBxKC - 1) / kBxKC;
+        const size_t gb = (size_t)P.kc_g * 16 * P.nct_b * kBxKC * 2, vb = (size_t)P.kc_v * 16 * P.nct_bo * kBxKC * 2;
+        P.o_Gh = take(gb);
+        P.o_Gl = take(gb);
+        P.o_Vh = take(vb);
+        P.o_Vl = take(vb);
+    }
     if (P.fused) {
         P.o_Gsw = take((size_t)P.fused_T * P.nct_p * 256 * sizeof(float));
         P.o_Gfold = take((size_t)P.fused_T * P.nct_o * 256 * sizeof(float));
@@ -589,11 +605,26 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
     const unsigned gx = (unsigned)((P.M + 63) / 64);
     const unsigned gx128 = (unsigned)((P.M + 127) / 128);
     e = h->ev_begin(KC_PROJECT, s);
-    if constexpr (f32)
-        hipLaunchKernelGGL((k_gemm_f32_mfma<MODE_PROJECT, 64>), dim3(gx128, (P.ldbcap + 63) / 64), dim3(256), 0, s,
-                           h->geom, op, (const DevState*)st, (const float*)h->Zc(), (const float*)Gop, (float*)B,
-                           h->rowdata());
-    else
+    if constexpr (f32) {
+        if (P.bf16x) {
+            __bf16* gh = h->at<__bf16>(P.o_Gh);
+            __bf16* gl = h->at<__bf16>(P.o_Gl);
+            hipLaunchKernelGGL(k_split_bf16, dim3(64), dim3(256), 0, s, (const DevState*)st, 0, (const float*)Gop,
+                               16 * P.nct_b, P.kc_g, gh, gl);
+            if (P.nct_b == 8)
+                hipLaunchKernelGGL((k_gemm_bf16x<MODE_PROJECT, 8>), dim3(gx128), dim3(256), 0, s, h->geom, op,
+                                   (const DevState*)st, (const float*)h->Zc(), (const __bf16*)gh, (const __bf16*)gl,
+                                   (float*)B, h->rowdata());
+            else
+                hipLaunchKernelGGL((k_gemm_bf16x<MODE_PROJECT, 4>), dim3(gx128), dim3(256), 0, s, h->geom, op,
+                                   (const DevState*)st, (const float*)h->Zc(), (const __bf16*)gh, (const __bf16*)gl,
+                                   (float*)B, h->rowdata());
+        } else {
+            hipLaunchKernelGGL((k_gemm_f32_mfma<MODE_PROJECT, 64>), dim3(gx128, (P.ldbcap + 63) / 64), dim3(256), 0, s,
+                               h->geom, op, (const DevState*)st, (const float*)h->Zc(), (const float*)Gop, (float*)B,
+                               h->rowdata());
+        }
+    } else
         hipLaunchKernelGGL((k_gather_gemm<T, MODE_PROJECT>), dim3(gx, (P.ldbcap + 63) / 64), dim3(256), 0, s, h->geom,
                            op, st, (const T*)h->Zc(), (const T*)Gop, B, h->rowdata());
     h->ev_end(e, s);
@@ -673,7 +704,20 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
 
     e = h->ev_begin(KC_OUTPUT, s);
     if constexpr (f32) {
-        if (P.ldzcap <= 32)
+        if (P.bf16x) {
+            __bf16* vh = h->at<__bf16>(P.o_Vh);
+            __bf16* vl = h->at<__bf16>(P.o_Vl);
+            hipLaunchKernelGGL(k_split_bf16, dim3(16), dim3(256), 0, s, (const DevState*)st, 1, (const float*)V,
+                               16 * P.nct_bo, P.kc_v, vh, vl);
+            if (P.nct_bo == 4)
+                hipLaunchKernelGGL((k_gemm_bf16x<MODE_OUTPUT, 4>), dim3(gx128), dim3(256), 0, s, h->geom, op,
+                                   (const DevState*)st, (const float*)B, (const __bf16*)vh, (const __bf16*)vl,
+                                   (float*)h->Zn(), h->rowdata());
+            else
+                hipLaunchKernelGGL((k_gemm_bf16x<MODE_OUTPUT, 2>), dim3(gx128), dim3(256), 0, s, h->geom, op,
+                                   (const DevState*)st, (const float*)B, (const __bf16*)vh, (const __bf16*)vl,
+                                   (float*)h->Zn(), h->rowdata());
+        } else if (P.ldzcap <= 32)
             hipLaunchKernelGGL((k_gemm_f32_mfma<MODE_OUTPUT, 32>), dim3(gx128, 1), dim3(256), 0, s, h->geom, op,
                                (const DevState*)st, (const float*)B, (const float*)V, (float*)h->Zn(), h->rowdata());
         else

@@ -322,3 +322,34 @@ def test_fused_fp32_3d_boundaries(tt, bc):
     for _ in range(3):
         Zo, To, Po, _ = ott.step(p, Zo, To, Po)
     assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 1e-5
+
+
+@pytest.mark.parametrize("case", ["2d", "3d_k1_128"])
+def test_one_step_bf16x(tt, case):
+    # split-BF16 contractions (FP32 state, FP64 Gram rounding): one step agrees
+    # with the FP64 oracle to the split's ~2^-16 relative error
+    if case == "2d":
+        p = _small(2, prec=ti.PREC_BF16X, tol=1e-5, cap=16)
+        Z, Th, Ph = _random_state(p, 6, 4, seed=21)
+    else:
+        p = _small3d(8, 16, ti.PREC_BF16X, bc=(1, 0, 0, 0, 0, 0), tol=1e-5, cap=40)
+        Z, Th, Ph = ti.random_tt(p.M, p.n_theta, p.n_phi, 20, 8, seed=7, decay=0.7)
+    s = tt.Solver(p)
+    s.set_cores(Z, Th, Ph)
+    s.solve(1)
+    Zo, To, Po, info = ott.step(p, Z, Th, Ph)
+    r1, r2 = s.get_ranks()
+    assert abs(r1 - info["r1"]) <= 1 and abs(r2 - info["r2"]) <= 1
+    assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 5e-5 + 2 * p.tol * (r1 != info["r1"] or r2 != info["r2"])
+
+
+def test_bf16x_3d_solve_within_1e4_of_fp64(tt):
+    # the 3D configuration's accuracy bar (rel-L2 <= 1e-4 against FP64) on a
+    # reduced grid of the same generator: 6^3 cells, 6 groups, 8 x 16 directions
+    p = ti.clumps3d(n=6, n_groups=6, n_theta=8, n_phi=16, tol=1e-5, rank_cap=32, precision=ti.PREC_BF16X,
+                    n_steps=24)
+    s = tt.Solver(p)
+    st = s.solve(p.n_steps)
+    assert st["nan_flag"] == 0
+    (Zo, To, Po), _ = ott.solve(p.copy(precision=ti.PREC_FP64), p.n_steps)
+    assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 1e-4
