@@ -90,10 +90,13 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x(Geom g, OpDesc op, const Dev
         for (int c = 0; c < NCT; ++c) acc[rt][c] = (f32x4b){0.f, 0.f, 0.f, 0.f};
     const int n_kc = (K + kBxKC - 1) / kBxKC;
     const int q = l >> 4, m = l & 15;
-    __syncthreads();
-    for (int kc = 0; kc < n_kc; ++kc) {
+    static_assert(NP * 4 <= 512, "at most two 16-byte operand slots per thread");
+    constexpr bool G2 = NP * 4 > 256;   // second 16-byte operand slot per thread (hi and lo each)
+    // registers holding the next chunk while the current one computes
+    float4 ra[4];
+    uint4 gh0 = make_uint4(0, 0, 0, 0), gl0 = gh0, gh1 = gh0, gl1 = gh0;
+    auto fetch = [&](int kc) __attribute__((always_inline)) {
         const int k0 = kc * kBxKC;
-        // A chunk: 128 rows x 32, four 4-float slots per thread (kper is a multiple of 8)
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
             const int slot = tid + 256 * it;
@@ -107,26 +110,52 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x(Geom g, OpDesc op, const Dev
                 if (src >= 0) v = *reinterpret_cast<const float4*>(A + src * (long long)lda + cc);
             } else if (MODE == MODE_PROJECT && k < K && rowk < g.M) {
                 float t[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int qq = k - KG + e;
                     if (qq < op.n_r1) t[e] = (float)rank1_value(g, op, rd, rowk, qq);
                 }
                 v = make_float4(t[0], t[1], t[2], t[3]);
             }
+            ra[it] = v;
+        }
+        const uint4* sh = reinterpret_cast<const uint4*>(Ghi + (size_t)kc * NP * kBxKC);
+        const uint4* sl = reinterpret_cast<const uint4*>(Glo + (size_t)kc * NP * kBxKC);
+        if (tid < NP * 4) {
+            gh0 = sh[tid];
+            gl0 = sl[tid];
+        }
+        if constexpr (G2) {
+            gh1 = sh[tid + 256];
+            gl1 = sl[tid + 256];
+        }
+    };
+    __syncthreads();
+    if (n_kc > 0) fetch(0);
+    for (int kc = 0; kc < n_kc; ++kc) {
+        __syncthreads();   // the previous chunk's readers are done
+        // A chunk (scaled by d) and operand chunk (hi, lo; column-major) into LDS
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int slot = tid + 256 * it;
+            const int r = slot >> 3, c4 = (slot & 7) * 4;
             const float d = rowd[r];
+            const float4 v = ra[it];
             *reinterpret_cast<float4*>(As + r * LDA + c4) = make_float4(v.x * d, v.y * d, v.z * d, v.w * d);
         }
-        // operand chunk: NP columns x 32 (hi and lo), 16-byte copies
-        {
-            const uint4* sh = reinterpret_cast<const uint4*>(Ghi + (size_t)kc * NP * kBxKC);
-            const uint4* sl = reinterpret_cast<const uint4*>(Glo + (size_t)kc * NP * kBxKC);
-            for (int idx = tid; idx < NP * 4; idx += 256) {
-                const int n = idx >> 2, part = idx & 3;
-                *reinterpret_cast<uint4*>(Bh + n * LDG + part * 8) = sh[idx];
-                *reinterpret_cast<uint4*>(Bl + n * LDG + part * 8) = sl[idx];
-            }
+        if (tid < NP * 4) {
+            const int n = tid >> 2, part = tid & 3;
+            *reinterpret_cast<uint4*>(Bh + n * LDG + part * 8) = gh0;
+            *reinterpret_cast<uint4*>(Bl + n * LDG + part * 8) = gl0;
+        }
+        if constexpr (G2) {
+            const int idx = tid + 256;
+            const int n = idx >> 2, part = idx & 3;
+            *reinterpret_cast<uint4*>(Bh + n * LDG + part * 8) = gh1;
+            *reinterpret_cast<uint4*>(Bl + n * LDG + part * 8) = gl1;
         }
         __syncthreads();
+        if (kc + 1 < n_kc) fetch(kc + 1);   // in flight while this chunk computes
         // A operand of both row tiles, split into hi / lo
         bf16x8 ah[2], al[2];
 #pragma unroll
@@ -153,7 +182,6 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x(Geom g, OpDesc op, const Dev
                 acc[rt][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[rt], bh, acc[rt][c], 0, 0, 0);
             }
         }
-        __syncthreads();
     }
     // D[i][j] of row tile rt: row 32 w + 16 rt + 4 q + r, column 16 c + m
 #pragma unroll
