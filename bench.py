@@ -97,6 +97,21 @@ def stored_traffic():
     return t
 
 
+def tt_rel_diff(x, y):
+    """||X - Y|| / ||X|| of two TTs (Z, Theta, Phi) from TT inner products (no
+    full tensor): <X, Y> = sum Phi_x Phi_y^T o (Theta_x^T (Z_x^T Z_y) Theta_y)."""
+    import numpy as np
+
+    def inner(a, b):
+        Za, Ta, Pa = a
+        Zb, Tb, Pb = b
+        A = Za.T @ Zb                                        # r1a x r1b
+        Bm = np.einsum("ij,ilp,jlq->pq", A, Ta, Tb)          # r2a x r2b
+        return float(np.sum(Bm * (Pa @ Pb.T)))
+    xx, yy, xy = inner(x, x), inner(y, y), inner(x, y)
+    return float(np.sqrt(max(xx + yy - 2.0 * xy, 0.0) / xx))
+
+
 def roofline(st1):
     """Roofline of the fused projection + FP64 Gram kernel from the single-solve
     event timing.  Its flops are FP32 MFMA (projection, 2 M R1 k1 per launch)
@@ -234,6 +249,7 @@ def main():
     ap.add_argument("--probe-steps", type=int, default=64)
     ap.add_argument("--copy-mb", type=int, default=512)
     ap.add_argument("--pmc-dir", default=os.path.join(ROOT, "gpurun_out", "traffic"))
+    ap.add_argument("--plain-fp64", type=int, default=1, help="also time the plain FP64 TT path on seed 0")
     ap.add_argument("--served", type=int, default=256,
                     help="requests of the served mix (0: skip the serving phase)")
     ap.add_argument("--served-budget-gb", type=float, default=64.0)
@@ -303,6 +319,19 @@ def main():
     single.set_timing(False)
     agg_ms, agg_n, agg_fl = st1["kernel_ms"], st1["kernel_launches"], st1["flops"]
 
+    # ---- phase 3: the plain FP64 TT path (FP64 state, Householder TSQR) on seed 0 ----
+    plain = None
+    if args.plain_fp64:
+        sp = tt.Solver(prob.copy(precision=ti.PREC_FP64), device=dev, round_method=tt.TT_ROUND_QR)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        stp = sp.solve(K)
+        plain_s = time.perf_counter() - t2
+        a, b = single.get_cores(), sp.get_cores()
+        plain = {"solves_per_s": 1.0 / plain_s, "ms": plain_s * 1e3, "ranks": [stp["r1"], stp["r2"]],
+                 "rel_l2_mixed_vs_fp64": tt_rel_diff(a, b),
+                 "speedup_batched_mixed_vs_plain_fp64": value * plain_s}
+        sp.destroy()
     lat_ms = np.array(lat) * 1e3
     out = {
         "metric": METRIC,
@@ -334,6 +363,8 @@ def main():
         "kernel_us_per_launch": {c: agg_ms[c] / agg_n[c] * 1e3 for c in tt.KERNEL_CLASSES if agg_n[c]},
         "roofline": roofline(st1),
     }
+    if plain:
+        out["plain_fp64"] = plain
     if args.served > 0:
         out["served"] = served_phase(args)
     if not args.no_cpu_baseline:

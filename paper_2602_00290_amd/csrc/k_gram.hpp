@@ -1,0 +1,97 @@
+// FP64 Gram matrix of a stored FP32 first core with 128 columns (k1 up to
+// 128) on FP64 MFMA, for the unfused Gram rounding of wide first cores.
+#pragma once
+
+#include "k_fused.hpp"
+
+namespace ttrt {
+
+// FP64 Gram matrix of a stored FP32 first core with 128 columns on FP64 MFMA
+// (the unfused Gram path for wide cores, k1 up to 128).  A block walks its
+// rows in chunks of 64: each chunk is loaded with coalesced 16-byte loads (the
+// next chunk's loads are in flight while the current one computes) and staged
+// in LDS.  Wave w of the 4 owns the upper 16 x 16 blocks of block rows w and
+// 7 - w (9 blocks each, balanced); its A operands are read from LDS at a
+// wave-uniform column, the B operands of all 8 column groups with
+// compile-time indices, and blocks left of the diagonal are skipped by a
+// scalar branch.  Each block writes its compact partial (36 blocks x 4
+// registers x 64 lanes) for k_sum_gram<8>.
+__global__ __launch_bounds__(256) void k_gram_f64_mfma_w8(const float* __restrict__ B, const DevState* __restrict__ st,
+                                                           long long nrows, long long rows_per_block,
+                                                           double* __restrict__ Gpart) {
+    constexpr int NCT = 8;
+    constexpr int NB = gram_blocks(NCT);
+    constexpr int NC = 16 * NCT;              // columns
+    constexpr int CH = 64;                    // rows per chunk
+    constexpr int LDC = NC + 4;               // LDS row stride (floats)
+    constexpr int V4 = CH * NC / 4 / 256;     // float4 loads per thread per chunk
+    __shared__ float Bs[CH * LDC];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int ldb = st->ldb;
+    const long long begin = (long long)blockIdx.x * rows_per_block;
+    long long end = begin + rows_per_block;
+    if (end > nrows) end = nrows;
+    const int gaA = w, gaB = NCT - 1 - w;     // this wave's two block rows
+    f64x4 accA[NCT], accB[NCT];
+#pragma unroll
+    for (int g = 0; g < NCT; ++g) {
+        accA[g] = (f64x4){0.0, 0.0, 0.0, 0.0};
+        accB[g] = accA[g];
+    }
+    float4 nx[V4];
+    auto load = [&](long long r0) {
+#pragma unroll
+        for (int v = 0; v < V4; ++v) {
+            const int slot = tid + 256 * v;
+            const int r = slot / (NC / 4), c4 = (slot % (NC / 4)) * 4;
+            const long long row = r0 + r;
+            float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+            // columns from k1 up to ldb are zero in B; beyond ldb they are not read
+            if (row < end && c4 < ldb) x = *reinterpret_cast<const float4*>(B + row * ldb + c4);
+            nx[v] = x;
+        }
+    };
+    const int col = l & 15, kr = l >> 4;
+    if (begin < end) load(begin);
+    for (long long r0 = begin; r0 < end; r0 += CH) {
+        __syncthreads();   // the previous chunk's readers are done
+#pragma unroll
+        for (int v = 0; v < V4; ++v) {
+            const int slot = tid + 256 * v;
+            const int r = slot / (NC / 4), c4 = (slot % (NC / 4)) * 4;
+            *reinterpret_cast<float4*>(Bs + r * LDC + c4) = nx[v];
+        }
+        __syncthreads();
+        if (r0 + CH < end) load(r0 + CH);
+#pragma unroll 2
+        for (int k = 0; k < CH; k += 4) {
+            const float* rp = Bs + (k + kr) * LDC + col;
+            const double a = (double)rp[16 * gaA], b2 = (double)rp[16 * gaB];
+            double v[NCT];
+#pragma unroll
+            for (int g = 0; g < NCT; ++g) v[g] = (double)rp[16 * g];
+#pragma unroll
+            for (int g = 0; g < NCT; ++g) {
+                if (g >= gaA) accA[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, v[g], accA[g], 0, 0, 0);
+                if (g >= gaB) accB[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(b2, v[g], accB[g], 0, 0, 0);
+            }
+        }
+    }
+    // block index of (ga, gb) in the upper enumeration: ga NCT - ga (ga - 1) / 2 + (gb - ga)
+    double* outp = Gpart + (size_t)blockIdx.x * NB * 256;
+#pragma unroll
+    for (int g = 0; g < NCT; ++g) {
+        if (g >= gaA) {
+            const int bi = gaA * NCT - gaA * (gaA - 1) / 2 + (g - gaA);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) outp[(bi * 4 + r) * 64 + l] = accA[g][r];
+        }
+        if (g >= gaB) {
+            const int bi = gaB * NCT - gaB * (gaB - 1) / 2 + (g - gaB);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) outp[(bi * 4 + r) * 64 + l] = accB[g][r];
+        }
+    }
+}
+
+}  // namespace ttrt

@@ -25,6 +25,7 @@
 #include "k_bf16x.hpp"
 #include "k_big.hpp"
 #include "k_fused.hpp"
+#include "k_gram.hpp"
 #include "k_mfma.hpp"
 #include "k_small.hpp"
 #include "tt_common.hpp"
