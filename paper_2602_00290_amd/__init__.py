@@ -91,6 +91,12 @@ class TTError(RuntimeError):
 
 
 def _load():
+    # PyTorch's HIP runtime must be the one in the process before the library
+    # is loaded: both carry the soname libamdhip64.so.7, so whichever is loaded
+    # first is used by both, and the library's first HIP call fails if torch
+    # later finds a runtime other than its own.
+    import torch  # noqa: F401
+
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "

@@ -8,6 +8,9 @@
 namespace ttrt {
 
 constexpr int kSmallThreads = 1024;
+// Sweep stop of the Gram-path eigensolver (largest rotation tangent of the
+// last sweep): the next sweep would rotate by ~1e-10, far below the FP32 data.
+constexpr double kGramSweepTol = 1e-5;
 constexpr int kSmallLdsBytes = 150 * 1024;
 
 // Operator description shared by the prep, projection and materialise kernels.
@@ -399,7 +402,11 @@ __device__ __forceinline__ int block_jacobi_1s_fixed(double* A, int lda, int n, 
 // matrix known to ~u tr(S) absolute, so off-diagonals below 1e-15 tr(S) are
 // noise and are not rotated (rotations inside the negligible block would
 // neither converge nor change its trace, i.e. the truncated tail norm).
-__device__ __forceinline__ int block_jacobi_sym(double* S, int n, int ld, double* W, double* cs, int* pa_, int* pb_, int* flag) {
+// Two-sided Jacobi on a symmetric matrix (the Gram path).  Sweeps stop after
+// one whose largest rotation tangent is at most tconv: the method converges
+// quadratically, so the next sweep would rotate by about tconv^2.
+__device__ __forceinline__ int block_jacobi_sym(double* S, int n, int ld, double* W, double* cs, int* pa_, int* pb_, int* flag,
+                                                double tconv) {
     if (n < 2) {
         __syncthreads();
         return 0;
@@ -422,7 +429,7 @@ __device__ __forceinline__ int block_jacobi_sym(double* S, int n, int ld, double
                     if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs) {
                         double t;
                         jacobi_rotation(app, aqq, apq, &c, &s, &t);
-                        if (fabs(t) > 1e-8) *flag = 1;
+                        if (fabs(t) > tconv) *flag = 1;
                     }
                 }
                 cs[2 * pp] = c;
@@ -468,7 +475,7 @@ __device__ __forceinline__ int block_jacobi_sym(double* S, int n, int ld, double
 // W <- W R is updated per (row, pair).  Same rotation and stopping rules as
 // block_jacobi_sym.
 __device__ __forceinline__ int block_jacobi_sym64(double* S, int ld, double* W, double* cs, int* pa_, int* pb_,
-                                                  int* flag) {
+                                                  int* flag, double tconv) {
     const int np = 64, npairs = 32;
     double tr = 0.0;
     for (int i = 0; i < 64; ++i) tr += fabs(S[i + (size_t)i * ld]);
@@ -486,7 +493,7 @@ __device__ __forceinline__ int block_jacobi_sym64(double* S, int ld, double* W, 
                 if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs) {
                     double t;
                     jacobi_rotation(app, aqq, apq, &c, &sn, &t);
-                    if (fabs(t) > 1e-8) *flag = 1;
+                    if (fabs(t) > tconv) *flag = 1;
                 }
                 cs[2 * threadIdx.x] = c;
                 cs[2 * threadIdx.x + 1] = sn;
@@ -510,7 +517,8 @@ __device__ __forceinline__ int block_jacobi_sym64(double* S, int ld, double* W, 
                 double* w1a = W + i1 + (size_t)aq * ld;
                 double* w1b = W + i1 + (size_t)bq * ld;
                 const double u0 = *w0a, v0 = *w0b, u1 = *w1a, v1 = *w1b;
-                __syncthreads();
+                // every thread reads and writes only its own 2 x 2 block of S and its
+                // own W entries (rows p, p + 32 of columns aq, bq): no barrier here
                 *s00 = cp * c00 - sp * c10;
                 *s01 = cp * c01 - sp * c11;
                 *s10 = sp * c00 + cp * c10;
@@ -527,6 +535,37 @@ __device__ __forceinline__ int block_jacobi_sym64(double* S, int ld, double* W, 
         if (!f) return sweep + 1;
     }
     return 40;
+}
+
+// C = A B for 64 x 64 operands in LDS, elements addressed as A(i, k) =
+// A[i * ai + k * ak], B(k, j) = B[k * bk + j * bj], C(i, j) = C[i + j * ldc];
+// threads 0..255 each form a 4 x 4 tile (8 LDS reads per 16 FMAs).  The caller
+// synchronises before and after.
+__device__ __forceinline__ void block_mm64(const double* A, int ai, int ak, const double* B, int bk, int bj, double* C,
+                                           int ldc) {
+    if (threadIdx.x >= 256) return;
+    const int i0 = 4 * (threadIdx.x & 15), j0 = 4 * (threadIdx.x >> 4);
+    double acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < 64; ++k) {
+        double a[4], bv[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) a[x] = A[(i0 + x) * ai + k * ak];
+#pragma unroll
+        for (int y = 0; y < 4; ++y) bv[y] = B[k * bk + (j0 + y) * bj];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * bv[y];
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) C[(i0 + x) + (size_t)(j0 + y) * ldc] = acc[x][y];
 }
 
 // Descending order of s[0..n) into perm (ties by index).
@@ -748,6 +787,10 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
                                                              double* __restrict__ PhOut, TC* __restrict__ Vout,
                                                              double* __restrict__ sv_out, const TC* __restrict__ Gop,
                                                              TC* __restrict__ Gfold, int nct_o) {
+    // Gop, Gfold, nct_o: non-null Gfold marks a fused pass (its operand G V_r is
+    // formed afterwards by k_fold); they only change the flop accounting here
+    (void)Gop;
+    (void)nct_o;
     extern __shared__ double lds[];
     __shared__ double red[16];
     __shared__ int sh_r[2];
@@ -808,7 +851,13 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
             s1[j] = sqrt(acc);
         }
     } else {
-        if (warm) {
+        if (warm && FAST) {
+            // J = W^T G W on 64 x 64 tiles in LDS (zero / identity padded beyond k1)
+            block_mm64(T, 1, ld, W, 1, ld, J, ld);       // J = G W
+            __syncthreads();
+            block_mm64(W, ld, 1, J, 1, ld, T, ld);       // T = W^T J
+            __syncthreads();
+        } else if (warm) {
             // J = W^T G W: J <- G W, then T <- W^T J
             for (int idx = threadIdx.x; idx < kp * kp; idx += blockDim.x) {
                 const int i = idx % kp, j = idx / kp;
@@ -832,9 +881,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
         __syncthreads();
         tph[1] = wall_clock64();
         if (FAST)
-            sw1 = block_jacobi_sym64(J, ld, W, cs, pa_, pb_, &sh_flag);
+            sw1 = block_jacobi_sym64(J, ld, W, cs, pa_, pb_, &sh_flag, kGramSweepTol);
         else
-            sw1 = block_jacobi_sym(J, k1, ld, W, cs, pa_, pb_, &sh_flag);
+            sw1 = block_jacobi_sym(J, k1, ld, W, cs, pa_, pb_, &sh_flag, kGramSweepTol);
         tph[2] = wall_clock64();
         for (int j = threadIdx.x; j < k1; j += blockDim.x) s1[j] = sqrt(fmax(J[j + (size_t)j * ld], 0.0));
     }
@@ -860,25 +909,6 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
         double v = 0.0;
         if (i < k1 && a < r1n) v = W[i + (size_t)p1[a] * ld];
         Vout[(size_t)i * ldzn + a] = (TC)v;
-    }
-    if (Gfold) {
-        // operand of the fused output contraction, G' = G V_r, in the lane
-        // order of the fused MFMA kernel (see k_prep)
-        const int kall = st->kall;
-        const int ng = (kall + 15) / 16;
-        for (int idx = threadIdx.x; idx < ng * nct_o * 256; idx += blockDim.x) {
-            const int e = idx & 3, ln = (idx >> 2) & 63, tc = idx >> 8;
-            const int c = tc % nct_o, t = tc / nct_o;
-            const int row = 16 * t + 4 * (ln >> 4) + e, a = 16 * c + (ln & 15);
-            double v = 0.0;
-            if (row < kall && a < r1n) {
-                const TC* gr = Gop + (size_t)row * ldb;
-                const double* wc = W + (size_t)p1[a] * ld;
-#pragma unroll 8
-                for (int i = 0; i < k1; ++i) v += (double)gr[i] * wc[i];
-            }
-            Gfold[idx] = (TC)v;
-        }
     }
     // Theta'' = V_r^T Q_Theta (r1n x m2) and C2 = diag(S_r) Theta'' as ((r1n N_theta) x k2)
     const int mC = r1n * nt;
@@ -967,6 +997,30 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
             st->fl[1] += gram ? M * kk * (kk + 1.0) : 2.0 * M * kk * kk - 2.0 / 3.0 * kk * kk * kk;
             st->fl[2] += 2.0 * M * kk * (double)r1n;
         }
+    }
+}
+
+// Operand of the fused output contraction, G' = G V_r (FP64 sums of the FP32
+// gather operand with the FP64 right singular vectors kept by the SVD chain),
+// in the lane order of the fused MFMA kernel: slot ((t * nct + c) * 64 + lane)
+// * 4 + e holds G'[16 t + 4 (lane / 16) + e][16 c + lane % 16].
+template <typename TC>
+__global__ __launch_bounds__(256) void k_fold(const DevState* __restrict__ st, const TC* __restrict__ Gop,
+                                              const double* __restrict__ Wkeep, TC* __restrict__ Gfold, int nct) {
+    const int kall = st->kall, k1 = st->k1, ldb = st->ldb, r1n = st->r1n;
+    const int ng = (kall + 15) / 16;
+    const int total = ng * nct * 256;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+        const int e = idx & 3, ln = (idx >> 2) & 63, tc = idx >> 8;
+        const int c = tc % nct, t = tc / nct;
+        const int row = 16 * t + 4 * (ln >> 4) + e, a = 16 * c + (ln & 15);
+        double v = 0.0;
+        if (row < kall && a < r1n) {
+            const TC* gr = Gop + (size_t)row * ldb;
+            const double* wc = Wkeep + (size_t)a * k1;
+            for (int i = 0; i < k1; ++i) v += (double)gr[i] * wc[i];
+        }
+        Gfold[idx] = (TC)v;
     }
 }
 

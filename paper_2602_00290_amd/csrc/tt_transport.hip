@@ -556,6 +556,8 @@ tt_status round_fused_t(tt_handle* h, int opkind, double tol, int cap, hipStream
                            (const double*)h->at<double>(P.o_QPh), tol, std::min(cap, P.r1cap), std::min(cap, P.r2cap),
                            sc, h->Thn(), h->Phn(), V, h->at<double>(P.o_sv), (const float*)Gop,
                            h->at<float>(P.o_Gfold), NO);
+    hipLaunchKernelGGL(k_fold<float>, dim3(64), dim3(256), 0, s, (const DevState*)st, (const float*)Gop,
+                       (const double*)sc.Wkeep, h->at<float>(P.o_Gfold), NO);
     h->ev_end(e, s);
     e = h->ev_begin(KC_OUTPUT, s);
     hipLaunchKernelGGL((k_fused_f32<NO, false>), dim3(P.fused_blocks_o), dim3(kFusedThreads), P.lds_o, s, h->geom, fn,
