@@ -494,6 +494,11 @@ __device__ __forceinline__ int block_jacobi_sym64(double* S, int ld, double* W, 
                     double t;
                     jacobi_rotation(app, aqq, apq, &c, &sn, &t);
                     if (fabs(t) > tconv) *flag = 1;
+                    // a rotation by less than 1e-10 changes nothing the rounding can see
+                    if (fabs(t) <= 1e-10) {
+                        c = 1.0;
+                        sn = 0.0;
+                    }
                 }
                 cs[2 * threadIdx.x] = c;
                 cs[2 * threadIdx.x + 1] = sn;
@@ -501,9 +506,10 @@ __device__ __forceinline__ int block_jacobi_sym64(double* S, int ld, double* W, 
                 pb_[threadIdx.x] = b;
             }
             __syncthreads();
-            {
+            const double sp = cs[2 * p + 1], sq = cs[2 * q + 1];
+            if (sp != 0.0 || sq != 0.0) {   // both rotations identity: block unchanged
                 const int ap = pa_[p], bp = pb_[p], aq = pa_[q], bq = pb_[q];
-                const double cp = cs[2 * p], sp = cs[2 * p + 1], cq = cs[2 * q], sq = cs[2 * q + 1];
+                const double cp = cs[2 * p], cq = cs[2 * q];
                 double* s00 = S + ap + (size_t)aq * ld;
                 double* s01 = S + ap + (size_t)bq * ld;
                 double* s10 = S + bp + (size_t)aq * ld;
