@@ -37,21 +37,18 @@ constexpr int kFusedThreads = 64 * kFusedWaves;
 
 __host__ __device__ constexpr int gram_blocks(int nct) { return nct * (nct + 1) / 2; }
 
-// Neighbour structure of the gather blocks of one operator (host-computed).
-// Block j of a row k reads row k + delta[j] inside the domain; across a
-// domain edge (boundary-mask bit ebit[j] of the row set) it reads
-// k + wdelta[j] if bit j of wok is set (periodic axis), else nothing.  The
-// rank-1 columns of the operator are a dense block of rw columns per row,
-// stored roff elements after the start of the current Z.  Every load of the
-// fused kernels is unconditional: a slot with nothing to read points at a
-// zero region (zoff), which keeps the loads branch-free so that they stay in
-// flight across the pipeline.
+// Gather structure of one operator for the fused kernels.  Gather block
+// j >= 1 of row k reads the row nbr[k * ns + j - 1] of the per-problem
+// neighbour table (-1: none), built once at create (every operator with
+// streaming terms has the same gather order).  The rank-1 columns of the
+// operator are a dense block of rw columns per row, stored roff elements
+// after the start of the current Z.  Every load of the fused kernels is
+// unconditional: a slot with nothing to read points at a zero region (zoff),
+// which keeps the loads branch-free so that they stay in flight across the
+// pipeline.
 struct FusedNbr {
-    int delta[kMaxTerms + 1];
-    int wdelta[kMaxTerms + 1];
-    int ebit[kMaxTerms + 1];
-    int wok;
     int n_gather;
+    int ns;           // entries per row of the neighbour table (2 d_X)
     int rw;
     long long roff;
     long long zoff;   // offset of a zero region of at least 64 elements (loads with nothing to read go there)
@@ -90,6 +87,19 @@ __global__ __launch_bounds__(256) void k_row_aux(Geom g, RowData rd, float2* __r
     aux[k] = v;
 }
 
+// Neighbour rows of the gather blocks j = 1 .. ns of operator `op` (shifted
+// copies of Z: the upwind neighbour of each streaming term, wrapped on
+// periodic axes, -1 outside the domain), ns per row.
+__global__ __launch_bounds__(256) void k_nbr_table(Geom g, OpDesc op, int ns, int* __restrict__ tab) {
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= g.M) return;
+    for (int j = 1; j <= ns; ++j) {
+        long long r = -1;
+        if (j < op.n_gather) r = neighbour_row(g, k, op.gaxis[j], op.gdir[j]);
+        tab[k * ns + j - 1] = (int)r;
+    }
+}
+
 // Rank-1 columns of operator `op` as a dense M x rw block (zero beyond
 // n_r1); the fused kernels scale them by d_k with the rest of the row.
 __global__ __launch_bounds__(256) void k_rank1_rows(Geom g, OpDesc op, RowData rd, int rw, float* __restrict__ R) {
@@ -103,7 +113,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
                                                               const float* __restrict__ Z,
                                                               const float* __restrict__ Gsw,
                                                               float* __restrict__ Out, const float2* __restrict__ aux,
-                                                              double* __restrict__ Gpart, long long ntiles) {
+                                                              const int* __restrict__ nbr, double* __restrict__ Gpart,
+                                                              long long ntiles) {
     constexpr int NB = gram_blocks(NCT);
     extern __shared__ __align__(16) unsigned char fused_lds[];
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
@@ -138,39 +149,42 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
     const long long nw = (long long)nb * kFusedWaves;
     const int t_begin = (int)(gw * ntiles / nw), t_end = (int)((gw + 1) * ntiles / nw);
 
-    // Row data of a tile (from its prefetched row-table entries a0, a1) into
-    // this wave's offset table; returns d of the lane's two A rows.  Lane
-    // (m, q) writes slots q and q + 4 of row m.
-    const int last = (int)g.M - 1;
-    auto aux_of = [&](int tile, int rt) -> float2 {
-        const int row = 32 * tile + 16 * rt + m;
-        return aux[row < last ? row : last];   // rows past the end are never used
+    // Row data of a tile into this wave's offset table (slots 0..8 of both row
+    // tiles), from the row's table entries loaded a tile ahead (RowPre).  Lane
+    // (m, q) writes slots q and q + 4 of row m: slot 0 is the row itself,
+    // slots 1..6 gather blocks, slot 7 the rank-1 block.  Returns d of the
+    // lane's two A rows.  Branch-free: a slot with nothing to read points at
+    // the zero region.
+    struct RowPre {
+        float2 a;
+        int n1, n2;   // neighbour rows of slots q and q + 4 (when they are gather blocks)
     };
-    auto tile_rows = [&](int tile, float2 a0, float2 a1, float& d0, float& d1) {
+    const int last = (int)g.M - 1;
+    const int ns = fn.ns;
+    const int i1 = min(max(q - 1, 0), ns - 1), i2 = min(q + 3, ns - 1);
+    auto pre_of = [&](int tile, int rt) -> RowPre {
+        int row = 32 * tile + 16 * rt + m;
+        row = row < last ? row : last;   // rows past the end are never used
+        RowPre r;
+        r.a = aux[row];
+        r.n1 = nbr[(size_t)row * ns + i1];
+        r.n2 = nbr[(size_t)row * ns + i2];
+        return r;
+    };
+    auto tile_rows = [&](int tile, const RowPre& p0, const RowPre& p1, float& d0, float& d1) {
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
             const int row = 32 * tile + 16 * rt + m;
             const bool valid = row < g.M;
-            const float2 a = rt == 0 ? a0 : a1;
-            const int mask = __float_as_int(a.y);
-            const float d = fn.scale_d ? a.x : 1.0f;
+            const RowPre& pr = rt == 0 ? p0 : p1;
+            const float d = fn.scale_d ? pr.a.x : 1.0f;
             if (rt == 0) d0 = d; else d1 = d;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                int o = zoff;
-                if (j < 7) {
-                    if (valid && j < fn.n_gather) {
-                        const bool edge = (mask >> fn.ebit[j]) & 1;
-                        int nr = -1;
-                        if (!edge) nr = row + fn.delta[j];
-                        else if ((fn.wok >> j) & 1) nr = row + fn.wdelta[j];
-                        if (nr >= 0) o = nr * ldz;
-                    }
-                } else if (valid && fn.rw > 0) {
-                    o = (int)(fn.roff + (long long)row * fn.rw);
-                }
-                if ((j & 3) == q) offs[(rt * kOffSlots + j) * 16 + m] = o;
-            }
+            int lo = (q < fn.n_gather && pr.n1 >= 0) ? pr.n1 * ldz : zoff;
+            lo = q == 0 ? row * ldz : lo;
+            int hi = (q + 4 < fn.n_gather && pr.n2 >= 0) ? pr.n2 * ldz : zoff;
+            hi = q == 3 ? (fn.rw > 0 ? (int)(fn.roff + (long long)row * fn.rw) : zoff) : hi;
+            offs[(rt * kOffSlots + q) * 16 + m] = valid ? lo : zoff;
+            offs[(rt * kOffSlots + q + 4) * 16 + m] = valid ? hi : zoff;
         }
     };
     // A operand of K group t for both row tiles (one 16-byte load each, not
@@ -204,7 +218,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
     float d0 = 0.f, d1 = 0.f, nd0 = 0.f, nd1 = 0.f;
     f32x4v x0 = zero4, x1 = zero4, y0 = zero4, y1 = zero4;
     if (t_begin < t_end) {
-        tile_rows(t_begin, aux_of(t_begin, 0), aux_of(t_begin, 1), d0, d1);
+        tile_rows(t_begin, pre_of(t_begin, 0), pre_of(t_begin, 1), d0, d1);
         load_a(0, x0, x1);
         load_a(1, y0, y1);
     }
@@ -226,7 +240,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
     };
     for (int tile = t_begin; tile < t_end; ++tile) {
         const bool more = tile + 1 < t_end;
-        const float2 na0 = aux_of(tile + 1, 0), na1 = aux_of(tile + 1, 1);
+        const RowPre na0 = pre_of(tile + 1, 0), na1 = pre_of(tile + 1, 1);
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
@@ -263,18 +277,26 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
                 }
         } else {
             // D[i][j] of row tile rt: row R0 + 16 rt + 4 q + r, column 16 c + m
+            const bool full = R0 + 32 <= g.M;
 #pragma unroll
-            for (int rt = 0; rt < 2; ++rt)
+            for (int c = 0; c < NCT; ++c) {
+                const int col = 16 * c + m;
+                if (col < ldo) {
+                    float* op = Out + (size_t)(R0 + 4 * q) * ldo + col;
+                    if (full) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = R0 + 16 * rt + 4 * q + r;
-                    if (row >= g.M) continue;
+                        for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-                    for (int c = 0; c < NCT; ++c) {
-                        const int col = 16 * c + m;
-                        if (col < ldo) Out[(size_t)row * ldo + col] = acc[rt][c][r];
+                            for (int r = 0; r < 4; ++r) op[(size_t)(16 * rt + r) * ldo] = acc[rt][c][r];
+                    } else {
+#pragma unroll
+                        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                if (R0 + 16 * rt + 4 * q + r < g.M) op[(size_t)(16 * rt + r) * ldo] = acc[rt][c][r];
                     }
                 }
+            }
         }
         d0 = nd0;
         d1 = nd1;

@@ -79,7 +79,7 @@ struct Plan {
     size_t lds_p = 0, lds_o = 0;
     size_t B_bytes = 0;
     // workspace layout (byte offsets)
-    size_t o_Gsw = 0, o_Gfold = 0, o_GP = 0, o_aux = 0, o_R1 = 0, o_R2 = 0, o_zero = 0;
+    size_t o_Gsw = 0, o_Gfold = 0, o_GP = 0, o_aux = 0, o_R1 = 0, o_R2 = 0, o_zero = 0, o_nbr = 0;
     // split-BF16 operands (precision TT_PREC_BF16X): chunked, column-major hi / lo
     bool bf16x = false;
     int nct_b = 4, nct_bo = 2, kc_g = 1, kc_v = 1;
@@ -252,6 +252,7 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         P.o_R1 = take((size_t)P.M * std::max(P.rw1, 1) * sizeof(float));
         P.o_R2 = take((size_t)P.M * std::max(P.rw2, 1) * sizeof(float));
         P.o_zero = take(1024);   // zero region for loads with nothing to read
+        P.o_nbr = take((size_t)P.M * P.n_terms * sizeof(int));
     }
     P.o_Th0 = take((size_t)P.r1cap * P.nt * P.r2cap * d);
     P.o_Th1 = take((size_t)P.r1cap * P.nt * P.r2cap * d);
@@ -497,19 +498,8 @@ FusedNbr fused_nbr(const tt_handle* h, int opkind) {
     FusedNbr f;
     std::memset(&f, 0, sizeof(f));
     f.n_gather = op.n_gather;
+    f.ns = P.n_terms;
     f.scale_d = op.scale_d;
-    for (int j = 0; j < kMaxTerms + 1; ++j) f.ebit[j] = 31;
-    for (int j = 1; j < op.n_gather; ++j) {
-        const int a = op.gaxis[j], sg = op.gdir[j];
-        const int n = a == 0 ? P.nx : (a == 1 ? P.ny : P.nz);
-        const int stride = a == 0 ? P.G : (a == 1 ? P.nx * P.G : P.nx * P.ny * P.G);
-        f.delta[j] = sg * stride;
-        f.ebit[j] = 2 * a + (sg > 0 ? 1 : 0);
-        if (h->geom.periodic[a]) {
-            f.wok |= 1 << j;
-            f.wdelta[j] = -sg * (n - 1) * stride;
-        }
-    }
     const size_t zoff = h->zcur ? P.o_Z1 : P.o_Z0;
     if (op.n_r1 > 0) {
         const bool src = opkind == OP_SOURCE;
@@ -535,9 +525,10 @@ tt_status round_fused_t(tt_handle* h, int opkind, double tol, int cap, hipStream
     const FusedNbr fn = fused_nbr(h, opkind);
     const float2* aux = h->at<float2>(P.o_aux);
     size_t e = h->ev_begin(KC_PROJECT, s);
+    const int* nbr = h->at<int>(P.o_nbr);
     hipLaunchKernelGGL((k_fused_f32<NP, true>), dim3(P.fused_blocks), dim3(kFusedThreads), P.lds_p, s, h->geom, fn,
                        (const DevState*)st, (const float*)h->Zc(), (const float*)h->at<float>(P.o_Gsw), (float*)nullptr,
-                       aux, GP, P.fused_tiles);
+                       aux, nbr, GP, P.fused_tiles);
     h->ev_end(e, s);
     e = h->ev_begin(KC_TREE, s);
     hipLaunchKernelGGL((k_sum_gram<NP>), dim3((gram_blocks(NP) * 256 + 31) / 32), dim3(256), 0, s, (const double*)GP,
@@ -562,7 +553,7 @@ tt_status round_fused_t(tt_handle* h, int opkind, double tol, int cap, hipStream
     e = h->ev_begin(KC_OUTPUT, s);
     hipLaunchKernelGGL((k_fused_f32<NO, false>), dim3(P.fused_blocks_o), dim3(kFusedThreads), P.lds_o, s, h->geom, fn,
                        (const DevState*)st, (const float*)h->Zc(), (const float*)h->at<float>(P.o_Gfold),
-                       (float*)h->Zn(), aux, (double*)nullptr, P.fused_tiles);
+                       (float*)h->Zn(), aux, nbr, (double*)nullptr, P.fused_tiles);
     h->ev_end(e, s);
     hipLaunchKernelGGL(k_commit, dim3(1), dim3(64), 0, s, st);
     HIP_TRY(hipGetLastError());
@@ -978,6 +969,7 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
         if (hipMemsetAsync(h->ws + P.o_zero, 0, 1024, s) != hipSuccess) { delete h; return fail(TT_ERR_HIP, "memset"); }
         const dim3 gr((unsigned)((P.M + 255) / 256));
         hipLaunchKernelGGL(k_row_aux, gr, dim3(256), 0, s, h->geom, h->rowdata(), h->at<float2>(P.o_aux));
+        hipLaunchKernelGGL(k_nbr_table, gr, dim3(256), 0, s, h->geom, h->ops[OP_FULL], P.n_terms, h->at<int>(P.o_nbr));
         if (P.rw1 > 0)
             hipLaunchKernelGGL(k_rank1_rows, gr, dim3(256), 0, s, h->geom, h->ops[h->step_order ? OP_TRANSPORT : OP_FULL],
                                h->rowdata(), P.rw1, h->at<float>(P.o_R1));
