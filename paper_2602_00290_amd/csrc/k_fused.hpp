@@ -199,8 +199,10 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
         const int cc = k0 < KG ? k0 - jj * ldz : (k0 < K ? k0 - KG : 0);
         const int o0 = offs[slot * 16 + m];
         const int o1 = offs[(kOffSlots + slot) * 16 + m];
-        a0 = *reinterpret_cast<const f32x4v*>(Z + o0 + cc);
-        a1 = *reinterpret_cast<const f32x4v*>(Z + o1 + cc);
+        // 32-bit byte offsets from the uniform base (the workspace spans < 4 GiB)
+        const char* zb = reinterpret_cast<const char*>(Z);
+        a0 = *reinterpret_cast<const f32x4v*>(zb + (unsigned)(o0 + cc) * 4u);
+        a1 = *reinterpret_cast<const f32x4v*>(zb + (unsigned)(o1 + cc) * 4u);
     };
 
     f64x4 gacc[GRAM ? NB : 1];
@@ -282,18 +284,21 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
             for (int c = 0; c < NCT; ++c) {
                 const int col = 16 * c + m;
                 if (col < ldo) {
-                    float* op = Out + (size_t)(R0 + 4 * q) * ldo + col;
+                    char* ob = reinterpret_cast<char*>(Out);
+                    const unsigned o0 = (unsigned)((R0 + 4 * q) * ldo + col) * 4u;
                     if (full) {
 #pragma unroll
                         for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-                            for (int r = 0; r < 4; ++r) op[(size_t)(16 * rt + r) * ldo] = acc[rt][c][r];
+                            for (int r = 0; r < 4; ++r)
+                                *reinterpret_cast<float*>(ob + o0 + (unsigned)((16 * rt + r) * ldo) * 4u) = acc[rt][c][r];
                     } else {
 #pragma unroll
                         for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
                             for (int r = 0; r < 4; ++r)
-                                if (R0 + 16 * rt + 4 * q + r < g.M) op[(size_t)(16 * rt + r) * ldo] = acc[rt][c][r];
+                                if (R0 + 16 * rt + 4 * q + r < g.M)
+                                    *reinterpret_cast<float*>(ob + o0 + (unsigned)((16 * rt + r) * ldo) * 4u) = acc[rt][c][r];
                     }
                 }
             }

@@ -295,7 +295,9 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
     P.o_colsum = take((size_t)256 * 128 * d);
     P.bytes = off;
     // element offsets of the rank-1 blocks from Z must fit 32 bits
-    P.fused_overflow = P.fused && (long long)(P.o_zero - P.o_Z0) / 4 + 256 >= (1LL << 31);
+    // the fused kernels address Z, the rank-1 blocks and the zero region with
+    // 32-bit byte offsets from the current Z
+    P.fused_overflow = P.fused && (long long)(P.o_zero - P.o_Z0) + 1024 >= (1LL << 32);
     return TT_OK;
 }
 
