@@ -222,8 +222,9 @@ def mode_pmc_summary(args):
         "write_bytes": write * fw,
         "raw_fetch_bytes": fetch, "raw_write_bytes": write, "dispatches": [nf, nw],
         "calibration": {"copy_bytes": nbytes, "fetch_factor": ff, "write_factor": fw},
-        # Z read once (ld 24 floats) + row table (8 B) + rank-1 block (4 floats) + Gram partials
-        "algorithmic_bytes": p.M * (24 * 4 + 8 + 16) + 256 * 10 * 256 * 8,
+        # Z read once (ld 24 floats) + row table (8 B) + neighbour table (4 ints) + rank-1
+        # block (4 floats) per row, + the Gram partials written
+        "algorithmic_bytes": p.M * (24 * 4 + 8 + 16 + 16) + 256 * 10 * 256 * 8,
         "commands": [f"rocprofv3 --pmc {c} --output-format csv -d <dir>/{s} -o {s} -- python3 bench.py --mode {m}"
                      for c, s, m in (("FETCH_SIZE", "fetch", "probe"), ("WRITE_SIZE", "write", "probe"),
                                      ("FETCH_SIZE", "copy_fetch", "copy"), ("WRITE_SIZE", "copy_write", "copy"))],
