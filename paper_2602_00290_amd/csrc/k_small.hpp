@@ -34,17 +34,17 @@ struct OpDesc {
 struct SmallScratch {
     double* A1;    // N_phi x R2cap
     double* Q1;    // N_phi x N_phi + R2cap x k2cap
-    double* A2;    // (N_theta k2cap) x R1cap
+    double* A2;    // max((N_theta k2cap) x R1cap, k1cap x (k1cap | 1))
     double* Q2;    // (N_theta k2cap) x k1cap
     double* tau;   // max(R1cap, R2cap)
-    double* J;     // k1cap x k1cap
+    double* J;     // k1cap x (k1cap | 1)
     double* Th2;   // r1cap x N_theta k2cap
     double* C2;    // r1cap N_theta x k2cap
     double* V2;    // k2cap x k2cap
     double* sv;    // 3 k1cap + k2cap
     int* perm;     // k1cap + k2cap
     int* flag;
-    double* W;     // k1cap x k1cap rotations of the first-bond Jacobi
+    double* W;     // k1cap x (k1cap | 1) rotations of the first-bond Jacobi
     double* Wkeep; // k1cap x k1cap right singular vectors of the previous round
 };
 
@@ -543,6 +543,91 @@ __device__ __forceinline__ int block_jacobi_sym64(double* S, int ld, double* W, 
     return 40;
 }
 
+// Two-sided Jacobi for n <= 128 with S (n x n, column-major, leading dimension
+// ld) in LDS and W in global memory (leading dimension ldw): each round
+// updates every 2 x 2 block (rows a_p, b_p; columns a_q, b_q) of S in one
+// phase, R_p^T B R_q, and the rows of W per column pair (W <- W R); rounds
+// leave the blocks of two identity rotations untouched.  Same rotation,
+// skipping and stopping rules as block_jacobi_sym64.  __syncthreads orders
+// the global W accesses of consecutive rounds within the workgroup.
+__device__ __forceinline__ int block_jacobi_sym_wide(double* S, int n, int ld, double* W, int ldw, double* cs, int* pa_,
+                                                     int* pb_, int* flag, double tconv) {
+    if (n < 2) {
+        __syncthreads();
+        return 0;
+    }
+    const int nt = blockDim.x;
+    const int np = (n + 1) & ~1, npairs = np / 2;
+    double tr = 0.0;
+    for (int i = 0; i < n; ++i) tr += fabs(S[i + (size_t)i * ld]);
+    const double floor_abs = 1e-15 * tr;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (threadIdx.x == 0) *flag = 0;
+        __syncthreads();
+        for (int round = 0; round < np - 1; ++round) {
+            for (int pp = threadIdx.x; pp < npairs; pp += nt) {
+                int a, b;
+                tournament_pair(pp, round, np, &a, &b);
+                double c = 1.0, sn = 0.0;
+                if (b < n) {
+                    const double app = S[a + (size_t)a * ld], aqq = S[b + (size_t)b * ld], apq = S[a + (size_t)b * ld];
+                    if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs) {
+                        double t;
+                        jacobi_rotation(app, aqq, apq, &c, &sn, &t);
+                        if (fabs(t) > tconv) *flag = 1;
+                        if (fabs(t) <= 1e-10) {
+                            c = 1.0;
+                            sn = 0.0;
+                        }
+                    }
+                }
+                cs[2 * pp] = c;
+                cs[2 * pp + 1] = sn;
+                pa_[pp] = a;
+                pb_[pp] = b;
+            }
+            __syncthreads();
+            // S <- R^T S R by 2 x 2 blocks (dummy pairs, b >= n, carry identity rotations)
+            for (int idx = threadIdx.x; idx < npairs * npairs; idx += nt) {
+                const int p = idx / npairs, q = idx % npairs;
+                const double sp = cs[2 * p + 1], sq = cs[2 * q + 1];
+                if (sp == 0.0 && sq == 0.0) continue;
+                const int ap = pa_[p], bp = pb_[p], aq = pa_[q], bq = pb_[q];
+                const double cp = cs[2 * p], cq = cs[2 * q];
+                // a dummy pair (odd n) has b = n: its row / column does not exist
+                const bool vp = bp < n, vq = bq < n;
+                const double b00 = S[ap + (size_t)aq * ld];
+                const double b01 = vq ? S[ap + (size_t)bq * ld] : 0.0;
+                const double b10 = vp ? S[bp + (size_t)aq * ld] : 0.0;
+                const double b11 = (vp && vq) ? S[bp + (size_t)bq * ld] : 0.0;
+                const double c00 = cq * b00 - sq * b01, c01 = sq * b00 + cq * b01;
+                const double c10 = cq * b10 - sq * b11, c11 = sq * b10 + cq * b11;
+                S[ap + (size_t)aq * ld] = cp * c00 - sp * c10;
+                if (vq) S[ap + (size_t)bq * ld] = cp * c01 - sp * c11;
+                if (vp) S[bp + (size_t)aq * ld] = sp * c00 + cp * c10;
+                if (vp && vq) S[bp + (size_t)bq * ld] = sp * c01 + cp * c11;
+            }
+            // W <- W R: row i of columns a_q, b_q
+            for (int idx = threadIdx.x; idx < npairs * n; idx += nt) {
+                const int q = idx / n, i = idx % n;
+                const double sq = cs[2 * q + 1];
+                if (sq == 0.0) continue;
+                const double cq = cs[2 * q];
+                double* wa = W + i + (size_t)pa_[q] * ldw;
+                double* wb = W + i + (size_t)pb_[q] * ldw;
+                const double u = *wa, v = *wb;
+                *wa = cq * u - sq * v;
+                *wb = sq * u + cq * v;
+            }
+            __syncthreads();
+        }
+        const int f = *flag;
+        __syncthreads();
+        if (!f) return sweep + 1;
+    }
+    return 40;
+}
+
 // C = A B for 64 x 64 operands in LDS, elements addressed as A(i, k) =
 // A[i * ai + k * ak], B(k, j) = B[k * bk + j * bj], C(i, j) = C[i + j * ldc];
 // threads 0..255 each form a 4 x 4 tile (8 LDS reads per 16 FMAs).  The caller
@@ -813,7 +898,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
     // banks), zero / identity padded beyond k1.  Otherwise LDS where it fits
     // and global scratch beyond.
     const int kp = FAST ? 64 : k1;                       // padded order
-    const int ld = FAST ? 65 : k1;
+    const int ld = FAST ? 65 : (k1 | 1);   // odd leading dimension: columns on different LDS banks
     const size_t reg0 = FAST ? (size_t)(64 * 65 > 257 * 16 ? 64 * 65 : 257 * 16) : 0;
     double* J = FAST ? lds : cv.take((size_t)k1 * ld, sc.J);
     double* W = FAST ? lds + reg0 : cv.take((size_t)k1 * ld, sc.W);
@@ -889,7 +974,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
         if (FAST)
             sw1 = block_jacobi_sym64(J, ld, W, cs, pa_, pb_, &sh_flag, kGramSweepTol);
         else
-            sw1 = block_jacobi_sym(J, k1, ld, W, cs, pa_, pb_, &sh_flag, kGramSweepTol);
+            sw1 = block_jacobi_sym_wide(J, k1, ld, W, ld, cs, pa_, pb_, &sh_flag, kGramSweepTol);
         tph[2] = wall_clock64();
         for (int j = threadIdx.x; j < k1; j += blockDim.x) s1[j] = sqrt(fmax(J[j + (size_t)j * ld], 0.0));
     }

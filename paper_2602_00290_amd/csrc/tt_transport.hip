@@ -89,6 +89,7 @@ struct Plan {
     size_t o_state, o_Z0, o_Z1, o_B, o_Th0, o_Th1, o_Ph0, o_Ph1, o_LTh, o_QTh, o_QPh, o_G, o_V, o_RA, o_RB, o_small,
         o_k0, o_ks, o_eps, o_ghost, o_gtab, o_htab, o_ThN, o_PhN, o_sv, o_colsum;
     size_t small_bytes = 0, n_parts_max = 1;
+    size_t k1sq = 1;                // k1cap x (k1cap | 1): SVD-chain matrices outside LDS
     size_t bytes = 0;
 };
 
@@ -270,17 +271,19 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
     P.small_bytes = 0;
     P.small_bytes += align256((size_t)P.np * P.R2cap * d);
     P.small_bytes += align256(((size_t)P.np * P.np + (size_t)P.R2cap * P.k2cap) * d);
-    P.small_bytes += align256(std::max(m2 * P.R1cap, (size_t)P.k1cap * P.k1cap) * d);
+    // matrices of the SVD chain outside LDS use an odd leading dimension (k1 | 1)
+    P.k1sq = (size_t)P.k1cap * (size_t)(P.k1cap | 1);
+    P.small_bytes += align256(std::max(m2 * P.R1cap, P.k1sq) * d);
     P.small_bytes += align256(m2 * P.k1cap * d);
     P.small_bytes += align256((size_t)std::max(P.R1cap, P.R2cap) * d);
-    P.small_bytes += align256((size_t)P.k1cap * P.k1cap * d);
+    P.small_bytes += align256(P.k1sq * d);
     P.small_bytes += align256((size_t)P.r1cap * m2 * d);
     P.small_bytes += align256((size_t)P.r1cap * P.nt * P.k2cap * d);
     P.small_bytes += align256((size_t)P.k2cap * P.k2cap * d);
     P.small_bytes += align256((size_t)(3 * P.k1cap + P.k2cap) * d);
     P.small_bytes += align256((size_t)(P.k1cap + P.k2cap) * sizeof(int));
     P.small_bytes += align256(sizeof(int));
-    P.small_bytes += align256((size_t)P.k1cap * P.k1cap * d);
+    P.small_bytes += align256(P.k1sq * d);
     P.small_bytes += align256((size_t)P.k1cap * P.k1cap * d);
     P.o_small = take(P.small_bytes);
     P.o_k0 = take((size_t)P.NX * d);
@@ -354,17 +357,17 @@ struct tt_handle {
         const size_t m2 = (size_t)P.nt * P.k2cap;
         s.A1 = (double*)b; b += align256((size_t)P.np * P.R2cap * d);
         s.Q1 = (double*)b; b += align256(((size_t)P.np * P.np + (size_t)P.R2cap * P.k2cap) * d);
-        s.A2 = (double*)b; b += align256(std::max(m2 * P.R1cap, (size_t)P.k1cap * P.k1cap) * d);
+        s.A2 = (double*)b; b += align256(std::max(m2 * P.R1cap, P.k1sq) * d);
         s.Q2 = (double*)b; b += align256(m2 * P.k1cap * d);
         s.tau = (double*)b; b += align256((size_t)std::max(P.R1cap, P.R2cap) * d);
-        s.J = (double*)b; b += align256((size_t)P.k1cap * P.k1cap * d);
+        s.J = (double*)b; b += align256(P.k1sq * d);
         s.Th2 = (double*)b; b += align256((size_t)P.r1cap * m2 * d);
         s.C2 = (double*)b; b += align256((size_t)P.r1cap * P.nt * P.k2cap * d);
         s.V2 = (double*)b; b += align256((size_t)P.k2cap * P.k2cap * d);
         s.sv = (double*)b; b += align256((size_t)(3 * P.k1cap + P.k2cap) * d);
         s.perm = (int*)b; b += align256((size_t)(P.k1cap + P.k2cap) * sizeof(int));
         s.flag = (int*)b; b += align256(sizeof(int));
-        s.W = (double*)b; b += align256((size_t)P.k1cap * P.k1cap * d);
+        s.W = (double*)b; b += align256(P.k1sq * d);
         s.Wkeep = (double*)b;
         return s;
     }
