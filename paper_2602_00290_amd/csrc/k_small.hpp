@@ -659,6 +659,47 @@ __device__ __forceinline__ void block_mm64(const double* A, int ai, int ak, cons
         for (int y = 0; y < 4; ++y) C[(i0 + x) + (size_t)(j0 + y) * ldc] = acc[x][y];
 }
 
+// C = A B with A (m x K) and B (K x n) in LDS or global memory: A(i, k) =
+// A[i * ai + k * ak], B(k, j) = B[k * bk + j * bj], C(i, j) = C[i * ci + j * cj].
+// Each thread forms 4 x 4 tiles of C (8 loads per 16 FMAs); indices beyond m
+// and n are clamped on load and not stored.  The caller synchronises before
+// and after.
+__device__ __forceinline__ void block_mm_tiled(int m, int n, int K, const double* A, int ai, int ak, const double* B,
+                                               int bk, int bj, double* C, int ci, int cj) {
+    const int mt = (m + 3) >> 2, nt = (n + 3) >> 2;
+    for (int t = threadIdx.x; t < mt * nt; t += blockDim.x) {
+        const int i0 = 4 * (t % mt), j0 = 4 * (t / mt);
+        int ia[4], jb[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            ia[x] = (i0 + x < m ? i0 + x : m - 1) * ai;
+            jb[x] = (j0 + x < n ? j0 + x : n - 1) * bj;
+        }
+        double acc[4][4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+#pragma unroll 4
+        for (int k = 0; k < K; ++k) {
+            double a[4], bv[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) a[x] = A[ia[x] + k * ak];
+#pragma unroll
+            for (int y = 0; y < 4; ++y) bv[y] = B[k * bk + jb[y]];
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * bv[y];
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y)
+                if (i0 + x < m && j0 + y < n) C[(size_t)(i0 + x) * ci + (size_t)(j0 + y) * cj] = acc[x][y];
+    }
+}
+
 // Descending order of s[0..n) into perm (ties by index).
 __device__ __forceinline__ void block_sort_desc(const double* s, int n, int* perm) {
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
@@ -950,19 +991,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
             __syncthreads();
         } else if (warm) {
             // J = W^T G W: J <- G W, then T <- W^T J
-            for (int idx = threadIdx.x; idx < kp * kp; idx += blockDim.x) {
-                const int i = idx % kp, j = idx / kp;
-                double acc = 0.0;
-                for (int k = 0; k < k1; ++k) acc += T[i + (size_t)k * ld] * W[k + (size_t)j * ld];
-                J[i + (size_t)j * ld] = acc;
-            }
+            block_mm_tiled(k1, k1, k1, T, 1, ld, W, 1, ld, J, 1, ld);
             __syncthreads();
-            for (int idx = threadIdx.x; idx < kp * kp; idx += blockDim.x) {
-                const int i = idx % kp, j = idx / kp;
-                double acc = 0.0;
-                for (int k = 0; k < k1; ++k) acc += W[k + (size_t)i * ld] * J[k + (size_t)j * ld];
-                T[i + (size_t)j * ld] = acc;
-            }
+            block_mm_tiled(k1, k1, k1, W, ld, 1, J, 1, ld, T, 1, ld);
             __syncthreads();
         }
         for (int idx = threadIdx.x; idx < kp * kp; idx += blockDim.x) {
@@ -1005,37 +1036,58 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
     const int mC = r1n * nt;
     const int mpad = FAST ? (mC <= 128 ? 128 : 256) : mC;   // fixed-layout row count (zero rows beyond mC)
     const int ldc = FAST ? mpad + 1 : mC;                    // padded column stride of C2
-    double* C2 = FAST ? lds : cv.take((size_t)ldc * k2, sc.C2);
+    // the first-bond matrix J is no longer needed: C2 takes its place where it fits
+    double* C2 = FAST ? lds : ((size_t)ldc * k2 <= (size_t)k1 * ld ? J : cv.take((size_t)ldc * k2, sc.C2));
     if (FAST)
         for (int idx = threadIdx.x; idx < ldc * k2; idx += blockDim.x) C2[idx] = 0.0;
-    __syncthreads();
     double* V2 = FAST ? s1 + k1 : cv.take((size_t)k2 * k2, sc.V2);
     double* nrm2 = FAST ? V2 + (size_t)k2 * k2 : cv.take((size_t)k2, sc.sv + k1);
-    for (int idx = threadIdx.x; idx < r1n * m2; idx += blockDim.x) {
-        const int a = idx / m2, col = idx % m2;
-        const double* w = W + (size_t)p1[a] * ld;
-        double acc = 0.0;
-        for (int i = 0; i < k1; ++i) acc += w[i] * QTh[(size_t)i * m2 + col];
-        sc.Th2[(size_t)a * m2 + col] = acc;
-        const int l = col / k2, c = col % k2;
-        C2[(a * nt + l) + (size_t)c * ldc] = s1[p1[a]] * acc;
-    }
+    // Theta'' = V_r^T Q_Theta from the sorted V (Wkeep, complete after the barrier)
+    __syncthreads();
+    block_mm_tiled(r1n, m2, k1, sc.Wkeep, k1, 1, QTh, m2, 1, sc.Th2, m2, 1);
     for (int idx = threadIdx.x; idx < k2 * k2; idx += blockDim.x) V2[idx] = (idx % k2 == idx / k2) ? 1.0 : 0.0;
     __syncthreads();
+    for (int idx = threadIdx.x; idx < r1n * m2; idx += blockDim.x) {
+        const int a = idx / m2, col = idx % m2;
+        const int l = col / k2, c = col % k2;
+        C2[(a * nt + l) + (size_t)c * ldc] = s1[p1[a]] * sc.Th2[idx];
+    }
+    __syncthreads();
     tph[3] = wall_clock64();
-    if (FAST && mpad == 128)
-        sw2 = block_jacobi_1s_fixed<8, 16, 1>(C2, ldc, k2, V2, k2, &sh_flag, red);
-    else if (FAST)
-        sw2 = block_jacobi_1s_fixed<16, 16, 1>(C2, ldc, k2, V2, k2, &sh_flag, red);
-    else
-        sw2 = block_jacobi_1s(C2, ldc, mC, k2, V2, k2, nrm2, &sh_flag, red);
-    tph[4] = wall_clock64();
     double* s2 = sc.sv + k1;
     int* p2 = sc.perm + k1;
-    for (int j = threadIdx.x; j < k2; j += blockDim.x) {
-        double acc = 0.0;
-        for (int i = 0; i < mC; ++i) acc += C2[i + (size_t)j * ldc] * C2[i + (size_t)j * ldc];
-        s2[j] = sqrt(acc);
+    if (!FAST && gram) {
+        // Gram route, as for the first bond: H = C2^T C2 in FP64 and its
+        // eigenvectors (V2) and eigenvalues (S2^2) by two-sided Jacobi
+        const int ldh = k2 | 1;
+        double* H = cv.take((size_t)k2 * ldh, sc.A2);
+        for (int idx = threadIdx.x; idx < k2 * k2; idx += blockDim.x) {
+            const int c = idx % k2, e = idx / k2;
+            if (c > e) continue;
+            const double* x = C2 + (size_t)c * ldc;
+            const double* y = C2 + (size_t)e * ldc;
+            double acc = 0.0;
+            for (int i = 0; i < mC; ++i) acc += x[i] * y[i];
+            H[c + (size_t)e * ldh] = acc;
+            H[e + (size_t)c * ldh] = acc;
+        }
+        __syncthreads();
+        sw2 = block_jacobi_sym_wide(H, k2, ldh, V2, k2, cs, pa_, pb_, &sh_flag, kGramSweepTol);
+        tph[4] = wall_clock64();
+        for (int j = threadIdx.x; j < k2; j += blockDim.x) s2[j] = sqrt(fmax(H[j + (size_t)j * ldh], 0.0));
+    } else {
+        if (FAST && mpad == 128)
+            sw2 = block_jacobi_1s_fixed<8, 16, 1>(C2, ldc, k2, V2, k2, &sh_flag, red);
+        else if (FAST)
+            sw2 = block_jacobi_1s_fixed<16, 16, 1>(C2, ldc, k2, V2, k2, &sh_flag, red);
+        else
+            sw2 = block_jacobi_1s(C2, ldc, mC, k2, V2, k2, nrm2, &sh_flag, red);
+        tph[4] = wall_clock64();
+        for (int j = threadIdx.x; j < k2; j += blockDim.x) {
+            double acc = 0.0;
+            for (int i = 0; i < mC; ++i) acc += C2[i + (size_t)j * ldc] * C2[i + (size_t)j * ldc];
+            s2[j] = sqrt(acc);
+        }
     }
     __syncthreads();
     block_sort_desc(s2, k2, p2);

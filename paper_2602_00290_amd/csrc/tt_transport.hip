@@ -90,6 +90,12 @@ struct Plan {
         o_k0, o_ks, o_eps, o_ghost, o_gtab, o_htab, o_ThN, o_PhN, o_sv, o_colsum;
     size_t small_bytes = 0, n_parts_max = 1;
     size_t k1sq = 1;                // k1cap x (k1cap | 1): SVD-chain matrices outside LDS
+    // A2 scratch (doubles): the operand of the second-bond QR, the first-bond
+    // matrix T outside LDS, or the second-bond Gram matrix
+    size_t a2n() const {
+        const size_t m2 = (size_t)nt * k2cap;
+        return std::max(std::max(m2 * R1cap, k1sq), (size_t)k2cap * (size_t)(k2cap | 1));
+    }
     size_t bytes = 0;
 };
 
@@ -273,7 +279,7 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
     P.small_bytes += align256(((size_t)P.np * P.np + (size_t)P.R2cap * P.k2cap) * d);
     // matrices of the SVD chain outside LDS use an odd leading dimension (k1 | 1)
     P.k1sq = (size_t)P.k1cap * (size_t)(P.k1cap | 1);
-    P.small_bytes += align256(std::max(m2 * P.R1cap, P.k1sq) * d);
+    P.small_bytes += align256(P.a2n() * d);
     P.small_bytes += align256(m2 * P.k1cap * d);
     P.small_bytes += align256((size_t)std::max(P.R1cap, P.R2cap) * d);
     P.small_bytes += align256(P.k1sq * d);
@@ -357,7 +363,7 @@ struct tt_handle {
         const size_t m2 = (size_t)P.nt * P.k2cap;
         s.A1 = (double*)b; b += align256((size_t)P.np * P.R2cap * d);
         s.Q1 = (double*)b; b += align256(((size_t)P.np * P.np + (size_t)P.R2cap * P.k2cap) * d);
-        s.A2 = (double*)b; b += align256(std::max(m2 * P.R1cap, P.k1sq) * d);
+        s.A2 = (double*)b; b += align256(P.a2n() * d);
         s.Q2 = (double*)b; b += align256(m2 * P.k1cap * d);
         s.tau = (double*)b; b += align256((size_t)std::max(P.R1cap, P.R2cap) * d);
         s.J = (double*)b; b += align256(P.k1sq * d);
