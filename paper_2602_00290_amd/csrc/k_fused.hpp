@@ -61,7 +61,8 @@ constexpr int kOffSlots = 9;   // gather blocks 0..6, 7: rank-1 block, 8: always
 // operand and per-wave row-offset tables (the Gram reduction reuses the
 // space).
 __host__ __device__ inline size_t fused_lds_bytes(int nct, bool gram, int ngroups) {
-    const size_t op = (size_t)((ngroups + 1) & ~1) * nct * 64 * 16;   // group count padded to even
+    const int g2 = ((ngroups + 1) & ~1) < 4 ? 4 : ((ngroups + 1) & ~1);   // group count padded to even, >= 4
+    const size_t op = (size_t)g2 * nct * 64 * 16;
     const size_t offs = (size_t)kFusedWaves * 2 * kOffSlots * 16 * sizeof(int);
     const size_t main = op + offs;
     const size_t red = gram ? (size_t)(kFusedWaves / 2) * gram_blocks(nct) * 256 * sizeof(double) : 0;
@@ -123,9 +124,10 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
     const int KG = fn.n_gather * ldz;
     const int K = KG + fn.rw;
     const int T = (K + 15) >> 4;
-    const int T2 = (T + 1) & ~1;   // groups padded to even (the padding group has a zero operand)
+    // groups padded to even and to at least 4 (padding groups have a zero operand)
+    const int T2 = ((T + 1) & ~1) < 4 ? 4 : ((T + 1) & ~1);
     const int ldo = GRAM ? 0 : st->ldzn;
-    const float rldz = 1.0f / (float)ldz;
+    const unsigned magic = ((1u << 20) + (unsigned)ldz - 1u) / (unsigned)ldz;   // k0 / ldz = (k0 magic) >> 20 for k0 < 2^14
 
     f32x4v* Gs = reinterpret_cast<f32x4v*>(fused_lds);
     int* offs_all = reinterpret_cast<int*>(fused_lds + (size_t)T2 * NCT * 64 * 16);
@@ -187,20 +189,25 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
             offs[(rt * kOffSlots + q + 4) * 16 + m] = valid ? hi : zoff;
         }
     };
-    // A operand of K group t for both row tiles (one 16-byte load each, not
-    // yet scaled by d: the scale is applied when the group is consumed, so
-    // the load stays in flight)
-    auto load_a = [&](int t, f32x4v& a0, f32x4v& a1) {
-        // slot of this lane's 4 K values: gather block k0 / ldz, the rank-1
-        // block (7) or nothing (8)
+    // Element offsets of the A operand of K group t (both row tiles) from the
+    // offset table: gather block k0 / ldz, the rank-1 block (7) or nothing
+    // (8), plus the column within the block.  Branch-free; the table entries
+    // are LDS reads whose results are used one pipeline stage later.
+    const char* zb = reinterpret_cast<const char*>(Z);
+    auto addr_a = [&](int t, int& o0, int& o1, int& cc) {
         const int k0 = 16 * t + 4 * q;
-        const int jj = (int)(((float)k0 + 0.5f) * rldz);   // k0 / ldz, exact for these small integers
-        const int slot = k0 < KG ? jj : (k0 < K ? 7 : 8);
-        const int cc = k0 < KG ? k0 - jj * ldz : (k0 < K ? k0 - KG : 0);
-        const int o0 = offs[slot * 16 + m];
-        const int o1 = offs[(kOffSlots + slot) * 16 + m];
-        // 32-bit byte offsets from the uniform base (the workspace spans < 4 GiB)
-        const char* zb = reinterpret_cast<const char*>(Z);
+        const int jj = (int)(__umul24((unsigned)k0, magic) >> 20);
+        // selects written as masks (all ones / zero)
+        const int gm = -(int)(k0 < KG), rm = -(int)(k0 < K);
+        const int slot = (jj & gm) | ((8 + rm) & ~gm);
+        cc = ((k0 - (int)__umul24((unsigned)jj, (unsigned)ldz)) & gm) | ((k0 - KG) & rm & ~gm);
+        o0 = offs[slot * 16 + m];
+        o1 = offs[(kOffSlots + slot) * 16 + m];
+    };
+    // one 16-byte load per row tile, not yet scaled by d (the scale is applied
+    // when the group is consumed, so the load stays in flight); 32-bit byte
+    // offsets from the uniform base (the workspace spans < 4 GiB)
+    auto load_a = [&](int o0, int o1, int cc, f32x4v& a0, f32x4v& a1) {
         a0 = *reinterpret_cast<const f32x4v*>(zb + (unsigned)(o0 + cc) * 4u);
         a1 = *reinterpret_cast<const f32x4v*>(zb + (unsigned)(o1 + cc) * 4u);
     };
@@ -211,26 +218,42 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
 
     // Software pipeline over the flat sequence of (tile, group).  Two register
     // stages X and Y alternate (the K loop is unrolled by two, so no stage is
-    // ever copied: a copy would wait for its load): group t computes from
-    // one stage and refills it with group t + 2; the B operand of group t + 1
-    // is read from LDS while group t computes.  The next tile's first two
-    // groups are issued before this tile's epilogue, and its row-table
-    // entries a whole tile ahead.
+    // ever copied: a copy would wait for its load).  Group t is scaled out of
+    // its stage, the stage is refilled with group t + 2 at once (addresses
+    // from the previous step), the offsets of group t + 3 are read, and only
+    // then are group t's MFMAs issued; the B operand of group t + 1 is read
+    // from LDS meanwhile.  Groups t + 2, t + 3 >= T2 are the next tile's
+    // first groups: its offset table is written once this tile's last
+    // offsets have been read (after step T2 - 4), so the pipeline runs
+    // across tile boundaries.  Row-table entries are loaded a tile ahead.
     const f32x4v zero4 = (f32x4v){0.f, 0.f, 0.f, 0.f};
     float d0 = 0.f, d1 = 0.f, nd0 = 0.f, nd1 = 0.f;
     f32x4v x0 = zero4, x1 = zero4, y0 = zero4, y1 = zero4;
+    int po0 = zoff, po1 = zoff, pcc = 0;
     if (t_begin < t_end) {
         tile_rows(t_begin, pre_of(t_begin, 0), pre_of(t_begin, 1), d0, d1);
-        load_a(0, x0, x1);
-        load_a(1, y0, y1);
+        int o0, o1, cc;
+        addr_a(0, o0, o1, cc);
+        load_a(o0, o1, cc, x0, x1);
+        addr_a(1, o0, o1, cc);
+        load_a(o0, o1, cc, y0, y1);
+        addr_a(2, po0, po1, pcc);
     }
     f32x4v acc[2][NCT];
-    // (group t + 1 = T2 reads past the operand into the offset tables and
-    // groups t + 2 >= T load from the zero region: both unused, both in bounds)
+    // (group t + 1 = T2 reads past the operand into the offset tables: unused
+    // and in bounds)
     auto stage = [&](int t, f32x4v& s0, f32x4v& s1, f32x4v (&bc)[NCT], f32x4v (&bn)[NCT]) {
 #pragma unroll
         for (int c = 0; c < NCT; ++c) bn[c] = Gs[((t + 1) * NCT + c) * 64 + l];
         const f32x4v a0 = s0 * d0, a1 = s1 * d1;
+        // the stage registers are free once scaled: refill them before the
+        // MFMAs (the empty asm keeps the scaling ahead of the refill, so the
+        // refill can reuse the stage registers)
+        asm volatile("" ::"v"(a0), "v"(a1));
+        __builtin_amdgcn_sched_barrier(0);
+        load_a(po0, po1, pcc, s0, s1);
+        __builtin_amdgcn_sched_barrier(0);
+        addr_a(t + 3 < T2 ? t + 3 : t + 3 - T2, po0, po1, pcc);
 #pragma unroll
         for (int e = 0; e < 4; ++e)
 #pragma unroll
@@ -238,7 +261,6 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
                 acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[e], bc[c][e], acc[0][c], 0, 0, 0);
                 acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[e], bc[c][e], acc[1][c], 0, 0, 0);
             }
-        load_a(t + 2, s0, s1);
     };
     for (int tile = t_begin; tile < t_end; ++tile) {
         const bool more = tile + 1 < t_end;
@@ -253,12 +275,13 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
         for (int c = 0; c < NCT; ++c) bA[c] = Gs[c * 64 + l];
         for (int t = 0; t < T2; t += 2) {
             stage(t, x0, x1, bA, bB);
+            // the offsets of group T2 - 1 were read in step T2 - 4: the
+            // table now takes the next tile's rows (past the last tile the
+            // old rows stay; their loads are in bounds and unused)
+            if (t == T2 - 4 && more) tile_rows(tile + 1, na0, na1, nd0, nd1);
             stage(t + 1, y0, y1, bB, bA);
         }
         const int R0 = 32 * tile;
-        if (more) tile_rows(tile + 1, na0, na1, nd0, nd1);
-        load_a(0, x0, x1);
-        load_a(1, y0, y1);
 
         if constexpr (GRAM) {
 #pragma unroll
