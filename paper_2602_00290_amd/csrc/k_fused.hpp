@@ -56,13 +56,21 @@ struct FusedNbr {
 };
 
 constexpr int kOffSlots = 9;   // gather blocks 0..6, 7: rank-1 block, 8: always empty
+constexpr int kFusedStages = 2;   // A-operand groups in flight per wave (4 measured no faster)
+
+// K groups the fused kernels run for T groups of data: a multiple of the
+// stage count and at least two rounds of stages (padding groups have a zero
+// operand).
+__host__ __device__ inline int fused_groups(int T, int ns) {
+    const int g = (T + ns - 1) / ns * ns;
+    return g < 2 * ns ? 2 * ns : g;
+}
 
 // Bytes of dynamic LDS for k_fused_f32<NCT, GRAM> with `ngroups` K groups:
 // operand and per-wave row-offset tables (the Gram reduction reuses the
 // space).
 __host__ __device__ inline size_t fused_lds_bytes(int nct, bool gram, int ngroups) {
-    const int g2 = ((ngroups + 1) & ~1) < 4 ? 4 : ((ngroups + 1) & ~1);   // group count padded to even, >= 4
-    const size_t op = (size_t)g2 * nct * 64 * 16;
+    const size_t op = (size_t)fused_groups(ngroups, kFusedStages) * nct * 64 * 16;
     const size_t offs = (size_t)kFusedWaves * 2 * kOffSlots * 16 * sizeof(int);
     const size_t main = op + offs;
     const size_t red = gram ? (size_t)(kFusedWaves / 2) * gram_blocks(nct) * 256 * sizeof(double) : 0;
@@ -124,8 +132,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
     const int KG = fn.n_gather * ldz;
     const int K = KG + fn.rw;
     const int T = (K + 15) >> 4;
-    // groups padded to even and to at least 4 (padding groups have a zero operand)
-    const int T2 = ((T + 1) & ~1) < 4 ? 4 : ((T + 1) & ~1);
+    constexpr int NS = kFusedStages;
+    const int T2 = fused_groups(T, NS);
     const int ldo = GRAM ? 0 : st->ldzn;
     const unsigned magic = ((1u << 20) + (unsigned)ldz - 1u) / (unsigned)ldz;   // k0 / ldz = (k0 magic) >> 20 for k0 < 2^14
 
@@ -216,28 +224,31 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
 #pragma unroll
     for (int i = 0; i < (GRAM ? NB : 1); ++i) gacc[i] = (f64x4){0.0, 0.0, 0.0, 0.0};
 
-    // Software pipeline over the flat sequence of (tile, group).  Two register
-    // stages X and Y alternate (the K loop is unrolled by two, so no stage is
-    // ever copied: a copy would wait for its load).  Group t is scaled out of
-    // its stage, the stage is refilled with group t + 2 at once (addresses
-    // from the previous step), the offsets of group t + 3 are read, and only
-    // then are group t's MFMAs issued; the B operand of group t + 1 is read
-    // from LDS meanwhile.  Groups t + 2, t + 3 >= T2 are the next tile's
-    // first groups: its offset table is written once this tile's last
-    // offsets have been read (after step T2 - 4), so the pipeline runs
-    // across tile boundaries.  Row-table entries are loaded a tile ahead.
+    // Software pipeline over the flat sequence of (tile, group) with NS
+    // register stages in rotation (the K loop is unrolled by NS, so no stage
+    // is ever copied: a copy would wait for its load).  Group t is scaled out
+    // of its stage, the stage is refilled with group t + NS at once (address
+    // from the previous step), the offsets of group t + NS + 1 are read, and
+    // only then are group t's MFMAs issued; the B operand of group t + 1 is
+    // read from LDS meanwhile.  Groups past T2 are the next tile's first
+    // groups: its offset table is written once this tile's last offsets have
+    // been read (after step T2 - NS - 2), so the pipeline runs across tile
+    // boundaries.  Row-table entries are loaded a tile ahead.
     const f32x4v zero4 = (f32x4v){0.f, 0.f, 0.f, 0.f};
     float d0 = 0.f, d1 = 0.f, nd0 = 0.f, nd1 = 0.f;
-    f32x4v x0 = zero4, x1 = zero4, y0 = zero4, y1 = zero4;
+    f32x4v sa[NS], sb[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) sa[u] = sb[u] = zero4;
     int po0 = zoff, po1 = zoff, pcc = 0;
     if (t_begin < t_end) {
         tile_rows(t_begin, pre_of(t_begin, 0), pre_of(t_begin, 1), d0, d1);
-        int o0, o1, cc;
-        addr_a(0, o0, o1, cc);
-        load_a(o0, o1, cc, x0, x1);
-        addr_a(1, o0, o1, cc);
-        load_a(o0, o1, cc, y0, y1);
-        addr_a(2, po0, po1, pcc);
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            int o0, o1, cc;
+            addr_a(u, o0, o1, cc);
+            load_a(o0, o1, cc, sa[u], sb[u]);
+        }
+        addr_a(NS, po0, po1, pcc);
     }
     f32x4v acc[2][NCT];
     // (group t + 1 = T2 reads past the operand into the offset tables: unused
@@ -253,7 +264,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
         __builtin_amdgcn_sched_barrier(0);
         load_a(po0, po1, pcc, s0, s1);
         __builtin_amdgcn_sched_barrier(0);
-        addr_a(t + 3 < T2 ? t + 3 : t + 3 - T2, po0, po1, pcc);
+        addr_a(t + NS + 1 < T2 ? t + NS + 1 : t + NS + 1 - T2, po0, po1, pcc);
 #pragma unroll
         for (int e = 0; e < 4; ++e)
 #pragma unroll
@@ -273,13 +284,18 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
         f32x4v bA[NCT], bB[NCT];
 #pragma unroll
         for (int c = 0; c < NCT; ++c) bA[c] = Gs[c * 64 + l];
-        for (int t = 0; t < T2; t += 2) {
-            stage(t, x0, x1, bA, bB);
-            // the offsets of group T2 - 1 were read in step T2 - 4: the
-            // table now takes the next tile's rows (past the last tile the
-            // old rows stay; their loads are in bounds and unused)
-            if (t == T2 - 4 && more) tile_rows(tile + 1, na0, na1, nd0, nd1);
-            stage(t + 1, y0, y1, bB, bA);
+        for (int t = 0; t < T2; t += NS) {
+#pragma unroll
+            for (int u = 0; u < NS; ++u) {
+                if (u & 1)
+                    stage(t + u, sa[u], sb[u], bB, bA);
+                else
+                    stage(t + u, sa[u], sb[u], bA, bB);
+                // the offsets of group T2 - 1 were read in step T2 - NS - 2:
+                // the table now takes the next tile's rows (past the last
+                // tile the old rows stay; their loads are in bounds and unused)
+                if (t + u == T2 - NS - 2 && more) tile_rows(tile + 1, na0, na1, nd0, nd1);
+            }
         }
         const int R0 = 32 * tile;
 

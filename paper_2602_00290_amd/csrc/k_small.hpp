@@ -728,6 +728,23 @@ __device__ __forceinline__ int delta_rank(const double* s, const int* perm, int 
     return r;
 }
 
+// Exact x / d and x % d for 0 <= x < 2^22 (the runtime divisors of the
+// small-core kernels are uniform and small; a plain integer division costs
+// tens of VALU instructions).  x times the FP32 reciprocal of d is within
+// (x / d) 2^-22 < 1 of x / d, so its truncation is off by at most one, which
+// the remainder test corrects.
+struct FastDiv {
+    float rcp;
+    int d;
+    __device__ explicit FastDiv(int dd) : rcp(__builtin_amdgcn_rcpf((float)dd)), d(dd) {}
+    __device__ int q(int x) const {
+        const int q0 = (int)((float)x * rcp);
+        const int r = x - __mul24(q0, d);
+        return q0 + (r >= d ? 1 : 0) - (r < 0 ? 1 : 0);
+    }
+    __device__ int r(int x) const { return x - __mul24(q(x), d); }
+};
+
 // ---------------------------------------------------------------------------
 // prep: right-to-left orthogonalisation of the small cores of the TT sum
 // ---------------------------------------------------------------------------
@@ -766,33 +783,53 @@ __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevSt
     const bool th_id = R1 >= m2;
     const int k1 = th_id ? m2 : R1;
     const int ldb = ld_for_rank(k1);
+    const FastDiv dnp(npn), dr1(r1), dr2(r2), dk2(k2), dm2(m2), dk1(k1), dldz(ldz), dldb(ldb);
+
+    // the angular core and the per-node factor tables in LDS where they fit
+    // (every entry below is read many times)
+    const double* thv = Th;
+    const double* gtv = gtab;
+    const double* htv = htab;
+    {
+        const int nth = r1 * nt * r2, ngt = (1 + g.n_terms) * nt, nht = (1 + g.n_terms) * npn;
+        double* a = cv.take((size_t)nth, nullptr);
+        double* b = cv.take((size_t)ngt, nullptr);
+        double* c = cv.take((size_t)nht, nullptr);
+        for (int i = threadIdx.x; a && i < nth; i += blockDim.x) a[i] = Th[i];
+        for (int i = threadIdx.x; b && i < ngt; i += blockDim.x) b[i] = gtab[i];
+        for (int i = threadIdx.x; c && i < nht; i += blockDim.x) c[i] = htab[i];
+        if (a) thv = a;
+        if (b) gtv = b;
+        if (c) htv = c;
+        __syncthreads();
+    }
 
     // 1. L_Phi (R2 x k2, row-major) and Q_Phi (k2 x N_phi)
     double* Lphi = cv.take((size_t)R2 * k2, sc.Q1 + (size_t)npn * npn);
     if (phi_id) {
         for (int idx = threadIdx.x; idx < R2 * npn; idx += blockDim.x) {
-            const int col = idx / npn, p = idx % npn;
+            const int col = dnp.q(idx), p = idx - col * npn;
             double v;
             if (col < nrb * r2) {
-                const int t = col / r2, b = col % r2;
-                v = Ph[(size_t)b * npn + p] * htab[op.rfac[t] * npn + p];
+                const int t = dr2.q(col), b = col - t * r2;
+                v = Ph[(size_t)b * npn + p] * htv[op.rfac[t] * npn + p];
             } else {
-                v = htab[op.r1fac[col - nrb * r2] * npn + p];
+                v = htv[op.r1fac[col - nrb * r2] * npn + p];
             }
             Lphi[idx] = v;
         }
-        for (int idx = threadIdx.x; idx < npn * npn; idx += blockDim.x) QPh[idx] = (idx / npn == idx % npn) ? 1.0 : 0.0;
+        for (int idx = threadIdx.x; idx < npn * npn; idx += blockDim.x) QPh[idx] = (dnp.q(idx) == dnp.r(idx)) ? 1.0 : 0.0;
     } else {
         double* A1 = cv.take((size_t)npn * R2, sc.A1);
         double* Q1 = cv.take((size_t)npn * k2, sc.Q1);
         for (int idx = threadIdx.x; idx < npn * R2; idx += blockDim.x) {
-            const int p = idx % npn, col = idx / npn;
+            const int col = dnp.q(idx), p = idx - col * npn;
             double v;
             if (col < nrb * r2) {
-                const int t = col / r2, b = col % r2;
-                v = Ph[(size_t)b * npn + p] * htab[op.rfac[t] * npn + p];
+                const int t = dr2.q(col), b = col - t * r2;
+                v = Ph[(size_t)b * npn + p] * htv[op.rfac[t] * npn + p];
             } else {
-                v = htab[op.r1fac[col - nrb * r2] * npn + p];
+                v = htv[op.r1fac[col - nrb * r2] * npn + p];
             }
             A1[p + (size_t)col * npn] = v;
         }
@@ -800,11 +837,11 @@ __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevSt
         block_householder_qr(A1, npn, npn, R2, sc.tau, red);
         block_form_q(A1, npn, npn, k2, sc.tau, Q1, npn);
         for (int idx = threadIdx.x; idx < k2 * npn; idx += blockDim.x) {
-            const int c = idx / npn, p = idx % npn;
+            const int c = dnp.q(idx), p = idx - c * npn;
             QPh[(size_t)c * npn + p] = Q1[p + (size_t)c * npn];
         }
         for (int idx = threadIdx.x; idx < R2 * k2; idx += blockDim.x) {
-            const int col = idx / k2, c = idx % k2;
+            const int col = dk2.q(idx), c = idx - col * k2;
             Lphi[idx] = (c <= col) ? A1[c + (size_t)col * npn] : 0.0;
         }
     }
@@ -813,40 +850,53 @@ __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevSt
     auto theta_p = [&](int row, int l, int c) -> double {
         double v = 0.0;
         if (row < nrb * r1) {
-            const int t = row / r1, a = row % r1;
-            const double* th = Th + ((size_t)a * nt + l) * r2;
+            const int t = dr1.q(row), a = row - t * r1;
+            const double* th = thv + ((size_t)a * nt + l) * r2;
             const double* lp = Lphi + (size_t)(t * r2) * k2 + c;
             for (int b = 0; b < r2; ++b) v += th[b] * lp[(size_t)b * k2];
-            v *= gtab[op.rfac[t] * nt + l];
+            v *= gtv[op.rfac[t] * nt + l];
         } else {
             const int q = row - nrb * r1;
-            v = gtab[op.r1fac[q] * nt + l] * Lphi[(size_t)(nrb * r2 + q) * k2 + c];
+            v = gtv[op.r1fac[q] * nt + l] * Lphi[(size_t)(nrb * r2 + q) * k2 + c];
         }
         return v;
     };
+    // L_Theta (R1 x k1) is only read here: LDS where it fits
+    double* LT = LTh;
+    int ldL = ldl;
     if (th_id) {
-        for (int idx = threadIdx.x; idx < R1 * m2; idx += blockDim.x) {
-            const int row = idx / m2, i = idx % m2;
-            LTh[(size_t)row * ldl + i] = theta_p(row, i / k2, i % k2);
+        if (double* a = cv.take((size_t)R1 * k1, nullptr)) {
+            LT = a;
+            ldL = k1;
         }
-        for (int idx = threadIdx.x; idx < m2 * m2; idx += blockDim.x) QTh[idx] = (idx / m2 == idx % m2) ? 1.0 : 0.0;
+        for (int idx = threadIdx.x; idx < R1 * m2; idx += blockDim.x) {
+            const int row = dm2.q(idx), i = idx - row * m2;
+            const int l = dk2.q(i);
+            LT[(size_t)row * ldL + i] = theta_p(row, l, i - l * k2);
+        }
+        for (int idx = threadIdx.x; idx < m2 * m2; idx += blockDim.x) QTh[idx] = (dm2.q(idx) == dm2.r(idx)) ? 1.0 : 0.0;
     } else {
         double* A2 = cv.take((size_t)m2 * R1, sc.A2);
         double* Q2 = cv.take((size_t)m2 * k1, sc.Q2);
         for (int idx = threadIdx.x; idx < m2 * R1; idx += blockDim.x) {
-            const int rowA = idx % m2, row = idx / m2;
-            A2[rowA + (size_t)row * m2] = theta_p(row, rowA / k2, rowA % k2);
+            const int row = dm2.q(idx), rowA = idx - row * m2;
+            const int l = dk2.q(rowA);
+            A2[rowA + (size_t)row * m2] = theta_p(row, l, rowA - l * k2);
         }
         __syncthreads();
         block_householder_qr(A2, m2, m2, R1, sc.tau, red);
         block_form_q(A2, m2, m2, k1, sc.tau, Q2, m2);
         for (int idx = threadIdx.x; idx < k1 * m2; idx += blockDim.x) {
-            const int i = idx / m2, rowA = idx % m2;
+            const int i = dm2.q(idx), rowA = idx - i * m2;
             QTh[(size_t)i * m2 + rowA] = Q2[rowA + (size_t)i * m2];
         }
+        if (double* a = cv.take((size_t)R1 * k1, nullptr)) {
+            LT = a;
+            ldL = k1;
+        }
         for (int idx = threadIdx.x; idx < R1 * k1; idx += blockDim.x) {
-            const int row = idx / k1, i = idx % k1;
-            LTh[(size_t)row * ldl + i] = (i <= row) ? A2[i + (size_t)row * m2] : 0.0;
+            const int row = dk1.q(idx), i = idx - row * k1;
+            LT[(size_t)row * ldL + i] = (i <= row) ? A2[i + (size_t)row * m2] : 0.0;
         }
     }
     __syncthreads();
@@ -856,32 +906,33 @@ __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevSt
         double v = 0.0;
         if (col < k1) {
             if (row < op.n_gather * ldz) {
-                const int j = row / ldz, a = row % ldz;
+                const int j = dldz.q(row), a = row - j * ldz;
                 if (a < r1) {
                     for (int t = 0; t < nrb; ++t) {
-                        const double l = LTh[(size_t)(t * r1 + a) * ldl + col];
+                        const double l = LT[(size_t)(t * r1 + a) * ldL + col];
                         if (j == 0) v += op.rcoef0[t] * l;
                         if (op.rshift[t] == j) v += op.rcoef[t] * l;
                     }
                 }
             } else {
                 const int q = row - op.n_gather * ldz;
-                v = LTh[(size_t)(nrb * r1 + q) * ldl + col];
+                v = LT[(size_t)(nrb * r1 + q) * ldL + col];
             }
         }
         return v;
     };
     for (int idx = threadIdx.x; idx < grows * ldb; idx += blockDim.x) {
-        const int row = idx / ldb, col = idx % ldb;
+        const int row = dldb.q(idx), col = idx - row * ldb;
         Gop[(size_t)row * ldb + col] = (TC)gval(row, col);
     }
     if (Gsw) {
         // the same operand in the lane order of the fused MFMA contraction:
         // slot ((t * nct + c) * 64 + lane) * 4 + e holds G[16 t + 4 (lane / 16) + e][16 c + lane % 16]
         const int ng = (grows + 15) / 16;
+        const FastDiv dnct(nct);
         for (int idx = threadIdx.x; idx < ng * nct * 256; idx += blockDim.x) {
             const int e = idx & 3, ln = (idx >> 2) & 63, tc = idx >> 8;
-            const int c = tc % nct, t = tc / nct;
+            const int t = dnct.q(tc), c = tc - t * nct;
             const int row = 16 * t + 4 * (ln >> 4) + e, col = 16 * c + (ln & 15);
             Gsw[idx] = (row < grows && col < ldb) ? (TC)gval(row, col) : (TC)0;
         }
@@ -949,10 +1000,11 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
     int* p1 = sc.perm;
     long long tph[8];
     int sw1 = 0, sw2 = 0;
+    const FastDiv dkp(kp), dk1(k1), dk2(k2), dm2(m2), dnt(nt), dnp(npn);
     tph[0] = wall_clock64();
     // stage the input (R_B or G, row-major in global) column-major into T; W0
     for (int idx = threadIdx.x; idx < kp * kp; idx += blockDim.x) {
-        const int j = idx % kp, i = idx / kp;      // coalesced along rows of the input
+        const int i = dkp.q(idx), j = idx - i * kp;      // coalesced along rows of the input
         T[i + (size_t)j * ld] = (i < k1 && j < k1) ? RB[(size_t)i * ldr + j] : 0.0;
         W[j + (size_t)i * ld] = (i < k1 && j < k1) ? (warm ? sc.Wkeep[j + (size_t)i * k1] : (i == j ? 1.0 : 0.0))
                                                    : (i == j ? 1.0 : 0.0);
@@ -961,7 +1013,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
     if (!gram) {
         // J = R_B W (R_B upper triangular)
         for (int idx = threadIdx.x; idx < kp * kp; idx += blockDim.x) {
-            const int i = idx % kp, j = idx / kp;
+            const int j = dkp.q(idx), i = idx - j * kp;
             double acc = 0.0;
             if (warm) {
                 for (int k = i; k < k1; ++k) acc += T[i + (size_t)k * ld] * W[k + (size_t)j * ld];
@@ -997,7 +1049,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
             __syncthreads();
         }
         for (int idx = threadIdx.x; idx < kp * kp; idx += blockDim.x) {
-            const int i = idx % kp, j = idx / kp;
+            const int j = dkp.q(idx), i = idx - j * kp;
             J[i + (size_t)j * ld] = T[i + (size_t)j * ld];
         }
         __syncthreads();
@@ -1023,11 +1075,12 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
     const int ldb = st->ldb;
     // sorted V -> Wkeep (next warm start); V_r -> Vout in the contraction precision
     for (int idx = threadIdx.x; idx < k1 * k1; idx += blockDim.x) {
-        const int i = idx % k1, a = idx / k1;
+        const int a = dk1.q(idx), i = idx - a * k1;
         sc.Wkeep[idx] = W[i + (size_t)p1[a] * ld];
     }
+    const FastDiv dldzn(ldzn);
     for (int idx = threadIdx.x; idx < ldb * ldzn; idx += blockDim.x) {
-        const int i = idx / ldzn, a = idx % ldzn;
+        const int i = dldzn.q(idx), a = idx - i * ldzn;
         double v = 0.0;
         if (i < k1 && a < r1n) v = W[i + (size_t)p1[a] * ld];
         Vout[(size_t)i * ldzn + a] = (TC)v;
@@ -1045,11 +1098,11 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
     // Theta'' = V_r^T Q_Theta from the sorted V (Wkeep, complete after the barrier)
     __syncthreads();
     block_mm_tiled(r1n, m2, k1, sc.Wkeep, k1, 1, QTh, m2, 1, sc.Th2, m2, 1);
-    for (int idx = threadIdx.x; idx < k2 * k2; idx += blockDim.x) V2[idx] = (idx % k2 == idx / k2) ? 1.0 : 0.0;
+    for (int idx = threadIdx.x; idx < k2 * k2; idx += blockDim.x) V2[idx] = (dk2.r(idx) == dk2.q(idx)) ? 1.0 : 0.0;
     __syncthreads();
     for (int idx = threadIdx.x; idx < r1n * m2; idx += blockDim.x) {
-        const int a = idx / m2, col = idx % m2;
-        const int l = col / k2, c = col % k2;
+        const int a = dm2.q(idx), col = idx - a * m2;
+        const int l = dk2.q(col), c = col - l * k2;
         C2[(a * nt + l) + (size_t)c * ldc] = s1[p1[a]] * sc.Th2[idx];
     }
     __syncthreads();
@@ -1062,7 +1115,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
         const int ldh = k2 | 1;
         double* H = cv.take((size_t)k2 * ldh, sc.A2);
         for (int idx = threadIdx.x; idx < k2 * k2; idx += blockDim.x) {
-            const int c = idx % k2, e = idx / k2;
+            const int e = dk2.q(idx), c = idx - e * k2;
             if (c > e) continue;
             const double* x = C2 + (size_t)c * ldc;
             const double* y = C2 + (size_t)e * ldc;
@@ -1094,16 +1147,17 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
     if (threadIdx.x == 0) sh_r[1] = delta_rank(s2, p2, k2, delta, cap2 < k2 ? cap2 : k2);
     __syncthreads();
     const int r2n = sh_r[1];
+    const FastDiv dr2n(r2n);
     for (int idx = threadIdx.x; idx < r1n * nt * r2n; idx += blockDim.x) {
-        const int q = idx % r2n, al = idx / r2n;
-        const int a = al / nt, l = al % nt;
+        const int al = dr2n.q(idx), q = idx - al * r2n;
+        const int a = dnt.q(al), l = al - a * nt;
         const int jq = p2[q];
         double acc = 0.0;
         for (int c = 0; c < k2; ++c) acc += sc.Th2[(size_t)a * m2 + l * k2 + c] * V2[c + (size_t)jq * k2];
         ThOut[idx] = acc;
     }
     for (int idx = threadIdx.x; idx < r2n * npn; idx += blockDim.x) {
-        const int q = idx / npn, p = idx % npn;
+        const int q = dnp.q(idx), p = idx - q * npn;
         const int jq = p2[q];
         double acc = 0.0;
         for (int c = 0; c < k2; ++c) acc += V2[c + (size_t)jq * k2] * QPh[(size_t)c * npn + p];
