@@ -785,6 +785,19 @@ __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevSt
     const int ldb = ld_for_rank(k1);
     const FastDiv dnp(npn), dr1(r1), dr2(r2), dk2(k2), dm2(m2), dk1(k1), dldz(ldz), dldb(ldb);
 
+    // the operator's block tables in LDS: they are indexed per lane below, and
+    // a per-lane index into the kernel arguments is a vector memory load
+    __shared__ int s_rfac[kMaxBlocks], s_rshift[kMaxBlocks], s_r1fac[kMaxBlocks];
+    __shared__ double s_rcoef0[kMaxBlocks], s_rcoef[kMaxBlocks];
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < kMaxBlocks; ++i) {
+            s_rfac[i] = op.rfac[i];
+            s_rshift[i] = op.rshift[i];
+            s_r1fac[i] = op.r1fac[i];
+            s_rcoef0[i] = op.rcoef0[i];
+            s_rcoef[i] = op.rcoef[i];
+        }
+    }
     // the angular core and the per-node factor tables in LDS where they fit
     // (every entry below is read many times)
     const double* thv = Th;
@@ -812,9 +825,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevSt
             double v;
             if (col < nrb * r2) {
                 const int t = dr2.q(col), b = col - t * r2;
-                v = Ph[(size_t)b * npn + p] * htv[op.rfac[t] * npn + p];
+                v = Ph[(size_t)b * npn + p] * htv[s_rfac[t] * npn + p];
             } else {
-                v = htv[op.r1fac[col - nrb * r2] * npn + p];
+                v = htv[s_r1fac[col - nrb * r2] * npn + p];
             }
             Lphi[idx] = v;
         }
@@ -827,9 +840,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevSt
             double v;
             if (col < nrb * r2) {
                 const int t = dr2.q(col), b = col - t * r2;
-                v = Ph[(size_t)b * npn + p] * htv[op.rfac[t] * npn + p];
+                v = Ph[(size_t)b * npn + p] * htv[s_rfac[t] * npn + p];
             } else {
-                v = htv[op.r1fac[col - nrb * r2] * npn + p];
+                v = htv[s_r1fac[col - nrb * r2] * npn + p];
             }
             A1[p + (size_t)col * npn] = v;
         }
@@ -854,10 +867,10 @@ __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevSt
             const double* th = thv + ((size_t)a * nt + l) * r2;
             const double* lp = Lphi + (size_t)(t * r2) * k2 + c;
             for (int b = 0; b < r2; ++b) v += th[b] * lp[(size_t)b * k2];
-            v *= gtv[op.rfac[t] * nt + l];
+            v *= gtv[s_rfac[t] * nt + l];
         } else {
             const int q = row - nrb * r1;
-            v = gtv[op.r1fac[q] * nt + l] * Lphi[(size_t)(nrb * r2 + q) * k2 + c];
+            v = gtv[s_r1fac[q] * nt + l] * Lphi[(size_t)(nrb * r2 + q) * k2 + c];
         }
         return v;
     };
@@ -910,8 +923,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevSt
                 if (a < r1) {
                     for (int t = 0; t < nrb; ++t) {
                         const double l = LT[(size_t)(t * r1 + a) * ldL + col];
-                        if (j == 0) v += op.rcoef0[t] * l;
-                        if (op.rshift[t] == j) v += op.rcoef[t] * l;
+                        if (j == 0) v += s_rcoef0[t] * l;
+                        if (s_rshift[t] == j) v += s_rcoef[t] * l;
                     }
                 }
             } else {
