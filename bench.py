@@ -19,7 +19,7 @@ committed counter summary (null when the kernel source has changed since).
 sample of the same workload.
 
 Other modes (for profiling runs; they print one line and exit):
-  --mode probe        one solve of the workload for `--probe-steps` steps
+  --mode probe        one solve of `--probe-workload` (plane2d or clumps3d) for `--probe-steps` steps
   --mode copy         a plain device-to-device copy of `--copy-mb` MiB (counter calibration)
   --mode served       only the served request mix (capacity, then Poisson arrivals)
   --mode pmc-summary  turn rocprofv3 counter CSVs (--pmc-dir) into profiles/traffic_plane2d.json
@@ -173,10 +173,12 @@ def mode_probe(args):
     import torch
     import paper_2602_00290_amd as tt
     import tt_inputs as ti
-    s = tt.Solver(ti.plane2d())
+    prob = ti.plane2d() if args.probe_workload == "plane2d" else ti.clumps3d(precision=ti.PREC_BF16X)
+    s = tt.Solver(prob)
     st = s.solve(args.probe_steps)
     torch.cuda.synchronize()
-    print(json.dumps({"mode": "probe", "steps": args.probe_steps, "ranks": [st["r1"], st["r2"]]}), flush=True)
+    print(json.dumps({"mode": "probe", "workload": args.probe_workload, "steps": args.probe_steps,
+                      "ranks": [st["r1"], st["r2"]]}), flush=True)
 
 
 def _pmc_rows(path, counter):
@@ -248,6 +250,8 @@ def main():
                     help="GPU_MAX_HW_QUEUES for this process (0: keep the environment's)")
     ap.add_argument("--mode", default="bench", choices=["bench", "probe", "copy", "pmc-summary", "served"])
     ap.add_argument("--probe-steps", type=int, default=64)
+    ap.add_argument("--probe-workload", default="plane2d", choices=["plane2d", "clumps3d"],
+                    help="probe workload: plane2d (FP32) or clumps3d (64^3 cells, 64 groups, split BF16)")
     ap.add_argument("--copy-mb", type=int, default=512)
     ap.add_argument("--pmc-dir", default=os.path.join(ROOT, "gpurun_out", "traffic"))
     ap.add_argument("--plain-fp64", type=int, default=1, help="also time the plain FP64 TT path on seed 0")
