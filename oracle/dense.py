@@ -7,6 +7,17 @@ The discretisation (Section 2.1 "Numerics"; operator form in Appendix A):
 forward-Euler upwind streaming, then the backward-Euler operator-split source
 update with zero scattering, density 1 and fixed temperature,
 I^{m+1} = (I* + c dt kappa eps) / (1 + c dt kappa).
+
+With a heat capacity C_v = rho c_v > 0 the medium temperature is coupled
+(Section 2.1, the coupled source stage): per cell, the stage temperature T+
+is the root of the scalar equation the paper writes for it,
+    T^m - T+ - sum_g (4 pi dt kappa_g / C_v) (eps_g(T+) - J_g^{m+1}(T+)) = 0,
+with J^{m+1} = (J* / (c dt) + kappa eps(T+)) / (1 / (c dt) + kappa) the
+angle-mean of the implicitly updated intensity (J* that of the intensity
+after streaming); the intensity is updated with eps(T+), and the new medium
+temperature follows from total-energy conservation,
+    C_v (T^{m+1} - T^m) = (4 pi / c) sum_g (J*_g - J_g^{m+1}),
+J = (1 / 4 pi) sum_lp w_l w_p I (the quadrature weights sum to 4 pi).
 """
 from __future__ import annotations
 
@@ -16,6 +27,8 @@ import subprocess
 import sys
 
 import numpy as np
+
+from scipy import optimize
 
 from . import planck
 
@@ -102,8 +115,11 @@ def ghost_values(prob) -> np.ndarray:
 
 
 def initial_dense(prob) -> np.ndarray:
-    """Isotropic Planck state at the medium temperature, shape (N_X*N_nu, N_theta, N_phi)."""
-    eps = emission(prob).reshape(-1)
+    """Isotropic Planck state, shape (N_X*N_nu, N_theta, N_phi): at the initial
+    radiation temperature when the problem gives one, else at the medium
+    temperature."""
+    T_rad = getattr(prob, "T_rad0", None)
+    eps = (emission(prob) if T_rad is None else planck.emission_field(prob.edges, T_rad)).reshape(-1)
     return np.broadcast_to(eps[:, None, None], (prob.M, prob.n_theta, prob.n_phi)).copy()
 
 
@@ -167,3 +183,75 @@ def energy(prob, I: np.ndarray) -> float:
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+# ---------------------------------------------------------------------------
+# coupled medium temperature (Section 2.1, coupled source stage)
+# ---------------------------------------------------------------------------
+
+def mean_intensity(prob, I: np.ndarray) -> np.ndarray:
+    """(N_X, N_nu) angle means J = (1 / 4 pi) sum_lp w_l w_p I."""
+    w = np.outer(prob.w_theta, prob.w_phi)
+    J = np.einsum("klp,lp->k", I, w) / (4.0 * np.pi)
+    return J.reshape(prob.n_x, prob.n_groups)
+
+
+def stage_temperature(prob, T_m: float, J_star: np.ndarray, kappa: np.ndarray, dt: float) -> float:
+    """Root T+ of the paper's scalar equation for one cell (written with
+    J^{m+1}(T+) spelled out), by Brent's method on a sign-changing bracket.
+    The left side falls strictly with T+ (eps_g rises with T); at T+ = 0 it
+    is T^m + sum_g (4 pi dt kappa_g / C_v) J*_g d_g >= 0, and at
+    T_hi = that value it is <= 0."""
+    C = float(prob.heat_capacity)
+    cdt = prob.c * dt
+
+    def f(T):
+        eps = planck.group_emission_quad(prob.edges, T)
+        J_new = (J_star / cdt + kappa * eps) / (1.0 / cdt + kappa)
+        return T_m - T - float(np.sum(4.0 * np.pi * dt * kappa / C * (eps - J_new)))
+
+    hi = T_m + float(np.sum(4.0 * np.pi * dt * kappa / C * J_star / (1.0 + cdt * kappa)))
+    hi = max(hi, T_m, 1e-300)
+    f_hi = f(hi)
+    while f_hi > 0.0:   # the bracket end rounded below the root (tiny coupling terms)
+        hi = 2.0 * hi
+        f_hi = f(hi)
+    if f_hi == 0.0:
+        return hi
+    f_lo = f(0.0)
+    if f_lo <= 0.0:
+        return 0.0
+    return optimize.brentq(f, 0.0, hi, xtol=1e-300, rtol=8.9e-16, maxiter=500)
+
+
+def coupled_source(prob, I_star: np.ndarray, T: np.ndarray):
+    """Coupled source stage on the dense intensity after streaming: returns
+    (I^{m+1}, T^{m+1})."""
+    dt = time_step(prob)
+    kap = kappa_field(prob)                      # (N_X, N_nu)
+    J_star = mean_intensity(prob, I_star)
+    T = np.asarray(T, dtype=float)
+    eps = np.zeros_like(kap)
+    for x in range(prob.n_x):
+        Tp = stage_temperature(prob, float(T[x]), J_star[x], kap[x], dt)
+        eps[x] = planck.group_emission_quad(prob.edges, Tp)
+    a = (prob.c * dt * kap).reshape(-1)
+    I_new = (I_star + (a * eps.reshape(-1))[:, None, None]) / (1.0 + a)[:, None, None]
+    J_new = mean_intensity(prob, I_new)
+    T_new = T + 4.0 * np.pi / (prob.c * float(prob.heat_capacity)) * np.sum(J_star - J_new, axis=1)
+    return I_new, T_new
+
+
+def march_coupled(prob, I0: np.ndarray, T0, n_steps: int, n_threads: int = 0):
+    """n_steps of streaming + coupled source; returns (I, T)."""
+    I = np.ascontiguousarray(I0, dtype=np.float64).copy()
+    T = np.asarray(T0, dtype=float).copy()
+    for _ in range(n_steps):
+        I, T = coupled_source(prob, transport(prob, I, n_threads), T)
+    return I, T
+
+
+def total_energy(prob, I: np.ndarray, T) -> float:
+    """Radiation plus medium energy: dV (sum_k (1 / c) sum_lp w I + C_v sum_x T)."""
+    dV = float(np.prod([prob.extent[d] / prob.n_cells[d] for d in range(prob.dim)]))
+    return energy(prob, I) / prob.c + dV * float(prob.heat_capacity) * float(np.sum(T))

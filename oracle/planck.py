@@ -14,6 +14,9 @@ a = 8 pi^5 / 15 (the gray limit stated right after the Planck function).
 
 The integral is evaluated with mpmath's tanh-sinh quadrature at 60 digits,
 an implementation independent of the library's series evaluation.
+`group_emission_quad` evaluates the same integrals in double precision with
+QUADPACK (scipy.integrate.quad); it serves the coupled-temperature oracle,
+which needs many evaluations at varying T.
 """
 from __future__ import annotations
 
@@ -22,6 +25,7 @@ import math
 
 import mpmath
 import numpy as np
+from scipy import integrate
 
 _DPS = 60
 
@@ -81,3 +85,33 @@ def emission_field(edges, T_cell) -> np.ndarray:
 def gray_emission(T: float) -> float:
     """Sum over all groups: 2 pi^4 T^4 / 15 (the single-group limit)."""
     return 2.0 * math.pi ** 4 * T ** 4 / 15.0
+
+
+def _x3_over_expm1(x: float) -> float:
+    """x^3 / (e^x - 1), written as x^3 e^{-x} / (1 - e^{-x}) (no overflow)."""
+    if x == 0.0:
+        return 0.0
+    return x ** 3 * math.exp(-x) / -math.expm1(-x)
+
+
+def group_emission_quad(edges, T: float) -> np.ndarray:
+    """eps_g(T) for every group by double-precision adaptive quadrature
+    (QUADPACK), h = k = c = 1; the integrand x^3 / (e^x - 1) is integrated
+    over each group's [nu_{g-1} / T, nu_g / T), split at x = 1, 4, 16, 64
+    and cut at x = 800 (beyond which it underflows)."""
+    edges = np.asarray(edges, dtype=float)
+    G = len(edges) - 1
+    out = np.zeros(G)
+    if T <= 0.0:
+        return out
+    for g in range(G):
+        xa = edges[g] / T
+        xb = min(edges[g + 1] / T, 800.0)
+        if not xb > xa:
+            continue
+        pts = [xa] + [c for c in (1.0, 4.0, 16.0, 64.0) if xa < c < xb] + [xb]
+        tot = 0.0
+        for lo, hi in zip(pts[:-1], pts[1:]):
+            tot += integrate.quad(_x3_over_expm1, lo, hi, epsabs=0.0, epsrel=1e-13, limit=200)[0]
+        out[g] = 2.0 * T ** 4 * tot
+    return out

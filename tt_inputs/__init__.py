@@ -66,6 +66,8 @@ class Problem:
     round_method: int = 2        # 0: Householder QR, 1: Gram, 2: QR for FP64 data, Gram otherwise
     n_steps: int = 1
     seed: int = 0
+    heat_capacity: float = 0.0   # rho c_v per volume; 0: fixed medium temperature, > 0: coupled temperature
+    T_rad0: Optional[np.ndarray] = None   # (N_X,) initial radiation temperature (None: T_cell)
 
     # ----- derived sizes (pure bookkeeping) -----
     @property
@@ -245,6 +247,37 @@ def plane2d(n=128, n_groups=32, n_theta=8, n_phi=8, T=0.1, T_b=1.0, tol=1e-6, ra
         kappa_scale=nu_power_scale(edges), T_cell=np.full(n * n, float(T)), mu=mu, w_theta=wt,
         phi=phi, w_phi=wp, bc=(BC_INFLOW_PLANCK, 0, 0, 0, 0, 0), bc_T=(T_b, 0, 0, 0, 0, 0),
         cfl=cfl, tol=tol, rank_cap=rank_cap, precision=precision, n_steps=n_steps, seed=seed)
+
+
+# Planck and Boltzmann constants (cgs) to express frequency edges given in Hz
+# as h nu / k_B in temperature units, and the radiation constant of the
+# emission units (h = k = 1): (4 pi / c) sum_g eps_g(T) = a T^4, a = 8 pi^5 / (15 c).
+H_CGS = 6.62607015e-27
+KB_CGS = 1.380649e-16
+
+
+def radiation_constant(c: float = 1.0) -> float:
+    return 8.0 * math.pi ** 5 / (15.0 * c)
+
+
+def thermal_relax(n_cells=1, n_theta=2, c_v=8.0, T=10.0, T_r=1.0, kappas=(10.0, 1.0, 0.1), k_hz=1.5e11,
+                  cfl=0.1, t_final=40.0, tol=1e-12, rank_cap=8, precision=PREC_FP64):
+    """Thermal relaxation with three groups (Section 4): periodic homogeneous
+    slab of unit cells, rho = 1, c_v = 8 in units where a = c = 1 (so the
+    heat capacity here is 8 a), medium at T = 10, radiation initially Planck
+    at T_r = 1, group edges nu_1 = k and nu_2 = 2 k (k = 1.5e11 Hz) and group
+    opacities 10, 1, 0.1."""
+    nu1 = H_CGS * k_hz / KB_CGS
+    edges = np.array([0.0, nu1, 2.0 * nu1, np.inf])
+    mu, wt, phi, wp = _angles(1, n_theta, 1, gl=True)
+    dt = cfl   # unit cells and c = 1
+    return Problem(
+        name="thermal_relax", dim=1, n_cells=(n_cells, 1, 1), extent=(float(n_cells), 1.0, 1.0), edges=edges,
+        kappa0=np.ones(n_cells), kappa_scale=np.asarray(kappas, float), T_cell=np.full(n_cells, float(T)),
+        mu=mu, w_theta=wt, phi=phi, w_phi=wp, bc=(BC_PERIODIC, BC_PERIODIC, 0, 0, 0, 0),
+        bc_T=(0, 0, 0, 0, 0, 0), c=1.0, cfl=cfl, tol=tol, rank_cap=rank_cap, precision=precision,
+        n_steps=int(round(t_final / dt)), heat_capacity=c_v * radiation_constant(1.0),
+        T_rad0=np.full(n_cells, float(T_r)))
 
 
 C3_CLUMPS = (((0.35, 0.5, 0.5), 0.1), ((0.65, 0.4, 0.6), 0.08))
