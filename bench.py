@@ -255,6 +255,8 @@ def main():
     ap.add_argument("--copy-mb", type=int, default=512)
     ap.add_argument("--pmc-dir", default=os.path.join(ROOT, "gpurun_out", "traffic"))
     ap.add_argument("--plain-fp64", type=int, default=1, help="also time the plain FP64 TT path on seed 0")
+    ap.add_argument("--coupled", type=int, default=1,
+                    help="also time seed 0 with the coupled medium temperature (heat capacity 8 a)")
     ap.add_argument("--served", type=int, default=256,
                     help="requests of the served mix (0: skip the serving phase)")
     ap.add_argument("--served-budget-gb", type=float, default=64.0)
@@ -337,6 +339,24 @@ def main():
                  "rel_l2_mixed_vs_fp64": tt_rel_diff(a, b),
                  "speedup_batched_mixed_vs_plain_fp64": value * plain_s}
         sp.destroy()
+    # ---- phase 4: seed 0 with the coupled medium temperature (Section 2.1 coupled source stage) ----
+    coupled = None
+    if args.coupled:
+        pc = prob.copy(heat_capacity=8.0 * ti.radiation_constant(prob.c))
+        sc = tt.Solver(pc, device=dev, round_method=method)
+        sc.set_timing(True)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        stc = sc.solve(K)
+        coupled_s = time.perf_counter() - t3
+        Tc = sc.get_temperature()
+        nc = stc["kernel_launches"]["couple"]
+        coupled = {"solves_per_s": 1.0 / coupled_s, "ms": coupled_s * 1e3, "timing": "HIP events on",
+                   "heat_capacity": "8 a (a = 8 pi^5 / (15 c))", "ranks": [stc["r1"], stc["r2"]],
+                   "couple_us_per_launch": stc["kernel_ms"]["couple"] / max(1, nc) * 1e3,
+                   "couple_launches": nc, "T_mean": float(Tc.mean()), "T_max": float(Tc.max()),
+                   "energy_total": stc["energy"] / pc.c + stc["medium_energy"]}
+        sc.destroy()
     lat_ms = np.array(lat) * 1e3
     out = {
         "metric": METRIC,
@@ -370,6 +390,8 @@ def main():
     }
     if plain:
         out["plain_fp64"] = plain
+    if coupled is not None:
+        out["coupled_temperature"] = coupled
     if args.served > 0:
         out["served"] = served_phase(args)
     if not args.no_cpu_baseline:

@@ -116,6 +116,20 @@ typedef struct tt_problem {
     int paper_step_order;           /* 0: one rounding per step after transport and
                                        source; 1: round after transport and again
                                        after the source (Section 3.1)              */
+    double heat_capacity;           /* rho c_v per unit volume (the density and
+                                       specific heat of Section 2).  0: the medium
+                                       temperature stays T_cell.  > 0: it is coupled
+                                       (Section 2.1, the coupled source stage): each
+                                       step takes the stage temperature T+ of every
+                                       cell as the root of the paper's scalar
+                                       equation, updates the intensity with
+                                       eps_g(T+), and advances T by total-energy
+                                       conservation with the angle means of the
+                                       rounded new state.  Needs paper_step_order 0;
+                                       such a problem advances only through
+                                       tt_transport_solve / step_batch / solve_batch. */
+    const double* T_rad0;           /* N_X initial radiation temperature (isotropic
+                                       Planck initial state), or NULL for T_cell  */
 } tt_problem;
 
 /* Statistics of the last solve / round (Section 3.2 metrics). */
@@ -134,9 +148,11 @@ typedef struct tt_stats {
                              is on: [0] prep, [1] project (first-core contraction),
                              [2] factor (TSQR or Gram), [3] factor tree / reduce,
                              [4] small-core SVD chain, [5] output contraction,
-                             [6] diagnostics, [7] unused                            */
+                             [6] diagnostics, [7] coupled medium temperature        */
     long long kernel_launches[8]; /* launches counted per class                      */
     double flops[8];      /* algorithmic flops per class, summed over the solve      */
+    double medium_energy; /* dV * heat_capacity * sum_x T[x] (0 when T is fixed); the
+                             radiation energy is energy / c                          */
 } tt_stats;
 
 typedef struct tt_handle tt_handle;
@@ -184,6 +200,12 @@ tt_status tt_transport_get_cores(tt_handle* h, double* Z, double* Theta, double*
  * (checkpoint restore, tests).  Synchronises. */
 tt_status tt_transport_set_cores(tt_handle* h, int r1, int r2, const double* Z,
                                  const double* Theta, const double* Phi, void* stream);
+
+/* Copy the medium temperature per cell (N_X doubles, cell = ix + Nx*(iy + Ny*iz))
+ * to host memory owned by the caller: the current values of a coupled problem
+ * (heat_capacity > 0), else T_cell as given.  Synchronises `stream` for a
+ * coupled problem.  Errors: TT_ERR_INVALID_ARG (NULL handle or T), TT_ERR_HIP. */
+tt_status tt_transport_get_temperature(tt_handle* h, double* T, void* stream);
 
 /* Fill `out` with the statistics of the current state (synchronises). */
 tt_status tt_transport_get_stats(tt_handle* h, tt_stats* out);

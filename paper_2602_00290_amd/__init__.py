@@ -23,7 +23,7 @@ TT_PREC_FP64, TT_PREC_FP32, TT_PREC_BF16X = 0, 1, 2
 TT_ROUND_QR, TT_ROUND_GRAM, TT_ROUND_AUTO = 0, 1, 2
 TT_BC_VACUUM, TT_BC_INFLOW_PLANCK, TT_BC_PERIODIC, TT_BC_INFLOW_VALUES = 0, 1, 2, 3
 
-KERNEL_CLASSES = ("prep", "project", "factor", "tree", "svd", "output", "diag", "unused")
+KERNEL_CLASSES = ("prep", "project", "factor", "tree", "svd", "output", "diag", "couple")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -54,6 +54,8 @@ class TTProblem(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("round_method", ctypes.c_int),
         ("paper_step_order", ctypes.c_int),
+        ("heat_capacity", ctypes.c_double),
+        ("T_rad0", _dp),
     ]
 
 
@@ -74,6 +76,7 @@ class TTStats(ctypes.Structure):
         ("kernel_ms", ctypes.c_double * 8),
         ("kernel_launches", ctypes.c_longlong * 8),
         ("flops", ctypes.c_double * 8),
+        ("medium_energy", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -81,6 +84,7 @@ class TTStats(ctypes.Structure):
         d["kernel_ms"] = dict(zip(KERNEL_CLASSES, list(self.kernel_ms)))
         d["kernel_launches"] = dict(zip(KERNEL_CLASSES, list(self.kernel_launches)))
         d["flops"] = dict(zip(KERNEL_CLASSES, list(self.flops)))
+        d["medium_energy"] = self.medium_energy
         return d
 
 
@@ -122,8 +126,10 @@ def _load():
     L.tt_transport_last_error.argtypes = []
     L.tt_transport_last_error.restype = ctypes.c_char_p
     L.tt_transport_group_emission.argtypes = [_dp, ctypes.c_int, ctypes.c_double, _dp]
+    L.tt_transport_get_temperature.argtypes = [vp, _dp, vp]
     for name in ("create", "apply_op", "round", "solve", "reset", "get_ranks", "get_cores", "set_cores",
-                 "get_stats", "set_timing", "step_batch", "solve_batch", "destroy", "group_emission"):
+                 "get_stats", "set_timing", "step_batch", "solve_batch", "destroy", "group_emission",
+                 "get_temperature"):
         getattr(L, "tt_transport_" + name).restype = ctypes.c_int
     return L
 
@@ -134,7 +140,7 @@ EXPORTED = ("tt_transport_workspace_bytes", "tt_transport_create", "tt_transport
             "tt_transport_solve", "tt_transport_reset", "tt_transport_get_ranks", "tt_transport_get_cores",
             "tt_transport_set_cores", "tt_transport_get_stats", "tt_transport_set_timing",
             "tt_transport_step_batch", "tt_transport_solve_batch", "tt_transport_destroy", "tt_transport_last_error",
-            "tt_transport_group_emission")
+            "tt_transport_group_emission", "tt_transport_get_temperature")
 
 
 def _check(status: int):
@@ -194,6 +200,8 @@ class ProblemStruct:
         s.precision = int(prob.precision)
         s.round_method = int(getattr(prob, "round_method", TT_ROUND_AUTO) if round_method is None else round_method)
         s.paper_step_order = int(prob.step_order)
+        s.heat_capacity = float(getattr(prob, "heat_capacity", 0.0))
+        s.T_rad0 = ptr(getattr(prob, "T_rad0", None))
         self.s = s
 
 
@@ -282,6 +290,12 @@ class Solver:
         Z, Th, Ph = _arr(Z), _arr(Th), _arr(Ph)
         _check(lib.tt_transport_set_cores(self.handle, Z.shape[1], Ph.shape[0], Z.ctypes.data_as(_dp),
                                           Th.ctypes.data_as(_dp), Ph.ctypes.data_as(_dp), self._sp()))
+
+    def get_temperature(self) -> np.ndarray:
+        """Medium temperature per cell (current values when coupled)."""
+        T = np.empty(self.prob.n_x)
+        _check(lib.tt_transport_get_temperature(self.handle, T.ctypes.data_as(_dp), self._sp()))
+        return T
 
     def get_stats(self) -> dict:
         st = TTStats()

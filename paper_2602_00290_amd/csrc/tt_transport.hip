@@ -27,12 +27,10 @@
 #include "k_fused.hpp"
 #include "k_gram.hpp"
 #include "k_mfma.hpp"
+#include "k_couple.hpp"
 #include "k_small.hpp"
+#include "planck.hpp"
 #include "tt_common.hpp"
-
-namespace ttrt {
-void group_emission(const double* edges, int n_groups, double T, double* out);
-}
 
 using namespace ttrt;
 
@@ -51,7 +49,7 @@ tt_status fail(tt_status s, const std::string& msg) {
         if (e_ != hipSuccess) return fail(TT_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-enum KClass { KC_PREP = 0, KC_PROJECT = 1, KC_FACTOR = 2, KC_TREE = 3, KC_SVD = 4, KC_OUTPUT = 5, KC_DIAG = 6 };
+enum KClass { KC_PREP = 0, KC_PROJECT = 1, KC_FACTOR = 2, KC_TREE = 3, KC_SVD = 4, KC_OUTPUT = 5, KC_DIAG = 6, KC_COUPLE = 7 };
 
 struct Plan {
     int dim = 1, nx = 1, ny = 1, nz = 1;
@@ -89,6 +87,9 @@ struct Plan {
     size_t o_state, o_Z0, o_Z1, o_B, o_Th0, o_Th1, o_Ph0, o_Ph1, o_LTh, o_QTh, o_QPh, o_G, o_V, o_RA, o_RB, o_small,
         o_k0, o_ks, o_eps, o_ghost, o_gtab, o_htab, o_ThN, o_PhN, o_sv, o_colsum;
     size_t small_bytes = 0, n_parts_max = 1;
+    // coupled medium temperature (heat_capacity > 0)
+    bool coupled = false;
+    size_t o_T = 0, o_T0 = 0, o_Js = 0, o_edges = 0, o_wth = 0, o_wph = 0;
     size_t k1sq = 1;                // k1cap x (k1cap | 1): SVD-chain matrices outside LDS
     // A2 scratch (doubles): the operand of the second-bond QR, the first-bond
     // matrix T outside LDS, or the second-bond Gram matrix
@@ -137,6 +138,10 @@ tt_status validate(const tt_problem* p) {
     if (p->precision < 0 || p->precision > 2) return fail(TT_ERR_INVALID_ARG, "unknown precision");
     if (p->round_method < 0 || p->round_method > 2) return fail(TT_ERR_INVALID_ARG, "unknown round_method");
     if (p->paper_step_order < 0 || p->paper_step_order > 1) return fail(TT_ERR_INVALID_ARG, "paper_step_order must be 0 or 1");
+    if (!(p->heat_capacity >= 0.0) || !std::isfinite(p->heat_capacity))
+        return fail(TT_ERR_INVALID_ARG, "heat_capacity must be finite and >= 0");
+    if (p->heat_capacity > 0.0 && p->paper_step_order != 0)
+        return fail(TT_ERR_INVALID_ARG, "the coupled medium temperature needs paper_step_order == 0");
     return TT_OK;
 }
 
@@ -302,6 +307,16 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
     P.o_PhN = take((size_t)P.R2cap * P.np * d);
     P.o_sv = take((size_t)(P.k1cap + P.k2cap) * d);
     P.o_colsum = take((size_t)256 * 128 * d);
+    if (p->heat_capacity > 0.0) {
+        // coupled medium temperature: T, its initial value, J* per row, edges and weights
+        P.coupled = true;
+        P.o_T = take((size_t)P.NX * d);
+        P.o_T0 = take((size_t)P.NX * d);
+        P.o_Js = take((size_t)P.M * d);
+        P.o_edges = take((size_t)(P.G + 1) * d);
+        P.o_wth = take((size_t)P.nt * d);
+        P.o_wph = take((size_t)P.np * d);
+    }
     P.bytes = off;
     // element offsets of the rank-1 blocks from Z must fit 32 bits
     // the fused kernels address Z, the rank-1 blocks and the zero region with
@@ -334,7 +349,11 @@ struct tt_handle {
     int pending = OP_NONE;
     OpDesc ops[4];
     std::vector<double> w_theta, w_phi;
-    std::vector<double> eps_host;
+    std::vector<double> eps_host;    // emission at the medium temperature (row order)
+    std::vector<double> init_host;   // initial first core: emission at the initial radiation temperature
+    std::vector<double> T_host;      // medium temperature as given (fixed unless coupled)
+    double heat_capacity = 0.0, c = 1.0;
+    int qe_full = -1, qe_source = -1;   // emission columns of the full and source operators
     // timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -497,8 +516,10 @@ tt_status set_cores_impl(tt_handle* h, int r1, int r2, const double* Z, const do
 tt_status reset_impl(tt_handle* h, hipStream_t s) {
     const Plan& P = h->P;
     std::vector<double> th((size_t)P.nt, 1.0), ph((size_t)P.np, 1.0);
-    if (h->precision == TT_PREC_FP64) return set_cores_impl<double>(h, 1, 1, h->eps_host.data(), th.data(), ph.data(), s);
-    return set_cores_impl<float>(h, 1, 1, h->eps_host.data(), th.data(), ph.data(), s);
+    if (P.coupled)
+        HIP_TRY(hipMemcpyAsync(h->ws + P.o_T, h->ws + P.o_T0, (size_t)P.NX * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (h->precision == TT_PREC_FP64) return set_cores_impl<double>(h, 1, 1, h->init_host.data(), th.data(), ph.data(), s);
+    return set_cores_impl<float>(h, 1, 1, h->init_host.data(), th.data(), ph.data(), s);
 }
 
 // Neighbour structure and rank-1 block of operator `opkind` for the fused
@@ -746,8 +767,65 @@ tt_status round_dispatch(tt_handle* h, int opkind, double tol, int cap, hipStrea
     return round_impl<float>(h, opkind, tol, cap, s);
 }
 
+CoupleArgs couple_args(tt_handle* h) {
+    const Plan& P = h->P;
+    CoupleArgs a;
+    a.edges = h->at<double>(P.o_edges);
+    a.wth = h->at<double>(P.o_wth);
+    a.wph = h->at<double>(P.o_wph);
+    a.gtab = h->at<double>(P.o_gtab);
+    a.htab = h->at<double>(P.o_htab);
+    a.T = h->at<double>(P.o_T);
+    a.Js = h->at<double>(P.o_Js);
+    a.eps = h->at<double>(P.o_eps);
+    a.R1 = (P.fused && P.rw1 > 0) ? h->at<float>(P.o_R1) : nullptr;
+    a.rw1 = P.rw1;
+    a.qe1 = h->qe_full;
+    a.R2 = (P.fused && P.rw2 > 0) ? h->at<float>(P.o_R2) : nullptr;
+    a.rw2 = P.rw2;
+    a.qe2 = h->qe_source;
+    a.heat_capacity = h->heat_capacity;
+    a.dt = h->dt;
+    a.c = h->c;
+    return a;
+}
+
+unsigned couple_grid(const Plan& P) {
+    return (unsigned)std::max<long long>(1, std::min<long long>(2048, (P.NX + 3) / 4));
+}
+
+// One step with the coupled medium temperature: the stage temperature and
+// emission before the rounding pass of the full operator, the
+// energy-conserving temperature update after it.
+template <typename T>
+tt_status coupled_step(tt_handle* h, hipStream_t s) {
+    const Plan& P = h->P;
+    const CoupleArgs a = couple_args(h);
+    const size_t lds_pre = couple_lds_doubles(P.n_gather_max * P.ldzcap + P.n_r1_max, 1 + P.n_terms, P.r1cap, P.r2cap) *
+                           sizeof(double);
+    size_t e = h->ev_begin(KC_COUPLE, s);
+    hipLaunchKernelGGL(k_couple_pre<T>, dim3(couple_grid(P)), dim3(kCoupleThreads), lds_pre, s, h->geom,
+                       h->ops[OP_TRANSPORT], h->rowdata(), (const DevState*)h->st(), (const T*)h->Zc(),
+                       (const double*)h->Thc(), (const double*)h->Phc(), a);
+    h->ev_end(e, s);
+    HIP_TRY(hipGetLastError());
+    tt_status r = round_dispatch(h, OP_FULL, h->tol, P.cap, s);
+    if (r != TT_OK) return r;
+    const size_t lds_post = (size_t)(P.r1cap + P.r2cap + 8) * sizeof(double);
+    e = h->ev_begin(KC_COUPLE, s);
+    hipLaunchKernelGGL(k_couple_post<T>, dim3(couple_grid(P)), dim3(kCoupleThreads), lds_post, s, h->geom,
+                       (const DevState*)h->st(), (const T*)h->Zc(), (const double*)h->Thc(), (const double*)h->Phc(), a);
+    h->ev_end(e, s);
+    HIP_TRY(hipGetLastError());
+    return TT_OK;
+}
+
 tt_status step_impl(tt_handle* h, hipStream_t s) {
     tt_status r;
+    if (h->P.coupled) {
+        if (h->pending != OP_NONE) return fail(TT_ERR_STATE, "an unrounded operator is pending");
+        return h->precision == TT_PREC_FP64 ? coupled_step<double>(h, s) : coupled_step<float>(h, s);
+    }
     if (h->pending != OP_NONE) {
         r = round_dispatch(h, h->pending, h->tol, h->P.cap, s);
         h->pending = OP_NONE;
@@ -818,6 +896,17 @@ tt_status fill_stats(tt_handle* h, tt_stats* out, hipStream_t s) {
     if (r != TT_OK) return r;
     out->energy = E;
     out->nan_flag = bad;
+    if (P.coupled) {
+        std::vector<double> T((size_t)P.NX);
+        HIP_TRY(hipMemcpyAsync(T.data(), h->ws + P.o_T, T.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        double sum = 0.0;
+        for (double t : T) {
+            if (!std::isfinite(t)) out->nan_flag = 1;
+            sum += t;
+        }
+        out->medium_energy = h->dV * h->heat_capacity * sum;
+    }
     const double dense = (double)P.M * P.nt * P.np;
     const double tt = (double)P.M * st.r1 + (double)P.nt * st.r1 * st.r2 + (double)P.np * st.r2;
     out->compression = dense / tt;
@@ -936,6 +1025,22 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
         }
     }
     h->eps_host = eps;
+    h->T_host.assign(p->T_cell, p->T_cell + P.NX);
+    h->heat_capacity = p->heat_capacity;
+    h->c = p->c;
+    // initial radiation: isotropic Planck at T_rad0 when given, else at the medium temperature
+    h->init_host = eps;
+    if (p->T_rad0) {
+        std::vector<double> e((size_t)P.G);
+        for (long long c = 0; c < P.NX; ++c) {
+            ttrt::group_emission(p->group_edges, P.G, p->T_rad0[c], e.data());
+            std::copy(e.begin(), e.end(), h->init_host.begin() + c * P.G);
+        }
+    }
+    for (int q = 0; q < h->ops[OP_FULL].n_r1; ++q)
+        if (h->ops[OP_FULL].r1kind[q] == 0) h->qe_full = q;
+    for (int q = 0; q < h->ops[OP_SOURCE].n_r1; ++q)
+        if (h->ops[OP_SOURCE].r1kind[q] == 0) h->qe_source = q;
     std::vector<double> ghost((size_t)6 * P.G, 0.0);
     for (int f = 0; f < 2 * P.dim; ++f) {
         if (p->bc[f] == TT_BC_INFLOW_PLANCK) ttrt::group_emission(p->group_edges, P.G, p->bc_T[f], &ghost[(size_t)f * P.G]);
@@ -975,6 +1080,13 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
     if ((u = upload(h->at<double>(P.o_ghost), ghost, s)) != TT_OK) { delete h; return u; }
     if ((u = upload(h->at<double>(P.o_gtab), gtab, s)) != TT_OK) { delete h; return u; }
     if ((u = upload(h->at<double>(P.o_htab), htab, s)) != TT_OK) { delete h; return u; }
+    if (P.coupled) {
+        std::vector<double> edges(p->group_edges, p->group_edges + P.G + 1);
+        if ((u = upload(h->at<double>(P.o_T0), h->T_host, s)) != TT_OK) { delete h; return u; }
+        if ((u = upload(h->at<double>(P.o_edges), edges, s)) != TT_OK) { delete h; return u; }
+        if ((u = upload(h->at<double>(P.o_wth), h->w_theta, s)) != TT_OK) { delete h; return u; }
+        if ((u = upload(h->at<double>(P.o_wph), h->w_phi, s)) != TT_OK) { delete h; return u; }
+    }
     if (hipMemsetAsync(h->ws + P.o_G, 0, P.o_V - P.o_G, s) != hipSuccess) { delete h; return fail(TT_ERR_HIP, "memset"); }
     if (P.fused) {
         if (hipMemsetAsync(h->ws + P.o_zero, 0, 1024, s) != hipSuccess) { delete h; return fail(TT_ERR_HIP, "memset"); }
@@ -1003,6 +1115,7 @@ tt_status tt_transport_apply_op(tt_handle* h, void* stream) {
     (void)stream;
     if (!h) return fail(TT_ERR_INVALID_ARG, "handle is NULL");
     if (h->pending != OP_NONE) return fail(TT_ERR_STATE, "an unrounded operator is already pending");
+    if (h->P.coupled) return fail(TT_ERR_STATE, "a coupled-temperature problem advances only by whole steps (solve / step_batch)");
     h->pending = h->step_order == 1 ? OP_TRANSPORT : OP_FULL;
     return TT_OK;
 }
@@ -1128,6 +1241,19 @@ tt_status tt_transport_set_cores(tt_handle* h, int r1, int r2, const double* Z, 
     hipStream_t s = (hipStream_t)stream;
     if (h->precision == TT_PREC_FP64) return set_cores_impl<double>(h, r1, r2, Z, Theta, Phi, s);
     return set_cores_impl<float>(h, r1, r2, Z, Theta, Phi, s);
+}
+
+tt_status tt_transport_get_temperature(tt_handle* h, double* T, void* stream) {
+    if (!h || !T) return fail(TT_ERR_INVALID_ARG, "handle and T must be non-NULL");
+    const Plan& P = h->P;
+    if (!P.coupled) {
+        std::copy(h->T_host.begin(), h->T_host.end(), T);
+        return TT_OK;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(T, h->ws + P.o_T, (size_t)P.NX * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return TT_OK;
 }
 
 tt_status tt_transport_get_stats(tt_handle* h, tt_stats* out) {

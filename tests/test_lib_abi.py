@@ -91,3 +91,15 @@ def test_create_rejects_small_or_null_workspace_without_gpu(tt):
     st = tt.lib.tt_transport_create(ctypes.byref(ps.s), fake, 64, None, ctypes.byref(h))
     assert st == tt.TT_ERR_OOM
     assert b"workspace too small" in tt.lib.tt_transport_last_error()
+
+
+def test_coupled_temperature_validation(tt):
+    p = ti.thermal_relax(n_cells=4)
+    fixed = p.copy(heat_capacity=0.0, T_rad0=None)
+    # the coupled problem carries T, its initial copy, J* per row, edges and weights
+    assert tt.workspace_bytes(p) > tt.workspace_bytes(fixed)
+    for bad in (p.copy(heat_capacity=-1.0), p.copy(heat_capacity=float("inf")), p.copy(step_order=1)):
+        with pytest.raises(tt.TTError) as e:
+            tt.workspace_bytes(bad)
+        assert e.value.status == tt.TT_ERR_INVALID_ARG
+    assert tt.workspace_bytes(fixed.copy(step_order=1)) > 0
