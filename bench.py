@@ -19,7 +19,7 @@ committed counter summary (null when the kernel source has changed since).
 sample of the same workload.
 
 Other modes (for profiling runs; they print one line and exit):
-  --mode probe        one solve of `--probe-workload` (plane2d or clumps3d) for `--probe-steps` steps
+  --mode probe        one solve of `--probe-workload` (plane2d, clumps3d, plane2d_coupled) for `--probe-steps` steps
   --mode copy         a plain device-to-device copy of `--copy-mb` MiB (counter calibration)
   --mode served       only the served request mix (capacity, then Poisson arrivals)
   --mode pmc-summary  turn rocprofv3 counter CSVs (--pmc-dir) into profiles/traffic_plane2d.json
@@ -173,7 +173,13 @@ def mode_probe(args):
     import torch
     import paper_2602_00290_amd as tt
     import tt_inputs as ti
-    prob = ti.plane2d() if args.probe_workload == "plane2d" else ti.clumps3d(precision=ti.PREC_BF16X)
+    if args.probe_workload == "clumps3d":
+        prob = ti.clumps3d(precision=ti.PREC_BF16X)
+    elif args.probe_workload == "plane2d_coupled":
+        prob = ti.plane2d()
+        prob = prob.copy(heat_capacity=8.0 * ti.radiation_constant(prob.c))
+    else:
+        prob = ti.plane2d()
     s = tt.Solver(prob)
     st = s.solve(args.probe_steps)
     torch.cuda.synchronize()
@@ -250,8 +256,9 @@ def main():
                     help="GPU_MAX_HW_QUEUES for this process (0: keep the environment's)")
     ap.add_argument("--mode", default="bench", choices=["bench", "probe", "copy", "pmc-summary", "served"])
     ap.add_argument("--probe-steps", type=int, default=64)
-    ap.add_argument("--probe-workload", default="plane2d", choices=["plane2d", "clumps3d"],
-                    help="probe workload: plane2d (FP32) or clumps3d (64^3 cells, 64 groups, split BF16)")
+    ap.add_argument("--probe-workload", default="plane2d", choices=["plane2d", "clumps3d", "plane2d_coupled"],
+                    help="probe workload: plane2d (FP32), clumps3d (64^3 cells, 64 groups, split BF16), or "
+                         "plane2d_coupled (plane2d with the coupled medium temperature, heat capacity 8 a)")
     ap.add_argument("--copy-mb", type=int, default=512)
     ap.add_argument("--pmc-dir", default=os.path.join(ROOT, "gpurun_out", "traffic"))
     ap.add_argument("--plain-fp64", type=int, default=1, help="also time the plain FP64 TT path on seed 0")

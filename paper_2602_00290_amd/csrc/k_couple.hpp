@@ -40,10 +40,47 @@ struct CoupleArgs {
     int rw1, qe1;            // its width and emission column (-1: none)
     float* R2;               // fused rank-1 block of the source operator (or null)
     int rw2, qe2;
+    const int* nbr;          // fused neighbour table (M x ns) or null
+    int ns;
     double heat_capacity;    // C_v = rho c_v
     double dt;
     double c;
 };
+
+// Lanes work in segments of the next power of two >= N_nu (at most 64): a
+// wave takes 64 / segment cells at once; with more groups it loops over them.
+__host__ __device__ inline int couple_seg(int G) {
+    int p = 1;
+    while (p < G && p < 64) p <<= 1;
+    return p;
+}
+
+// sum over the lanes of one aligned segment of `seg` lanes (a power of two)
+__device__ inline double seg_sum(double v, int seg) {
+    for (int off = seg >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// sum_{a < r} z[a] v[a] over a row of Z (rows start 32-byte aligned: the
+// leading dimension is a multiple of 8), with 16-byte loads
+template <typename T>
+__device__ inline double row_dot(const T* __restrict__ zr, const double* __restrict__ v, int r) {
+    double s = 0.0;
+    int a = 0;
+    if constexpr (sizeof(T) == 4) {
+        for (; a + 4 <= r; a += 4) {
+            const float4 z = *reinterpret_cast<const float4*>(zr + a);
+            s += (double)z.x * v[a] + (double)z.y * v[a + 1] + (double)z.z * v[a + 2] + (double)z.w * v[a + 3];
+        }
+    } else {
+        for (; a + 2 <= r; a += 2) {
+            const double2 z = *reinterpret_cast<const double2*>(zr + a);
+            s += (double)z.x * v[a] + (double)z.y * v[a + 1];
+        }
+    }
+    for (; a < r; ++a) s += (double)zr[a] * v[a];
+    return s;
+}
 
 // Dynamic LDS (doubles) of k_couple_pre: one-column operand (K), per-term
 // angular moments of Theta (n_rblk x r1) and of Phi (n_rblk x r2).
@@ -111,66 +148,91 @@ __global__ __launch_bounds__(kCoupleThreads) void k_couple_pre(Geom g, OpDesc op
     __syncthreads();
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int Gp = couple_seg(G), cpw = 64 / Gp, seg = lane / Gp, gl = lane - seg * Gp;
+    const bool one = G <= 64;   // at most one group per lane: its values stay in registers
     const long long ncell = g.M / G;
     const double C = ca.heat_capacity, dt = ca.dt, cdt = g.cdt;
-    for (long long cell = (long long)blockIdx.x * 4 + w; cell < ncell; cell += (long long)gridDim.x * 4) {
+    for (long long c0 = ((long long)blockIdx.x * 4 + w) * cpw; c0 < ncell; c0 += (long long)gridDim.x * 4 * cpw) {
+        const long long cell = c0 + seg;
+        if (cell >= ncell) continue;   // this segment has no cell (segments are independent)
         const double Tm = ca.T[cell];
-        double F0 = 0.0;
-        for (int gg = lane; gg < G; gg += 64) {
+        double F0 = 0.0, js1 = 0.0, coef1 = 0.0;
+        for (int gg = gl; gg < G; gg += Gp) {
             const long long k = cell * G + gg;
-            double js = 0.0;
-            for (int j = 0; j < ng; ++j) {
-                const long long src = j == 0 ? k : neighbour_row(g, k, op.gaxis[j], op.gdir[j]);
-                if (src < 0) continue;
-                const T* zr = Z + src * ldz;
-                const double* gj = GJ + (size_t)j * ldz;
-                for (int a = 0; a < r1; ++a) js += (double)zr[a] * gj[a];
+            double js = row_dot(Z + k * ldz, GJ, r1);
+            for (int j = 1; j < ng; ++j) {
+                const long long src = ca.nbr ? (long long)ca.nbr[k * ca.ns + j - 1]
+                                             : neighbour_row(g, k, op.gaxis[j], op.gdir[j]);
+                if (src >= 0) js += row_dot(Z + src * ldz, GJ + (size_t)j * ldz, r1);
             }
-            for (int q = 0; q < nr1; ++q) js += rank1_value(g, op, rd, k, q) * GJ[KG + q];
+            // inflow columns: the first columns of the fused rank-1 block when there is one
+            for (int q = 0; q < nr1; ++q)
+                js += (ca.R1 ? (double)ca.R1[k * ca.rw1 + q] : rank1_value(g, op, rd, k, q)) * GJ[KG + q];
             ca.Js[k] = js;
             const double kap = row_kappa(g, rd, k);
-            F0 += 4.0 * M_PI * dt * kap / (1.0 + cdt * kap) / C * js;
+            const double coef = 4.0 * M_PI * dt * kap / (1.0 + cdt * kap) / C;
+            F0 += coef * js;
+            js1 = js;
+            coef1 = coef;
         }
-        F0 = wave_sum(F0);
-        // f(T) = Tm - T - sum_g coef_g (eps_g(T) - J*_g) and f'(T), summed over the wave
+        F0 = seg_sum(F0, Gp);
+        // f(T) = Tm - T - sum_g coef_g (eps_g(T) - J*_g) and f'(T), summed over the segment;
+        // the lane keeps its last emission and derivative (e1, de1 at Te)
+        double e1 = 0.0, de1 = 0.0, Te = 0.0;
         auto eval = [&](double Tt, double& f, double& df) {
             double s = 0.0, ds = 0.0;
-            for (int gg = lane; gg < G; gg += 64) {
-                const long long k = cell * G + gg;
-                const double kap = row_kappa(g, rd, k);
-                const double coef = 4.0 * M_PI * dt * kap / (1.0 + cdt * kap) / C;
-                double de;
-                const double e = group_emission_1(ca.edges[gg], ca.edges[gg + 1], Tt, &de);
-                s += coef * (e - ca.Js[k]);
-                ds += coef * de;
+            if (one) {
+                if (gl < G) {
+                    e1 = group_emission_1(ca.edges[gl], ca.edges[gl + 1], Tt, &de1);
+                    s = coef1 * (e1 - js1);
+                    ds = coef1 * de1;
+                }
+            } else {
+                for (int gg = gl; gg < G; gg += Gp) {
+                    const long long k = cell * G + gg;
+                    const double kap = row_kappa(g, rd, k);
+                    const double coef = 4.0 * M_PI * dt * kap / (1.0 + cdt * kap) / C;
+                    double de;
+                    const double e = group_emission_1(ca.edges[gg], ca.edges[gg + 1], Tt, &de);
+                    s += coef * (e - ca.Js[k]);
+                    ds += coef * de;
+                }
             }
-            s = wave_sum(s);
-            ds = wave_sum(ds);
+            Te = Tt;
+            s = seg_sum(s, Gp);
+            ds = seg_sum(ds, Gp);
             f = Tm - Tt - s;
             df = -1.0 - ds;
         };
-        // f(hi) <= 0 at hi = Tm + sum coef J* (eps >= 0); widen if rounding put hi below the root
-        double lo = 0.0, hi = fmax(fmax(Tm + F0, Tm), 1e-300);
+        // Newton from T^m (the stage temperature is usually close to it) inside
+        // a bracket: f(0) >= 0, and f <= 0 at Tm + sum coef J* (eps >= 0), up to
+        // rounding, which the step-size stop below absorbs
+        const double Thi = fmax(fmax(Tm + F0, Tm), 1e-300);
+        double Tc = fmax(Tm, 1e-300);
         double f, df;
-        eval(hi, f, df);
-        for (int it = 0; f > 0.0 && it < 64; ++it) {
-            lo = hi;
-            hi *= 2.0;
-            eval(hi, f, df);
-        }
-        double Tc = hi;
+        eval(Tc, f, df);
+        double lo = f > 0.0 ? Tc : 0.0, hi = f > 0.0 ? fmax(Thi, Tc) : Tc;
         for (int it = 0; it < 100 && f != 0.0; ++it) {
-            if (f > 0.0) lo = Tc; else hi = Tc;
-            double Tn = Tc - f / df;
+            if (f > 0.0) lo = fmax(lo, Tc); else hi = fmin(hi, Tc);
+            const double step = f / df;
+            // a Newton step below 1e-14 of T is at the level of the rounding in
+            // f: take it and stop (testing it against the bracket instead would
+            // turn rounding noise into a bisection step)
+            if (fabs(step) <= 1e-14 * Tc) {
+                Tc -= step;
+                break;
+            }
+            double Tn = Tc - step;
             if (!(Tn > lo && Tn < hi)) Tn = 0.5 * (lo + hi);
-            const bool done = fabs(Tn - Tc) <= 1e-15 * Tn;
             Tc = Tn;
             eval(Tc, f, df);
-            if (done) break;
+            if (hi - lo <= 1e-15 * hi) break;
         }
-        for (int gg = lane; gg < G; gg += 64) {
+        // emission at T+: the last evaluation moved to T+ to first order
+        // (|T+ - Te| <= 1e-14 T+, so the neglected term is ~1e-28 relative)
+        for (int gg = gl; gg < G; gg += Gp) {
             const long long k = cell * G + gg;
-            const double e = group_emission_1(ca.edges[gg], ca.edges[gg + 1], Tc, nullptr);
+            const double e = one ? e1 + de1 * (Tc - Te) : group_emission_1(ca.edges[gg], ca.edges[gg + 1], Tc, nullptr);
             ca.eps[k] = e;
             const double v = cdt * row_kappa(g, rd, k) * e;
             if (ca.R1 && ca.qe1 >= 0) ca.R1[k * ca.rw1 + ca.qe1] = (float)v;
@@ -206,19 +268,19 @@ __global__ __launch_bounds__(kCoupleThreads) void k_couple_post(Geom g, const De
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int Gp = couple_seg(G), cpw = 64 / Gp, seg = lane / Gp, gl = lane - seg * Gp;
     const long long ncell = g.M / G;
     const double coefT = 4.0 * M_PI / (ca.c * ca.heat_capacity);
-    for (long long cell = (long long)blockIdx.x * 4 + w; cell < ncell; cell += (long long)gridDim.x * 4) {
+    for (long long c0 = ((long long)blockIdx.x * 4 + w) * cpw; c0 < ncell; c0 += (long long)gridDim.x * 4 * cpw) {
+        const long long cell = c0 + seg;
+        if (cell >= ncell) continue;
         double diff = 0.0;
-        for (int gg = lane; gg < G; gg += 64) {
+        for (int gg = gl; gg < G; gg += Gp) {
             const long long k = cell * G + gg;
-            const T* zr = Z + k * ldz;
-            double jn = 0.0;
-            for (int a = 0; a < r1; ++a) jn += (double)zr[a] * v[a];
-            diff += ca.Js[k] - jn;
+            diff += ca.Js[k] - row_dot(Z + k * ldz, v, r1);
         }
-        diff = wave_sum(diff);
-        if (lane == 0) ca.T[cell] += coefT * diff;
+        diff = seg_sum(diff, Gp);
+        if (gl == 0) ca.T[cell] += coefT * diff;
     }
 }
 

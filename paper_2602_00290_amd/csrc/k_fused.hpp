@@ -273,37 +273,6 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
                 acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[e], bc[c][e], acc[1][c], 0, 0, 0);
             }
     };
-    // output tiles are stored one tile late, after the next tile's first
-    // loads: vmcnt counts loads and stores in issue order, so stores issued
-    // before a load would hold up the wait for that load
-    f32x4v oacc[GRAM ? 1 : 2][GRAM ? 1 : NCT];
-    int oR0 = -1;
-    auto store_tile = [&](int R0) {
-        // D[i][j] of row tile rt: row R0 + 16 rt + 4 q + r, column 16 c + m
-        const bool full = R0 + 32 <= g.M;
-#pragma unroll
-        for (int c = 0; c < NCT; ++c) {
-            const int col = 16 * c + m;
-            if (col < ldo) {
-                char* ob = reinterpret_cast<char*>(Out);
-                const unsigned o0 = (unsigned)((R0 + 4 * q) * ldo + col) * 4u;
-                if (full) {
-#pragma unroll
-                    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            *reinterpret_cast<float*>(ob + o0 + (unsigned)((16 * rt + r) * ldo) * 4u) = oacc[rt][c][r];
-                } else {
-#pragma unroll
-                    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            if (R0 + 16 * rt + 4 * q + r < g.M)
-                                *reinterpret_cast<float*>(ob + o0 + (unsigned)((16 * rt + r) * ldo) * 4u) = oacc[rt][c][r];
-                }
-            }
-        }
-    };
     for (int tile = t_begin; tile < t_end; ++tile) {
         const bool more = tile + 1 < t_end;
         const RowPre na0 = pre_of(tile + 1, 0), na1 = pre_of(tile + 1, 1);
@@ -326,12 +295,6 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
                 // the table now takes the next tile's rows (past the last
                 // tile the old rows stay; their loads are in bounds and unused)
                 if (t + u == T2 - NS - 2 && more) tile_rows(tile + 1, na0, na1, nd0, nd1);
-                if constexpr (!GRAM) {
-                    if (t + u == 1 && oR0 >= 0) {
-                        store_tile(oR0);
-                        oR0 = -1;
-                    }
-                }
             }
         }
         const int R0 = 32 * tile;
@@ -354,17 +317,33 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
                         }
                 }
         } else {
+            // D[i][j] of row tile rt: row R0 + 16 rt + 4 q + r, column 16 c + m
+            const bool full = R0 + 32 <= g.M;
 #pragma unroll
-            for (int rt = 0; rt < 2; ++rt)
+            for (int c = 0; c < NCT; ++c) {
+                const int col = 16 * c + m;
+                if (col < ldo) {
+                    char* ob = reinterpret_cast<char*>(Out);
+                    const unsigned o0 = (unsigned)((R0 + 4 * q) * ldo + col) * 4u;
+                    if (full) {
 #pragma unroll
-                for (int c = 0; c < NCT; ++c) oacc[rt][c] = acc[rt][c];
-            oR0 = R0;
+                        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                *reinterpret_cast<float*>(ob + o0 + (unsigned)((16 * rt + r) * ldo) * 4u) = acc[rt][c][r];
+                    } else {
+#pragma unroll
+                        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                if (R0 + 16 * rt + 4 * q + r < g.M)
+                                    *reinterpret_cast<float*>(ob + o0 + (unsigned)((16 * rt + r) * ldo) * 4u) = acc[rt][c][r];
+                    }
+                }
+            }
         }
         d0 = nd0;
         d1 = nd1;
-    }
-    if constexpr (!GRAM) {
-        if (oR0 >= 0) store_tile(oR0);
     }
 
     if constexpr (GRAM) {

@@ -25,11 +25,15 @@ namespace ttrt {
 
 constexpr double kPlanckXS = 1.5;
 
-// B_{2j} / (2j)! for j = 1..14 (Bernoulli numbers B_2 .. B_28 as exact
-// rationals, divided by (2j)! at compile time)
+constexpr int kPlanckTailTerms = 200;
+
+// Compile-time coefficient tables (no division is left for run time):
+//   c[j] = B_{2j} / ((2j)! (2j + 3)) for j = 1..14 (Bernoulli numbers B_2 .. B_28
+//   as exact rationals), and inv[k] = 1 / k for the tail series.
 struct PlanckSeries {
     double c[15];
-    constexpr PlanckSeries() : c{} {
+    double inv[kPlanckTailTerms + 1];
+    constexpr PlanckSeries() : c{}, inv{} {
         const double num[15] = {0.0, 1.0, -1.0, 1.0, -1.0, 5.0, -691.0, 7.0, -3617.0, 43867.0,
                                 -174611.0, 854513.0, -236364091.0, 8553103.0, -23749461029.0};
         const double den[15] = {1.0, 6.0, 30.0, 42.0, 30.0, 66.0, 2730.0, 6.0, 510.0, 798.0,
@@ -37,20 +41,22 @@ struct PlanckSeries {
         double fact = 1.0;   // (2j)!
         for (int j = 1; j <= 14; ++j) {
             fact *= (double)(2 * j - 1) * (double)(2 * j);
-            c[j] = (num[j] / den[j]) / fact;
+            c[j] = (num[j] / den[j]) / fact / (double)(2 * j + 3);
         }
+        for (int k = 1; k <= kPlanckTailTerms; ++k) inv[k] = 1.0 / (double)k;
     }
 };
+constexpr PlanckSeries kPlanckSeries{};
 
 __host__ __device__ inline double planck_low(double x) {   // int_0^x t^3/(e^t-1) dt, 0 <= x <= XS
-    constexpr PlanckSeries S{};
+    const PlanckSeries& S = kPlanckSeries;
     if (x <= 0.0) return 0.0;
     const double x2 = x * x;
-    double sum = x2 * x / 3.0 - x2 * x2 / 8.0;
+    double sum = x2 * x * (1.0 / 3.0) - x2 * x2 * 0.125;
     double p = x2 * x;   // x^{2j+3} built incrementally
     for (int j = 1; j <= 14; ++j) {
         p *= x2;
-        const double term = S.c[j] * p / (2 * j + 3);
+        const double term = S.c[j] * p;
         sum += term;
         if (fabs(term) < 1e-18 * fabs(sum)) break;
     }
@@ -59,14 +65,16 @@ __host__ __device__ inline double planck_low(double x) {   // int_0^x t^3/(e^t-1
 
 __host__ __device__ inline double planck_tail(double x) {  // int_x^inf t^3/(e^t-1) dt, x >= XS
     if (__builtin_isinf(x)) return 0.0;
+    const PlanckSeries& S = kPlanckSeries;
     double sum = 0.0;
     const double q = exp(-x);
+    const double x2 = x * x, x3 = x2 * x;
     double ek = 1.0;
-    for (int k = 1; k <= 200; ++k) {
+    for (int k = 1; k <= kPlanckTailTerms; ++k) {
         ek *= q;
-        const double kk = (double)k;
-        const double term = ek * (x * x * x / kk + 3.0 * x * x / (kk * kk) + 6.0 * x / (kk * kk * kk) +
-                                  6.0 / (kk * kk * kk * kk));
+        const double ik = S.inv[k];
+        // e^{-kx} (x^3/k + 3x^2/k^2 + 6x/k^3 + 6/k^4), Horner in 1/k
+        const double term = ek * ik * (x3 + ik * (3.0 * x2 + ik * (6.0 * x + 6.0 * ik)));
         sum += term;
         if (term < 1e-18 * sum) break;
     }

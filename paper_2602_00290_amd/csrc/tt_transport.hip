@@ -784,14 +784,20 @@ CoupleArgs couple_args(tt_handle* h) {
     a.R2 = (P.fused && P.rw2 > 0) ? h->at<float>(P.o_R2) : nullptr;
     a.rw2 = P.rw2;
     a.qe2 = h->qe_source;
+    a.nbr = P.fused ? h->at<int>(P.o_nbr) : nullptr;
+    a.ns = P.n_terms;
     a.heat_capacity = h->heat_capacity;
     a.dt = h->dt;
     a.c = h->c;
     return a;
 }
 
-unsigned couple_grid(const Plan& P) {
-    return (unsigned)std::max<long long>(1, std::min<long long>(2048, (P.NX + 3) / 4));
+// Blocks of the coupling kernels: enough for one pass over the cells, at most
+// `cap` (the pre-pass rebuilds its one-column operand per block, so it runs
+// one resident round, 3 blocks per CU at its register count, and loops).
+unsigned couple_grid(const Plan& P, long long cap) {
+    const long long per_block = 4LL * (64 / couple_seg(P.G));   // cells per block and pass
+    return (unsigned)std::max<long long>(1, std::min<long long>(cap, (P.NX + per_block - 1) / per_block));
 }
 
 // One step with the coupled medium temperature: the stage temperature and
@@ -804,7 +810,7 @@ tt_status coupled_step(tt_handle* h, hipStream_t s) {
     const size_t lds_pre = couple_lds_doubles(P.n_gather_max * P.ldzcap + P.n_r1_max, 1 + P.n_terms, P.r1cap, P.r2cap) *
                            sizeof(double);
     size_t e = h->ev_begin(KC_COUPLE, s);
-    hipLaunchKernelGGL(k_couple_pre<T>, dim3(couple_grid(P)), dim3(kCoupleThreads), lds_pre, s, h->geom,
+    hipLaunchKernelGGL(k_couple_pre<T>, dim3(couple_grid(P, 768)), dim3(kCoupleThreads), lds_pre, s, h->geom,
                        h->ops[OP_TRANSPORT], h->rowdata(), (const DevState*)h->st(), (const T*)h->Zc(),
                        (const double*)h->Thc(), (const double*)h->Phc(), a);
     h->ev_end(e, s);
@@ -813,7 +819,7 @@ tt_status coupled_step(tt_handle* h, hipStream_t s) {
     if (r != TT_OK) return r;
     const size_t lds_post = (size_t)(P.r1cap + P.r2cap + 8) * sizeof(double);
     e = h->ev_begin(KC_COUPLE, s);
-    hipLaunchKernelGGL(k_couple_post<T>, dim3(couple_grid(P)), dim3(kCoupleThreads), lds_post, s, h->geom,
+    hipLaunchKernelGGL(k_couple_post<T>, dim3(couple_grid(P, 2048)), dim3(kCoupleThreads), lds_post, s, h->geom,
                        (const DevState*)h->st(), (const T*)h->Zc(), (const double*)h->Thc(), (const double*)h->Phc(), a);
     h->ev_end(e, s);
     HIP_TRY(hipGetLastError());
