@@ -267,3 +267,49 @@ def tt_energy(prob, Z, Th, Ph) -> float:
     dV = float(np.prod([prob.extent[d] / prob.n_cells[d] for d in range(prob.dim)]))
     a = np.einsum("alb,l,bp,p->a", Th, np.asarray(prob.w_theta), Ph, np.asarray(prob.w_phi))
     return dV * float(Z.sum(axis=0) @ a)
+
+
+# ---------------------------------------------------------------------------
+# internal ranks of the combined core (the discussion of the internal
+# structure of Z: internal delta-ranks and relative compression ratios)
+# ---------------------------------------------------------------------------
+
+def right_orthonormal_gauge(Z, Th, Ph):
+    """Z' such that (Z', Theta', Phi') is the same tensor with Theta' and Phi'
+    right-orthonormal: Phi = L_Phi Q_Phi, then the row unfolding of
+    Theta x_3 L_Phi = L_Theta Q_Theta (QRs of the transposes), Z' = Z L_Theta."""
+    r1, nt, r2 = Th.shape
+    qp, rp = np.linalg.qr(Ph.T)                    # Phi^T = Q R, Phi = R^T Q^T
+    Thp = np.einsum("alb,bc->alc", Th, rp.T)       # Theta x_3 L_Phi
+    qt, rt = np.linalg.qr(Thp.reshape(r1, -1).T)   # unfolding^T = Q R
+    return Z @ rt.T
+
+
+def delta_rank_rel(s: np.ndarray, delta: float) -> int:
+    """Smallest k with ||s[k:]||_2 <= delta ||s||_2 (s sorted descending), at least 1."""
+    s = np.asarray(s, float)
+    tot = float(np.sum(s * s))
+    tail = np.concatenate([np.cumsum((s * s)[::-1])[::-1], [0.0]])
+    for k in range(1, len(s) + 1):
+        if math.sqrt(max(tail[k], 0.0)) <= delta * math.sqrt(tot):
+            return k
+    return len(s)
+
+
+def internal_ranks(n_x: int, n_groups: int, Z, Th, Ph, delta: float) -> dict:
+    """Internal delta-ranks of the combined core: r_nux from the SVD of
+    reshape(Z', [N_nu, N_X r1]) and r_xnu from reshape(Z', [N_X, N_nu r1]), Z'
+    in the right-orthonormal gauge (so the local error is the global one),
+    with the relative compression ratios C_rel^nu and C_rel^x (the TT entry
+    count over the entries of the split-core topologies)."""
+    r1, nt, r2 = Th.shape
+    npn = Ph.shape[1]
+    Zp = right_orthonormal_gauge(Z, Th, Ph).reshape(n_x, n_groups, r1)   # [x, g, a]
+    s_nu = np.linalg.svd(Zp.transpose(1, 0, 2).reshape(n_groups, n_x * r1), compute_uv=False)
+    s_x = np.linalg.svd(Zp.reshape(n_x, n_groups * r1), compute_uv=False)
+    r_nux = delta_rank_rel(s_nu, delta)
+    r_xnu = delta_rank_rel(s_x, delta)
+    n_tt = n_x * n_groups * r1 + nt * r1 * r2 + npn * r2
+    c_nu = n_tt / (n_groups * r_nux + n_x * r_nux * r1 + nt * r1 * r2 + npn * r2)
+    c_x = n_tt / (n_x * r_xnu + n_groups * r_xnu * r1 + nt * r1 * r2 + npn * r2)
+    return {"r_nux": r_nux, "r_xnu": r_xnu, "C_rel_nu": c_nu, "C_rel_x": c_x, "s_nu": s_nu, "s_x": s_x}
