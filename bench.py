@@ -332,6 +332,13 @@ def main():
     single_s = time.perf_counter() - t1
     single.set_timing(False)
     agg_ms, agg_n, agg_fl = st1["kernel_ms"], st1["kernel_launches"], st1["flops"]
+    # internal delta-ranks of the final combined core (discussion of the internal structure of Z)
+    internal = {}
+    for delta in (1e-3, 1e-6):
+        t4 = time.perf_counter()
+        ir = single.internal_ranks(delta)
+        internal[f"{delta:g}"] = {"r_nux": ir["r_nux"], "r_xnu": ir["r_xnu"], "C_rel_nu": ir["C_rel_nu"],
+                                  "C_rel_x": ir["C_rel_x"], "ms": (time.perf_counter() - t4) * 1e3}
 
     # ---- phase 3: the plain FP64 TT path (FP64 state, Householder TSQR) on seed 0 ----
     plain = None
@@ -394,6 +401,7 @@ def main():
         "kernel_ms_per_solve": {c: agg_ms[c] for c in tt.KERNEL_CLASSES if agg_n[c]},
         "kernel_us_per_launch": {c: agg_ms[c] / agg_n[c] * 1e3 for c in tt.KERNEL_CLASSES if agg_n[c]},
         "roofline": roofline(st1),
+        "internal_ranks": internal,
     }
     if plain:
         out["plain_fp64"] = plain

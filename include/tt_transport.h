@@ -155,6 +155,17 @@ typedef struct tt_stats {
                              radiation energy is energy / c                          */
 } tt_stats;
 
+/* Internal delta-ranks of the combined core Z (section "Internal structure of
+ * the combined core" and its relative compression equations). */
+typedef struct tt_internal_ranks {
+    int r_nux;        /* delta-rank of the N_nu x (N_X r1) unfolding of Z'        */
+    int r_xnu;        /* delta-rank of the N_X x (N_nu r1) unfolding of Z'        */
+    double C_rel_nu;  /* TT entries / entries with Z split as (frequency, space)  */
+    double C_rel_x;   /* TT entries / entries with Z split as (space, frequency)  */
+    int n_sv_nu;      /* number of singular values of the first unfolding        */
+    int n_sv_x;       /* number of singular values of the second unfolding       */
+} tt_internal_ranks;
+
 typedef struct tt_handle tt_handle;
 
 /* Bytes of device workspace needed for `p` at its rank cap.  Returns 0 for an
@@ -206,6 +217,25 @@ tt_status tt_transport_set_cores(tt_handle* h, int r1, int r2, const double* Z,
  * (heat_capacity > 0), else T_cell as given.  Synchronises `stream` for a
  * coupled problem.  Errors: TT_ERR_INVALID_ARG (NULL handle or T), TT_ERR_HIP. */
 tt_status tt_transport_get_temperature(tt_handle* h, double* T, void* stream);
+
+/* Internal delta-ranks of the current combined core (section "Internal
+ * structure of the combined core").  Z' = Z L_Theta is Z in the gauge where
+ * Theta and Phi are right-orthonormal, so that a truncation of Z' carries the
+ * same Frobenius error as of the whole tensor.  r_nux is the smallest k whose
+ * singular-value tail of reshape(Z', [N_nu, N_X r1]) is <= delta times the
+ * norm of all of them, r_xnu the same for reshape(Z', [N_X, N_nu r1]); C_rel_nu
+ * and C_rel_x are the paper's relative compression ratios for the two split
+ * topologies.  The singular values (descending; out->n_sv_nu = N_nu and
+ * out->n_sv_x = min(N_X, N_nu r1) of them) are copied to sv_nu / sv_x, at most
+ * n_sv_nu / n_sv_x each; either pointer may be NULL.  The Gram of the
+ * N_X x (N_nu ld) unfolding is formed in FP64 on the device in the handle's
+ * round scratch, then reduced on the host, so singular values below about
+ * 1e-8 of the largest are not resolved.  Synchronises `stream`.
+ * Errors: TT_ERR_INVALID_ARG (NULL handle/out, delta < 0, N_nu * ld > 2048),
+ * TT_ERR_STATE (an unrounded sum is pending, or the scratch is too small),
+ * TT_ERR_HIP. */
+tt_status tt_transport_internal_ranks(tt_handle* h, double delta, tt_internal_ranks* out, double* sv_nu,
+                                      int n_sv_nu, double* sv_x, int n_sv_x, void* stream);
 
 /* Fill `out` with the statistics of the current state (synchronises). */
 tt_status tt_transport_get_stats(tt_handle* h, tt_stats* out);

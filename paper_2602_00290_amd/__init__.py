@@ -88,6 +88,17 @@ class TTStats(ctypes.Structure):
         return d
 
 
+class TTInternalRanks(ctypes.Structure):
+    _fields_ = [
+        ("r_nux", ctypes.c_int),
+        ("r_xnu", ctypes.c_int),
+        ("C_rel_nu", ctypes.c_double),
+        ("C_rel_x", ctypes.c_double),
+        ("n_sv_nu", ctypes.c_int),
+        ("n_sv_x", ctypes.c_int),
+    ]
+
+
 class TTError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"tt_transport error {status}: {msg}")
@@ -127,9 +138,11 @@ def _load():
     L.tt_transport_last_error.restype = ctypes.c_char_p
     L.tt_transport_group_emission.argtypes = [_dp, ctypes.c_int, ctypes.c_double, _dp]
     L.tt_transport_get_temperature.argtypes = [vp, _dp, vp]
+    L.tt_transport_internal_ranks.argtypes = [vp, ctypes.c_double, ctypes.POINTER(TTInternalRanks), _dp, ctypes.c_int,
+                                              _dp, ctypes.c_int, vp]
     for name in ("create", "apply_op", "round", "solve", "reset", "get_ranks", "get_cores", "set_cores",
                  "get_stats", "set_timing", "step_batch", "solve_batch", "destroy", "group_emission",
-                 "get_temperature"):
+                 "get_temperature", "internal_ranks"):
         getattr(L, "tt_transport_" + name).restype = ctypes.c_int
     return L
 
@@ -140,7 +153,7 @@ EXPORTED = ("tt_transport_workspace_bytes", "tt_transport_create", "tt_transport
             "tt_transport_solve", "tt_transport_reset", "tt_transport_get_ranks", "tt_transport_get_cores",
             "tt_transport_set_cores", "tt_transport_get_stats", "tt_transport_set_timing",
             "tt_transport_step_batch", "tt_transport_solve_batch", "tt_transport_destroy", "tt_transport_last_error",
-            "tt_transport_group_emission", "tt_transport_get_temperature")
+            "tt_transport_group_emission", "tt_transport_get_temperature", "tt_transport_internal_ranks")
 
 
 def _check(status: int):
@@ -296,6 +309,19 @@ class Solver:
         T = np.empty(self.prob.n_x)
         _check(lib.tt_transport_get_temperature(self.handle, T.ctypes.data_as(_dp), self._sp()))
         return T
+
+    def internal_ranks(self, delta: float) -> dict:
+        """Internal delta-ranks r_nux, r_xnu of the combined core with the
+        relative compression ratios and the singular values of both unfoldings."""
+        n_groups = self.M // self.prob.n_x
+        cap_x = n_groups * max(self.get_ranks()[0], 1)
+        sv_nu = np.zeros(n_groups)
+        sv_x = np.zeros(cap_x)
+        out = TTInternalRanks()
+        _check(lib.tt_transport_internal_ranks(self.handle, float(delta), ctypes.byref(out), sv_nu.ctypes.data_as(_dp),
+                                               n_groups, sv_x.ctypes.data_as(_dp), cap_x, self._sp()))
+        return {"r_nux": out.r_nux, "r_xnu": out.r_xnu, "C_rel_nu": out.C_rel_nu, "C_rel_x": out.C_rel_x,
+                "s_nu": sv_nu[:min(out.n_sv_nu, n_groups)], "s_x": sv_x[:min(out.n_sv_x, cap_x)]}
 
     def get_stats(self) -> dict:
         st = TTStats()

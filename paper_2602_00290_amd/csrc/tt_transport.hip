@@ -28,6 +28,7 @@
 #include "k_gram.hpp"
 #include "k_mfma.hpp"
 #include "k_couple.hpp"
+#include "k_diag.hpp"
 #include "k_small.hpp"
 #include "planck.hpp"
 #include "tt_common.hpp"
@@ -930,6 +931,117 @@ tt_status fill_stats(tt_handle* h, tt_stats* out, hipStream_t s) {
     return TT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// host linear algebra for the internal-rank diagnostic (small matrices, FP64)
+// ---------------------------------------------------------------------------
+
+// R factor (min(m, n) x n, row-major, upper trapezoidal) of the Householder
+// QR of the m x n row-major matrix A (overwritten).
+std::vector<double> host_qr_r(std::vector<double> A, int m, int n) {
+    const int q = std::min(m, n);
+    for (int k = 0; k < q; ++k) {
+        double nrm = 0.0;
+        for (int i = k; i < m; ++i) nrm += A[(size_t)i * n + k] * A[(size_t)i * n + k];
+        nrm = std::sqrt(nrm);
+        if (nrm == 0.0) continue;
+        const double alpha = A[(size_t)k * n + k] > 0 ? -nrm : nrm;
+        std::vector<double> v((size_t)(m - k));
+        for (int i = k; i < m; ++i) v[i - k] = A[(size_t)i * n + k];
+        v[0] -= alpha;
+        double vv = 0.0;
+        for (double x : v) vv += x * x;
+        if (vv == 0.0) continue;
+        for (int j = k; j < n; ++j) {
+            double dot = 0.0;
+            for (int i = k; i < m; ++i) dot += v[i - k] * A[(size_t)i * n + j];
+            const double f = 2.0 * dot / vv;
+            for (int i = k; i < m; ++i) A[(size_t)i * n + j] -= f * v[i - k];
+        }
+    }
+    std::vector<double> R((size_t)q * n, 0.0);
+    for (int i = 0; i < q; ++i)
+        for (int j = i; j < n; ++j) R[(size_t)i * n + j] = A[(size_t)i * n + j];
+    return R;
+}
+
+// Eigenvalues (descending) of the symmetric n x n row-major matrix A:
+// Householder reduction to tridiagonal form, then bisection on the Sturm
+// sequence count of each eigenvalue.
+std::vector<double> host_sym_eigenvalues(std::vector<double> A, int n) {
+    std::vector<double> d((size_t)n), e((size_t)std::max(n - 1, 0));
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m = n - k - 1;   // trailing block starts at k + 1
+        double nrm = 0.0;
+        for (int i = k + 1; i < n; ++i) nrm += A[(size_t)i * n + k] * A[(size_t)i * n + k];
+        nrm = std::sqrt(nrm);
+        if (nrm == 0.0) continue;
+        const double alpha = A[(size_t)(k + 1) * n + k] > 0 ? -nrm : nrm;
+        std::vector<double> v((size_t)m), p((size_t)m);
+        for (int i = 0; i < m; ++i) v[i] = A[(size_t)(k + 1 + i) * n + k];
+        v[0] -= alpha;
+        double vv = 0.0;
+        for (double x : v) vv += x * x;
+        if (vv == 0.0) continue;
+        const double beta = 2.0 / vv;
+        // p = beta A v, w = p - (beta / 2) (v^T p) v;  A <- A - v w^T - w v^T on the trailing block
+        for (int i = 0; i < m; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < m; ++j) s += A[(size_t)(k + 1 + i) * n + k + 1 + j] * v[j];
+            p[i] = beta * s;
+        }
+        double vp = 0.0;
+        for (int i = 0; i < m; ++i) vp += v[i] * p[i];
+        for (int i = 0; i < m; ++i) p[i] -= 0.5 * beta * vp * v[i];
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) A[(size_t)(k + 1 + i) * n + k + 1 + j] -= v[i] * p[j] + p[i] * v[j];
+        A[(size_t)(k + 1) * n + k] = alpha;
+        A[(size_t)k * n + k + 1] = alpha;
+        for (int i = k + 2; i < n; ++i) A[(size_t)i * n + k] = A[(size_t)k * n + i] = 0.0;
+    }
+    for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i];
+    for (int i = 0; i + 1 < n; ++i) e[i] = A[(size_t)(i + 1) * n + i];
+    // Gershgorin interval
+    double lo = 0.0, hi = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0);
+        lo = std::min(lo, d[i] - r);
+        hi = std::max(hi, d[i] + r);
+    }
+    const double scale = std::max(std::fabs(lo), std::fabs(hi));
+    auto count_below = [&](double x) {   // number of eigenvalues < x
+        int c = 0;
+        double q = 1.0;
+        for (int i = 0; i < n; ++i) {
+            q = d[i] - x - (i > 0 ? e[i - 1] * e[i - 1] / q : 0.0);
+            if (q == 0.0) q = -1e-300 * std::max(scale, 1e-300);
+            if (q < 0.0) ++c;
+        }
+        return c;
+    };
+    std::vector<double> ev((size_t)n);
+    for (int k = 0; k < n; ++k) {   // k-th smallest
+        double a = lo, b = hi;
+        for (int it = 0; it < 200 && b - a > 4e-16 * std::max(scale, 1e-300); ++it) {
+            const double mid = 0.5 * (a + b);
+            if (count_below(mid) > k) b = mid; else a = mid;
+        }
+        ev[(size_t)(n - 1 - k)] = 0.5 * (a + b);
+    }
+    return ev;
+}
+
+// Smallest k >= 1 with sqrt(sum_{j >= k} s_j^2) <= delta * sqrt(sum_j s_j^2), s descending
+int delta_rank_host(const std::vector<double>& s, double delta) {
+    double tot = 0.0;
+    for (double x : s) tot += x * x;
+    double tail = tot;
+    for (size_t k = 1; k <= s.size(); ++k) {
+        tail -= s[k - 1] * s[k - 1];
+        if (std::sqrt(std::max(tail, 0.0)) <= delta * std::sqrt(tot)) return (int)k;
+    }
+    return (int)s.size();
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1247,6 +1359,108 @@ tt_status tt_transport_set_cores(tt_handle* h, int r1, int r2, const double* Z, 
     hipStream_t s = (hipStream_t)stream;
     if (h->precision == TT_PREC_FP64) return set_cores_impl<double>(h, r1, r2, Z, Theta, Phi, s);
     return set_cores_impl<float>(h, r1, r2, Z, Theta, Phi, s);
+}
+
+tt_status tt_transport_internal_ranks(tt_handle* h, double delta, tt_internal_ranks* out, double* sv_nu, int n_sv_nu,
+                                      double* sv_x, int n_sv_x, void* stream) {
+    if (!h || !out) return fail(TT_ERR_INVALID_ARG, "handle and out must be non-NULL");
+    if (!(delta >= 0.0)) return fail(TT_ERR_INVALID_ARG, "delta must be >= 0");
+    const Plan& P = h->P;
+    hipStream_t s = (hipStream_t)stream;
+    DevState st;
+    tt_status r = read_state(h, st, s);
+    if (r != TT_OK) return r;
+    if (h->pending != OP_NONE) return fail(TT_ERR_STATE, "an unrounded operator is pending");
+    const int r1 = st.r1, r2 = st.r2, ldz = st.ldz, G = P.G, nt = P.nt, np = P.np;
+    const long long NX = P.NX;
+    const int n = G * ldz;
+    if (n > 2048) return fail(TT_ERR_INVALID_ARG, "internal ranks: N_nu * ld(r1) above 2048 is not supported");
+    // raw Gram of the N_X x (N_nu ldz) unfolding of Z on the device, in strips
+    // of rows that fit the round scratch
+    const int ntile = (n + 63) / 64;
+    const int per = (int)std::min<size_t>((size_t)n, P.B_bytes / ((size_t)n * sizeof(double)));
+    if (per < 1) return fail(TT_ERR_STATE, "internal ranks: round scratch below one row of the Gram");
+    double* Gd = h->at<double>(P.o_B);
+    std::vector<double> Gr((size_t)n * n), th((size_t)r1 * nt * r2), ph((size_t)r2 * np);
+    for (int lo = 0; lo < n; lo += per) {
+        const int hi = std::min(n, lo + per);
+        const unsigned tiles_y = (unsigned)((hi - 1) / 64 - lo / 64 + 1);
+        if (h->precision == TT_PREC_FP64)
+            hipLaunchKernelGGL(k_unfold_gram<double>, dim3(ntile, tiles_y), dim3(256), 0, s, (const double*)h->Zc(),
+                               NX, n, lo, hi, Gd);
+        else
+            hipLaunchKernelGGL(k_unfold_gram<float>, dim3(ntile, tiles_y), dim3(256), 0, s, (const float*)h->Zc(), NX,
+                               n, lo, hi, Gd);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(Gr.data() + (size_t)lo * n, Gd, (size_t)(hi - lo) * n * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipMemcpyAsync(th.data(), h->Thc(), th.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ph.data(), h->Phc(), ph.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < i; ++j) Gr[(size_t)i * n + j] = Gr[(size_t)j * n + i];
+    // right-orthonormal gauge: Phi = L_Phi Q_Phi, Theta x_3 L_Phi = L_Theta Q_Theta, Z' = Z L_Theta
+    std::vector<double> pt((size_t)np * r2);
+    for (int b = 0; b < r2; ++b)
+        for (int p = 0; p < np; ++p) pt[(size_t)p * r2 + b] = ph[(size_t)b * np + p];
+    const std::vector<double> Rp = host_qr_r(pt, np, r2);   // r2 x r2 (r2 <= N_phi)
+    const int m2 = nt * r2;
+    std::vector<double> tt((size_t)m2 * r1);                  // (Theta x_3 L_Phi) unfolding, transposed
+    for (int a = 0; a < r1; ++a)
+        for (int l = 0; l < nt; ++l)
+            for (int c = 0; c < r2; ++c) {
+                double v = 0.0;
+                for (int b = c; b < r2; ++b) v += th[((size_t)a * nt + l) * r2 + b] * Rp[(size_t)c * r2 + b];
+                tt[((size_t)l * r2 + c) * r1 + a] = v;
+            }
+    const int q = std::min(m2, r1);
+    const std::vector<double> Rt = host_qr_r(tt, m2, r1);     // q x r1; L_Theta = Rt^T (r1 x q)
+    // G_x = (L (x) I)^T G_raw (L (x) I) over (g, i) with i < q;  G_nu[g, g'] = sum_i G_x[(g,i),(g',i)]
+    const int nx = G * q;
+    std::vector<double> Gx((size_t)nx * nx), tmp((size_t)ldz * q);
+    for (int g = 0; g < G; ++g)
+        for (int g2 = 0; g2 < G; ++g2) {
+            // block (g, g2) of G_raw is ldz x ldz; rows/cols a < r1 carry data
+            for (int a = 0; a < r1; ++a)
+                for (int j = 0; j < q; ++j) {
+                    double v = 0.0;
+                    for (int b = j; b < r1; ++b) v += Gr[(size_t)(g * ldz + a) * n + g2 * ldz + b] * Rt[(size_t)j * r1 + b];
+                    tmp[(size_t)a * q + j] = v;
+                }
+            for (int i = 0; i < q; ++i)
+                for (int j = 0; j < q; ++j) {
+                    double v = 0.0;
+                    for (int a = i; a < r1; ++a) v += Rt[(size_t)i * r1 + a] * tmp[(size_t)a * q + j];
+                    Gx[(size_t)(g * q + i) * nx + g2 * q + j] = v;
+                }
+        }
+    std::vector<double> Gn((size_t)G * G, 0.0);
+    for (int g = 0; g < G; ++g)
+        for (int g2 = 0; g2 < G; ++g2)
+            for (int i = 0; i < q; ++i) Gn[(size_t)g * G + g2] += Gx[(size_t)(g * q + i) * nx + g2 * q + i];
+    auto singular = [](std::vector<double> ev) {
+        for (double& x : ev) x = std::sqrt(std::max(x, 0.0));
+        return ev;
+    };
+    std::vector<double> s_nu = singular(host_sym_eigenvalues(Gn, G));
+    std::vector<double> s_x = singular(host_sym_eigenvalues(Gx, nx));
+    // a matrix with N_X rows has at most N_X nonzero singular values
+    if ((long long)s_x.size() > NX) s_x.resize((size_t)NX);
+    if ((long long)s_nu.size() > NX * q) s_nu.resize((size_t)(NX * q));
+    const int r_nux = delta_rank_host(s_nu, delta), r_xnu = delta_rank_host(s_x, delta);
+    const double n_tt = (double)NX * G * r1 + (double)nt * r1 * r2 + (double)np * r2;
+    out->r_nux = r_nux;
+    out->r_xnu = r_xnu;
+    out->C_rel_nu = n_tt / ((double)G * r_nux + (double)NX * r_nux * r1 + (double)nt * r1 * r2 + (double)np * r2);
+    out->C_rel_x = n_tt / ((double)NX * r_xnu + (double)G * r_xnu * r1 + (double)nt * r1 * r2 + (double)np * r2);
+    out->n_sv_nu = (int)s_nu.size();
+    out->n_sv_x = (int)s_x.size();
+    if (sv_nu)
+        for (int i = 0; i < std::min(n_sv_nu, (int)s_nu.size()); ++i) sv_nu[i] = s_nu[i];
+    if (sv_x)
+        for (int i = 0; i < std::min(n_sv_x, (int)s_x.size()); ++i) sv_x[i] = s_x[i];
+    return TT_OK;
 }
 
 tt_status tt_transport_get_temperature(tt_handle* h, double* T, void* stream) {
