@@ -95,8 +95,10 @@ typedef struct tt_problem {
     double extent[3];               /* domain [0, extent_d] per axis                */
     int n_groups;                   /* N_nu >= 1                                    */
     const double* group_edges;      /* N_nu + 1 edges, [0] = 0, [N_nu] = +inf       */
-    const double* kappa0;           /* N_X spatial opacity factor (>= 0)            */
-    const double* kappa_group_scale;/* N_nu: kappa[cell,g] = kappa0[cell]*scale[g]  */
+    const double* kappa0;           /* N_X spatial opacity factor (>= 0); may be
+                                       NULL when kappa_full is given              */
+    const double* kappa_group_scale;/* N_nu: kappa[cell,g] = kappa0[cell]*scale[g]
+                                       (NULL allowed with kappa_full)             */
     const double* T_cell;           /* N_X fixed medium temperature (>= 0)          */
     int n_theta;                    /* polar nodes                                  */
     int n_phi;                      /* azimuthal nodes (must be 1 when dim == 1)    */
@@ -130,6 +132,13 @@ typedef struct tt_problem {
                                        tt_transport_solve / step_batch / solve_batch. */
     const double* T_rad0;           /* N_X initial radiation temperature (isotropic
                                        Planck initial state), or NULL for T_cell  */
+    const double* kappa_full;       /* N_X * N_nu opacities kappa_{a,g}(x) (>= 0),
+                                       row cell * N_nu + g, for fields that do not
+                                       factor (several materials: the opacity
+                                       matrix then has rank N_materials, Section 4
+                                       and the internal-structure discussion), or
+                                       NULL for kappa0 x kappa_group_scale.  Copied
+                                       to the workspace (N_X N_nu doubles more).  */
 } tt_problem;
 
 /* Statistics of the last solve / round (Section 3.2 metrics). */

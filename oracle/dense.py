@@ -93,7 +93,11 @@ def time_step(prob) -> float:
 
 
 def kappa_field(prob) -> np.ndarray:
-    """(N_X, N_nu) opacity kappa0(x) * scale(g)."""
+    """(N_X, N_nu) opacity kappa_{a,g}(x) of the transport equation (Section 2):
+    the full field when given, else kappa0(x) * scale(g)."""
+    kf = getattr(prob, "kappa_full", None)
+    if kf is not None:
+        return np.asarray(kf, float).reshape(prob.n_x, prob.n_groups)
     return np.outer(np.asarray(prob.kappa0, float), np.asarray(prob.kappa_scale, float))
 
 

@@ -56,6 +56,7 @@ class TTProblem(ctypes.Structure):
         ("paper_step_order", ctypes.c_int),
         ("heat_capacity", ctypes.c_double),
         ("T_rad0", _dp),
+        ("kappa_full", _dp),
     ]
 
 
@@ -215,6 +216,8 @@ class ProblemStruct:
         s.paper_step_order = int(prob.step_order)
         s.heat_capacity = float(getattr(prob, "heat_capacity", 0.0))
         s.T_rad0 = ptr(getattr(prob, "T_rad0", None))
+        kf = getattr(prob, "kappa_full", None)
+        s.kappa_full = ptr(None if kf is None else np.asarray(kf, float).reshape(-1))
         self.s = s
 
 

@@ -13,9 +13,11 @@ struct RowData {
     const double* kscale;   // N_nu
     const double* eps;      // M  (eps_g(T_cell))
     const double* ghost;    // 6 x N_nu isotropic ghost intensities
+    const double* kfull;    // M opacities per (cell, group) row, or null for kappa0 x kscale
 };
 
 __device__ inline double row_kappa(const Geom& g, const RowData& rd, long long k) {
+    if (rd.kfull) return rd.kfull[k];
     const long long cell = k / g.G;
     const int grp = (int)(k - cell * g.G);
     return rd.kappa0[cell] * rd.kscale[grp];

@@ -86,10 +86,11 @@ struct Plan {
     int rw1 = 0, rw2 = 0;           // widths of the rank-1 row blocks (transport / source operators)
     bool fused_overflow = false;
     size_t o_state, o_Z0, o_Z1, o_B, o_Th0, o_Th1, o_Ph0, o_Ph1, o_LTh, o_QTh, o_QPh, o_G, o_V, o_RA, o_RB, o_small,
-        o_k0, o_ks, o_eps, o_ghost, o_gtab, o_htab, o_ThN, o_PhN, o_sv, o_colsum;
+        o_k0, o_ks, o_kfull = 0, o_eps, o_ghost, o_gtab, o_htab, o_ThN, o_PhN, o_sv, o_colsum;
     size_t small_bytes = 0, n_parts_max = 1;
     // coupled medium temperature (heat_capacity > 0)
     bool coupled = false;
+    bool kfull = false;   // opacity given per (cell, group) row
     size_t o_T = 0, o_T0 = 0, o_Js = 0, o_edges = 0, o_wth = 0, o_wph = 0;
     size_t k1sq = 1;                // k1cap x (k1cap | 1): SVD-chain matrices outside LDS
     // A2 scratch (doubles): the operand of the second-bond QR, the first-bond
@@ -116,7 +117,9 @@ tt_status validate(const tt_problem* p) {
     if (!(p->group_edges[0] >= 0.0)) return fail(TT_ERR_INVALID_ARG, "group_edges[0] must be >= 0");
     for (int g = 0; g < p->n_groups; ++g)
         if (!(p->group_edges[g + 1] > p->group_edges[g])) return fail(TT_ERR_INVALID_ARG, "group edges must increase");
-    if (!p->kappa0 || !p->kappa_group_scale || !p->T_cell) return fail(TT_ERR_INVALID_ARG, "kappa0, kappa_group_scale and T_cell are required");
+    if (!p->T_cell) return fail(TT_ERR_INVALID_ARG, "T_cell is required");
+    if (!p->kappa_full && (!p->kappa0 || !p->kappa_group_scale))
+        return fail(TT_ERR_INVALID_ARG, "kappa_full, or kappa0 and kappa_group_scale, are required");
     if (p->n_theta < 1 || !p->mu || !p->w_theta) return fail(TT_ERR_INVALID_ARG, "need n_theta >= 1, mu and w_theta");
     if (p->n_phi < 1 || !p->w_phi) return fail(TT_ERR_INVALID_ARG, "need n_phi >= 1 and w_phi");
     if (p->dim == 1 && p->n_phi != 1) return fail(TT_ERR_INVALID_ARG, "dim == 1 requires n_phi == 1");
@@ -300,6 +303,8 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
     P.o_small = take(P.small_bytes);
     P.o_k0 = take((size_t)P.NX * d);
     P.o_ks = take((size_t)P.G * d);
+    P.kfull = p->kappa_full != nullptr;
+    if (P.kfull) P.o_kfull = take((size_t)P.M * d);
     P.o_eps = take((size_t)P.M * d);
     P.o_ghost = take((size_t)6 * P.G * d);
     P.o_gtab = take((size_t)(1 + P.n_terms) * P.nt * d);
@@ -375,7 +380,10 @@ struct tt_handle {
     double* Thn() const { return at<double>(ccur ? P.o_Th0 : P.o_Th1); }
     double* Phc() const { return at<double>(ccur ? P.o_Ph1 : P.o_Ph0); }
     double* Phn() const { return at<double>(ccur ? P.o_Ph0 : P.o_Ph1); }
-    RowData rowdata() const { return RowData{at<double>(P.o_k0), at<double>(P.o_ks), at<double>(P.o_eps), at<double>(P.o_ghost)}; }
+    RowData rowdata() const {
+        return RowData{at<double>(P.o_k0), at<double>(P.o_ks), at<double>(P.o_eps), at<double>(P.o_ghost),
+                       P.kfull ? at<double>(P.o_kfull) : nullptr};
+    }
     SmallScratch scratch() const {
         SmallScratch s;
         char* b = ws + P.o_small;
@@ -1071,11 +1079,20 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
     if (bytes < P.bytes) return fail(TT_ERR_OOM, "workspace too small: need " + std::to_string(P.bytes) + " bytes");
     if (((uintptr_t)dev_workspace) & 255) return fail(TT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     for (long long i = 0; i < P.NX; ++i)
-        if (!(p->kappa0[i] >= 0.0) || !std::isfinite(p->kappa0[i]) || !(p->T_cell[i] >= 0.0))
-            return fail(TT_ERR_INVALID_ARG, "kappa0 and T_cell must be finite and >= 0");
-    for (int g = 0; g < P.G; ++g)
-        if (!(p->kappa_group_scale[g] >= 0.0) || !std::isfinite(p->kappa_group_scale[g]))
-            return fail(TT_ERR_INVALID_ARG, "kappa_group_scale must be finite and >= 0");
+        if (!(p->T_cell[i] >= 0.0) || !std::isfinite(p->T_cell[i]))
+            return fail(TT_ERR_INVALID_ARG, "T_cell must be finite and >= 0");
+    if (p->kappa_full) {
+        for (long long k = 0; k < P.M; ++k)
+            if (!(p->kappa_full[k] >= 0.0) || !std::isfinite(p->kappa_full[k]))
+                return fail(TT_ERR_INVALID_ARG, "kappa_full must be finite and >= 0");
+    } else {
+        for (long long i = 0; i < P.NX; ++i)
+            if (!(p->kappa0[i] >= 0.0) || !std::isfinite(p->kappa0[i]))
+                return fail(TT_ERR_INVALID_ARG, "kappa0 must be finite and >= 0");
+        for (int g = 0; g < P.G; ++g)
+            if (!(p->kappa_group_scale[g] >= 0.0) || !std::isfinite(p->kappa_group_scale[g]))
+                return fail(TT_ERR_INVALID_ARG, "kappa_group_scale must be finite and >= 0");
+    }
     {
         static bool attrs_set = false;
         if (!attrs_set) {
@@ -1190,8 +1207,17 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
             }
         }
     }
-    std::vector<double> k0(p->kappa0, p->kappa0 + P.NX), ks(p->kappa_group_scale, p->kappa_group_scale + P.G);
+    // with kappa_full the factored arrays are unused (zero-filled)
+    std::vector<double> k0((size_t)P.NX, 0.0), ks((size_t)P.G, 0.0);
+    if (!p->kappa_full) {
+        k0.assign(p->kappa0, p->kappa0 + P.NX);
+        ks.assign(p->kappa_group_scale, p->kappa_group_scale + P.G);
+    }
     tt_status u;
+    if (p->kappa_full) {
+        std::vector<double> kf(p->kappa_full, p->kappa_full + P.M);
+        if ((u = upload(h->at<double>(P.o_kfull), kf, s)) != TT_OK) { delete h; return u; }
+    }
     if ((u = upload(h->at<double>(P.o_k0), k0, s)) != TT_OK) { delete h; return u; }
     if ((u = upload(h->at<double>(P.o_ks), ks, s)) != TT_OK) { delete h; return u; }
     if ((u = upload(h->at<double>(P.o_eps), eps, s)) != TT_OK) { delete h; return u; }

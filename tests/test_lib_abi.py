@@ -104,3 +104,14 @@ def test_coupled_temperature_validation(tt):
             tt.workspace_bytes(bad)
         assert e.value.status == tt.TT_ERR_INVALID_ARG
     assert tt.workspace_bytes(fixed.copy(step_order=1)) > 0
+
+
+def test_kappa_full_validation(tt):
+    p = ti.slab1d(n_cells=16, n_groups=4, n_theta=4)
+    K = np.outer(p.kappa0, p.kappa_scale)
+    q = p.copy(kappa_full=K, kappa0=None, kappa_scale=None)
+    # the full field takes N_X N_nu doubles of workspace more
+    assert tt.workspace_bytes(q) >= tt.workspace_bytes(p) + 16 * 4 * 8
+    with pytest.raises(tt.TTError) as e:
+        tt.workspace_bytes(p.copy(kappa0=None))
+    assert e.value.status == tt.TT_ERR_INVALID_ARG

@@ -198,3 +198,38 @@ def test_mirror_symmetry():
     # GL nodes are symmetric: index l <-> 5 - l flips mu
     Ib = dense.march(pb, I0[::-1, :, ::-1].reshape(-1, 6, 1), 5).reshape(9, G, 6)
     np.testing.assert_allclose(Ib[::-1, :, ::-1], Ia, rtol=1e-13, atol=1e-16)
+
+
+@pytest.mark.parametrize("n_mat", [1, 3, 5])
+def test_multi_material_kappa_has_rank_of_material_count(n_mat):
+    # the opacity matrix of n materials on a partition has rank n (n <= N_nu)
+    edges = ti.log_group_edges(8, 0.01, 10.0)
+    K = ti.multi_material_kappa((9, 7, 1), (1.0, 1.0, 1.0), edges, n_mat, seed=n_mat)
+    assert K.shape == (63, 8) and np.all(K > 0)
+    assert np.linalg.matrix_rank(K) == n_mat
+    assert len(np.unique(K[:, 0])) == n_mat
+
+
+def test_kappa_full_of_a_factored_field_equals_the_factored_march():
+    p = ti.slab1d(n_cells=16, n_groups=4, n_theta=6)
+    p.kappa0 = ti.lognormal_kappa0(p.n_cells, p.extent, 1, seed=2)
+    q = p.copy(kappa_full=np.outer(p.kappa0, p.kappa_scale), kappa0=None, kappa_scale=None)
+    a = dense.march(p, dense.initial_dense(p), 5)
+    b = dense.march(q, dense.initial_dense(q), 5)
+    assert np.array_equal(a, b)
+
+
+def test_kappa_full_rows_follow_cell_major_order():
+    # kappa = "infinity" on rows (cell, g) with cell + g even, 0 elsewhere: after
+    # one step the former hold eps_g(T_cell) and the latter the pure streaming
+    # result, which fixes the row order cell * N_nu + g of kappa_full.
+    p = ti.slab1d(n_cells=15, n_groups=4, n_theta=6, T=0.4)
+    cell, g = np.meshgrid(np.arange(15), np.arange(4), indexing="ij")
+    thick = (cell + g) % 2 == 0
+    q = p.copy(kappa_full=np.where(thick, 1e300, 0.0))
+    I0 = dense.initial_dense(q) * 0.25
+    got = dense.march(q, I0, 1).reshape(15, 4, -1)
+    stream = dense.march(p.copy(kappa0=np.zeros(15)), I0, 1).reshape(15, 4, -1)
+    eps = dense.emission(p).reshape(15, 4)
+    np.testing.assert_allclose(got[thick], np.broadcast_to(eps[thick][:, None], got[thick].shape), rtol=1e-14)
+    np.testing.assert_array_equal(got[~thick], stream[~thick])

@@ -68,6 +68,7 @@ class Problem:
     seed: int = 0
     heat_capacity: float = 0.0   # rho c_v per volume; 0: fixed medium temperature, > 0: coupled temperature
     T_rad0: Optional[np.ndarray] = None   # (N_X,) initial radiation temperature (None: T_cell)
+    kappa_full: Optional[np.ndarray] = None   # (N_X, N_nu) opacity per cell and group (None: kappa0 x kappa_scale)
 
     # ----- derived sizes (pure bookkeeping) -----
     @property
@@ -205,6 +206,29 @@ def add_clumps(kappa0, n_cells, extent, clumps, factor=100.0) -> np.ndarray:
         d2 = ((x - np.asarray(centre)) ** 2).sum(axis=1)
         out[d2 <= radius ** 2] *= factor
     return out
+
+
+def multi_material_kappa(n_cells, extent, edges, n_materials, seed=0, power_range=(1.0, 3.0),
+                         jitter=0.5) -> np.ndarray:
+    """(N_X, N_nu) opacity of n_materials materials on a seeded Voronoi
+    partition of the domain: material m has kappa_m(nu_g) = a_m nu_g^-p_m
+    exp(jitter z_{m,g}), a_m lognormal, p_m uniform in power_range, z standard
+    normal, so the opacity matrix has rank min(n_materials, N_nu) when every
+    material holds a cell (the multi-material setting whose rank equals the
+    number of materials)."""
+    rng = np.random.default_rng(seed)
+    x = cell_centres(n_cells, extent)
+    dim = x.shape[1]
+    seeds = rng.uniform(0.0, 1.0, (n_materials, dim)) * np.asarray(extent[:dim], float)
+    mat = np.argmin(((x[:, None, :] - seeds[None, :, :]) ** 2).sum(axis=2), axis=1)
+    # make every material own at least its nearest cell
+    for m in range(n_materials):
+        mat[np.argmin(((x - seeds[m]) ** 2).sum(axis=1))] = m
+    nu = group_centers(edges)
+    a = np.exp(rng.standard_normal(n_materials))
+    p = rng.uniform(*power_range, n_materials)
+    K = a[:, None] * nu[None, :] ** (-p[:, None]) * np.exp(jitter * rng.standard_normal((n_materials, len(nu))))
+    return K[mat]
 
 
 # ---------------------------------------------------------------------------
