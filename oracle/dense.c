@@ -15,6 +15,15 @@
  * intensities: the given isotropic value on inflow faces, 0 on vacuum faces,
  * wrap-around on periodic axes.
  *
+ * The transport half alone (oracle_dense_transport) also takes the Rusanov flux
+ * (Section 2.1 names upwind, Rusanov and HLL; the Rusanov interface flux for
+ * the flux function c n_d I is (c n_d / 2)(I_L + I_R) - (S+ / 2)(I_R - I_L)):
+ *
+ *   I* = I - sum_d [ (lambda_d / 2) n_d (I_{c+e_d} - I_{c-e_d})
+ *                    - (lambda_d s / 2) (I_{c+e_d} - 2 I_c + I_{c-e_d}) ],
+ *
+ * s = S+ / c.  Ghost intensities enter both neighbours for every direction.
+ *
  * Direction vector: in 1D n_x = mu; in 2D/3D n = (sin t cos p, sin t sin p, mu)
  * with sin t = sqrt(1 - mu^2).
  *
@@ -116,10 +125,12 @@ int oracle_dense_march(int dim, const int* n_cells, const double* extent, int G,
 }
 
 /* Transport half only (no source), one step: used for the paper's step order
-   where rounding happens between the transport and the source update. */
+   where rounding happens between the transport and the source update, and
+   for the Rusanov flux (flux = 1, s = S+ / c); flux = 0 is the upwind flux. */
 int oracle_dense_transport(int dim, const int* n_cells, const double* extent, int G, int NT, int NP,
                            const double* mu, const double* phi, const int* bc, const double* ghost,
-                           double c, double dt, const double* I, double* out, int n_threads) {
+                           double c, double dt, const double* I, double* out, int n_threads, int flux,
+                           double s_rus) {
     int N[3] = { n_cells[0], dim > 1 ? n_cells[1] : 1, dim > 2 ? n_cells[2] : 1 };
     long NX = (long)N[0] * N[1] * N[2];
     int A = NT * NP;
@@ -144,7 +155,12 @@ int oracle_dense_transport(int dim, const int* n_cells, const double* extent, in
                 double acc = v;
                 for (int d = 0; d < dim; ++d) {
                     double n = nd[3 * a + d];
-                    if (n > 0.0) {
+                    if (flux == 1) {
+                        double lo = neighbour(I, N, d, -1, idx, g, G, A, a, bc, ghost);
+                        double hi = neighbour(I, N, d, +1, idx, g, G, A, a, bc, ghost);
+                        acc -= 0.5 * lam[d] * n * (hi - lo);
+                        acc += 0.5 * lam[d] * s_rus * (hi - 2.0 * v + lo);
+                    } else if (n > 0.0) {
                         double up = neighbour(I, N, d, -1, idx, g, G, A, a, bc, ghost);
                         acc -= lam[d] * n * (v - up);
                     } else if (n < 0.0) {

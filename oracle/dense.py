@@ -18,6 +18,15 @@ after streaming); the intensity is updated with eps(T+), and the new medium
 temperature follows from total-energy conservation,
     C_v (T^{m+1} - T^m) = (4 pi / c) sum_g (J*_g - J_g^{m+1}),
 J = (1 / 4 pi) sum_lp w_l w_p I (the quadrature weights sum to 4 pi).
+
+Isotropic elastic scattering (the kappa_s term of the transport equation and
+of its backward-Euler source update, Section 2.1) with a = c dt kappa_a,
+b = c dt kappa_s: the angle mean of the update gives
+J^{m+1} = (J* + a eps) / (1 + a) (scattering drops out), and then
+I^{m+1} = (I* + a eps + b J^{m+1}) / (1 + a + b).
+
+The Rusanov flux (the second of the three stencils Section 2.1 names) is
+taken in the transport half: see dense.c.
 """
 from __future__ import annotations
 
@@ -65,7 +74,7 @@ def lib():
         L.oracle_dense_march.restype = ctypes.c_int
         L.oracle_dense_transport.argtypes = [
             ctypes.c_int, ip, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, ip, dp,
-            ctypes.c_double, ctypes.c_double, dp, dp, ctypes.c_int]
+            ctypes.c_double, ctypes.c_double, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double]
         L.oracle_dense_transport.restype = ctypes.c_int
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -101,6 +110,24 @@ def kappa_field(prob) -> np.ndarray:
     return np.outer(np.asarray(prob.kappa0, float), np.asarray(prob.kappa_scale, float))
 
 
+def kappa_s_field(prob) -> np.ndarray:
+    """(N_X, N_nu) scattering opacity kappa_{s,g}(x) (zero when not given)."""
+    ks = getattr(prob, "kappa_s_full", None)
+    if ks is None:
+        return np.zeros((prob.n_x, prob.n_groups))
+    return np.asarray(ks, float).reshape(prob.n_x, prob.n_groups)
+
+
+def flux_params(prob):
+    """(flux, s): 0 for the upwind flux, 1 for Rusanov with s = S+ / c."""
+    flux = int(getattr(prob, "flux", 0))
+    return flux, float(getattr(prob, "rusanov_s", 1.0)) if flux == 1 else 0.0
+
+
+def _plain(prob) -> bool:
+    return flux_params(prob)[0] == 0 and getattr(prob, "kappa_s_full", None) is None
+
+
 def emission(prob) -> np.ndarray:
     return planck.emission_field(prob.edges, prob.T_cell)
 
@@ -129,6 +156,11 @@ def initial_dense(prob) -> np.ndarray:
 
 def march(prob, I0: np.ndarray, n_steps: int, n_threads: int = 0, dt: float = None) -> np.ndarray:
     """n_steps full steps (transport + source) of the dense FP64 scheme."""
+    if not _plain(prob):
+        I = np.ascontiguousarray(I0, dtype=np.float64).copy()
+        for _ in range(n_steps):
+            I = source(prob, transport(prob, I, n_threads, dt=dt), dt=dt)
+        return I
     I = np.ascontiguousarray(I0, dtype=np.float64).copy()
     work = np.empty_like(I)
     nc = np.ascontiguousarray(np.asarray(prob.n_cells, dtype=np.int32))
@@ -150,8 +182,8 @@ def march(prob, I0: np.ndarray, n_steps: int, n_threads: int = 0, dt: float = No
     return I
 
 
-def transport(prob, I: np.ndarray, n_threads: int = 0) -> np.ndarray:
-    """Transport half-step only (no source update)."""
+def transport(prob, I: np.ndarray, n_threads: int = 0, dt: float = None) -> np.ndarray:
+    """Transport half-step only (no source update), upwind or Rusanov flux."""
     I = np.ascontiguousarray(I, dtype=np.float64)
     out = np.empty_like(I)
     nc = np.ascontiguousarray(np.asarray(prob.n_cells, dtype=np.int32))
@@ -160,22 +192,28 @@ def transport(prob, I: np.ndarray, n_threads: int = 0) -> np.ndarray:
     ghost = np.ascontiguousarray(ghost_values(prob))
     mu = np.ascontiguousarray(np.asarray(prob.mu, float))
     phi = np.ascontiguousarray(np.asarray(prob.phi, float))
+    flux, s_rus = flux_params(prob)
     rc = lib().oracle_dense_transport(
         prob.dim, _ip(nc), _dp(ext), prob.n_groups, prob.n_theta, prob.n_phi, _dp(mu), _dp(phi),
-        _ip(bc), _dp(ghost), float(prob.c), float(time_step(prob)), _dp(I), _dp(out),
-        int(n_threads))
+        _ip(bc), _dp(ghost), float(prob.c), float(time_step(prob) if dt is None else dt), _dp(I), _dp(out),
+        int(n_threads), flux, s_rus)
     if rc != 0:
         raise RuntimeError("oracle_dense_transport failed")
     return out
 
 
-def source(prob, I: np.ndarray) -> np.ndarray:
-    """Implicit absorption/emission update at fixed T (scattering zero, rho = 1)."""
-    dt = time_step(prob)
+def source(prob, I: np.ndarray, dt: float = None) -> np.ndarray:
+    """Implicit absorption/emission and isotropic scattering update at fixed T
+    (rho = 1)."""
+    dt = time_step(prob) if dt is None else dt
     kap = kappa_field(prob).reshape(-1)
     eps = emission(prob).reshape(-1)
     a = prob.c * dt * kap
-    return (I + (a * eps)[:, None, None]) / (1.0 + a)[:, None, None]
+    if getattr(prob, "kappa_s_full", None) is None:
+        return (I + (a * eps)[:, None, None]) / (1.0 + a)[:, None, None]
+    b = prob.c * dt * kappa_s_field(prob).reshape(-1)
+    J_new = (mean_intensity(prob, I).reshape(-1) + a * eps) / (1.0 + a)
+    return (I + (a * eps + b * J_new)[:, None, None]) / (1.0 + a + b)[:, None, None]
 
 
 def energy(prob, I: np.ndarray) -> float:
@@ -240,7 +278,10 @@ def coupled_source(prob, I_star: np.ndarray, T: np.ndarray):
         Tp = stage_temperature(prob, float(T[x]), J_star[x], kap[x], dt)
         eps[x] = planck.group_emission_quad(prob.edges, Tp)
     a = (prob.c * dt * kap).reshape(-1)
-    I_new = (I_star + (a * eps.reshape(-1))[:, None, None]) / (1.0 + a)[:, None, None]
+    b = (prob.c * dt * kappa_s_field(prob)).reshape(-1)
+    # J^{m+1} of the implicit update (independent of the scattering opacity)
+    Jn = (J_star.reshape(-1) + a * eps.reshape(-1)) / (1.0 + a)
+    I_new = (I_star + (a * eps.reshape(-1) + b * Jn)[:, None, None]) / (1.0 + a + b)[:, None, None]
     J_new = mean_intensity(prob, I_new)
     T_new = T + 4.0 * np.pi / (prob.c * float(prob.heat_capacity)) * np.sum(J_star - J_new, axis=1)
     return I_new, T_new

@@ -18,6 +18,19 @@ with the negative part.  Boundary ghost values enter as a rank-1 Dirichlet TT
 with the rank-1 field d = 1/(1 + c dt kappa) plus the rank-1 emission term
 c dt kappa eps d (Section 3.1: rank-1 TT lift of spatio-spectral fields).
 
+The Rusanov flux (Section 2.1 names it among the three stencils; Appendix A,
+"Value of n", shows it is also two rank-1 operators per axis) gives, per axis
+d, with lambda = lambda_d and s = S+ / c: one term with the full direction
+component n_d acting on Z as -(lambda / 2)(O_{d+} - O_{d-}), and one without
+angular factor acting as (lambda s / 2)(O_{d+} - 2 I + O_{d-}).  In every
+case a ghost value enters the rank-1 Dirichlet term of a face through the
+coefficient its term puts on the shift that leaves the domain there.
+
+Isotropic scattering (kappa_s, Section 2.1 source update): with
+a = c dt kappa_a, b = c dt kappa_s and J* the angle mean of the transported
+TT, the source becomes d I* plus the rank-1 isotropic column
+d (a eps + b J^{m+1}), d = 1 / (1 + a + b), J^{m+1} = (J* + a eps) / (1 + a).
+
 The sum is formed explicitly: Z_new is the block row [Z, S_1 Z, ..., S_n Z,
 bc..., emission], Theta_new is block diagonal and Phi_new is stacked, so the
 ranks after the update are (n+1) r + n_bc + 1 (Appendix A, ranks of the
@@ -66,6 +79,37 @@ def direction_factors(prob):
     return terms
 
 
+def transport_terms(prob):
+    """The streaming operator's rank-1 terms as (axis, g, h, c0, cm, cp): the
+    angular factors g[N_theta], h[N_phi] and the spatial part
+    c0 I + cm O_{d-} + cp O_{d+} ((O_{d-/+} Z)[cell] = Z[cell -/+ e_d])."""
+    dt = dense.time_step(prob)
+    flux, s_rus = dense.flux_params(prob)
+    out = []
+    if flux == 0:
+        for axis, sgn, g, h in direction_factors(prob):
+            lam = prob.c * dt / (prob.extent[axis] / prob.n_cells[axis])
+            if sgn > 0:   # -lambda n^+ (I - O_{d-})
+                out.append((axis, g, h, -lam, lam, 0.0))
+            else:         # -lambda n^- (O_{d+} - I)
+                out.append((axis, g, h, lam, 0.0, -lam))
+        return out
+    mu = np.asarray(prob.mu, float)
+    phi = np.asarray(prob.phi, float)
+    st = np.sqrt(np.maximum(0.0, 1.0 - mu * mu))
+    for axis in range(prob.dim):
+        lam = prob.c * dt / (prob.extent[axis] / prob.n_cells[axis])
+        if prob.dim == 1 or axis == 2:
+            g, h = mu.copy(), np.ones(prob.n_phi)
+        else:
+            g, h = st.copy(), (np.cos(phi) if axis == 0 else np.sin(phi))
+        out.append((axis, g, h, 0.0, 0.5 * lam, -0.5 * lam))
+        if s_rus != 0.0:
+            out.append((axis, np.ones(prob.n_theta), np.ones(prob.n_phi), -lam * s_rus, 0.5 * lam * s_rus,
+                        0.5 * lam * s_rus))
+    return out
+
+
 def _cell_index(prob):
     nx = int(prob.n_cells[0])
     ny = int(prob.n_cells[1]) if prob.dim > 1 else 1
@@ -95,33 +139,32 @@ def shift(prob, Z: np.ndarray, axis: int, s: int) -> np.ndarray:
 
 
 def bc_columns(prob):
-    """Rank-1 Dirichlet terms: list of (z[M], g[N_theta], h[N_phi]) for every
-    inflow face.  Low face of axis d: value +lambda_d * ghost_g on the first cell
-    layer with the (d, +) angular factors; high face: -lambda_d * ghost_g on the
-    last layer with the (d, -) factors."""
-    dt = dense.time_step(prob)
+    """Rank-1 Dirichlet terms: list of (z[M], g[N_theta], h[N_phi]).  On the
+    first cell layer of an inflow face at the low end of axis d, each term of
+    that axis contributes cm * ghost_g with its angular factors (its O_{d-}
+    shift reads the ghost there); at the high end cp * ghost_g on the last
+    layer.  Upwind: +lambda ghost with n_d^+ (low), -lambda ghost with n_d^-
+    (high)."""
     ghost = dense.ghost_values(prob)
     idx, N = _cell_index(prob)
-    terms = {(a, s): (g, h) for a, s, g, h in direction_factors(prob)}
-    G = prob.n_groups
     cols = []
     for face in range(2 * prob.dim):
         kind = prob.bc[face]
         if kind not in (dense.FACE_INFLOW_PLANCK, dense.FACE_INFLOW_VALUES):
             continue
         axis, high = face // 2, face % 2
-        lam = prob.c * dt / (prob.extent[axis] / prob.n_cells[axis])
         layer = (idx[:, axis] == (N[axis] - 1 if high else 0)).astype(float)
-        sign = -1.0 if high else 1.0
-        z = (sign * lam * layer[:, None] * ghost[face][None, :]).reshape(-1)
-        g, h = terms[(axis, -1 if high else +1)]
-        cols.append((z, g, h))
+        for ax, g, h, c0, cm, cp in transport_terms(prob):
+            coef = cp if high else cm
+            if ax != axis or coef == 0.0:
+                continue
+            z = (coef * layer[:, None] * ghost[face][None, :]).reshape(-1)
+            cols.append((z, g, h))
     return cols
 
 
 def n_bc(prob) -> int:
-    return sum(1 for f in range(2 * prob.dim) if prob.bc[f] in (dense.FACE_INFLOW_PLANCK,
-                                                                 dense.FACE_INFLOW_VALUES))
+    return len(bc_columns(prob))
 
 
 def _assemble(blocksZ, blocksTh, blocksPh, n_theta):
@@ -141,14 +184,13 @@ def _assemble(blocksZ, blocksTh, blocksPh, n_theta):
 
 def apply_transport(prob, Z, Th, Ph):
     """I* = (identity + sum of the n rank-1 upwind operators) I + Dirichlet terms."""
-    dt = dense.time_step(prob)
     bZ, bT, bP = [Z], [Th], [Ph]
-    for axis, s, g, h in direction_factors(prob):
-        lam = prob.c * dt / (prob.extent[axis] / prob.n_cells[axis])
-        if s > 0:
-            SZ = -lam * (Z - shift(prob, Z, axis, -1))
-        else:
-            SZ = -lam * (shift(prob, Z, axis, +1) - Z)
+    for axis, g, h, c0, cm, cp in transport_terms(prob):
+        SZ = c0 * Z
+        if cm != 0.0:
+            SZ = SZ + cm * shift(prob, Z, axis, -1)
+        if cp != 0.0:
+            SZ = SZ + cp * shift(prob, Z, axis, +1)
         bZ.append(SZ)
         bT.append(Th * g[None, :, None])
         bP.append(Ph * h[None, :])
@@ -160,13 +202,24 @@ def apply_transport(prob, Z, Th, Ph):
 
 
 def apply_source(prob, Z, Th, Ph):
-    """Backward-Euler absorption/emission at fixed T: d * I + c dt kappa eps d."""
+    """Backward-Euler absorption/emission (and isotropic scattering) at fixed
+    T: d * I + d (c dt kappa eps + c dt kappa_s J^{m+1})."""
     dt = dense.time_step(prob)
     kap = dense.kappa_field(prob).reshape(-1)
     eps = dense.emission(prob).reshape(-1)
     a = prob.c * dt * kap
-    d = 1.0 / (1.0 + a)
-    bZ = [Z * d[:, None], (a * eps * d)[:, None]]
+    if getattr(prob, "kappa_s_full", None) is None:
+        d = 1.0 / (1.0 + a)
+        col = a * eps * d
+    else:
+        b = prob.c * dt * dense.kappa_s_field(prob).reshape(-1)
+        d = 1.0 / (1.0 + a + b)
+        # angle mean of the TT: J*[k] = (1 / 4 pi) sum_a Z[k, a] sum_{l,b,p} w_l Theta[a,l,b] Phi[b,p] w_p
+        e = np.einsum("alb,l,bp,p->a", Th, np.asarray(prob.w_theta, float), Ph, np.asarray(prob.w_phi, float))
+        J_star = Z @ e / (4.0 * np.pi)
+        J_new = (J_star + a * eps) / (1.0 + a)
+        col = (a * eps + b * J_new) * d
+    bZ = [Z * d[:, None], col[:, None]]
     bT = [Th, np.ones((1, prob.n_theta, 1))]
     bP = [Ph, np.ones((1, prob.n_phi))]
     return _assemble(bZ, bT, bP, prob.n_theta)

@@ -69,6 +69,9 @@ class Problem:
     heat_capacity: float = 0.0   # rho c_v per volume; 0: fixed medium temperature, > 0: coupled temperature
     T_rad0: Optional[np.ndarray] = None   # (N_X,) initial radiation temperature (None: T_cell)
     kappa_full: Optional[np.ndarray] = None   # (N_X, N_nu) opacity per cell and group (None: kappa0 x kappa_scale)
+    kappa_s_full: Optional[np.ndarray] = None  # (N_X, N_nu) isotropic scattering opacity (None: no scattering)
+    flux: int = 0                # streaming flux: 0 upwind, 1 Rusanov
+    rusanov_s: float = 1.0       # Rusanov wave speed S+ / c (1: S+ = c, 0: central differences)
 
     # ----- derived sizes (pure bookkeeping) -----
     @property
@@ -282,6 +285,39 @@ KB_CGS = 1.380649e-16
 
 def radiation_constant(c: float = 1.0) -> float:
     return 8.0 * math.pi ** 5 / (15.0 * c)
+
+
+FLUX_UPWIND, FLUX_RUSANOV = 0, 1
+
+
+def gaussian_diffusion(n_cells=128, n_groups=4, n_theta=16, ks_min=1000.0, ks_max=2000.0, width=0.25,
+                       cfl=1.0, tol=1e-8, rank_cap=16, precision=PREC_FP64, seed=0, n_steps=2400):
+    """1D Gaussian pulse diffusing through a purely scattering slab on
+    [-5, 5] (stored as [0, 10], x - 5 the physical coordinate): kappa_a = 0,
+    kappa_{s,g} ~ U[ks_min, ks_max] per group (seeded), the Rusanov flux with
+    S+ = 0, vacuum faces, c = 1.  The initial state (gaussian_initial) is the
+    isotropic field J_g(0, x) with 4 D_g t_{0,g} = width for every group, so all
+    groups start equal.  D_g = c / (3 kappa_{s,g})."""
+    rng = np.random.default_rng(seed)
+    ks = np.sort(rng.uniform(ks_min, ks_max, n_groups))
+    edges = log_group_edges(n_groups, 0.01, 10.0)
+    mu, wt, phi, wp = _angles(1, n_theta, 1, gl=True)
+    return Problem(
+        name="gaussian_diffusion", dim=1, n_cells=(n_cells, 1, 1), extent=(10.0, 1.0, 1.0), edges=edges,
+        kappa0=np.zeros(n_cells), kappa_scale=np.ones(n_groups), T_cell=np.zeros(n_cells), mu=mu, w_theta=wt,
+        phi=phi, w_phi=wp, bc=(BC_VACUUM, BC_VACUUM, 0, 0, 0, 0), bc_T=(0.0,) * 6, cfl=cfl, tol=tol,
+        rank_cap=rank_cap, precision=precision, n_steps=n_steps, seed=seed,
+        kappa_s_full=np.tile(ks, (n_cells, 1)), flux=FLUX_RUSANOV, rusanov_s=0.0)
+
+
+def gaussian_profile(prob, t: float, width: float = 0.25, A: float = 1.0) -> np.ndarray:
+    """(N_X, N_nu) closed-form mean intensity of the diffusing pulse at time t:
+    A / sqrt(4 pi D (t0 + t)) exp(-x^2 / (4 D (t0 + t))), with 4 D t0 = width."""
+    x = cell_centres(prob.n_cells, prob.extent)[:, 0] - 0.5 * prob.extent[0]
+    ks = np.asarray(prob.kappa_s_full, float).reshape(prob.n_x, prob.n_groups)[0]
+    D = prob.c / (3.0 * ks)
+    w = width + 4.0 * D * t              # 4 D (t0 + t)
+    return A / np.sqrt(np.pi * w)[None, :] * np.exp(-x[:, None] ** 2 / w[None, :])
 
 
 def thermal_relax(n_cells=1, n_theta=2, c_v=8.0, T=10.0, T_r=1.0, kappas=(10.0, 1.0, 0.1), k_hz=1.5e11,
