@@ -169,6 +169,15 @@ def mode_copy(args):
     print(json.dumps({"mode": "copy", "bytes_per_copy": n * 4, "copies": 8}), flush=True)
 
 
+def rusanov_scatter_problem(ti):
+    """plane2d with the Rusanov flux (S+ = c) and isotropic scattering
+    kappa_s = kappa_a (the absorption field of the same seed)."""
+    import numpy as np
+    prob = ti.plane2d()
+    ks = np.outer(prob.kappa0, prob.kappa_scale)
+    return prob.copy(flux=ti.FLUX_RUSANOV, rusanov_s=1.0, kappa_s_full=ks)
+
+
 def mode_probe(args):
     import torch
     import paper_2602_00290_amd as tt
@@ -178,6 +187,8 @@ def mode_probe(args):
     elif args.probe_workload == "plane2d_coupled":
         prob = ti.plane2d()
         prob = prob.copy(heat_capacity=8.0 * ti.radiation_constant(prob.c))
+    elif args.probe_workload == "plane2d_rusanov_scatter":
+        prob = rusanov_scatter_problem(ti)
     else:
         prob = ti.plane2d()
     s = tt.Solver(prob)
@@ -256,14 +267,18 @@ def main():
                     help="GPU_MAX_HW_QUEUES for this process (0: keep the environment's)")
     ap.add_argument("--mode", default="bench", choices=["bench", "probe", "copy", "pmc-summary", "served"])
     ap.add_argument("--probe-steps", type=int, default=64)
-    ap.add_argument("--probe-workload", default="plane2d", choices=["plane2d", "clumps3d", "plane2d_coupled"],
-                    help="probe workload: plane2d (FP32), clumps3d (64^3 cells, 64 groups, split BF16), or "
-                         "plane2d_coupled (plane2d with the coupled medium temperature, heat capacity 8 a)")
+    ap.add_argument("--probe-workload", default="plane2d",
+                    choices=["plane2d", "clumps3d", "plane2d_coupled", "plane2d_rusanov_scatter"],
+                    help="probe workload: plane2d (FP32), clumps3d (64^3 cells, 64 groups, split BF16), "
+                         "plane2d_coupled (plane2d with the coupled medium temperature, heat capacity 8 a), or "
+                         "plane2d_rusanov_scatter (plane2d with the Rusanov flux and scattering kappa_s = kappa_a)")
     ap.add_argument("--copy-mb", type=int, default=512)
     ap.add_argument("--pmc-dir", default=os.path.join(ROOT, "gpurun_out", "traffic"))
     ap.add_argument("--plain-fp64", type=int, default=1, help="also time the plain FP64 TT path on seed 0")
     ap.add_argument("--coupled", type=int, default=1,
                     help="also time seed 0 with the coupled medium temperature (heat capacity 8 a)")
+    ap.add_argument("--rusanov-scatter", type=int, default=1,
+                    help="also time seed 0 with the Rusanov flux and isotropic scattering (kappa_s = kappa_a)")
     ap.add_argument("--served", type=int, default=256,
                     help="requests of the served mix (0: skip the serving phase)")
     ap.add_argument("--served-budget-gb", type=float, default=64.0)
@@ -371,6 +386,24 @@ def main():
                    "couple_launches": nc, "T_mean": float(Tc.mean()), "T_max": float(Tc.max()),
                    "energy_total": stc["energy"] / pc.c + stc["medium_energy"]}
         sc.destroy()
+    # ---- phase 5: seed 0 with the Rusanov flux and isotropic scattering ----
+    rus = None
+    if args.rusanov_scatter:
+        pr = rusanov_scatter_problem(ti)
+        sr = tt.Solver(pr, device=dev, round_method=method)
+        sr.set_timing(True)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        str_ = sr.solve(K)
+        rus_s = time.perf_counter() - t5
+        nr = str_["kernel_launches"]["couple"]
+        rus = {"solves_per_s": 1.0 / rus_s, "ms": rus_s * 1e3, "timing": "HIP events on",
+               "flux": "Rusanov, S+ = c", "scattering": "kappa_s = kappa_a", "ranks": [str_["r1"], str_["r2"]],
+               "max_R": [str_["max_R1"], str_["max_R2"]],
+               "prepass_us_per_launch": str_["kernel_ms"]["couple"] / max(1, nr) * 1e3,
+               "kernel_us_per_launch": {c: str_["kernel_ms"][c] / str_["kernel_launches"][c] * 1e3
+                                        for c in tt.KERNEL_CLASSES if str_["kernel_launches"][c]}}
+        sr.destroy()
     lat_ms = np.array(lat) * 1e3
     out = {
         "metric": METRIC,
@@ -407,6 +440,8 @@ def main():
         out["plain_fp64"] = plain
     if coupled is not None:
         out["coupled_temperature"] = coupled
+    if rus is not None:
+        out["rusanov_scattering"] = rus
     if args.served > 0:
         out["served"] = served_phase(args)
     if not args.no_cpu_baseline:

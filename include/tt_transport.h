@@ -17,6 +17,11 @@
  *        I' = (I* + c dt kappa eps) / (1 + c dt kappa),   lambda_d = c dt / dx_d,
  *     as a sum of n = 2 d_X rank-1 TT operators plus rank-1 boundary and
  *     emission terms (Appendix A), so the ranks grow to (n+1) r + n_bc + 1.
+ *     Options: the Rusanov flux instead of upwind (tt_problem.flux), still
+ *     two rank-1 operators per axis (Appendix A, "Value of n"); isotropic
+ *     scattering (tt_problem.kappa_s_full), which enters the same rank-1
+ *     isotropic source column; and the coupled medium temperature
+ *     (tt_problem.heat_capacity).
  *   * Rank is restored by TT-SVD rounding (Oseledets 2011, the SVD rounding
  *     the paper uses, Section 3.1 footnote): right-to-left QR
  *     orthogonalisation, then left-to-right delta-truncated SVDs with
@@ -89,6 +94,12 @@ typedef enum {
 
 /* Problem statement (Section 2 and 2.1; quadrature and group conventions of
  * Section 4).  Faces are ordered x-, x+, y-, y+, z-, z+. */
+/* Streaming flux (Section 2.1 names upwind, Rusanov and HLL; HLL is not
+ * provided).  Rusanov: F_{i+1/2} = (c n_d / 2)(I_i + I_{i+1}) - (S+ / 2)(I_{i+1} - I_i)
+ * with S+ = rusanov_s * c; a ghost value enters both neighbours of every
+ * direction on an inflow face. */
+typedef enum { TT_FLUX_UPWIND = 0, TT_FLUX_RUSANOV = 1 } tt_flux;
+
 typedef struct tt_problem {
     int dim;                        /* 1, 2 or 3                                    */
     int n_cells[3];                 /* cells per axis (unused axes: 1)              */
@@ -139,6 +150,23 @@ typedef struct tt_problem {
                                        and the internal-structure discussion), or
                                        NULL for kappa0 x kappa_group_scale.  Copied
                                        to the workspace (N_X N_nu doubles more).  */
+    int flux;                       /* tt_flux (0: upwind)                          */
+    double rusanov_s;               /* S+ / c of the Rusanov flux, in [0, 1] (1: S+ = c;
+                                       0: central differences, the Gaussian
+                                       diffusion setting of Section 4)              */
+    const double* kappa_s_full;     /* N_X * N_nu isotropic scattering opacities
+                                       kappa_{s,g}(x) >= 0, row cell * N_nu + g, or
+                                       NULL for none.  The source update becomes
+                                       I' = (I* + a eps + b J') / (1 + a + b) with
+                                       a = c dt kappa, b = c dt kappa_s and
+                                       J' = (J* + a eps) / (1 + a) the angle mean
+                                       of the update (J* that of I*): a per-step
+                                       pre-pass computes J* from the cores.  Needs
+                                       paper_step_order 0; such a problem advances
+                                       only through solve / step_batch / solve_batch
+                                       (apply_op returns TT_ERR_STATE).  Adds 2 N_X
+                                       N_nu doubles of workspace (3 without a
+                                       coupled temperature).                        */
 } tt_problem;
 
 /* Statistics of the last solve / round (Section 3.2 metrics). */
@@ -157,7 +185,8 @@ typedef struct tt_stats {
                              is on: [0] prep, [1] project (first-core contraction),
                              [2] factor (TSQR or Gram), [3] factor tree / reduce,
                              [4] small-core SVD chain, [5] output contraction,
-                             [6] diagnostics, [7] coupled medium temperature        */
+                             [6] diagnostics, [7] source pre-pass (coupled medium
+                             temperature and / or scattering)                       */
     long long kernel_launches[8]; /* launches counted per class                      */
     double flops[8];      /* algorithmic flops per class, summed over the solve      */
     double medium_energy; /* dV * heat_capacity * sum_x T[x] (0 when T is fixed); the

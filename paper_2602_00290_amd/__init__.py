@@ -22,6 +22,7 @@ TT_OK, TT_ERR_INVALID_ARG, TT_ERR_OOM, TT_ERR_NUMERIC, TT_ERR_HIP, TT_ERR_STATE 
 TT_PREC_FP64, TT_PREC_FP32, TT_PREC_BF16X = 0, 1, 2
 TT_ROUND_QR, TT_ROUND_GRAM, TT_ROUND_AUTO = 0, 1, 2
 TT_BC_VACUUM, TT_BC_INFLOW_PLANCK, TT_BC_PERIODIC, TT_BC_INFLOW_VALUES = 0, 1, 2, 3
+TT_FLUX_UPWIND, TT_FLUX_RUSANOV = 0, 1
 
 KERNEL_CLASSES = ("prep", "project", "factor", "tree", "svd", "output", "diag", "couple")
 
@@ -57,6 +58,9 @@ class TTProblem(ctypes.Structure):
         ("heat_capacity", ctypes.c_double),
         ("T_rad0", _dp),
         ("kappa_full", _dp),
+        ("flux", ctypes.c_int),
+        ("rusanov_s", ctypes.c_double),
+        ("kappa_s_full", _dp),
     ]
 
 
@@ -218,6 +222,10 @@ class ProblemStruct:
         s.T_rad0 = ptr(getattr(prob, "T_rad0", None))
         kf = getattr(prob, "kappa_full", None)
         s.kappa_full = ptr(None if kf is None else np.asarray(kf, float).reshape(-1))
+        s.flux = int(getattr(prob, "flux", TT_FLUX_UPWIND))
+        s.rusanov_s = float(getattr(prob, "rusanov_s", 1.0))
+        ks = getattr(prob, "kappa_s_full", None)
+        s.kappa_s_full = ptr(None if ks is None else np.asarray(ks, float).reshape(-1))
         self.s = s
 
 

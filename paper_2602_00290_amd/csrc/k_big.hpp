@@ -14,6 +14,8 @@ struct RowData {
     const double* eps;      // M  (eps_g(T_cell))
     const double* ghost;    // 6 x N_nu isotropic ghost intensities
     const double* kfull;    // M opacities per (cell, group) row, or null for kappa0 x kscale
+    const double* kscat;    // M scattering opacities, or null (no scattering)
+    const double* jn;       // M angle means J^{m+1} of the source update (with scattering)
 };
 
 __device__ inline double row_kappa(const Geom& g, const RowData& rd, long long k) {
@@ -23,10 +25,18 @@ __device__ inline double row_kappa(const Geom& g, const RowData& rd, long long k
     return rd.kappa0[cell] * rd.kscale[grp];
 }
 
-// Value in row k of rank-1 column q of the operator (before the d scaling).
+// absorption plus scattering opacity of row k (the implicit source's denominator)
+__device__ inline double row_kappa_tot(const Geom& g, const RowData& rd, long long k) {
+    const double ka = row_kappa(g, rd, k);
+    return rd.kscat ? ka + rd.kscat[k] : ka;
+}
+
+// Value in row k of rank-1 column q of the operator (before the d scaling):
+// the isotropic source c dt (kappa eps + kappa_s J^{m+1}), or an inflow column.
 __device__ inline double rank1_value(const Geom& g, const OpDesc& op, const RowData& rd, long long k, int q) {
     if (op.r1kind[q] == 0) {
-        return g.cdt * row_kappa(g, rd, k) * rd.eps[k];
+        const double v = g.cdt * row_kappa(g, rd, k) * rd.eps[k];
+        return rd.kscat ? v + g.cdt * rd.kscat[k] * rd.jn[k] : v;
     }
     const int face = op.r1face[q];
     const int axis = face >> 1, high = face & 1;
@@ -35,12 +45,11 @@ __device__ inline double rank1_value(const Geom& g, const OpDesc& op, const RowD
     if (idx != (high ? n - 1 : 0)) return 0.0;
     const long long cell = k / g.G;
     const int grp = (int)(k - cell * g.G);
-    const double v = g.lam[axis] * rd.ghost[face * g.G + grp];
-    return high ? -v : v;
+    return op.r1coef[q] * rd.ghost[face * g.G + grp];
 }
 
 __device__ inline double row_scale(const Geom& g, const OpDesc& op, const RowData& rd, long long k) {
-    return op.scale_d ? 1.0 / (1.0 + g.cdt * row_kappa(g, rd, k)) : 1.0;
+    return op.scale_d ? 1.0 / (1.0 + g.cdt * row_kappa_tot(g, rd, k)) : 1.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -346,6 +355,11 @@ __global__ void k_materialize(Geom g, OpDesc op, const DevState* __restrict__ st
         if (col < op.n_rblk * r1) {
             const int t = col / r1, a = col % r1;
             v = op.rcoef0[t] * (double)Z[k * ldz + a];
+            if (op.rshift2[t] >= 0) {
+                const int j = op.rshift2[t];
+                const long long s = neighbour_row(g, k, op.gaxis[j], op.gdir[j]);
+                if (s >= 0) v += op.rcoef2[t] * (double)Z[s * ldz + a];
+            }
             if (op.rshift[t] >= 0) {
                 const int j = op.rshift[t];
                 const long long s = neighbour_row(g, k, op.gaxis[j], op.gdir[j]);

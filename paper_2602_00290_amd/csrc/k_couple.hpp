@@ -1,4 +1,12 @@
-// Coupled medium temperature (Section 2.1, the coupled source stage).
+// Source pre-pass: the coupled medium temperature (Section 2.1, the coupled
+// source stage) and isotropic scattering (the kappa_s term of the source
+// update).
+//
+// With scattering, J^{m+1} = (J* + a eps) / (1 + a) (a = c dt kappa; the
+// scattering term drops out of the angle mean of the update) enters the
+// isotropic source column c dt (kappa eps + kappa_s J^{m+1}); k_couple_pre
+// writes it per row, after the stage temperature when T is coupled and from
+// the fixed emission otherwise.
 //
 // Per step, around the rounding pass of the full operator:
 //   k_couple_pre   the angle means J* of the intensity after streaming (from
@@ -45,6 +53,8 @@ struct CoupleArgs {
     double heat_capacity;    // C_v = rho c_v
     double dt;
     double c;
+    int coupled;             // 1: solve for the stage temperature; 0: fixed emission
+    double* jn;              // M angle means J^{m+1} (with scattering) or null
 };
 
 // Lanes work in segments of the next power of two >= N_nu (at most 64): a
@@ -134,6 +144,7 @@ __global__ __launch_bounds__(kCoupleThreads) void k_couple_pre(Geom g, OpDesc op
                 const double m = Mt[(size_t)t * r1 + a];
                 if (j == 0) v += op.rcoef0[t] * m;
                 if (op.rshift[t] == j) v += op.rcoef[t] * m;
+                if (op.rshift2[t] == j) v += op.rcoef2[t] * m;
             }
         GJ[idx] = v;
     }
@@ -155,7 +166,7 @@ __global__ __launch_bounds__(kCoupleThreads) void k_couple_pre(Geom g, OpDesc op
     for (long long c0 = ((long long)blockIdx.x * 4 + w) * cpw; c0 < ncell; c0 += (long long)gridDim.x * 4 * cpw) {
         const long long cell = c0 + seg;
         if (cell >= ncell) continue;   // this segment has no cell (segments are independent)
-        const double Tm = ca.T[cell];
+        const double Tm = ca.coupled ? ca.T[cell] : 0.0;
         double F0 = 0.0, js1 = 0.0, coef1 = 0.0;
         for (int gg = gl; gg < G; gg += Gp) {
             const long long k = cell * G + gg;
@@ -169,72 +180,88 @@ __global__ __launch_bounds__(kCoupleThreads) void k_couple_pre(Geom g, OpDesc op
             for (int q = 0; q < nr1; ++q)
                 js += (ca.R1 ? (double)ca.R1[k * ca.rw1 + q] : rank1_value(g, op, rd, k, q)) * GJ[KG + q];
             ca.Js[k] = js;
-            const double kap = row_kappa(g, rd, k);
-            const double coef = 4.0 * M_PI * dt * kap / (1.0 + cdt * kap) / C;
-            F0 += coef * js;
             js1 = js;
-            coef1 = coef;
+            if (ca.coupled) {
+                const double kap = row_kappa(g, rd, k);
+                const double coef = 4.0 * M_PI * dt * kap / (1.0 + cdt * kap) / C;
+                F0 += coef * js;
+                coef1 = coef;
+            }
         }
-        F0 = seg_sum(F0, Gp);
-        // f(T) = Tm - T - sum_g coef_g (eps_g(T) - J*_g) and f'(T), summed over the segment;
-        // the lane keeps its last emission and derivative (e1, de1 at Te)
-        double e1 = 0.0, de1 = 0.0, Te = 0.0;
-        auto eval = [&](double Tt, double& f, double& df) {
-            double s = 0.0, ds = 0.0;
-            if (one) {
-                if (gl < G) {
-                    e1 = group_emission_1(ca.edges[gl], ca.edges[gl + 1], Tt, &de1);
-                    s = coef1 * (e1 - js1);
-                    ds = coef1 * de1;
+        double e1 = 0.0, de1 = 0.0, Te = 0.0, Tc = 0.0;
+        if (ca.coupled) {
+            F0 = seg_sum(F0, Gp);
+            // f(T) = Tm - T - sum_g coef_g (eps_g(T) - J*_g) and f'(T), summed over the segment;
+            // the lane keeps its last emission and derivative (e1, de1 at Te)
+            auto eval = [&](double Tt, double& f, double& df) {
+                double s = 0.0, ds = 0.0;
+                if (one) {
+                    if (gl < G) {
+                        e1 = group_emission_1(ca.edges[gl], ca.edges[gl + 1], Tt, &de1);
+                        s = coef1 * (e1 - js1);
+                        ds = coef1 * de1;
+                    }
+                } else {
+                    for (int gg = gl; gg < G; gg += Gp) {
+                        const long long k = cell * G + gg;
+                        const double kap = row_kappa(g, rd, k);
+                        const double coef = 4.0 * M_PI * dt * kap / (1.0 + cdt * kap) / C;
+                        double de;
+                        const double e = group_emission_1(ca.edges[gg], ca.edges[gg + 1], Tt, &de);
+                        s += coef * (e - ca.Js[k]);
+                        ds += coef * de;
+                    }
                 }
-            } else {
-                for (int gg = gl; gg < G; gg += Gp) {
-                    const long long k = cell * G + gg;
-                    const double kap = row_kappa(g, rd, k);
-                    const double coef = 4.0 * M_PI * dt * kap / (1.0 + cdt * kap) / C;
-                    double de;
-                    const double e = group_emission_1(ca.edges[gg], ca.edges[gg + 1], Tt, &de);
-                    s += coef * (e - ca.Js[k]);
-                    ds += coef * de;
-                }
-            }
-            Te = Tt;
-            s = seg_sum(s, Gp);
-            ds = seg_sum(ds, Gp);
-            f = Tm - Tt - s;
-            df = -1.0 - ds;
-        };
-        // Newton from T^m (the stage temperature is usually close to it) inside
-        // a bracket: f(0) >= 0, and f <= 0 at Tm + sum coef J* (eps >= 0), up to
-        // rounding, which the step-size stop below absorbs
-        const double Thi = fmax(fmax(Tm + F0, Tm), 1e-300);
-        double Tc = fmax(Tm, 1e-300);
-        double f, df;
-        eval(Tc, f, df);
-        double lo = f > 0.0 ? Tc : 0.0, hi = f > 0.0 ? fmax(Thi, Tc) : Tc;
-        for (int it = 0; it < 100 && f != 0.0; ++it) {
-            if (f > 0.0) lo = fmax(lo, Tc); else hi = fmin(hi, Tc);
-            const double step = f / df;
-            // a Newton step below 1e-14 of T is at the level of the rounding in
-            // f: take it and stop (testing it against the bracket instead would
-            // turn rounding noise into a bisection step)
-            if (fabs(step) <= 1e-14 * Tc) {
-                Tc -= step;
-                break;
-            }
-            double Tn = Tc - step;
-            if (!(Tn > lo && Tn < hi)) Tn = 0.5 * (lo + hi);
-            Tc = Tn;
+                Te = Tt;
+                s = seg_sum(s, Gp);
+                ds = seg_sum(ds, Gp);
+                f = Tm - Tt - s;
+                df = -1.0 - ds;
+            };
+            // Newton from T^m (the stage temperature is usually close to it) inside
+            // a bracket: f(0) >= 0, and f <= 0 at Tm + sum coef J* (eps >= 0), up to
+            // rounding, which the step-size stop below absorbs
+            const double Thi = fmax(fmax(Tm + F0, Tm), 1e-300);
+            Tc = fmax(Tm, 1e-300);
+            double f, df;
             eval(Tc, f, df);
-            if (hi - lo <= 1e-15 * hi) break;
+            double lo = f > 0.0 ? Tc : 0.0, hi = f > 0.0 ? fmax(Thi, Tc) : Tc;
+            for (int it = 0; it < 100 && f != 0.0; ++it) {
+                if (f > 0.0) lo = fmax(lo, Tc); else hi = fmin(hi, Tc);
+                const double step = f / df;
+                // a Newton step below 1e-14 of T is at the level of the rounding in
+                // f: take it and stop (testing it against the bracket instead would
+                // turn rounding noise into a bisection step)
+                if (fabs(step) <= 1e-14 * Tc) {
+                    Tc -= step;
+                    break;
+                }
+                double Tn = Tc - step;
+                if (!(Tn > lo && Tn < hi)) Tn = 0.5 * (lo + hi);
+                Tc = Tn;
+                eval(Tc, f, df);
+                if (hi - lo <= 1e-15 * hi) break;
+            }
         }
         // emission at T+: the last evaluation moved to T+ to first order
         // (|T+ - Te| <= 1e-14 T+, so the neglected term is ~1e-28 relative)
         for (int gg = gl; gg < G; gg += Gp) {
             const long long k = cell * G + gg;
-            const double e = one ? e1 + de1 * (Tc - Te) : group_emission_1(ca.edges[gg], ca.edges[gg + 1], Tc, nullptr);
-            ca.eps[k] = e;
-            const double v = cdt * row_kappa(g, rd, k) * e;
+            double e;
+            if (ca.coupled) {
+                e = one ? e1 + de1 * (Tc - Te) : group_emission_1(ca.edges[gg], ca.edges[gg + 1], Tc, nullptr);
+                ca.eps[k] = e;
+            } else {
+                e = rd.eps[k];
+            }
+            const double ka = row_kappa(g, rd, k);
+            double v = cdt * ka * e;
+            if (rd.kscat) {
+                const double jsk = one ? js1 : ca.Js[k];
+                const double jn = (jsk + cdt * ka * e) / (1.0 + cdt * ka);
+                ca.jn[k] = jn;
+                v += cdt * rd.kscat[k] * jn;
+            }
             if (ca.R1 && ca.qe1 >= 0) ca.R1[k * ca.rw1 + ca.qe1] = (float)v;
             if (ca.R2 && ca.qe2 >= 0) ca.R2[k * ca.rw2 + ca.qe2] = (float)v;
         }

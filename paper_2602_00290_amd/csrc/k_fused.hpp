@@ -78,7 +78,7 @@ __host__ __device__ inline size_t fused_lds_bytes(int nct, bool gram, int ngroup
 }
 
 // Per-row constants of the fused kernels, computed once per problem (T is
-// fixed): d_k = 1 / (1 + c dt kappa_k) in FP32 and the boundary mask of the
+// fixed): d_k = 1 / (1 + c dt (kappa_k + kappa_s,k)) in FP32 and the boundary mask of the
 // row's cell (bit 2a: first cell along axis a, bit 2a + 1: last cell).
 __global__ __launch_bounds__(256) void k_row_aux(Geom g, RowData rd, float2* __restrict__ aux) {
     const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_row_aux(Geom g, RowData rd, float2* __r
         if (idx == n - 1) mask |= 1 << (2 * a + 1);
     }
     float2 v;
-    v.x = (float)(1.0 / (1.0 + g.cdt * row_kappa(g, rd, k)));
+    v.x = (float)(1.0 / (1.0 + g.cdt * row_kappa_tot(g, rd, k)));
     v.y = __int_as_float(mask);
     aux[k] = v;
 }

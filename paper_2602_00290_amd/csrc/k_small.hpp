@@ -20,13 +20,16 @@ struct OpDesc {
     int rshift[kMaxBlocks];     // gather block holding the shifted copy (-1: none)
     double rcoef0[kMaxBlocks];  // coefficient on the unshifted Z
     double rcoef[kMaxBlocks];   // coefficient on the shifted copy
+    int rshift2[kMaxBlocks];    // second shifted copy (the other neighbour; -1: none)
+    double rcoef2[kMaxBlocks];
     int n_gather;               // gather blocks: 0 = Z itself, then shifted copies of Z
     int gaxis[kMaxBlocks];
     int gdir[kMaxBlocks];
     int n_r1;                   // rank-1 blocks (boundary columns, emission)
     int r1fac[kMaxBlocks];
-    int r1kind[kMaxBlocks];     // 0: emission c dt kappa eps, 1: inflow column
+    int r1kind[kMaxBlocks];     // 0: emission c dt kappa eps (+ scattering), 1: inflow column
     int r1face[kMaxBlocks];
+    double r1coef[kMaxBlocks];  // inflow column: value r1coef * ghost on the face's cell layer
     int scale_d;                // rows scaled by d = 1/(1 + c dt kappa)
 };
 
@@ -787,8 +790,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevSt
 
     // the operator's block tables in LDS: they are indexed per lane below, and
     // a per-lane index into the kernel arguments is a vector memory load
-    __shared__ int s_rfac[kMaxBlocks], s_rshift[kMaxBlocks], s_r1fac[kMaxBlocks];
-    __shared__ double s_rcoef0[kMaxBlocks], s_rcoef[kMaxBlocks];
+    __shared__ int s_rfac[kMaxBlocks], s_rshift[kMaxBlocks], s_rshift2[kMaxBlocks], s_r1fac[kMaxBlocks];
+    __shared__ double s_rcoef0[kMaxBlocks], s_rcoef[kMaxBlocks], s_rcoef2[kMaxBlocks];
     if (threadIdx.x == 0) {
         for (int i = 0; i < kMaxBlocks; ++i) {
             s_rfac[i] = op.rfac[i];
@@ -796,6 +799,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevSt
             s_r1fac[i] = op.r1fac[i];
             s_rcoef0[i] = op.rcoef0[i];
             s_rcoef[i] = op.rcoef[i];
+            s_rshift2[i] = op.rshift2[i];
+            s_rcoef2[i] = op.rcoef2[i];
         }
     }
     // the angular core and the per-node factor tables in LDS where they fit
@@ -925,6 +930,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevSt
                         const double l = LT[(size_t)(t * r1 + a) * ldL + col];
                         if (j == 0) v += s_rcoef0[t] * l;
                         if (s_rshift[t] == j) v += s_rcoef[t] * l;
+                        if (s_rshift2[t] == j) v += s_rcoef2[t] * l;
                     }
                 }
             } else {

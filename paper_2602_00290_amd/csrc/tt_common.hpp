@@ -7,7 +7,7 @@
 namespace ttrt {
 
 constexpr int kMaxTerms = 6;     // n = 2 d_X streaming terms
-constexpr int kMaxBC = 6;        // inflow faces
+constexpr int kMaxBC = 12;       // inflow columns: one per inflow face (upwind), two with the Rusanov dissipation
 constexpr int kMaxBlocks = 1 + kMaxTerms + kMaxBC + 1;
 
 // Which operator a rounding pass applies to the stored TT before truncating.

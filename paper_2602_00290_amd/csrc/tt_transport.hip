@@ -91,7 +91,11 @@ struct Plan {
     // coupled medium temperature (heat_capacity > 0)
     bool coupled = false;
     bool kfull = false;   // opacity given per (cell, group) row
-    size_t o_T = 0, o_T0 = 0, o_Js = 0, o_edges = 0, o_wth = 0, o_wph = 0;
+    bool kscat = false;   // isotropic scattering opacity given
+    bool prepass = false; // the source column depends on the state (coupled T or scattering)
+    int flux = 0;         // 0 upwind, 1 Rusanov
+    double rus_s = 1.0;   // Rusanov S+ / c
+    size_t o_T = 0, o_T0 = 0, o_Js = 0, o_edges = 0, o_wth = 0, o_wph = 0, o_kscat = 0, o_jn = 0;
     size_t k1sq = 1;                // k1cap x (k1cap | 1): SVD-chain matrices outside LDS
     // A2 scratch (doubles): the operand of the second-bond QR, the first-bond
     // matrix T outside LDS, or the second-bond Gram matrix
@@ -146,6 +150,11 @@ tt_status validate(const tt_problem* p) {
         return fail(TT_ERR_INVALID_ARG, "heat_capacity must be finite and >= 0");
     if (p->heat_capacity > 0.0 && p->paper_step_order != 0)
         return fail(TT_ERR_INVALID_ARG, "the coupled medium temperature needs paper_step_order == 0");
+    if (p->flux != TT_FLUX_UPWIND && p->flux != TT_FLUX_RUSANOV) return fail(TT_ERR_INVALID_ARG, "unknown flux");
+    if (p->flux == TT_FLUX_RUSANOV && !(p->rusanov_s >= 0.0 && p->rusanov_s <= 1.0))
+        return fail(TT_ERR_INVALID_ARG, "rusanov_s must lie in [0, 1]");
+    if (p->kappa_s_full && p->paper_step_order != 0)
+        return fail(TT_ERR_INVALID_ARG, "scattering needs paper_step_order == 0");
     return TT_OK;
 }
 
@@ -162,8 +171,12 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
     P.nt = p->n_theta;
     P.np = p->n_phi;
     P.n_terms = 2 * p->dim;
+    P.flux = p->flux;
+    P.rus_s = p->flux == TT_FLUX_RUSANOV ? p->rusanov_s : 0.0;
+    // inflow columns: one per inflow face; the Rusanov dissipation adds a second
+    const int per_face = (P.flux == TT_FLUX_RUSANOV && P.rus_s != 0.0) ? 2 : 1;
     P.n_bc = 0;
-    for (int f = 0; f < 2 * p->dim; ++f) P.n_bc += is_inflow(p->bc[f]) ? 1 : 0;
+    for (int f = 0; f < 2 * p->dim; ++f) P.n_bc += is_inflow(p->bc[f]) ? per_face : 0;
     P.cap = p->rank_cap;
     const long long full1 = std::min<long long>(P.M, (long long)P.nt * P.np);
     P.r1cap = (int)std::min<long long>(P.cap, full1);
@@ -313,11 +326,21 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
     P.o_PhN = take((size_t)P.R2cap * P.np * d);
     P.o_sv = take((size_t)(P.k1cap + P.k2cap) * d);
     P.o_colsum = take((size_t)256 * 128 * d);
-    if (p->heat_capacity > 0.0) {
-        // coupled medium temperature: T, its initial value, J* per row, edges and weights
-        P.coupled = true;
+    P.coupled = p->heat_capacity > 0.0;
+    P.kscat = p->kappa_s_full != nullptr;
+    P.prepass = P.coupled || P.kscat;
+    if (P.coupled) {
+        // coupled medium temperature: T and its initial value
         P.o_T = take((size_t)P.NX * d);
         P.o_T0 = take((size_t)P.NX * d);
+    }
+    if (P.kscat) {
+        // scattering opacity and J^{m+1} per row
+        P.o_kscat = take((size_t)P.M * d);
+        P.o_jn = take((size_t)P.M * d);
+    }
+    if (P.prepass) {
+        // source pre-pass: J* per row, group edges and quadrature weights
         P.o_Js = take((size_t)P.M * d);
         P.o_edges = take((size_t)(P.G + 1) * d);
         P.o_wth = take((size_t)P.nt * d);
@@ -382,7 +405,8 @@ struct tt_handle {
     double* Phn() const { return at<double>(ccur ? P.o_Ph0 : P.o_Ph1); }
     RowData rowdata() const {
         return RowData{at<double>(P.o_k0), at<double>(P.o_ks), at<double>(P.o_eps), at<double>(P.o_ghost),
-                       P.kfull ? at<double>(P.o_kfull) : nullptr};
+                       P.kfull ? at<double>(P.o_kfull) : nullptr, P.kscat ? at<double>(P.o_kscat) : nullptr,
+                       P.kscat ? at<double>(P.o_jn) : nullptr};
     }
     SmallScratch scratch() const {
         SmallScratch s;
@@ -450,7 +474,55 @@ void build_ops(tt_handle* h, const tt_problem* p) {
         o.n_gather = 1;
         const bool stream = kind == OP_FULL || kind == OP_TRANSPORT;
         const bool source = kind == OP_FULL || kind == OP_SOURCE;
-        if (stream) {
+        for (int i = 0; i < kMaxBlocks; ++i) o.rshift2[i] = -1;
+        if (stream && P.flux == TT_FLUX_RUSANOV) {
+            // per axis: (n_d) (-(lambda / 2)) (O_{d+} - O_{d-}) and, when S+ > 0,
+            // (1) (lambda s / 2) (O_{d+} - 2 I + O_{d-}); gather blocks c - e_d, c + e_d
+            const double sr = P.rus_s;
+            for (int axis = 0; axis < P.dim; ++axis) {
+                const double lam = h->geom.lam[axis];
+                const int jm = o.n_gather++, jp = o.n_gather++;
+                o.gaxis[jm] = axis;
+                o.gdir[jm] = -1;
+                o.gaxis[jp] = axis;
+                o.gdir[jp] = +1;
+                int t = o.n_rblk++;
+                o.rfac[t] = 1 + 2 * axis;
+                o.rcoef0[t] = 0.0;
+                o.rshift[t] = jm;
+                o.rcoef[t] = 0.5 * lam;
+                o.rshift2[t] = jp;
+                o.rcoef2[t] = -0.5 * lam;
+                if (sr != 0.0) {
+                    t = o.n_rblk++;
+                    o.rfac[t] = 2 + 2 * axis;
+                    o.rcoef0[t] = -lam * sr;
+                    o.rshift[t] = jm;
+                    o.rcoef[t] = 0.5 * lam * sr;
+                    o.rshift2[t] = jp;
+                    o.rcoef2[t] = 0.5 * lam * sr;
+                }
+            }
+            // a ghost enters each term of the face's axis through the coefficient
+            // of the shift that leaves the domain there
+            for (int f = 0; f < 2 * P.dim; ++f) {
+                if (!is_inflow(p->bc[f])) continue;
+                const int axis = f / 2, high = f & 1;
+                const double lam = h->geom.lam[axis];
+                int q = o.n_r1++;
+                o.r1kind[q] = 1;
+                o.r1face[q] = f;
+                o.r1fac[q] = 1 + 2 * axis;
+                o.r1coef[q] = high ? -0.5 * lam : 0.5 * lam;
+                if (sr != 0.0) {
+                    q = o.n_r1++;
+                    o.r1kind[q] = 1;
+                    o.r1face[q] = f;
+                    o.r1fac[q] = 2 + 2 * axis;
+                    o.r1coef[q] = 0.5 * lam * sr;
+                }
+            }
+        } else if (stream) {
             for (int axis = 0; axis < P.dim; ++axis) {
                 for (int sign = 1; sign >= -1; sign -= 2) {
                     const int t = o.n_rblk++;
@@ -471,6 +543,7 @@ void build_ops(tt_handle* h, const tt_problem* p) {
                 o.r1kind[q] = 1;
                 o.r1face[q] = f;
                 o.r1fac[q] = term_index(f / 2, (f & 1) ? -1 : +1);
+                o.r1coef[q] = (f & 1) ? -h->geom.lam[f / 2] : h->geom.lam[f / 2];
             }
         }
         if (source) {
@@ -798,6 +871,8 @@ CoupleArgs couple_args(tt_handle* h) {
     a.heat_capacity = h->heat_capacity;
     a.dt = h->dt;
     a.c = h->c;
+    a.coupled = P.coupled ? 1 : 0;
+    a.jn = P.kscat ? h->at<double>(P.o_jn) : nullptr;
     return a;
 }
 
@@ -826,6 +901,7 @@ tt_status coupled_step(tt_handle* h, hipStream_t s) {
     HIP_TRY(hipGetLastError());
     tt_status r = round_dispatch(h, OP_FULL, h->tol, P.cap, s);
     if (r != TT_OK) return r;
+    if (!P.coupled) return TT_OK;
     const size_t lds_post = (size_t)(P.r1cap + P.r2cap + 8) * sizeof(double);
     e = h->ev_begin(KC_COUPLE, s);
     hipLaunchKernelGGL(k_couple_post<T>, dim3(couple_grid(P, 2048)), dim3(kCoupleThreads), lds_post, s, h->geom,
@@ -837,7 +913,7 @@ tt_status coupled_step(tt_handle* h, hipStream_t s) {
 
 tt_status step_impl(tt_handle* h, hipStream_t s) {
     tt_status r;
-    if (h->P.coupled) {
+    if (h->P.prepass) {
         if (h->pending != OP_NONE) return fail(TT_ERR_STATE, "an unrounded operator is pending");
         return h->precision == TT_PREC_FP64 ? coupled_step<double>(h, s) : coupled_step<float>(h, s);
     }
@@ -1081,6 +1157,10 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
     for (long long i = 0; i < P.NX; ++i)
         if (!(p->T_cell[i] >= 0.0) || !std::isfinite(p->T_cell[i]))
             return fail(TT_ERR_INVALID_ARG, "T_cell must be finite and >= 0");
+    if (p->kappa_s_full)
+        for (long long k = 0; k < P.M; ++k)
+            if (!(p->kappa_s_full[k] >= 0.0) || !std::isfinite(p->kappa_s_full[k]))
+                return fail(TT_ERR_INVALID_ARG, "kappa_s_full must be finite and >= 0");
     if (p->kappa_full) {
         for (long long k = 0; k < P.M; ++k)
             if (!(p->kappa_full[k] >= 0.0) || !std::isfinite(p->kappa_full[k]))
@@ -1182,7 +1262,8 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
         if (p->bc[f] == TT_BC_INFLOW_VALUES)
             for (int gg = 0; gg < P.G; ++gg) ghost[(size_t)f * P.G + gg] = p->bc_values[(size_t)f * P.G + gg];
     }
-    // angular factors of each operator term: g(l) h(p) = positive / negative part of n_d
+    // angular factors of each operator term: g(l) h(p) = positive / negative part
+    // of n_d (upwind), or rows 1 + 2 d = n_d and 2 + 2 d = 1 (Rusanov)
     const int nf = 1 + P.n_terms;
     std::vector<double> gtab((size_t)nf * P.nt, 1.0), htab((size_t)nf * P.np, 1.0);
     for (int axis = 0; axis < P.dim; ++axis) {
@@ -1193,7 +1274,8 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
                 const double mu = p->mu[l];
                 const double st = std::sqrt(std::max(0.0, 1.0 - mu * mu));
                 double gv;
-                if (P.dim == 1 || axis == 2) gv = pos ? std::max(mu, 0.0) : std::min(mu, 0.0);
+                if (P.flux == TT_FLUX_RUSANOV) gv = pos ? ((P.dim == 1 || axis == 2) ? mu : st) : 1.0;
+                else if (P.dim == 1 || axis == 2) gv = pos ? std::max(mu, 0.0) : std::min(mu, 0.0);
                 else gv = st;
                 gtab[(size_t)t * P.nt + l] = gv;
             }
@@ -1201,7 +1283,8 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
                 double hv = 1.0;
                 if (P.dim > 1 && axis < 2) {
                     const double v = axis == 0 ? std::cos(p->phi[pp]) : std::sin(p->phi[pp]);
-                    hv = pos ? std::max(v, 0.0) : std::min(v, 0.0);
+                    if (P.flux == TT_FLUX_RUSANOV) hv = pos ? v : 1.0;
+                    else hv = pos ? std::max(v, 0.0) : std::min(v, 0.0);
                 }
                 htab[(size_t)t * P.np + pp] = hv;
             }
@@ -1224,9 +1307,15 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
     if ((u = upload(h->at<double>(P.o_ghost), ghost, s)) != TT_OK) { delete h; return u; }
     if ((u = upload(h->at<double>(P.o_gtab), gtab, s)) != TT_OK) { delete h; return u; }
     if ((u = upload(h->at<double>(P.o_htab), htab, s)) != TT_OK) { delete h; return u; }
-    if (P.coupled) {
-        std::vector<double> edges(p->group_edges, p->group_edges + P.G + 1);
+    if (P.kscat) {
+        std::vector<double> ksv(p->kappa_s_full, p->kappa_s_full + P.M);
+        if ((u = upload(h->at<double>(P.o_kscat), ksv, s)) != TT_OK) { delete h; return u; }
+        if (hipMemsetAsync(h->ws + P.o_jn, 0, (size_t)P.M * sizeof(double), s) != hipSuccess) { delete h; return fail(TT_ERR_HIP, "memset"); }
+    }
+    if (P.coupled)
         if ((u = upload(h->at<double>(P.o_T0), h->T_host, s)) != TT_OK) { delete h; return u; }
+    if (P.prepass) {
+        std::vector<double> edges(p->group_edges, p->group_edges + P.G + 1);
         if ((u = upload(h->at<double>(P.o_edges), edges, s)) != TT_OK) { delete h; return u; }
         if ((u = upload(h->at<double>(P.o_wth), h->w_theta, s)) != TT_OK) { delete h; return u; }
         if ((u = upload(h->at<double>(P.o_wph), h->w_phi, s)) != TT_OK) { delete h; return u; }
@@ -1259,7 +1348,8 @@ tt_status tt_transport_apply_op(tt_handle* h, void* stream) {
     (void)stream;
     if (!h) return fail(TT_ERR_INVALID_ARG, "handle is NULL");
     if (h->pending != OP_NONE) return fail(TT_ERR_STATE, "an unrounded operator is already pending");
-    if (h->P.coupled) return fail(TT_ERR_STATE, "a coupled-temperature problem advances only by whole steps (solve / step_batch)");
+    if (h->P.prepass)
+        return fail(TT_ERR_STATE, "a coupled-temperature or scattering problem advances only by whole steps (solve / step_batch)");
     h->pending = h->step_order == 1 ? OP_TRANSPORT : OP_FULL;
     return TT_OK;
 }

@@ -115,3 +115,18 @@ def test_kappa_full_validation(tt):
     with pytest.raises(tt.TTError) as e:
         tt.workspace_bytes(p.copy(kappa0=None))
     assert e.value.status == tt.TT_ERR_INVALID_ARG
+
+
+def test_flux_and_scattering_validation(tt):
+    p = ti.slab1d(n_cells=16, n_groups=4, n_theta=4)
+    ks = np.ones((16, 4))
+    base = tt.workspace_bytes(p)
+    # scattering: the opacity, J^{m+1} and the pre-pass rows (3 N_X N_nu doubles)
+    assert tt.workspace_bytes(p.copy(kappa_s_full=ks)) >= base + 3 * 16 * 4 * 8
+    assert tt.workspace_bytes(p.copy(flux=ti.FLUX_RUSANOV, rusanov_s=0.0)) > 0
+    for bad in (p.copy(flux=2), p.copy(flux=ti.FLUX_RUSANOV, rusanov_s=1.5),
+                p.copy(flux=ti.FLUX_RUSANOV, rusanov_s=float("nan")),
+                p.copy(kappa_s_full=ks, step_order=1)):
+        with pytest.raises(tt.TTError) as e:
+            tt.workspace_bytes(bad)
+        assert e.value.status == tt.TT_ERR_INVALID_ARG
