@@ -73,10 +73,16 @@ def cpu_baseline(prob, budget_s: float = 12.0):
         steps += 4
     dt = time.perf_counter() - t0
     per_step = dt / steps
+    # the same march on one host core, over a few steps
+    t1 = time.perf_counter()
+    dense.march(prob, I, 4, n_threads=1)
+    one = (time.perf_counter() - t1) / 4
     return {
         "value": 1.0 / (per_step * prob.n_steps),
         "unit": "solves/s",
         "cores": nthr,
+        "one_core": {"ms_per_step": one * 1e3, "solves_per_s": 1.0 / (one * prob.n_steps),
+                     "dof_updates_per_s": prob.dense_entries / one, "sample": "4 steps, 1 thread"},
         "kind": "oracle",
         "sample": f"dense FP64 upwind march (C/OpenMP), {steps} of {prob.n_steps} steps of the same workload "
                   f"({prob.dense_entries} entries), {per_step * 1e3:.1f} ms/step, "
@@ -131,6 +137,22 @@ def roofline(st1):
            "flops_per_launch": {"fp32": f32 / n["project"], "fp64": f64 / n["project"]}}
     if t:
         out["traffic_detail"] = {k: t[k] for k in ("fetch_bytes", "write_bytes", "algorithmic_bytes")}
+    return out
+
+
+def kernel_hbm(st1, M):
+    """Achieved algorithmic HBM rate of the two first-core kernels from the
+    single-solve event timing, with the minimum bytes of each launch at the
+    final ranks: the projection reads the state Z (M r1 FP32 values), the
+    output kernel reads Z and writes Z_out (2 M r1 values)."""
+    ms, n = st1["kernel_ms"], st1["kernel_launches"]
+    r1 = st1["r1"]
+    out = {}
+    for cls, words in (("project", 1), ("output", 2)):
+        if n[cls] and ms[cls]:
+            t = ms[cls] / n[cls] * 1e-3
+            out[cls] = {"GB_per_s": words * M * r1 * 4 / t / 1e9, "bytes_per_launch": words * M * r1 * 4,
+                        "avg_launch_us": t * 1e6}
     return out
 
 
@@ -434,6 +456,7 @@ def main():
         "kernel_ms_per_solve": {c: agg_ms[c] for c in tt.KERNEL_CLASSES if agg_n[c]},
         "kernel_us_per_launch": {c: agg_ms[c] / agg_n[c] * 1e3 for c in tt.KERNEL_CLASSES if agg_n[c]},
         "roofline": roofline(st1),
+        "hbm_algorithmic": kernel_hbm(st1, prob.M),
         "internal_ranks": internal,
     }
     if plain:

@@ -142,3 +142,21 @@ def test_scattering_problem_rejects_apply_op_and_bad_inputs(tt):
     with pytest.raises(tt.TTError) as e:
         tt.Solver(p.copy(kappa_s_full=bad))
     assert e.value.status == tt.TT_ERR_INVALID_ARG
+
+
+def test_plane2d_full_size_rusanov_scattering_one_step_fp32(tt):
+    # the 2D workload at full size (128 x 128 cells, 32 groups, 8 x 8 angles,
+    # FP32 fused path, cap 32) with the Rusanov flux (S+ = c) and kappa_s =
+    # kappa_a, as the benchmark times it: one step from a seeded rank-(32, 8)
+    # state against the oracle's TT step
+    p = ti.plane2d()
+    p = p.copy(flux=ti.FLUX_RUSANOV, rusanov_s=1.0, kappa_s_full=np.outer(p.kappa0, p.kappa_scale))
+    s = tt.Solver(p)
+    Z, Th, Ph = ti.random_tt(p.M, 8, 8, 32, 8, seed=3, decay=0.8)
+    s.set_cores(Z, Th, Ph)
+    s.solve(1)
+    Zo, To, Po, info = ott.step(p, Z, Th, Ph)
+    r1, r2 = s.get_ranks()
+    assert (r1, r2) == (info["r1"], info["r2"])
+    assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 2e-6
+    s.destroy()
