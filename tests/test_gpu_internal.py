@@ -153,3 +153,23 @@ def test_error_paths(tt):
         s.internal_ranks(1e-3)
     assert e.value.status == tt.TT_ERR_INVALID_ARG
     s.destroy()
+
+
+def test_gaussian_diffusion_internal_rank_one_when_gray(tt):
+    # equal scattering opacities in every group make the multigroup diffusion a
+    # gray problem scaled per group: r_nux = 1; a spread of opacities makes the
+    # groups diffuse at different rates and r_nux > 1 (the Gaussian diffusion
+    # discussion of the internal ranks)
+    base = ti.gaussian_diffusion(n_cells=96, n_groups=4, n_theta=8, tol=1e-10, rank_cap=12)
+    J0 = ti.gaussian_profile(base, 0.0).reshape(-1)
+    out = {}
+    for name, ks_max in (("gray", 1000.0), ("spread", 5000.0)):
+        p = ti.gaussian_diffusion(n_cells=96, n_groups=4, n_theta=8, tol=1e-10, rank_cap=12,
+                                  ks_min=1000.0, ks_max=ks_max)
+        s = tt.Solver(p)
+        s.set_cores(J0[:, None], np.ones((1, p.n_theta, 1)), np.ones((1, 1)))
+        s.solve(400)
+        out[name] = s.internal_ranks(1e-5)
+        s.destroy()
+    assert out["gray"]["r_nux"] == 1
+    assert out["spread"]["r_nux"] > 1
