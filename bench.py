@@ -220,6 +220,45 @@ def mode_probe(args):
                       "ranks": [st["r1"], st["r2"]]}), flush=True)
 
 
+def mode_c5_slab(args):
+    """The 256^3 spike workload on one GPU's share: a 256 x 256 x 32 z-slab
+    (128 groups, 16 x 16 directions, split BF16), at the largest rank cap whose
+    projected rank fits the SVD chain (k1 <= 128: cap 18).  Untimed steps until
+    the ranks reach the cap, then --steps timed steps with HIP-event kernel
+    timing."""
+    import torch
+    import paper_2602_00290_amd as tt
+    import tt_inputs as ti
+    prob = ti.spikes3d_slab(rank_cap=args.c5_cap)
+    ws = tt.workspace_bytes(prob)
+    print(json.dumps({"mode": "c5-slab", "phase": "setup", "rows": prob.M, "workspace_gb": ws / 2 ** 30}),
+          flush=True)
+    s = tt.Solver(prob)
+    warm = 0
+    while warm < args.c5_warmup:
+        st = s.solve(1)
+        warm += 1
+        print(json.dumps({"phase": "warmup", "step": warm, "ranks": [st["r1"], st["r2"]],
+                          "ms": st["seconds"] * 1e3}), flush=True)
+        if st["r1"] >= prob.rank_cap and warm >= 4:
+            break
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = s.solve(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    n = st["kernel_launches"]
+    print(json.dumps({
+        "mode": "c5-slab", "workload": "spikes3d z-slab 256 x 256 x 32 cells (1/8 of the 256^3 cube), 128 groups, "
+                                       "16 x 16 directions, split BF16 contractions, FP64 rounding, tol 1e-5",
+        "rows": prob.M, "rank_cap": prob.rank_cap, "warmup_steps": warm, "steps": args.steps,
+        "ms_per_step": el / args.steps * 1e3, "ranks": [st["r1"], st["r2"]], "max_R": [st["max_R1"], st["max_R2"]],
+        "compression": st["compression"], "workspace_gb": ws / 2 ** 30, "timing": "HIP events on",
+        "kernel_ms_per_step": {c: st["kernel_ms"][c] / args.steps for c in tt.KERNEL_CLASSES if n[c]},
+        "flops_per_step": sum(st["flops"].values()) / args.steps}), flush=True)
+
+
 def _pmc_rows(path, counter):
     rows = []
     for fn in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
@@ -287,7 +326,9 @@ def main():
     ap.add_argument("--streams", type=int, default=16, help="HIP streams for the batch")
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="GPU_MAX_HW_QUEUES for this process (0: keep the environment's)")
-    ap.add_argument("--mode", default="bench", choices=["bench", "probe", "copy", "pmc-summary", "served"])
+    ap.add_argument("--mode", default="bench", choices=["bench", "probe", "copy", "pmc-summary", "served", "c5-slab"])
+    ap.add_argument("--c5-cap", type=int, default=18, help="rank cap of --mode c5-slab")
+    ap.add_argument("--c5-warmup", type=int, default=40, help="at most this many untimed steps in --mode c5-slab")
     ap.add_argument("--probe-steps", type=int, default=64)
     ap.add_argument("--probe-workload", default="plane2d",
                     choices=["plane2d", "clumps3d", "plane2d_coupled", "plane2d_rusanov_scatter"],
@@ -320,6 +361,8 @@ def main():
         return mode_copy(args)
     if args.mode == "probe":
         return mode_probe(args)
+    if args.mode == "c5-slab":
+        return mode_c5_slab(args)
     if args.mode == "served":
         print(json.dumps({"mode": "served", **served_phase(args)}), flush=True)
         return

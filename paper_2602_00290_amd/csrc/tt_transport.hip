@@ -85,6 +85,7 @@ struct Plan {
     size_t o_Gh = 0, o_Gl = 0, o_Vh = 0, o_Vl = 0;
     int rw1 = 0, rw2 = 0;           // widths of the rank-1 row blocks (transport / source operators)
     bool fused_overflow = false;
+    bool row_tables = false;        // per-row d, neighbour and rank-1 tables (fused and split-BF16 paths)
     size_t o_state, o_Z0, o_Z1, o_B, o_Th0, o_Th1, o_Ph0, o_Ph1, o_LTh, o_QTh, o_QPh, o_G, o_V, o_RA, o_RB, o_small,
         o_k0, o_ks, o_kfull = 0, o_eps, o_ghost, o_gtab, o_htab, o_ThN, o_PhN, o_sv, o_colsum;
     size_t small_bytes = 0, n_parts_max = 1;
@@ -257,6 +258,8 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         P.B_bytes = std::min<size_t>(P.B_bytes, std::max<size_t>((size_t)16 << 20, (size_t)P.R1cap * sizeof(double)));
     P.o_B = take(P.B_bytes);
     P.bf16x = p->precision == TT_PREC_BF16X;
+    if (P.bf16x && P.M >= (1LL << 31))
+        return fail(TT_ERR_INVALID_ARG, "split-BF16 contractions need fewer than 2^31 rows of Z");
     if (P.bf16x) {
         P.nct_b = P.ldbcap <= 64 ? 4 : 8;
         P.nct_bo = P.ldzcap <= 32 ? 2 : 4;
@@ -272,6 +275,9 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         P.o_Gsw = take((size_t)P.fused_T * P.nct_p * 256 * sizeof(float));
         P.o_Gfold = take((size_t)P.fused_T * P.nct_o * 256 * sizeof(float));
         P.o_GP = take((size_t)P.fused_blocks * gram_blocks(P.nct_p) * 256 * d);
+    }
+    P.row_tables = P.fused || P.bf16x;
+    if (P.row_tables) {
         P.o_aux = take((size_t)P.M * sizeof(float2));
         // rank-1 columns as dense row blocks: the full (or transport) operator, and
         // the source operator when the paper's step order is used
@@ -719,14 +725,20 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
             __bf16* gl = h->at<__bf16>(P.o_Gl);
             hipLaunchKernelGGL(k_split_bf16, dim3(64), dim3(256), 0, s, (const DevState*)st, 0, (const float*)Gop,
                                16 * P.nct_b, P.kc_g, gh, gl);
+            // the operator's rank-1 block: the source operator's, or the full
+            // (transport, with the paper's step order) operator's
+            const bool srcop = opkind == OP_SOURCE;
+            if ((srcop ? P.rw2 : P.rw1) < op.n_r1) return fail(TT_ERR_STATE, "no rank-1 row block for this operator");
+            const BxRows rows{h->at<float2>(P.o_aux), h->at<int>(P.o_nbr), P.n_terms,
+                              h->at<float>(srcop ? P.o_R2 : P.o_R1), srcop ? P.rw2 : P.rw1};
             if (P.nct_b == 8)
                 hipLaunchKernelGGL((k_gemm_bf16x<MODE_PROJECT, 8>), dim3(gx128), dim3(256), 0, s, h->geom, op,
                                    (const DevState*)st, (const float*)h->Zc(), (const __bf16*)gh, (const __bf16*)gl,
-                                   (float*)B, h->rowdata());
+                                   (float*)B, rows);
             else
                 hipLaunchKernelGGL((k_gemm_bf16x<MODE_PROJECT, 4>), dim3(gx128), dim3(256), 0, s, h->geom, op,
                                    (const DevState*)st, (const float*)h->Zc(), (const __bf16*)gh, (const __bf16*)gl,
-                                   (float*)B, h->rowdata());
+                                   (float*)B, rows);
         } else {
             hipLaunchKernelGGL((k_gemm_f32_mfma<MODE_PROJECT, 64>), dim3(gx128, (P.ldbcap + 63) / 64), dim3(256), 0, s,
                                h->geom, op, (const DevState*)st, (const float*)h->Zc(), (const float*)Gop, (float*)B,
@@ -820,11 +832,11 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
             if (P.nct_bo == 4)
                 hipLaunchKernelGGL((k_gemm_bf16x<MODE_OUTPUT, 4>), dim3(gx128), dim3(256), 0, s, h->geom, op,
                                    (const DevState*)st, (const float*)B, (const __bf16*)vh, (const __bf16*)vl,
-                                   (float*)h->Zn(), h->rowdata());
+                                   (float*)h->Zn(), BxRows{});
             else
                 hipLaunchKernelGGL((k_gemm_bf16x<MODE_OUTPUT, 2>), dim3(gx128), dim3(256), 0, s, h->geom, op,
                                    (const DevState*)st, (const float*)B, (const __bf16*)vh, (const __bf16*)vl,
-                                   (float*)h->Zn(), h->rowdata());
+                                   (float*)h->Zn(), BxRows{});
         } else if (P.ldzcap <= 32)
             hipLaunchKernelGGL((k_gemm_f32_mfma<MODE_OUTPUT, 32>), dim3(gx128, 1), dim3(256), 0, s, h->geom, op,
                                (const DevState*)st, (const float*)B, (const float*)V, (float*)h->Zn(), h->rowdata());
@@ -860,13 +872,13 @@ CoupleArgs couple_args(tt_handle* h) {
     a.T = h->at<double>(P.o_T);
     a.Js = h->at<double>(P.o_Js);
     a.eps = h->at<double>(P.o_eps);
-    a.R1 = (P.fused && P.rw1 > 0) ? h->at<float>(P.o_R1) : nullptr;
+    a.R1 = (P.row_tables && P.rw1 > 0) ? h->at<float>(P.o_R1) : nullptr;
     a.rw1 = P.rw1;
     a.qe1 = h->qe_full;
-    a.R2 = (P.fused && P.rw2 > 0) ? h->at<float>(P.o_R2) : nullptr;
+    a.R2 = (P.row_tables && P.rw2 > 0) ? h->at<float>(P.o_R2) : nullptr;
     a.rw2 = P.rw2;
     a.qe2 = h->qe_source;
-    a.nbr = P.fused ? h->at<int>(P.o_nbr) : nullptr;
+    a.nbr = P.row_tables ? h->at<int>(P.o_nbr) : nullptr;
     a.ns = P.n_terms;
     a.heat_capacity = h->heat_capacity;
     a.dt = h->dt;
@@ -1321,7 +1333,7 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
         if ((u = upload(h->at<double>(P.o_wph), h->w_phi, s)) != TT_OK) { delete h; return u; }
     }
     if (hipMemsetAsync(h->ws + P.o_G, 0, P.o_V - P.o_G, s) != hipSuccess) { delete h; return fail(TT_ERR_HIP, "memset"); }
-    if (P.fused) {
+    if (P.row_tables) {
         if (hipMemsetAsync(h->ws + P.o_zero, 0, 1024, s) != hipSuccess) { delete h; return fail(TT_ERR_HIP, "memset"); }
         const dim3 gr((unsigned)((P.M + 255) / 256));
         hipLaunchKernelGGL(k_row_aux, gr, dim3(256), 0, s, h->geom, h->rowdata(), h->at<float2>(P.o_aux));

@@ -378,6 +378,19 @@ def spikes3d(n=256, n_groups=128, n_theta=16, n_phi=16, T=0.1, T_b=1.0, tol=1e-5
         rank_cap=rank_cap, precision=precision, n_steps=n_steps, seed=seed)
 
 
+def spikes3d_slab(n=256, nz=32, slab=0, n_groups=128, n_theta=16, n_phi=16, T=0.1, T_b=1.0, tol=1e-5,
+                  rank_cap=18, precision=PREC_BF16X, n_steps=8, cfl=0.5, seed=0, nu=(0.01, 10.0)):
+    """One z-slab (n x n x nz cells) of the spikes3d cube: the share of one GPU
+    when the cube is split into n / nz slabs along z.  The opacity field is the
+    cube's (same seed), cut to the slab; the slab's z faces are vacuum (in a
+    split run they would be exchanged halos).  Cells keep the cube's spacing."""
+    cube = spikes3d(n=n, n_groups=n_groups, n_theta=n_theta, n_phi=n_phi, T=T, T_b=T_b, tol=tol,
+                    rank_cap=rank_cap, precision=precision, n_steps=n_steps, cfl=cfl, seed=seed, nu=nu)
+    k0 = np.asarray(cube.kappa0).reshape(n, n, n)[slab * nz:(slab + 1) * nz].ravel().copy()
+    return cube.copy(name="spikes3d_slab", n_cells=(n, n, nz), extent=(1.0, 1.0, nz / n), kappa0=k0,
+                     T_cell=np.full(n * n * nz, float(T)))
+
+
 def served_requests(n_requests=256, seed=0, steps=64):
     """Request mix of the served batch: half 1D (16 GL mu), half 2D (8x8); cells per
     dimension ~ U{64..256}; groups ~ U{16..64}; rank caps ~ U{4..48}; seeded kappa0."""
