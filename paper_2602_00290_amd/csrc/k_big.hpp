@@ -406,23 +406,39 @@ __global__ void k_sum_small_cores(Geom g, OpDesc op, const DevState* __restrict_
     }
 }
 
-// Column sums of Z (r1 entries) and the NaN/Inf check, for diagnostics.
+// Column sums of Z (r1 entries), for diagnostics: one pass over Z.  Block b
+// of 1024 threads sums rows b*16 + rl (rl = thread / 64) with stride 16 *
+// gridDim.x, four rows in flight per lane; lane c of a wave holds column
+// c0 + c (64-column tiles), so a wave reads contiguous row segments.  The 16
+// row lanes are added in a fixed order and the block writes parts[b * 128 + a]
+// (the host adds the blocks).
 template <typename TS>
-__global__ void k_colsum(const DevState* __restrict__ st, const TS* __restrict__ Z, long long M,
-                         double* __restrict__ parts) {
+__global__ __launch_bounds__(1024) void k_colsum(const DevState* __restrict__ st, const TS* __restrict__ Z, long long M,
+                                                 double* __restrict__ parts) {
     const int r1 = st->r1, ldz = st->ldz;
-    __shared__ double sh[256];
-    for (int a = 0; a < r1; ++a) {
-        double s = 0.0;
-        for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < M; k += (long long)gridDim.x * blockDim.x)
-            s += (double)Z[k * ldz + a];
-        sh[threadIdx.x] = s;
-        __syncthreads();
-        for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-            if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-            __syncthreads();
+    __shared__ double sh[16][64];
+    const int c = threadIdx.x & 63, rl = threadIdx.x >> 6;
+    const long long stride = (long long)gridDim.x * 16;
+    for (int c0 = 0; c0 < r1; c0 += 64) {
+        const int a = c0 + c;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        if (a < r1) {
+            long long k = (long long)blockIdx.x * 16 + rl;
+            for (; k + 3 * stride < M; k += 4 * stride) {
+                s0 += (double)Z[k * ldz + a];
+                s1 += (double)Z[(k + stride) * ldz + a];
+                s2 += (double)Z[(k + 2 * stride) * ldz + a];
+                s3 += (double)Z[(k + 3 * stride) * ldz + a];
+            }
+            for (; k < M; k += stride) s0 += (double)Z[k * ldz + a];
         }
-        if (threadIdx.x == 0) parts[(size_t)blockIdx.x * 128 + a] = sh[0];
+        sh[rl][c] = (s0 + s1) + (s2 + s3);
+        __syncthreads();
+        if (rl == 0 && a < r1) {
+            double t = 0.0;
+            for (int i = 0; i < 16; ++i) t += sh[i][c];
+            parts[(size_t)blockIdx.x * 128 + a] = t;
+        }
         __syncthreads();
     }
 }

@@ -951,7 +951,7 @@ tt_status energy_impl(tt_handle* h, hipStream_t s, double* energy, int* nanflag)
     tt_status r = read_state(h, st, s);
     if (r != TT_OK) return r;
     double* parts = h->at<double>(P.o_colsum);
-    hipLaunchKernelGGL(k_colsum<T>, dim3(256), dim3(256), 0, s, (const DevState*)h->st(), (const T*)h->Zc(), P.M, parts);
+    hipLaunchKernelGGL(k_colsum<T>, dim3(256), dim3(1024), 0, s, (const DevState*)h->st(), (const T*)h->Zc(), P.M, parts);
     HIP_TRY(hipGetLastError());
     std::vector<double> hp((size_t)256 * 128);
     std::vector<double> th((size_t)st.r1 * P.nt * st.r2), ph((size_t)st.r2 * P.np);
