@@ -10,34 +10,29 @@ namespace ttrt {
 // (the unfused Gram path for wide cores, k1 up to 128).  A block walks its
 // rows in chunks of 64: each chunk is loaded with coalesced 16-byte loads (the
 // next chunk's loads are in flight while the current one computes) and staged
-// in LDS.  Wave w of the 4 owns the upper 16 x 16 blocks of block rows w and
-// 7 - w (9 blocks each, balanced); its A operands are read from LDS at a
-// wave-uniform column, the B operands of all 8 column groups with
-// compile-time indices, and blocks left of the diagonal are skipped by a
-// scalar branch.  Each block writes its compact partial (36 blocks x 4
-// registers x 64 lanes) for k_sum_gram<8>.
-__global__ __launch_bounds__(256) void k_gram_f64_mfma_w8(const float* __restrict__ B, const DevState* __restrict__ st,
-                                                           long long nrows, long long rows_per_block,
-                                                           double* __restrict__ Gpart) {
+// in LDS.  Wave W of the 4 owns the upper 16 x 16 blocks of block rows W and
+// 7 - W (9 blocks each, balanced).  Each wave runs its own instantiation of
+// the loop with the block rows fixed at compile time, so only its 9
+// accumulators are live (three waves per SIMD instead of two); its A operands
+// are read from LDS at fixed columns and the B operands of the column groups
+// it needs.  Each block writes its compact partial (36 blocks x 4 registers x
+// 64 lanes) for k_sum_gram<8>.
+template <int W>
+__device__ __forceinline__ void gram_w8_wave(const float* __restrict__ B, int ldb, long long begin, long long end,
+                                             float* Bs, double* __restrict__ outp) {
     constexpr int NCT = 8;
-    constexpr int NB = gram_blocks(NCT);
     constexpr int NC = 16 * NCT;              // columns
     constexpr int CH = 64;                    // rows per chunk
     constexpr int LDC = NC + 4;               // LDS row stride (floats)
     constexpr int V4 = CH * NC / 4 / 256;     // float4 loads per thread per chunk
-    __shared__ float Bs[CH * LDC];
-    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-    const int ldb = st->ldb;
-    const long long begin = (long long)blockIdx.x * rows_per_block;
-    long long end = begin + rows_per_block;
-    if (end > nrows) end = nrows;
-    const int gaA = w, gaB = NCT - 1 - w;     // this wave's two block rows
-    f64x4 accA[NCT], accB[NCT];
+    constexpr int GA = W, GB = NCT - 1 - W;   // this wave's two block rows
+    constexpr int NA = NCT - GA, NBB = NCT - GB;
+    const int tid = threadIdx.x, l = tid & 63;
+    f64x4 accA[NA], accB[NBB];
 #pragma unroll
-    for (int g = 0; g < NCT; ++g) {
-        accA[g] = (f64x4){0.0, 0.0, 0.0, 0.0};
-        accB[g] = accA[g];
-    }
+    for (int g = 0; g < NA; ++g) accA[g] = (f64x4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int g = 0; g < NBB; ++g) accB[g] = (f64x4){0.0, 0.0, 0.0, 0.0};
     float4 nx[V4];
     auto load = [&](long long r0) {
 #pragma unroll
@@ -66,31 +61,48 @@ __global__ __launch_bounds__(256) void k_gram_f64_mfma_w8(const float* __restric
 #pragma unroll 2
         for (int k = 0; k < CH; k += 4) {
             const float* rp = Bs + (k + kr) * LDC + col;
-            const double a = (double)rp[16 * gaA], b2 = (double)rp[16 * gaB];
+            const double a = (double)rp[16 * GA], b2 = (double)rp[16 * GB];
             double v[NCT];
 #pragma unroll
-            for (int g = 0; g < NCT; ++g) v[g] = (double)rp[16 * g];
+            for (int g = GB < GA ? GB : GA; g < NCT; ++g) v[g] = (double)rp[16 * g];
 #pragma unroll
-            for (int g = 0; g < NCT; ++g) {
-                if (g >= gaA) accA[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, v[g], accA[g], 0, 0, 0);
-                if (g >= gaB) accB[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(b2, v[g], accB[g], 0, 0, 0);
-            }
+            for (int g = 0; g < NA; ++g) accA[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, v[GA + g], accA[g], 0, 0, 0);
+#pragma unroll
+            for (int g = 0; g < NBB; ++g)
+                accB[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(b2, v[GB + g], accB[g], 0, 0, 0);
         }
     }
     // block index of (ga, gb) in the upper enumeration: ga NCT - ga (ga - 1) / 2 + (gb - ga)
+#pragma unroll
+    for (int g = 0; g < NA; ++g) {
+        const int bi = GA * NCT - GA * (GA - 1) / 2 + g;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) outp[(bi * 4 + r) * 64 + l] = accA[g][r];
+    }
+#pragma unroll
+    for (int g = 0; g < NBB; ++g) {
+        const int bi = GB * NCT - GB * (GB - 1) / 2 + g;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) outp[(bi * 4 + r) * 64 + l] = accB[g][r];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gram_f64_mfma_w8(const float* __restrict__ B, const DevState* __restrict__ st,
+                                                           long long nrows, long long rows_per_block,
+                                                           double* __restrict__ Gpart) {
+    constexpr int NB = gram_blocks(8);
+    __shared__ float Bs[64 * (128 + 4)];
+    const int ldb = st->ldb;
+    const long long begin = (long long)blockIdx.x * rows_per_block;
+    long long end = begin + rows_per_block;
+    if (end > nrows) end = nrows;
     double* outp = Gpart + (size_t)blockIdx.x * NB * 256;
-#pragma unroll
-    for (int g = 0; g < NCT; ++g) {
-        if (g >= gaA) {
-            const int bi = gaA * NCT - gaA * (gaA - 1) / 2 + (g - gaA);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) outp[(bi * 4 + r) * 64 + l] = accA[g][r];
-        }
-        if (g >= gaB) {
-            const int bi = gaB * NCT - gaB * (gaB - 1) / 2 + (g - gaB);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) outp[(bi * 4 + r) * 64 + l] = accB[g][r];
-        }
+    // the wave index is uniform over a wave; every branch meets the same barriers
+    switch (threadIdx.x >> 6) {
+        case 0: gram_w8_wave<0>(B, ldb, begin, end, Bs, outp); break;
+        case 1: gram_w8_wave<1>(B, ldb, begin, end, Bs, outp); break;
+        case 2: gram_w8_wave<2>(B, ldb, begin, end, Bs, outp); break;
+        default: gram_w8_wave<3>(B, ldb, begin, end, Bs, outp); break;
     }
 }
 
