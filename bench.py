@@ -19,7 +19,10 @@ committed counter summary (null when the kernel source has changed since).
 sample of the same workload.
 
 Other modes (for profiling runs; they print one line and exit):
-  --mode probe        one solve of `--probe-workload` (plane2d, clumps3d, plane2d_coupled) for `--probe-steps` steps
+  --mode probe        one solve of `--probe-workload` (plane2d, clumps3d, plane2d_coupled, plane2d_rusanov_scatter)
+                      for `--probe-steps` steps
+  --mode c3           the 64^3 clump workload at steady state: ranks at the cap, then `--steps` timed steps
+  --mode c5-slab      one GPU's z-slab of the 256^3 spike workload (cap 18), `--steps` timed steps
   --mode copy         a plain device-to-device copy of `--copy-mb` MiB (counter calibration)
   --mode served       only the served request mix (capacity, then Poisson arrivals)
   --mode pmc-summary  turn rocprofv3 counter CSVs (--pmc-dir) into profiles/traffic_plane2d.json
@@ -226,21 +229,38 @@ def mode_c5_slab(args):
     projected rank fits the SVD chain (k1 <= 128: cap 18).  Untimed steps until
     the ranks reach the cap, then --steps timed steps with HIP-event kernel
     timing."""
-    import torch
-    import paper_2602_00290_amd as tt
     import tt_inputs as ti
     prob = ti.spikes3d_slab(rank_cap=args.c5_cap)
+    return steady_steps(args, prob, "c5-slab",
+                        "spikes3d z-slab 256 x 256 x 32 cells (1/8 of the 256^3 cube), 128 groups, "
+                        "16 x 16 directions, split BF16 contractions, FP64 rounding, tol 1e-5", args.c5_warmup, 4)
+
+
+def mode_c3(args):
+    """The 64^3 clump workload (64 groups, 8 x 16 directions, cap 64, split
+    BF16): untimed steps until the ranks have reached the cap (about 30 steps),
+    then --steps timed steps with HIP-event kernel timing (steady state)."""
+    import tt_inputs as ti
+    prob = ti.clumps3d(precision=ti.PREC_BF16X)
+    return steady_steps(args, prob, "c3",
+                        "clumps3d 64^3 cells, 64 groups, 8 x 16 directions, split BF16 contractions, "
+                        "FP64 rounding, cap 64, tol 1e-5", 48, 32)
+
+
+def steady_steps(args, prob, mode, workload, max_warm, min_warm):
+    import torch
+    import paper_2602_00290_amd as tt
     ws = tt.workspace_bytes(prob)
-    print(json.dumps({"mode": "c5-slab", "phase": "setup", "rows": prob.M, "workspace_gb": ws / 2 ** 30}),
+    print(json.dumps({"mode": mode, "phase": "setup", "rows": prob.M, "workspace_gb": ws / 2 ** 30}),
           flush=True)
     s = tt.Solver(prob)
     warm = 0
-    while warm < args.c5_warmup:
+    while warm < max_warm:
         st = s.solve(1)
         warm += 1
         print(json.dumps({"phase": "warmup", "step": warm, "ranks": [st["r1"], st["r2"]],
                           "ms": st["seconds"] * 1e3}), flush=True)
-        if st["r1"] >= prob.rank_cap and warm >= 4:
+        if st["r1"] >= prob.rank_cap and warm >= min_warm:
             break
     s.set_timing(True)
     torch.cuda.synchronize()
@@ -250,9 +270,8 @@ def mode_c5_slab(args):
     el = time.perf_counter() - t0
     n = st["kernel_launches"]
     print(json.dumps({
-        "mode": "c5-slab", "workload": "spikes3d z-slab 256 x 256 x 32 cells (1/8 of the 256^3 cube), 128 groups, "
-                                       "16 x 16 directions, split BF16 contractions, FP64 rounding, tol 1e-5",
-        "rows": prob.M, "rank_cap": prob.rank_cap, "warmup_steps": warm, "steps": args.steps,
+        "mode": mode, "workload": workload, "rows": prob.M, "rank_cap": prob.rank_cap, "warmup_steps": warm,
+        "steps": args.steps,
         "ms_per_step": el / args.steps * 1e3, "ranks": [st["r1"], st["r2"]], "max_R": [st["max_R1"], st["max_R2"]],
         "compression": st["compression"], "workspace_gb": ws / 2 ** 30, "timing": "HIP events on",
         "kernel_ms_per_step": {c: st["kernel_ms"][c] / args.steps for c in tt.KERNEL_CLASSES if n[c]},
@@ -326,7 +345,8 @@ def main():
     ap.add_argument("--streams", type=int, default=16, help="HIP streams for the batch")
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="GPU_MAX_HW_QUEUES for this process (0: keep the environment's)")
-    ap.add_argument("--mode", default="bench", choices=["bench", "probe", "copy", "pmc-summary", "served", "c5-slab"])
+    ap.add_argument("--mode", default="bench",
+                    choices=["bench", "probe", "copy", "pmc-summary", "served", "c5-slab", "c3"])
     ap.add_argument("--c5-cap", type=int, default=18, help="rank cap of --mode c5-slab")
     ap.add_argument("--c5-warmup", type=int, default=40, help="at most this many untimed steps in --mode c5-slab")
     ap.add_argument("--probe-steps", type=int, default=64)
@@ -363,6 +383,8 @@ def main():
         return mode_probe(args)
     if args.mode == "c5-slab":
         return mode_c5_slab(args)
+    if args.mode == "c3":
+        return mode_c3(args)
     if args.mode == "served":
         print(json.dumps({"mode": "served", **served_phase(args)}), flush=True)
         return
