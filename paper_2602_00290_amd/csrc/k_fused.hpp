@@ -56,7 +56,8 @@ struct FusedNbr {
 };
 
 constexpr int kOffSlots = 9;   // gather blocks 0..6, 7: rank-1 block, 8: always empty
-constexpr int kFusedStages = 2;   // A-operand groups in flight per wave (4 measured no faster)
+constexpr int kFusedStages = 2;
+constexpr int kTbStride = 36;   // row stride (floats) of the output kernel's per-wave transpose buffer   // A-operand groups in flight per wave (4 measured no faster)
 
 // K groups the fused kernels run for T groups of data: a multiple of the
 // stage count and at least two rounds of stages (padding groups have a zero
@@ -72,7 +73,8 @@ __host__ __device__ inline int fused_groups(int T, int ns) {
 __host__ __device__ inline size_t fused_lds_bytes(int nct, bool gram, int ngroups) {
     const size_t op = (size_t)fused_groups(ngroups, kFusedStages) * nct * 64 * 16;
     const size_t offs = (size_t)kFusedWaves * 2 * kOffSlots * 16 * sizeof(int);
-    const size_t main = op + offs;
+    const size_t tb = gram ? 0 : (size_t)kFusedWaves * 32 * kTbStride * sizeof(float);
+    const size_t main = op + offs + tb;
     const size_t red = gram ? (size_t)(kFusedWaves / 2) * gram_blocks(nct) * 256 * sizeof(double) : 0;
     return main > red ? main : red;
 }
@@ -135,11 +137,13 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
     constexpr int NS = kFusedStages;
     const int T2 = fused_groups(T, NS);
     const int ldo = GRAM ? 0 : st->ldzn;
+    const FastDiv dldo(GRAM ? 1 : ldo);
     const unsigned magic = ((1u << 20) + (unsigned)ldz - 1u) / (unsigned)ldz;   // k0 / ldz = (k0 magic) >> 20 for k0 < 2^14
 
     f32x4v* Gs = reinterpret_cast<f32x4v*>(fused_lds);
     int* offs_all = reinterpret_cast<int*>(fused_lds + (size_t)T2 * NCT * 64 * 16);
     int* offs = offs_all + w * (2 * kOffSlots * 16);                 // [rt][slot][m] of this wave
+    float* tb = reinterpret_cast<float*>(offs_all + kFusedWaves * 2 * kOffSlots * 16) + w * 32 * kTbStride;
 
     {   // operand, already in lane order
         const f32x4v* src = reinterpret_cast<const f32x4v*>(Gsw);
@@ -317,30 +321,25 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_f32(Geom g, FusedNbr fn
                         }
                 }
         } else {
-            // D[i][j] of row tile rt: row R0 + 16 rt + 4 q + r, column 16 c + m
-            const bool full = R0 + 32 <= g.M;
+            // the tile's 32 rows x ldo columns are contiguous in Out: transpose
+            // the accumulators (D[i][j] of row tile rt: row 16 rt + 4 q + r,
+            // column 16 c + m) through this wave's LDS buffer, then 16-byte stores
 #pragma unroll
-            for (int c = 0; c < NCT; ++c) {
-                const int col = 16 * c + m;
-                if (col < ldo) {
-                    char* ob = reinterpret_cast<char*>(Out);
-                    const unsigned o0 = (unsigned)((R0 + 4 * q) * ldo + col) * 4u;
-                    if (full) {
+            for (int c = 0; c < NCT; ++c)
 #pragma unroll
-                        for (int rt = 0; rt < 2; ++rt)
+                for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-                            for (int r = 0; r < 4; ++r)
-                                *reinterpret_cast<float*>(ob + o0 + (unsigned)((16 * rt + r) * ldo) * 4u) = acc[rt][c][r];
-                    } else {
-#pragma unroll
-                        for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-                            for (int r = 0; r < 4; ++r)
-                                if (R0 + 16 * rt + 4 * q + r < g.M)
-                                    *reinterpret_cast<float*>(ob + o0 + (unsigned)((16 * rt + r) * ldo) * 4u) = acc[rt][c][r];
-                    }
-                }
+                    for (int r = 0; r < 4; ++r) tb[(16 * rt + 4 * q + r) * kTbStride + 16 * c + m] = acc[rt][c][r];
+            asm volatile("" ::: "memory");
+            const int nrow = (int)min((long long)32, g.M - (long long)R0);
+            const int nvec = (nrow * ldo) >> 2;
+            char* ob = reinterpret_cast<char*>(Out) + (size_t)R0 * ldo * 4;
+            for (int e = l; e < nvec; e += 64) {
+                const int f = 4 * e, row = dldo.q(f), col = f - row * ldo;
+                const f32x4v v = *reinterpret_cast<const f32x4v*>(tb + row * kTbStride + col);
+                *reinterpret_cast<f32x4v*>(ob + (unsigned)f * 4u) = v;
             }
+            asm volatile("" ::: "memory");
         }
         d0 = nd0;
         d1 = nd1;
