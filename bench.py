@@ -362,6 +362,8 @@ def main():
                     help="also time seed 0 with the coupled medium temperature (heat capacity 8 a)")
     ap.add_argument("--rusanov-scatter", type=int, default=1,
                     help="also time seed 0 with the Rusanov flux and isotropic scattering (kappa_s = kappa_a)")
+    ap.add_argument("--c1-batch", type=int, default=256,
+                    help="also time this many independent 1D slab solves (FP64, 128 steps) as one batch")
     ap.add_argument("--served", type=int, default=256,
                     help="requests of the served mix (0: skip the serving phase)")
     ap.add_argument("--served-budget-gb", type=float, default=64.0)
@@ -473,6 +475,33 @@ def main():
                    "couple_launches": nc, "T_mean": float(Tc.mean()), "T_max": float(Tc.max()),
                    "energy_total": stc["energy"] / pc.c + stc["medium_energy"]}
         sc.destroy()
+    # ---- phase 6: the 1D slab (FP64, cap 8, 128 steps), batched: latency-bound solves ----
+    c1 = None
+    if args.c1_batch > 0:
+        p1 = ti.slab1d()
+        c1s = [tt.Solver(p1, device=dev) for _ in range(args.c1_batch)]
+        c1st = [torch.cuda.Stream(device=dev) for _ in range(min(args.c1_batch, args.streams))]
+        for sv in c1s:
+            sv.reset()
+        tt.solve_batch(c1s, p1.n_steps, c1st)        # warm-up
+        torch.cuda.synchronize()
+        t6 = time.perf_counter()
+        for sv in c1s:
+            sv.reset()
+        c1stats = tt.solve_batch(c1s, p1.n_steps, c1st)
+        torch.cuda.synchronize()
+        c1_s = time.perf_counter() - t6
+        one = c1s[0]
+        one.reset()
+        torch.cuda.synchronize()
+        t7 = time.perf_counter()
+        one.solve(p1.n_steps)
+        c1_one = time.perf_counter() - t7
+        c1 = {"workload": "slab1d: 64 cells, 8 groups [0.01,10], 16 GL mu, FP64, cap 8, tol 1e-8, 128 steps",
+              "batch": args.c1_batch, "streams": len(c1st), "solves_per_s": args.c1_batch / c1_s,
+              "single_solve_ms": c1_one * 1e3, "ranks": [c1stats[0]["r1"], c1stats[0]["r2"]]}
+        for sv in c1s:
+            sv.destroy()
     # ---- phase 5: seed 0 with the Rusanov flux and isotropic scattering ----
     rus = None
     if args.rusanov_scatter:
@@ -530,6 +559,8 @@ def main():
         out["coupled_temperature"] = coupled
     if rus is not None:
         out["rusanov_scattering"] = rus
+    if c1 is not None:
+        out["c1_slab1d"] = c1
     if args.served > 0:
         out["served"] = served_phase(args)
     if not args.no_cpu_baseline:
