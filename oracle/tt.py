@@ -47,7 +47,7 @@ import math
 
 import numpy as np
 
-from . import dense
+from . import dense, philox
 
 
 # ---------------------------------------------------------------------------
@@ -287,24 +287,98 @@ def round_tt(Z, Th, Ph, tol: float, cap: int):
     return Zo, Tho, Pho, info
 
 
-def step(prob, Z, Th, Ph, tol=None, cap=None):
+# Randomized rounding (Section 3.1 footnote: the solver's third rounding
+# method).  Each pass first compresses the TT sum to sketch ranks equal to the
+# incoming solution ranks plus a constant (the "randomized preconditioning"),
+# then truncates the result with the same delta-truncated TT-SVD rounding as
+# the SVD method.  The compression is the randomize-then-orthogonalize scheme
+# of the cited randomized rounding work (Al Daas et al. 2023): contract the
+# sum from the right with a random TT of the sketch ranks, take an orthonormal
+# basis of the sketch of the first core, project the sum onto it, and repeat
+# for the middle core.  The random cores are counter-based (oracle.philox),
+# uniform on [-1, 1).
+
+RAND_KEEP = 1e-7     # a sketch direction is kept when its singular value exceeds RAND_KEEP times the largest
+ROUND_RAND = 3
+
+
+def sketch_ranks(R1: int, R2: int, n_theta: int, n_phi: int, r_in, p: int):
+    """Sketch ranks (l1, l2): the incoming ranks plus p, at most the ranks the
+    sum has after right-to-left orthogonalisation, k2 = min(R2, N_phi) and
+    k1 = min(R1, N_theta k2)."""
+    k2 = min(R2, n_phi)
+    k1 = min(R1, n_theta * k2)
+    return min(r_in[0] + p, k1), min(r_in[1] + p, k2)
+
+
+def sketch_cores(seed: int, round_index: int, l1: int, n_theta: int, l2: int, n_phi: int):
+    """The random TT's second core (l1, N_theta, l2) and third core (l2, N_phi)."""
+    G2 = philox.sketch_entries(seed, 0, round_index, l1 * n_theta * l2).reshape(l1, n_theta, l2)
+    G3 = philox.sketch_entries(seed, 1, round_index, l2 * n_phi).reshape(l2, n_phi)
+    return G2, G3
+
+
+def range_basis(Y: np.ndarray) -> np.ndarray:
+    """Orthonormal basis of the numerical range of Y: the left singular vectors
+    whose singular values exceed RAND_KEEP times the largest (at least one)."""
+    U, s, _ = np.linalg.svd(Y, full_matrices=False)
+    keep = max(1, int(np.sum(s > RAND_KEEP * s[0]))) if s.size and s[0] > 0 else 1
+    return U[:, :keep]
+
+
+def randomized_precondition(Z, Th, Ph, G2, G3):
+    """Randomize-then-orthogonalize compression of the TT (Z, Theta, Phi) with
+    the random cores G2 (l1, N_theta, l2) and G3 (l2, N_phi).  Returns the
+    left-orthonormal TT (Q1, Q2, Phi') of ranks at most (l1, l2)."""
+    R1, nt, R2 = Th.shape
+    W3 = Ph @ G3.T                                   # R2 x l2: right contraction of the last core
+    W2 = np.einsum("alb,glh,bh->ag", Th, G2, W3)     # R1 x l1: and of the last two
+    Q1 = range_basis(Z @ W2)                         # M x l1'
+    Th1 = np.einsum("ja,alb->jlb", Q1.T @ Z, Th)     # (Q1^T Z) x_1 Theta: l1' x N_theta x R2
+    Th1m = Th1.reshape(-1, R2)
+    Q2 = range_basis(Th1m @ W3)                      # (l1' N_theta) x l2'
+    Ph1 = (Q2.T @ Th1m) @ Ph                         # l2' x N_phi
+    return Q1, Q2.reshape(Q1.shape[1], nt, Q2.shape[1]), Ph1
+
+
+def randomized_round(Z, Th, Ph, tol: float, cap: int, r_in, p: int, seed: int, round_index: int):
+    """Randomized rounding of the TT sum (Z, Theta, Phi) whose incoming
+    solution had ranks r_in: compression to the sketch ranks, then round_tt."""
+    R1, nt, R2 = Th.shape
+    l1, l2 = sketch_ranks(R1, R2, nt, Ph.shape[1], r_in, p)
+    G2, G3 = sketch_cores(seed, round_index, l1, nt, l2, Ph.shape[1])
+    Zo, Tho, Pho, info = round_tt(*randomized_precondition(Z, Th, Ph, G2, G3), tol, cap)
+    info.update(R1=R1, R2=R2, l1=l1, l2=l2)
+    return Zo, Tho, Pho, info
+
+
+def _round(prob, Z, Th, Ph, tol, cap, r_in, round_index):
+    if getattr(prob, "round_method", 2) == ROUND_RAND:
+        return randomized_round(Z, Th, Ph, tol, cap, r_in, prob.rand_oversample, prob.rand_seed, round_index)
+    return round_tt(Z, Th, Ph, tol, cap)
+
+
+def step(prob, Z, Th, Ph, tol=None, cap=None, round_index=0):
     """One step then truncate.  step_order 0: one rounding after transport and
     source; step_order 1: round after the transport and again after the source
-    (the paper's order, Section 3.1 closing paragraph)."""
+    (the paper's order, Section 3.1 closing paragraph).  round_index numbers
+    the rounding passes (it keys the randomized method's sketch)."""
     tol = prob.tol if tol is None else tol
     cap = prob.rank_cap if cap is None else cap
+    r_in = (Z.shape[1], Ph.shape[0])
     if prob.step_order == 1:
-        Z, Th, Ph, _ = round_tt(*apply_transport(prob, Z, Th, Ph), tol, cap)
-        return round_tt(*apply_source(prob, Z, Th, Ph), tol, cap)
-    return round_tt(*apply_step(prob, Z, Th, Ph), tol, cap)
+        Z, Th, Ph, _ = _round(prob, *apply_transport(prob, Z, Th, Ph), tol, cap, r_in, round_index)
+        return _round(prob, *apply_source(prob, Z, Th, Ph), tol, cap, (Z.shape[1], Ph.shape[0]), round_index + 1)
+    return _round(prob, *apply_step(prob, Z, Th, Ph), tol, cap, r_in, round_index)
 
 
 def solve(prob, n_steps=None, cores=None, tol=None, cap=None):
     Z, Th, Ph = initial_tt(prob) if cores is None else cores
     n_steps = prob.n_steps if n_steps is None else n_steps
+    per = 2 if prob.step_order == 1 else 1
     infos = []
-    for _ in range(n_steps):
-        Z, Th, Ph, info = step(prob, Z, Th, Ph, tol, cap)
+    for m in range(n_steps):
+        Z, Th, Ph, info = step(prob, Z, Th, Ph, tol, cap, round_index=m * per)
         infos.append(info)
     return (Z, Th, Ph), infos
 

@@ -36,6 +36,7 @@ BC_INFLOW_VALUES = 3   # isotropic ghost intensity given per group
 PREC_FP64 = 0
 PREC_FP32 = 1
 PREC_BF16X = 2
+ROUND_QR, ROUND_GRAM, ROUND_AUTO, ROUND_RAND = 0, 1, 2, 3
 
 
 @dataclasses.dataclass
@@ -63,7 +64,7 @@ class Problem:
     rank_cap: int = 8
     precision: int = PREC_FP64
     step_order: int = 0          # 0: one rounding per step; 1: round after transport and after source
-    round_method: int = 2        # 0: Householder QR, 1: Gram, 2: QR for FP64 data, Gram otherwise
+    round_method: int = 2        # 0: Householder QR, 1: Gram, 2: QR for FP64 data, Gram otherwise, 3: randomized
     n_steps: int = 1
     seed: int = 0
     heat_capacity: float = 0.0   # rho c_v per volume; 0: fixed medium temperature, > 0: coupled temperature
@@ -72,6 +73,8 @@ class Problem:
     kappa_s_full: Optional[np.ndarray] = None  # (N_X, N_nu) isotropic scattering opacity (None: no scattering)
     flux: int = 0                # streaming flux: 0 upwind, 1 Rusanov
     rusanov_s: float = 1.0       # Rusanov wave speed S+ / c (1: S+ = c, 0: central differences)
+    rand_oversample: int = 4     # randomized rounding: sketch ranks = current ranks + this
+    rand_seed: int = 0           # randomized rounding: key of the counter-based generator
 
     # ----- derived sizes (pure bookkeeping) -----
     @property
