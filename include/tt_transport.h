@@ -80,9 +80,20 @@ typedef enum {
     TT_ROUND_GRAM = 1,  /* FP64 Gram matrix of the projected core, then an FP64
                            symmetric eigensolver (Gram rounding, Section 3.1
                            footnote); accurate when tol >> 1e-8                  */
-    TT_ROUND_AUTO = 2   /* QR for TT_PREC_FP64; Gram for FP32 / split-BF16 data,
+    TT_ROUND_AUTO = 2,  /* QR for TT_PREC_FP64; Gram for FP32 / split-BF16 data,
                            whose own rounding (>= 6e-8) is above the Gram's
                            FP64 accuracy floor (~1.5e-8 relative)                */
+    TT_ROUND_RAND = 3   /* randomized rounding (Section 3.1 footnote): each pass
+                           first compresses the TT sum to sketch ranks
+                           (incoming ranks + rand_oversample, at most the
+                           sum's orthogonalised ranks) by randomize-then-
+                           orthogonalize with a random TT drawn from
+                           Philox-4x32-10 (key rand_seed; counter = entry,
+                           core, pass number since create), then truncates
+                           like TT_ROUND_GRAM.  The sketch acts on the Gram of
+                           the projected core, so it adds one single-workgroup
+                           kernel and no pass over Z; same accuracy floor as
+                           TT_ROUND_GRAM.                                        */
 } tt_round_method;
 
 typedef enum {
@@ -167,6 +178,11 @@ typedef struct tt_problem {
                                        (apply_op returns TT_ERR_STATE).  Adds 2 N_X
                                        N_nu doubles of workspace (3 without a
                                        coupled temperature).                        */
+    int rand_oversample;            /* TT_ROUND_RAND: sketch ranks = solution ranks
+                                       + this, in [1, 128] (the paper's comparison
+                                       uses 4); ignored by the other methods        */
+    unsigned long long rand_seed;   /* TT_ROUND_RAND: generator key; the same key
+                                       reproduces a solve bit for bit              */
 } tt_problem;
 
 /* Statistics of the last solve / round (Section 3.2 metrics). */
@@ -191,6 +207,9 @@ typedef struct tt_stats {
     double flops[8];      /* algorithmic flops per class, summed over the solve      */
     double medium_energy; /* dV * heat_capacity * sum_x T[x] (0 when T is fixed); the
                              radiation energy is energy / c                          */
+    int sketch_r1, sketch_r2; /* TT_ROUND_RAND: ranks of the last randomized
+                             compression after null sketch directions were
+                             dropped (0 for the other methods)                       */
 } tt_stats;
 
 /* Internal delta-ranks of the combined core Z (section "Internal structure of

@@ -318,25 +318,29 @@ def sketch_cores(seed: int, round_index: int, l1: int, n_theta: int, l2: int, n_
     return G2, G3
 
 
-def range_basis(Y: np.ndarray) -> np.ndarray:
+def range_basis(Y: np.ndarray, sv_out=None) -> np.ndarray:
     """Orthonormal basis of the numerical range of Y: the left singular vectors
-    whose singular values exceed RAND_KEEP times the largest (at least one)."""
+    whose singular values exceed RAND_KEEP times the largest (at least one).
+    The singular values relative to the largest are appended to sv_out."""
     U, s, _ = np.linalg.svd(Y, full_matrices=False)
     keep = max(1, int(np.sum(s > RAND_KEEP * s[0]))) if s.size and s[0] > 0 else 1
+    if sv_out is not None:
+        sv_out.append(s / s[0] if s.size and s[0] > 0 else s)
     return U[:, :keep]
 
 
-def randomized_precondition(Z, Th, Ph, G2, G3):
+def randomized_precondition(Z, Th, Ph, G2, G3, sv_out=None):
     """Randomize-then-orthogonalize compression of the TT (Z, Theta, Phi) with
     the random cores G2 (l1, N_theta, l2) and G3 (l2, N_phi).  Returns the
-    left-orthonormal TT (Q1, Q2, Phi') of ranks at most (l1, l2)."""
+    left-orthonormal TT (Q1, Q2, Phi') of ranks at most (l1, l2); the two
+    sketches' relative singular values are appended to sv_out."""
     R1, nt, R2 = Th.shape
     W3 = Ph @ G3.T                                   # R2 x l2: right contraction of the last core
     W2 = np.einsum("alb,glh,bh->ag", Th, G2, W3)     # R1 x l1: and of the last two
-    Q1 = range_basis(Z @ W2)                         # M x l1'
+    Q1 = range_basis(Z @ W2, sv_out)                 # M x l1'
     Th1 = np.einsum("ja,alb->jlb", Q1.T @ Z, Th)     # (Q1^T Z) x_1 Theta: l1' x N_theta x R2
     Th1m = Th1.reshape(-1, R2)
-    Q2 = range_basis(Th1m @ W3)                      # (l1' N_theta) x l2'
+    Q2 = range_basis(Th1m @ W3, sv_out)              # (l1' N_theta) x l2'
     Ph1 = (Q2.T @ Th1m) @ Ph                         # l2' x N_phi
     return Q1, Q2.reshape(Q1.shape[1], nt, Q2.shape[1]), Ph1
 
@@ -347,8 +351,9 @@ def randomized_round(Z, Th, Ph, tol: float, cap: int, r_in, p: int, seed: int, r
     R1, nt, R2 = Th.shape
     l1, l2 = sketch_ranks(R1, R2, nt, Ph.shape[1], r_in, p)
     G2, G3 = sketch_cores(seed, round_index, l1, nt, l2, Ph.shape[1])
-    Zo, Tho, Pho, info = round_tt(*randomized_precondition(Z, Th, Ph, G2, G3), tol, cap)
-    info.update(R1=R1, R2=R2, l1=l1, l2=l2)
+    svs = []
+    Zo, Tho, Pho, info = round_tt(*randomized_precondition(Z, Th, Ph, G2, G3, svs), tol, cap)
+    info.update(R1=R1, R2=R2, l1=l1, l2=l2, sketch_sv=svs)
     return Zo, Tho, Pho, info
 
 

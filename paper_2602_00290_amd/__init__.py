@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libtt_transport.so")
 
 TT_OK, TT_ERR_INVALID_ARG, TT_ERR_OOM, TT_ERR_NUMERIC, TT_ERR_HIP, TT_ERR_STATE = 0, -1, -2, -3, -4, -5
 TT_PREC_FP64, TT_PREC_FP32, TT_PREC_BF16X = 0, 1, 2
-TT_ROUND_QR, TT_ROUND_GRAM, TT_ROUND_AUTO = 0, 1, 2
+TT_ROUND_QR, TT_ROUND_GRAM, TT_ROUND_AUTO, TT_ROUND_RAND = 0, 1, 2, 3
 TT_BC_VACUUM, TT_BC_INFLOW_PLANCK, TT_BC_PERIODIC, TT_BC_INFLOW_VALUES = 0, 1, 2, 3
 TT_FLUX_UPWIND, TT_FLUX_RUSANOV = 0, 1
 
@@ -61,6 +61,8 @@ class TTProblem(ctypes.Structure):
         ("flux", ctypes.c_int),
         ("rusanov_s", ctypes.c_double),
         ("kappa_s_full", _dp),
+        ("rand_oversample", ctypes.c_int),
+        ("rand_seed", ctypes.c_ulonglong),
     ]
 
 
@@ -82,6 +84,8 @@ class TTStats(ctypes.Structure):
         ("kernel_launches", ctypes.c_longlong * 8),
         ("flops", ctypes.c_double * 8),
         ("medium_energy", ctypes.c_double),
+        ("sketch_r1", ctypes.c_int),
+        ("sketch_r2", ctypes.c_int),
     ]
 
     def as_dict(self) -> dict:
@@ -90,6 +94,7 @@ class TTStats(ctypes.Structure):
         d["kernel_launches"] = dict(zip(KERNEL_CLASSES, list(self.kernel_launches)))
         d["flops"] = dict(zip(KERNEL_CLASSES, list(self.flops)))
         d["medium_energy"] = self.medium_energy
+        d["sketch_r1"], d["sketch_r2"] = self.sketch_r1, self.sketch_r2
         return d
 
 
@@ -226,6 +231,8 @@ class ProblemStruct:
         s.rusanov_s = float(getattr(prob, "rusanov_s", 1.0))
         ks = getattr(prob, "kappa_s_full", None)
         s.kappa_s_full = ptr(None if ks is None else np.asarray(ks, float).reshape(-1))
+        s.rand_oversample = int(getattr(prob, "rand_oversample", 4))
+        s.rand_seed = int(getattr(prob, "rand_seed", 0))
         self.s = s
 
 

@@ -551,10 +551,11 @@ __device__ __forceinline__ int block_jacobi_sym64(double* S, int ld, double* W, 
 // updates every 2 x 2 block (rows a_p, b_p; columns a_q, b_q) of S in one
 // phase, R_p^T B R_q, and the rows of W per column pair (W <- W R); rounds
 // leave the blocks of two identity rotations untouched.  Same rotation,
-// skipping and stopping rules as block_jacobi_sym64.  __syncthreads orders
+// skipping and stopping rules as block_jacobi_sym64, except that rotations
+// with |t| <= tskip (default 1e-10) are skipped.  __syncthreads orders
 // the global W accesses of consecutive rounds within the workgroup.
 __device__ __forceinline__ int block_jacobi_sym_wide(double* S, int n, int ld, double* W, int ldw, double* cs, int* pa_,
-                                                     int* pb_, int* flag, double tconv) {
+                                                     int* pb_, int* flag, double tconv, double tskip = 1e-10) {
     if (n < 2) {
         __syncthreads();
         return 0;
@@ -578,7 +579,7 @@ __device__ __forceinline__ int block_jacobi_sym_wide(double* S, int n, int ld, d
                         double t;
                         jacobi_rotation(app, aqq, apq, &c, &sn, &t);
                         if (fabs(t) > tconv) *flag = 1;
-                        if (fabs(t) <= 1e-10) {
+                        if (fabs(t) <= tskip) {
                             c = 1.0;
                             sn = 0.0;
                         }
@@ -958,7 +959,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevSt
     }
     if (threadIdx.x == 0) {
         st->kall = grows;
-        st->R1 = R1; st->R2 = R2; st->k1 = k1; st->k2 = k2; st->ldb = ldb;
+        st->R1 = R1; st->R2 = R2; st->k1 = k1; st->k2 = k2; st->ldb = ldb; st->k1b = k1;
         if (R1 > st->max_R1) st->max_R1 = R1;
         if (R2 > st->max_R2) st->max_R2 = R2;
         st->canon_prev = st->canon;
@@ -1200,7 +1201,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
         st->k1_prev = k1;
         if (!(norm2 < 1e300) || norm2 != norm2) st->nan_flag = 1;
         st->rounds += 1;
-        const double M = (double)g.M, R1 = (double)st->R1, kk = (double)k1;
+        // B's width (a randomized pass runs the chain on its compressed core)
+        const double M = (double)g.M, R1 = (double)st->R1, kk = (double)st->k1b;
         if (Gfold) {
             // fused path: projection (FP32, fl[0]) and symmetric Gram (FP64,
             // fl[1]) run in one kernel; the output contraction re-reads Z

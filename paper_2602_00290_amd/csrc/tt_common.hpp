@@ -42,6 +42,8 @@ struct DevState {
     int sweeps[2];     // Jacobi sweeps of the last round (bond 1, bond 2)
     long long tph[8];  // wall_clock64 stamps at phase boundaries of the last SVD chain
     int kall;          // rows of the gather operand: n_gather * ldz + n_r1
+    int k1b;           // columns of the projected core B (k1 until a randomized pass compresses the sum)
+    int l1s, l2s;      // ranks of the last randomized compression (after dropping null sketch directions)
     int pad2;
 };
 

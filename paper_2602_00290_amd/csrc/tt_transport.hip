@@ -30,6 +30,7 @@
 #include "k_couple.hpp"
 #include "k_diag.hpp"
 #include "k_small.hpp"
+#include "k_rand.hpp"
 #include "planck.hpp"
 #include "tt_common.hpp"
 
@@ -85,6 +86,9 @@ struct Plan {
     size_t o_Gh = 0, o_Gl = 0, o_Vh = 0, o_Vl = 0;
     int rw1 = 0, rw2 = 0;           // widths of the rank-1 row blocks (transport / source operators)
     bool fused_overflow = false;
+    // randomized rounding (TT_ROUND_RAND): sketch buffers
+    bool rand = false;
+    size_t o_rG = 0, o_rQTh = 0, o_rQPh = 0, o_rP = 0, o_rVeff = 0, o_rw = 0;
     bool row_tables = false;        // per-row d, neighbour and rank-1 tables (fused and split-BF16 paths)
     size_t o_state, o_Z0, o_Z1, o_B, o_Th0, o_Th1, o_Ph0, o_Ph1, o_LTh, o_QTh, o_QPh, o_G, o_V, o_RA, o_RB, o_small,
         o_k0, o_ks, o_kfull = 0, o_eps, o_ghost, o_gtab, o_htab, o_ThN, o_PhN, o_sv, o_colsum;
@@ -145,7 +149,9 @@ tt_status validate(const tt_problem* p) {
     if (!(p->tol >= 0.0)) return fail(TT_ERR_INVALID_ARG, "tol must be >= 0");
     if (p->rank_cap < 1) return fail(TT_ERR_INVALID_ARG, "rank_cap must be >= 1");
     if (p->precision < 0 || p->precision > 2) return fail(TT_ERR_INVALID_ARG, "unknown precision");
-    if (p->round_method < 0 || p->round_method > 2) return fail(TT_ERR_INVALID_ARG, "unknown round_method");
+    if (p->round_method < 0 || p->round_method > 3) return fail(TT_ERR_INVALID_ARG, "unknown round_method");
+    if (p->round_method == TT_ROUND_RAND && (p->rand_oversample < 1 || p->rand_oversample > 128))
+        return fail(TT_ERR_INVALID_ARG, "rand_oversample must lie in [1, 128] for randomized rounding");
     if (p->paper_step_order < 0 || p->paper_step_order > 1) return fail(TT_ERR_INVALID_ARG, "paper_step_order must be 0 or 1");
     if (!(p->heat_capacity >= 0.0) || !std::isfinite(p->heat_capacity))
         return fail(TT_ERR_INVALID_ARG, "heat_capacity must be finite and >= 0");
@@ -212,7 +218,9 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         P.nct_o = P.ldzcap <= 32 ? 2 : 4;
         P.lds_p = fused_lds_bytes(P.nct_p, true, P.fused_T);
         P.lds_o = fused_lds_bytes(P.nct_o, false, P.fused_T);
-        P.fused = allow_fused && p->precision == TT_PREC_FP32 && method == TT_ROUND_GRAM && P.k1cap <= 64 && P.ldzcap <= 64 &&
+        P.rand = method == TT_ROUND_RAND;
+        P.fused = allow_fused && p->precision == TT_PREC_FP32 && (method == TT_ROUND_GRAM || P.rand) && P.k1cap <= 64 &&
+                  P.ldzcap <= 64 &&
                   (long long)(P.M + 64) * P.ldzcap < (1LL << 31) && std::max(P.lds_p, P.lds_o) <= 160 * 1024;
         P.fused_tiles = (P.M + 31) / 32;
         const long long want = (P.fused_tiles + kFusedWaves - 1) / kFusedWaves;
@@ -275,6 +283,14 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         P.o_Gsw = take((size_t)P.fused_T * P.nct_p * 256 * sizeof(float));
         P.o_Gfold = take((size_t)P.fused_T * P.nct_o * 256 * sizeof(float));
         P.o_GP = take((size_t)P.fused_blocks * gram_blocks(P.nct_p) * 256 * d);
+    }
+    if (P.rand) {
+        P.o_rG = take((size_t)P.KP * P.KP * d);
+        P.o_rQTh = take((size_t)P.k1cap * P.nt * P.k2cap * d);
+        P.o_rQPh = take((size_t)P.k2cap * P.np * d);
+        P.o_rP = take((size_t)P.k1cap * P.k1cap * d);
+        P.o_rVeff = take((size_t)P.k1cap * P.k1cap * d);
+        P.o_rw = take(rand_work_doubles(P.k1cap, P.nt, P.np, P.k2cap) * d);
     }
     P.row_tables = P.fused || P.bf16x;
     if (P.row_tables) {
@@ -375,6 +391,8 @@ struct tt_handle {
     Plan P;
     Geom geom{};
     int precision = 0, round_method = 0, step_order = 0;
+    int rand_p = 4;                   // randomized rounding: sketch ranks = ranks + rand_p
+    unsigned long long rand_seed = 0; // and the key of its counter-based generator
     double tol = 0.0;
     double dt = 0.0;
     double dV = 1.0;
@@ -413,6 +431,10 @@ struct tt_handle {
         return RowData{at<double>(P.o_k0), at<double>(P.o_ks), at<double>(P.o_eps), at<double>(P.o_ghost),
                        P.kfull ? at<double>(P.o_kfull) : nullptr, P.kscat ? at<double>(P.o_kscat) : nullptr,
                        P.kscat ? at<double>(P.o_jn) : nullptr};
+    }
+    RandBufs rand_bufs() {
+        return RandBufs{at<double>(P.o_rG), at<double>(P.o_rQTh), at<double>(P.o_rQPh), at<double>(P.o_rP),
+                        at<double>(P.o_rVeff), at<double>(P.o_rw)};
     }
     SmallScratch scratch() const {
         SmallScratch s;
@@ -655,20 +677,34 @@ tt_status round_fused_t(tt_handle* h, int opkind, double tol, int cap, hipStream
                        P.fused_blocks, RB, P.KP);
     h->ev_end(e, s);
     e = h->ev_begin(KC_SVD, s);
+    const double* Gin = RB;
+    const double* QThIn = h->at<double>(P.o_QTh);
+    const double* QPhIn = h->at<double>(P.o_QPh);
+    const double* Wk = sc.Wkeep;
+    const RandBufs rb = h->rand_bufs();
+    if (P.rand) {
+        hipLaunchKernelGGL(k_rand_sketch, dim3(1), dim3(kSmallThreads), kSmallLdsBytes, s, h->geom, st, Gin, P.KP,
+                           QThIn, QPhIn, h->rand_p, h->rand_seed, rb, P.KP);
+        Gin = rb.G;
+        QThIn = rb.QTh;
+        QPhIn = rb.QPh;
+        Wk = rb.Veff;
+    }
     if (P.svd_fast)
         hipLaunchKernelGGL((k_svd_chain<float, true>), dim3(1), dim3(kSmallThreads), kSmallLdsBytes, s, h->geom, st,
-                           (const double*)RB, P.KP, 1, (const double*)h->at<double>(P.o_QTh),
-                           (const double*)h->at<double>(P.o_QPh), tol, std::min(cap, P.r1cap), std::min(cap, P.r2cap),
-                           sc, h->Thn(), h->Phn(), V, h->at<double>(P.o_sv), (const float*)Gop,
-                           h->at<float>(P.o_Gfold), NO);
+                           Gin, P.KP, 1, QThIn, QPhIn, tol, std::min(cap, P.r1cap), std::min(cap, P.r2cap), sc,
+                           h->Thn(), h->Phn(), V, h->at<double>(P.o_sv), (const float*)Gop, h->at<float>(P.o_Gfold),
+                           NO);
     else
         hipLaunchKernelGGL((k_svd_chain<float, false>), dim3(1), dim3(kSmallThreads), kSmallLdsBytes, s, h->geom, st,
-                           (const double*)RB, P.KP, 1, (const double*)h->at<double>(P.o_QTh),
-                           (const double*)h->at<double>(P.o_QPh), tol, std::min(cap, P.r1cap), std::min(cap, P.r2cap),
-                           sc, h->Thn(), h->Phn(), V, h->at<double>(P.o_sv), (const float*)Gop,
-                           h->at<float>(P.o_Gfold), NO);
-    hipLaunchKernelGGL(k_fold<float>, dim3(64), dim3(256), 0, s, (const DevState*)st, (const float*)Gop,
-                       (const double*)sc.Wkeep, h->at<float>(P.o_Gfold), NO);
+                           Gin, P.KP, 1, QThIn, QPhIn, tol, std::min(cap, P.r1cap), std::min(cap, P.r2cap), sc,
+                           h->Thn(), h->Phn(), V, h->at<double>(P.o_sv), (const float*)Gop, h->at<float>(P.o_Gfold),
+                           NO);
+    if (P.rand)
+        hipLaunchKernelGGL(k_rand_fold<float>, dim3(1), dim3(1024), 0, s, st, (const double*)rb.P,
+                           (const double*)sc.Wkeep, rb.Veff, V);
+    hipLaunchKernelGGL(k_fold<float>, dim3(64), dim3(256), 0, s, (const DevState*)st, (const float*)Gop, Wk,
+                       h->at<float>(P.o_Gfold), NO);
     h->ev_end(e, s);
     e = h->ev_begin(KC_OUTPUT, s);
     hipLaunchKernelGGL((k_fused_f32<NO, false>), dim3(P.fused_blocks_o), dim3(kFusedThreads), P.lds_o, s, h->geom, fn,
@@ -810,16 +846,28 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
     }
 
     e = h->ev_begin(KC_SVD, s);
+    const double* QThIn = QTh;
+    const double* QPhIn = QPh;
+    const RandBufs rb = h->rand_bufs();
+    if (P.rand) {
+        hipLaunchKernelGGL(k_rand_sketch, dim3(1), dim3(kSmallThreads), kSmallLdsBytes, s, h->geom, st, RB, ldr, QThIn,
+                           QPhIn, h->rand_p, h->rand_seed, rb, P.KP);
+        RB = rb.G;
+        ldr = P.KP;
+        QThIn = rb.QTh;
+        QPhIn = rb.QPh;
+    }
     if (P.svd_fast)
         hipLaunchKernelGGL((k_svd_chain<T, true>), dim3(1), dim3(kSmallThreads), kSmallLdsBytes, s, h->geom, st, RB, ldr,
-                           gram, (const double*)QTh, (const double*)QPh, tol, std::min(cap, P.r1cap),
-                           std::min(cap, P.r2cap), sc, h->Thn(), h->Phn(), V, h->at<double>(P.o_sv),
-                           (const T*)nullptr, (T*)nullptr, 0);
+                           gram, QThIn, QPhIn, tol, std::min(cap, P.r1cap), std::min(cap, P.r2cap), sc, h->Thn(),
+                           h->Phn(), V, h->at<double>(P.o_sv), (const T*)nullptr, (T*)nullptr, 0);
     else
         hipLaunchKernelGGL((k_svd_chain<T, false>), dim3(1), dim3(kSmallThreads), kSmallLdsBytes, s, h->geom, st, RB, ldr,
-                           gram, (const double*)QTh, (const double*)QPh, tol, std::min(cap, P.r1cap),
-                           std::min(cap, P.r2cap), sc, h->Thn(), h->Phn(), V, h->at<double>(P.o_sv),
-                           (const T*)nullptr, (T*)nullptr, 0);
+                           gram, QThIn, QPhIn, tol, std::min(cap, P.r1cap), std::min(cap, P.r2cap), sc, h->Thn(),
+                           h->Phn(), V, h->at<double>(P.o_sv), (const T*)nullptr, (T*)nullptr, 0);
+    if (P.rand)
+        hipLaunchKernelGGL(k_rand_fold<T>, dim3(1), dim3(1024), 0, s, st, (const double*)rb.P, (const double*)sc.Wkeep,
+                           rb.Veff, V);
     h->ev_end(e, s);
 
     e = h->ev_begin(KC_OUTPUT, s);
@@ -991,6 +1039,10 @@ tt_status fill_stats(tt_handle* h, tt_stats* out, hipStream_t s) {
     out->r2 = st.r2;
     out->max_R1 = st.max_R1;
     out->max_R2 = st.max_R2;
+    if (h->P.rand) {
+        out->sketch_r1 = st.l1s;
+        out->sketch_r2 = st.l2s;
+    }
     out->norm = st.norm;
     out->discarded_rel = st.norm > 0 ? std::sqrt(std::max(st.disc2, 0.0)) / st.norm : 0.0;
     double E = 0.0;
@@ -1194,6 +1246,7 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
             HIP_TRY(hipFuncSetAttribute((const void*)k_svd_chain<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, kSmallLdsBytes));
             HIP_TRY(hipFuncSetAttribute((const void*)k_svd_chain<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, kSmallLdsBytes));
             HIP_TRY(hipFuncSetAttribute((const void*)k_svd_chain<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, kSmallLdsBytes));
+            HIP_TRY(hipFuncSetAttribute((const void*)k_rand_sketch, hipFuncAttributeMaxDynamicSharedMemorySize, kSmallLdsBytes));
             HIP_TRY(hipFuncSetAttribute((const void*)k_fused_f32<2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
             HIP_TRY(hipFuncSetAttribute((const void*)k_fused_f32<4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
             HIP_TRY(hipFuncSetAttribute((const void*)k_fused_f32<2, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
@@ -1209,6 +1262,8 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
                           ? (p->precision == TT_PREC_FP64 ? TT_ROUND_QR : TT_ROUND_GRAM)
                           : p->round_method;
     h->step_order = p->paper_step_order;
+    h->rand_p = p->rand_oversample;
+    h->rand_seed = p->rand_seed;
     h->tol = p->tol;
     h->ws = (char*)dev_workspace;
     h->create_stream = s;

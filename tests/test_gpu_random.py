@@ -1,0 +1,190 @@
+"""GPU parity of randomized rounding (TT_ROUND_RAND; Section 3.1 footnote:
+each pass compresses the TT sum to the incoming ranks plus a constant, then
+truncates at the rounding tolerance) through the C ABI against the oracle's
+randomized rounding, which draws the same random cores from its own
+Philox-4x32-10 and works on the explicit sum.
+
+The library's compression acts on the FP64 Gram of the projected first core,
+so its bounds are those of the Gram route: FP64 data 1e-8 per step and 1e-7
+over tens of steps, FP32 data 2e-6 per step and 1e-4 over tens of steps."""
+import numpy as np
+import pytest
+
+import tt_inputs as ti
+from oracle import tt as ott
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_00290_amd as tt
+    return tt
+
+
+def full(Z, Th, Ph):
+    return np.einsum("ka,alb,bp->klp", Z, Th, Ph, optimize=True)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _case(dim, prec=ti.PREC_FP64, tol=1e-7, cap=16, step_order=0, seed=0, p_over=4, key=5):
+    if dim == 1:
+        p = ti.slab1d(n_cells=37, n_groups=5, n_theta=8, tol=tol, rank_cap=cap, precision=prec, seed=seed)
+        p.kappa0 = ti.lognormal_kappa0(p.n_cells, p.extent, 1, seed=seed)
+        p.bc = (ti.BC_INFLOW_PLANCK, ti.BC_INFLOW_PLANCK, 0, 0, 0, 0)
+    elif dim == 2:
+        p = ti.plane2d(n=11, n_groups=4, n_theta=4, n_phi=6, tol=tol, rank_cap=cap, precision=prec, seed=seed)
+        p.n_cells = (11, 9, 1)
+        p.kappa0 = ti.lognormal_kappa0(p.n_cells, p.extent, 2, seed=seed)
+        p.T_cell = np.full(99, 0.1)
+    else:
+        p = ti.clumps3d(n=5, n_groups=3, n_theta=4, n_phi=4, tol=tol, rank_cap=cap, precision=prec, seed=seed)
+        p.n_cells = (5, 4, 3)
+        p.kappa0 = ti.lognormal_kappa0(p.n_cells, p.extent, 3, seed=seed)
+        p.T_cell = np.full(60, 0.1)
+    return p.copy(round_method=ti.ROUND_RAND, step_order=step_order, rand_oversample=p_over, rand_seed=key)
+
+
+@pytest.mark.parametrize("prec", [ti.PREC_FP64, ti.PREC_FP32])
+def test_randomized_one_step_matches_oracle(tt, prec):
+    p = _case(2, prec=prec, tol=1e-6)
+    print(f"rand one step prec={prec}", flush=True)
+    s = tt.Solver(p)
+    Z, Th, Ph = ti.random_tt(p.M, p.n_theta, p.n_phi, 4, 3, seed=5, decay=0.6)
+    s.set_cores(Z, Th, Ph)
+    s.solve(1)
+    Zo, To, Po, info = ott.step(p, Z, Th, Ph, round_index=0)
+    assert info["l1"] == 8 and info["l2"] == 6
+    assert s.get_ranks() == (info["r1"], info["r2"])
+    assert rel(full(*s.get_cores()), full(Zo, To, Po)) < (1e-8 if prec == ti.PREC_FP64 else 2e-6)
+    s.destroy()
+
+
+def _kept(info):
+    # sketch directions the oracle kept: singular values above the threshold
+    return tuple(max(1, int(np.sum(sv > ott.RAND_KEEP))) for sv in info["sketch_sv"])
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_randomized_fp64_solve_matches_oracle_step_by_step(tt, dim):
+    # every step of a 20-step solve from the library's own state against the
+    # oracle's randomized step from the same cores (same pass number).  When
+    # the oracle keeps every sketch direction and both sides take the same
+    # integer decisions (directions kept, truncation ranks), the compression is
+    # the projection onto the whole sketch range, which is unique: 1e-8, the
+    # Gram route's one-step bound.  When directions are dropped, the keep
+    # threshold tau lies near the Gram's resolution (~sqrt(k1 eps) of the
+    # largest singular value): the library cannot tell which of two directions
+    # near tau is the larger, so the kept subspace is fixed only up to
+    # directions of size ~tau and the results differ by at most the threshold
+    # plus the truncation tolerance per bond: 2 (tau + tol)
+    p = _case(dim)
+    K = 20
+    print(f"rand fp64 solve dim={dim}", flush=True)
+    s = tt.Solver(p)
+    same = 0
+    for k in range(K):
+        Z, Th, Ph = s.get_cores()
+        st = s.solve(1)
+        Zo, To, Po, info = ott.step(p, Z, Th, Ph, round_index=k)
+        d = rel(full(*s.get_cores()), full(Zo, To, Po))
+        kept = _kept(info)
+        if (st["sketch_r1"], st["sketch_r2"]) == kept == (info["l1"], info["l2"]) and \
+                s.get_ranks() == (info["r1"], info["r2"]):
+            same += 1
+            assert d < 1e-8, (k, d)
+        else:
+            assert d < 2 * (ott.RAND_KEEP + p.tol), (k, d)
+    print(f"whole sketch kept, same decisions: {same} of {K} steps", flush=True)
+    # and the whole solve stays within the tolerance's accumulation of the oracle's
+    (Zo, To, Po), _ = ott.solve(p, K)
+    assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 2 * K * p.tol
+    s.destroy()
+
+
+def test_randomized_paper_step_order_numbers_both_passes(tt):
+    p = _case(2, step_order=1)
+    K = 10
+    s = tt.Solver(p)
+    s.solve(K)
+    (Zo, To, Po), _ = ott.solve(p, K)
+    assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 1e-7
+    s.destroy()
+
+
+def test_randomized_fp32_fused_matches_oracle(tt):
+    p = _case(2, prec=ti.PREC_FP32, tol=1e-6, cap=12)
+    K = 20
+    s = tt.Solver(p)
+    s.solve(K)
+    (Zo, To, Po), _ = ott.solve(p, K)
+    assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 1e-4
+    s.destroy()
+
+
+def test_randomized_bf16x_within_1e4_of_fp64(tt):
+    p = _case(3, prec=ti.PREC_BF16X, tol=1e-6, cap=16)
+    out = []
+    for prob in (p, p.copy(precision=ti.PREC_FP64)):
+        s = tt.Solver(prob)
+        s.solve(8)
+        out.append(full(*s.get_cores()))
+        s.destroy()
+    assert rel(out[0], out[1]) < 1e-4
+
+
+@pytest.mark.parametrize("prec", [ti.PREC_FP64, ti.PREC_FP32])
+def test_randomized_one_step_k1_128(tt, prec):
+    # 8 x 16 directions: the projected core has k1 = 128 columns and the
+    # sketch is 24 wide; FP32 runs the unfused Gram path at this width
+    p = ti.clumps3d(n=5, n_groups=3, n_theta=8, n_phi=16, tol=1e-7, rank_cap=40, precision=prec)
+    p.n_cells = (5, 4, 3)
+    p.kappa0 = ti.lognormal_kappa0(p.n_cells, p.extent, 3, seed=0)
+    p.T_cell = np.full(60, 0.1)
+    p = p.copy(bc=(1, 0, 0, 0, 0, 0), round_method=ti.ROUND_RAND, rand_seed=2)
+    s = tt.Solver(p)
+    Z, Th, Ph = ti.random_tt(p.M, p.n_theta, p.n_phi, 20, 8, seed=7, decay=0.7)
+    s.set_cores(Z, Th, Ph)
+    s.solve(1)
+    Zo, To, Po, info = ott.step(p, Z, Th, Ph, round_index=0)
+    assert info["R1"] >= 128 and info["l1"] == 24
+    assert s.get_ranks() == (info["r1"], info["r2"])
+    assert rel(full(*s.get_cores()), full(Zo, To, Po)) < (1e-8 if prec == ti.PREC_FP64 else 2e-6)
+    s.destroy()
+
+
+def test_randomized_key_reproduces_and_changes_the_solve(tt):
+    p = _case(2, tol=1e-6, cap=12)
+    K = 10
+    out = []
+    for prob in (p, p, p.copy(rand_seed=9)):
+        s = tt.Solver(prob)
+        s.solve(K)
+        out.append(s.get_cores())
+        s.destroy()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+    d = rel(full(*out[2]), full(*out[0]))
+    assert 0 < d < 2 * K * p.tol
+
+
+def test_plane2d_full_size_randomized_one_step_fp32(tt):
+    # the 2D workload at full size (128 x 128 cells, 32 groups, 8 x 8 angles,
+    # FP32 fused path, cap 32) from a seeded rank-(32, 8) state: sketch ranks
+    # (36, 8), against the oracle's randomized step on the explicit sum
+    p = ti.plane2d().copy(round_method=ti.ROUND_RAND, rand_seed=1)
+    s = tt.Solver(p)
+    Z, Th, Ph = ti.random_tt(p.M, 8, 8, 32, 8, seed=3, decay=0.8)
+    s.set_cores(Z, Th, Ph)
+    s.solve(1)
+    Zo, To, Po, info = ott.step(p, Z, Th, Ph, round_index=0)
+    assert (info["l1"], info["l2"]) == (36, 8)
+    assert s.get_ranks() == (info["r1"], info["r2"])
+    assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 2e-6
+    s.destroy()

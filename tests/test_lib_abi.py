@@ -124,6 +124,14 @@ def test_flux_and_scattering_validation(tt):
     # scattering: the opacity, J^{m+1} and the pre-pass rows (3 N_X N_nu doubles)
     assert tt.workspace_bytes(p.copy(kappa_s_full=ks)) >= base + 3 * 16 * 4 * 8
     assert tt.workspace_bytes(p.copy(flux=ti.FLUX_RUSANOV, rusanov_s=0.0)) > 0
+    # randomized rounding: sketch buffers, and its oversampling is checked
+    assert tt.workspace_bytes(p.copy(round_method=ti.ROUND_RAND)) > tt.workspace_bytes(p.copy(round_method=ti.ROUND_GRAM))
+    for bad in (p.copy(round_method=4), p.copy(round_method=ti.ROUND_RAND, rand_oversample=0),
+                p.copy(round_method=ti.ROUND_RAND, rand_oversample=129)):
+        with pytest.raises(tt.TTError) as e:
+            tt.workspace_bytes(bad)
+        assert e.value.status == tt.TT_ERR_INVALID_ARG
+    assert tt.workspace_bytes(p.copy(round_method=ti.ROUND_GRAM, rand_oversample=0)) > 0
     for bad in (p.copy(flux=2), p.copy(flux=ti.FLUX_RUSANOV, rusanov_s=1.5),
                 p.copy(flux=ti.FLUX_RUSANOV, rusanov_s=float("nan")),
                 p.copy(kappa_s_full=ks, step_order=1)):
