@@ -19,7 +19,8 @@ committed counter summary (null when the kernel source has changed since).
 sample of the same workload.
 
 Other modes (for profiling runs; they print one line and exit):
-  --mode probe        one solve of `--probe-workload` (plane2d, clumps3d, plane2d_coupled, plane2d_rusanov_scatter)
+  --mode probe        one solve of `--probe-workload` (plane2d, clumps3d, plane2d_coupled, plane2d_rusanov_scatter,
+                      plane2d_randomized)
                       for `--probe-steps` steps
   --mode c3           the 64^3 clump workload at steady state: ranks at the cap, then `--steps` timed steps
   --mode c5-slab      one GPU's z-slab of the 256^3 spike workload (cap 18), `--steps` timed steps
@@ -214,6 +215,8 @@ def mode_probe(args):
         prob = prob.copy(heat_capacity=8.0 * ti.radiation_constant(prob.c))
     elif args.probe_workload == "plane2d_rusanov_scatter":
         prob = rusanov_scatter_problem(ti)
+    elif args.probe_workload == "plane2d_randomized":
+        prob = ti.plane2d().copy(round_method=ti.ROUND_RAND, rand_oversample=4, rand_seed=0)
     else:
         prob = ti.plane2d()
     s = tt.Solver(prob)
@@ -351,10 +354,11 @@ def main():
     ap.add_argument("--c5-warmup", type=int, default=40, help="at most this many untimed steps in --mode c5-slab")
     ap.add_argument("--probe-steps", type=int, default=64)
     ap.add_argument("--probe-workload", default="plane2d",
-                    choices=["plane2d", "clumps3d", "plane2d_coupled", "plane2d_rusanov_scatter"],
+                    choices=["plane2d", "clumps3d", "plane2d_coupled", "plane2d_rusanov_scatter", "plane2d_randomized"],
                     help="probe workload: plane2d (FP32), clumps3d (64^3 cells, 64 groups, split BF16), "
-                         "plane2d_coupled (plane2d with the coupled medium temperature, heat capacity 8 a), or "
-                         "plane2d_rusanov_scatter (plane2d with the Rusanov flux and scattering kappa_s = kappa_a)")
+                         "plane2d_coupled (plane2d with the coupled medium temperature, heat capacity 8 a), "
+                         "plane2d_rusanov_scatter (plane2d with the Rusanov flux and scattering kappa_s = kappa_a), "
+                         "or plane2d_randomized (plane2d with randomized rounding, sketch ranks = ranks + 4)")
     ap.add_argument("--copy-mb", type=int, default=512)
     ap.add_argument("--pmc-dir", default=os.path.join(ROOT, "gpurun_out", "traffic"))
     ap.add_argument("--plain-fp64", type=int, default=1, help="also time the plain FP64 TT path on seed 0")
@@ -362,6 +366,8 @@ def main():
                     help="also time seed 0 with the coupled medium temperature (heat capacity 8 a)")
     ap.add_argument("--rusanov-scatter", type=int, default=1,
                     help="also time seed 0 with the Rusanov flux and isotropic scattering (kappa_s = kappa_a)")
+    ap.add_argument("--randomized", type=int, default=1,
+                    help="also time seed 0 with randomized rounding (sketch ranks = ranks + 4) beside Gram rounding")
     ap.add_argument("--c1-batch", type=int, default=256,
                     help="also time this many independent 1D slab solves (FP64, 128 steps) as one batch")
     ap.add_argument("--served", type=int, default=256,
@@ -520,6 +526,37 @@ def main():
                "kernel_us_per_launch": {c: str_["kernel_ms"][c] / str_["kernel_launches"][c] * 1e3
                                         for c in tt.KERNEL_CLASSES if str_["kernel_launches"][c]}}
         sr.destroy()
+    # ---- phase 7: seed 0 with randomized rounding (Section 3.1 footnote), beside Gram rounding ----
+    rnd = None
+    if args.randomized:
+        prr = prob.copy(round_method=ti.ROUND_RAND, rand_oversample=4, rand_seed=0)
+        srr = tt.Solver(prr, device=dev)
+        srr.solve(2)                                   # warm-up
+        srr.reset()
+        torch.cuda.synchronize()
+        t8 = time.perf_counter()
+        strr = srr.solve(K)
+        rnd_s = time.perf_counter() - t8
+        diff = tt_rel_diff(single.get_cores(), srr.get_cores())
+        # the Gram-rounded solve under the same conditions (no events)
+        single.reset()
+        single.set_timing(False)
+        torch.cuda.synchronize()
+        t9 = time.perf_counter()
+        single.solve(K)
+        gram_s = time.perf_counter() - t9
+        srr.reset()
+        srr.set_timing(True)
+        stre = srr.solve(K)
+        ns = stre["kernel_launches"]["svd"]
+        rnd = {"solves_per_s": 1.0 / rnd_s, "ms": rnd_s * 1e3, "gram_single_solve_ms": gram_s * 1e3,
+               "oversample": 4, "ranks": [strr["r1"], strr["r2"]],
+               "sketch_ranks_last": [strr["sketch_r1"], strr["sketch_r2"]],
+               "rel_l2_vs_gram_solve": diff,
+               "svd_class_us_per_round": stre["kernel_ms"]["svd"] / max(1, K) * 1e3,
+               "svd_class_launches_per_round": ns / max(1, K),
+               "timing": "solve without events; per-class times from a second solve with HIP events"}
+        srr.destroy()
     lat_ms = np.array(lat) * 1e3
     out = {
         "metric": METRIC,
@@ -559,6 +596,8 @@ def main():
         out["coupled_temperature"] = coupled
     if rus is not None:
         out["rusanov_scattering"] = rus
+    if rnd is not None:
+        out["randomized_rounding"] = rnd
     if c1 is not None:
         out["c1_slab1d"] = c1
     if args.served > 0:

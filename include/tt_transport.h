@@ -89,7 +89,8 @@ typedef enum {
                            sum's orthogonalised ranks) by randomize-then-
                            orthogonalize with a random TT drawn from
                            Philox-4x32-10 (key rand_seed; counter = entry,
-                           core, pass number since create), then truncates
+                           core, number of rounding passes since create,
+                           set_cores or reset), then truncates
                            like TT_ROUND_GRAM.  The sketch acts on the Gram of
                            the projected core, so it adds one single-workgroup
                            kernel and no pass over Z; same accuracy floor as

@@ -106,6 +106,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_rand_sketch(Geom g, DevState*
         wk += (n + 1) & ~(size_t)1;
         return q;
     };
+    // LDS where it fits (iterated arrays first), else the global work area
+    auto place = [&](size_t n) { return cv.take(n, take(n)); };
     // random cores: R2[(a nt + l) l2 + b], R3[b np + p]
     double* R3 = take((size_t)l2 * npn);
     double* R2 = take((size_t)l1 * nt * l2);
@@ -139,8 +141,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_rand_sketch(Geom g, DevState*
     block_mm_tiled(k1, l1, k1, G, ldg, 1, Om, l1, 1, GO, l1, 1);
     __syncthreads();
     const int ldS = l1 | 1;
-    double* S = cv.take((size_t)l1 * ldS, take((size_t)l1 * ldS));
-    double* V1 = cv.take((size_t)l1 * ldS, take((size_t)l1 * ldS));
+    double* S = place((size_t)l1 * ldS);
+    double* V1 = place((size_t)l1 * ldS);
     block_mm_tiled(l1, l1, k1, Om, 1, l1, GO, l1, 1, S, 1, ldS);
     for (int idx = tid; idx < l1 * l1; idx += nth) {
         const int j = idx / l1, i = idx - j * l1;
@@ -171,7 +173,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_rand_sketch(Geom g, DevState*
     __syncthreads();
     const int l1k = sh_n;
     // P1 = Omega V Lambda^-1/2 over the kept directions (Q1 = B P1), Mq = P1^T G (= Q1^T B)
-    double* P1 = take((size_t)k1 * l1k);
+    double* P1 = place((size_t)k1 * l1k);
     for (int idx = tid; idx < k1 * l1k; idx += nth) {
         const int a = idx / l1k, j = idx - a * l1k;
         const double lam = sval[perm[j]];
@@ -189,8 +191,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_rand_sketch(Geom g, DevState*
         double* GP = take((size_t)k1 * l1k);
         block_mm_tiled(k1, l1k, k1, G, ldg, 1, P1, l1k, 1, GP, l1k, 1);
         __syncthreads();
-        double* H = take((size_t)l1k * l1k);
-        double* Rc = take((size_t)l1k * l1k);
+        double* H = place((size_t)l1k * l1k);
+        double* Rc = place((size_t)l1k * l1k);
         block_mm_tiled(l1k, l1k, k1, P1, 1, l1k, GP, l1k, 1, H, l1k, 1);
         __syncthreads();
         // right-looking Cholesky: row j of R from the current trailing block,
@@ -226,9 +228,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_rand_sketch(Geom g, DevState*
     __syncthreads();
     // middle-core sketch Y2 = Theta'_(2) W3 ((l1k N_theta) x l2, column-major)
     const int mY = l1k * nt;
-    double* Y2 = take((size_t)mY * l2);
-    double* V2 = take((size_t)l2 * l2);
-    double* nrm = take((size_t)l2);
+    double* Y2 = place((size_t)mY * l2);
+    double* V2 = place((size_t)l2 * l2);
+    double* nrm = place((size_t)l2);
     block_mm_tiled(mY, l2, k2, Thp, k2, 1, W3, l2, 1, Y2, 1, mY);
     for (int idx = tid; idx < l2 * l2; idx += nth) V2[idx] = (idx % l2 == idx / l2) ? 1.0 : 0.0;
     __syncthreads();
@@ -248,7 +250,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_rand_sketch(Geom g, DevState*
     __syncthreads();
     const int l2k = sh_n;
     // Q2: the kept columns of Y2 V2, normalised ((l1k N_theta) x l2k, column-major)
-    double* Q2 = take((size_t)mY * l2k);
+    double* Q2 = place((size_t)mY * l2k);
     for (int idx = tid; idx < mY * l2k; idx += nth) {
         const int q = idx / mY, i = idx - q * mY;
         const double s = sval[perm[q]];
@@ -259,7 +261,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_rand_sketch(Geom g, DevState*
     double* M2 = take((size_t)l2k * k2);
     block_mm_tiled(l2k, k2, mY, Q2, mY, 1, Thp, k2, 1, M2, k2, 1);
     __syncthreads();
-    double* Php = take((size_t)l2k * npn);
+    double* Php = place((size_t)l2k * npn);
     block_mm_tiled(l2k, npn, k2, M2, k2, 1, QPh, npn, 1, Php, npn, 1);
     __syncthreads();
     // right-orthogonalise the last core: Phi'^T (N_phi x l2k, column-major: the
@@ -276,7 +278,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_rand_sketch(Geom g, DevState*
     block_form_q(Php, npn, npn, kk, tau, rb.QPh, npn);   // rb.QPh[p + c np] = Q[p][c] = Q_Phi'[c][p]
     // Theta^ = Q2 x_3 R^T ((l1k N_theta) x kk row-major = l1k x (N_theta kk))
     const int mT = nt * kk;
-    double* Thh = take((size_t)mY * kk);
+    double* Thh = place((size_t)mY * kk);
     block_mm_tiled(mY, kk, l2k, Q2, 1, mY, Lf, kk, 1, Thh, kk, 1);
     __syncthreads();
     // Theta^ (l1k x mT) = R^T Q^T from the QR of its transpose (mT x l1k,
