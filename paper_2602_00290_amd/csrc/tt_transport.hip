@@ -204,8 +204,14 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         // bond-2 matrix of at most 256 rows x 16 columns
         const size_t reg0 = std::max<size_t>(64 * 65, 257 * 16);
         const size_t need = reg0 + 2 * 64 * 65 + 2 * 64 + (size_t)P.k2cap * P.k2cap + P.k2cap;
-        P.svd_fast = P.k1cap <= 64 && (long long)P.r1cap * P.nt <= 256 && P.k2cap <= 16 &&
-                     need * sizeof(double) <= (size_t)kSmallLdsBytes;
+        // the fixed layout pays for 64 columns whatever k1 is: for k1 <= 32 the
+        // Gram route's two-sided Jacobi is faster on the actual order (1D FP32,
+        // k1 = 16: 11.1 -> 6.6 ms per 64 steps); the QR route's fixed one-sided
+        // Jacobi stays faster there (30 against 41 ms for the 1D slab)
+        const bool gram_route = p->round_method == TT_ROUND_GRAM || p->round_method == TT_ROUND_RAND ||
+                                (p->round_method == TT_ROUND_AUTO && p->precision != TT_PREC_FP64);
+        P.svd_fast = P.k1cap <= 64 && !(gram_route && P.k1cap <= 32) && (long long)P.r1cap * P.nt <= 256 &&
+                     P.k2cap <= 16 && need * sizeof(double) <= (size_t)kSmallLdsBytes;
     }
     P.chunk = P.KP == 64 ? 8 * 16 : 4 * 16;
     P.elem = p->precision == TT_PREC_FP64 ? 8 : 4;

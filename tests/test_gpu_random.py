@@ -188,3 +188,28 @@ def test_plane2d_full_size_randomized_one_step_fp32(tt):
     assert s.get_ranks() == (info["r1"], info["r2"])
     assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 2e-6
     s.destroy()
+
+
+def test_randomized_solves_are_the_same_alone_and_in_a_batch(tt):
+    # three randomized solves (different problems and keys) interleaved over
+    # two streams equal each one run alone, bit for bit: every pass draws its
+    # sketch from its own handle's key and pass count
+    import torch
+    probs = [_case(2, prec=ti.PREC_FP32, tol=1e-6, cap=12, key=3),
+             _case(2, tol=1e-7, cap=16, key=4, seed=1),
+             _case(1, tol=1e-7, cap=8, key=5)]
+    K = 6
+    alone = []
+    for p in probs:
+        s = tt.Solver(p)
+        s.solve(K)
+        alone.append(s.get_cores())
+        s.destroy()
+    solvers = [tt.Solver(p) for p in probs]
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    stats = tt.solve_batch(solvers, K, streams)
+    for s, a, st in zip(solvers, alone, stats):
+        for x, y in zip(s.get_cores(), a):
+            assert np.array_equal(x, y)
+        assert st["sketch_r1"] >= 1
+        s.destroy()
