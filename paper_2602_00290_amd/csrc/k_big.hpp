@@ -178,9 +178,12 @@ __global__ __launch_bounds__(256) void k_gather_gemm(Geom g, OpDesc op, const De
 // through LDS.  The block writes its final R (KP x KP, zeros below the
 // diagonal) to Rout[blockIdx.x].
 // ncols = k1 from the state; lda is the state's ldb when lda_from_state.
+// rows_per_R > 0 (tree levels): the input is a stack of KP x KP R factors of
+// which only the first rows_per_R rows can be non-zero (k1 <= rows_per_R);
+// row r of the level is row r % rows_per_R of factor r / rows_per_R.
 template <typename TS, int KP, int NG, int BR>
 __global__ __launch_bounds__(KP* NG) void k_tsqr(const TS* __restrict__ A, int lda_static, int lda_from_state,
-                                                 long long nrows, long long rows_per_block,
+                                                 int rows_per_R, long long nrows, long long rows_per_block,
                                                  const DevState* __restrict__ st, double* __restrict__ Rout) {
     __shared__ double R[KP][KP];
     __shared__ double vbuf[2][NG * BR];
@@ -200,7 +203,8 @@ __global__ __launch_bounds__(KP* NG) void k_tsqr(const TS* __restrict__ A, int l
 #pragma unroll
         for (int i = 0; i < BR; ++i) {
             const long long row = k0 + rg * BR + i;
-            T[i] = (row < end && c < ncols) ? (double)A[row * lda + c] : 0.0;
+            const long long src = rows_per_R > 0 ? (row / rows_per_R) * KP + row % rows_per_R : row;
+            T[i] = (row < end && c < ncols) ? (double)A[src * lda + c] : 0.0;
         }
         for (int j = 0; j < ncols; ++j) {
             const int p = j & 1;

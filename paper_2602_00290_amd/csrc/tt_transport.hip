@@ -238,14 +238,19 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
     // TSQR levels
     {
         long long n = P.M;
-        int P1 = (int)std::min<long long>(2048, std::max<long long>(1, (n + 4 * P.chunk - 1) / (4 * P.chunk)));
+        // four chunks per leaf block; a small core (fewer than four such
+        // blocks) gets one chunk per block, and its tree stays short
+        long long want = (n + 4 * P.chunk - 1) / (4 * P.chunk);
+        if (want < 4) want = (n + P.chunk - 1) / P.chunk;
+        int P1 = (int)std::min<long long>(2048, std::max<long long>(1, want));
         long long rows = (n + P1 - 1) / P1;
         rows = (rows + P.chunk - 1) / P.chunk * P.chunk;
         P1 = (int)((n + rows - 1) / rows);
         P.levP.push_back(P1); P.levRows.push_back(rows); P.levN.push_back(n);
         int prev = P1;
         while (prev > 1) {
-            long long nn = (long long)prev * P.KP;
+            // only the first k1 <= k1cap rows of each R factor can be non-zero
+            long long nn = (long long)prev * P.k1cap;
             long long rr = 4LL * P.chunk;
             int Pn = (int)((nn + rr - 1) / rr);
             P.levP.push_back(Pn); P.levRows.push_back(rr); P.levN.push_back(nn);
@@ -803,17 +808,17 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
             e = h->ev_begin(L == 0 ? KC_FACTOR : KC_TREE, s);
             if (P.KP == 64) {
                 if (L == 0)
-                    hipLaunchKernelGGL((k_tsqr<T, 64, 8, 16>), dim3(P.levP[L]), dim3(512), 0, s, (const T*)B, 0, 1,
+                    hipLaunchKernelGGL((k_tsqr<T, 64, 8, 16>), dim3(P.levP[L]), dim3(512), 0, s, (const T*)B, 0, 1, 0,
                                        P.levN[L], P.levRows[L], (const DevState*)st, out);
                 else
-                    hipLaunchKernelGGL((k_tsqr<double, 64, 8, 16>), dim3(P.levP[L]), dim3(512), 0, s, in, 64, 0,
+                    hipLaunchKernelGGL((k_tsqr<double, 64, 8, 16>), dim3(P.levP[L]), dim3(512), 0, s, in, 64, 0, P.k1cap,
                                        P.levN[L], P.levRows[L], (const DevState*)st, out);
             } else {
                 if (L == 0)
-                    hipLaunchKernelGGL((k_tsqr<T, 128, 4, 16>), dim3(P.levP[L]), dim3(512), 0, s, (const T*)B, 0, 1,
+                    hipLaunchKernelGGL((k_tsqr<T, 128, 4, 16>), dim3(P.levP[L]), dim3(512), 0, s, (const T*)B, 0, 1, 0,
                                        P.levN[L], P.levRows[L], (const DevState*)st, out);
                 else
-                    hipLaunchKernelGGL((k_tsqr<double, 128, 4, 16>), dim3(P.levP[L]), dim3(512), 0, s, in, 128, 0,
+                    hipLaunchKernelGGL((k_tsqr<double, 128, 4, 16>), dim3(P.levP[L]), dim3(512), 0, s, in, 128, 0, P.k1cap,
                                        P.levN[L], P.levRows[L], (const DevState*)st, out);
             }
             h->ev_end(e, s);
