@@ -25,7 +25,10 @@
  *   * Rank is restored by TT-SVD rounding (Oseledets 2011, the SVD rounding
  *     the paper uses, Section 3.1 footnote): right-to-left QR
  *     orthogonalisation, then left-to-right delta-truncated SVDs with
- *     delta = tol * ||I||_F / sqrt(2); each rank is also capped.
+ *     delta = tol * ||I||_F / sqrt(2); each rank is also capped.  The first
+ *     core's factorisation is Householder QR or an FP64 Gram matrix (the
+ *     footnote's SVD and Gram methods); the footnote's randomized method
+ *     compresses the sum to sketch ranks first (tt_problem.round_method).
  *   * Group emission eps_g(T) = 2 T^4 int x^3/(e^x - 1) dx over the group
  *     in units h = k = c_light = 1 (Section 2, group emission; the solver's
  *     own c is a separate input).
