@@ -61,6 +61,7 @@ struct Plan {
     int r1cap = 1, r2cap = 1, R1cap = 1, R2cap = 1, k1cap = 1, k2cap = 1, ldzcap = 8, ldbcap = 8;
     int n_gather_max = 1, n_r1_max = 1;
     int KP = 64, chunk = 128;
+    int KPt = 64;                   // column tile of the TSQR (16 for QR-route cores of k1cap <= 16)
     std::vector<int> levP;          // blocks per TSQR level
     std::vector<long long> levRows; // rows per block per level
     std::vector<long long> levN;    // rows of the level input
@@ -213,7 +214,15 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         P.svd_fast = P.k1cap <= 64 && !(gram_route && P.k1cap <= 32) && (long long)P.r1cap * P.nt <= 256 &&
                      P.k2cap <= 16 && need * sizeof(double) <= (size_t)kSmallLdsBytes;
     }
-    P.chunk = P.KP == 64 ? 8 * 16 : 4 * 16;
+    // TSQR tile: a QR-route core of at most 16 columns uses a 16-column tile
+    // with 32 row groups (512-row chunks: the 1D slab's core is one chunk)
+    {
+        const int method_q = p->round_method == TT_ROUND_AUTO
+                                 ? (p->precision == TT_PREC_FP64 ? TT_ROUND_QR : TT_ROUND_GRAM)
+                                 : p->round_method;
+        P.KPt = (method_q == TT_ROUND_QR && P.k1cap <= 16) ? 16 : P.KP;
+    }
+    P.chunk = P.KPt == 16 ? 32 * 16 : (P.KP == 64 ? 8 * 16 : 4 * 16);
     P.elem = p->precision == TT_PREC_FP64 ? 8 : 4;
     {
         const int method = p->round_method == TT_ROUND_AUTO
@@ -806,7 +815,14 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
         double* out = RA;
         for (size_t L = 0; L < P.levP.size(); ++L) {
             e = h->ev_begin(L == 0 ? KC_FACTOR : KC_TREE, s);
-            if (P.KP == 64) {
+            if (P.KPt == 16) {
+                if (L == 0)
+                    hipLaunchKernelGGL((k_tsqr<T, 16, 32, 16>), dim3(P.levP[L]), dim3(512), 0, s, (const T*)B, 0, 1, 0,
+                                       P.levN[L], P.levRows[L], (const DevState*)st, out);
+                else
+                    hipLaunchKernelGGL((k_tsqr<double, 16, 32, 16>), dim3(P.levP[L]), dim3(512), 0, s, in, 16, 0, P.k1cap,
+                                       P.levN[L], P.levRows[L], (const DevState*)st, out);
+            } else if (P.KP == 64) {
                 if (L == 0)
                     hipLaunchKernelGGL((k_tsqr<T, 64, 8, 16>), dim3(P.levP[L]), dim3(512), 0, s, (const T*)B, 0, 1, 0,
                                        P.levN[L], P.levRows[L], (const DevState*)st, out);
@@ -826,6 +842,7 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
             out = (out == RA) ? RBuf : RA;
         }
         RB = in;
+        ldr = P.KPt;
     } else {
         gram = 1;
         e = h->ev_begin(KC_FACTOR, s);
