@@ -1045,9 +1045,11 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
         __syncthreads();
         tph[1] = wall_clock64();
         // J = R_B W has non-zero rows only below k1 (R_B is k1 x k1 upper
-        // triangular): for k1 <= 16 the rotations run over 16 rows
+        // triangular): for k1 <= 16 (32) the rotations run over 16 (32) rows
         if (FAST && k1 <= 16)
             sw1 = block_jacobi_1s_fixed<2, 8, 2>(J, ld, k1, W, ld, &sh_flag, red);
+        else if (FAST && k1 <= 32)
+            sw1 = block_jacobi_1s_fixed<4, 8, 4>(J, ld, k1, W, ld, &sh_flag, red);
         else if (FAST)
             sw1 = block_jacobi_1s_fixed<8, 8, 8>(J, ld, k1, W, ld, &sh_flag, red);
         else
