@@ -213,3 +213,21 @@ def test_randomized_solves_are_the_same_alone_and_in_a_batch(tt):
             assert np.array_equal(x, y)
         assert st["sketch_r1"] >= 1
         s.destroy()
+
+
+def test_randomized_with_rusanov_flux_and_scattering_one_step(tt):
+    # the source pre-pass (scattering) and the Rusanov operator feed the same
+    # randomized pass: one step from a seeded state against the oracle's
+    # randomized step, FP64 (Gram route bound 1e-8)
+    p = _case(2, tol=1e-6, cap=16)
+    rng = np.random.default_rng(8)
+    p = p.copy(flux=ti.FLUX_RUSANOV, rusanov_s=1.0, kappa_s_full=rng.uniform(0.0, 3.0, (p.n_x, p.n_groups)))
+    s = tt.Solver(p)
+    Z, Th, Ph = ti.random_tt(p.M, p.n_theta, p.n_phi, 5, 3, seed=9, decay=0.6)
+    s.set_cores(Z, Th, Ph)
+    st = s.solve(1)
+    Zo, To, Po, info = ott.step(p, Z, Th, Ph, round_index=0)
+    assert s.get_ranks() == (info["r1"], info["r2"])
+    assert (st["sketch_r1"], st["sketch_r2"]) == _kept(info)
+    assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 1e-8
+    s.destroy()
