@@ -283,8 +283,15 @@ def round_tt(Z, Th, Ph, tol: float, cap: int):
     Pho = (s2[:r2, None] * Vt2[:r2]) @ Ph_o
     info = dict(norm=norm, r1=r1, r2=r2, sv1=s, sv2=s2,
                 discarded=float(math.sqrt(np.sum(s[r1:] ** 2) + np.sum(s2[r2:] ** 2))),
-                R1=R1, R2=R2)
+                R1=R1, R2=R2, k_s=storage_factor((Z, Th, Ph), (Zo, Tho, Pho)))
     return Zo, Tho, Pho, info
+
+
+def storage_factor(before, after) -> float:
+    """k_s of one rounding (Section 3.2 and the appendix on compression): the
+    entries of the TT as it stands before rounding (the explicit sum the SVD
+    method forms) over the entries of the rounded TT, counted on the arrays."""
+    return float(sum(a.size for a in before)) / float(sum(a.size for a in after))
 
 
 # Randomized rounding (Section 3.1 footnote: the solver's third rounding

@@ -200,3 +200,20 @@ def test_compression_formula_paper_values():
     assert round(tt.compression(p, 1, 1), -2) == 4100.0
     p100 = p.copy(edges=np.zeros(101), kappa_scale=np.ones(100))
     assert 0.9e5 < tt.compression(p100, 1, 1) < 1.25e5
+
+
+@pytest.mark.parametrize("dim,n,nphi,nt", [(1, (40,), 1, 8), (2, (12, 10), 4, 4)])
+def test_storage_factor_within_the_papers_bounds(dim, n, nphi, nt):
+    # the appendix on compression: once the ranks exceed n and the first core
+    # dominates the storage, the SVD method's k_s lies between n + 1 (the
+    # transport update scales the ranks by n + 1) and (n + 1)^2; k_s counts
+    # the entries of the explicit sum the oracle builds over the rounded TT
+    p = _prob(dim, n, G=6, nt=nt, nphi=nphi, bc=(1, 0, 0, 0, 0, 0)).copy(tol=1e-9, rank_cap=64)
+    Z, Th, Ph = ti.random_tt(p.M, nt, nphi, 8, min(nphi, 3), seed=2, decay=0.8)
+    nterm = 2 * dim
+    for _ in range(6):
+        Zs, Ts, Ps = tt.apply_step(p, Z, Th, Ph)
+        Z, Th, Ph, info = tt.round_tt(Zs, Ts, Ps, p.tol, p.rank_cap)
+        assert info["k_s"] == (Zs.size + Ts.size + Ps.size) / (Z.size + Th.size + Ph.size)
+    assert Z.shape[1] > nterm
+    assert nterm + 1 <= info["k_s"] <= (nterm + 1) ** 2
