@@ -198,7 +198,10 @@ typedef struct tt_stats {
     double norm;          /* ||I||_F before the last truncation                       */
     double discarded_rel; /* sqrt(sum of discarded sigma^2) / norm, last rounding     */
     double energy;        /* dV * sum_k sum_lp w_l w_p I[k,l,p] of the current state */
-    double k_s;           /* peak storage / post-round storage (Section 3.2 k_s)      */
+    double k_s;           /* storage factor of the last rounding pass (Section 3.2
+                             k_s): entries of the TT sum before rounding (ranks
+                             R1, R2, as SVD rounding forms it) over the entries
+                             of the rounded TT; 1 before the first pass          */
     double compression;   /* N_X N_nu N_theta N_phi / TT entries (Section 3.2 eq.)    */
     double seconds;       /* wall time of the last solve (host clock, synchronised)  */
     double kernel_ms[8];  /* summed HIP-event durations per kernel class when timing
@@ -214,6 +217,11 @@ typedef struct tt_stats {
     int sketch_r1, sketch_r2; /* TT_ROUND_RAND: ranks of the last randomized
                              compression after null sketch directions were
                              dropped (0 for the other methods)                       */
+    double k_s_impl;      /* this library's peak storage in the last pass (input Z,
+                             stored projected core M x k1 unless the pass is
+                             fused, output Z, the R1 x N_theta x R2 core) over the
+                             entries of the rounded TT; the TT sum itself is
+                             never formed                                             */
 } tt_stats;
 
 /* Internal delta-ranks of the combined core Z (section "Internal structure of

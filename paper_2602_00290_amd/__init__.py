@@ -86,6 +86,7 @@ class TTStats(ctypes.Structure):
         ("medium_energy", ctypes.c_double),
         ("sketch_r1", ctypes.c_int),
         ("sketch_r2", ctypes.c_int),
+        ("k_s_impl", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -95,6 +96,7 @@ class TTStats(ctypes.Structure):
         d["flops"] = dict(zip(KERNEL_CLASSES, list(self.flops)))
         d["medium_energy"] = self.medium_energy
         d["sketch_r1"], d["sketch_r2"] = self.sketch_r1, self.sketch_r2
+        d["k_s_impl"] = self.k_s_impl
         return d
 
 

@@ -704,13 +704,15 @@ __device__ __forceinline__ void block_mm_tiled(int m, int n, int K, const double
     }
 }
 
-// Descending order of s[0..n) into perm (ties by index).
+// Descending order of s[0..n) into perm (ties by index).  A NaN sorts as
+// -inf, so the comparison stays a total order and perm a permutation of
+// 0..n-1 whatever the values (a NaN state is then reported, not indexed).
 __device__ __forceinline__ void block_sort_desc(const double* s, int n, int* perm) {
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const double v = s[j];
+        const double v = s[j] == s[j] ? s[j] : -INFINITY;
         int rank = 0;
         for (int i = 0; i < n; ++i) {
-            const double u = s[i];
+            const double u = s[i] == s[i] ? s[i] : -INFINITY;
             if (u > v || (u == v && i < j)) ++rank;
         }
         perm[rank] = j;
@@ -1251,6 +1253,7 @@ __global__ __launch_bounds__(256) void k_fold(const DevState* __restrict__ st, c
 // Make the truncated cores current.
 __global__ void k_commit(DevState* st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->r1_in = st->r1;
         st->r1 = st->r1n;
         st->r2 = st->r2n;
         st->ldz = st->ldzn;

@@ -44,7 +44,7 @@ struct DevState {
     int kall;          // rows of the gather operand: n_gather * ldz + n_r1
     int k1b;           // columns of the projected core B (k1 until a randomized pass compresses the sum)
     int l1s, l2s;      // ranks of the last randomized compression (after dropping null sketch directions)
-    int pad2;
+    int r1_in;         // first rank of the state the last rounding pass started from
 };
 
 // Static description of the problem shared by all kernels (passed by value).

@@ -1093,9 +1093,23 @@ tt_status fill_stats(tt_handle* h, tt_stats* out, hipStream_t s) {
     const double dense = (double)P.M * P.nt * P.np;
     const double tt = (double)P.M * st.r1 + (double)P.nt * st.r1 * st.r2 + (double)P.np * st.r2;
     out->compression = dense / tt;
-    // peak working set of a round (input Z, projected core B, output Z) over the rounded TT
-    const double peak = (double)P.M * (st.r1 + P.k1cap + st.r1) + (double)P.nt * P.R1cap * P.R2cap;
-    out->k_s = peak / tt;
+    // Storage factor k_s of the last rounding pass (Sec. 3.2 and the appendix
+    // on compression): entries of the TT sum before rounding, as the SVD
+    // rounding forms it explicitly (ranks R1, R2), over the rounded TT.
+    // k_s_impl: this library's own peak of the pass, at the sizes it reached:
+    // input Z, the stored projected core B (M x k1; none on the fused path),
+    // output Z and the (R1, R2) middle core, over the rounded TT.
+    if (st.rounds > 0 && st.R1 > 0 && st.R2 > 0) {
+        const double sum = (double)P.M * st.R1 + (double)P.nt * st.R1 * st.R2 + (double)P.np * st.R2;
+        out->k_s = sum / tt;
+        const double bst = P.fused ? 0.0 : (double)P.M * st.k1;
+        const double impl = (double)P.M * (st.r1_in + st.r1) + bst + (double)P.nt * st.R1 * st.R2 +
+                            (double)P.np * st.R2;
+        out->k_s_impl = impl / tt;
+    } else {
+        out->k_s = 1.0;
+        out->k_s_impl = 1.0;
+    }
     out->seconds = h->last_seconds;
     for (int i = 0; i < 8; ++i) {
         out->kernel_ms[i] = h->kernel_ms[i];
