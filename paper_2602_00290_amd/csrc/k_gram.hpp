@@ -1,5 +1,5 @@
-// FP64 Gram matrix of a stored FP32 first core with 128 columns (k1 up to
-// 128) on FP64 MFMA, for the unfused Gram rounding of wide first cores.
+// FP64 Gram matrix of a stored FP32 or FP64 first core with 128 columns (k1
+// up to 128) on FP64 MFMA, for the unfused Gram rounding of wide first cores.
 #pragma once
 
 #include "k_fused.hpp"
@@ -17,14 +17,18 @@ namespace ttrt {
 // are read from LDS at fixed columns and the B operands of the column groups
 // it needs.  Each block writes its compact partial (36 blocks x 4 registers x
 // 64 lanes) for k_sum_gram<8>.
-template <int W>
-__device__ __forceinline__ void gram_w8_wave(const float* __restrict__ B, int ldb, long long begin, long long end,
-                                             float* Bs, double* __restrict__ outp) {
+// TB is the stored element type (float, or double for FP64 data: 32-row
+// chunks, the same LDS bytes).
+template <int W, typename TB>
+__device__ __forceinline__ void gram_w8_wave(const TB* __restrict__ B, int ldb, long long begin, long long end,
+                                             TB* Bs, double* __restrict__ outp) {
     constexpr int NCT = 8;
     constexpr int NC = 16 * NCT;              // columns
-    constexpr int CH = 64;                    // rows per chunk
-    constexpr int LDC = NC + 4;               // LDS row stride (floats)
-    constexpr int V4 = CH * NC / 4 / 256;     // float4 loads per thread per chunk
+    constexpr int VE = 16 / sizeof(TB);       // elements per 16-byte load
+    constexpr int CH = 16 * VE;               // rows per chunk: 64 (float), 32 (double)
+    constexpr int LDC = NC + 4;               // LDS row stride (elements)
+    constexpr int V4 = CH * NC / VE / 256;    // 16-byte loads per thread per chunk
+    typedef TB vec_t __attribute__((ext_vector_type(VE)));
     constexpr int GA = W, GB = NCT - 1 - W;   // this wave's two block rows
     constexpr int NA = NCT - GA, NBB = NCT - GB;
     const int tid = threadIdx.x, l = tid & 63;
@@ -33,16 +37,16 @@ __device__ __forceinline__ void gram_w8_wave(const float* __restrict__ B, int ld
     for (int g = 0; g < NA; ++g) accA[g] = (f64x4){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int g = 0; g < NBB; ++g) accB[g] = (f64x4){0.0, 0.0, 0.0, 0.0};
-    float4 nx[V4];
+    vec_t nx[V4];
     auto load = [&](long long r0) {
 #pragma unroll
         for (int v = 0; v < V4; ++v) {
             const int slot = tid + 256 * v;
-            const int r = slot / (NC / 4), c4 = (slot % (NC / 4)) * 4;
+            const int r = slot / (NC / VE), c4 = (slot % (NC / VE)) * VE;
             const long long row = r0 + r;
-            float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+            vec_t x = (vec_t)(TB)0;
             // columns from k1 up to ldb are zero in B; beyond ldb they are not read
-            if (row < end && c4 < ldb) x = *reinterpret_cast<const float4*>(B + row * ldb + c4);
+            if (row < end && c4 < ldb) x = *reinterpret_cast<const vec_t*>(B + row * ldb + c4);
             nx[v] = x;
         }
     };
@@ -53,14 +57,14 @@ __device__ __forceinline__ void gram_w8_wave(const float* __restrict__ B, int ld
 #pragma unroll
         for (int v = 0; v < V4; ++v) {
             const int slot = tid + 256 * v;
-            const int r = slot / (NC / 4), c4 = (slot % (NC / 4)) * 4;
-            *reinterpret_cast<float4*>(Bs + r * LDC + c4) = nx[v];
+            const int r = slot / (NC / VE), c4 = (slot % (NC / VE)) * VE;
+            *reinterpret_cast<vec_t*>(Bs + r * LDC + c4) = nx[v];
         }
         __syncthreads();
         if (r0 + CH < end) load(r0 + CH);
 #pragma unroll 2
         for (int k = 0; k < CH; k += 4) {
-            const float* rp = Bs + (k + kr) * LDC + col;
+            const TB* rp = Bs + (k + kr) * LDC + col;
             const double a = (double)rp[16 * GA], b2 = (double)rp[16 * GB];
             double v[NCT];
 #pragma unroll
@@ -99,10 +103,29 @@ __global__ __launch_bounds__(256) void k_gram_f64_mfma_w8(const float* __restric
     double* outp = Gpart + (size_t)blockIdx.x * NB * 256;
     // the wave index is uniform over a wave; every branch meets the same barriers
     switch (threadIdx.x >> 6) {
-        case 0: gram_w8_wave<0>(B, ldb, begin, end, Bs, outp); break;
-        case 1: gram_w8_wave<1>(B, ldb, begin, end, Bs, outp); break;
-        case 2: gram_w8_wave<2>(B, ldb, begin, end, Bs, outp); break;
-        default: gram_w8_wave<3>(B, ldb, begin, end, Bs, outp); break;
+        case 0: gram_w8_wave<0, float>(B, ldb, begin, end, Bs, outp); break;
+        case 1: gram_w8_wave<1, float>(B, ldb, begin, end, Bs, outp); break;
+        case 2: gram_w8_wave<2, float>(B, ldb, begin, end, Bs, outp); break;
+        default: gram_w8_wave<3, float>(B, ldb, begin, end, Bs, outp); break;
+    }
+}
+
+// The same for a stored FP64 first core (FP64 data on the Gram route).
+__global__ __launch_bounds__(256) void k_gram_f64_mfma_w8d(const double* __restrict__ B,
+                                                            const DevState* __restrict__ st, long long nrows,
+                                                            long long rows_per_block, double* __restrict__ Gpart) {
+    constexpr int NB = gram_blocks(8);
+    __shared__ double Bs[32 * (128 + 4)];
+    const int ldb = st->ldb;
+    const long long begin = (long long)blockIdx.x * rows_per_block;
+    long long end = begin + rows_per_block;
+    if (end > nrows) end = nrows;
+    double* outp = Gpart + (size_t)blockIdx.x * NB * 256;
+    switch (threadIdx.x >> 6) {
+        case 0: gram_w8_wave<0, double>(B, ldb, begin, end, Bs, outp); break;
+        case 1: gram_w8_wave<1, double>(B, ldb, begin, end, Bs, outp); break;
+        case 2: gram_w8_wave<2, double>(B, ldb, begin, end, Bs, outp); break;
+        default: gram_w8_wave<3, double>(B, ldb, begin, end, Bs, outp); break;
     }
 }
 

@@ -25,6 +25,7 @@
 #include "k_bf16x.hpp"
 #include "k_big.hpp"
 #include "k_fused.hpp"
+#include "k_f64.hpp"
 #include "k_gram.hpp"
 #include "k_mfma.hpp"
 #include "k_couple.hpp"
@@ -91,6 +92,10 @@ struct Plan {
     bool rand = false;
     size_t o_rG = 0, o_rQTh = 0, o_rQPh = 0, o_rP = 0, o_rVeff = 0, o_rw = 0;
     bool row_tables = false;        // per-row d, neighbour and rank-1 tables (fused and split-BF16 paths)
+    // FP64 data: projection and output contractions on FP64 MFMA (k_mm_f64)
+    bool f64mm = false;
+    int nct_f = 1, nct_fo = 1;      // 16-column tiles of B / of Z_out
+    int f64_blocks = 1;             // blocks of the persistent projection / output kernels
     size_t o_state, o_Z0, o_Z1, o_B, o_Th0, o_Th1, o_Ph0, o_Ph1, o_LTh, o_QTh, o_QPh, o_G, o_V, o_RA, o_RB, o_small,
         o_k0, o_ks, o_kfull = 0, o_eps, o_ghost, o_gtab, o_htab, o_ThN, o_PhN, o_sv, o_colsum;
     size_t small_bytes = 0, n_parts_max = 1;
@@ -244,6 +249,16 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         P.fused_blocks_o = (int)std::max<long long>(1, std::min<long long>(512, want));
         if (P.fused_blocks_o > 8) P.fused_blocks_o = P.fused_blocks_o / 8 * 8;
     }
+    // FP64 MFMA contractions: B up to 128 columns, Z_out up to 64
+    {
+        auto nct_for = [](int ld) { return ld <= 16 ? 1 : (ld <= 32 ? 2 : (ld <= 64 ? 4 : 8)); };
+        P.f64mm = p->precision == TT_PREC_FP64 && P.ldbcap <= 128 && P.ldzcap <= 64 && P.M < (1LL << 31);
+        P.nct_f = nct_for(P.ldbcap);
+        P.nct_fo = nct_for(P.ldzcap);
+        const long long nrb = (P.M + kF64Rows - 1) / kF64Rows;
+        P.f64_blocks = (int)std::max<long long>(1, std::min<long long>(256, nrb));
+        if (P.f64_blocks > 8) P.f64_blocks = P.f64_blocks / 8 * 8;
+    }
     // TSQR levels
     {
         long long n = P.M;
@@ -273,6 +288,7 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         P.Pg = (int)((P.M + rows - 1) / rows);
         P.rowsg = rows;
         P.n_parts_max = std::max<size_t>(P.n_parts_max, (size_t)P.Pg);
+        P.n_parts_max = std::max<size_t>(P.n_parts_max, (size_t)P.f64_blocks);
     }
     // layout
     size_t off = 0;
@@ -745,6 +761,48 @@ tt_status round_fused(tt_handle* h, int opkind, double tol, int cap, hipStream_t
     return P.nct_o == 4 ? round_fused_t<2, 4>(h, opkind, tol, cap, s) : round_fused_t<2, 2>(h, opkind, tol, cap, s);
 }
 
+// FP64 MFMA contractions (k_mm_f64): the projection B = Z_new L_Theta, with
+// the FP64 Gram partials of B fused in when `gram` (16 NCT <= 64 columns), and
+// the output Z_out = B V_r.
+template <int MODE, int NCT, bool GRAM>
+void launch_mm_f64(tt_handle* h, const OpDesc& op, const double* A, const double* Gop, double* Out, double* parts,
+                   hipStream_t s) {
+    const Plan& P = h->P;
+    // one row tile per wave where two would spill: 128 columns, or 64 with the fused Gram
+    constexpr int RT = (NCT == 8 || (NCT == 4 && GRAM)) ? 1 : 2;
+    hipLaunchKernelGGL((k_mm_f64<MODE, NCT, GRAM, RT>), dim3(P.f64_blocks), dim3(kF64Threads),
+                       f64_lds_bytes(NCT, GRAM), s, h->geom, op, (const DevState*)h->st(), A, Gop, Out, h->rowdata(),
+                       parts);
+}
+
+void project_f64(tt_handle* h, const OpDesc& op, bool gram, double* parts, hipStream_t s) {
+    const Plan& P = h->P;
+    const double* Z = (const double*)h->Zc();
+    const double* G = h->at<double>(P.o_G);
+    double* B = h->at<double>(P.o_B);
+    switch (P.nct_f) {
+        case 1: gram ? launch_mm_f64<MODE_PROJECT, 1, true>(h, op, Z, G, B, parts, s)
+                     : launch_mm_f64<MODE_PROJECT, 1, false>(h, op, Z, G, B, parts, s); break;
+        case 2: gram ? launch_mm_f64<MODE_PROJECT, 2, true>(h, op, Z, G, B, parts, s)
+                     : launch_mm_f64<MODE_PROJECT, 2, false>(h, op, Z, G, B, parts, s); break;
+        case 4: gram ? launch_mm_f64<MODE_PROJECT, 4, true>(h, op, Z, G, B, parts, s)
+                     : launch_mm_f64<MODE_PROJECT, 4, false>(h, op, Z, G, B, parts, s); break;
+        default: launch_mm_f64<MODE_PROJECT, 8, false>(h, op, Z, G, B, parts, s); break;
+    }
+}
+
+void output_f64(tt_handle* h, const OpDesc& op, hipStream_t s) {
+    const Plan& P = h->P;
+    const double* B = h->at<double>(P.o_B);
+    const double* V = h->at<double>(P.o_V);
+    double* Zo = (double*)h->Zn();
+    switch (P.nct_fo) {
+        case 1: launch_mm_f64<MODE_OUTPUT, 1, false>(h, op, B, V, Zo, nullptr, s); break;
+        case 2: launch_mm_f64<MODE_OUTPUT, 2, false>(h, op, B, V, Zo, nullptr, s); break;
+        default: launch_mm_f64<MODE_OUTPUT, 4, false>(h, op, B, V, Zo, nullptr, s); break;
+    }
+}
+
 // One rounding pass applying operator `op` (OP_NONE: plain rounding).
 template <typename T>
 tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t s) {
@@ -800,6 +858,8 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
                                h->geom, op, (const DevState*)st, (const float*)h->Zc(), (const float*)Gop, (float*)B,
                                h->rowdata());
         }
+    } else if (P.f64mm) {
+        project_f64(h, op, h->round_method != TT_ROUND_QR && P.nct_f <= 4, h->at<double>(P.o_RA), s);
     } else
         hipLaunchKernelGGL((k_gather_gemm<T, MODE_PROJECT>), dim3(gx, (P.ldbcap + 63) / 64), dim3(256), 0, s, h->geom,
                            op, st, (const T*)h->Zc(), (const T*)Gop, B, h->rowdata());
@@ -843,6 +903,28 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
         }
         RB = in;
         ldr = P.KPt;
+    } else if (!f32 && P.f64mm) {
+        // FP64 Gram of the stored B: fused into the projection (partials in RA)
+        // for up to 64 columns, else the 128-column FP64 MFMA Gram over B
+        gram = 1;
+        e = h->ev_begin(KC_FACTOR, s);
+        if (P.nct_f == 8)
+            hipLaunchKernelGGL(k_gram_f64_mfma_w8d, dim3(P.Pg), dim3(256), 0, s, (const double*)B, (const DevState*)st,
+                               P.M, P.rowsg, RA);
+        h->ev_end(e, s);
+        e = h->ev_begin(KC_TREE, s);
+        switch (P.nct_f) {
+            case 1: hipLaunchKernelGGL(k_sum_gram<1>, dim3((gram_blocks(1) * 256 + 31) / 32), dim3(256), 0, s,
+                                       (const double*)RA, P.f64_blocks, RBuf, P.KP); break;
+            case 2: hipLaunchKernelGGL(k_sum_gram<2>, dim3((gram_blocks(2) * 256 + 31) / 32), dim3(256), 0, s,
+                                       (const double*)RA, P.f64_blocks, RBuf, P.KP); break;
+            case 4: hipLaunchKernelGGL(k_sum_gram<4>, dim3((gram_blocks(4) * 256 + 31) / 32), dim3(256), 0, s,
+                                       (const double*)RA, P.f64_blocks, RBuf, P.KP); break;
+            default: hipLaunchKernelGGL(k_sum_gram<8>, dim3((gram_blocks(8) * 256 + 31) / 32), dim3(256), 0, s,
+                                        (const double*)RA, P.Pg, RBuf, P.KP); break;
+        }
+        h->ev_end(e, s);
+        RB = RBuf;
     } else {
         gram = 1;
         e = h->ev_begin(KC_FACTOR, s);
@@ -920,6 +1002,8 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
             hipLaunchKernelGGL((k_gemm_f32_mfma<MODE_OUTPUT, 64>), dim3(gx128, (P.ldzcap + 63) / 64), dim3(256), 0, s,
                                h->geom, op, (const DevState*)st, (const float*)B, (const float*)V, (float*)h->Zn(),
                                h->rowdata());
+    } else if (P.f64mm) {
+        output_f64(h, op, s);
     } else {
         hipLaunchKernelGGL((k_gather_gemm<T, MODE_OUTPUT>), dim3(gx, (P.ldzcap + 63) / 64), dim3(256), 0, s, h->geom,
                            op, (const DevState*)st, (const T*)B, (const T*)V, (T*)h->Zn(), h->rowdata());
@@ -1293,6 +1377,20 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
             HIP_TRY(hipFuncSetAttribute((const void*)k_fused_f32<4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
             HIP_TRY(hipFuncSetAttribute((const void*)k_fused_f32<2, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
             HIP_TRY(hipFuncSetAttribute((const void*)k_fused_f32<4, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+            // the FP64 MFMA kernels: their own dynamic LDS (they also hold a little static LDS)
+            const std::pair<const void*, size_t> f64k[] = {
+                {(const void*)k_mm_f64<MODE_PROJECT, 1, false, 2>, f64_lds_bytes(1, false)},
+                {(const void*)k_mm_f64<MODE_PROJECT, 1, true, 2>, f64_lds_bytes(1, true)},
+                {(const void*)k_mm_f64<MODE_PROJECT, 2, false, 2>, f64_lds_bytes(2, false)},
+                {(const void*)k_mm_f64<MODE_PROJECT, 2, true, 2>, f64_lds_bytes(2, true)},
+                {(const void*)k_mm_f64<MODE_PROJECT, 4, false, 2>, f64_lds_bytes(4, false)},
+                {(const void*)k_mm_f64<MODE_PROJECT, 4, true, 1>, f64_lds_bytes(4, true)},
+                {(const void*)k_mm_f64<MODE_PROJECT, 8, false, 1>, f64_lds_bytes(8, false)},
+                {(const void*)k_mm_f64<MODE_OUTPUT, 1, false, 2>, f64_lds_bytes(1, false)},
+                {(const void*)k_mm_f64<MODE_OUTPUT, 2, false, 2>, f64_lds_bytes(2, false)},
+                {(const void*)k_mm_f64<MODE_OUTPUT, 4, false, 2>, f64_lds_bytes(4, false)}};
+            for (const auto& fk : f64k)
+                HIP_TRY(hipFuncSetAttribute(fk.first, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fk.second));
             attrs_set = true;
         }
     }
