@@ -249,6 +249,22 @@ size_t tt_transport_workspace_bytes(const tt_problem* p);
 tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t bytes,
                               void* stream, tt_handle** out);
 
+/* The same as tt_transport_create, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the workspace is a static array of 64 MiB that the
+ * library holds on each device from module load until the process ends, so
+ * this call allocates nothing.  It serves problems whose
+ * tt_transport_workspace_bytes() is at most 64 MiB (small requests such as
+ * the 1D slab, ~1 MiB); larger ones fail with TT_ERR_INVALID_ARG.  One
+ * handle at a time may hold a device's array: a second call on the same
+ * device fails with TT_ERR_STATE until the first handle is destroyed.
+ * Work of a destroyed handle still in flight on a stream races with the
+ * next handle's: synchronise the stream before tt_transport_destroy.  The
+ * array keeps the last handle's contents; creation initialises everything a
+ * solve reads.  Synchronises like tt_transport_create.
+ * Errors: TT_ERR_INVALID_ARG, TT_ERR_STATE, TT_ERR_HIP. */
+tt_status tt_transport_create_noalloc(const tt_problem* p, void* stream, tt_handle** out);
+
 /* Apply the transport + source operator once without rounding (Appendix A):
  * afterwards the handle holds the unrounded TT sum with ranks
  * (n+1) r + n_bc + 1; tt_transport_get_cores materialises it.  With

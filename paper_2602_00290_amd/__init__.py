@@ -133,6 +133,7 @@ def _load():
     L.tt_transport_workspace_bytes.argtypes = [ctypes.POINTER(TTProblem)]
     L.tt_transport_workspace_bytes.restype = ctypes.c_size_t
     L.tt_transport_create.argtypes = [ctypes.POINTER(TTProblem), vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.tt_transport_create_noalloc.argtypes = [ctypes.POINTER(TTProblem), vp, ctypes.POINTER(vp)]
     L.tt_transport_apply_op.argtypes = [vp, vp]
     L.tt_transport_round.argtypes = [vp, ctypes.c_double, ctypes.c_int, vp]
     L.tt_transport_solve.argtypes = [vp, ctypes.c_int, ctypes.POINTER(TTStats), vp]
@@ -152,7 +153,7 @@ def _load():
     L.tt_transport_get_temperature.argtypes = [vp, _dp, vp]
     L.tt_transport_internal_ranks.argtypes = [vp, ctypes.c_double, ctypes.POINTER(TTInternalRanks), _dp, ctypes.c_int,
                                               _dp, ctypes.c_int, vp]
-    for name in ("create", "apply_op", "round", "solve", "reset", "get_ranks", "get_cores", "set_cores",
+    for name in ("create", "create_noalloc", "apply_op", "round", "solve", "reset", "get_ranks", "get_cores", "set_cores",
                  "get_stats", "set_timing", "step_batch", "solve_batch", "destroy", "group_emission",
                  "get_temperature", "internal_ranks"):
         getattr(L, "tt_transport_" + name).restype = ctypes.c_int
@@ -161,7 +162,7 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ("tt_transport_workspace_bytes", "tt_transport_create", "tt_transport_apply_op", "tt_transport_round",
+EXPORTED = ("tt_transport_workspace_bytes", "tt_transport_create", "tt_transport_create_noalloc", "tt_transport_apply_op", "tt_transport_round",
             "tt_transport_solve", "tt_transport_reset", "tt_transport_get_ranks", "tt_transport_get_cores",
             "tt_transport_set_cores", "tt_transport_get_stats", "tt_transport_set_timing",
             "tt_transport_step_batch", "tt_transport_solve_batch", "tt_transport_destroy", "tt_transport_last_error",
@@ -250,7 +251,10 @@ class Solver:
     """One TT transport solve on a GPU: owns the device workspace (a torch
     uint8 tensor) and the library handle."""
 
-    def __init__(self, prob, device="cuda:0", stream=None, round_method: Optional[int] = None, workspace=None):
+    def __init__(self, prob, device="cuda:0", stream=None, round_method: Optional[int] = None, workspace=None,
+                 noalloc: bool = False):
+        """noalloc: create with tt_transport_create_noalloc (the library's static
+        workspace of its device; nothing is allocated)."""
         import torch
 
         self.prob = prob
@@ -260,16 +264,22 @@ class Solver:
         if nbytes == 0:
             _check(TT_ERR_INVALID_ARG)
         self.nbytes = int(nbytes)
-        if workspace is None:
-            workspace = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
-        self.workspace = workspace
-        base = workspace.data_ptr()
-        aligned = (base + 255) & ~255
         self._stream = stream
+        self._noalloc = bool(noalloc)
         self.handle = ctypes.c_void_p()
-        _check(lib.tt_transport_create(ctypes.byref(self._ps.s), ctypes.c_void_p(aligned),
-                                       self.nbytes + 256 - (aligned - base), self._sp(),
-                                       ctypes.byref(self.handle)))
+        if noalloc:
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                _check(lib.tt_transport_create_noalloc(ctypes.byref(self._ps.s), self._sp(), ctypes.byref(self.handle)))
+        else:
+            if workspace is None:
+                workspace = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+            self.workspace = workspace
+            base = workspace.data_ptr()
+            aligned = (base + 255) & ~255
+            _check(lib.tt_transport_create(ctypes.byref(self._ps.s), ctypes.c_void_p(aligned),
+                                           self.nbytes + 256 - (aligned - base), self._sp(),
+                                           ctypes.byref(self.handle)))
         self.M = prob.n_x * (len(prob.edges) - 1)
         self.n_theta = len(prob.mu)
         self.n_phi = len(prob.w_phi)
@@ -353,6 +363,11 @@ class Solver:
 
     def destroy(self):
         if self.handle:
+            if getattr(self, "_noalloc", False):
+                # the static workspace is shared by the next handle on this device:
+                # let this handle's work finish first
+                import torch
+                torch.cuda.synchronize(self.device)
             lib.tt_transport_destroy(self.handle)
             self.handle = ctypes.c_void_p()
 

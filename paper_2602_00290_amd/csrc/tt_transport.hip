@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -425,6 +426,7 @@ tt_status make_plan(const tt_problem* p, Plan& P) {
 
 struct tt_handle {
     Plan P;
+    int noalloc_dev = -1;             // device whose static workspace this handle holds (-1: caller's workspace)
     Geom geom{};
     int precision = 0, round_method = 0, step_order = 0;
     int rand_p = 4;                   // randomized rounding: sketch ranks = ranks + rand_p
@@ -1319,6 +1321,43 @@ int delta_rank_host(const std::vector<double>& s, double delta) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Static workspace for tt_transport_create_noalloc
+// ---------------------------------------------------------------------------
+//
+// A file-scope device array: every GPU the library runs on holds its own copy
+// from module load until the process ends.  Host code never passes its name
+// to a kernel or a copy (in host code the name is a host-side stand-in):
+// each device's address is taken once, with that device current, by
+// hipGetSymbolAddress and kept here.  One handle at a time may hold a
+// device's array; the array keeps the last handle's contents, and create
+// initialises every part of the workspace a solve reads.
+namespace {
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+tt_handle* g_scratch_owner[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+// Address of the current device's static workspace (taken on the first call
+// on that device).  Call with g_scratch_mu held.
+tt_status scratch_address(int dev, void** out) {
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(TT_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return TT_OK;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -1543,6 +1582,32 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
     }
     if ((u = reset_impl(h, s)) != TT_OK) { delete h; return u; }
     *out = h;
+    return TT_OK;
+}
+
+tt_status tt_transport_create_noalloc(const tt_problem* p, void* stream, tt_handle** out) {
+    if (!out) return fail(TT_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    Plan P;
+    tt_status r = make_plan(p, P);
+    if (r != TT_OK) return r;
+    if (P.bytes > kNoAllocBytes)
+        return fail(TT_ERR_INVALID_ARG, "the problem needs " + std::to_string(P.bytes) +
+                                            " bytes of workspace, above the static workspace of " +
+                                            std::to_string(kNoAllocBytes) + " bytes: use tt_transport_create");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(TT_ERR_INVALID_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_owner[dev])
+        return fail(TT_ERR_STATE, "the static workspace of this device is held by another handle: destroy it first");
+    void* ws = nullptr;
+    r = scratch_address(dev, &ws);
+    if (r != TT_OK) return r;
+    r = tt_transport_create(p, ws, kNoAllocBytes, stream, out);
+    if (r != TT_OK) return r;
+    (*out)->noalloc_dev = dev;
+    g_scratch_owner[dev] = *out;
     return TT_OK;
 }
 
@@ -1848,6 +1913,10 @@ tt_status tt_transport_solve_batch(tt_handle** hs, int n, int n_steps, void** st
 
 tt_status tt_transport_destroy(tt_handle* h) {
     if (!h) return TT_OK;
+    if (h->noalloc_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (g_scratch_owner[h->noalloc_dev] == h) g_scratch_owner[h->noalloc_dev] = nullptr;
+    }
     for (auto& pr : h->ev_pool) {
         (void)hipEventDestroy(pr.first);
         (void)hipEventDestroy(pr.second);
