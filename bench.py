@@ -1,32 +1,40 @@
 """Benchmark: TT multigroup transport solves on one MI355X.
 
-Workload (the 2D configuration): 128 x 128 cells on [0,1]^2, 32 groups with
-log-spaced edges on [0.01, 10], 8 polar x 8 azimuthal product quadrature,
-seeded lognormal kappa0 (sigma 1, correlation length 0.1), kappa_g = kappa0 nu_g^-3,
-medium T = 0.1, Planck T = 1 inflow on x = 0; FP32 contractions with FP64
-Gram / SVD / truncation, rank cap 32, tol 1e-6; one solve = 512 steps (t = L/c
-at CFL 0.5) from the rank-1 Planck state.  A benchmark step is one full solve
-of a batch of B independent requests of this workload (seeds 0..B-1)
-advanced together on B streams.
+Headline workload (the 3D configuration, the largest that fits one GPU):
+64^3 cells on [0,1]^3, 64 groups with log-spaced edges on [0.01, 10], 8
+polar x 16 azimuthal product quadrature, seeded lognormal kappa0 (sigma 1,
+correlation length 0.1) with two dense spherical clumps (x100), kappa_g =
+kappa0 nu_g^-3, medium T = 0.1, Planck T = 1 inflow on x = 0, rank cap 64,
+tol 1e-5; a solve is 384 steps (t = L/c at CFL 0.5).  The headline runs it
+with an FP64 state, FP64 contractions on FP64 MFMA and FP64 Gram rounding.
+One benchmark step is one time step of that solve (the whole apply + round
+path over the 16.8M-row first core).  Untimed steps first bring the ranks to
+the cap (the solve's steady state, R1 = 450 and k1 = 128), then --warmup
+untimed steps, then --steps timed steps; `value` = 1 / (384 x time per step)
+= TT solves/s with the state resident in HBM.
 
-Prints one JSON line.  `value` = aggregate solves/s of the batch with inputs
-resident on the device.  A second timed phase runs one solve alone with
-HIP-event timing of every kernel class on the library's stream; `roofline`
-reports the kernel that bounds the batched throughput (the fused projection +
-FP64 Gram contraction) from it, and `traffic` its HBM bytes per launch from the
-committed counter summary (null when the kernel source has changed since).
-`cpu_baseline` times the dense FP64 CPU oracle on this host for a bounded
-sample of the same workload.
+Beside it: the same workload in split BF16 and FP32 (with their relative L2
+difference from the FP64 state after the same steps) and with Householder QR
+rounding in FP64; the 2D configuration (128^2 x 32 groups x 8 x 8 angles) as
+16 batched FP32 solves, one FP32 solve and one FP64 solve (Gram and QR
+rounding), each compared with the dense FP64 oracle march; the 1D slab as
+256 batched solves; the served request mix (p50 / p99 latency, also the
+top-level p50_ms / p99_ms); and `cpu_baseline`, the dense FP64 CPU oracle
+timed on z-slabs of the same 64^3 cube and scaled to the whole cube.
+
+Prints one JSON line.  `roofline` covers the dominant kernel, the FP64 MFMA
+gather projection of the 3D headline, from its HIP-event times; `traffic` its
+HBM bytes per launch from the committed counter summary (null when the kernel
+source has changed since).
 
 Other modes (for profiling runs; they print one line and exit):
-  --mode probe        one solve of `--probe-workload` (plane2d, clumps3d, plane2d_coupled, plane2d_rusanov_scatter,
-                      plane2d_randomized)
-                      for `--probe-steps` steps
-  --mode c3           the 64^3 clump workload at steady state: ranks at the cap, then `--steps` timed steps
+  --mode probe        one solve of `--probe-workload` for `--probe-steps` steps (clumps3d_fp64 first
+                      brings the ranks to the cap)
+  --mode c3           the 64^3 clump workload in split BF16 at steady state, `--steps` timed steps
   --mode c5-slab      one GPU's z-slab of the 256^3 spike workload (cap 18), `--steps` timed steps
   --mode copy         a plain device-to-device copy of `--copy-mb` MiB (counter calibration)
   --mode served       only the served request mix (capacity, then Poisson arrivals)
-  --mode pmc-summary  turn rocprofv3 counter CSVs (--pmc-dir) into profiles/traffic_plane2d.json
+  --mode pmc-summary  turn rocprofv3 counter CSVs (--pmc-dir) into profiles/traffic_<workload>.json
 """
 from __future__ import annotations
 
@@ -48,10 +56,12 @@ PEAKS = {  # MI355X published dense peaks, TFLOP/s
 HBM_PEAK_GBS = 8000.0
 
 METRIC = "TT solves/s & TT apply+round GFLOP/s (% MFMA peak); p50/p99 solve latency"
-FUSED_KERNEL = "k_fused_f32<4, true>"
-KERNEL_SOURCES = ["paper_2602_00290_amd/csrc/k_fused.hpp", "paper_2602_00290_amd/csrc/k_mfma.hpp",
+C3_STEPS_PER_SOLVE = 384
+# the dominant kernel of the headline (FP64 gather projection, 128 columns)
+HEAD_KERNEL = "k_mm_f64<0, 8, false, 1>"
+KERNEL_SOURCES = ["paper_2602_00290_amd/csrc/k_f64.hpp", "paper_2602_00290_amd/csrc/k_fused.hpp",
                   "paper_2602_00290_amd/csrc/tt_common.hpp"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plane2d.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_clumps3d_fp64.json")
 
 
 def kernel_source_hash() -> str:
@@ -62,40 +72,46 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(prob, budget_s: float = 12.0):
-    """Dense FP64 oracle march on the host cores for a bounded number of steps
-    of the same workload, scaled to solves/s."""
+def host_cores() -> int:
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_baseline_c3(budget_s: float = 15.0, nz: int = 4):
+    """Dense FP64 oracle march (C/OpenMP) of z-slabs of the 64^3 clump cube on
+    all host cores: steps of one 64 x 64 x nz slab (the cube's field and cell
+    spacing) until about budget_s has passed, scaled by 64 / nz to the whole
+    cube and by 384 steps to a solve."""
+    import tt_inputs as ti
     from oracle import dense
+    prob = ti.clumps3d_slab(nz=nz, precision=ti.PREC_FP64)
+    cores = host_cores()
     I = dense.initial_dense(prob)
-    cores = len(os.sched_getaffinity(0))
-    nthr = min(cores, 16)
-    dense.march(prob, I, 1, n_threads=nthr)     # warm (page-in, thread pool)
+    I = dense.march(prob, I, 1, n_threads=cores)     # warm (page-in, thread pool)
     steps = 0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s and steps < prob.n_steps:
-        I = dense.march(prob, I, 4, n_threads=nthr)
-        steps += 4
-    dt = time.perf_counter() - t0
-    per_step = dt / steps
-    # the same march on one host core, over a few steps
-    t1 = time.perf_counter()
-    dense.march(prob, I, 4, n_threads=1)
-    one = (time.perf_counter() - t1) / 4
+    while time.perf_counter() - t0 < budget_s and steps < 64:
+        I = dense.march(prob, I, 2, n_threads=cores)
+        steps += 2
+    per_slab_step = (time.perf_counter() - t0) / steps
+    scale = 64 // nz
+    per_step = per_slab_step * scale
+    del I
     return {
-        "value": 1.0 / (per_step * prob.n_steps),
+        "value": 1.0 / (per_step * C3_STEPS_PER_SOLVE),
         "unit": "solves/s",
-        "cores": nthr,
-        "one_core": {"ms_per_step": one * 1e3, "solves_per_s": 1.0 / (one * prob.n_steps),
-                     "dof_updates_per_s": prob.dense_entries / one, "sample": "4 steps, 1 thread"},
+        "cores": cores,
+        "threads": cores,
         "kind": "oracle",
-        "sample": f"dense FP64 upwind march (C/OpenMP), {steps} of {prob.n_steps} steps of the same workload "
-                  f"({prob.dense_entries} entries), {per_step * 1e3:.1f} ms/step, "
-                  f"{prob.dense_entries / per_step:.3e} DOF-updates/s",
+        "sample": f"dense FP64 upwind march (C/OpenMP) of a 64 x 64 x {nz}-cell z-slab of the 64^3 cube "
+                  f"(64 groups, 8 x 16 directions, {prob.dense_entries} entries), {steps} steps at "
+                  f"{per_slab_step * 1e3:.1f} ms each, scaled x{scale} to the cube ({per_step:.2f} s/step) and "
+                  f"x{C3_STEPS_PER_SOLVE} steps to a solve",
+        "dof_updates_per_s": prob.dense_entries / per_slab_step,
     }
 
 
 def stored_traffic():
-    """HBM bytes per launch of the fused kernel from the committed counter
+    """HBM bytes per launch of the dominant kernel from the committed counter
     summary, or None if it is missing or was taken on different kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
@@ -107,57 +123,133 @@ def stored_traffic():
     return t
 
 
-def tt_rel_diff(x, y):
-    """||X - Y|| / ||X|| of two TTs (Z, Theta, Phi) from TT inner products (no
-    full tensor): <X, Y> = sum Phi_x Phi_y^T o (Theta_x^T (Z_x^T Z_y) Theta_y)."""
+def tt_diff_norm(x, y):
+    """||X - Y||_F and ||Y||_F of two TTs (Z, Theta, Phi) without the full
+    tensor: the difference is the TT with Z = [Z_x, Z_y], Theta block-diagonal
+    and Phi = [Phi_x; -Phi_y]; its norm is that of R x (Theta, Phi) with R the
+    triangular factor of the stacked first core, taken by row chunks (a
+    Householder R of the chunk R's), so no cancellation limits it."""
     import numpy as np
 
-    def inner(a, b):
-        Za, Ta, Pa = a
-        Zb, Tb, Pb = b
-        A = Za.T @ Zb                                        # r1a x r1b
-        Bm = np.einsum("ij,ilp,jlq->pq", A, Ta, Tb)          # r2a x r2b
-        return float(np.sum(Bm * (Pa @ Pb.T)))
-    xx, yy, xy = inner(x, x), inner(y, y), inner(x, y)
-    return float(np.sqrt(max(xx + yy - 2.0 * xy, 0.0) / xx))
+    def first_core_r(Zs):
+        Rs = []
+        M = Zs[0].shape[0]
+        for k0 in range(0, M, 1 << 20):
+            C = np.hstack([Z[k0:k0 + (1 << 20)] for Z in Zs])
+            Rs.append(np.linalg.qr(C, mode="r"))
+        return np.linalg.qr(np.vstack(Rs), mode="r")
+
+    def norm_of(R, Th, Ph):
+        T = np.einsum("ia,alb->ilb", R, Th)
+        return float(np.linalg.norm(np.einsum("ilb,bp->ilp", T, Ph)))
+
+    Zx, Tx, Px = x
+    Zy, Ty, Py = y
+    r1x, nt, r2x = Tx.shape
+    r1y, _, r2y = Ty.shape
+    Th = np.zeros((r1x + r1y, nt, r2x + r2y))
+    Th[:r1x, :, :r2x] = Tx
+    Th[r1x:, :, r2x:] = Ty
+    Ph = np.vstack([Px, -Py])
+    dn = norm_of(first_core_r([Zx, Zy]), Th, Ph)
+    yn = norm_of(first_core_r([Zy]), Ty, Py)
+    return dn, yn
 
 
-def roofline(st1):
-    """Roofline of the fused projection + FP64 Gram kernel from the single-solve
-    event timing.  Its flops are FP32 MFMA (projection, 2 M R1 k1 per launch)
-    plus FP64 MFMA (symmetric Gram, M k1 (k1 + 1)); the peak is the rate of
-    that mix at the published dense peaks: (F32 + F64) / (F32 / P32 + F64 / P64)."""
-    ms, n, fl = st1["kernel_ms"], st1["kernel_launches"], st1["flops"]
+def tt_rel_diff(x, y):
+    """||X - Y|| / ||Y|| of two TTs (see tt_diff_norm)."""
+    dn, yn = tt_diff_norm(x, y)
+    return dn / yn if yn > 0 else dn
+
+
+def roofline_c3(st, M):
+    """Roofline of the dominant kernel (the FP64 MFMA gather projection of the
+    3D headline) from its HIP-event times over the timed steps.  `achieved`
+    counts the first rounding pass as the method defines it, the R factor of
+    the explicit M x R1 sum: 2 M R1^2 - 2/3 R1^3 flops per launch with R1 the
+    sum's rank (450 at the cap); `executed` counts what the kernel runs, the
+    projection onto the k1-column angular row space, 2 M R1 k1."""
+    ms, n, fl = st["kernel_ms"], st["kernel_launches"], st["flops"]
     if not n["project"] or not ms["project"]:
         return None
-    f32, f64 = fl["project"], (fl["factor"] if n["factor"] == 0 else 0.0)
-    sec = ms["project"] * 1e-3
-    achieved = (f32 + f64) / sec / 1e12
-    peak = (f32 + f64) / (f32 / PEAKS["fp32"] + f64 / PEAKS["fp64"]) if (f32 + f64) > 0 else PEAKS["fp32"]
+    R1 = st["max_R1"]
+    t_launch = ms["project"] / n["project"] * 1e-3
+    alg = 2.0 * M * R1 * R1 - 2.0 / 3.0 * R1 ** 3
+    exe = fl["project"] / n["project"]
+    peak = PEAKS["fp64"]
     t = stored_traffic()
-    out = {"bound": "mfma", "kernel": FUSED_KERNEL, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-           "frac": achieved / peak, "traffic": (t["fetch_bytes"] + t["write_bytes"]) if t else None,
-           "avg_launch_ms": ms["project"] / n["project"], "launches": n["project"],
-           "flops_per_launch": {"fp32": f32 / n["project"], "fp64": f64 / n["project"]}}
+    out = {"bound": "mfma", "kernel": HEAD_KERNEL, "achieved": alg / t_launch / 1e12, "peak": peak,
+           "unit": "TFLOP/s", "frac": alg / t_launch / 1e12 / peak,
+           "traffic": (t["fetch_bytes"] + t["write_bytes"]) if t else None,
+           "avg_launch_ms": t_launch * 1e3, "launches": n["project"],
+           "algorithmic_flops_per_launch": alg, "R1": R1,
+           "executed": {"flops_per_launch": exe, "TFLOP_per_s": exe / t_launch / 1e12,
+                        "frac": exe / t_launch / 1e12 / peak}}
     if t:
         out["traffic_detail"] = {k: t[k] for k in ("fetch_bytes", "write_bytes", "algorithmic_bytes")}
     return out
 
 
-def kernel_hbm(st1, M):
-    """Achieved algorithmic HBM rate of the two first-core kernels from the
-    single-solve event timing, with the minimum bytes of each launch at the
-    final ranks: the projection reads the state Z (M r1 FP32 values), the
-    output kernel reads Z and writes Z_out (2 M r1 values)."""
-    ms, n = st1["kernel_ms"], st1["kernel_launches"]
-    r1 = st1["r1"]
-    out = {}
-    for cls, words in (("project", 1), ("output", 2)):
-        if n[cls] and ms[cls]:
-            t = ms[cls] / n[cls] * 1e-3
-            out[cls] = {"GB_per_s": words * M * r1 * 4 / t / 1e9, "bytes_per_launch": words * M * r1 * 4,
-                        "avg_launch_us": t * 1e6}
-    return out
+def c3_run(prob, method, rank_warm, args, label, keep_cores=True, timing_steps=4):
+    """The 3D workload from its initial state: rank_warm untimed steps (or,
+    when None, until the ranks reach the cap), args.warmup untimed steps,
+    args.steps timed steps (no events), then timing_steps more with HIP-event
+    timing of every kernel class.  Returns the measurements and the cores."""
+    import torch
+    import paper_2602_00290_amd as tt
+    s = tt.Solver(prob, round_method=method)
+    warm = 0
+    if rank_warm is None:
+        while warm < 48:
+            st = s.solve(1)
+            warm += 1
+            if st["r1"] >= prob.rank_cap and warm >= 24:
+                break
+    else:
+        s.solve(rank_warm)
+        warm = rank_warm
+    if args.warmup > 0:
+        s.solve(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.solve_async(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s.set_timing(True)
+    stt = s.solve(timing_steps)
+    s.set_timing(False)
+    n = stt["kernel_launches"]
+    out = {"label": label, "ms_per_step": el / args.steps * 1e3, "rank_warmup_steps": warm,
+           "ranks": [stt["r1"], stt["r2"]], "max_R": [stt["max_R1"], stt["max_R2"]],
+           "compression": stt["compression"],
+           "kernel_ms_per_step": {c: stt["kernel_ms"][c] / timing_steps for c in tt.KERNEL_CLASSES if n[c]},
+           "flops_per_step": sum(stt["flops"].values()) / timing_steps,
+           "workspace_gb": s.nbytes / 2 ** 30}
+    print(json.dumps({"phase": label, "ms_per_step": out["ms_per_step"], "ranks": out["ranks"]}),
+          file=sys.stderr, flush=True)
+    cores = s.get_cores() if keep_cores else None
+    s.destroy()
+    return out, stt, cores
+
+
+def c3_phase(args):
+    """The headline (FP64) and the other precisions and rounding beside it."""
+    import tt_inputs as ti
+    import paper_2602_00290_amd as tt
+    p64 = ti.clumps3d(precision=ti.PREC_FP64)
+    head, st64, cores64 = c3_run(p64, tt.TT_ROUND_GRAM, None, args, "clumps3d fp64 gram")
+    warm = head["rank_warmup_steps"]
+    beside = {}
+    if args.c3_beside:
+        for name, prob, method in (("bf16x", ti.clumps3d(precision=ti.PREC_BF16X), tt.TT_ROUND_AUTO),
+                                   ("fp32", ti.clumps3d(precision=ti.PREC_FP32), tt.TT_ROUND_AUTO),
+                                   ("fp64_qr", p64, tt.TT_ROUND_QR)):
+            r, _, cores = c3_run(prob, method, warm, args, "clumps3d " + name)
+            r["rel_l2_vs_fp64_gram"] = tt_rel_diff(cores, cores64)
+            r["solves_per_s"] = 1e3 / (C3_STEPS_PER_SOLVE * r["ms_per_step"])
+            beside[name] = r
+            del cores
+    return head, st64, beside, p64
 
 
 def served_phase(args):
@@ -208,6 +300,21 @@ def mode_probe(args):
     import torch
     import paper_2602_00290_amd as tt
     import tt_inputs as ti
+    if args.probe_workload == "clumps3d_fp64":
+        # the headline: ranks brought to the cap, then --probe-steps steps
+        prob = ti.clumps3d(precision=ti.PREC_FP64)
+        s = tt.Solver(prob, round_method=tt.TT_ROUND_GRAM)
+        warm = 0
+        while warm < 48:
+            st = s.solve(1)
+            warm += 1
+            if st["r1"] >= prob.rank_cap and warm >= 24:
+                break
+        st = s.solve(args.probe_steps)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "probe", "workload": args.probe_workload, "rank_warmup_steps": warm,
+                          "steps": args.probe_steps, "ranks": [st["r1"], st["r2"]]}), flush=True)
+        return
     if args.probe_workload == "clumps3d":
         prob = ti.clumps3d(precision=ti.PREC_BF16X)
     elif args.probe_workload == "plane2d_coupled":
@@ -293,10 +400,12 @@ def _pmc_rows(path, counter):
 
 
 def mode_pmc_summary(args):
-    """profiles/traffic_plane2d.json from four counter runs under --pmc-dir:
-    fetch/ and write/ (FETCH_SIZE, WRITE_SIZE of `--mode probe`), copy_fetch/ and
-    copy_write/ (the same counters of `--mode copy`).  Counter values are KiB per
-    dispatch; each is scaled by copy bytes / counter of the copy kernel."""
+    """profiles/traffic_clumps3d_fp64.json from four counter runs under
+    --pmc-dir: fetch/ and write/ (FETCH_SIZE, WRITE_SIZE of `--mode probe
+    --probe-workload clumps3d_fp64`), copy_fetch/ and copy_write/ (the same
+    counters of `--mode copy`).  Counter values are KiB per dispatch; each is
+    scaled by copy bytes / counter of the copy kernel.  The dominant kernel's
+    dispatches of the last --probe-steps steps (ranks at the cap) are averaged."""
     d = args.pmc_dir
     nbytes = args.copy_mb * (1 << 20)
 
@@ -305,29 +414,32 @@ def mode_pmc_summary(args):
         vals = sorted(v for _, _, v in rows)[-4:]          # the large copies
         return nbytes / (sum(vals) / len(vals) * 1024.0)
 
-    def fused(sub, counter):
-        key = FUSED_KERNEL.replace(" ", "")
+    def kernel(sub, counter):
+        key = HEAD_KERNEL.replace(" ", "")
         rows = [v for _, k, v in _pmc_rows(os.path.join(d, sub), counter) if key in k.replace(" ", "")]
-        steady = rows[len(rows) // 2:]                      # second half: ranks at their steady values
+        steady = rows[-args.probe_steps:]
         return sum(steady) / len(steady) * 1024.0, len(steady)
 
     ff, fw = copy_factor("copy_fetch", "FETCH_SIZE"), copy_factor("copy_write", "WRITE_SIZE")
-    fetch, nf = fused("fetch", "FETCH_SIZE")
-    write, nw = fused("write", "WRITE_SIZE")
+    fetch, nf = kernel("fetch", "FETCH_SIZE")
+    write, nw = kernel("write", "WRITE_SIZE")
     import tt_inputs as ti
-    p = ti.plane2d()
+    p = ti.clumps3d(precision=ti.PREC_FP64)
     out = {
-        "kernel": FUSED_KERNEL,
-        "workload": "plane2d steady state (second half of a 64-step probe)",
+        "kernel": HEAD_KERNEL,
+        "workload": "clumps3d 64^3 FP64 at the rank cap (R1 = 450, k1 = 128, r1 = 64), last "
+                    f"{args.probe_steps} steps of a probe",
         "source_hash": kernel_source_hash(),
         "fetch_bytes": fetch * ff,
         "write_bytes": write * fw,
         "raw_fetch_bytes": fetch, "raw_write_bytes": write, "dispatches": [nf, nw],
         "calibration": {"copy_bytes": nbytes, "fetch_factor": ff, "write_factor": fw},
-        # Z read once (ld 24 floats) + row table (8 B) + neighbour table (4 ints) + rank-1
-        # block (4 floats) per row, + the Gram partials written
-        "algorithmic_bytes": p.M * (24 * 4 + 8 + 16 + 16) + 256 * 10 * 256 * 8,
+        # the method's minimum for this pass: read the state Z once (M x r1 FP64);
+        # this design also writes the projected core B (M x k1 FP64)
+        "algorithmic_bytes": p.M * 64 * 8,
+        "design_bytes": p.M * (64 + 128) * 8,
         "commands": [f"rocprofv3 --pmc {c} --output-format csv -d <dir>/{s} -o {s} -- python3 bench.py --mode {m}"
+                     + (f" --probe-workload clumps3d_fp64 --probe-steps {args.probe_steps}" if m == "probe" else "")
                      for c, s, m in (("FETCH_SIZE", "fetch", "probe"), ("WRITE_SIZE", "write", "probe"),
                                      ("FETCH_SIZE", "copy_fetch", "copy"), ("WRITE_SIZE", "copy_write", "copy"))],
     }
@@ -336,38 +448,240 @@ def mode_pmc_summary(args):
     print(json.dumps({"mode": "pmc-summary", **{k: out[k] for k in ("fetch_bytes", "write_bytes")}}), flush=True)
 
 
+def plane2d_phase(args, dev):
+    """The 2D configuration: B batched FP32 solves (seeds 0..B-1) on B streams;
+    seed 0 alone in FP32 (with and without per-kernel HIP events), in FP64 with
+    Gram rounding on FP64 MFMA and in FP64 with Householder QR (the plain TT-SVD
+    path); each result of seed 0 against the dense FP64 oracle march."""
+    import numpy as np
+    import torch
+    import paper_2602_00290_amd as tt
+    import tt_inputs as ti
+    from oracle import dense
+
+    prob = ti.plane2d()
+    K = prob.n_steps
+    B = max(1, args.batch)
+    probs = [prob] + [ti.plane2d(seed=b) for b in range(1, B)]
+    solvers = [tt.Solver(p, device=dev) for p in probs]
+    streams = [torch.cuda.Stream(device=dev) for _ in range(min(B, args.streams))]
+    for sv in solvers:
+        sv.reset()
+    tt.solve_batch(solvers, K, streams)                 # warm-up batch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.c2_batches):
+        for sv in solvers:
+            sv.reset()
+        stats = tt.solve_batch(solvers, K, streams)
+    torch.cuda.synchronize()
+    batched = B * args.c2_batches / (time.perf_counter() - t0)
+    last = stats[0]
+    batch_flops = sum(sum(st["flops"].values()) for st in stats)
+    for sv in solvers[1:]:
+        sv.destroy()
+    single = solvers[0]
+
+    def alone(sv, timing):
+        sv.reset()
+        sv.set_timing(timing)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = sv.solve(K)
+        el = time.perf_counter() - t
+        sv.set_timing(False)
+        return st, el
+
+    st1, single_s = alone(single, False)
+    st1t, _ = alone(single, True)
+    ms1, n1 = st1t["kernel_ms"], st1t["kernel_launches"]
+    cores32 = single.get_cores()
+    internal = {}
+    for delta in (1e-3, 1e-6):
+        t4 = time.perf_counter()
+        ir = single.internal_ranks(delta)
+        internal[f"{delta:g}"] = {"r_nux": ir["r_nux"], "r_xnu": ir["r_xnu"], "C_rel_nu": ir["C_rel_nu"],
+                                  "C_rel_x": ir["C_rel_x"], "ms": (time.perf_counter() - t4) * 1e3}
+    p64 = prob.copy(precision=ti.PREC_FP64)
+    runs = {}
+    for name, method in (("fp64_gram", tt.TT_ROUND_GRAM), ("fp64_qr", tt.TT_ROUND_QR)):
+        sv = tt.Solver(p64, device=dev, round_method=method)
+        sv.solve(2)
+        st, el = alone(sv, False)
+        stt, _ = alone(sv, True)
+        runs[name] = {"solves_per_s": 1.0 / el, "ms": el * 1e3, "ranks": [st["r1"], st["r2"]],
+                      "kernel_us_per_step": {c: stt["kernel_ms"][c] / K * 1e3 for c in tt.KERNEL_CLASSES
+                                             if stt["kernel_launches"][c]},
+                      "cores": sv.get_cores()}
+        sv.destroy()
+    # the dense FP64 oracle march of seed 0 (same discretisation, no rounding)
+    t5 = time.perf_counter()
+    ref = dense.march(prob, dense.initial_dense(prob), K, n_threads=host_cores())
+    oracle_s = time.perf_counter() - t5
+
+    def err(c):
+        X = np.einsum("ka,alb,bp->klp", *c, optimize=True)
+        return float(np.linalg.norm(X - ref) / np.linalg.norm(ref))
+
+    e32 = err(cores32)
+    out = {
+        "workload": "plane2d: 128x128 cells, 32 groups [0.01,10], 8x8 angles, lognormal kappa0 (sigma 1, l 0.1), "
+                    "rank cap 32, tol 1e-6, 512 steps per solve",
+        "batched_fp32": {"solves_per_s": batched, "batch": B, "streams": len(streams), "seeds": f"0..{B - 1}",
+                         "batches_timed": args.c2_batches,
+                         "gflops": batch_flops * args.c2_batches / (B * args.c2_batches / batched) / 1e9,
+                         "ranks": [last["r1"], last["r2"]], "max_R": [last["max_R1"], last["max_R2"]],
+                         "compression": last["compression"]},
+        "single_fp32": {"solves_per_s": 1.0 / single_s, "ms": single_s * 1e3, "rel_l2_vs_dense_oracle": e32,
+                        "kernel_us_per_launch": {c: ms1[c] / n1[c] * 1e3 for c in tt.KERNEL_CLASSES if n1[c]}},
+        "dense_oracle": {"seconds": oracle_s, "threads": host_cores(), "steps": K},
+        "internal_ranks": internal,
+    }
+    for name, r in runs.items():
+        r["rel_l2_vs_dense_oracle"] = err(r.pop("cores"))
+        out[name] = r
+    # equal accuracy: both meet the same relative L2 bound against the oracle
+    bound = max(e32, runs["fp64_qr"]["rel_l2_vs_dense_oracle"]) * 1.01
+    out["equal_accuracy_bound"] = bound
+    out["speedup_batched_fp32_vs_fp64_qr"] = batched / runs["fp64_qr"]["solves_per_s"]
+    out["speedup_batched_fp32_vs_fp64_gram"] = batched / runs["fp64_gram"]["solves_per_s"]
+    return out, single
+
+
+def c1_phase(args, dev):
+    """The 1D slab (FP64, cap 8, 128 steps): many independent solves as one batch."""
+    import torch
+    import paper_2602_00290_amd as tt
+    import tt_inputs as ti
+    p1 = ti.slab1d()
+    c1s = [tt.Solver(p1, device=dev) for _ in range(args.c1_batch)]
+    c1st = [torch.cuda.Stream(device=dev) for _ in range(min(args.c1_batch, args.streams))]
+    for sv in c1s:
+        sv.reset()
+    tt.solve_batch(c1s, p1.n_steps, c1st)        # warm-up
+    torch.cuda.synchronize()
+    t6 = time.perf_counter()
+    for sv in c1s:
+        sv.reset()
+    c1stats = tt.solve_batch(c1s, p1.n_steps, c1st)
+    torch.cuda.synchronize()
+    c1_s = time.perf_counter() - t6
+    one = c1s[0]
+    one.reset()
+    torch.cuda.synchronize()
+    t7 = time.perf_counter()
+    one.solve(p1.n_steps)
+    c1_one = time.perf_counter() - t7
+    for sv in c1s:
+        sv.destroy()
+    return {"workload": "slab1d: 64 cells, 8 groups [0.01,10], 16 GL mu, FP64, cap 8, tol 1e-8, 128 steps",
+            "batch": args.c1_batch, "streams": len(c1st), "solves_per_s": args.c1_batch / c1_s,
+            "single_solve_ms": c1_one * 1e3, "ranks": [c1stats[0]["r1"], c1stats[0]["r2"]]}
+
+
+def extras_phase(args, dev, single):
+    """Seed 0 of the 2D workload with the coupled medium temperature, with the
+    Rusanov flux and scattering, and with randomized rounding."""
+    import torch
+    import paper_2602_00290_amd as tt
+    import tt_inputs as ti
+    prob = ti.plane2d()
+    K = prob.n_steps
+    out = {}
+    if args.coupled:
+        pc = prob.copy(heat_capacity=8.0 * ti.radiation_constant(prob.c))
+        sc = tt.Solver(pc, device=dev)
+        sc.set_timing(True)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        stc = sc.solve(K)
+        coupled_s = time.perf_counter() - t3
+        Tc = sc.get_temperature()
+        nc = stc["kernel_launches"]["couple"]
+        out["coupled_temperature"] = {
+            "solves_per_s": 1.0 / coupled_s, "ms": coupled_s * 1e3, "timing": "HIP events on",
+            "heat_capacity": "8 a (a = 8 pi^5 / (15 c))", "ranks": [stc["r1"], stc["r2"]],
+            "couple_us_per_launch": stc["kernel_ms"]["couple"] / max(1, nc) * 1e3, "couple_launches": nc,
+            "T_mean": float(Tc.mean()), "T_max": float(Tc.max()),
+            "energy_total": stc["energy"] / pc.c + stc["medium_energy"]}
+        sc.destroy()
+    if args.rusanov_scatter:
+        pr = rusanov_scatter_problem(ti)
+        sr = tt.Solver(pr, device=dev)
+        sr.set_timing(True)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        str_ = sr.solve(K)
+        rus_s = time.perf_counter() - t5
+        nr = str_["kernel_launches"]["couple"]
+        out["rusanov_scattering"] = {
+            "solves_per_s": 1.0 / rus_s, "ms": rus_s * 1e3, "timing": "HIP events on",
+            "flux": "Rusanov, S+ = c", "scattering": "kappa_s = kappa_a", "ranks": [str_["r1"], str_["r2"]],
+            "max_R": [str_["max_R1"], str_["max_R2"]],
+            "prepass_us_per_launch": str_["kernel_ms"]["couple"] / max(1, nr) * 1e3,
+            "kernel_us_per_launch": {c: str_["kernel_ms"][c] / str_["kernel_launches"][c] * 1e3
+                                     for c in tt.KERNEL_CLASSES if str_["kernel_launches"][c]}}
+        sr.destroy()
+    if args.randomized:
+        prr = prob.copy(round_method=ti.ROUND_RAND, rand_oversample=4, rand_seed=0)
+        srr = tt.Solver(prr, device=dev)
+        srr.solve(2)
+        srr.reset()
+        torch.cuda.synchronize()
+        t8 = time.perf_counter()
+        strr = srr.solve(K)
+        rnd_s = time.perf_counter() - t8
+        single.reset()
+        single.solve(K)
+        diff = tt_rel_diff(srr.get_cores(), single.get_cores())
+        single.reset()
+        torch.cuda.synchronize()
+        t9 = time.perf_counter()
+        single.solve(K)
+        gram_s = time.perf_counter() - t9
+        out["randomized_rounding"] = {
+            "solves_per_s": 1.0 / rnd_s, "ms": rnd_s * 1e3, "gram_single_solve_ms": gram_s * 1e3,
+            "oversample": 4, "ranks": [strr["r1"], strr["r2"]],
+            "sketch_ranks_last": [strr["sketch_r1"], strr["sketch_r2"]], "rel_l2_vs_gram_solve": diff}
+        srr.destroy()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed steps of the 3D headline")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed steps after the ranks reach the cap")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--round-method", default="auto", choices=["qr", "gram", "auto"])
-    ap.add_argument("--timing", type=int, default=1, help="HIP-event timing of kernel classes")
-    ap.add_argument("--batch", type=int, default=16, help="independent solves advanced together")
-    ap.add_argument("--streams", type=int, default=16, help="HIP streams for the batch")
+    ap.add_argument("--batch", type=int, default=16, help="independent 2D solves advanced together")
+    ap.add_argument("--c2-batches", type=int, default=2, help="timed batches of the 2D workload")
+    ap.add_argument("--streams", type=int, default=16, help="HIP streams for the batches")
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="GPU_MAX_HW_QUEUES for this process (0: keep the environment's)")
     ap.add_argument("--mode", default="bench",
                     choices=["bench", "probe", "copy", "pmc-summary", "served", "c5-slab", "c3"])
+    ap.add_argument("--c3-beside", type=int, default=1,
+                    help="also run the 3D workload in split BF16, FP32 and FP64 with QR rounding")
     ap.add_argument("--c5-cap", type=int, default=18, help="rank cap of --mode c5-slab")
     ap.add_argument("--c5-warmup", type=int, default=40, help="at most this many untimed steps in --mode c5-slab")
     ap.add_argument("--probe-steps", type=int, default=64)
     ap.add_argument("--probe-workload", default="plane2d",
-                    choices=["plane2d", "clumps3d", "plane2d_coupled", "plane2d_rusanov_scatter", "plane2d_randomized"],
+                    choices=["plane2d", "clumps3d", "clumps3d_fp64", "plane2d_coupled", "plane2d_rusanov_scatter",
+                             "plane2d_randomized"],
                     help="probe workload: plane2d (FP32), clumps3d (64^3 cells, 64 groups, split BF16), "
+                         "clumps3d_fp64 (the headline: FP64, Gram rounding, ranks at the cap first), "
                          "plane2d_coupled (plane2d with the coupled medium temperature, heat capacity 8 a), "
                          "plane2d_rusanov_scatter (plane2d with the Rusanov flux and scattering kappa_s = kappa_a), "
                          "or plane2d_randomized (plane2d with randomized rounding, sketch ranks = ranks + 4)")
     ap.add_argument("--copy-mb", type=int, default=512)
     ap.add_argument("--pmc-dir", default=os.path.join(ROOT, "gpurun_out", "traffic"))
-    ap.add_argument("--plain-fp64", type=int, default=1, help="also time the plain FP64 TT path on seed 0")
     ap.add_argument("--coupled", type=int, default=1,
                     help="also time seed 0 with the coupled medium temperature (heat capacity 8 a)")
     ap.add_argument("--rusanov-scatter", type=int, default=1,
                     help="also time seed 0 with the Rusanov flux and isotropic scattering (kappa_s = kappa_a)")
     ap.add_argument("--randomized", type=int, default=1,
                     help="also time seed 0 with randomized rounding (sketch ranks = ranks + 4) beside Gram rounding")
+    ap.add_argument("--c2", type=int, default=1, help="run the 2D workload phase")
     ap.add_argument("--c1-batch", type=int, default=256,
                     help="also time this many independent 1D slab solves (FP64, 128 steps) as one batch")
     ap.add_argument("--served", type=int, default=256,
@@ -397,167 +711,13 @@ def main():
         print(json.dumps({"mode": "served", **served_phase(args)}), flush=True)
         return
 
-    import numpy as np
     import torch
-
-    import paper_2602_00290_amd as tt
-    import tt_inputs as ti
-
-    prob = ti.plane2d()
-    method = {"qr": tt.TT_ROUND_QR, "gram": tt.TT_ROUND_GRAM, "auto": tt.TT_ROUND_AUTO}[args.round_method]
     dev = torch.device("cuda:0")
-    K = prob.n_steps
-    B = max(1, args.batch)
 
-    # ---- phase 1: batched throughput (B independent solves, seeds 0..B-1) ----
-    probs = [prob] + [ti.plane2d(seed=b) for b in range(1, B)]
-    solvers = [tt.Solver(p, device=dev, round_method=method) for p in probs]
-    streams = [torch.cuda.Stream(device=dev) for _ in range(min(B, args.streams))]
-    for _ in range(args.warmup):
-        for sv in solvers:
-            sv.reset()
-        tt.solve_batch(solvers, K, streams)
-    torch.cuda.synchronize()
-    lat = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s0 = time.perf_counter()
-        for sv in solvers:
-            sv.reset()
-        stats = tt.solve_batch(solvers, K, streams)
-        lat.append(time.perf_counter() - s0)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    last = stats[0]
-    value = B * args.steps / elapsed
-    batch_flops = sum(sum(st["flops"].values()) for st in stats)   # flops of the last batch solve
-
-    # ---- phase 2: one solve alone, HIP-event timing of every kernel class ----
-    single = solvers[0]
-    single.reset()
-    single.set_timing(bool(args.timing))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st1 = single.solve(K)
-    single_s = time.perf_counter() - t1
-    single.set_timing(False)
-    agg_ms, agg_n, agg_fl = st1["kernel_ms"], st1["kernel_launches"], st1["flops"]
-    # internal delta-ranks of the final combined core (discussion of the internal structure of Z)
-    internal = {}
-    for delta in (1e-3, 1e-6):
-        t4 = time.perf_counter()
-        ir = single.internal_ranks(delta)
-        internal[f"{delta:g}"] = {"r_nux": ir["r_nux"], "r_xnu": ir["r_xnu"], "C_rel_nu": ir["C_rel_nu"],
-                                  "C_rel_x": ir["C_rel_x"], "ms": (time.perf_counter() - t4) * 1e3}
-
-    # ---- phase 3: the plain FP64 TT path (FP64 state, Householder TSQR) on seed 0 ----
-    plain = None
-    if args.plain_fp64:
-        sp = tt.Solver(prob.copy(precision=ti.PREC_FP64), device=dev, round_method=tt.TT_ROUND_QR)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        stp = sp.solve(K)
-        plain_s = time.perf_counter() - t2
-        a, b = single.get_cores(), sp.get_cores()
-        plain = {"solves_per_s": 1.0 / plain_s, "ms": plain_s * 1e3, "ranks": [stp["r1"], stp["r2"]],
-                 "rel_l2_mixed_vs_fp64": tt_rel_diff(a, b),
-                 "speedup_batched_mixed_vs_plain_fp64": value * plain_s}
-        sp.destroy()
-    # ---- phase 4: seed 0 with the coupled medium temperature (Section 2.1 coupled source stage) ----
-    coupled = None
-    if args.coupled:
-        pc = prob.copy(heat_capacity=8.0 * ti.radiation_constant(prob.c))
-        sc = tt.Solver(pc, device=dev, round_method=method)
-        sc.set_timing(True)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        stc = sc.solve(K)
-        coupled_s = time.perf_counter() - t3
-        Tc = sc.get_temperature()
-        nc = stc["kernel_launches"]["couple"]
-        coupled = {"solves_per_s": 1.0 / coupled_s, "ms": coupled_s * 1e3, "timing": "HIP events on",
-                   "heat_capacity": "8 a (a = 8 pi^5 / (15 c))", "ranks": [stc["r1"], stc["r2"]],
-                   "couple_us_per_launch": stc["kernel_ms"]["couple"] / max(1, nc) * 1e3,
-                   "couple_launches": nc, "T_mean": float(Tc.mean()), "T_max": float(Tc.max()),
-                   "energy_total": stc["energy"] / pc.c + stc["medium_energy"]}
-        sc.destroy()
-    # ---- phase 6: the 1D slab (FP64, cap 8, 128 steps), batched: latency-bound solves ----
-    c1 = None
-    if args.c1_batch > 0:
-        p1 = ti.slab1d()
-        c1s = [tt.Solver(p1, device=dev) for _ in range(args.c1_batch)]
-        c1st = [torch.cuda.Stream(device=dev) for _ in range(min(args.c1_batch, args.streams))]
-        for sv in c1s:
-            sv.reset()
-        tt.solve_batch(c1s, p1.n_steps, c1st)        # warm-up
-        torch.cuda.synchronize()
-        t6 = time.perf_counter()
-        for sv in c1s:
-            sv.reset()
-        c1stats = tt.solve_batch(c1s, p1.n_steps, c1st)
-        torch.cuda.synchronize()
-        c1_s = time.perf_counter() - t6
-        one = c1s[0]
-        one.reset()
-        torch.cuda.synchronize()
-        t7 = time.perf_counter()
-        one.solve(p1.n_steps)
-        c1_one = time.perf_counter() - t7
-        c1 = {"workload": "slab1d: 64 cells, 8 groups [0.01,10], 16 GL mu, FP64, cap 8, tol 1e-8, 128 steps",
-              "batch": args.c1_batch, "streams": len(c1st), "solves_per_s": args.c1_batch / c1_s,
-              "single_solve_ms": c1_one * 1e3, "ranks": [c1stats[0]["r1"], c1stats[0]["r2"]]}
-        for sv in c1s:
-            sv.destroy()
-    # ---- phase 5: seed 0 with the Rusanov flux and isotropic scattering ----
-    rus = None
-    if args.rusanov_scatter:
-        pr = rusanov_scatter_problem(ti)
-        sr = tt.Solver(pr, device=dev, round_method=method)
-        sr.set_timing(True)
-        torch.cuda.synchronize()
-        t5 = time.perf_counter()
-        str_ = sr.solve(K)
-        rus_s = time.perf_counter() - t5
-        nr = str_["kernel_launches"]["couple"]
-        rus = {"solves_per_s": 1.0 / rus_s, "ms": rus_s * 1e3, "timing": "HIP events on",
-               "flux": "Rusanov, S+ = c", "scattering": "kappa_s = kappa_a", "ranks": [str_["r1"], str_["r2"]],
-               "max_R": [str_["max_R1"], str_["max_R2"]],
-               "prepass_us_per_launch": str_["kernel_ms"]["couple"] / max(1, nr) * 1e3,
-               "kernel_us_per_launch": {c: str_["kernel_ms"][c] / str_["kernel_launches"][c] * 1e3
-                                        for c in tt.KERNEL_CLASSES if str_["kernel_launches"][c]}}
-        sr.destroy()
-    # ---- phase 7: seed 0 with randomized rounding (Section 3.1 footnote), beside Gram rounding ----
-    rnd = None
-    if args.randomized:
-        prr = prob.copy(round_method=ti.ROUND_RAND, rand_oversample=4, rand_seed=0)
-        srr = tt.Solver(prr, device=dev)
-        srr.solve(2)                                   # warm-up
-        srr.reset()
-        torch.cuda.synchronize()
-        t8 = time.perf_counter()
-        strr = srr.solve(K)
-        rnd_s = time.perf_counter() - t8
-        diff = tt_rel_diff(single.get_cores(), srr.get_cores())
-        # the Gram-rounded solve under the same conditions (no events)
-        single.reset()
-        single.set_timing(False)
-        torch.cuda.synchronize()
-        t9 = time.perf_counter()
-        single.solve(K)
-        gram_s = time.perf_counter() - t9
-        srr.reset()
-        srr.set_timing(True)
-        stre = srr.solve(K)
-        ns = stre["kernel_launches"]["svd"]
-        rnd = {"solves_per_s": 1.0 / rnd_s, "ms": rnd_s * 1e3, "gram_single_solve_ms": gram_s * 1e3,
-               "oversample": 4, "ranks": [strr["r1"], strr["r2"]],
-               "sketch_ranks_last": [strr["sketch_r1"], strr["sketch_r2"]],
-               "rel_l2_vs_gram_solve": diff,
-               "svd_class_us_per_round": stre["kernel_ms"]["svd"] / max(1, K) * 1e3,
-               "svd_class_launches_per_round": ns / max(1, K),
-               "timing": "solve without events; per-class times from a second solve with HIP events"}
-        srr.destroy()
-    lat_ms = np.array(lat) * 1e3
+    # ---- the headline: the 3D workload in FP64 at steady state ----
+    head, st64, beside, p64 = c3_phase(args)
+    ms_step = head["ms_per_step"]
+    value = 1e3 / (C3_STEPS_PER_SOLVE * ms_step)
     out = {
         "metric": METRIC,
         "value": value,
@@ -565,45 +725,45 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "plane2d: 128x128 cells, 32 groups [0.01,10], 8x8 angles, lognormal kappa0 "
-                               "(sigma 1, l 0.1), FP32 contractions + FP64 Gram/SVD, rank cap 32, tol 1e-6, "
-                               "512 steps per solve",
-                   "batch": B, "streams": len(streams), "seeds": f"0..{B - 1}",
-                   "round_method": args.round_method, "timesteps_per_solve": K},
-        "gflops": batch_flops * args.steps / elapsed / 1e9,
-        "p50_ms": float(np.percentile(lat_ms, 50)),
-        "p99_ms": float(np.percentile(lat_ms, 99)),
-        "single_solve": {"solves_per_s": 1.0 / single_s, "ms": single_s * 1e3,
-                         "gflops": sum(agg_fl.values()) / single_s / 1e9},
-        "ranks": [last["r1"], last["r2"]],
-        "max_R": [last["max_R1"], last["max_R2"]],
-        "compression": last["compression"],
-        "kernel_ms_per_solve": {c: agg_ms[c] for c in tt.KERNEL_CLASSES if agg_n[c]},
-        "kernel_us_per_launch": {c: agg_ms[c] / agg_n[c] * 1e3 for c in tt.KERNEL_CLASSES if agg_n[c]},
-        "roofline": roofline(st1),
-        "hbm_algorithmic": kernel_hbm(st1, prob.M),
-        "internal_ranks": internal,
+        "config": {"workload": "clumps3d: 64^3 cells on [0,1]^3, 64 groups [0.01,10], 8x16 angles, lognormal "
+                               "kappa0 (sigma 1, l 0.1) with two clumps x100, Planck T=1 inflow on x=0, rank cap 64, "
+                               "tol 1e-5, 384 steps per solve; FP64 state and contractions (FP64 MFMA), FP64 Gram "
+                               "rounding; a step is one time step at the rank cap (R1 = 450, k1 = 128)",
+                   "rank_warmup_steps": head["rank_warmup_steps"], "timesteps_per_solve": C3_STEPS_PER_SOLVE,
+                   "round_method": "gram"},
+        "timesteps_per_s": 1e3 / ms_step,
+        "gflops": head["flops_per_step"] / ms_step / 1e6,
+        "ranks": head["ranks"], "max_R": head["max_R"], "compression": head["compression"],
+        "workspace_gb": head["workspace_gb"],
+        "kernel_ms_per_step": head["kernel_ms_per_step"],
+        "roofline": roofline_c3(st64, p64.M),
+        "precisions_beside": beside,
     }
-    if plain:
-        out["plain_fp64"] = plain
-    if coupled is not None:
-        out["coupled_temperature"] = coupled
-    if rus is not None:
-        out["rusanov_scattering"] = rus
-    if rnd is not None:
-        out["randomized_rounding"] = rnd
-    if c1 is not None:
-        out["c1_slab1d"] = c1
+    del beside
+    # ---- the 2D workload against the dense oracle, the 1D slab, extras ----
+    single = None
+    if args.c2:
+        c2, single = plane2d_phase(args, dev)
+        out["plane2d"] = c2
+        out.update(extras_phase(args, dev, single))
+        single.destroy()
+    if args.c1_batch > 0:
+        out["c1_slab1d"] = c1_phase(args, dev)
     if args.served > 0:
-        out["served"] = served_phase(args)
+        sv = served_phase(args)
+        out["served"] = sv
+        out["p50_ms"] = sv["p50_ms"]
+        out["p99_ms"] = sv["p99_ms"]
+        out["latency_source"] = ("served request mix (256 requests, Poisson arrivals at 0.8 x capacity): "
+                                 "per-request time from arrival to completion")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob)
+        out["cpu_baseline"] = cpu_baseline_c3()
     print(json.dumps(out), flush=True)
 
 

@@ -1,5 +1,6 @@
 """Host-side helpers of bench.py whose outputs are reported numbers: the TT
-difference of two solutions (from core inner products, no full tensor), the
+difference of two solutions (through the R factor of the stacked first cores,
+no full tensor), the
 kernel-source hash that keys the stored traffic counters, and the refusal of
 more than one GPU."""
 import os
@@ -7,6 +8,7 @@ import subprocess
 import sys
 
 import numpy as np
+import pytest
 
 import bench
 import tt_inputs as ti
@@ -15,18 +17,30 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_tt_rel_diff_equals_the_dense_difference():
+    # the difference is taken through a Householder R of the stacked first
+    # cores, with no cancellation: it resolves relative differences far below
+    # sqrt(eps), down to the rounding of the cores themselves
     rng = np.random.default_rng(0)
     x = ti.random_tt(40, 4, 6, 5, 3, seed=1)
     for y in (ti.random_tt(40, 4, 6, 7, 2, seed=2),                      # different ranks
-              (x[0] * (1 + 1e-4 * rng.standard_normal(x[0].shape)), x[1], x[2])):   # a near copy
+              (x[0] * (1 + 1e-4 * rng.standard_normal(x[0].shape)), x[1], x[2]),   # a near copy
+              (x[0] * (1 + 1e-11 * rng.standard_normal(x[0].shape)), x[1], x[2])):  # a very near copy
         X = np.einsum("ka,alb,bp->klp", *x)
         Y = np.einsum("ka,alb,bp->klp", *y)
-        ref = np.linalg.norm(X - Y) / np.linalg.norm(X)
-        # ||X - Y||^2 = <X,X> + <Y,Y> - 2 <X,Y> cancels to a few eps of ||X||^2,
-        # so d = ||X - Y|| / ||X|| carries an absolute error of about 2 eps / d
-        eps = np.finfo(float).eps
-        assert abs(bench.tt_rel_diff(x, y) - ref) <= 1e-12 * ref + 32 * eps / ref
-    assert bench.tt_rel_diff(x, x) < 1e-7
+        ref = np.linalg.norm(X - Y) / np.linalg.norm(Y)
+        assert abs(bench.tt_rel_diff(x, y) - ref) <= 1e-6 * ref + 1e-15
+    assert bench.tt_rel_diff(x, x) < 1e-15
+
+
+def test_tt_rel_diff_over_row_chunks():
+    # more rows than one chunk of the first-core R (2^20 rows)
+    x = ti.random_tt((1 << 20) + 37, 3, 2, 3, 2, seed=3)
+    y = (x[0].copy(), x[1].copy(), x[2].copy())
+    y[0][-5:] += 1e-3
+    X = np.einsum("ka,alb,bp->klp", *x)
+    Y = np.einsum("ka,alb,bp->klp", *y)
+    ref = np.linalg.norm(X - Y) / np.linalg.norm(Y)
+    assert bench.tt_rel_diff(x, y) == pytest.approx(ref, rel=1e-8)
 
 
 def test_kernel_source_hash_tracks_the_counted_sources():

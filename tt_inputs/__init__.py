@@ -362,6 +362,17 @@ def clumps3d(n=64, n_groups=64, n_theta=8, n_phi=16, T=0.1, T_b=1.0, tol=1e-5, r
         cfl=cfl, tol=tol, rank_cap=rank_cap, precision=precision, n_steps=n_steps, seed=seed)
 
 
+def clumps3d_slab(n=64, nz=4, slab=0, **kw):
+    """One z-slab (n x n x nz cells) of the clumps3d cube with the cube's
+    opacity field (same seed) cut to the slab and the cube's cell spacing, so
+    a step costs nz / n of the cube's.  Used to time the dense CPU reference on
+    a bounded part of the 64^3 workload."""
+    cube = clumps3d(n=n, **kw)
+    k0 = np.asarray(cube.kappa0).reshape(n, n, n)[slab * nz:(slab + 1) * nz].ravel().copy()
+    return cube.copy(name="clumps3d_slab", n_cells=(n, n, nz), extent=(1.0, 1.0, nz / n), kappa0=k0,
+                     T_cell=np.asarray(cube.T_cell).reshape(n, n, n)[slab * nz:(slab + 1) * nz].ravel().copy())
+
+
 def spikes3d(n=256, n_groups=128, n_theta=16, n_phi=16, T=0.1, T_b=1.0, tol=1e-5, rank_cap=128,
              precision=PREC_BF16X, n_steps=8, cfl=0.5, seed=0, nu=(0.01, 10.0)):
     """3D cube, lognormal kappa0, 8 random groups with kappa x50 (line-like spikes)."""
