@@ -341,6 +341,21 @@ tt_status tt_transport_step_batch(tt_handle** hs, int n, void** streams, int n_s
 tt_status tt_transport_solve_batch(tt_handle** hs, int n, int n_steps, void** streams, int n_streams,
                                    tt_stats* out);
 
+/* Advance many small independent requests with one persistent ragged kernel
+ * (the batching of many solves with different grids, group counts, ranks and
+ * step counts): handle i takes n_steps[i] full steps, each request in one
+ * 1024-thread workgroup that runs the whole apply + round path of every step
+ * (small-core QR, gather projection, Householder QR of the first core, SVD
+ * chain, output contraction) without a launch per kernel, up to 256 requests
+ * per launch side by side.  Eligible handles: FP64 data, Householder QR
+ * rounding (TT_ROUND_QR, or AUTO with FP64), a projected first core of at most
+ * 16 columns (N_theta N_phi <= 16, e.g. 1D slabs with up to 16 directions),
+ * one rounding per step, no coupled temperature or scattering, timing off;
+ * others fail with TT_ERR_INVALID_ARG naming the reason.  A request's result
+ * does not depend on the other requests of the batch.  Runs on `stream`,
+ * then synchronises it; out (may be NULL) receives n stats. */
+tt_status tt_transport_solve_small_batch(tt_handle** hs, int n, const int* n_steps, void* stream, tt_stats* out);
+
 /* Release the handle's host resources.  Never frees the caller's workspace. */
 tt_status tt_transport_destroy(tt_handle* h);
 

@@ -146,6 +146,8 @@ def _load():
     L.tt_transport_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int]
     L.tt_transport_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp),
                                            ctypes.c_int, ctypes.POINTER(TTStats)]
+    L.tt_transport_solve_small_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int), vp,
+                                                 ctypes.POINTER(TTStats)]
     L.tt_transport_destroy.argtypes = [vp]
     L.tt_transport_last_error.argtypes = []
     L.tt_transport_last_error.restype = ctypes.c_char_p
@@ -154,7 +156,8 @@ def _load():
     L.tt_transport_internal_ranks.argtypes = [vp, ctypes.c_double, ctypes.POINTER(TTInternalRanks), _dp, ctypes.c_int,
                                               _dp, ctypes.c_int, vp]
     for name in ("create", "create_noalloc", "apply_op", "round", "solve", "reset", "get_ranks", "get_cores", "set_cores",
-                 "get_stats", "set_timing", "step_batch", "solve_batch", "destroy", "group_emission",
+                 "get_stats", "set_timing", "step_batch", "solve_batch", "solve_small_batch", "destroy",
+                 "group_emission",
                  "get_temperature", "internal_ranks"):
         getattr(L, "tt_transport_" + name).restype = ctypes.c_int
     return L
@@ -165,7 +168,8 @@ lib = _load()
 EXPORTED = ("tt_transport_workspace_bytes", "tt_transport_create", "tt_transport_create_noalloc", "tt_transport_apply_op", "tt_transport_round",
             "tt_transport_solve", "tt_transport_reset", "tt_transport_get_ranks", "tt_transport_get_cores",
             "tt_transport_set_cores", "tt_transport_get_stats", "tt_transport_set_timing",
-            "tt_transport_step_batch", "tt_transport_solve_batch", "tt_transport_destroy", "tt_transport_last_error",
+            "tt_transport_step_batch", "tt_transport_solve_batch", "tt_transport_solve_small_batch",
+            "tt_transport_destroy", "tt_transport_last_error",
             "tt_transport_group_emission", "tt_transport_get_temperature", "tt_transport_internal_ranks")
 
 
@@ -394,4 +398,19 @@ def solve_batch(solvers, n_steps, streams):
     arr = (ctypes.c_void_p * len(solvers))(*[s.handle for s in solvers])
     stats = (TTStats * len(solvers))()
     _check(lib.tt_transport_solve_batch(arr, len(solvers), int(n_steps), _stream_array(streams), len(streams), stats))
+    return [st.as_dict() for st in stats]
+
+
+def solve_small_batch(solvers, n_steps, stream=None):
+    """n_steps[i] steps of solver i (an int applies to all) in the persistent
+    ragged small-solve kernel; synchronises; returns one stats dict per solver."""
+    import torch
+    n = len(solvers)
+    if isinstance(n_steps, int):
+        n_steps = [n_steps] * n
+    arr = (ctypes.c_void_p * n)(*[s.handle for s in solvers])
+    steps = (ctypes.c_int * n)(*[int(k) for k in n_steps])
+    stats = (TTStats * n)()
+    sp = torch.cuda.current_stream().cuda_stream if stream is None else stream.cuda_stream
+    _check(lib.tt_transport_solve_small_batch(arr, n, steps, ctypes.c_void_p(sp), stats))
     return [st.as_dict() for st in stats]

@@ -181,10 +181,12 @@ __global__ __launch_bounds__(256) void k_gather_gemm(Geom g, OpDesc op, const De
 // rows_per_R > 0 (tree levels): the input is a stack of KP x KP R factors of
 // which only the first rows_per_R rows can be non-zero (k1 <= rows_per_R);
 // row r of the level is row r % rows_per_R of factor r / rows_per_R.
+// (the body of k_tsqr for the block with index blk; also called by the
+// persistent small-solve kernel with one block over all rows)
 template <typename TS, int KP, int NG, int BR>
-__global__ __launch_bounds__(KP* NG) void k_tsqr(const TS* __restrict__ A, int lda_static, int lda_from_state,
-                                                 int rows_per_R, long long nrows, long long rows_per_block,
-                                                 const DevState* __restrict__ st, double* __restrict__ Rout) {
+__device__ __forceinline__ void tsqr_body(const TS* __restrict__ A, int lda_static, int lda_from_state, int rows_per_R,
+                                          long long nrows, long long rows_per_block, const DevState* __restrict__ st,
+                                          double* __restrict__ Rout, int blk) {
     __shared__ double R[KP][KP];
     __shared__ double vbuf[2][NG * BR];
     __shared__ double pdot[2][NG][KP];
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(KP* NG) void k_tsqr(const TS* __restrict__ A, int l
     const int lda = lda_from_state ? st->ldb : lda_static;
     for (int idx = tid; idx < KP * KP; idx += KP * NG) R[idx / KP][idx % KP] = 0.0;
     __syncthreads();
-    const long long begin = (long long)blockIdx.x * rows_per_block;
+    const long long begin = (long long)blk * rows_per_block;
     long long end = begin + rows_per_block;
     if (end > nrows) end = nrows;
     double T[BR];
@@ -254,11 +256,18 @@ __global__ __launch_bounds__(KP* NG) void k_tsqr(const TS* __restrict__ A, int l
         }
     }
     __syncthreads();
-    double* out = Rout + (size_t)blockIdx.x * KP * KP;
+    double* out = Rout + (size_t)blk * KP * KP;
     for (int idx = tid; idx < KP * KP; idx += KP * NG) {
         const int i = idx / KP, j = idx % KP;
         out[idx] = (j >= i) ? R[i][j] : 0.0;
     }
+}
+
+template <typename TS, int KP, int NG, int BR>
+__global__ __launch_bounds__(KP* NG) void k_tsqr(const TS* __restrict__ A, int lda_static, int lda_from_state,
+                                                 int rows_per_R, long long nrows, long long rows_per_block,
+                                                 const DevState* __restrict__ st, double* __restrict__ Rout) {
+    tsqr_body<TS, KP, NG, BR>(A, lda_static, lda_from_state, rows_per_R, nrows, rows_per_block, st, Rout, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------

@@ -769,16 +769,17 @@ struct FastDiv {
 // The state gets R1, R2, k1, k2, ldb, and whether both Q's are identities
 // (the projected basis is then the canonical angular basis, so the previous
 // round's singular vectors are a valid warm start).
+// (the body of k_prep, also called by the persistent small-solve kernel;
+// lds is the block's dynamic LDS of lds_doubles doubles)
 template <typename TC>
-__global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevState* st, const double* __restrict__ Th,
-                                                        const double* __restrict__ Ph, const double* __restrict__ gtab,
-                                                        const double* __restrict__ htab, SmallScratch sc,
-                                                        double* __restrict__ LTh, int ldl, double* __restrict__ QTh,
-                                                        double* __restrict__ QPh, TC* __restrict__ Gop,
-                                                        TC* __restrict__ Gsw, int nct) {
-    extern __shared__ double lds[];
+__device__ __forceinline__ void prep_body(const Geom& g, const OpDesc& op, DevState* st, const double* __restrict__ Th,
+                                          const double* __restrict__ Ph, const double* __restrict__ gtab,
+                                          const double* __restrict__ htab, const SmallScratch& sc,
+                                          double* __restrict__ LTh, int ldl, double* __restrict__ QTh,
+                                          double* __restrict__ QPh, TC* __restrict__ Gop, TC* __restrict__ Gsw,
+                                          int nct, double* lds, size_t lds_doubles) {
     __shared__ double red[16];
-    LdsCarver cv{lds, 0, (size_t)kSmallLdsBytes / sizeof(double)};
+    LdsCarver cv{lds, 0, lds_doubles};
     const int nt = g.nt, npn = g.np;
     const int r1 = st->r1, r2 = st->r2, ldz = st->ldz;
     const int nrb = op.n_rblk, nr1 = op.n_r1;
@@ -984,25 +985,27 @@ __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevSt
 // in Z:  Z_out = B V_r;  Theta'' = V_r^T Q_Theta;  SVD of diag(S_r) Theta''
 // ((r1 N_theta) x k2) -> V2, S2;  Theta_out = Theta'' x_3 V2_r;
 // Phi_out = V2_r^T Q_Phi.  Truncation: delta = tol ||X||_F / sqrt(2) per bond.
+// (the body of k_svd_chain, also called by the persistent small-solve
+// kernel; lds is the block's dynamic LDS of lds_doubles doubles, at least the
+// fixed layout's when FAST)
 template <typename TC, bool FAST>
-__global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* st, const double* __restrict__ RB, int ldr,
-                                                             int gram, const double* __restrict__ QTh,
-                                                             const double* __restrict__ QPh, double tol, int cap1,
-                                                             int cap2, SmallScratch sc, double* __restrict__ ThOut,
-                                                             double* __restrict__ PhOut, TC* __restrict__ Vout,
-                                                             double* __restrict__ sv_out, const TC* __restrict__ Gop,
-                                                             TC* __restrict__ Gfold, int nct_o) {
+__device__ __forceinline__ void svd_chain_body(const Geom& g, DevState* st, const double* __restrict__ RB, int ldr,
+                                               int gram, const double* __restrict__ QTh,
+                                               const double* __restrict__ QPh, double tol, int cap1, int cap2,
+                                               const SmallScratch& sc, double* __restrict__ ThOut,
+                                               double* __restrict__ PhOut, TC* __restrict__ Vout,
+                                               double* __restrict__ sv_out, const TC* __restrict__ Gop,
+                                               TC* __restrict__ Gfold, int nct_o, double* lds, size_t lds_doubles) {
     // Gop, Gfold, nct_o: non-null Gfold marks a fused pass (its operand G V_r is
     // formed afterwards by k_fold); they only change the flop accounting here
     (void)Gop;
     (void)nct_o;
-    extern __shared__ double lds[];
     __shared__ double red[16];
     __shared__ int sh_r[2];
     __shared__ int sh_flag;
     __shared__ double cs[2 * 128];
     __shared__ int pa_[128], pb_[128];
-    LdsCarver cv{lds, 0, (size_t)kSmallLdsBytes / sizeof(double)};
+    LdsCarver cv{lds, 0, lds_doubles};
     const int nt = g.nt, npn = g.np;
     const int k1 = st->k1, k2 = st->k2;
     const int m2 = nt * k2;
@@ -1230,6 +1233,31 @@ __global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* s
 // gather operand with the FP64 right singular vectors kept by the SVD chain),
 // in the lane order of the fused MFMA kernel: slot ((t * nct + c) * 64 + lane)
 // * 4 + e holds G'[16 t + 4 (lane / 16) + e][16 c + lane % 16].
+template <typename TC>
+__global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevState* st, const double* __restrict__ Th,
+                                                        const double* __restrict__ Ph, const double* __restrict__ gtab,
+                                                        const double* __restrict__ htab, SmallScratch sc,
+                                                        double* __restrict__ LTh, int ldl, double* __restrict__ QTh,
+                                                        double* __restrict__ QPh, TC* __restrict__ Gop,
+                                                        TC* __restrict__ Gsw, int nct) {
+    extern __shared__ double lds[];
+    prep_body<TC>(g, op, st, Th, Ph, gtab, htab, sc, LTh, ldl, QTh, QPh, Gop, Gsw, nct, lds,
+                  (size_t)kSmallLdsBytes / sizeof(double));
+}
+
+template <typename TC, bool FAST>
+__global__ __launch_bounds__(kSmallThreads) void k_svd_chain(Geom g, DevState* st, const double* __restrict__ RB, int ldr,
+                                                             int gram, const double* __restrict__ QTh,
+                                                             const double* __restrict__ QPh, double tol, int cap1,
+                                                             int cap2, SmallScratch sc, double* __restrict__ ThOut,
+                                                             double* __restrict__ PhOut, TC* __restrict__ Vout,
+                                                             double* __restrict__ sv_out, const TC* __restrict__ Gop,
+                                                             TC* __restrict__ Gfold, int nct_o) {
+    extern __shared__ double lds[];
+    svd_chain_body<TC, FAST>(g, st, RB, ldr, gram, QTh, QPh, tol, cap1, cap2, sc, ThOut, PhOut, Vout, sv_out, Gop,
+                             Gfold, nct_o, lds, (size_t)kSmallLdsBytes / sizeof(double));
+}
+
 template <typename TC>
 __global__ __launch_bounds__(256) void k_fold(const DevState* __restrict__ st, const TC* __restrict__ Gop,
                                               const double* __restrict__ Wkeep, TC* __restrict__ Gfold, int nct) {

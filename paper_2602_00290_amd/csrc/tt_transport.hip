@@ -27,6 +27,7 @@
 #include "k_big.hpp"
 #include "k_fused.hpp"
 #include "k_f64.hpp"
+#include "k_batch.hpp"
 #include "k_gram.hpp"
 #include "k_mfma.hpp"
 #include "k_couple.hpp"
@@ -109,6 +110,7 @@ struct Plan {
     double rus_s = 1.0;   // Rusanov S+ / c
     size_t o_T = 0, o_T0 = 0, o_Js = 0, o_edges = 0, o_wth = 0, o_wph = 0, o_kscat = 0, o_jn = 0;
     size_t k1sq = 1;                // k1cap x (k1cap | 1): SVD-chain matrices outside LDS
+    size_t o_desc = 0;
     // A2 scratch (doubles): the operand of the second-bond QR, the first-bond
     // matrix T outside LDS, or the second-bond Gram matrix
     size_t a2n() const {
@@ -385,6 +387,7 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
     P.o_PhN = take((size_t)P.R2cap * P.np * d);
     P.o_sv = take((size_t)(P.k1cap + P.k2cap) * d);
     P.o_colsum = take((size_t)256 * 128 * d);
+    P.o_desc = take(sizeof(SmallSolve));   // descriptor of the persistent small-solve kernel
     P.coupled = p->heat_capacity > 0.0;
     P.kscat = p->kappa_s_full != nullptr;
     P.prepass = P.coupled || P.kscat;
@@ -1321,6 +1324,59 @@ int delta_rank_host(const std::vector<double>& s, double delta) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Persistent ragged small-solve kernel (k_solve_small)
+// ---------------------------------------------------------------------------
+
+// Why a handle cannot run in k_solve_small ("" when it can).
+std::string small_ineligible(const tt_handle* h) {
+    const Plan& P = h->P;
+    if (h->precision != TT_PREC_FP64) return "FP64 data only";
+    if (h->round_method != TT_ROUND_QR) return "Householder QR rounding only";
+    if (P.KPt != 16) return "a projected first core of at most 16 columns only";
+    if (h->step_order != 0) return "one rounding per step only";
+    if (P.prepass) return "no coupled temperature or scattering";
+    if (!P.svd_fast) return "the SVD chain's fixed LDS layout is needed";
+    if (h->pending != OP_NONE) return "an unrounded operator is pending";
+    if (h->timing) return "per-kernel timing is on";
+    return "";
+}
+
+SmallSolve small_desc(tt_handle* h, int n_steps) {
+    const Plan& P = h->P;
+    SmallSolve q;
+    std::memset(&q, 0, sizeof(q));
+    q.g = h->geom;
+    q.op = h->ops[OP_FULL];
+    q.st = h->st();
+    q.Z[0] = (double*)(h->ws + P.o_Z0);
+    q.Z[1] = (double*)(h->ws + P.o_Z1);
+    q.Th[0] = h->at<double>(P.o_Th0);
+    q.Th[1] = h->at<double>(P.o_Th1);
+    q.Ph[0] = h->at<double>(P.o_Ph0);
+    q.Ph[1] = h->at<double>(P.o_Ph1);
+    q.gtab = h->at<double>(P.o_gtab);
+    q.htab = h->at<double>(P.o_htab);
+    q.sc = h->scratch();
+    q.LTh = h->at<double>(P.o_LTh);
+    q.QTh = h->at<double>(P.o_QTh);
+    q.QPh = h->at<double>(P.o_QPh);
+    q.Gop = h->at<double>(P.o_G);
+    q.B = h->at<double>(P.o_B);
+    q.V = h->at<double>(P.o_V);
+    q.R = h->at<double>(P.o_RA);
+    q.sv = h->at<double>(P.o_sv);
+    q.rd = h->rowdata();
+    q.tol = h->tol;
+    q.k1cap = P.k1cap;
+    q.cap1 = std::min(P.cap, P.r1cap);
+    q.cap2 = std::min(P.cap, P.r2cap);
+    q.n_steps = n_steps;
+    // Z and the small cores flip together; both start at the handle's current parity
+    q.zcur0 = h->zcur;
+    return q;
+}
+
+// ---------------------------------------------------------------------------
 // Static workspace for tt_transport_create_noalloc
 // ---------------------------------------------------------------------------
 //
@@ -1905,6 +1961,70 @@ tt_status tt_transport_solve_batch(tt_handle** hs, int n, int n_steps, void** st
         hs[i]->ev_collect();
         if (out) {
             tt_status r = fill_stats(hs[i], &out[i], (hipStream_t)streams[i % n_streams]);
+            if (r != TT_OK) return r;
+        }
+    }
+    return TT_OK;
+}
+
+tt_status tt_transport_solve_small_batch(tt_handle** hs, int n, const int* n_steps, void* stream, tt_stats* out) {
+    if (!hs || n < 0 || (n > 0 && !n_steps)) return fail(TT_ERR_INVALID_ARG, "bad arguments");
+    for (int i = 0; i < n; ++i) {
+        if (!hs[i]) return fail(TT_ERR_INVALID_ARG, "NULL handle");
+        if (n_steps[i] < 0) return fail(TT_ERR_INVALID_ARG, "n_steps must be >= 0");
+        for (int j = i + 1; j < n; ++j)
+            if (hs[i] == hs[j]) return fail(TT_ERR_INVALID_ARG, "handles must be distinct");
+        const std::string why = small_ineligible(hs[i]);
+        if (!why.empty()) return fail(TT_ERR_INVALID_ARG, "handle " + std::to_string(i) + ": " + why);
+        if (hs[i]->zcur != hs[i]->ccur) return fail(TT_ERR_STATE, "handle " + std::to_string(i) + ": core parity");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    {
+        static bool attr = false;
+        if (!attr) {
+            HIP_TRY(hipFuncSetAttribute((const void*)k_solve_small, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)kBatchLdsBytes));
+            attr = true;
+        }
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    for (int b0 = 0; b0 < n; b0 += kBatchMax) {
+        const int nb = std::min(kBatchMax, n - b0);
+        SmallBatch batch;
+        std::memset(&batch, 0, sizeof(batch));
+        for (int i = 0; i < nb; ++i) {
+            tt_handle* h = hs[b0 + i];
+            for (int c = 0; c < 8; ++c) { h->kernel_ms[c] = 0; h->kernel_launches[c] = 0; h->flops[c] = 0; }
+            DevState st;
+            tt_status r = read_state(h, st, s);
+            if (r != TT_OK) return r;
+            for (int c = 0; c < 4; ++c) st.fl[c] = 0.0;
+            r = write_state(h, st, s);
+            if (r != TT_OK) return r;
+            const SmallSolve q = small_desc(h, n_steps[b0 + i]);
+            SmallSolve* dq = reinterpret_cast<SmallSolve*>(h->ws + h->P.o_desc);
+            HIP_TRY(hipMemcpyAsync(dq, &q, sizeof(q), hipMemcpyHostToDevice, s));
+            batch.req[i] = dq;
+        }
+        HIP_TRY(hipStreamSynchronize(s));   // the descriptors are in place (their host copies go out of scope)
+        hipLaunchKernelGGL(k_solve_small, dim3(nb), dim3(kSmallThreads), kBatchLdsBytes, s, batch);
+        HIP_TRY(hipGetLastError());
+        for (int i = 0; i < nb; ++i) {
+            tt_handle* h = hs[b0 + i];
+            if (n_steps[b0 + i] & 1) {
+                h->zcur ^= 1;
+                h->ccur ^= 1;
+            }
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    auto t1 = std::chrono::steady_clock::now();
+    const double sec = std::chrono::duration<double>(t1 - t0).count();
+    for (int i = 0; i < n; ++i) {
+        hs[i]->last_seconds = sec;
+        hs[i]->last_steps = n_steps[i];
+        if (out) {
+            tt_status r = fill_stats(hs[i], &out[i], s);
             if (r != TT_OK) return r;
         }
     }
