@@ -322,6 +322,15 @@ tt_status tt_transport_get_temperature(tt_handle* h, double* T, void* stream);
 tt_status tt_transport_internal_ranks(tt_handle* h, double delta, tt_internal_ranks* out, double* sv_nu,
                                       int n_sv_nu, double* sv_x, int n_sv_x, void* stream);
 
+/* Replay the step sequence as a HIP graph (on = 1) or launch every kernel
+ * (on = 0, the default).  With graphs on, tt_transport_solve captures two
+ * steps (the kernels of every rounding pass of both, and nothing else) into a
+ * graph on first use, then launches that graph once per two steps; an odd
+ * last step is launched kernel by kernel.  The result is bitwise the same as
+ * without graphs.  Needs a non-null stream; graphs are not used while kernel
+ * timing is on or an unrounded operator is pending.  on = 0 frees the graphs. */
+tt_status tt_transport_set_graph(tt_handle* h, int on);
+
 /* Fill `out` with the statistics of the current state (synchronises). */
 tt_status tt_transport_get_stats(tt_handle* h, tt_stats* out);
 

@@ -143,6 +143,7 @@ def _load():
     L.tt_transport_set_cores.argtypes = [vp, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, vp]
     L.tt_transport_get_stats.argtypes = [vp, ctypes.POINTER(TTStats)]
     L.tt_transport_set_timing.argtypes = [vp, ctypes.c_int]
+    L.tt_transport_set_graph.argtypes = [vp, ctypes.c_int]
     L.tt_transport_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int]
     L.tt_transport_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp),
                                            ctypes.c_int, ctypes.POINTER(TTStats)]
@@ -156,7 +157,7 @@ def _load():
     L.tt_transport_internal_ranks.argtypes = [vp, ctypes.c_double, ctypes.POINTER(TTInternalRanks), _dp, ctypes.c_int,
                                               _dp, ctypes.c_int, vp]
     for name in ("create", "create_noalloc", "apply_op", "round", "solve", "reset", "get_ranks", "get_cores", "set_cores",
-                 "get_stats", "set_timing", "step_batch", "solve_batch", "solve_small_batch", "destroy",
+                 "get_stats", "set_timing", "set_graph", "step_batch", "solve_batch", "solve_small_batch", "destroy",
                  "group_emission",
                  "get_temperature", "internal_ranks"):
         getattr(L, "tt_transport_" + name).restype = ctypes.c_int
@@ -167,7 +168,7 @@ lib = _load()
 
 EXPORTED = ("tt_transport_workspace_bytes", "tt_transport_create", "tt_transport_create_noalloc", "tt_transport_apply_op", "tt_transport_round",
             "tt_transport_solve", "tt_transport_reset", "tt_transport_get_ranks", "tt_transport_get_cores",
-            "tt_transport_set_cores", "tt_transport_get_stats", "tt_transport_set_timing",
+            "tt_transport_set_cores", "tt_transport_get_stats", "tt_transport_set_timing", "tt_transport_set_graph",
             "tt_transport_step_batch", "tt_transport_solve_batch", "tt_transport_solve_small_batch",
             "tt_transport_destroy", "tt_transport_last_error",
             "tt_transport_group_emission", "tt_transport_get_temperature", "tt_transport_internal_ranks")
@@ -364,6 +365,10 @@ class Solver:
 
     def set_timing(self, on: bool):
         _check(lib.tt_transport_set_timing(self.handle, 1 if on else 0))
+
+    def set_graph(self, on: bool):
+        """Replay the steps of solve() as HIP graphs (needs a non-default stream)."""
+        _check(lib.tt_transport_set_graph(self.handle, 1 if on else 0))
 
     def destroy(self):
         if self.handle:

@@ -458,6 +458,12 @@ struct tt_handle {
     double flops[8] = {0};
     double last_seconds = 0.0;
     int last_steps = 0;
+    // hipGraph replay of the step sequence (tt_transport_set_graph): two steps
+    // per graph, so the ping-pong buffers are back at the captured parity; one
+    // graph per parity of the current buffers
+    bool use_graph = false;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
 
     template <typename T>
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -1691,6 +1697,77 @@ tt_status tt_transport_round(tt_handle* h, double tol, int rank_cap, void* strea
     return round_dispatch(h, op, tol, rank_cap, (hipStream_t)stream);
 }
 
+namespace {
+// Capture two steps of h on stream s into the graph of the current parity.
+tt_status capture_two_steps(tt_handle* h, hipStream_t s) {
+    const int par = h->zcur;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    tt_status r = step_impl(h, s);
+    if (r == TT_OK) r = step_impl(h, s);
+    hipGraph_t gph = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &gph);
+    if (r != TT_OK) {
+        if (gph) (void)hipGraphDestroy(gph);
+        return r;
+    }
+    if (e != hipSuccess) return fail(TT_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    if (h->zcur != par) {
+        (void)hipGraphDestroy(gph);
+        return fail(TT_ERR_STATE, "two steps did not return to the captured buffer parity");
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&ex, gph, nullptr, nullptr, 0);
+    if (e2 != hipSuccess) {
+        (void)hipGraphDestroy(gph);
+        return fail(TT_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+    }
+    h->graph[par] = gph;
+    h->graph_exec[par] = ex;
+    return TT_OK;
+}
+
+void drop_graphs(tt_handle* h) {
+    for (int i = 0; i < 2; ++i) {
+        if (h->graph_exec[i]) (void)hipGraphExecDestroy(h->graph_exec[i]);
+        if (h->graph[i]) (void)hipGraphDestroy(h->graph[i]);
+        h->graph_exec[i] = nullptr;
+        h->graph[i] = nullptr;
+    }
+}
+
+// n_steps steps: graph replays of two steps while at least two remain (when
+// graphs are on and the handle allows them), launched steps otherwise.
+tt_status run_steps(tt_handle* h, int n_steps, hipStream_t s) {
+    int i = 0;
+    if (h->use_graph && !h->timing && h->pending == OP_NONE && s != nullptr) {
+        for (; i + 2 <= n_steps; i += 2) {
+            const int par = h->zcur;
+            if (!h->graph_exec[par]) {
+                tt_status r = capture_two_steps(h, s);
+                if (r != TT_OK) return r;
+            }
+            HIP_TRY(hipGraphLaunch(h->graph_exec[par], s));
+        }
+    }
+    for (; i < n_steps; ++i) {
+        tt_status r = step_impl(h, s);
+        if (r != TT_OK) return r;
+        if (h->timing && h->ev_used > 4096) {
+            HIP_TRY(hipStreamSynchronize(s));
+            h->ev_collect();
+        }
+    }
+    return TT_OK;
+}
+}  // namespace
+
+tt_status tt_transport_set_graph(tt_handle* h, int on) {
+    if (!h) return fail(TT_ERR_INVALID_ARG, "handle is NULL");
+    h->use_graph = on != 0;
+    if (!h->use_graph) drop_graphs(h);
+    return TT_OK;
+}
+
 tt_status tt_transport_solve(tt_handle* h, int n_steps, tt_stats* out, void* stream) {
     if (!h) return fail(TT_ERR_INVALID_ARG, "handle is NULL");
     if (n_steps < 0) return fail(TT_ERR_INVALID_ARG, "n_steps must be >= 0");
@@ -1705,13 +1782,9 @@ tt_status tt_transport_solve(tt_handle* h, int n_steps, tt_stats* out, void* str
         if (r != TT_OK) return r;
     }
     auto t0 = std::chrono::steady_clock::now();
-    for (int i = 0; i < n_steps; ++i) {
-        tt_status r = step_impl(h, s);
+    {
+        tt_status r = run_steps(h, n_steps, s);
         if (r != TT_OK) return r;
-        if (h->timing && h->ev_used > 4096) {
-            HIP_TRY(hipStreamSynchronize(s));
-            h->ev_collect();
-        }
     }
     HIP_TRY(hipStreamSynchronize(s));
     auto t1 = std::chrono::steady_clock::now();
@@ -1948,7 +2021,24 @@ tt_status tt_transport_step_batch(tt_handle** hs, int n, void** streams, int n_s
 tt_status tt_transport_solve_batch(tt_handle** hs, int n, int n_steps, void** streams, int n_streams, tt_stats* out) {
     if (n_steps < 0) return fail(TT_ERR_INVALID_ARG, "n_steps must be >= 0");
     auto t0 = std::chrono::steady_clock::now();
-    for (int k = 0; k < n_steps; ++k) {
+    {
+        tt_status r = tt_transport_step_batch(hs, 0, streams, n_streams);   // argument checks
+        if (r != TT_OK) return r;
+        for (int i = 0; i < n; ++i) {
+            if (!hs[i]) return fail(TT_ERR_INVALID_ARG, "NULL handle");
+            for (int j = i + 1; j < n; ++j)
+                if (hs[i] == hs[j]) return fail(TT_ERR_INVALID_ARG, "handles must be distinct");
+        }
+    }
+    // two steps of every handle at a time (one graph launch each for handles
+    // with graphs on), interleaved across the streams
+    int k = 0;
+    for (; k + 2 <= n_steps; k += 2)
+        for (int i = 0; i < n; ++i) {
+            tt_status r = run_steps(hs[i], 2, (hipStream_t)streams[i % n_streams]);
+            if (r != TT_OK) return r;
+        }
+    for (; k < n_steps; ++k) {
         tt_status r = tt_transport_step_batch(hs, n, streams, n_streams);
         if (r != TT_OK) return r;
     }
@@ -2033,6 +2123,7 @@ tt_status tt_transport_solve_small_batch(tt_handle** hs, int n, const int* n_ste
 
 tt_status tt_transport_destroy(tt_handle* h) {
     if (!h) return TT_OK;
+    drop_graphs(h);
     if (h->noalloc_dev >= 0) {
         std::lock_guard<std::mutex> lk(g_scratch_mu);
         if (g_scratch_owner[h->noalloc_dev] == h) g_scratch_owner[h->noalloc_dev] = nullptr;
