@@ -24,6 +24,19 @@
  *
  * s = S+ / c.  Ghost intensities enter both neighbours for every direction.
  *
+ * The HLL flux (oracle_dense_transport_hll; Section 2.1 names it as the
+ * asymptotic-preserving stencil whose only multigroup change is a per-group
+ * optical depth tau_{c,f}): at each interface the flux of c n_d I with wave
+ * speeds +-c |n_d| eps, reduced by the interface's optical depth,
+ *
+ *   F = (c n_d / 2)(I_L + I_R) - (c |n_d| eps / 2)(I_R - I_L),
+ *   eps = (1 - exp(-tau)) / tau,  tau = beta dx_d (kappa_L + kappa_R) / 2,
+ *
+ * kappa the total (absorption + scattering) opacity of the two cells in the
+ * group (the inside cell's on a boundary face); eps -> 1 in thin cells (the
+ * upwind flux) and -> 1 / tau in thick ones (central differences, so the
+ * numerical diffusion stays below the physical one in the diffusion limit).
+ *
  * Direction vector: in 1D n_x = mu; in 2D/3D n = (sin t cos p, sin t sin p, mu)
  * with sin t = sqrt(1 - mu^2).
  *
@@ -167,6 +180,78 @@ int oracle_dense_transport(int dim, const int* n_cells, const double* extent, in
                         double dn = neighbour(I, N, d, +1, idx, g, G, A, a, bc, ghost);
                         acc -= lam[d] * n * (dn - v);
                     }
+                }
+                out[(cell * G + g) * (long)A + a] = acc;
+            }
+        }
+    }
+    free(nd);
+    return 0;
+}
+
+/* Total opacity of the neighbour of `cell` along axis d in direction s for
+   group g, or the cell's own on a non-periodic boundary face. */
+static double kappa_across(const double* kap, const int N[3], int d, int s, const int idx[3], long cell, int g,
+                           int G, const int* bc) {
+    int j[3] = { idx[0], idx[1], idx[2] };
+    j[d] += s;
+    if (j[d] < 0 || j[d] >= N[d]) {
+        int face = 2 * d + (s > 0 ? 1 : 0);
+        if (bc[face] != FACE_PERIODIC) return kap[cell * G + g];
+        j[d] = (j[d] + N[d]) % N[d];
+    }
+    long nc = j[0] + (long)N[0] * (j[1] + (long)N[1] * j[2]);
+    return kap[nc * G + g];
+}
+
+/* eps(tau) = (1 - exp(-tau)) / tau, 1 at tau = 0 */
+static double hll_eps(double tau) { return tau > 0.0 ? -expm1(-tau) / tau : 1.0; }
+
+/* Transport half with the HLL flux, one step (no source).  kap: total
+   opacity per (cell, group) row; beta: the optical-depth factor. */
+int oracle_dense_transport_hll(int dim, const int* n_cells, const double* extent, int G, int NT, int NP,
+                               const double* mu, const double* phi, const int* bc, const double* ghost, double c,
+                               double dt, const double* I, double* out, int n_threads, const double* kap,
+                               double beta) {
+    int N[3] = { n_cells[0], dim > 1 ? n_cells[1] : 1, dim > 2 ? n_cells[2] : 1 };
+    long NX = (long)N[0] * N[1] * N[2];
+    int A = NT * NP;
+    double lam[3], dx[3];
+    for (int d = 0; d < 3; ++d) {
+        dx[d] = (d < dim) ? extent[d] / N[d] : 1.0;
+        lam[d] = (d < dim) ? c * dt / dx[d] : 0.0;
+    }
+    double* nd = (double*)malloc(sizeof(double) * 3 * A);
+    if (!nd) return -1;
+    for (int l = 0; l < NT; ++l)
+        for (int p = 0; p < NP; ++p) direction(dim, mu[l], phi[p], nd + 3 * (l * NP + p));
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+#pragma omp parallel for schedule(static)
+    for (long cell = 0; cell < NX; ++cell) {
+        int idx[3];
+        idx[0] = (int)(cell % N[0]);
+        idx[1] = (int)((cell / N[0]) % N[1]);
+        idx[2] = (int)(cell / ((long)N[0] * N[1]));
+        for (int g = 0; g < G; ++g) {
+            double epsL[3], epsR[3];
+            const double k0 = kap[cell * G + g];
+            for (int d = 0; d < dim; ++d) {
+                epsL[d] = hll_eps(beta * dx[d] * 0.5 * (k0 + kappa_across(kap, N, d, -1, idx, cell, g, G, bc)));
+                epsR[d] = hll_eps(beta * dx[d] * 0.5 * (k0 + kappa_across(kap, N, d, +1, idx, cell, g, G, bc)));
+            }
+            for (int a = 0; a < A; ++a) {
+                double v = I[(cell * G + g) * (long)A + a];
+                double acc = v;
+                for (int d = 0; d < dim; ++d) {
+                    const double n = nd[3 * a + d], an = fabs(n);
+                    const double lo = neighbour(I, N, d, -1, idx, g, G, A, a, bc, ghost);
+                    const double hi = neighbour(I, N, d, +1, idx, g, G, A, a, bc, ghost);
+                    /* lambda (F_{+1/2} - F_{-1/2}) / c */
+                    const double fr = 0.5 * n * (v + hi) - 0.5 * an * epsR[d] * (hi - v);
+                    const double fl = 0.5 * n * (lo + v) - 0.5 * an * epsL[d] * (v - lo);
+                    acc -= lam[d] * (fr - fl);
                 }
                 out[(cell * G + g) * (long)A + a] = acc;
             }

@@ -76,6 +76,10 @@ def lib():
             ctypes.c_int, ip, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, ip, dp,
             ctypes.c_double, ctypes.c_double, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double]
         L.oracle_dense_transport.restype = ctypes.c_int
+        L.oracle_dense_transport_hll.argtypes = [
+            ctypes.c_int, ip, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, ip, dp,
+            ctypes.c_double, ctypes.c_double, dp, dp, ctypes.c_int, dp, ctypes.c_double]
+        L.oracle_dense_transport_hll.restype = ctypes.c_int
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -119,9 +123,16 @@ def kappa_s_field(prob) -> np.ndarray:
 
 
 def flux_params(prob):
-    """(flux, s): 0 for the upwind flux, 1 for Rusanov with s = S+ / c."""
+    """(flux, s): 0 for the upwind flux, 1 for Rusanov with s = S+ / c, 2 for
+    HLL (s unused)."""
     flux = int(getattr(prob, "flux", 0))
     return flux, float(getattr(prob, "rusanov_s", 1.0)) if flux == 1 else 0.0
+
+
+def kappa_total(prob) -> np.ndarray:
+    """(N_X, N_nu) absorption plus scattering opacity: the optical depth of the
+    HLL flux (tau_{c,f}, per cell and group)."""
+    return kappa_field(prob) + kappa_s_field(prob)
 
 
 def _plain(prob) -> bool:
@@ -183,7 +194,7 @@ def march(prob, I0: np.ndarray, n_steps: int, n_threads: int = 0, dt: float = No
 
 
 def transport(prob, I: np.ndarray, n_threads: int = 0, dt: float = None) -> np.ndarray:
-    """Transport half-step only (no source update), upwind or Rusanov flux."""
+    """Transport half-step only (no source update): upwind, Rusanov or HLL flux."""
     I = np.ascontiguousarray(I, dtype=np.float64)
     out = np.empty_like(I)
     nc = np.ascontiguousarray(np.asarray(prob.n_cells, dtype=np.int32))
@@ -193,6 +204,15 @@ def transport(prob, I: np.ndarray, n_threads: int = 0, dt: float = None) -> np.n
     mu = np.ascontiguousarray(np.asarray(prob.mu, float))
     phi = np.ascontiguousarray(np.asarray(prob.phi, float))
     flux, s_rus = flux_params(prob)
+    if flux == 2:
+        kap = np.ascontiguousarray(kappa_total(prob).reshape(-1))
+        rc = lib().oracle_dense_transport_hll(
+            prob.dim, _ip(nc), _dp(ext), prob.n_groups, prob.n_theta, prob.n_phi, _dp(mu), _dp(phi),
+            _ip(bc), _dp(ghost), float(prob.c), float(time_step(prob) if dt is None else dt), _dp(I), _dp(out),
+            int(n_threads), _dp(kap), float(getattr(prob, "hll_beta", 20.0)))
+        if rc != 0:
+            raise RuntimeError("oracle_dense_transport_hll failed")
+        return out
     rc = lib().oracle_dense_transport(
         prob.dim, _ip(nc), _dp(ext), prob.n_groups, prob.n_theta, prob.n_phi, _dp(mu), _dp(phi),
         _ip(bc), _dp(ghost), float(prob.c), float(time_step(prob) if dt is None else dt), _dp(I), _dp(out),

@@ -26,6 +26,13 @@ angular factor acting as (lambda s / 2)(O_{d+} - 2 I + O_{d-}).  In every
 case a ghost value enters the rank-1 Dirichlet term of a face through the
 coefficient its term puts on the shift that leaves the domain there.
 
+The HLL flux (Section 2.1: the asymptotic-preserving stencil, the only one
+whose multigroup form changes, through a per-group optical depth; Appendix
+A: still the upwind structure, two rank-1 operators per axis, with spatially
+varying coefficients): per axis the n_d^+ and n_d^- terms of the upwind flux
+with the spatial parts built from the interface factors eps (hll_eps) of the
+row's own group opacity, so the coefficients vary per (cell, group) row.
+
 Isotropic scattering (kappa_s, Section 2.1 source update): with
 a = c dt kappa_a, b = c dt kappa_s and J* the angle mean of the transported
 TT, the source becomes d I* plus the rank-1 isotropic column
@@ -79,13 +86,54 @@ def direction_factors(prob):
     return terms
 
 
+def hll_eps(prob, axis):
+    """Interface factors of the HLL flux along `axis` for every row k = cell
+    N_nu + g: eps = (1 - exp(-tau)) / tau with tau = beta dx (kappa_k + kappa
+    of the neighbour row) / 2 (kappa: absorption plus scattering; the row's own
+    opacity on a non-periodic boundary face).  Returns (eps_low, eps_high),
+    each of shape (M,), for the faces towards cell - e_d and cell + e_d."""
+    kap = dense.kappa_total(prob)                      # (N_X, N_nu)
+    beta = float(getattr(prob, "hll_beta", 20.0))
+    dx = prob.extent[axis] / prob.n_cells[axis]
+    idx, N = _cell_index(prob)
+    periodic = prob.bc[2 * axis] == dense.FACE_PERIODIC
+    out = []
+    for s in (-1, +1):
+        j = idx.copy()
+        j[:, axis] += s
+        inside = (j[:, axis] >= 0) & (j[:, axis] < N[axis])
+        if periodic:
+            j[:, axis] %= N[axis]
+            inside[:] = True
+        src = np.where(inside, j[:, 0] + N[0] * (j[:, 1] + N[1] * j[:, 2]), np.arange(len(idx)))
+        tau = beta * dx * 0.5 * (kap + kap[src])
+        safe = np.where(tau > 0.0, tau, 1.0)
+        out.append(np.where(tau > 0.0, -np.expm1(-safe) / safe, 1.0).reshape(-1))
+    return out[0], out[1]
+
+
 def transport_terms(prob):
     """The streaming operator's rank-1 terms as (axis, g, h, c0, cm, cp): the
     angular factors g[N_theta], h[N_phi] and the spatial part
-    c0 I + cm O_{d-} + cp O_{d+} ((O_{d-/+} Z)[cell] = Z[cell -/+ e_d])."""
+    c0 I + cm O_{d-} + cp O_{d+} ((O_{d-/+} Z)[cell] = Z[cell -/+ e_d]).
+    The coefficients are scalars, or per-row arrays (M,) for the HLL flux,
+    whose interface factors depend on the row's group opacity."""
     dt = dense.time_step(prob)
     flux, s_rus = dense.flux_params(prob)
     out = []
+    if flux == 2:
+        # HLL (Appendix A: the upwind-structured form with spatially varying
+        # coefficients): for n_d >= 0 the flux through the faces is
+        # c n_d [(1 + eps)/2 I_L + (1 - eps)/2 I_R], for n_d < 0
+        # c n_d [(1 - eps)/2 I_L + (1 + eps)/2 I_R]
+        for axis, sgn, g, h in direction_factors(prob):
+            lam = prob.c * dt / (prob.extent[axis] / prob.n_cells[axis])
+            eL, eR = hll_eps(prob, axis)
+            if sgn > 0:
+                out.append((axis, g, h, -lam * 0.5 * (eL + eR), lam * 0.5 * (1.0 + eL), -lam * 0.5 * (1.0 - eR)))
+            else:
+                out.append((axis, g, h, lam * 0.5 * (eL + eR), lam * 0.5 * (1.0 - eL), -lam * 0.5 * (1.0 + eR)))
+        return out
     if flux == 0:
         for axis, sgn, g, h in direction_factors(prob):
             lam = prob.c * dt / (prob.extent[axis] / prob.n_cells[axis])
@@ -156,8 +204,9 @@ def bc_columns(prob):
         layer = (idx[:, axis] == (N[axis] - 1 if high else 0)).astype(float)
         for ax, g, h, c0, cm, cp in transport_terms(prob):
             coef = cp if high else cm
-            if ax != axis or coef == 0.0:
+            if ax != axis or np.all(np.asarray(coef) == 0.0):
                 continue
+            coef = np.asarray(coef, float).reshape(-1, prob.n_groups) if np.ndim(coef) else coef
             z = (coef * layer[:, None] * ghost[face][None, :]).reshape(-1)
             cols.append((z, g, h))
     return cols
@@ -185,12 +234,16 @@ def _assemble(blocksZ, blocksTh, blocksPh, n_theta):
 def apply_transport(prob, Z, Th, Ph):
     """I* = (identity + sum of the n rank-1 upwind operators) I + Dirichlet terms."""
     bZ, bT, bP = [Z], [Th], [Ph]
+
+    def scaled(c, X):   # scalar or per-row coefficient times the rows of X
+        return c * X if np.ndim(c) == 0 else np.asarray(c)[:, None] * X
+
     for axis, g, h, c0, cm, cp in transport_terms(prob):
-        SZ = c0 * Z
-        if cm != 0.0:
-            SZ = SZ + cm * shift(prob, Z, axis, -1)
-        if cp != 0.0:
-            SZ = SZ + cp * shift(prob, Z, axis, +1)
+        SZ = scaled(c0, Z)
+        if np.any(np.asarray(cm) != 0.0):
+            SZ = SZ + scaled(cm, shift(prob, Z, axis, -1))
+        if np.any(np.asarray(cp) != 0.0):
+            SZ = SZ + scaled(cp, shift(prob, Z, axis, +1))
         bZ.append(SZ)
         bT.append(Th * g[None, :, None])
         bP.append(Ph * h[None, :])

@@ -73,6 +73,7 @@ class Problem:
     kappa_s_full: Optional[np.ndarray] = None  # (N_X, N_nu) isotropic scattering opacity (None: no scattering)
     flux: int = 0                # streaming flux: 0 upwind, 1 Rusanov
     rusanov_s: float = 1.0       # Rusanov wave speed S+ / c (1: S+ = c, 0: central differences)
+    hll_beta: float = 20.0       # HLL: optical-depth factor of the interface wave-speed reduction
     rand_oversample: int = 4     # randomized rounding: sketch ranks = current ranks + this
     rand_seed: int = 0           # randomized rounding: key of the counter-based generator
 
@@ -290,7 +291,7 @@ def radiation_constant(c: float = 1.0) -> float:
     return 8.0 * math.pi ** 5 / (15.0 * c)
 
 
-FLUX_UPWIND, FLUX_RUSANOV = 0, 1
+FLUX_UPWIND, FLUX_RUSANOV, FLUX_HLL = 0, 1, 2
 
 
 def gaussian_diffusion(n_cells=128, n_groups=4, n_theta=16, ks_min=1000.0, ks_max=2000.0, width=0.25,
