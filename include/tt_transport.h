@@ -109,11 +109,19 @@ typedef enum {
 
 /* Problem statement (Section 2 and 2.1; quadrature and group conventions of
  * Section 4).  Faces are ordered x-, x+, y-, y+, z-, z+. */
-/* Streaming flux (Section 2.1 names upwind, Rusanov and HLL; HLL is not
- * provided).  Rusanov: F_{i+1/2} = (c n_d / 2)(I_i + I_{i+1}) - (S+ / 2)(I_{i+1} - I_i)
+/* Streaming flux (Section 2.1 names upwind, Rusanov and HLL).
+ * Rusanov: F_{i+1/2} = (c n_d / 2)(I_i + I_{i+1}) - (S+ / 2)(I_{i+1} - I_i)
  * with S+ = rusanov_s * c; a ghost value enters both neighbours of every
- * direction on an inflow face. */
-typedef enum { TT_FLUX_UPWIND = 0, TT_FLUX_RUSANOV = 1 } tt_flux;
+ * direction on an inflow face.
+ * HLL (the asymptotic-preserving flux; its only multigroup change is a
+ * per-group optical depth): F_{i+1/2} = (c n_d / 2)(I_i + I_{i+1})
+ * - (c |n_d| eps / 2)(I_{i+1} - I_i) with eps = (1 - exp(-tau)) / tau and
+ * tau = hll_beta dx_d (kappa_i + kappa_{i+1}) / 2 in the group (the inside
+ * cell's on a boundary face): upwind in thin cells, central differences in
+ * thick ones.  Still two rank-1 operators per axis, whose spatial parts vary
+ * per (cell, group) row (Appendix A).  Provided for FP64 data without
+ * scattering or a coupled temperature. */
+typedef enum { TT_FLUX_UPWIND = 0, TT_FLUX_RUSANOV = 1, TT_FLUX_HLL = 2 } tt_flux;
 
 typedef struct tt_problem {
     int dim;                        /* 1, 2 or 3                                    */
@@ -187,6 +195,9 @@ typedef struct tt_problem {
                                        uses 4); ignored by the other methods        */
     unsigned long long rand_seed;   /* TT_ROUND_RAND: generator key; the same key
                                        reproduces a solve bit for bit              */
+    double hll_beta;                /* TT_FLUX_HLL: optical-depth factor beta of the
+                                       interface wave-speed reduction (> 0; the
+                                       paper's HLL runs use 20)                      */
 } tt_problem;
 
 /* Statistics of the last solve / round (Section 3.2 metrics). */

@@ -22,7 +22,7 @@ TT_OK, TT_ERR_INVALID_ARG, TT_ERR_OOM, TT_ERR_NUMERIC, TT_ERR_HIP, TT_ERR_STATE 
 TT_PREC_FP64, TT_PREC_FP32, TT_PREC_BF16X = 0, 1, 2
 TT_ROUND_QR, TT_ROUND_GRAM, TT_ROUND_AUTO, TT_ROUND_RAND = 0, 1, 2, 3
 TT_BC_VACUUM, TT_BC_INFLOW_PLANCK, TT_BC_PERIODIC, TT_BC_INFLOW_VALUES = 0, 1, 2, 3
-TT_FLUX_UPWIND, TT_FLUX_RUSANOV = 0, 1
+TT_FLUX_UPWIND, TT_FLUX_RUSANOV, TT_FLUX_HLL = 0, 1, 2
 
 KERNEL_CLASSES = ("prep", "project", "factor", "tree", "svd", "output", "diag", "couple")
 
@@ -63,6 +63,7 @@ class TTProblem(ctypes.Structure):
         ("kappa_s_full", _dp),
         ("rand_oversample", ctypes.c_int),
         ("rand_seed", ctypes.c_ulonglong),
+        ("hll_beta", ctypes.c_double),
     ]
 
 
@@ -241,6 +242,7 @@ class ProblemStruct:
         s.kappa_s_full = ptr(None if ks is None else np.asarray(ks, float).reshape(-1))
         s.rand_oversample = int(getattr(prob, "rand_oversample", 4))
         s.rand_seed = int(getattr(prob, "rand_seed", 0))
+        s.hll_beta = float(getattr(prob, "hll_beta", 20.0))
         self.s = s
 
 

@@ -31,6 +31,34 @@ __device__ inline double row_kappa_tot(const Geom& g, const RowData& rd, long lo
     return rd.kscat ? ka + rd.kscat[k] : ka;
 }
 
+// HLL flux: interface factor eps = (1 - exp(-tau)) / tau (1 at tau = 0) of
+// the face of row k towards its neighbour along axis d in direction s, with
+// tau = beta dx_d (kappa_k + kappa_neighbour) / 2 (total opacities of the
+// row's group; the row's own on a non-periodic boundary face).
+__device__ inline double hll_eps_of(double tau) { return tau > 0.0 ? -expm1(-tau) / tau : 1.0; }
+
+__device__ inline double hll_face_eps(const Geom& g, const RowData& rd, long long k, int d, int s) {
+    const double k0 = row_kappa_tot(g, rd, k);
+    const long long nb = neighbour_row(g, k, d, s);
+    const double kn = nb >= 0 ? row_kappa_tot(g, rd, nb) : k0;
+    return hll_eps_of(g.hbeta * g.dx[d] * 0.5 * (k0 + kn));
+}
+
+// Per-row weight of HLL weight kind w (1..6: centre, minus and plus
+// coefficients of the n^+ term, then of the n^- term) from the row's face
+// factors eL (towards cell - e_d) and eR along the block's axis with lam_d.
+__device__ inline double hll_weight(int w, double eL, double eR, double lam) {
+    switch (w) {
+        case 1: return -0.5 * lam * (eL + eR);
+        case 2: return 0.5 * lam * (1.0 + eL);
+        case 3: return -0.5 * lam * (1.0 - eR);
+        case 4: return 0.5 * lam * (eL + eR);
+        case 5: return 0.5 * lam * (1.0 - eL);
+        case 6: return -0.5 * lam * (1.0 + eR);
+        default: return 1.0;
+    }
+}
+
 // Value in row k of rank-1 column q of the operator (before the d scaling):
 // the isotropic source c dt (kappa eps + kappa_s J^{m+1}), or an inflow column.
 __device__ inline double rank1_value(const Geom& g, const OpDesc& op, const RowData& rd, long long k, int q) {
@@ -45,7 +73,12 @@ __device__ inline double rank1_value(const Geom& g, const OpDesc& op, const RowD
     if (idx != (high ? n - 1 : 0)) return 0.0;
     const long long cell = k / g.G;
     const int grp = (int)(k - cell * g.G);
-    return op.r1coef[q] * rd.ghost[face * g.G + grp];
+    double coef = op.r1coef[q];
+    if (op.r1kind[q] == 2) {   // HLL inflow: the face's factor, the inside cell's opacity
+        const double e = hll_face_eps(g, rd, k, axis, high ? 1 : -1);
+        coef *= op.r1hll[q] == 1 ? 0.5 * (1.0 + e) : 0.5 * (1.0 - e);
+    }
+    return coef * rd.ghost[face * g.G + grp];
 }
 
 __device__ inline double row_scale(const Geom& g, const OpDesc& op, const RowData& rd, long long k) {
@@ -365,7 +398,21 @@ __global__ void k_materialize(Geom g, OpDesc op, const DevState* __restrict__ st
         const int col = (int)(idx % R1);
         const long long k = k0 + kk;
         double v;
-        if (col < op.n_rblk * r1) {
+        if (col < op.n_rblk * r1 && op.hll) {
+            // HLL: the r-block's gather blocks, each with its per-row weight
+            const int t = col / r1, a = col % r1;
+            v = 0.0;
+            for (int j = 0; j < op.n_gather; ++j) {
+                if (op.gterm[j] != t) continue;
+                const int ax = op.gaxis[j];
+                const long long s = op.gdir[j] == 0 ? k : neighbour_row(g, k, ax, op.gdir[j]);
+                if (s < 0) continue;
+                const double w = op.gwk[j] == 0 ? 1.0
+                                                : hll_weight(op.gwk[j], hll_face_eps(g, rd, k, ax, -1),
+                                                             hll_face_eps(g, rd, k, ax, 1), g.lam[ax]);
+                v += w * (double)Z[s * ldz + a];
+            }
+        } else if (col < op.n_rblk * r1) {
             const int t = col / r1, a = col % r1;
             v = op.rcoef0[t] * (double)Z[k * ldz + a];
             if (op.rshift2[t] >= 0) {

@@ -43,12 +43,19 @@ constexpr int kF64Z = kMaxBC + 4;          // rank-1 value rows (read four at a 
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
-// Dynamic LDS bytes of k_mm_f64<.., NCT, GRAM>: two operand buffers and the
-// row data (the Gram reduction at the end reuses the space).
-__host__ __device__ inline size_t f64_lds_bytes(int nct, bool gram) {
+// Gather blocks whose rows the row data holds: the identity and the shifted
+// copies (upwind, Rusanov), or up to kMaxBlocks with the HLL flux's
+// per-(term, shift) blocks.
+__host__ __device__ constexpr int f64_nbr_rows(bool hll) { return hll ? kMaxBlocks : kMaxTerms + 1; }
+
+// Dynamic LDS bytes of k_mm_f64<.., NCT, GRAM, RT, HLL>: two operand buffers
+// and the row data of 128 RT rows (the Gram reduction at the end reuses the
+// space).
+__host__ __device__ inline size_t f64_lds_bytes(int nct, bool gram, int rt, bool hll = false) {
+    const size_t nrow = (size_t)16 * rt * kF64Waves;
     const size_t op = (size_t)2 * 16 * nct * kF64LdK * sizeof(double);
-    const size_t rows = (size_t)kF64Rows * (sizeof(double) + (kMaxTerms + 1) * sizeof(int)) +
-                        (size_t)kF64Z * kF64Rows * sizeof(double);
+    const size_t rows = nrow * (sizeof(double) + f64_nbr_rows(hll) * sizeof(int)) +
+                        (size_t)kF64Z * nrow * sizeof(double) + (hll ? (size_t)kMaxBlocks * nrow * sizeof(double) : 0);
     const size_t main = op + rows;
     const size_t red = gram ? (size_t)(kF64Waves / 2) * gram_blocks(nct) * 256 * sizeof(double) : 0;
     return main > red ? main : red;
@@ -65,7 +72,7 @@ __device__ __forceinline__ int divmod_d(int x, int d, double rcp, int& rem) {
     return q;
 }
 
-template <int MODE, int NCT, bool GRAM, int RT>
+template <int MODE, int NCT, bool GRAM, int RT, bool HLL = false>
 __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const DevState* __restrict__ st,
                                                          const double* __restrict__ A,
                                                          const double* __restrict__ Gop, double* __restrict__ Out,
@@ -76,11 +83,13 @@ __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const
     extern __shared__ __align__(16) unsigned char f64_lds[];
     // the operator's per-block tables (dynamically indexed: kept out of SGPRs)
     __shared__ int s_gax[kMaxBlocks], s_gdir[kMaxBlocks], s_r1kind[kMaxBlocks], s_r1face[kMaxBlocks];
+    __shared__ int s_gwk[kMaxBlocks], s_r1hll[kMaxBlocks];
     __shared__ double s_r1coef[kMaxBlocks];
     double* Bs0 = reinterpret_cast<double*>(f64_lds);                         // 2 x [NP][kF64LdK]
     double* rowd = Bs0 + (size_t)2 * NP * kF64LdK;                             // [rows]
     double* rowz = rowd + ROWS;                                            // [kF64Z][rows]
-    int* nbr = reinterpret_cast<int*>(rowz + (size_t)kF64Z * ROWS);        // [1 + terms][rows]
+    double* rowc = rowz + (size_t)kF64Z * ROWS;                            // HLL: [blocks][rows] weights
+    int* nbr = reinterpret_cast<int*>(rowc + (HLL ? (size_t)kMaxBlocks * ROWS : 0));   // [blocks][rows]
 
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int m = l & 15, q = l >> 4;
@@ -90,6 +99,8 @@ __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const
         s_r1kind[tid] = op.r1kind[tid];
         s_r1face[tid] = op.r1face[tid];
         s_r1coef[tid] = op.r1coef[tid];
+        s_gwk[tid] = op.gwk[tid];
+        s_r1hll[tid] = op.r1hll[tid];
     }
     int lda, K, KG, ldo, nblk, kper, ldg;
     if (MODE == MODE_PROJECT) {
@@ -146,6 +157,7 @@ __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const
     // this lane's A fragments of chunk kc: two 16-K groups x RT row tiles,
     // four consecutive K values each
     f64x2 ra[2][RT][2];
+    double rw[2][RT];   // HLL: the per-row weight of the fragment's gather block
     auto fetch_a = [&](int kc) __attribute__((always_inline)) {
 #pragma unroll
         for (int gi = 0; gi < 2; ++gi)
@@ -154,9 +166,11 @@ __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const
                 const int r = 16 * RT * w + 16 * rt + m;
                 const int k = kc * kF64KC + 16 * gi + 4 * q;
                 f64x2 v0 = (f64x2){0.0, 0.0}, v1 = v0;
+                if constexpr (HLL) rw[gi][rt] = 1.0;
                 if (k < KG) {
                     const int j = dkp.q(k), cc = k - j * kper;
                     const int src = nbr[j * ROWS + r];
+                    if constexpr (HLL) rw[gi][rt] = rowc[j * ROWS + r];
                     if (src >= 0) {
                         const double* ap = A + (long long)src * lda + cc;
                         v0 = *reinterpret_cast<const f64x2*>(ap);
@@ -186,6 +200,15 @@ __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const
             iz = divmod_d(iy, g.ny, rny, iy);
             const int idx3[3] = {ix, iy, iz}, n3[3] = {g.nx, g.ny, g.nz};
             const int st3[3] = {g.G, g.G * g.nx, g.G * g.nx * g.ny};
+            // HLL: the row's face factors along each axis (towards cell -/+ e_d)
+            double eL[3] = {1.0, 1.0, 1.0}, eR[3] = {1.0, 1.0, 1.0};
+            if constexpr (HLL) {
+                if (ok)
+                    for (int ax = 0; ax < g.dim; ++ax) {
+                        eL[ax] = hll_face_eps(g, rd, k, ax, -1);
+                        eR[ax] = hll_face_eps(g, rd, k, ax, 1);
+                    }
+            }
             for (int j = 0; j < nblk; ++j) {
                 int src = ok ? (int)k : -1;
                 if (MODE == MODE_PROJECT && j > 0 && ok) {
@@ -199,6 +222,10 @@ __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const
                     }
                 }
                 nbr[j * ROWS + tid] = src;
+                if constexpr (HLL) {
+                    const int ax = s_gax[j];
+                    rowc[j * ROWS + tid] = s_gwk[j] == 0 ? 1.0 : hll_weight(s_gwk[j], eL[ax], eR[ax], g.lam[ax]);
+                }
             }
             if (MODE == MODE_PROJECT) {
                 double kap = 0.0;
@@ -214,7 +241,12 @@ __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const
                         } else {
                             const int face = s_r1face[qq], ax = face >> 1;
                             const int edge = (face & 1) ? n3[ax] - 1 : 0;
-                            if (idx3[ax] == edge) v = s_r1coef[qq] * rd.ghost[face * g.G + grp];
+                            double coef = s_r1coef[qq];
+                            if (s_r1kind[qq] == 2) {   // HLL inflow column: the face's factor
+                                const double e = (face & 1) ? eR[ax] : eL[ax];
+                                coef *= s_r1hll[qq] == 1 ? 0.5 * (1.0 + e) : 0.5 * (1.0 - e);
+                            }
+                            if (idx3[ax] == edge) v = coef * rd.ghost[face * g.G + grp];
                         }
                     }
                     rowz[qq * ROWS + tid] = v;
@@ -240,8 +272,13 @@ __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const
             for (int gi = 0; gi < 2; ++gi)
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt) {
-                    a[gi][rt][0] = ra[gi][rt][0];
-                    a[gi][rt][1] = ra[gi][rt][1];
+                    if constexpr (HLL) {
+                        a[gi][rt][0] = ra[gi][rt][0] * rw[gi][rt];
+                        a[gi][rt][1] = ra[gi][rt][1] * rw[gi][rt];
+                    } else {
+                        a[gi][rt][0] = ra[gi][rt][0];
+                        a[gi][rt][1] = ra[gi][rt][1];
+                    }
                 }
             const bool more = kc + 1 < n_kc;
             if (more) {   // in flight while this chunk computes

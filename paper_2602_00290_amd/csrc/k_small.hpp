@@ -31,6 +31,15 @@ struct OpDesc {
     int r1face[kMaxBlocks];
     double r1coef[kMaxBlocks];  // inflow column: value r1coef * ghost on the face's cell layer
     int scale_d;                // rows scaled by d = 1/(1 + c dt kappa)
+    // HLL flux: every gather block belongs to one r-block (gterm) with unit
+    // coefficient and carries a per-row weight of kind gwk (0: 1; 1..6: the
+    // centre / minus / plus coefficient of the n^+ (1..3) or n^- (4..6) term,
+    // built from the row's interface factors); inflow columns of kind 2 take
+    // (1 + eps) / 2 (r1hll 1) or (1 - eps) / 2 (r1hll 2) of the face's factor
+    int hll;
+    int gterm[kMaxBlocks];
+    int gwk[kMaxBlocks];
+    int r1hll[kMaxBlocks];
 };
 
 // Global fallbacks and persistent small buffers of the rounding.
@@ -796,6 +805,7 @@ __device__ __forceinline__ void prep_body(const Geom& g, const OpDesc& op, DevSt
     // a per-lane index into the kernel arguments is a vector memory load
     __shared__ int s_rfac[kMaxBlocks], s_rshift[kMaxBlocks], s_rshift2[kMaxBlocks], s_r1fac[kMaxBlocks];
     __shared__ double s_rcoef0[kMaxBlocks], s_rcoef[kMaxBlocks], s_rcoef2[kMaxBlocks];
+    __shared__ int s_gterm[kMaxBlocks];
     if (threadIdx.x == 0) {
         for (int i = 0; i < kMaxBlocks; ++i) {
             s_rfac[i] = op.rfac[i];
@@ -805,6 +815,7 @@ __device__ __forceinline__ void prep_body(const Geom& g, const OpDesc& op, DevSt
             s_rcoef[i] = op.rcoef[i];
             s_rshift2[i] = op.rshift2[i];
             s_rcoef2[i] = op.rcoef2[i];
+            s_gterm[i] = op.gterm[i];
         }
     }
     // the angular core and the per-node factor tables in LDS where they fit
@@ -930,11 +941,16 @@ __device__ __forceinline__ void prep_body(const Geom& g, const OpDesc& op, DevSt
             if (row < op.n_gather * ldz) {
                 const int j = dldz.q(row), a = row - j * ldz;
                 if (a < r1) {
-                    for (int t = 0; t < nrb; ++t) {
-                        const double l = LT[(size_t)(t * r1 + a) * ldL + col];
-                        if (j == 0) v += s_rcoef0[t] * l;
-                        if (s_rshift[t] == j) v += s_rcoef[t] * l;
-                        if (s_rshift2[t] == j) v += s_rcoef2[t] * l;
+                    if (op.hll) {
+                        // HLL: block j is its r-block's shifted copy with a per-row weight
+                        v = LT[(size_t)(s_gterm[j] * r1 + a) * ldL + col];
+                    } else {
+                        for (int t = 0; t < nrb; ++t) {
+                            const double l = LT[(size_t)(t * r1 + a) * ldL + col];
+                            if (j == 0) v += s_rcoef0[t] * l;
+                            if (s_rshift[t] == j) v += s_rcoef[t] * l;
+                            if (s_rshift2[t] == j) v += s_rcoef2[t] * l;
+                        }
                     }
                 }
             } else {

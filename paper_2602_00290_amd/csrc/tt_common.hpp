@@ -59,6 +59,8 @@ struct Geom {
     int periodic[3];   // per axis
     double lam[3];     // c dt / dx_d
     double cdt;        // c * dt
+    double dx[3];      // cell widths
+    double hbeta;      // HLL flux: optical-depth factor of the interface wave-speed reduction
     int bc_face[kMaxBC];   // face index of each inflow column
 };
 

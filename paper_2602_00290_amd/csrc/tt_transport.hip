@@ -166,7 +166,16 @@ tt_status validate(const tt_problem* p) {
         return fail(TT_ERR_INVALID_ARG, "heat_capacity must be finite and >= 0");
     if (p->heat_capacity > 0.0 && p->paper_step_order != 0)
         return fail(TT_ERR_INVALID_ARG, "the coupled medium temperature needs paper_step_order == 0");
-    if (p->flux != TT_FLUX_UPWIND && p->flux != TT_FLUX_RUSANOV) return fail(TT_ERR_INVALID_ARG, "unknown flux");
+    if (p->flux != TT_FLUX_UPWIND && p->flux != TT_FLUX_RUSANOV && p->flux != TT_FLUX_HLL)
+        return fail(TT_ERR_INVALID_ARG, "unknown flux");
+    if (p->flux == TT_FLUX_HLL) {
+        if (!(p->hll_beta > 0.0) || !std::isfinite(p->hll_beta))
+            return fail(TT_ERR_INVALID_ARG, "hll_beta must be finite and > 0");
+        if (p->precision != TT_PREC_FP64)
+            return fail(TT_ERR_INVALID_ARG, "the HLL flux needs FP64 data (TT_PREC_FP64) in this build");
+        if (p->kappa_s_full || p->heat_capacity > 0.0)
+            return fail(TT_ERR_INVALID_ARG, "the HLL flux is provided without scattering or a coupled temperature");
+    }
     if (p->flux == TT_FLUX_RUSANOV && !(p->rusanov_s >= 0.0 && p->rusanov_s <= 1.0))
         return fail(TT_ERR_INVALID_ARG, "rusanov_s must lie in [0, 1]");
     if (p->kappa_s_full && p->paper_step_order != 0)
@@ -190,7 +199,7 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
     P.flux = p->flux;
     P.rus_s = p->flux == TT_FLUX_RUSANOV ? p->rusanov_s : 0.0;
     // inflow columns: one per inflow face; the Rusanov dissipation adds a second
-    const int per_face = (P.flux == TT_FLUX_RUSANOV && P.rus_s != 0.0) ? 2 : 1;
+    const int per_face = ((P.flux == TT_FLUX_RUSANOV && P.rus_s != 0.0) || P.flux == TT_FLUX_HLL) ? 2 : 1;
     P.n_bc = 0;
     for (int f = 0; f < 2 * p->dim; ++f) P.n_bc += is_inflow(p->bc[f]) ? per_face : 0;
     P.cap = p->rank_cap;
@@ -199,7 +208,8 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
     P.r2cap = std::min(P.cap, P.np);
     const int nrb = 1 + P.n_terms;
     P.n_r1_max = P.n_bc + 1;
-    P.n_gather_max = 1 + P.n_terms;
+    // HLL: one gather block per (term, shift): the centre and both neighbours
+    P.n_gather_max = P.flux == TT_FLUX_HLL ? 1 + 3 * P.n_terms : 1 + P.n_terms;
     P.R1cap = nrb * P.r1cap + P.n_r1_max;
     P.R2cap = nrb * P.r2cap + P.n_r1_max;
     P.k2cap = std::min(P.R2cap, P.np);
@@ -409,6 +419,8 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         P.o_wph = take((size_t)P.np * d);
     }
     P.bytes = off;
+    if (P.flux == TT_FLUX_HLL && !P.f64mm)
+        return fail(TT_ERR_INVALID_ARG, "the HLL flux needs the FP64 MFMA contractions (projected rank <= 128, rank cap <= 64)");
     // element offsets of the rank-1 blocks from Z must fit 32 bits
     // the fused kernels address Z, the rank-1 blocks and the zero region with
     // 32-bit byte offsets from the current Z
@@ -550,7 +562,43 @@ void build_ops(tt_handle* h, const tt_problem* p) {
         const bool stream = kind == OP_FULL || kind == OP_TRANSPORT;
         const bool source = kind == OP_FULL || kind == OP_SOURCE;
         for (int i = 0; i < kMaxBlocks; ++i) o.rshift2[i] = -1;
-        if (stream && P.flux == TT_FLUX_RUSANOV) {
+        if (stream && P.flux == TT_FLUX_HLL) {
+            // HLL (Appendix A: the upwind structure with spatially varying
+            // coefficients): per axis the n^+ and n^- terms, each with gather
+            // blocks for the centre and both neighbours carrying per-row weights
+            o.hll = 1;
+            o.gterm[0] = 0;
+            o.gwk[0] = 0;
+            for (int axis = 0; axis < P.dim; ++axis) {
+                for (int sign = 1; sign >= -1; sign -= 2) {
+                    const int t = o.n_rblk++;
+                    o.rfac[t] = term_index(axis, sign);
+                    o.rcoef0[t] = 0.0;
+                    for (int kind = 0; kind < 3; ++kind) {
+                        const int j = o.n_gather++;
+                        o.gaxis[j] = axis;
+                        o.gdir[j] = kind == 0 ? 0 : (kind == 1 ? -1 : 1);
+                        o.gterm[j] = t;
+                        o.gwk[j] = 1 + (sign > 0 ? 0 : 3) + kind;
+                    }
+                }
+            }
+            // an inflow ghost enters both terms of its axis through the shift
+            // that leaves the domain: (1 +- eps) / 2 of the face's factor
+            for (int f = 0; f < 2 * P.dim; ++f) {
+                if (!is_inflow(p->bc[f])) continue;
+                const int axis = f / 2, high = f & 1;
+                const double lam = h->geom.lam[axis];
+                for (int sign = 1; sign >= -1; sign -= 2) {
+                    const int q = o.n_r1++;
+                    o.r1kind[q] = 2;
+                    o.r1face[q] = f;
+                    o.r1fac[q] = term_index(axis, sign);
+                    o.r1coef[q] = high ? -lam : lam;
+                    o.r1hll[q] = high ? (sign > 0 ? 2 : 1) : (sign > 0 ? 1 : 2);
+                }
+            }
+        } else if (stream && P.flux == TT_FLUX_RUSANOV) {
             // per axis: (n_d) (-(lambda / 2)) (O_{d+} - O_{d-}) and, when S+ > 0,
             // (1) (lambda s / 2) (O_{d+} - 2 I + O_{d-}); gather blocks c - e_d, c + e_d
             const double sr = P.rus_s;
@@ -781,9 +829,14 @@ void launch_mm_f64(tt_handle* h, const OpDesc& op, const double* A, const double
     const Plan& P = h->P;
     // one row tile per wave where two would spill: 128 columns, or 64 with the fused Gram
     constexpr int RT = (NCT == 8 || (NCT == 4 && GRAM)) ? 1 : 2;
-    hipLaunchKernelGGL((k_mm_f64<MODE, NCT, GRAM, RT>), dim3(P.f64_blocks), dim3(kF64Threads),
-                       f64_lds_bytes(NCT, GRAM), s, h->geom, op, (const DevState*)h->st(), A, Gop, Out, h->rowdata(),
-                       parts);
+    if (MODE == MODE_PROJECT && op.hll)
+        hipLaunchKernelGGL((k_mm_f64<MODE, NCT, GRAM, RT, true>), dim3(P.f64_blocks), dim3(kF64Threads),
+                           f64_lds_bytes(NCT, GRAM, RT, true), s, h->geom, op, (const DevState*)h->st(), A, Gop, Out,
+                           h->rowdata(), parts);
+    else
+        hipLaunchKernelGGL((k_mm_f64<MODE, NCT, GRAM, RT>), dim3(P.f64_blocks), dim3(kF64Threads),
+                           f64_lds_bytes(NCT, GRAM, RT), s, h->geom, op, (const DevState*)h->st(), A, Gop, Out,
+                           h->rowdata(), parts);
 }
 
 void project_f64(tt_handle* h, const OpDesc& op, bool gram, double* parts, hipStream_t s) {
@@ -1341,6 +1394,7 @@ std::string small_ineligible(const tt_handle* h) {
     if (P.KPt != 16) return "a projected first core of at most 16 columns only";
     if (h->step_order != 0) return "one rounding per step only";
     if (P.prepass) return "no coupled temperature or scattering";
+    if (P.flux == TT_FLUX_HLL) return "the upwind or Rusanov flux only";
     if (!P.svd_fast) return "the SVD chain's fixed LDS layout is needed";
     if (h->pending != OP_NONE) return "an unrounded operator is pending";
     if (h->timing) return "per-kernel timing is on";
@@ -1480,16 +1534,23 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
             HIP_TRY(hipFuncSetAttribute((const void*)k_fused_f32<4, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
             // the FP64 MFMA kernels: their own dynamic LDS (they also hold a little static LDS)
             const std::pair<const void*, size_t> f64k[] = {
-                {(const void*)k_mm_f64<MODE_PROJECT, 1, false, 2>, f64_lds_bytes(1, false)},
-                {(const void*)k_mm_f64<MODE_PROJECT, 1, true, 2>, f64_lds_bytes(1, true)},
-                {(const void*)k_mm_f64<MODE_PROJECT, 2, false, 2>, f64_lds_bytes(2, false)},
-                {(const void*)k_mm_f64<MODE_PROJECT, 2, true, 2>, f64_lds_bytes(2, true)},
-                {(const void*)k_mm_f64<MODE_PROJECT, 4, false, 2>, f64_lds_bytes(4, false)},
-                {(const void*)k_mm_f64<MODE_PROJECT, 4, true, 1>, f64_lds_bytes(4, true)},
-                {(const void*)k_mm_f64<MODE_PROJECT, 8, false, 1>, f64_lds_bytes(8, false)},
-                {(const void*)k_mm_f64<MODE_OUTPUT, 1, false, 2>, f64_lds_bytes(1, false)},
-                {(const void*)k_mm_f64<MODE_OUTPUT, 2, false, 2>, f64_lds_bytes(2, false)},
-                {(const void*)k_mm_f64<MODE_OUTPUT, 4, false, 2>, f64_lds_bytes(4, false)}};
+                {(const void*)k_mm_f64<MODE_PROJECT, 1, false, 2>, f64_lds_bytes(1, false, 2)},
+                {(const void*)k_mm_f64<MODE_PROJECT, 1, true, 2>, f64_lds_bytes(1, true, 2)},
+                {(const void*)k_mm_f64<MODE_PROJECT, 2, false, 2>, f64_lds_bytes(2, false, 2)},
+                {(const void*)k_mm_f64<MODE_PROJECT, 2, true, 2>, f64_lds_bytes(2, true, 2)},
+                {(const void*)k_mm_f64<MODE_PROJECT, 4, false, 2>, f64_lds_bytes(4, false, 2)},
+                {(const void*)k_mm_f64<MODE_PROJECT, 4, true, 1>, f64_lds_bytes(4, true, 1)},
+                {(const void*)k_mm_f64<MODE_PROJECT, 8, false, 1>, f64_lds_bytes(8, false, 1)},
+                {(const void*)k_mm_f64<MODE_OUTPUT, 1, false, 2>, f64_lds_bytes(1, false, 2)},
+                {(const void*)k_mm_f64<MODE_OUTPUT, 2, false, 2>, f64_lds_bytes(2, false, 2)},
+                {(const void*)k_mm_f64<MODE_OUTPUT, 4, false, 2>, f64_lds_bytes(4, false, 2)},
+                {(const void*)k_mm_f64<MODE_PROJECT, 1, false, 2, true>, f64_lds_bytes(1, false, 2, true)},
+                {(const void*)k_mm_f64<MODE_PROJECT, 1, true, 2, true>, f64_lds_bytes(1, true, 2, true)},
+                {(const void*)k_mm_f64<MODE_PROJECT, 2, false, 2, true>, f64_lds_bytes(2, false, 2, true)},
+                {(const void*)k_mm_f64<MODE_PROJECT, 2, true, 2, true>, f64_lds_bytes(2, true, 2, true)},
+                {(const void*)k_mm_f64<MODE_PROJECT, 4, false, 2, true>, f64_lds_bytes(4, false, 2, true)},
+                {(const void*)k_mm_f64<MODE_PROJECT, 4, true, 1, true>, f64_lds_bytes(4, true, 1, true)},
+                {(const void*)k_mm_f64<MODE_PROJECT, 8, false, 1, true>, f64_lds_bytes(8, false, 1, true)}};
             for (const auto& fk : f64k)
                 HIP_TRY(hipFuncSetAttribute(fk.first, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fk.second));
             attrs_set = true;
@@ -1524,7 +1585,9 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
     for (int d = 0; d < 3; ++d) {
         g.periodic[d] = (d < P.dim && p->bc[2 * d] == TT_BC_PERIODIC) ? 1 : 0;
         g.lam[d] = d < P.dim ? p->c * h->dt / (p->extent[d] / p->n_cells[d]) : 0.0;
+        g.dx[d] = d < P.dim ? p->extent[d] / p->n_cells[d] : 1.0;
     }
+    g.hbeta = p->flux == TT_FLUX_HLL ? p->hll_beta : 0.0;
     {
         int q = 0;
         for (int f = 0; f < 2 * P.dim; ++f)

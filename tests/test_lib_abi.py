@@ -132,9 +132,15 @@ def test_flux_and_scattering_validation(tt):
             tt.workspace_bytes(bad)
         assert e.value.status == tt.TT_ERR_INVALID_ARG
     assert tt.workspace_bytes(p.copy(round_method=ti.ROUND_GRAM, rand_oversample=0)) > 0
-    for bad in (p.copy(flux=2), p.copy(flux=ti.FLUX_RUSANOV, rusanov_s=1.5),
+    # HLL: FP64 data without scattering or a coupled temperature, beta > 0
+    assert tt.workspace_bytes(p.copy(flux=ti.FLUX_HLL, precision=ti.PREC_FP64)) > 0
+    for bad in (p.copy(flux=3), p.copy(flux=ti.FLUX_RUSANOV, rusanov_s=1.5),
                 p.copy(flux=ti.FLUX_RUSANOV, rusanov_s=float("nan")),
-                p.copy(kappa_s_full=ks, step_order=1)):
+                p.copy(kappa_s_full=ks, step_order=1),
+                p.copy(flux=ti.FLUX_HLL, precision=ti.PREC_FP32),
+                p.copy(flux=ti.FLUX_HLL, precision=ti.PREC_FP64, kappa_s_full=ks),
+                p.copy(flux=ti.FLUX_HLL, precision=ti.PREC_FP64, hll_beta=0.0),
+                p.copy(flux=ti.FLUX_HLL, precision=ti.PREC_FP64, hll_beta=float("inf"))):
         with pytest.raises(tt.TTError) as e:
             tt.workspace_bytes(bad)
         assert e.value.status == tt.TT_ERR_INVALID_ARG
