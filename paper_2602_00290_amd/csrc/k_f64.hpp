@@ -154,37 +154,36 @@ __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const
             }
         }
     };
-    // this lane's A fragments of chunk kc: two 16-K groups x RT row tiles,
-    // four consecutive K values each
-    f64x2 ra[2][RT][2];
-    double rw[2][RT];   // HLL: the per-row weight of the fragment's gather block
-    auto fetch_a = [&](int kc) __attribute__((always_inline)) {
+    // this lane's A fragments of one 16-K group (flat index t = 2 kc + gi):
+    // RT row tiles, four consecutive K values each; loaded one group ahead
+    f64x2 ra[RT][2];
+    double rw[RT];   // HLL: the per-row weight of the fragment's gather block
+    auto fetch_a = [&](int t) __attribute__((always_inline)) {
 #pragma unroll
-        for (int gi = 0; gi < 2; ++gi)
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-                const int r = 16 * RT * w + 16 * rt + m;
-                const int k = kc * kF64KC + 16 * gi + 4 * q;
-                f64x2 v0 = (f64x2){0.0, 0.0}, v1 = v0;
-                if constexpr (HLL) rw[gi][rt] = 1.0;
-                if (k < KG) {
-                    const int j = dkp.q(k), cc = k - j * kper;
-                    const int src = nbr[j * ROWS + r];
-                    if constexpr (HLL) rw[gi][rt] = rowc[j * ROWS + r];
-                    if (src >= 0) {
-                        const double* ap = A + (long long)src * lda + cc;
-                        v0 = *reinterpret_cast<const f64x2*>(ap);
-                        v1 = *reinterpret_cast<const f64x2*>(ap + 2);
-                    }
-                } else if (MODE == MODE_PROJECT && k < K) {
-                    const int qq = k - KG;
-                    v0 = (f64x2){rowz[qq * ROWS + r], rowz[(qq + 1) * ROWS + r]};
-                    v1 = (f64x2){rowz[(qq + 2) * ROWS + r], rowz[(qq + 3) * ROWS + r]};
+        for (int rt = 0; rt < RT; ++rt) {
+            const int r = 16 * RT * w + 16 * rt + m;
+            const int k = 16 * t + 4 * q;
+            f64x2 v0 = (f64x2){0.0, 0.0}, v1 = v0;
+            if constexpr (HLL) rw[rt] = 1.0;
+            if (k < KG) {
+                const int j = dkp.q(k), cc = k - j * kper;
+                const int src = nbr[j * ROWS + r];
+                if constexpr (HLL) rw[rt] = rowc[j * ROWS + r];
+                if (src >= 0) {
+                    const double* ap = A + (long long)src * lda + cc;
+                    v0 = *reinterpret_cast<const f64x2*>(ap);
+                    v1 = *reinterpret_cast<const f64x2*>(ap + 2);
                 }
-                ra[gi][rt][0] = v0;
-                ra[gi][rt][1] = v1;
+            } else if (MODE == MODE_PROJECT && k < K) {
+                const int qq = k - KG;
+                v0 = (f64x2){rowz[qq * ROWS + r], rowz[(qq + 1) * ROWS + r]};
+                v1 = (f64x2){rowz[(qq + 2) * ROWS + r], rowz[(qq + 3) * ROWS + r]};
             }
+            ra[rt][0] = v0;
+            ra[rt][1] = v1;
+        }
     };
+    const int n_grp = (K + 15) >> 4;   // 16-K groups with data (the last chunk may hold one)
 
     for (long long rb = rb_begin; rb < rb_end; ++rb) {
         const long long row0 = rb * ROWS;
@@ -267,26 +266,24 @@ __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const
         for (int kc = 0; kc < n_kc; ++kc) {
             __syncthreads();   // chunk kc is in buffer kc & 1; the other buffer's readers are done
             const double* Bs = Bs0 + (size_t)(kc & 1) * NP * kF64LdK;
-            f64x2 a[2][RT][2];
+            const bool more = kc + 1 < n_kc;
+            if (more) fetch_op(kc + 1);   // in flight while this chunk computes
 #pragma unroll
-            for (int gi = 0; gi < 2; ++gi)
+            for (int gi = 0; gi < 2; ++gi) {
+                const int t = 2 * kc + gi;
+                if (t >= n_grp) break;    // an all-zero padding group (uniform)
+                f64x2 a[RT][2];
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt) {
                     if constexpr (HLL) {
-                        a[gi][rt][0] = ra[gi][rt][0] * rw[gi][rt];
-                        a[gi][rt][1] = ra[gi][rt][1] * rw[gi][rt];
+                        a[rt][0] = ra[rt][0] * rw[rt];
+                        a[rt][1] = ra[rt][1] * rw[rt];
                     } else {
-                        a[gi][rt][0] = ra[gi][rt][0];
-                        a[gi][rt][1] = ra[gi][rt][1];
+                        a[rt][0] = ra[rt][0];
+                        a[rt][1] = ra[rt][1];
                     }
                 }
-            const bool more = kc + 1 < n_kc;
-            if (more) {   // in flight while this chunk computes
-                fetch_op(kc + 1);
-                fetch_a(kc + 1);
-            }
-#pragma unroll
-            for (int gi = 0; gi < 2; ++gi)
+                if (t + 1 < n_grp) fetch_a(t + 1);   // the next group, across the chunk boundary
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     double bv[NCT];
@@ -296,9 +293,10 @@ __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const
                     for (int c = 0; c < NCT; ++c)
 #pragma unroll
                         for (int rt = 0; rt < RT; ++rt)
-                            acc[rt][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[gi][rt][e >> 1][e & 1], bv[c],
+                            acc[rt][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt][e >> 1][e & 1], bv[c],
                                                                               acc[rt][c], 0, 0, 0);
                 }
+            }
             if (more) store_op(Bs0 + (size_t)((kc + 1) & 1) * NP * kF64LdK);
         }
         // row factor d on the rows (row 4 r + q of the tile in register r) and store
