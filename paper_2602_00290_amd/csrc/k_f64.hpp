@@ -125,20 +125,25 @@ __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const
     for (int i = 0; i < (GRAM ? NB : 1); ++i) gacc[i] = (f64x4){0.0, 0.0, 0.0, 0.0};
 
     // operand chunk kc (K rows k0 .. k0 + 31, NP columns, zero beyond K and
-    // ldg) into registers: thread t holds the pairs (k, n), (k, n + 1)
-    constexpr int OPP = kF64KC * NP / 2;                 // pairs per chunk
+    // ldg) into registers: slot s holds column n = s % NP of the K rows
+    // 2 (s / NP) and 2 (s / NP) + 1, so that consecutive lanes read
+    // consecutive columns (coalesced) and write 16 bytes along K into the
+    // [n][k] layout, lanes n .. n + 15 starting 4 banks apart
+    constexpr int OPP = kF64KC * NP / 2;                 // slots per chunk
     constexpr int OPN = (OPP + kF64Threads - 1) / kF64Threads;
     f64x2 opr[OPN];
     auto fetch_op = [&](int kc) __attribute__((always_inline)) {
+        const double* gk = Gop + (size_t)kc * kF64KC * ldg;   // uniform chunk base, 32-bit offsets
+        const int kr = K - kc * kF64KC;                       // K rows left from the chunk start
 #pragma unroll
         for (int v = 0; v < OPN; ++v) {
             const int idx = tid + kF64Threads * v;
-            const int kk = idx / (NP / 2), n = 2 * (idx % (NP / 2));
-            const int k = kc * kF64KC + kk;
+            const int n = idx % NP, kk = 2 * (idx / NP);
             f64x2 x = (f64x2){0.0, 0.0};
-            if (idx < OPP && k < K) {
-                if (n + 1 < ldg) x = *reinterpret_cast<const f64x2*>(Gop + (size_t)k * ldg + n);
-                else if (n < ldg) x[0] = Gop[(size_t)k * ldg + n];
+            if (idx < OPP && n < ldg) {
+                const int o = kk * ldg + n;
+                if (kk < kr) x[0] = gk[o];
+                if (kk + 1 < kr) x[1] = gk[o + ldg];
             }
             opr[v] = x;
         }
@@ -147,11 +152,8 @@ __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const
 #pragma unroll
         for (int v = 0; v < OPN; ++v) {
             const int idx = tid + kF64Threads * v;
-            if (idx < OPP) {
-                const int kk = idx / (NP / 2), n = 2 * (idx % (NP / 2));
-                Bs[(size_t)n * kF64LdK + kk] = opr[v][0];
-                Bs[(size_t)(n + 1) * kF64LdK + kk] = opr[v][1];
-            }
+            if (idx < OPP)
+                *reinterpret_cast<f64x2*>(Bs + (size_t)(idx % NP) * kF64LdK + 2 * (idx / NP)) = opr[v];
         }
     };
     // this lane's A fragments of one 16-K group (flat index t = 2 kc + gi):
