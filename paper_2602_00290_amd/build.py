@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtt_transport.so")
 SOURCES = ["tt_transport.hip"]
 HEADERS = ["tt_common.hpp", "k_small.hpp", "k_big.hpp", "k_mfma.hpp", "k_fused.hpp", "k_gram.hpp", "k_bf16x.hpp",
-           "k_couple.hpp", "planck.hpp", "k_diag.hpp", "k_rand.hpp"]
+           "k_couple.hpp", "planck.hpp", "k_diag.hpp", "k_rand.hpp", "k_f64.hpp", "k_batch.hpp", "k_eig.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("TT_OFFLOAD_ARCH", "gfx950")

@@ -760,6 +760,12 @@ struct FastDiv {
     __device__ int r(int x) const { return x - __mul24(q(x), d); }
 };
 
+}  // namespace ttrt
+
+#include "k_eig.hpp"
+
+namespace ttrt {
+
 // ---------------------------------------------------------------------------
 // prep: right-to-left orthogonalisation of the small cores of the TT sum
 // ---------------------------------------------------------------------------
@@ -1025,7 +1031,6 @@ __device__ __forceinline__ void svd_chain_body(const Geom& g, DevState* st, cons
     const int nt = g.nt, npn = g.np;
     const int k1 = st->k1, k2 = st->k2;
     const int m2 = nt * k2;
-    const bool warm = st->canon && st->canon_prev && st->k1_prev == k1;
     // FAST (k1 <= 64, r1 N_theta <= 256, k2 <= 16): working matrices at fixed
     // LDS offsets, 64 x 64 with leading dimension 65 (columns on different
     // banks), zero / identity padded beyond k1.  Otherwise LDS where it fits
@@ -1034,23 +1039,65 @@ __device__ __forceinline__ void svd_chain_body(const Geom& g, DevState* st, cons
     const int ld = FAST ? 65 : (k1 | 1);   // odd leading dimension: columns on different LDS banks
     const size_t reg0 = FAST ? (size_t)(64 * 65 > 257 * 16 ? 64 * 65 : 257 * 16) : 0;
     double* J = FAST ? lds : cv.take((size_t)k1 * ld, sc.J);
+    // The Gram route's first bond by tridiagonalisation (k_eig.hpp) when its
+    // scratch fits in LDS beside J; the Jacobi eigensolver otherwise, and as
+    // the fallback when its eigenvectors fail their checks.
+    double* trd_mem = nullptr;
+    // (at k1 <= 64 the warm-started Jacobi on LDS is as fast: the fixed layout)
+    if (gram && k1 >= 2 && !FAST && J != sc.J) trd_mem = cv.take(kTrdScratch, nullptr);
     double* W = FAST ? lds + reg0 : cv.take((size_t)k1 * ld, sc.W);
     double* T = FAST ? W + (size_t)kp * ld : cv.take((size_t)k1 * ld, sc.A2);
     double* nrm = FAST ? T + (size_t)kp * ld : cv.take((size_t)k1, sc.sv + 2 * k1);
     double* s1 = FAST ? nrm + kp : cv.take((size_t)k1, sc.sv);
     int* p1 = sc.perm;
+    bool trd = trd_mem != nullptr;
+    const bool warm = !trd && st->canon && st->canon_prev && st->k1_prev == k1;
     long long tph[8];
     int sw1 = 0, sw2 = 0;
     const FastDiv dkp(kp), dk1(k1), dk2(k2), dm2(m2), dnt(nt), dnp(npn);
     tph[0] = wall_clock64();
     // stage the input (R_B or G, row-major in global) column-major into T; W0
-    for (int idx = threadIdx.x; idx < kp * kp; idx += blockDim.x) {
-        const int i = dkp.q(idx), j = idx - i * kp;      // coalesced along rows of the input
-        T[i + (size_t)j * ld] = (i < k1 && j < k1) ? RB[(size_t)i * ldr + j] : 0.0;
-        W[j + (size_t)i * ld] = (i < k1 && j < k1) ? (warm ? sc.Wkeep[j + (size_t)i * k1] : (i == j ? 1.0 : 0.0))
-                                                   : (i == j ? 1.0 : 0.0);
-    }
-    __syncthreads();
+    auto stage = [&](bool wrm) {
+        for (int idx = threadIdx.x; idx < kp * kp; idx += blockDim.x) {
+            const int i = dkp.q(idx), j = idx - i * kp;      // coalesced along rows of the input
+            T[i + (size_t)j * ld] = (i < k1 && j < k1) ? RB[(size_t)i * ldr + j] : 0.0;
+            W[j + (size_t)i * ld] = (i < k1 && j < k1) ? (wrm ? sc.Wkeep[j + (size_t)i * k1] : (i == j ? 1.0 : 0.0))
+                                                       : (i == j ? 1.0 : 0.0);
+        }
+        __syncthreads();
+    };
+    // Gram route by Jacobi: J = W^T G W (warm) or G, two-sided Jacobi, s1 = sqrt(diag)
+    auto jacobi_gram = [&](bool wrm) {
+        if (wrm && FAST) {
+            // J = W^T G W on 64 x 64 tiles in LDS (zero / identity padded beyond k1)
+            block_mm64(T, 1, ld, W, 1, ld, J, ld);       // J = G W
+            __syncthreads();
+            block_mm64(W, ld, 1, J, 1, ld, T, ld);       // T = W^T J
+            __syncthreads();
+        } else if (wrm) {
+            // J = W^T G W: J <- G W, then T <- W^T J
+            block_mm_tiled(k1, k1, k1, T, 1, ld, W, 1, ld, J, 1, ld);
+            __syncthreads();
+            block_mm_tiled(k1, k1, k1, W, ld, 1, J, 1, ld, T, 1, ld);
+            __syncthreads();
+        }
+        for (int idx = threadIdx.x; idx < kp * kp; idx += blockDim.x) {
+            const int j = dkp.q(idx), i = idx - j * kp;
+            J[i + (size_t)j * ld] = T[i + (size_t)j * ld];
+        }
+        __syncthreads();
+        tph[1] = wall_clock64();
+        if (FAST)
+            sw1 = block_jacobi_sym64(J, ld, W, cs, pa_, pb_, &sh_flag, kGramSweepTol);
+        else
+            sw1 = block_jacobi_sym_wide(J, k1, ld, W, ld, cs, pa_, pb_, &sh_flag, kGramSweepTol);
+        tph[2] = wall_clock64();
+        for (int j = threadIdx.x; j < k1; j += blockDim.x) s1[j] = sqrt(fmax(J[j + (size_t)j * ld], 0.0));
+    };
+    stage(warm);
+    TrdScratch ws;
+    if (trd) ws.carve(trd_mem);
+    const int K = k1 < cap1 ? k1 : cap1;   // eigenvalues the truncation can keep
     if (!gram) {
         // J = R_B W (R_B upper triangular)
         for (int idx = threadIdx.x; idx < kp * kp; idx += blockDim.x) {
@@ -1081,43 +1128,73 @@ __device__ __forceinline__ void svd_chain_body(const Geom& g, DevState* st, cons
             for (int i = 0; i < kp; ++i) acc += J[i + (size_t)j * ld] * J[i + (size_t)j * ld];
             s1[j] = sqrt(acc);
         }
-    } else {
-        if (warm && FAST) {
-            // J = W^T G W on 64 x 64 tiles in LDS (zero / identity padded beyond k1)
-            block_mm64(T, 1, ld, W, 1, ld, J, ld);       // J = G W
-            __syncthreads();
-            block_mm64(W, ld, 1, J, 1, ld, T, ld);       // T = W^T J
-            __syncthreads();
-        } else if (warm) {
-            // J = W^T G W: J <- G W, then T <- W^T J
-            block_mm_tiled(k1, k1, k1, T, 1, ld, W, 1, ld, J, 1, ld);
-            __syncthreads();
-            block_mm_tiled(k1, k1, k1, W, ld, 1, J, 1, ld, T, 1, ld);
-            __syncthreads();
-        }
+    } else if (trd) {
+        // J = G; T = Q^T G Q; the K largest eigenvalues, the rest of the trace
+        // in entry K (so the tail sums of the truncation are trace-based); p1 = I
         for (int idx = threadIdx.x; idx < kp * kp; idx += blockDim.x) {
             const int j = dkp.q(idx), i = idx - j * kp;
             J[i + (size_t)j * ld] = T[i + (size_t)j * ld];
         }
         __syncthreads();
         tph[1] = wall_clock64();
-        if (FAST)
-            sw1 = block_jacobi_sym64(J, ld, W, cs, pa_, pb_, &sh_flag, kGramSweepTol);
-        else
-            sw1 = block_jacobi_sym_wide(J, k1, ld, W, ld, cs, pa_, pb_, &sh_flag, kGramSweepTol);
+        block_tridiag(J, k1, ld, ws, red);
+        const double tr = block_trd_eigvals(k1, K, ws);
+        const double gsc = ws.zr[4];   // the scale of the tridiagonalised matrix
+        double part = 0.0;
+        for (int j = threadIdx.x; j < K; j += blockDim.x) part += ws.lam[j];
+        const double top = block_sum(part, red);
+        for (int j = threadIdx.x; j < k1; j += blockDim.x) {
+            s1[j] = j < K ? sqrt(fmax(ws.lam[j] * gsc, 0.0)) : (j == K ? sqrt(fmax((tr - top) * gsc, 0.0)) : 0.0);
+            p1[j] = j;
+        }
         tph[2] = wall_clock64();
-        for (int j = threadIdx.x; j < k1; j += blockDim.x) s1[j] = sqrt(fmax(J[j + (size_t)j * ld], 0.0));
+    } else {
+        jacobi_gram(warm);
     }
     __syncthreads();
-    block_sort_desc(s1, k1, p1);
-    double part = 0.0;
-    for (int j = threadIdx.x; j < k1; j += blockDim.x) part += s1[j] * s1[j];
-    const double norm2 = block_sum(part, red);
-    const double norm = sqrt(norm2);
-    const double delta = tol * norm / sqrt(2.0);
-    if (threadIdx.x == 0) sh_r[0] = delta_rank(s1, p1, k1, delta, cap1);
-    __syncthreads();
-    const int r1n = sh_r[0];
+    double norm2 = 0.0, norm = 0.0, delta = 0.0;
+    int r1n = 1;
+    auto truncate = [&](bool sort) {
+        if (sort) block_sort_desc(s1, k1, p1);
+        double part = 0.0;
+        for (int j = threadIdx.x; j < k1; j += blockDim.x) part += s1[j] * s1[j];
+        norm2 = block_sum(part, red);
+        norm = sqrt(norm2);
+        delta = tol * norm / sqrt(2.0);
+        if (threadIdx.x == 0) sh_r[0] = delta_rank(s1, p1, k1, delta, cap1);
+        __syncthreads();
+        r1n = sh_r[0];
+    };
+    truncate(!trd);
+    int trd_status = 0;        // 0 not tried, 1 done, 2 / 3 / 4 vectors refused (residual / orthogonality / > 64)
+    double trd_emax = 0.0;
+    if (trd) {
+        // the r1n kept eigenvectors into columns 0 .. r1n - 1 of W
+        const double tn = ws.zr[1];
+        int fail;
+        {
+            // the reflectors to global memory, then the vectors of T in J's place
+            for (int idx = threadIdx.x; idx < k1 * ld; idx += blockDim.x) {
+                const int k = idx / ld, i = idx - k * ld;
+                if (k < k1 - 2 && i >= k + 2 && i < k1) sc.J[idx] = J[idx];
+            }
+            __syncthreads();
+            const bool cfit = (size_t)ld * r1n + (size_t)r1n * r1n <= (size_t)k1 * ld;
+            double* C = cfit ? J + (size_t)ld * r1n : sc.A2;
+            // more than 64 kept vectors (four per wave): the Jacobi below
+            fail = r1n <= 64 ? block_trd_vectors<2, 4>(k1, r1n, ws, tn, sc.J, ld, J, ld, C, r1n, W, ld, red, trd_emax)
+                             : 3;
+        }
+        trd_status = 1 + fail;
+        if (fail) {
+            // Jacobi from the cold start, then the truncation again
+            trd = false;
+            stage(false);
+            jacobi_gram(false);
+            __syncthreads();
+            truncate(true);
+        }
+    }
     const int ldzn = ld_for_rank(r1n);
     const int ldb = st->ldb;
     // sorted V -> Wkeep (next warm start); V_r -> Vout in the contraction precision
@@ -1218,6 +1295,8 @@ __device__ __forceinline__ void svd_chain_body(const Geom& g, DevState* st, cons
     tph[5] = wall_clock64();
     if (threadIdx.x == 0) {
         for (int i = 0; i < 6; ++i) st->tph[i] = tph[i];
+        st->tph[6] = trd_status;
+        st->tph[7] = __double_as_longlong(trd_emax);
         st->sweeps[0] = sw1;
         st->sweeps[1] = sw2;
         st->r1n = r1n;
