@@ -694,4 +694,80 @@ __device__ __forceinline__ int block_trd_vectors(int n, int nv, TrdScratch& ws, 
     return 0;
 }
 
+// Two-sided cyclic Jacobi on a symmetric n x n S (n <= 16, S[a + b ld]),
+// accumulating the rotations into W (W[i + a ldw], caller-initialised), by
+// one wave with no block barriers: per round, lane L < 8 forms the rotation
+// of pair L of the tournament over 16 players (players >= n are zero rows and
+// never rotate) into cs / pa / pb (LDS), then lane L applies R_p^T B R_q to the
+// 2 x 2 block (p, q) = (L / 8, L % 8) of S and rotates two rows of W.  The
+// wave's LDS writes precede its later reads in program order, so no barrier
+// is needed.  Rotation, skipping and stopping rules as block_jacobi_sym64.
+// Called by all 64 lanes of one wave; returns the sweeps.
+__device__ __forceinline__ int wave_jacobi_sym16(double* S, int n, int ld, double* W, int ldw, double* cs, int* pa,
+                                                 int* pb, double tconv) {
+    const int l = threadIdx.x & 63, p = l >> 3, q = l & 7;
+    double tr = 0.0;
+    for (int i = 0; i < n; ++i) tr += fabs(S[i + (size_t)i * ld]);
+    const double floor_abs = 1e-15 * tr;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        int big = 0;
+        for (int round = 0; round < 15; ++round) {
+            if (l < 8) {
+                int a, b;
+                tournament_pair(l, round, 16, &a, &b);
+                double c = 1.0, sn = 0.0;
+                if (b < n) {
+                    const double app = S[a + (size_t)a * ld], aqq = S[b + (size_t)b * ld], apq = S[a + (size_t)b * ld];
+                    if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs) {
+                        double t;
+                        jacobi_rotation(app, aqq, apq, &c, &sn, &t);
+                        if (fabs(t) > tconv) big = 1;
+                        if (fabs(t) <= 1e-10) {
+                            c = 1.0;
+                            sn = 0.0;
+                        }
+                    }
+                }
+                cs[2 * l] = c;
+                cs[2 * l + 1] = sn;
+                pa[l] = a;
+                pb[l] = b;
+            }
+            const double sp = cs[2 * p + 1], sq = cs[2 * q + 1];
+            const double cp = cs[2 * p], cq = cs[2 * q];
+            const int ap = pa[p], bp = pb[p], aq = pa[q], bq = pb[q];
+            if (sp != 0.0 || sq != 0.0) {   // both rotations identity: block unchanged
+                // a rotation acts on existing rows / columns only (b < n), its partner a < b too;
+                // an identity pair's second player may lie past n: that row / column is zero
+                const bool vp = bp < n, vq = bq < n, up = ap < n, uq = aq < n;
+                const double b00 = (up && uq) ? S[ap + (size_t)aq * ld] : 0.0;
+                const double b01 = (up && vq) ? S[ap + (size_t)bq * ld] : 0.0;
+                const double b10 = (vp && uq) ? S[bp + (size_t)aq * ld] : 0.0;
+                const double b11 = (vp && vq) ? S[bp + (size_t)bq * ld] : 0.0;
+                const double c00 = cq * b00 - sq * b01, c01 = sq * b00 + cq * b01;
+                const double c10 = cq * b10 - sq * b11, c11 = sq * b10 + cq * b11;
+                if (up && uq) S[ap + (size_t)aq * ld] = cp * c00 - sp * c10;
+                if (up && vq) S[ap + (size_t)bq * ld] = cp * c01 - sp * c11;
+                if (vp && uq) S[bp + (size_t)aq * ld] = sp * c00 + cp * c10;
+                if (vp && vq) S[bp + (size_t)bq * ld] = sp * c01 + cp * c11;
+            }
+            if (sq != 0.0) {   // W <- W R: rows p and p + 8 of the column pair q
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int i = p + 8 * h;
+                    if (i < n) {
+                        double* wa = W + i + (size_t)aq * ldw;
+                        double* wb = W + i + (size_t)bq * ldw;
+                        const double u = *wa, v = *wb;
+                        *wa = cq * u - sq * v;
+                        *wb = sq * u + cq * v;
+                    }
+                }
+            }
+        }
+        if (__ballot(big) == 0) return sweep + 1;
+    }
+    return 40;
+}
+
 }  // namespace ttrt

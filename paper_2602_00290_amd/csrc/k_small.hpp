@@ -1249,7 +1249,13 @@ __device__ __forceinline__ void svd_chain_body(const Geom& g, DevState* st, cons
             H[e + (size_t)c * ldh] = acc;
         }
         __syncthreads();
-        sw2 = block_jacobi_sym_wide(H, k2, ldh, V2, k2, cs, pa_, pb_, &sh_flag, kGramSweepTol);
+        if (k2 <= 16) {
+            // one wave, no block barriers (V2 holds the identity)
+            if (threadIdx.x < 64) sw2 = wave_jacobi_sym16(H, k2, ldh, V2, k2, cs, pa_, pb_, kGramSweepTol);
+            __syncthreads();
+        } else {
+            sw2 = block_jacobi_sym_wide(H, k2, ldh, V2, k2, cs, pa_, pb_, &sh_flag, kGramSweepTol);
+        }
         tph[4] = wall_clock64();
         for (int j = threadIdx.x; j < k2; j += blockDim.x) s2[j] = sqrt(fmax(H[j + (size_t)j * ldh], 0.0));
     } else {
