@@ -58,7 +58,7 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "TT solves/s & TT apply+round GFLOP/s (% MFMA peak); p50/p99 solve latency"
 C3_STEPS_PER_SOLVE = 384
 # the dominant kernel of the headline (FP64 gather projection, 128 columns)
-HEAD_KERNEL = "k_mm_f64<0, 8, false, 1>"
+HEAD_KERNEL = "k_mm_f64<0, 8, false, 1, false>"
 KERNEL_SOURCES = ["paper_2602_00290_amd/csrc/k_f64.hpp", "paper_2602_00290_amd/csrc/k_fused.hpp",
                   "paper_2602_00290_amd/csrc/tt_common.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_clumps3d_fp64.json")
