@@ -110,15 +110,18 @@ def cpu_baseline_c3(budget_s: float = 15.0, nz: int = 4):
     }
 
 
-def stored_traffic():
+def stored_traffic(project_blocks=None):
     """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, or None if it is missing or was taken on different kernel source."""
+    summary, or None if it is missing, was taken on different kernel source, or
+    at a grid other than `project_blocks` (when given)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("source_hash") != kernel_source_hash():
+        return None
+    if project_blocks is not None and t.get("project_blocks") != project_blocks:
         return None
     return t
 
@@ -162,7 +165,7 @@ def tt_rel_diff(x, y):
     return dn / yn if yn > 0 else dn
 
 
-def roofline_c3(st, M):
+def roofline_c3(st, M, tuning=None):
     """Roofline of the dominant kernel (the FP64 MFMA gather projection of the
     3D headline) from its HIP-event times over the timed steps.  `achieved`
     counts the first rounding pass as the method defines it, the R factor of
@@ -177,7 +180,7 @@ def roofline_c3(st, M):
     alg = 2.0 * M * R1 * R1 - 2.0 / 3.0 * R1 ** 3
     exe = fl["project"] / n["project"]
     peak = PEAKS["fp64"]
-    t = stored_traffic()
+    t = stored_traffic(tuning["project_blocks"] if tuning else None)
     out = {"bound": "mfma", "kernel": HEAD_KERNEL, "achieved": alg / t_launch / 1e12, "peak": peak,
            "unit": "TFLOP/s", "frac": alg / t_launch / 1e12 / peak,
            "traffic": (t["fetch_bytes"] + t["write_bytes"]) if t else None,
@@ -208,6 +211,8 @@ def c3_run(prob, method, rank_warm, args, label, keep_cores=True, timing_steps=4
     else:
         s.solve(rank_warm)
         warm = rank_warm
+    # launch shapes tuned on the state at the cap (untimed set-up)
+    tuning = s.tune(args.tune_cache) if args.tune else None
     if args.warmup > 0:
         s.solve(args.warmup)
     torch.cuda.synchronize()
@@ -224,7 +229,7 @@ def c3_run(prob, method, rank_warm, args, label, keep_cores=True, timing_steps=4
            "compression": stt["compression"],
            "kernel_ms_per_step": {c: stt["kernel_ms"][c] / timing_steps for c in tt.KERNEL_CLASSES if n[c]},
            "flops_per_step": sum(stt["flops"].values()) / timing_steps,
-           "workspace_gb": s.nbytes / 2 ** 30}
+           "workspace_gb": s.nbytes / 2 ** 30, "tuning": tuning}
     print(json.dumps({"phase": label, "ms_per_step": out["ms_per_step"], "ranks": out["ranks"]}),
           file=sys.stderr, flush=True)
     cores = s.get_cores() if keep_cores else None
@@ -310,10 +315,11 @@ def mode_probe(args):
             warm += 1
             if st["r1"] >= prob.rank_cap and warm >= 24:
                 break
+        tuning = s.tune(args.tune_cache) if args.tune else None
         st = s.solve(args.probe_steps)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "probe", "workload": args.probe_workload, "rank_warmup_steps": warm,
-                          "steps": args.probe_steps, "ranks": [st["r1"], st["r2"]]}), flush=True)
+                          "steps": args.probe_steps, "ranks": [st["r1"], st["r2"]], "tuning": tuning}), flush=True)
         return
     if args.probe_workload == "clumps3d":
         prob = ti.clumps3d(precision=ti.PREC_BF16X)
@@ -420,9 +426,21 @@ def mode_pmc_summary(args):
         steady = rows[-args.probe_steps:]
         return sum(steady) / len(steady) * 1024.0, len(steady)
 
+    def probe_grid(sub):
+        # the projection grid the probe ran at (its JSON line on stdout)
+        try:
+            for line in open(os.path.join(d, sub + ".log")):
+                if line.startswith("{") and '"probe"' in line:
+                    tun = json.loads(line).get("tuning")
+                    return tun["project_blocks"] if tun else None
+        except (OSError, ValueError):
+            pass
+        return None
+
     ff, fw = copy_factor("copy_fetch", "FETCH_SIZE"), copy_factor("copy_write", "WRITE_SIZE")
     fetch, nf = kernel("fetch", "FETCH_SIZE")
     write, nw = kernel("write", "WRITE_SIZE")
+    grids = {probe_grid("fetch"), probe_grid("write")}
     import tt_inputs as ti
     p = ti.clumps3d(precision=ti.PREC_FP64)
     out = {
@@ -433,6 +451,8 @@ def mode_pmc_summary(args):
         "fetch_bytes": fetch * ff,
         "write_bytes": write * fw,
         "raw_fetch_bytes": fetch, "raw_write_bytes": write, "dispatches": [nf, nw],
+        # the projection's grid in both counter runs (null if they differ or were not recorded)
+        "project_blocks": grids.pop() if len(grids) == 1 else None,
         "calibration": {"copy_bytes": nbytes, "fetch_factor": ff, "write_factor": fw},
         # the method's minimum for this pass: read the state Z once (M x r1 FP64);
         # this design also writes the projected core B (M x k1 FP64)
@@ -696,6 +716,9 @@ def main():
                          "plane2d_coupled (plane2d with the coupled medium temperature, heat capacity 8 a), "
                          "plane2d_rusanov_scatter (plane2d with the Rusanov flux and scattering kappa_s = kappa_a), "
                          "or plane2d_randomized (plane2d with randomized rounding, sketch ranks = ranks + 4)")
+    ap.add_argument("--tune", type=int, default=1,
+                    help="tune the launch shapes of the 3D solves once their ranks reach the cap (untimed)")
+    ap.add_argument("--tune-cache", default=None, help="tuning cache file (default: none, always time)")
     ap.add_argument("--copy-mb", type=int, default=512)
     ap.add_argument("--pmc-dir", default=os.path.join(ROOT, "gpurun_out", "traffic"))
     ap.add_argument("--coupled", type=int, default=1,
@@ -765,7 +788,8 @@ def main():
         "ranks": head["ranks"], "max_R": head["max_R"], "compression": head["compression"],
         "workspace_gb": head["workspace_gb"],
         "kernel_ms_per_step": head["kernel_ms_per_step"],
-        "roofline": roofline_c3(st64, p64.M),
+        "tuning": head["tuning"],
+        "roofline": roofline_c3(st64, p64.M, head["tuning"]),
         "precisions_beside": beside,
     }
     del beside

@@ -342,6 +342,56 @@ tt_status tt_transport_internal_ranks(tt_handle* h, double delta, tt_internal_ra
  * timing is on or an unrounded operator is pending.  on = 0 frees the graphs. */
 tt_status tt_transport_set_graph(tt_handle* h, int on);
 
+/* Launch shapes (grid sizes) of the persistent contraction kernels, for
+ * tt_transport_tune, tt_transport_set_launch and tt_transport_get_launch.  A
+ * block count of 0 means the plan launches no such kernel (on input: keep).
+ * The kernels are the projection B = Z_new L_Theta (FP64 MFMA contractions;
+ * with FP32 data the fused projection + FP64 Gram), the output
+ * Z_out = B V_r (or its fused FP32 form from Z), and the FP64 Gram of a
+ * stored first core (one row range and one partial per block; its grid is
+ * rounded to whole row ranges of a multiple of 16 rows, at least 64).  These
+ * are the contractions of the rounding pass (Sec. 3.1, the first-core steps
+ * of the TT rounding); their grids change only the order of the Gram's
+ * partial sums, never what is computed. */
+typedef struct tt_tuning {
+    int project_blocks;            /* blocks of the projection kernel */
+    int output_blocks;             /* blocks of the output kernel */
+    int gram_blocks;               /* blocks of the Gram kernel */
+    int from_cache;                /* out (tune): 1 if the shapes came from the cache file, untimed */
+    double project_ms, output_ms, gram_ms;                 /* out (tune): ms per launch at the chosen shapes */
+    double project_ms_default, output_ms_default, gram_ms_default;   /* out (tune): ms per launch at the plan's defaults */
+} tt_tuning;
+
+/* Launch-shape autotuning (batching extension: launch shapes per workload).
+ * Times candidate grids of each tunable kernel of the handle's rounding pass
+ * (64 to 1024 blocks, up to the plan's maximum) on the handle's current state
+ * and keeps the fastest for this handle, unless it is within 2 % of the
+ * plan's default.  The state is not changed: the kernels write only the
+ * handle's round scratch (B, Gram partials, the next Z buffer), and the gather
+ * operand the tuner prepares is the one the next rounding pass prepares
+ * again.  Tune once the ranks are representative (after the first steps of a
+ * solve), since the best grid depends on them.  cache_path (may be NULL) names
+ * a text file, one line per tuned problem: "key project output gram", the key
+ * naming the device (architecture, compute units) and the problem's shape
+ * (precision, rounding route, rows, groups, dimension, angles, rank caps,
+ * flux), not the current ranks; a matching line is applied without timing or
+ * touching the device (out->from_cache = 1), so a new handle of a tuned
+ * problem can take its grids before its first step; otherwise the result is
+ * appended.
+ * One writer per file.  Drops captured graphs.  Synchronises `stream`.
+ * Errors: TT_ERR_INVALID_ARG (NULL handle/out, cache file not writable),
+ * TT_ERR_STATE (an unrounded operator is pending), TT_ERR_HIP. */
+tt_status tt_transport_tune(tt_handle* h, const char* cache_path, tt_tuning* out, void* stream);
+
+/* Set launch shapes explicitly (the *_ms fields and from_cache are ignored;
+ * a block count of 0 keeps the current one).  Errors: TT_ERR_INVALID_ARG
+ * (NULL arguments, a count outside [1, maximum], or a count for a kernel the
+ * plan does not launch).  Drops captured graphs. */
+tt_status tt_transport_set_launch(tt_handle* h, const tt_tuning* shapes);
+
+/* The current launch shapes and the largest allowed (either may be NULL). */
+tt_status tt_transport_get_launch(tt_handle* h, tt_tuning* current, tt_tuning* maximum);
+
 /* Fill `out` with the statistics of the current state (synchronises). */
 tt_status tt_transport_get_stats(tt_handle* h, tt_stats* out);
 

@@ -112,6 +112,24 @@ class TTInternalRanks(ctypes.Structure):
     ]
 
 
+class TTTuning(ctypes.Structure):
+    _fields_ = [
+        ("project_blocks", ctypes.c_int),
+        ("output_blocks", ctypes.c_int),
+        ("gram_blocks", ctypes.c_int),
+        ("from_cache", ctypes.c_int),
+        ("project_ms", ctypes.c_double),
+        ("output_ms", ctypes.c_double),
+        ("gram_ms", ctypes.c_double),
+        ("project_ms_default", ctypes.c_double),
+        ("output_ms_default", ctypes.c_double),
+        ("gram_ms_default", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class TTError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"tt_transport error {status}: {msg}")
@@ -145,6 +163,9 @@ def _load():
     L.tt_transport_get_stats.argtypes = [vp, ctypes.POINTER(TTStats)]
     L.tt_transport_set_timing.argtypes = [vp, ctypes.c_int]
     L.tt_transport_set_graph.argtypes = [vp, ctypes.c_int]
+    L.tt_transport_tune.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(TTTuning), vp]
+    L.tt_transport_set_launch.argtypes = [vp, ctypes.POINTER(TTTuning)]
+    L.tt_transport_get_launch.argtypes = [vp, ctypes.POINTER(TTTuning), ctypes.POINTER(TTTuning)]
     L.tt_transport_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int]
     L.tt_transport_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp),
                                            ctypes.c_int, ctypes.POINTER(TTStats)]
@@ -158,7 +179,7 @@ def _load():
     L.tt_transport_internal_ranks.argtypes = [vp, ctypes.c_double, ctypes.POINTER(TTInternalRanks), _dp, ctypes.c_int,
                                               _dp, ctypes.c_int, vp]
     for name in ("create", "create_noalloc", "apply_op", "round", "solve", "reset", "get_ranks", "get_cores", "set_cores",
-                 "get_stats", "set_timing", "set_graph", "step_batch", "solve_batch", "solve_small_batch", "destroy",
+                 "get_stats", "set_timing", "set_graph", "tune", "set_launch", "get_launch", "step_batch", "solve_batch", "solve_small_batch", "destroy",
                  "group_emission",
                  "get_temperature", "internal_ranks"):
         getattr(L, "tt_transport_" + name).restype = ctypes.c_int
@@ -170,6 +191,7 @@ lib = _load()
 EXPORTED = ("tt_transport_workspace_bytes", "tt_transport_create", "tt_transport_create_noalloc", "tt_transport_apply_op", "tt_transport_round",
             "tt_transport_solve", "tt_transport_reset", "tt_transport_get_ranks", "tt_transport_get_cores",
             "tt_transport_set_cores", "tt_transport_get_stats", "tt_transport_set_timing", "tt_transport_set_graph",
+            "tt_transport_tune", "tt_transport_set_launch", "tt_transport_get_launch",
             "tt_transport_step_batch", "tt_transport_solve_batch", "tt_transport_solve_small_batch",
             "tt_transport_destroy", "tt_transport_last_error",
             "tt_transport_group_emission", "tt_transport_get_temperature", "tt_transport_internal_ranks")
@@ -371,6 +393,27 @@ class Solver:
     def set_graph(self, on: bool):
         """Replay the steps of solve() as HIP graphs (needs a non-default stream)."""
         _check(lib.tt_transport_set_graph(self.handle, 1 if on else 0))
+
+    def tune(self, cache_path: Optional[str] = None) -> dict:
+        """Time candidate grids of the persistent contraction kernels on the
+        current state and keep the fastest (tt_transport_tune)."""
+        out = TTTuning()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(lib.tt_transport_tune(self.handle, path, ctypes.byref(out), self._sp()))
+        return out.as_dict()
+
+    def set_launch(self, project_blocks: int = 0, output_blocks: int = 0, gram_blocks: int = 0):
+        """Set grid sizes explicitly (0 keeps the current one)."""
+        t = TTTuning(project_blocks=int(project_blocks), output_blocks=int(output_blocks),
+                     gram_blocks=int(gram_blocks))
+        _check(lib.tt_transport_set_launch(self.handle, ctypes.byref(t)))
+
+    def get_launch(self) -> tuple:
+        """(current, maximum) grid sizes as dicts."""
+        cur, mx = TTTuning(), TTTuning()
+        _check(lib.tt_transport_get_launch(self.handle, ctypes.byref(cur), ctypes.byref(mx)))
+        keys = ("project_blocks", "output_blocks", "gram_blocks")
+        return {k: getattr(cur, k) for k in keys}, {k: getattr(mx, k) for k in keys}
 
     def destroy(self):
         if self.handle:

@@ -56,6 +56,10 @@ tt_status fail(tt_status s, const std::string& msg) {
 
 enum KClass { KC_PREP = 0, KC_PROJECT = 1, KC_FACTOR = 2, KC_TREE = 3, KC_SVD = 4, KC_OUTPUT = 5, KC_DIAG = 6, KC_COUPLE = 7 };
 
+// Largest grid the launch-shape tuner tries for the persistent contraction
+// kernels (four blocks per CU); the partial buffers are sized for it.
+constexpr int kTuneMaxBlocks = 1024;
+
 struct Plan {
     int dim = 1, nx = 1, ny = 1, nz = 1;
     long long NX = 0, M = 0;
@@ -68,8 +72,9 @@ struct Plan {
     std::vector<int> levP;          // blocks per TSQR level
     std::vector<long long> levRows; // rows per block per level
     std::vector<long long> levN;    // rows of the level input
-    int Pg = 1;
-    long long rowsg = 0;
+    int Pg = 1;                     // blocks (row ranges, one partial each) of the first core's Gram
+    long long rowsg = 0;            // rows per Gram block
+    int Pg_max = 1;
     bool svd_fast = false;          // all SVD-chain matrices fit the LDS layout
     size_t elem = 8;                // bytes per stored element of Z / B
     // fused FP32 Gram path: projection + FP64 Gram in one kernel, output
@@ -79,6 +84,7 @@ struct Plan {
     int fused_T = 1;                // K groups of 16 at the rank caps
     int fused_blocks = 1;           // blocks of the projection + Gram kernel (one partial each)
     int fused_blocks_o = 1;         // blocks of the output kernel
+    int fused_blocks_max = 1;       // largest grid of either (the partial buffer's size)
     long long fused_tiles = 0;      // 32-row tiles
     size_t lds_p = 0, lds_o = 0;
     size_t B_bytes = 0;
@@ -97,7 +103,9 @@ struct Plan {
     // FP64 data: projection and output contractions on FP64 MFMA (k_mm_f64)
     bool f64mm = false;
     int nct_f = 1, nct_fo = 1;      // 16-column tiles of B / of Z_out
-    int f64_blocks = 1;             // blocks of the persistent projection / output kernels
+    int f64_blocks = 1;             // blocks of the persistent projection kernel (one Gram partial each when fused)
+    int f64_blocks_o = 1;           // blocks of the persistent output kernel
+    int f64_blocks_max = 1;         // largest grid of either
     size_t o_state, o_Z0, o_Z1, o_B, o_Th0, o_Th1, o_Ph0, o_Ph1, o_LTh, o_QTh, o_QPh, o_G, o_V, o_RA, o_RB, o_small,
         o_k0, o_ks, o_kfull = 0, o_eps, o_ghost, o_gtab, o_htab, o_ThN, o_PhN, o_sv, o_colsum;
     size_t small_bytes = 0, n_parts_max = 1;
@@ -261,6 +269,7 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         if (P.fused_blocks > 8) P.fused_blocks = P.fused_blocks / 8 * 8;
         P.fused_blocks_o = (int)std::max<long long>(1, std::min<long long>(512, want));
         if (P.fused_blocks_o > 8) P.fused_blocks_o = P.fused_blocks_o / 8 * 8;
+        P.fused_blocks_max = std::max(P.fused_blocks, P.fused_blocks_o);
     }
     // FP64 MFMA contractions: B up to 128 columns, Z_out up to 64
     {
@@ -271,6 +280,10 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         const long long nrb = (P.M + kF64Rows - 1) / kF64Rows;
         P.f64_blocks = (int)std::max<long long>(1, std::min<long long>(256, nrb));
         if (P.f64_blocks > 8) P.f64_blocks = P.f64_blocks / 8 * 8;
+        P.f64_blocks_o = P.f64_blocks;
+        // launch-shape tuning may take up to four blocks per CU
+        P.f64_blocks_max = (int)std::max<long long>(1, std::min<long long>(kTuneMaxBlocks, nrb));
+        if (P.f64_blocks_max > 8) P.f64_blocks_max = P.f64_blocks_max / 8 * 8;
     }
     // TSQR levels
     {
@@ -300,8 +313,9 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         rows = (rows + 15) / 16 * 16;
         P.Pg = (int)((P.M + rows - 1) / rows);
         P.rowsg = rows;
+        P.Pg_max = P.Pg;   // the most partials any Gram row split may take
         P.n_parts_max = std::max<size_t>(P.n_parts_max, (size_t)P.Pg);
-        P.n_parts_max = std::max<size_t>(P.n_parts_max, (size_t)P.f64_blocks);
+        P.n_parts_max = std::max<size_t>(P.n_parts_max, (size_t)(P.f64mm ? P.f64_blocks_max : P.f64_blocks));
     }
     // layout
     size_t off = 0;
@@ -331,7 +345,7 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
     if (P.fused) {
         P.o_Gsw = take((size_t)P.fused_T * P.nct_p * 256 * sizeof(float));
         P.o_Gfold = take((size_t)P.fused_T * P.nct_o * 256 * sizeof(float));
-        P.o_GP = take((size_t)P.fused_blocks * gram_blocks(P.nct_p) * 256 * d);
+        P.o_GP = take((size_t)P.fused_blocks_max * gram_blocks(P.nct_p) * 256 * d);
     }
     if (P.rand) {
         P.o_rG = take((size_t)P.KP * P.KP * d);
@@ -750,6 +764,26 @@ FusedNbr fused_nbr(const tt_handle* h, int opkind) {
 // Fused FP32 Gram rounding pass (after k_prep): projection + FP64 Gram in one
 // persistent MFMA kernel, fixed-order sum of the block partials, SVD chain
 // (which also folds V_r into the gather operand), then Z_out straight from Z.
+// The fused FP32 projection + Gram partials (P.fused_blocks partials in GP).
+template <int NP>
+void launch_fused_project(tt_handle* h, int opkind, hipStream_t s) {
+    const Plan& P = h->P;
+    hipLaunchKernelGGL((k_fused_f32<NP, true>), dim3(P.fused_blocks), dim3(kFusedThreads), P.lds_p, s, h->geom,
+                       fused_nbr(h, opkind), (const DevState*)h->st(), (const float*)h->Zc(),
+                       (const float*)h->at<float>(P.o_Gsw), (float*)nullptr, h->at<float2>(P.o_aux),
+                       h->at<int>(P.o_nbr), h->at<double>(P.o_GP), P.fused_tiles);
+}
+
+// The fused FP32 output Z_out from Z with V_r folded into the operand.
+template <int NO>
+void launch_fused_output(tt_handle* h, int opkind, hipStream_t s) {
+    const Plan& P = h->P;
+    hipLaunchKernelGGL((k_fused_f32<NO, false>), dim3(P.fused_blocks_o), dim3(kFusedThreads), P.lds_o, s, h->geom,
+                       fused_nbr(h, opkind), (const DevState*)h->st(), (const float*)h->Zc(),
+                       (const float*)h->at<float>(P.o_Gfold), (float*)h->Zn(), h->at<float2>(P.o_aux),
+                       h->at<int>(P.o_nbr), (double*)nullptr, P.fused_tiles);
+}
+
 template <int NP, int NO>
 tt_status round_fused_t(tt_handle* h, int opkind, double tol, int cap, hipStream_t s) {
     const Plan& P = h->P;
@@ -759,13 +793,8 @@ tt_status round_fused_t(tt_handle* h, int opkind, double tol, int cap, hipStream
     float* V = h->at<float>(P.o_V);
     double* GP = h->at<double>(P.o_GP);
     double* RB = h->at<double>(P.o_RB);
-    const FusedNbr fn = fused_nbr(h, opkind);
-    const float2* aux = h->at<float2>(P.o_aux);
     size_t e = h->ev_begin(KC_PROJECT, s);
-    const int* nbr = h->at<int>(P.o_nbr);
-    hipLaunchKernelGGL((k_fused_f32<NP, true>), dim3(P.fused_blocks), dim3(kFusedThreads), P.lds_p, s, h->geom, fn,
-                       (const DevState*)st, (const float*)h->Zc(), (const float*)h->at<float>(P.o_Gsw), (float*)nullptr,
-                       aux, nbr, GP, P.fused_tiles);
+    launch_fused_project<NP>(h, opkind, s);
     h->ev_end(e, s);
     e = h->ev_begin(KC_TREE, s);
     hipLaunchKernelGGL((k_sum_gram<NP>), dim3((gram_blocks(NP) * 256 + 31) / 32), dim3(256), 0, s, (const double*)GP,
@@ -802,9 +831,7 @@ tt_status round_fused_t(tt_handle* h, int opkind, double tol, int cap, hipStream
                        h->at<float>(P.o_Gfold), NO);
     h->ev_end(e, s);
     e = h->ev_begin(KC_OUTPUT, s);
-    hipLaunchKernelGGL((k_fused_f32<NO, false>), dim3(P.fused_blocks_o), dim3(kFusedThreads), P.lds_o, s, h->geom, fn,
-                       (const DevState*)st, (const float*)h->Zc(), (const float*)h->at<float>(P.o_Gfold),
-                       (float*)h->Zn(), aux, nbr, (double*)nullptr, P.fused_tiles);
+    launch_fused_output<NO>(h, opkind, s);
     h->ev_end(e, s);
     hipLaunchKernelGGL(k_commit, dim3(1), dim3(64), 0, s, st);
     HIP_TRY(hipGetLastError());
@@ -829,12 +856,13 @@ void launch_mm_f64(tt_handle* h, const OpDesc& op, const double* A, const double
     const Plan& P = h->P;
     // one row tile per wave where two would spill: 128 columns, or 64 with the fused Gram
     constexpr int RT = (NCT == 8 || (NCT == 4 && GRAM)) ? 1 : 2;
+    const int nb = MODE == MODE_OUTPUT ? P.f64_blocks_o : P.f64_blocks;
     if (MODE == MODE_PROJECT && op.hll)
-        hipLaunchKernelGGL((k_mm_f64<MODE, NCT, GRAM, RT, true>), dim3(P.f64_blocks), dim3(kF64Threads),
+        hipLaunchKernelGGL((k_mm_f64<MODE, NCT, GRAM, RT, true>), dim3(nb), dim3(kF64Threads),
                            f64_lds_bytes(NCT, GRAM, RT, true), s, h->geom, op, (const DevState*)h->st(), A, Gop, Out,
                            h->rowdata(), parts);
     else
-        hipLaunchKernelGGL((k_mm_f64<MODE, NCT, GRAM, RT>), dim3(P.f64_blocks), dim3(kF64Threads),
+        hipLaunchKernelGGL((k_mm_f64<MODE, NCT, GRAM, RT>), dim3(nb), dim3(kF64Threads),
                            f64_lds_bytes(NCT, GRAM, RT), s, h->geom, op, (const DevState*)h->st(), A, Gop, Out,
                            h->rowdata(), parts);
 }
@@ -867,36 +895,32 @@ void output_f64(tt_handle* h, const OpDesc& op, hipStream_t s) {
     }
 }
 
-// One rounding pass applying operator `op` (OP_NONE: plain rounding).
+// Small-core QR of Theta and Phi, L_Theta and the gather operand of
+// operator `opkind` for the current state (k_prep).
 template <typename T>
-tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t s) {
+void launch_prep(tt_handle* h, int opkind, hipStream_t s) {
+    const Plan& P = h->P;
+    constexpr bool f32 = std::is_same<T, float>::value;
+    const bool fused = f32 && P.fused;
+    hipLaunchKernelGGL(k_prep<T>, dim3(1), dim3(kSmallThreads), kSmallLdsBytes, s, h->geom, h->ops[opkind], h->st(),
+                       h->Thc(), h->Phc(), h->at<double>(P.o_gtab), h->at<double>(P.o_htab), h->scratch(),
+                       h->at<double>(P.o_LTh), P.k1cap, h->at<double>(P.o_QTh), h->at<double>(P.o_QPh),
+                       h->at<T>(P.o_G), fused ? h->at<T>(P.o_Gsw) : (T*)nullptr, P.nct_p);
+}
+
+// The projection B = Z_new L_Theta into the stored first core (every path but
+// the fused FP32 one); with FP64 MFMA contractions on the Gram route and at
+// most 64 columns, the FP64 Gram partials of B come with it (in RA).
+template <typename T>
+tt_status launch_project(tt_handle* h, int opkind, hipStream_t s) {
     const Plan& P = h->P;
     const OpDesc& op = h->ops[opkind];
     DevState* st = h->st();
-    SmallScratch sc = h->scratch();
     T* Gop = h->at<T>(P.o_G);
     T* B = h->at<T>(P.o_B);
-    T* V = h->at<T>(P.o_V);
-    double* LTh = h->at<double>(P.o_LTh);
-    double* QTh = h->at<double>(P.o_QTh);
-    double* QPh = h->at<double>(P.o_QPh);
-    size_t e;
-
     constexpr bool f32 = std::is_same<T, float>::value;
-    const bool fused = f32 && P.fused;
-    T* Gsw = fused ? h->at<T>(P.o_Gsw) : nullptr;
-    T* Gfold = fused ? h->at<T>(P.o_Gfold) : nullptr;
-    e = h->ev_begin(KC_PREP, s);
-    hipLaunchKernelGGL(k_prep<T>, dim3(1), dim3(kSmallThreads), kSmallLdsBytes, s, h->geom, op, st, h->Thc(), h->Phc(),
-                       h->at<double>(P.o_gtab), h->at<double>(P.o_htab), sc, LTh, P.k1cap, QTh, QPh, Gop, Gsw, P.nct_p);
-    h->ev_end(e, s);
-    if constexpr (f32) {
-        if (fused) return round_fused(h, opkind, tol, cap, s);
-    }
-
     const unsigned gx = (unsigned)((P.M + 63) / 64);
     const unsigned gx128 = (unsigned)((P.M + 127) / 128);
-    e = h->ev_begin(KC_PROJECT, s);
     if constexpr (f32) {
         if (P.bf16x) {
             __bf16* gh = h->at<__bf16>(P.o_Gh);
@@ -927,6 +951,68 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
     } else
         hipLaunchKernelGGL((k_gather_gemm<T, MODE_PROJECT>), dim3(gx, (P.ldbcap + 63) / 64), dim3(256), 0, s, h->geom,
                            op, st, (const T*)h->Zc(), (const T*)Gop, B, h->rowdata());
+    return TT_OK;
+}
+
+// FP64 Gram partials of the stored first core B, one per block of P.Pg (each
+// over P.rowsg rows), into RA.  Not used where the projection forms them.
+template <typename T>
+void launch_gram_parts(tt_handle* h, hipStream_t s) {
+    const Plan& P = h->P;
+    const DevState* st = h->st();
+    const T* B = h->at<T>(P.o_B);
+    double* RA = h->at<double>(P.o_RA);
+    if constexpr (std::is_same<T, double>::value) {
+        if (P.f64mm) {   // 128 columns
+            hipLaunchKernelGGL(k_gram_f64_mfma_w8d, dim3(P.Pg), dim3(256), 0, s, (const double*)B, st, P.M, P.rowsg,
+                               RA);
+            return;
+        }
+    } else {
+        if (P.KP == 128) {
+            hipLaunchKernelGGL(k_gram_f64_mfma_w8, dim3(P.Pg), dim3(256), 0, s, (const float*)B, st, P.M, P.rowsg, RA);
+            return;
+        }
+        if (P.KP == 64) {
+            hipLaunchKernelGGL(k_gram_f64_mfma, dim3(P.Pg), dim3(256), 0, s, (const float*)B, st, P.M, P.rowsg, RA);
+            return;
+        }
+    }
+    if (P.KP == 64)
+        hipLaunchKernelGGL((k_gram<T, 64>), dim3(P.Pg), dim3(256), 0, s, B, st, P.M, P.rowsg, RA);
+    else
+        hipLaunchKernelGGL((k_gram<T, 128>), dim3(P.Pg), dim3(256), 0, s, B, st, P.M, P.rowsg, RA);
+}
+
+// One rounding pass applying operator `op` (OP_NONE: plain rounding).
+template <typename T>
+tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t s) {
+    const Plan& P = h->P;
+    const OpDesc& op = h->ops[opkind];
+    DevState* st = h->st();
+    SmallScratch sc = h->scratch();
+    T* Gop = h->at<T>(P.o_G);
+    T* B = h->at<T>(P.o_B);
+    T* V = h->at<T>(P.o_V);
+    double* QTh = h->at<double>(P.o_QTh);
+    double* QPh = h->at<double>(P.o_QPh);
+    size_t e;
+
+    constexpr bool f32 = std::is_same<T, float>::value;
+    e = h->ev_begin(KC_PREP, s);
+    launch_prep<T>(h, opkind, s);
+    h->ev_end(e, s);
+    if constexpr (f32) {
+        if (P.fused) return round_fused(h, opkind, tol, cap, s);
+    }
+
+    const unsigned gx = (unsigned)((P.M + 63) / 64);
+    const unsigned gx128 = (unsigned)((P.M + 127) / 128);
+    e = h->ev_begin(KC_PROJECT, s);
+    {
+        const tt_status r = launch_project<T>(h, opkind, s);
+        if (r != TT_OK) return r;
+    }
     h->ev_end(e, s);
 
     const double* RB = nullptr;
@@ -972,9 +1058,7 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
         // for up to 64 columns, else the 128-column FP64 MFMA Gram over B
         gram = 1;
         e = h->ev_begin(KC_FACTOR, s);
-        if (P.nct_f == 8)
-            hipLaunchKernelGGL(k_gram_f64_mfma_w8d, dim3(P.Pg), dim3(256), 0, s, (const double*)B, (const DevState*)st,
-                               P.M, P.rowsg, RA);
+        if (P.nct_f == 8) launch_gram_parts<T>(h, s);
         h->ev_end(e, s);
         e = h->ev_begin(KC_TREE, s);
         switch (P.nct_f) {
@@ -992,25 +1076,14 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
     } else {
         gram = 1;
         e = h->ev_begin(KC_FACTOR, s);
+        launch_gram_parts<T>(h, s);
+        h->ev_end(e, s);
         if (f32 && P.KP == 128) {
-            hipLaunchKernelGGL(k_gram_f64_mfma_w8, dim3(P.Pg), dim3(256), 0, s, (const float*)B, (const DevState*)st,
-                               P.M, P.rowsg, RA);
-            h->ev_end(e, s);
             e = h->ev_begin(KC_TREE, s);
             hipLaunchKernelGGL(k_sum_gram<8>, dim3((gram_blocks(8) * 256 + 31) / 32), dim3(256), 0, s,
                                (const double*)RA, P.Pg, RBuf, P.KP);
             h->ev_end(e, s);
         } else {
-            if (f32 && P.KP == 64)
-                hipLaunchKernelGGL(k_gram_f64_mfma, dim3(P.Pg), dim3(256), 0, s, (const float*)B, (const DevState*)st,
-                                   P.M, P.rowsg, RA);
-            else if (P.KP == 64)
-                hipLaunchKernelGGL((k_gram<T, 64>), dim3(P.Pg), dim3(256), 0, s, (const T*)B, (const DevState*)st, P.M,
-                                   P.rowsg, RA);
-            else
-                hipLaunchKernelGGL((k_gram<T, 128>), dim3(P.Pg), dim3(256), 0, s, (const T*)B, (const DevState*)st, P.M,
-                                   P.rowsg, RA);
-            h->ev_end(e, s);
             e = h->ev_begin(KC_TREE, s);
             const int n = P.KP * P.KP;
             hipLaunchKernelGGL(k_sum_parts, dim3((n + 31) / 32), dim3(256), 0, s, (const double*)RA, P.Pg, n, RBuf);
@@ -1437,6 +1510,293 @@ SmallSolve small_desc(tt_handle* h, int n_steps) {
 }
 
 // ---------------------------------------------------------------------------
+// Launch-shape tuning
+// ---------------------------------------------------------------------------
+//
+// The persistent contraction kernels (FP64 MFMA projection and output, fused
+// FP32 projection + Gram and output) and the Gram of a stored first core take
+// their grid from the plan.  How many blocks run best depends on the shape
+// (rows, columns, K) and on how many blocks of the kernel fit a CU at its
+// register and LDS use, so the tuner times candidate grids on the handle's
+// own state and keeps the fastest, and a cache file keyed by device and shape
+// saves the timing next time.
+namespace {
+
+struct TuneUse {
+    bool project, output, gram;
+};
+
+// Which tunable kernels the plan's rounding pass launches.
+TuneUse tune_use(const tt_handle* h) {
+    const Plan& P = h->P;
+    TuneUse u{false, false, false};
+    u.project = u.output = P.f64mm || P.fused;
+    u.gram = h->round_method != TT_ROUND_QR && !P.fused && !(P.f64mm && P.nct_f <= 4);
+    return u;
+}
+
+void launch_current(const tt_handle* h, tt_tuning* t) {
+    const Plan& P = h->P;
+    const TuneUse u = tune_use(h);
+    *t = tt_tuning{};
+    t->project_blocks = !u.project ? 0 : (P.f64mm ? P.f64_blocks : P.fused_blocks);
+    t->output_blocks = !u.output ? 0 : (P.f64mm ? P.f64_blocks_o : P.fused_blocks_o);
+    t->gram_blocks = u.gram ? P.Pg : 0;
+}
+
+void launch_maximum(const tt_handle* h, tt_tuning* t) {
+    const Plan& P = h->P;
+    const TuneUse u = tune_use(h);
+    *t = tt_tuning{};
+    t->project_blocks = !u.project ? 0 : (P.f64mm ? P.f64_blocks_max : P.fused_blocks_max);
+    t->output_blocks = !u.output ? 0 : (P.f64mm ? P.f64_blocks_max : P.fused_blocks_max);
+    t->gram_blocks = u.gram ? P.Pg_max : 0;
+}
+
+// Rows per Gram block for about `nb` blocks: a multiple of 16, at least 64.
+long long gram_rows_for(const Plan& P, int nb) {
+    long long rows = std::max<long long>(64, (P.M + nb - 1) / nb);
+    return (rows + 15) / 16 * 16;
+}
+
+// Check the shapes of `t` (0: keep) against the plan; message on failure.
+bool launch_valid(const tt_handle* h, const tt_tuning& t, std::string* why) {
+    tt_tuning mx;
+    launch_maximum(h, &mx);
+    auto check = [&](int v, int m, const char* name) {
+        if (v == 0) return true;
+        if (m == 0) {
+            *why = std::string("this plan launches no tunable ") + name + " kernel";
+            return false;
+        }
+        if (v < 1 || v > m) {
+            *why = std::string(name) + " blocks must be in [1, " + std::to_string(m) + "], got " + std::to_string(v);
+            return false;
+        }
+        return true;
+    };
+    return check(t.project_blocks, mx.project_blocks, "projection") &&
+           check(t.output_blocks, mx.output_blocks, "output") && check(t.gram_blocks, mx.gram_blocks, "Gram");
+}
+
+// Set the shapes of `t` (0: keep); `t` must be valid.
+void launch_apply(tt_handle* h, const tt_tuning& t) {
+    Plan& P = h->P;
+    if (t.project_blocks > 0) (P.f64mm ? P.f64_blocks : P.fused_blocks) = t.project_blocks;
+    if (t.output_blocks > 0) (P.f64mm ? P.f64_blocks_o : P.fused_blocks_o) = t.output_blocks;
+    if (t.gram_blocks > 0) {
+        P.rowsg = gram_rows_for(P, t.gram_blocks);
+        P.Pg = (int)((P.M + P.rowsg - 1) / P.rowsg);
+    }
+}
+
+// Cache key: the device and the problem's shape (the plan's caps, not the
+// current ranks), so that a new handle of the same problem finds the grids
+// tuned at another handle's steady state.
+std::string tune_key(const tt_handle* h, int opkind) {
+    const Plan& P = h->P;
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    int cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        cus = prop.multiProcessorCount;
+    }
+    for (char& c : arch)
+        if (c == ' ' || c == '\t' || c == '\n') c = '_';
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s/cu%d/prec%d/route%d/M%lld/G%d/dim%d/ang%dx%d/cap%d/R1cap%d/k1cap%d/fused%d/hll%d",
+             arch.c_str(), cus, h->precision, h->round_method, P.M, P.G, P.dim, P.nt, P.np, P.cap, P.R1cap,
+             P.k1cap, P.fused ? 1 : 0, h->ops[opkind].hll ? 1 : 0);
+    return buf;
+}
+
+// The last entry for `key` in the cache file (lines "key project output gram").
+bool cache_lookup(const char* path, const std::string& key, tt_tuning* out) {
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[1024], k[600];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        int a = 0, b = 0, c = 0;
+        if (sscanf(line, "%599s %d %d %d", k, &a, &b, &c) == 4 && key == k) {
+            *out = tt_tuning{};
+            out->project_blocks = a;
+            out->output_blocks = b;
+            out->gram_blocks = c;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+// Average duration (ms) of one launch of `launch` on `s`: one untimed launch,
+// a timed one that sets the batch size (about 20 ms of launches, at most 20),
+// then the best of two timed batches.
+template <class F>
+tt_status time_launch(F&& launch, hipStream_t s, hipEvent_t e0, hipEvent_t e1, double* out) {
+    float ms = 0.f;
+    launch();
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(e0, s));
+    launch();
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    const int reps = std::max(1, std::min(20, (int)(20.0 / std::max(ms, 1e-3f))));
+    double best = ms;
+    for (int b = 0; b < 2; ++b) {
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int i = 0; i < reps; ++i) launch();
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        best = std::min(best, (double)ms / reps);
+    }
+    HIP_TRY(hipGetLastError());
+    *out = best;
+    return TT_OK;
+}
+
+// Grid candidates up to `maxb`, the default first.
+std::vector<int> grid_candidates(int def, int maxb) {
+    static const int base[] = {64, 128, 192, 256, 384, 512, 768, 1024};
+    std::vector<int> c{def};
+    for (int b : base)
+        if (b <= maxb && b != def) c.push_back(b);
+    return c;
+}
+
+// Time every candidate of one kernel (`set` installs a shape, `run` launches
+// the kernel) and keep the fastest, unless it is within 2 % of the default.
+template <class Set, class Run>
+tt_status tune_one(const std::vector<int>& cand, Set&& set, Run&& run, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                   int* best_out, double* best_ms, double* def_ms) {
+    std::vector<double> t(cand.size(), 0.0);
+    for (size_t i = 0; i < cand.size(); ++i) {
+        set(cand[i]);
+        const tt_status r = time_launch(run, s, e0, e1, &t[i]);
+        if (r != TT_OK) return r;
+    }
+    size_t b = 0;
+    for (size_t i = 1; i < cand.size(); ++i)
+        if (t[i] < t[b]) b = i;
+    if (b != 0 && t[b] > 0.98 * t[0]) b = 0;
+    set(cand[b]);
+    *best_out = cand[b];
+    *best_ms = t[b];
+    *def_ms = t[0];
+    return TT_OK;
+}
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+template <typename T>
+tt_status tune_impl(tt_handle* h, const char* cache, tt_tuning* out, hipStream_t s) {
+    Plan& P = h->P;
+    const TuneUse u = tune_use(h);
+    const int opkind = h->step_order == 1 ? OP_TRANSPORT : OP_FULL;
+    const OpDesc& op = h->ops[opkind];
+    const std::string key = tune_key(h, opkind);
+    if (cache) {
+        tt_tuning c;
+        std::string why;
+        if (cache_lookup(cache, key, &c) && launch_valid(h, c, &why)) {
+            launch_apply(h, c);
+            launch_current(h, out);
+            out->from_cache = 1;
+            return TT_OK;
+        }
+        FILE* f = fopen(cache, "a");
+        if (!f) return fail(TT_ERR_INVALID_ARG, std::string("cannot write the tuning cache ") + cache);
+        fclose(f);
+    }
+    // the gather operand and the pending sum's shapes for the current state
+    // (the next rounding pass recomputes the same)
+    launch_prep<T>(h, opkind, s);
+    HIP_TRY(hipGetLastError());
+    EventPair ev;
+    HIP_TRY(hipEventCreate(&ev.a));
+    HIP_TRY(hipEventCreate(&ev.b));
+    tt_tuning res;
+    launch_current(h, &res);
+    tt_tuning mx;
+    launch_maximum(h, &mx);
+    tt_status r = TT_OK;
+    if (u.project) {
+        auto set = [&](int nb) { (P.f64mm ? P.f64_blocks : P.fused_blocks) = nb; };
+        auto run = [&]() {
+            if (P.f64mm)
+                (void)launch_project<T>(h, opkind, s);
+            else if (P.nct_p == 4)
+                launch_fused_project<4>(h, opkind, s);
+            else
+                launch_fused_project<2>(h, opkind, s);
+        };
+        r = tune_one(grid_candidates(res.project_blocks, mx.project_blocks), set, run, s, ev.a, ev.b,
+                     &res.project_blocks, &res.project_ms, &res.project_ms_default);
+        if (r != TT_OK) return r;
+    }
+    if (u.gram) {
+        r = launch_project<T>(h, opkind, s);   // B for the Gram
+        if (r != TT_OK) return r;
+        std::vector<int> cand{P.Pg};
+        for (int nb : {256, 384, 512, 768, 1024}) {
+            if (nb > mx.gram_blocks) continue;
+            const long long rows = gram_rows_for(P, nb);
+            const int pg = (int)((P.M + rows - 1) / rows);
+            if (std::find(cand.begin(), cand.end(), pg) == cand.end()) cand.push_back(pg);
+        }
+        auto set = [&](int nb) {
+            P.rowsg = gram_rows_for(P, nb);
+            P.Pg = (int)((P.M + P.rowsg - 1) / P.rowsg);
+        };
+        auto run = [&]() { launch_gram_parts<T>(h, s); };
+        r = tune_one(cand, set, run, s, ev.a, ev.b, &res.gram_blocks, &res.gram_ms, &res.gram_ms_default);
+        if (r != TT_OK) return r;
+    }
+    if (u.output) {
+        auto set = [&](int nb) { (P.f64mm ? P.f64_blocks_o : P.fused_blocks_o) = nb; };
+        auto run = [&]() {
+            if (P.f64mm)
+                output_f64(h, op, s);
+            else if (P.nct_o == 4)
+                launch_fused_output<4>(h, opkind, s);
+            else
+                launch_fused_output<2>(h, opkind, s);
+        };
+        r = tune_one(grid_candidates(res.output_blocks, mx.output_blocks), set, run, s, ev.a, ev.b,
+                     &res.output_blocks, &res.output_ms, &res.output_ms_default);
+        if (r != TT_OK) return r;
+    }
+    launch_current(h, out);
+    out->project_ms = res.project_ms;
+    out->output_ms = res.output_ms;
+    out->gram_ms = res.gram_ms;
+    out->project_ms_default = res.project_ms_default;
+    out->output_ms_default = res.output_ms_default;
+    out->gram_ms_default = res.gram_ms_default;
+    out->from_cache = 0;
+    if (cache) {
+        FILE* f = fopen(cache, "a");
+        if (!f) return fail(TT_ERR_INVALID_ARG, std::string("cannot write the tuning cache ") + cache);
+        fprintf(f, "%s %d %d %d\n", key.c_str(), out->project_blocks, out->output_blocks, out->gram_blocks);
+        fclose(f);
+    }
+    return TT_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // Static workspace for tt_transport_create_noalloc
 // ---------------------------------------------------------------------------
 //
@@ -1823,6 +2183,32 @@ tt_status run_steps(tt_handle* h, int n_steps, hipStream_t s) {
     return TT_OK;
 }
 }  // namespace
+
+tt_status tt_transport_tune(tt_handle* h, const char* cache_path, tt_tuning* out, void* stream) {
+    if (!h || !out) return fail(TT_ERR_INVALID_ARG, "tune: NULL handle or out");
+    if (h->pending != OP_NONE) return fail(TT_ERR_STATE, "tune: an unrounded operator is pending");
+    hipStream_t s = (hipStream_t)stream;
+    const tt_status r = h->precision == TT_PREC_FP64 ? tune_impl<double>(h, cache_path, out, s)
+                                                     : tune_impl<float>(h, cache_path, out, s);
+    drop_graphs(h);   // captured graphs hold the old grids
+    return r;
+}
+
+tt_status tt_transport_set_launch(tt_handle* h, const tt_tuning* shapes) {
+    if (!h || !shapes) return fail(TT_ERR_INVALID_ARG, "set_launch: NULL handle or shapes");
+    std::string why;
+    if (!launch_valid(h, *shapes, &why)) return fail(TT_ERR_INVALID_ARG, "set_launch: " + why);
+    launch_apply(h, *shapes);
+    drop_graphs(h);
+    return TT_OK;
+}
+
+tt_status tt_transport_get_launch(tt_handle* h, tt_tuning* current, tt_tuning* maximum) {
+    if (!h) return fail(TT_ERR_INVALID_ARG, "get_launch: NULL handle");
+    if (current) launch_current(h, current);
+    if (maximum) launch_maximum(h, maximum);
+    return TT_OK;
+}
 
 tt_status tt_transport_set_graph(tt_handle* h, int on) {
     if (!h) return fail(TT_ERR_INVALID_ARG, "handle is NULL");

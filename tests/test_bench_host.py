@@ -1,7 +1,8 @@
 """Host-side helpers of bench.py whose outputs are reported numbers: the TT
 difference of two solutions (through the R factor of the stacked first cores,
 no full tensor), the
-kernel-source hash that keys the stored traffic counters, and the refusal of
+kernel-source hash and projection grid that key the stored traffic counters,
+and the refusal of
 more than one GPU."""
 import os
 import subprocess
@@ -54,3 +55,17 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)
+
+
+def test_stored_traffic_requires_the_profiled_grid(tmp_path, monkeypatch):
+    # counters taken at one projection grid do not describe another
+    import json
+    f = tmp_path / "traffic.json"
+    f.write_text(json.dumps({"source_hash": bench.kernel_source_hash(), "project_blocks": 256,
+                             "fetch_bytes": 1.0, "write_bytes": 2.0}))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.stored_traffic() is not None
+    assert bench.stored_traffic(256) is not None
+    assert bench.stored_traffic(512) is None
+    f.write_text(json.dumps({"source_hash": "0" * 16, "project_blocks": 256}))
+    assert bench.stored_traffic(256) is None

@@ -57,6 +57,7 @@ def test_struct_layout_matches_header(tt):
     assert _field_names(text, "tt_problem") == [f for f, _ in tt.TTProblem._fields_]
     assert _field_names(text, "tt_stats") == [f for f, _ in tt.TTStats._fields_]
     assert _field_names(text, "tt_internal_ranks") == [f for f, _ in tt.TTInternalRanks._fields_]
+    assert _field_names(text, "tt_tuning") == [f for f, _ in tt.TTTuning._fields_]
 
 
 @pytest.mark.parametrize("T", [0.0, 0.03, 0.1, 1.0, 2.7696])
