@@ -230,9 +230,15 @@ typedef struct tt_stats {
                              dropped (0 for the other methods)                       */
     double k_s_impl;      /* this library's peak storage in the last pass (input Z,
                              stored projected core M x k1 unless the pass is
-                             fused, output Z, the R1 x N_theta x R2 core) over the
+                             fused, and Y = Z W beside it when the pass projected
+                             in direction space, output Z, the R1 x N_theta x R2
+                             core) over the
                              entries of the rounded TT; the TT sum itself is
                              never formed                                             */
+    int direction_space_rounds; /* rounding passes since create / reset whose
+                             projection ran in direction space (FP64 data,
+                             128-column cores, both small-core factors square):
+                             Y = Z W, then the operator's stencil on Y          */
 } tt_stats;
 
 /* Internal delta-ranks of the combined core Z (section "Internal structure of

@@ -88,6 +88,7 @@ class TTStats(ctypes.Structure):
         ("sketch_r1", ctypes.c_int),
         ("sketch_r2", ctypes.c_int),
         ("k_s_impl", ctypes.c_double),
+        ("direction_space_rounds", ctypes.c_int),
     ]
 
     def as_dict(self) -> dict:
@@ -98,6 +99,7 @@ class TTStats(ctypes.Structure):
         d["medium_energy"] = self.medium_energy
         d["sketch_r1"], d["sketch_r2"] = self.sketch_r1, self.sketch_r2
         d["k_s_impl"] = self.k_s_impl
+        d["direction_space_rounds"] = self.direction_space_rounds
         return d
 
 

@@ -95,7 +95,8 @@ __device__ inline double row_scale(const Geom& g, const OpDesc& op, const RowDat
 //                sum without forming Z_new (Appendix A operator terms).
 // MODE_OUTPUT:   Z_out = B V_r (plain contraction, K = ldb).
 // 64 x 64 output tile per 256-thread block, K staged through LDS in chunks of 8.
-enum { MODE_PROJECT = 0, MODE_OUTPUT = 1 };
+// MODE_ANGLE: Y = Z W of the direction-space projection (k_mm_f64 only)
+enum { MODE_PROJECT = 0, MODE_OUTPUT = 1, MODE_ANGLE = 2 };
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_gather_gemm(Geom g, OpDesc op, const DevState* __restrict__ st,

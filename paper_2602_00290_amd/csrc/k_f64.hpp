@@ -48,10 +48,16 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 // per-(term, shift) blocks.
 __host__ __device__ constexpr int f64_nbr_rows(bool hll) { return hll ? kMaxBlocks : kMaxTerms + 1; }
 
-// Dynamic LDS bytes of k_mm_f64<.., NCT, GRAM, RT, HLL>: two operand buffers
-// and the row data of 128 RT rows (the Gram reduction at the end reuses the
-// space).
-__host__ __device__ inline size_t f64_lds_bytes(int nct, bool gram, int rt, bool hll = false) {
+// Chunks of the resident operand of the output (V_r, K = ldb <= 128) and of
+// Y = Z W (W, K = ldz <= 64).
+constexpr int kF64OutChunks = 128 / kF64KC;
+constexpr int kF64AngChunks = 64 / kF64KC;
+
+// Dynamic LDS bytes of k_mm_f64<MODE, NCT, GRAM, RT, HLL>: the projection's
+// two operand buffers and the row data of 128 RT rows (the Gram reduction at
+// the end reuses the space); the output's whole operand.
+__host__ __device__ inline size_t f64_lds_bytes(int nct, bool gram, int rt, bool hll = false, int out_chunks = 0) {
+    if (out_chunks > 0) return (size_t)out_chunks * 16 * nct * kF64LdK * sizeof(double);
     const size_t nrow = (size_t)16 * rt * kF64Waves;
     const size_t op = (size_t)2 * 16 * nct * kF64LdK * sizeof(double);
     const size_t rows = nrow * (sizeof(double) + f64_nbr_rows(hll) * sizeof(int)) +
@@ -102,10 +108,16 @@ __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const
         s_gwk[tid] = op.gwk[tid];
         s_r1hll[tid] = op.r1hll[tid];
     }
+    // the gathered projection stands aside for the direction-space one, and
+    // Y = Z W is formed only for it (uniform exits)
+    if (MODE == MODE_PROJECT && st->stencil) return;
+    if (MODE == MODE_ANGLE && !st->stencil) return;
     int lda, K, KG, ldo, nblk, kper, ldg;
     if (MODE == MODE_PROJECT) {
         lda = st->ldz; kper = st->ldz; nblk = op.n_gather; KG = nblk * kper; K = st->kall; ldo = st->ldb;
         ldg = st->ldb;
+    } else if (MODE == MODE_ANGLE) {
+        lda = st->ldz; kper = st->ldz; nblk = 1; KG = kper; K = kper; ldo = st->ldb; ldg = st->ldb;
     } else {
         lda = st->ldb; kper = st->ldb; nblk = 1; KG = kper; K = kper; ldo = st->ldzn; ldg = st->ldzn;
     }
@@ -186,6 +198,103 @@ __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const
         }
     };
     const int n_grp = (K + 15) >> 4;   // 16-K groups with data (the last chunk may hold one)
+
+    if constexpr (MODE != MODE_PROJECT) {
+        // Z_out = B V_r (or Y = Z W).  V_r (K = ldb <= 128 rows) stays in LDS for the whole
+        // kernel, chunk after chunk as staged, so the row-block loop has no
+        // barrier: each lane streams its A fragments (four consecutive K of
+        // one row of B) straight from memory two 16-K groups ahead, across
+        // row-block boundaries, and the waves run independently.
+        for (int kc = 0; kc < n_kc; ++kc) {
+            fetch_op(kc);
+            store_op(Bs0 + (size_t)kc * NP * kF64LdK);
+        }
+        __syncthreads();
+        // groups per row block, even (the staged chunks hold two each; groups
+        // past K read zeros), so that the two prefetch slots alternate with
+        // the group's parity
+        const int ng = 2 * n_kc;
+        f64x2 rq[2][RT][2];
+        auto fetch_o = [&](long long rb, int t, f64x2 (&dst)[RT][2]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                const long long row = rb * ROWS + 16 * RT * w + 16 * rt + m;
+                const int k = 16 * t + 4 * q;
+                f64x2 v0 = (f64x2){0.0, 0.0}, v1 = v0;
+                if (rb < rb_end && row < g.M && k < K) {
+                    const double* ap = A + row * lda + k;
+                    v0 = *reinterpret_cast<const f64x2*>(ap);
+                    v1 = *reinterpret_cast<const f64x2*>(ap + 2);
+                }
+                dst[rt][0] = v0;
+                dst[rt][1] = v1;
+            }
+        };
+        // group t of row block rb with this slot's fragments, then the slot
+        // takes the group two ahead (into the next row block past the end)
+        auto group = [&](long long rb, int t, f64x2 (&slot)[RT][2], f64x4 (&acc)[RT][NCT])
+                         __attribute__((always_inline)) {
+            f64x2 a[RT][2];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                a[rt][0] = slot[rt][0];
+                a[rt][1] = slot[rt][1];
+            }
+            if (t + 2 < ng)
+                fetch_o(rb, t + 2, slot);
+            else
+                fetch_o(rb + 1, t + 2 - ng, slot);
+            const double* Bs = Bs0 + (size_t)(t >> 1) * NP * kF64LdK + 16 * (t & 1);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                double bv[NCT];
+#pragma unroll
+                for (int c = 0; c < NCT; ++c) bv[c] = Bs[(size_t)(16 * c + m) * kF64LdK + 4 * q + e];
+#pragma unroll
+                for (int c = 0; c < NCT; ++c)
+#pragma unroll
+                    for (int rt = 0; rt < RT; ++rt)
+                        acc[rt][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt][e >> 1][e & 1], bv[c], acc[rt][c],
+                                                                          0, 0, 0);
+            }
+        };
+        if (ng > 0) {
+            fetch_o(rb_begin, 0, rq[0]);
+            fetch_o(rb_begin, 1, rq[1]);
+        }
+        for (long long rb = rb_begin; rb < rb_end; ++rb) {
+            f64x4 acc[RT][NCT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int c = 0; c < NCT; ++c) acc[rt][c] = (f64x4){0.0, 0.0, 0.0, 0.0};
+            for (int t = 0; t < ng; t += 2) {
+                group(rb, t, rq[0], acc);
+                group(rb, t + 1, rq[1], acc);
+            }
+            const long long row0 = rb * ROWS;
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const long long row = row0 + 16 * RT * w + 16 * rt + 4 * r + q;
+                    // Y is stored group-major (row grp N_X + cell), where the
+                    // stencil's neighbours are 1, n_x and n_x n_y rows apart
+                    long long orow = row;
+                    if (MODE == MODE_ANGLE && row < g.M) {
+                        int grp = 0;
+                        const int cell = divmod_d((int)row, g.G, rG, grp);
+                        orow = (long long)grp * (g.M / g.G) + cell;
+                    }
+#pragma unroll
+                    for (int c = 0; c < NCT; ++c) {
+                        const int col = 16 * c + m;
+                        if (row < g.M && col < ldo) Out[orow * ldo + col] = acc[rt][c][r];
+                    }
+                }
+        }
+        return;
+    }
 
     for (long long rb = rb_begin; rb < rb_end; ++rb) {
         const long long row0 = rb * ROWS;
@@ -363,6 +472,147 @@ __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const
 #pragma unroll
                 for (int r = 0; r < 4; ++r) outp[(bi * 4 + r) * 64 + l] = gacc[bi][r];
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Projection in direction space
+// ---------------------------------------------------------------------------
+//
+// When both small-core factors are square (k2 = N_phi and k1 = N_theta N_phi,
+// the steady state once the sum's ranks exceed the angle counts), the columns
+// of L_Theta are the directions (theta, phi), and block t of the pending
+// sum's angular core is the state's angular matrix W = Theta x_3 Phi
+// (r1 x N_theta N_phi) scaled per direction by the term's factors
+// g_t(theta) h_t(phi).  So B = Z_new L_Theta is
+//   B[k, i] = d_k (sum_j C_j[i] Y[nbr_j(k), i] + sum_q z_q(k) R_q[i]),
+// Y = Z W: one contraction over r1 (k_mm_f64<MODE_ANGLE>) instead of over
+// the n_gather r1 + n_r1 gathered columns, then this kernel: C_j is gather
+// block j's direction factor (the sum of its terms' coefficients times
+// g_t h_t), R_q the direction row of rank-1 block q and z_q(k) its value on
+// row k, d_k the implicit absorption factor, as in the gathered projection.
+
+constexpr int kStWaves = 4;    // waves per block
+constexpr int kStRows = 64;    // rows per wave batch: the lanes set up one row each
+constexpr int kStZ = 8;        // rank-1 blocks at most on this path
+constexpr int kStNG = kMaxTerms + 1;   // gather blocks at most (the row and its shifts)
+
+__global__ __launch_bounds__(64 * kStWaves) void k_stencil_f64(Geom g, OpDesc op, const DevState* __restrict__ st,
+                                                              const double* __restrict__ Y,
+                                                              const double* __restrict__ Cst, double* __restrict__ B,
+                                                              RowData rd) {
+    if (!st->stencil) return;
+    __shared__ double s_R[kStZ * 128];                       // rank-1 direction rows
+    __shared__ int s_nbr[kStWaves][kStNG][kStRows];          // gather rows (-1: none)
+    __shared__ double s_d[kStWaves][kStRows];                // absorption factor
+    __shared__ double s_z[kStWaves][kStZ][kStRows];          // rank-1 values
+    __shared__ int s_row[kStWaves][kStRows];                 // row of B (cell G + grp)
+    const int ldb = st->ldb, ng = op.n_gather, nq = op.n_r1;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    for (int i = tid; i < nq * ldb; i += 64 * kStWaves) {
+        const int q = i / ldb, c = i - q * ldb;
+        s_R[q * 128 + c] = Cst[(size_t)(ng + q) * ldb + c];
+    }
+    // this lane's two columns of the gather blocks' direction factors
+    const int c0 = 2 * l;
+    const bool colok = c0 < ldb;   // ldb is a multiple of 8, so c0 + 1 < ldb too
+    f64x2 cf[kStNG];
+#pragma unroll
+    for (int j = 0; j < kStNG; ++j)
+        cf[j] = (j < ng && colok) ? *reinterpret_cast<const f64x2*>(Cst + (size_t)j * ldb + c0) : (f64x2){0.0, 0.0};
+    __syncthreads();
+
+    // Rows are taken in Y's group-major order (grp N_X + cell), in batches
+    // of 64: each XCD sweeps a contiguous region, its waves taking
+    // consecutive batches in turn, so that the neighbours (1, n_x and
+    // n_x n_y rows away) are read at about the same time by waves sharing
+    // the XCD's L2.  B is written in its own order (cell G + grp).
+    const int nb = gridDim.x, b = blockIdx.x;
+    const long long nbat = (g.M + kStRows - 1) / kStRows;
+    int xcd = 0, nwx = nb * kStWaves, wx = b * kStWaves + w;   // XCD, its waves, this wave's index there
+    long long reg0 = 0, reg1 = nbat;
+    if (nb % 8 == 0) {
+        xcd = b % 8;
+        nwx = (nb / 8) * kStWaves;
+        wx = (b / 8) * kStWaves + w;
+        reg0 = xcd * nbat / 8;
+        reg1 = (xcd + 1) * nbat / 8;
+    }
+    const int NXc = g.nx * g.ny * g.nz;
+    const double rNX = 1.0 / NXc, rnx = 1.0 / g.nx, rny = 1.0 / g.ny;
+    for (long long bt = reg0 + wx; bt < reg1; bt += nwx) {
+        const long long row0 = bt * kStRows;   // group-major
+        {
+            // lane l: row data of group-major row row0 + l (row k of Z and B)
+            const long long kg = row0 + l;
+            const bool ok = kg < g.M;
+            int cell = 0, ix = 0, iy = 0, iz = 0;
+            const int grp = ok ? divmod_d((int)kg, NXc, rNX, cell) : 0;
+            const long long k = (long long)cell * g.G + grp;
+            iy = divmod_d(cell, g.nx, rnx, ix);
+            iz = divmod_d(iy, g.ny, rny, iy);
+            const int idx3[3] = {ix, iy, iz}, n3[3] = {g.nx, g.ny, g.nz};
+            const int st3[3] = {1, g.nx, g.nx * g.ny};
+            for (int j = 0; j < ng; ++j) {
+                int src = ok ? (int)kg : -1;
+                if (j > 0 && ok) {
+                    const int ax = op.gaxis[j], dir = op.gdir[j];
+                    int jj = idx3[ax] + dir;
+                    const bool out = jj < 0 || jj >= n3[ax];
+                    if (out && !g.periodic[ax]) src = -1;
+                    else {
+                        jj = out ? (jj + n3[ax]) % n3[ax] : jj;
+                        src = (int)kg + (jj - idx3[ax]) * st3[ax];
+                    }
+                }
+                s_nbr[w][j][l] = src;
+            }
+            s_row[w][l] = ok ? (int)k : -1;
+            double kap = 0.0;
+            if (ok) kap = rd.kfull ? rd.kfull[k] : rd.kappa0[cell] * rd.kscale[grp];
+            const double ktot = (ok && rd.kscat) ? kap + rd.kscat[k] : kap;
+            s_d[w][l] = (ok && op.scale_d) ? 1.0 / (1.0 + g.cdt * ktot) : 1.0;
+            for (int qq = 0; qq < nq; ++qq) {
+                double v = 0.0;
+                if (ok) {
+                    if (op.r1kind[qq] == 0) {
+                        v = g.cdt * kap * rd.eps[k];
+                        if (rd.kscat) v += g.cdt * rd.kscat[k] * rd.jn[k];
+                    } else {
+                        const int face = op.r1face[qq], ax = face >> 1;
+                        const int edge = (face & 1) ? n3[ax] - 1 : 0;
+                        if (idx3[ax] == edge) v = op.r1coef[qq] * rd.ghost[face * g.G + grp];
+                    }
+                }
+                s_z[w][qq][l] = v;
+            }
+        }
+        // the row data is read by the other lanes of this wave: LDS
+        // operations of a wave complete in order, and the compiler keeps
+        // them in program order across this barrier
+        __builtin_amdgcn_wave_barrier();
+        const int nrow = (int)((g.M - row0) < kStRows ? (g.M - row0) : kStRows);
+        for (int i = 0; i < nrow; ++i) {
+            const long long row = s_row[w][i];
+            f64x2 y[kStNG];
+#pragma unroll
+            for (int j = 0; j < kStNG; ++j) {
+                y[j] = (f64x2){0.0, 0.0};
+                if (j < ng) {
+                    const int src = s_nbr[w][j][i];
+                    if (src >= 0 && colok) y[j] = *reinterpret_cast<const f64x2*>(Y + (size_t)src * ldb + c0);
+                }
+            }
+            f64x2 acc = (f64x2){0.0, 0.0};
+#pragma unroll
+            for (int j = 0; j < kStNG; ++j) acc += cf[j] * y[j];
+            for (int qq = 0; qq < nq; ++qq) {
+                const double z = s_z[w][qq][i];
+                acc += z * *reinterpret_cast<const f64x2*>(s_R + qq * 128 + c0);
+            }
+            if (colok) *reinterpret_cast<f64x2*>(B + (size_t)row * ldb + c0) = acc * s_d[w][i];
+        }
+        __builtin_amdgcn_wave_barrier();   // this batch's row data is read before the next overwrites it
     }
 }
 

@@ -792,7 +792,8 @@ __device__ __forceinline__ void prep_body(const Geom& g, const OpDesc& op, DevSt
                                           const double* __restrict__ htab, const SmallScratch& sc,
                                           double* __restrict__ LTh, int ldl, double* __restrict__ QTh,
                                           double* __restrict__ QPh, TC* __restrict__ Gop, TC* __restrict__ Gsw,
-                                          int nct, double* lds, size_t lds_doubles) {
+                                          int nct, double* lds, size_t lds_doubles,
+                                          double* __restrict__ Wst = nullptr, double* __restrict__ Cst = nullptr) {
     __shared__ double red[16];
     LdsCarver cv{lds, 0, lds_doubles};
     const int nt = g.nt, npn = g.np;
@@ -982,7 +983,46 @@ __device__ __forceinline__ void prep_body(const Geom& g, const OpDesc& op, DevSt
             Gsw[idx] = (row < grows && col < ldb) ? (TC)gval(row, col) : (TC)0;
         }
     }
+    // 4. direction-space form of the projection (both factors square, so the
+    //    columns of L_Theta are the directions (theta, phi)): block t of the
+    //    sum's angular core is W = Theta x_3 Phi scaled by g_t(theta) h_t(phi).
+    //    W (ldz x ldb, zero past r1 and k1), then per gather block j the
+    //    direction factor C_j = sum_t coef(t, j) g_t h_t, then the rank-1
+    //    blocks' direction rows R_q = g h (rows n_gather + q).
+    const bool stencil = Wst && Cst && th_id && phi_id && !op.hll;
+    if (stencil) {
+        for (int idx = threadIdx.x; idx < ldz * ldb; idx += blockDim.x) {
+            const int a = dldb.q(idx), i = idx - a * ldb;
+            double v = 0.0;
+            if (a < r1 && i < k1) {
+                const int l = dnp.q(i), p = i - l * npn;
+                const double* th = thv + ((size_t)a * nt + l) * r2;
+                for (int b = 0; b < r2; ++b) v += th[b] * Ph[(size_t)b * npn + p];
+            }
+            Wst[idx] = v;
+        }
+        for (int idx = threadIdx.x; idx < (op.n_gather + nr1) * ldb; idx += blockDim.x) {
+            const int j = dldb.q(idx), i = idx - j * ldb;
+            double v = 0.0;
+            if (i < k1) {
+                const int l = dnp.q(i), p = i - l * npn;
+                if (j < op.n_gather) {
+                    for (int t = 0; t < nrb; ++t) {
+                        const double gh = gtv[s_rfac[t] * nt + l] * htv[s_rfac[t] * npn + p];
+                        if (j == 0) v += s_rcoef0[t] * gh;
+                        if (s_rshift[t] == j) v += s_rcoef[t] * gh;
+                        if (s_rshift2[t] == j) v += s_rcoef2[t] * gh;
+                    }
+                } else {
+                    const int q = j - op.n_gather;
+                    v = gtv[s_r1fac[q] * nt + l] * htv[s_r1fac[q] * npn + p];
+                }
+            }
+            Cst[idx] = v;
+        }
+    }
     if (threadIdx.x == 0) {
+        st->stencil = stencil ? op.n_gather + nr1 : 0;
         st->kall = grows;
         st->R1 = R1; st->R2 = R2; st->k1 = k1; st->k2 = k2; st->ldb = ldb; st->k1b = k1;
         if (R1 > st->max_R1) st->max_R1 = R1;
@@ -1313,6 +1353,7 @@ __device__ __forceinline__ void svd_chain_body(const Geom& g, DevState* st, cons
         st->k1_prev = k1;
         if (!(norm2 < 1e300) || norm2 != norm2) st->nan_flag = 1;
         st->rounds += 1;
+        if (st->stencil) st->stencil_rounds += 1;
         // B's width (a randomized pass runs the chain on its compressed core)
         const double M = (double)g.M, R1 = (double)st->R1, kk = (double)st->k1b;
         if (Gfold) {
@@ -1323,7 +1364,9 @@ __device__ __forceinline__ void svd_chain_body(const Geom& g, DevState* st, cons
             st->fl[1] += M * kk * (kk + 1.0);
             st->fl[2] += 2.0 * M * R1 * (double)r1n;
         } else {
-            st->fl[0] += 2.0 * M * R1 * kk;
+            // direction-space projection: Y = Z W (K = ldz), then one
+            // multiply-add per gather and rank-1 block
+            st->fl[0] += st->stencil ? 2.0 * M * kk * ((double)st->ldz + st->stencil) : 2.0 * M * R1 * kk;
             st->fl[1] += gram ? M * kk * (kk + 1.0) : 2.0 * M * kk * kk - 2.0 / 3.0 * kk * kk * kk;
             st->fl[2] += 2.0 * M * kk * (double)r1n;
         }
@@ -1340,10 +1383,11 @@ __global__ __launch_bounds__(kSmallThreads) void k_prep(Geom g, OpDesc op, DevSt
                                                         const double* __restrict__ htab, SmallScratch sc,
                                                         double* __restrict__ LTh, int ldl, double* __restrict__ QTh,
                                                         double* __restrict__ QPh, TC* __restrict__ Gop,
-                                                        TC* __restrict__ Gsw, int nct) {
+                                                        TC* __restrict__ Gsw, int nct, double* __restrict__ Wst,
+                                                        double* __restrict__ Cst) {
     extern __shared__ double lds[];
     prep_body<TC>(g, op, st, Th, Ph, gtab, htab, sc, LTh, ldl, QTh, QPh, Gop, Gsw, nct, lds,
-                  (size_t)kSmallLdsBytes / sizeof(double));
+                  (size_t)kSmallLdsBytes / sizeof(double), Wst, Cst);
 }
 
 template <typename TC, bool FAST>

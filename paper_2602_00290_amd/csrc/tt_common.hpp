@@ -45,6 +45,9 @@ struct DevState {
     int k1b;           // columns of the projected core B (k1 until a randomized pass compresses the sum)
     int l1s, l2s;      // ranks of the last randomized compression (after dropping null sketch directions)
     int r1_in;         // first rank of the state the last rounding pass started from
+    int stencil;       // 0, or this pass projects in direction space (Y = Z W, then the operator's
+                       // stencil on Y) with this many direction rows (gather plus rank-1 blocks)
+    int stencil_rounds; // rounding passes so far that projected in direction space
 };
 
 // Static description of the problem shared by all kernels (passed by value).

@@ -106,6 +106,11 @@ struct Plan {
     int f64_blocks = 1;             // blocks of the persistent projection kernel (one Gram partial each when fused)
     int f64_blocks_o = 1;           // blocks of the persistent output kernel
     int f64_blocks_max = 1;         // largest grid of either
+    // direction-space projection (Y = Z W, then the operator's stencil on Y)
+    // for 128-column FP64 cores once both small-core factors are square
+    bool stencil = false;
+    int st_blocks = 1;              // blocks of the stencil kernel
+    size_t o_Y = 0, o_Wst = 0, o_Cst = 0;
     size_t o_state, o_Z0, o_Z1, o_B, o_Th0, o_Th1, o_Ph0, o_Ph1, o_LTh, o_QTh, o_QPh, o_G, o_V, o_RA, o_RB, o_small,
         o_k0, o_ks, o_kfull = 0, o_eps, o_ghost, o_gtab, o_htab, o_ThN, o_PhN, o_sv, o_colsum;
     size_t small_bytes = 0, n_parts_max = 1;
@@ -281,6 +286,9 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         P.f64_blocks = (int)std::max<long long>(1, std::min<long long>(256, nrb));
         if (P.f64_blocks > 8) P.f64_blocks = P.f64_blocks / 8 * 8;
         P.f64_blocks_o = P.f64_blocks;
+        P.stencil = P.f64mm && P.nct_f == 8;
+        P.st_blocks = (int)std::max<long long>(1, std::min<long long>(1024, (P.M + kStRows - 1) / kStRows / kStWaves));
+        if (P.st_blocks > 8) P.st_blocks = P.st_blocks / 8 * 8;
         // launch-shape tuning may take up to four blocks per CU
         P.f64_blocks_max = (int)std::max<long long>(1, std::min<long long>(kTuneMaxBlocks, nrb));
         if (P.f64_blocks_max > 8) P.f64_blocks_max = P.f64_blocks_max / 8 * 8;
@@ -328,6 +336,11 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
     if (P.fused)   // B is not stored; keep a staging buffer for explicit TT-sum reads
         P.B_bytes = std::min<size_t>(P.B_bytes, std::max<size_t>((size_t)16 << 20, (size_t)P.R1cap * sizeof(double)));
     P.o_B = take(P.B_bytes);
+    if (P.stencil) {
+        P.o_Y = take((size_t)P.M * P.ldbcap * sizeof(double));
+        P.o_Wst = take((size_t)P.ldzcap * P.ldbcap * sizeof(double));
+        P.o_Cst = take((size_t)(kStNG + kStZ) * P.ldbcap * sizeof(double));
+    }
     P.bf16x = p->precision == TT_PREC_BF16X;
     if (P.bf16x && P.M >= (1LL << 31))
         return fail(TT_ERR_INVALID_ARG, "split-BF16 contractions need fewer than 2^31 rows of Z");
@@ -863,7 +876,8 @@ void launch_mm_f64(tt_handle* h, const OpDesc& op, const double* A, const double
                            h->rowdata(), parts);
     else
         hipLaunchKernelGGL((k_mm_f64<MODE, NCT, GRAM, RT>), dim3(nb), dim3(kF64Threads),
-                           f64_lds_bytes(NCT, GRAM, RT), s, h->geom, op, (const DevState*)h->st(), A, Gop, Out,
+                           f64_lds_bytes(NCT, GRAM, RT, false, MODE == MODE_OUTPUT ? kF64OutChunks : 0), s, h->geom, op,
+                           (const DevState*)h->st(), A, Gop, Out,
                            h->rowdata(), parts);
 }
 
@@ -897,15 +911,24 @@ void output_f64(tt_handle* h, const OpDesc& op, hipStream_t s) {
 
 // Small-core QR of Theta and Phi, L_Theta and the gather operand of
 // operator `opkind` for the current state (k_prep).
+// Whether operator `opkind`'s projection may run in direction space (the
+// prep then decides per pass: only when both small-core factors are square).
+bool stencil_op(const tt_handle* h, int opkind) {
+    const OpDesc& op = h->ops[opkind];
+    return h->P.stencil && !op.hll && op.n_gather <= kStNG && op.n_r1 <= kStZ;
+}
+
 template <typename T>
 void launch_prep(tt_handle* h, int opkind, hipStream_t s) {
     const Plan& P = h->P;
     constexpr bool f32 = std::is_same<T, float>::value;
     const bool fused = f32 && P.fused;
+    const bool sten = !f32 && stencil_op(h, opkind);
     hipLaunchKernelGGL(k_prep<T>, dim3(1), dim3(kSmallThreads), kSmallLdsBytes, s, h->geom, h->ops[opkind], h->st(),
                        h->Thc(), h->Phc(), h->at<double>(P.o_gtab), h->at<double>(P.o_htab), h->scratch(),
                        h->at<double>(P.o_LTh), P.k1cap, h->at<double>(P.o_QTh), h->at<double>(P.o_QPh),
-                       h->at<T>(P.o_G), fused ? h->at<T>(P.o_Gsw) : (T*)nullptr, P.nct_p);
+                       h->at<T>(P.o_G), fused ? h->at<T>(P.o_Gsw) : (T*)nullptr, P.nct_p,
+                       sten ? h->at<double>(P.o_Wst) : (double*)nullptr, sten ? h->at<double>(P.o_Cst) : (double*)nullptr);
 }
 
 // The projection B = Z_new L_Theta into the stored first core (every path but
@@ -947,6 +970,19 @@ tt_status launch_project(tt_handle* h, int opkind, hipStream_t s) {
                                h->rowdata());
         }
     } else if (P.f64mm) {
+        if (stencil_op(h, opkind)) {
+            // direction space when the prep found both factors square (the
+            // kernels read its flag; otherwise these two exit and the
+            // gathered projection below runs)
+            double* Yb = h->at<double>(P.o_Y);
+            hipLaunchKernelGGL((k_mm_f64<MODE_ANGLE, 8, false, 1>), dim3(P.f64_blocks), dim3(kF64Threads),
+                               f64_lds_bytes(8, false, 1, false, kF64AngChunks), s, h->geom, op, (const DevState*)st,
+                               (const double*)h->Zc(), (const double*)h->at<double>(P.o_Wst), Yb, h->rowdata(),
+                               (double*)nullptr);
+            hipLaunchKernelGGL(k_stencil_f64, dim3(P.st_blocks), dim3(64 * kStWaves), 0, s, h->geom, op,
+                               (const DevState*)st, (const double*)Yb, (const double*)h->at<double>(P.o_Cst),
+                               (double*)B, h->rowdata());
+        }
         project_f64(h, op, h->round_method != TT_ROUND_QR && P.nct_f <= 4, h->at<double>(P.o_RA), s);
     } else
         hipLaunchKernelGGL((k_gather_gemm<T, MODE_PROJECT>), dim3(gx, (P.ldbcap + 63) / 64), dim3(256), 0, s, h->geom,
@@ -1292,6 +1328,7 @@ tt_status fill_stats(tt_handle* h, tt_stats* out, hipStream_t s) {
         out->sketch_r1 = st.l1s;
         out->sketch_r2 = st.l2s;
     }
+    out->direction_space_rounds = st.stencil_rounds;
     out->norm = st.norm;
     out->discarded_rel = st.norm > 0 ? std::sqrt(std::max(st.disc2, 0.0)) / st.norm : 0.0;
     double E = 0.0;
@@ -1323,7 +1360,8 @@ tt_status fill_stats(tt_handle* h, tt_stats* out, hipStream_t s) {
     if (st.rounds > 0 && st.R1 > 0 && st.R2 > 0) {
         const double sum = (double)P.M * st.R1 + (double)P.nt * st.R1 * st.R2 + (double)P.np * st.R2;
         out->k_s = sum / tt;
-        const double bst = P.fused ? 0.0 : (double)P.M * st.k1;
+        // (plus Y = Z W, M x k1, when the pass projected in direction space)
+        const double bst = P.fused ? 0.0 : (double)P.M * st.k1 * (st.stencil ? 2.0 : 1.0);
         const double impl = (double)P.M * (st.r1_in + st.r1) + bst + (double)P.nt * st.R1 * st.R2 +
                             (double)P.np * st.R2;
         out->k_s_impl = impl / tt;
@@ -1901,9 +1939,10 @@ tt_status tt_transport_create(const tt_problem* p, void* dev_workspace, size_t b
                 {(const void*)k_mm_f64<MODE_PROJECT, 4, false, 2>, f64_lds_bytes(4, false, 2)},
                 {(const void*)k_mm_f64<MODE_PROJECT, 4, true, 1>, f64_lds_bytes(4, true, 1)},
                 {(const void*)k_mm_f64<MODE_PROJECT, 8, false, 1>, f64_lds_bytes(8, false, 1)},
-                {(const void*)k_mm_f64<MODE_OUTPUT, 1, false, 2>, f64_lds_bytes(1, false, 2)},
-                {(const void*)k_mm_f64<MODE_OUTPUT, 2, false, 2>, f64_lds_bytes(2, false, 2)},
-                {(const void*)k_mm_f64<MODE_OUTPUT, 4, false, 2>, f64_lds_bytes(4, false, 2)},
+                {(const void*)k_mm_f64<MODE_ANGLE, 8, false, 1>, f64_lds_bytes(8, false, 1, false, kF64AngChunks)},
+                {(const void*)k_mm_f64<MODE_OUTPUT, 1, false, 2>, f64_lds_bytes(1, false, 2, false, kF64OutChunks)},
+                {(const void*)k_mm_f64<MODE_OUTPUT, 2, false, 2>, f64_lds_bytes(2, false, 2, false, kF64OutChunks)},
+                {(const void*)k_mm_f64<MODE_OUTPUT, 4, false, 2>, f64_lds_bytes(4, false, 2, false, kF64OutChunks)},
                 {(const void*)k_mm_f64<MODE_PROJECT, 1, false, 2, true>, f64_lds_bytes(1, false, 2, true)},
                 {(const void*)k_mm_f64<MODE_PROJECT, 1, true, 2, true>, f64_lds_bytes(1, true, 2, true)},
                 {(const void*)k_mm_f64<MODE_PROJECT, 2, false, 2, true>, f64_lds_bytes(2, false, 2, true)},
