@@ -57,8 +57,11 @@ HBM_PEAK_GBS = 8000.0
 
 METRIC = "TT solves/s & TT apply+round GFLOP/s (% MFMA peak); p50/p99 solve latency"
 C3_STEPS_PER_SOLVE = 384
-# the dominant kernel of the headline (FP64 gather projection, 128 columns)
-HEAD_KERNEL = "k_mm_f64<0, 8, false, 1, false>"
+# the dominant kernel of the headline: the direction-space stencil of the
+# FP64 projection (128 columns); beside it Y = Z W and the gathered projection
+HEAD_KERNEL = "k_stencil_f64"
+ANGLE_KERNEL = "k_mm_f64<2, 8, false, 1, false>"
+GATHER_KERNEL = "k_mm_f64<0, 8, false, 1, false>"
 KERNEL_SOURCES = ["paper_2602_00290_amd/csrc/k_f64.hpp", "paper_2602_00290_amd/csrc/k_fused.hpp",
                   "paper_2602_00290_amd/csrc/tt_common.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_clumps3d_fp64.json")
@@ -110,16 +113,19 @@ def cpu_baseline_c3(budget_s: float = 15.0, nz: int = 4):
     }
 
 
-def stored_traffic(project_blocks=None):
+def stored_traffic(project_blocks=None, kernel=None):
     """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, or None if it is missing, was taken on different kernel source, or
-    at a grid other than `project_blocks` (when given)."""
+    summary, or None if it is missing, was taken on different kernel source,
+    for another kernel than `kernel` or at a grid other than `project_blocks`
+    (when given)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("source_hash") != kernel_source_hash():
+        return None
+    if kernel is not None and t.get("kernel") != kernel:
         return None
     if project_blocks is not None and t.get("project_blocks") != project_blocks:
         return None
@@ -165,29 +171,55 @@ def tt_rel_diff(x, y):
     return dn / yn if yn > 0 else dn
 
 
-def roofline_c3(st, M, tuning=None):
-    """Roofline of the dominant kernel (the FP64 MFMA gather projection of the
-    3D headline) from its HIP-event times over the timed steps.  `achieved`
-    counts the first rounding pass as the method defines it, the R factor of
-    the explicit M x R1 sum: 2 M R1^2 - 2/3 R1^3 flops per launch with R1 the
-    sum's rank (450 at the cap); `executed` counts what the kernel runs, the
-    projection onto the k1-column angular row space, 2 M R1 k1."""
+def roofline_c3(st, M, tuning=None, ndir=128):
+    """Roofline of the headline's dominant kernel from its HIP-event times
+    over the timed steps.
+
+    In the steady state the first-core pass runs in direction space: Y = Z W
+    (FP64 MFMA, K = r1) and the operator's stencil on Y, which is the longest
+    kernel of the step and HBM-bound: its algorithmic bytes per launch are one
+    read of Y and one write of B, 2 M k1 8 with k1 = N_theta N_phi.  Beside
+    it, `projection_stage` counts the whole pass as the method defines it, the
+    R factor of the explicit M x R1 sum (2 M R1^2 - 2/3 R1^3 flops per launch,
+    R1 = 450 at the cap), over the time of both kernels, and `executed` the
+    flops they run.  Without direction-space passes the gathered projection
+    is reported by that count as before."""
     ms, n, fl = st["kernel_ms"], st["kernel_launches"], st["flops"]
+    R1 = st["max_R1"]
+    alg = 2.0 * M * R1 * R1 - 2.0 / 3.0 * R1 ** 3
+    peak64 = PEAKS["fp64"]
+    if n.get("stencil") and st.get("direction_space_rounds", 0) > 0 and ms["stencil"] > 0:
+        t_st = ms["stencil"] / n["stencil"] * 1e-3
+        t_ang = ms["angle"] / n["angle"] * 1e-3
+        t_pass = t_st + t_ang
+        byt = 2.0 * M * ndir * 8
+        t = stored_traffic(kernel=HEAD_KERNEL)
+        exe = (fl["angle"] + fl["stencil"]) / n["stencil"]
+        out = {"bound": "hbm", "kernel": HEAD_KERNEL, "achieved": byt / t_st / 1e9, "peak": HBM_PEAK_GBS,
+               "unit": "GB/s", "frac": byt / t_st / 1e9 / HBM_PEAK_GBS,
+               "traffic": (t["fetch_bytes"] + t["write_bytes"]) if t else None,
+               "avg_launch_ms": t_st * 1e3, "launches": n["stencil"], "algorithmic_bytes_per_launch": byt,
+               "projection_stage": {
+                   "kernels": [ANGLE_KERNEL, HEAD_KERNEL], "avg_ms": t_pass * 1e3, "angle_ms": t_ang * 1e3,
+                   "algorithmic_flops_per_launch": alg, "R1": R1, "achieved": alg / t_pass / 1e12, "peak": peak64,
+                   "unit": "TFLOP/s", "frac": alg / t_pass / 1e12 / peak64,
+                   "executed": {"flops_per_launch": exe, "TFLOP_per_s": exe / t_pass / 1e12,
+                                "frac": exe / t_pass / 1e12 / peak64}}}
+        if t:
+            out["traffic_detail"] = {k: t[k] for k in ("fetch_bytes", "write_bytes", "algorithmic_bytes")}
+        return out
     if not n["project"] or not ms["project"]:
         return None
-    R1 = st["max_R1"]
     t_launch = ms["project"] / n["project"] * 1e-3
-    alg = 2.0 * M * R1 * R1 - 2.0 / 3.0 * R1 ** 3
     exe = fl["project"] / n["project"]
-    peak = PEAKS["fp64"]
-    t = stored_traffic(tuning["project_blocks"] if tuning else None)
-    out = {"bound": "mfma", "kernel": HEAD_KERNEL, "achieved": alg / t_launch / 1e12, "peak": peak,
-           "unit": "TFLOP/s", "frac": alg / t_launch / 1e12 / peak,
+    t = stored_traffic(tuning["project_blocks"] if tuning else None, kernel=GATHER_KERNEL)
+    out = {"bound": "mfma", "kernel": GATHER_KERNEL, "achieved": alg / t_launch / 1e12, "peak": peak64,
+           "unit": "TFLOP/s", "frac": alg / t_launch / 1e12 / peak64,
            "traffic": (t["fetch_bytes"] + t["write_bytes"]) if t else None,
            "avg_launch_ms": t_launch * 1e3, "launches": n["project"],
            "algorithmic_flops_per_launch": alg, "R1": R1,
            "executed": {"flops_per_launch": exe, "TFLOP_per_s": exe / t_launch / 1e12,
-                        "frac": exe / t_launch / 1e12 / peak}}
+                        "frac": exe / t_launch / 1e12 / peak64}}
     if t:
         out["traffic_detail"] = {k: t[k] for k in ("fetch_bytes", "write_bytes", "algorithmic_bytes")}
     return out
@@ -445,8 +477,8 @@ def mode_pmc_summary(args):
     p = ti.clumps3d(precision=ti.PREC_FP64)
     out = {
         "kernel": HEAD_KERNEL,
-        "workload": "clumps3d 64^3 FP64 at the rank cap (R1 = 450, k1 = 128, r1 = 64), last "
-                    f"{args.probe_steps} steps of a probe",
+        "workload": "clumps3d 64^3 FP64 at the rank cap (R1 = 450, k1 = 128, r1 = 64), direction-space "
+                    f"projection, last {args.probe_steps} steps of a probe",
         "source_hash": kernel_source_hash(),
         "fetch_bytes": fetch * ff,
         "write_bytes": write * fw,
@@ -454,10 +486,8 @@ def mode_pmc_summary(args):
         # the projection's grid in both counter runs (null if they differ or were not recorded)
         "project_blocks": grids.pop() if len(grids) == 1 else None,
         "calibration": {"copy_bytes": nbytes, "fetch_factor": ff, "write_factor": fw},
-        # the method's minimum for this pass: read the state Z once (M x r1 FP64);
-        # this design also writes the projected core B (M x k1 FP64)
-        "algorithmic_bytes": p.M * 64 * 8,
-        "design_bytes": p.M * (64 + 128) * 8,
+        # the stencil's minimum: read Y = Z W once and write B once (M x k1 FP64 each)
+        "algorithmic_bytes": 2 * p.M * 128 * 8,
         "commands": [f"rocprofv3 --pmc {c} --output-format csv -d <dir>/{s} -o {s} -- python3 bench.py --mode {m}"
                      + (f" --probe-workload clumps3d_fp64 --probe-steps {args.probe_steps}" if m == "probe" else "")
                      for c, s, m in (("FETCH_SIZE", "fetch", "probe"), ("WRITE_SIZE", "write", "probe"),
@@ -789,7 +819,7 @@ def main():
         "workspace_gb": head["workspace_gb"],
         "kernel_ms_per_step": head["kernel_ms_per_step"],
         "tuning": head["tuning"],
-        "roofline": roofline_c3(st64, p64.M, head["tuning"]),
+        "roofline": roofline_c3(st64, p64.M, head["tuning"], p64.n_theta * p64.n_phi),
         "precisions_beside": beside,
     }
     del beside

@@ -215,14 +215,19 @@ typedef struct tt_stats {
                              of the rounded TT; 1 before the first pass          */
     double compression;   /* N_X N_nu N_theta N_phi / TT entries (Section 3.2 eq.)    */
     double seconds;       /* wall time of the last solve (host clock, synchronised)  */
-    double kernel_ms[8];  /* summed HIP-event durations per kernel class when timing
-                             is on: [0] prep, [1] project (first-core contraction),
-                             [2] factor (TSQR or Gram), [3] factor tree / reduce,
-                             [4] small-core SVD chain, [5] output contraction,
-                             [6] diagnostics, [7] source pre-pass (coupled medium
-                             temperature and / or scattering)                       */
-    long long kernel_launches[8]; /* launches counted per class                      */
-    double flops[8];      /* algorithmic flops per class, summed over the solve      */
+    double kernel_ms[10]; /* summed HIP-event durations per kernel class when timing
+                             is on: [0] prep, [1] project (the gathered first-core
+                             contraction; a few microseconds when the pass runs
+                             in direction space), [2] factor (TSQR or Gram),
+                             [3] factor tree / reduce, [4] small-core SVD chain,
+                             [5] output contraction, [6] diagnostics, [7] source
+                             pre-pass (coupled medium temperature and / or
+                             scattering), [8] angle (Y = Z W of the direction-space
+                             projection), [9] stencil (its per-direction stencil;
+                             both launched on every eligible pass, a few
+                             microseconds when the pass is not in direction space) */
+    long long kernel_launches[10]; /* launches counted per class                     */
+    double flops[10];     /* executed flops per class, summed over the solve          */
     double medium_energy; /* dV * heat_capacity * sum_x T[x] (0 when T is fixed); the
                              radiation energy is energy / c                          */
     int sketch_r1, sketch_r2; /* TT_ROUND_RAND: ranks of the last randomized

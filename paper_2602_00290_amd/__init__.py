@@ -24,7 +24,7 @@ TT_ROUND_QR, TT_ROUND_GRAM, TT_ROUND_AUTO, TT_ROUND_RAND = 0, 1, 2, 3
 TT_BC_VACUUM, TT_BC_INFLOW_PLANCK, TT_BC_PERIODIC, TT_BC_INFLOW_VALUES = 0, 1, 2, 3
 TT_FLUX_UPWIND, TT_FLUX_RUSANOV, TT_FLUX_HLL = 0, 1, 2
 
-KERNEL_CLASSES = ("prep", "project", "factor", "tree", "svd", "output", "diag", "couple")
+KERNEL_CLASSES = ("prep", "project", "factor", "tree", "svd", "output", "diag", "couple", "angle", "stencil")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -81,9 +81,9 @@ class TTStats(ctypes.Structure):
         ("k_s", ctypes.c_double),
         ("compression", ctypes.c_double),
         ("seconds", ctypes.c_double),
-        ("kernel_ms", ctypes.c_double * 8),
-        ("kernel_launches", ctypes.c_longlong * 8),
-        ("flops", ctypes.c_double * 8),
+        ("kernel_ms", ctypes.c_double * 10),
+        ("kernel_launches", ctypes.c_longlong * 10),
+        ("flops", ctypes.c_double * 10),
         ("medium_energy", ctypes.c_double),
         ("sketch_r1", ctypes.c_int),
         ("sketch_r2", ctypes.c_int),

@@ -492,7 +492,7 @@ __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const
 // g_t h_t), R_q the direction row of rank-1 block q and z_q(k) its value on
 // row k, d_k the implicit absorption factor, as in the gathered projection.
 
-constexpr int kStWaves = 4;    // waves per block
+constexpr int kStWaves = 16;   // waves per block
 constexpr int kStRows = 64;    // rows per wave batch: the lanes set up one row each
 constexpr int kStZ = 8;        // rank-1 blocks at most on this path
 constexpr int kStNG = kMaxTerms + 1;   // gather blocks at most (the row and its shifts)
@@ -522,97 +522,122 @@ __global__ __launch_bounds__(64 * kStWaves) void k_stencil_f64(Geom g, OpDesc op
         cf[j] = (j < ng && colok) ? *reinterpret_cast<const f64x2*>(Cst + (size_t)j * ldb + c0) : (f64x2){0.0, 0.0};
     __syncthreads();
 
-    // Rows are taken in Y's group-major order (grp N_X + cell), in batches
-    // of 64: each XCD sweeps a contiguous region, its waves taking
-    // consecutive batches in turn, so that the neighbours (1, n_x and
-    // n_x n_y rows away) are read at about the same time by waves sharing
-    // the XCD's L2.  B is written in its own order (cell G + grp).
+    // Rows are taken in Y's group-major order (grp N_X + cell), in batches of
+    // 64.  When an x-y plane is a whole number of batches, a block's task is
+    // one batch position pb of the plane in kStWaves consecutive planes of one
+    // group: wave w takes plane iz0 + w, so most z-neighbours of a wave's
+    // rows are the rows its neighbouring waves load at the same time (the
+    // block's waves keep step by a barrier per task), and consecutive tasks,
+    // dealt to the XCD's blocks in turn, are the next batch positions of the
+    // plane (the y-neighbours when n_x = 64).  Each XCD sweeps a contiguous
+    // region of tasks.  Otherwise the waves take consecutive batches in
+    // turn.  B is written in its own order (cell G + grp).
     const int nb = gridDim.x, b = blockIdx.x;
     const long long nbat = (g.M + kStRows - 1) / kStRows;
-    int xcd = 0, nwx = nb * kStWaves, wx = b * kStWaves + w;   // XCD, its waves, this wave's index there
-    long long reg0 = 0, reg1 = nbat;
-    if (nb % 8 == 0) {
-        xcd = b % 8;
-        nwx = (nb / 8) * kStWaves;
-        wx = (b / 8) * kStWaves + w;
-        reg0 = xcd * nbat / 8;
-        reg1 = (xcd + 1) * nbat / 8;
-    }
     const int NXc = g.nx * g.ny * g.nz;
+    const int plane = g.nx * g.ny;
+    const int PB = (plane % kStRows == 0) ? plane / kStRows : 0;   // batches per plane (0: no tiling)
+    const int nzb = (g.nz + kStWaves - 1) / kStWaves;                // plane blocks per group
+    const long long ntask = PB ? (long long)g.G * nzb * PB : (nbat + kStWaves - 1) / kStWaves;
+    int nbx = nb, bx = b;            // blocks of this XCD, this block's index there
+    long long reg0 = 0, reg1 = ntask;
+    if (nb % 8 == 0) {
+        const int xcd = b % 8;
+        nbx = nb / 8;
+        bx = b / 8;
+        reg0 = xcd * ntask / 8;
+        reg1 = (xcd + 1) * ntask / 8;
+    }
     const double rNX = 1.0 / NXc, rnx = 1.0 / g.nx, rny = 1.0 / g.ny;
-    for (long long bt = reg0 + wx; bt < reg1; bt += nwx) {
+    for (long long task = reg0 + bx; task < reg1; task += nbx) {
+        long long bt;
+        bool have;
+        if (PB) {
+            const int pb = (int)(task % PB);
+            const long long t2 = task / PB;
+            const int zb = (int)(t2 % nzb), grp0 = (int)(t2 / nzb);
+            const int iz = zb * kStWaves + w;
+            have = iz < g.nz;
+            bt = ((long long)grp0 * g.nz + iz) * PB + pb;
+        } else {
+            bt = task * kStWaves + w;
+            have = bt < nbat;
+        }
         const long long row0 = bt * kStRows;   // group-major
-        {
-            // lane l: row data of group-major row row0 + l (row k of Z and B)
-            const long long kg = row0 + l;
-            const bool ok = kg < g.M;
-            int cell = 0, ix = 0, iy = 0, iz = 0;
-            const int grp = ok ? divmod_d((int)kg, NXc, rNX, cell) : 0;
-            const long long k = (long long)cell * g.G + grp;
-            iy = divmod_d(cell, g.nx, rnx, ix);
-            iz = divmod_d(iy, g.ny, rny, iy);
-            const int idx3[3] = {ix, iy, iz}, n3[3] = {g.nx, g.ny, g.nz};
-            const int st3[3] = {1, g.nx, g.nx * g.ny};
-            for (int j = 0; j < ng; ++j) {
-                int src = ok ? (int)kg : -1;
-                if (j > 0 && ok) {
-                    const int ax = op.gaxis[j], dir = op.gdir[j];
-                    int jj = idx3[ax] + dir;
-                    const bool out = jj < 0 || jj >= n3[ax];
-                    if (out && !g.periodic[ax]) src = -1;
-                    else {
-                        jj = out ? (jj + n3[ax]) % n3[ax] : jj;
-                        src = (int)kg + (jj - idx3[ax]) * st3[ax];
+        if (have) {
+            {
+                // lane l: row data of group-major row row0 + l (row k of Z and B)
+                const long long kg = row0 + l;
+                const bool ok = kg < g.M;
+                int cell = 0, ix = 0, iy = 0, iz = 0;
+                const int grp = ok ? divmod_d((int)kg, NXc, rNX, cell) : 0;
+                const long long k = (long long)cell * g.G + grp;
+                iy = divmod_d(cell, g.nx, rnx, ix);
+                iz = divmod_d(iy, g.ny, rny, iy);
+                const int idx3[3] = {ix, iy, iz}, n3[3] = {g.nx, g.ny, g.nz};
+                const int st3[3] = {1, g.nx, g.nx * g.ny};
+                for (int j = 0; j < ng; ++j) {
+                    int src = ok ? (int)kg : -1;
+                    if (j > 0 && ok) {
+                        const int ax = op.gaxis[j], dir = op.gdir[j];
+                        int jj = idx3[ax] + dir;
+                        const bool out = jj < 0 || jj >= n3[ax];
+                        if (out && !g.periodic[ax]) src = -1;
+                        else {
+                            jj = out ? (jj + n3[ax]) % n3[ax] : jj;
+                            src = (int)kg + (jj - idx3[ax]) * st3[ax];
+                        }
+                    }
+                    s_nbr[w][j][l] = src;
+                }
+                s_row[w][l] = ok ? (int)k : -1;
+                double kap = 0.0;
+                if (ok) kap = rd.kfull ? rd.kfull[k] : rd.kappa0[cell] * rd.kscale[grp];
+                const double ktot = (ok && rd.kscat) ? kap + rd.kscat[k] : kap;
+                s_d[w][l] = (ok && op.scale_d) ? 1.0 / (1.0 + g.cdt * ktot) : 1.0;
+                for (int qq = 0; qq < nq; ++qq) {
+                    double v = 0.0;
+                    if (ok) {
+                        if (op.r1kind[qq] == 0) {
+                            v = g.cdt * kap * rd.eps[k];
+                            if (rd.kscat) v += g.cdt * rd.kscat[k] * rd.jn[k];
+                        } else {
+                            const int face = op.r1face[qq], ax = face >> 1;
+                            const int edge = (face & 1) ? n3[ax] - 1 : 0;
+                            if (idx3[ax] == edge) v = op.r1coef[qq] * rd.ghost[face * g.G + grp];
+                        }
+                    }
+                    s_z[w][qq][l] = v;
+                }
+            }
+            // the row data is read by the other lanes of this wave: LDS
+            // operations of a wave complete in order, and the compiler keeps
+            // them in program order across this barrier
+            __builtin_amdgcn_wave_barrier();
+            const int nrow = (int)((g.M - row0) < kStRows ? (g.M - row0) : kStRows);
+            for (int i = 0; i < nrow; ++i) {
+                const long long row = s_row[w][i];
+                f64x2 y[kStNG];
+#pragma unroll
+                for (int j = 0; j < kStNG; ++j) {
+                    y[j] = (f64x2){0.0, 0.0};
+                    if (j < ng) {
+                        const int src = s_nbr[w][j][i];
+                        if (src >= 0 && colok) y[j] = *reinterpret_cast<const f64x2*>(Y + (size_t)src * ldb + c0);
                     }
                 }
-                s_nbr[w][j][l] = src;
-            }
-            s_row[w][l] = ok ? (int)k : -1;
-            double kap = 0.0;
-            if (ok) kap = rd.kfull ? rd.kfull[k] : rd.kappa0[cell] * rd.kscale[grp];
-            const double ktot = (ok && rd.kscat) ? kap + rd.kscat[k] : kap;
-            s_d[w][l] = (ok && op.scale_d) ? 1.0 / (1.0 + g.cdt * ktot) : 1.0;
-            for (int qq = 0; qq < nq; ++qq) {
-                double v = 0.0;
-                if (ok) {
-                    if (op.r1kind[qq] == 0) {
-                        v = g.cdt * kap * rd.eps[k];
-                        if (rd.kscat) v += g.cdt * rd.kscat[k] * rd.jn[k];
-                    } else {
-                        const int face = op.r1face[qq], ax = face >> 1;
-                        const int edge = (face & 1) ? n3[ax] - 1 : 0;
-                        if (idx3[ax] == edge) v = op.r1coef[qq] * rd.ghost[face * g.G + grp];
-                    }
-                }
-                s_z[w][qq][l] = v;
-            }
-        }
-        // the row data is read by the other lanes of this wave: LDS
-        // operations of a wave complete in order, and the compiler keeps
-        // them in program order across this barrier
-        __builtin_amdgcn_wave_barrier();
-        const int nrow = (int)((g.M - row0) < kStRows ? (g.M - row0) : kStRows);
-        for (int i = 0; i < nrow; ++i) {
-            const long long row = s_row[w][i];
-            f64x2 y[kStNG];
+                f64x2 acc = (f64x2){0.0, 0.0};
 #pragma unroll
-            for (int j = 0; j < kStNG; ++j) {
-                y[j] = (f64x2){0.0, 0.0};
-                if (j < ng) {
-                    const int src = s_nbr[w][j][i];
-                    if (src >= 0 && colok) y[j] = *reinterpret_cast<const f64x2*>(Y + (size_t)src * ldb + c0);
+                for (int j = 0; j < kStNG; ++j) acc += cf[j] * y[j];
+                for (int qq = 0; qq < nq; ++qq) {
+                    const double z = s_z[w][qq][i];
+                    acc += z * *reinterpret_cast<const f64x2*>(s_R + qq * 128 + c0);
                 }
+                if (colok) *reinterpret_cast<f64x2*>(B + (size_t)row * ldb + c0) = acc * s_d[w][i];
             }
-            f64x2 acc = (f64x2){0.0, 0.0};
-#pragma unroll
-            for (int j = 0; j < kStNG; ++j) acc += cf[j] * y[j];
-            for (int qq = 0; qq < nq; ++qq) {
-                const double z = s_z[w][qq][i];
-                acc += z * *reinterpret_cast<const f64x2*>(s_R + qq * 128 + c0);
-            }
-            if (colok) *reinterpret_cast<f64x2*>(B + (size_t)row * ldb + c0) = acc * s_d[w][i];
+            __builtin_amdgcn_wave_barrier();   // this batch's row data is read before the next overwrites it
         }
-        __builtin_amdgcn_wave_barrier();   // this batch's row data is read before the next overwrites it
+        __syncthreads();   // the block's waves start each task together
     }
 }
 

@@ -1364,9 +1364,14 @@ __device__ __forceinline__ void svd_chain_body(const Geom& g, DevState* st, cons
             st->fl[1] += M * kk * (kk + 1.0);
             st->fl[2] += 2.0 * M * R1 * (double)r1n;
         } else {
-            // direction-space projection: Y = Z W (K = ldz), then one
-            // multiply-add per gather and rank-1 block
-            st->fl[0] += st->stencil ? 2.0 * M * kk * ((double)st->ldz + st->stencil) : 2.0 * M * R1 * kk;
+            if (st->stencil) {
+                // direction-space projection: Y = Z W (K = ldz), then one
+                // multiply-add per gather and rank-1 block
+                st->fl_dir[0] += 2.0 * M * kk * (double)st->ldz;
+                st->fl_dir[1] += 2.0 * M * kk * (double)st->stencil;
+            } else {
+                st->fl[0] += 2.0 * M * R1 * kk;
+            }
             st->fl[1] += gram ? M * kk * (kk + 1.0) : 2.0 * M * kk * kk - 2.0 / 3.0 * kk * kk * kk;
             st->fl[2] += 2.0 * M * kk * (double)r1n;
         }

@@ -48,6 +48,7 @@ struct DevState {
     int stencil;       // 0, or this pass projects in direction space (Y = Z W, then the operator's
                        // stencil on Y) with this many direction rows (gather plus rank-1 blocks)
     int stencil_rounds; // rounding passes so far that projected in direction space
+    double fl_dir[2];  // executed flops of the direction-space passes: Y = Z W, the stencil
 };
 
 // Static description of the problem shared by all kernels (passed by value).

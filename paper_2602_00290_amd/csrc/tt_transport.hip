@@ -54,7 +54,10 @@ tt_status fail(tt_status s, const std::string& msg) {
         if (e_ != hipSuccess) return fail(TT_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-enum KClass { KC_PREP = 0, KC_PROJECT = 1, KC_FACTOR = 2, KC_TREE = 3, KC_SVD = 4, KC_OUTPUT = 5, KC_DIAG = 6, KC_COUPLE = 7 };
+enum KClass {
+    KC_PREP = 0, KC_PROJECT = 1, KC_FACTOR = 2, KC_TREE = 3, KC_SVD = 4, KC_OUTPUT = 5, KC_DIAG = 6, KC_COUPLE = 7,
+    KC_ANGLE = 8, KC_STENCIL = 9, KC_COUNT = 10
+};
 
 // Largest grid the launch-shape tuner tries for the persistent contraction
 // kernels (four blocks per CU); the partial buffers are sized for it.
@@ -287,7 +290,7 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         if (P.f64_blocks > 8) P.f64_blocks = P.f64_blocks / 8 * 8;
         P.f64_blocks_o = P.f64_blocks;
         P.stencil = P.f64mm && P.nct_f == 8;
-        P.st_blocks = (int)std::max<long long>(1, std::min<long long>(1024, (P.M + kStRows - 1) / kStRows / kStWaves));
+        P.st_blocks = (int)std::max<long long>(1, std::min<long long>(256, (P.M + kStRows - 1) / kStRows / kStWaves));
         if (P.st_blocks > 8) P.st_blocks = P.st_blocks / 8 * 8;
         // launch-shape tuning may take up to four blocks per CU
         P.f64_blocks_max = (int)std::max<long long>(1, std::min<long long>(kTuneMaxBlocks, nrb));
@@ -492,9 +495,9 @@ struct tt_handle {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
     std::vector<int> ev_class;
     size_t ev_used = 0;
-    double kernel_ms[8] = {0};
-    long long kernel_launches[8] = {0};
-    double flops[8] = {0};
+    double kernel_ms[KC_COUNT] = {0};
+    long long kernel_launches[KC_COUNT] = {0};
+    double flops[KC_COUNT] = {0};
     double last_seconds = 0.0;
     int last_steps = 0;
     // hipGraph replay of the step sequence (tt_transport_set_graph): two steps
@@ -944,6 +947,26 @@ tt_status launch_project(tt_handle* h, int opkind, hipStream_t s) {
     constexpr bool f32 = std::is_same<T, float>::value;
     const unsigned gx = (unsigned)((P.M + 63) / 64);
     const unsigned gx128 = (unsigned)((P.M + 127) / 128);
+    if constexpr (!f32) {
+        if (P.f64mm && stencil_op(h, opkind)) {
+            // direction space when the prep found both factors square (the
+            // kernels read its flag; otherwise these two exit and the
+            // gathered projection below runs)
+            double* Yb = h->at<double>(P.o_Y);
+            size_t e = h->ev_begin(KC_ANGLE, s);
+            hipLaunchKernelGGL((k_mm_f64<MODE_ANGLE, 8, false, 1>), dim3(P.f64_blocks), dim3(kF64Threads),
+                               f64_lds_bytes(8, false, 1, false, kF64AngChunks), s, h->geom, op, (const DevState*)st,
+                               (const double*)h->Zc(), (const double*)h->at<double>(P.o_Wst), Yb, h->rowdata(),
+                               (double*)nullptr);
+            h->ev_end(e, s);
+            e = h->ev_begin(KC_STENCIL, s);
+            hipLaunchKernelGGL(k_stencil_f64, dim3(P.st_blocks), dim3(64 * kStWaves), 0, s, h->geom, op,
+                               (const DevState*)st, (const double*)Yb, (const double*)h->at<double>(P.o_Cst),
+                               (double*)B, h->rowdata());
+            h->ev_end(e, s);
+        }
+    }
+    const size_t e = h->ev_begin(KC_PROJECT, s);
     if constexpr (f32) {
         if (P.bf16x) {
             __bf16* gh = h->at<__bf16>(P.o_Gh);
@@ -970,23 +993,11 @@ tt_status launch_project(tt_handle* h, int opkind, hipStream_t s) {
                                h->rowdata());
         }
     } else if (P.f64mm) {
-        if (stencil_op(h, opkind)) {
-            // direction space when the prep found both factors square (the
-            // kernels read its flag; otherwise these two exit and the
-            // gathered projection below runs)
-            double* Yb = h->at<double>(P.o_Y);
-            hipLaunchKernelGGL((k_mm_f64<MODE_ANGLE, 8, false, 1>), dim3(P.f64_blocks), dim3(kF64Threads),
-                               f64_lds_bytes(8, false, 1, false, kF64AngChunks), s, h->geom, op, (const DevState*)st,
-                               (const double*)h->Zc(), (const double*)h->at<double>(P.o_Wst), Yb, h->rowdata(),
-                               (double*)nullptr);
-            hipLaunchKernelGGL(k_stencil_f64, dim3(P.st_blocks), dim3(64 * kStWaves), 0, s, h->geom, op,
-                               (const DevState*)st, (const double*)Yb, (const double*)h->at<double>(P.o_Cst),
-                               (double*)B, h->rowdata());
-        }
         project_f64(h, op, h->round_method != TT_ROUND_QR && P.nct_f <= 4, h->at<double>(P.o_RA), s);
     } else
         hipLaunchKernelGGL((k_gather_gemm<T, MODE_PROJECT>), dim3(gx, (P.ldbcap + 63) / 64), dim3(256), 0, s, h->geom,
                            op, st, (const T*)h->Zc(), (const T*)Gop, B, h->rowdata());
+    h->ev_end(e, s);
     return TT_OK;
 }
 
@@ -1044,12 +1055,10 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
 
     const unsigned gx = (unsigned)((P.M + 63) / 64);
     const unsigned gx128 = (unsigned)((P.M + 127) / 128);
-    e = h->ev_begin(KC_PROJECT, s);
     {
-        const tt_status r = launch_project<T>(h, opkind, s);
+        const tt_status r = launch_project<T>(h, opkind, s);   // timed per kernel inside
         if (r != TT_OK) return r;
     }
-    h->ev_end(e, s);
 
     const double* RB = nullptr;
     int ldr = P.KP;
@@ -1370,11 +1379,13 @@ tt_status fill_stats(tt_handle* h, tt_stats* out, hipStream_t s) {
         out->k_s_impl = 1.0;
     }
     out->seconds = h->last_seconds;
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < KC_COUNT; ++i) {
         out->kernel_ms[i] = h->kernel_ms[i];
         out->kernel_launches[i] = h->kernel_launches[i];
     }
     out->flops[KC_PROJECT] = st.fl[0];
+    out->flops[KC_ANGLE] = st.fl_dir[0];
+    out->flops[KC_STENCIL] = st.fl_dir[1];
     out->flops[KC_FACTOR] = st.fl[1];
     out->flops[KC_OUTPUT] = st.fl[2];
     return TT_OK;
@@ -2260,7 +2271,7 @@ tt_status tt_transport_solve(tt_handle* h, int n_steps, tt_stats* out, void* str
     if (!h) return fail(TT_ERR_INVALID_ARG, "handle is NULL");
     if (n_steps < 0) return fail(TT_ERR_INVALID_ARG, "n_steps must be >= 0");
     hipStream_t s = (hipStream_t)stream;
-    for (int i = 0; i < 8; ++i) { h->kernel_ms[i] = 0; h->kernel_launches[i] = 0; h->flops[i] = 0; }
+    for (int i = 0; i < KC_COUNT; ++i) { h->kernel_ms[i] = 0; h->kernel_launches[i] = 0; h->flops[i] = 0; }
     {
         DevState st;
         tt_status r = read_state(h, st, s);
@@ -2572,7 +2583,7 @@ tt_status tt_transport_solve_small_batch(tt_handle** hs, int n, const int* n_ste
         std::memset(&batch, 0, sizeof(batch));
         for (int i = 0; i < nb; ++i) {
             tt_handle* h = hs[b0 + i];
-            for (int c = 0; c < 8; ++c) { h->kernel_ms[c] = 0; h->kernel_launches[c] = 0; h->flops[c] = 0; }
+            for (int c = 0; c < KC_COUNT; ++c) { h->kernel_ms[c] = 0; h->kernel_launches[c] = 0; h->flops[c] = 0; }
             DevState st;
             tt_status r = read_state(h, st, s);
             if (r != TT_OK) return r;

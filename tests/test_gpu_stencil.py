@@ -26,7 +26,11 @@ result with the oracle:
 * HLL and a Rusanov case with more rank-1 blocks than the path holds: the
   gathered projection, against the oracle's TT solve (1e-10, equal ranks);
 * one step of the 3D workload's shape from a seeded rank-(64, 16) state
-  (R1 = 450), QR route, against the oracle's step (1e-12, equal ranks).
+  (R1 = 450), QR route, against the oracle's step (1e-12, equal ranks);
+* one step on 8 x 8 x 5 cells, where an x-y plane is a whole number of
+  64-row batches and the stencil's blocks take eight consecutive planes (five
+  here, so three waves of each block idle), with z periodic or with inflow on
+  both z faces: against the oracle's step (1e-12, equal ranks).
 """
 import numpy as np
 import pytest
@@ -160,6 +164,31 @@ def test_one_step_of_the_3d_shape_at_the_cap(tt):
     st = s.solve(1)
     Zo, To, Po, info = ott.step(p, Z, Th, Ph)
     assert st["max_R1"] == 450 and st["direction_space_rounds"] == 1
+    assert s.get_ranks() == (info["r1"], info["r2"])
+    assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 1e-12
+    s.destroy()
+
+
+@pytest.mark.parametrize("zbc", ["periodic", "inflow"])
+def test_one_step_with_plane_tiles(tt, zbc):
+    p = ti.clumps3d(n=8, n_groups=4, n_theta=8, n_phi=16, tol=1e-9, rank_cap=48, precision=ti.PREC_FP64, T=0.3)
+    p.n_cells = (8, 8, 5)
+    rng = np.random.default_rng(9)
+    p.kappa0 = rng.uniform(0.3, 3.0, 320)
+    p.T_cell = np.full(320, 0.3)
+    if zbc == "periodic":
+        p.bc = (ti.BC_INFLOW_PLANCK, 0, 0, 0, ti.BC_PERIODIC, ti.BC_PERIODIC)
+        p.bc_T = (1.0, 0.0, 0.0, 0.0, 0.0, 0.0)
+    else:
+        p.bc = (ti.BC_INFLOW_PLANCK, 0, 0, 0, ti.BC_INFLOW_PLANCK, ti.BC_INFLOW_PLANCK)
+        p.bc_T = (1.0, 0.0, 0.0, 0.0, 0.7, 0.4)
+    print(f"stencil: plane tiles z {zbc} M={p.M}", flush=True)
+    s = tt.Solver(p, round_method=tt.TT_ROUND_QR)
+    Z, Th, Ph = ti.random_tt(p.M, 8, 16, 24, 16, seed=41, decay=0.8)
+    s.set_cores(Z, Th, Ph)
+    st = s.solve(1)
+    Zo, To, Po, info = ott.step(p, Z, Th, Ph)
+    assert st["direction_space_rounds"] == 1
     assert s.get_ranks() == (info["r1"], info["r2"])
     assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 1e-12
     s.destroy()
