@@ -28,9 +28,10 @@ result with the oracle:
 * one step of the 3D workload's shape from a seeded rank-(64, 16) state
   (R1 = 450), QR route, against the oracle's step (1e-12, equal ranks);
 * one step on 8 x 8 x 5 cells, where an x-y plane is a whole number of
-  64-row batches and the stencil's blocks take eight consecutive planes (five
-  here, so three waves of each block idle), with z periodic or with inflow on
-  both z faces: against the oracle's step (1e-12, equal ranks).
+  64-row batches and each stencil block takes one batch position in up to 16
+  consecutive planes (five here, so most of its waves idle), with z periodic
+  or with inflow on both z faces: against the oracle's step (1e-12, equal
+  ranks).
 """
 import numpy as np
 import pytest
