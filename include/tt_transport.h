@@ -161,9 +161,12 @@ typedef struct tt_problem {
                                        equation, updates the intensity with
                                        eps_g(T+), and advances T by total-energy
                                        conservation with the angle means of the
-                                       rounded new state.  Needs paper_step_order 0;
-                                       such a problem advances only through
-                                       tt_transport_solve / step_batch / solve_batch. */
+                                       rounded new state.  With paper_step_order 1
+                                       the stage acts on the rounded state after
+                                       transport (its angle means are J*) and is
+                                       rounded again.  Such a problem advances only
+                                       through tt_transport_solve / step_batch /
+                                       solve_batch.                                 */
     const double* T_rad0;           /* N_X initial radiation temperature (isotropic
                                        Planck initial state), or NULL for T_cell  */
     const double* kappa_full;       /* N_X * N_nu opacities kappa_{a,g}(x) (>= 0),
@@ -184,8 +187,9 @@ typedef struct tt_problem {
                                        a = c dt kappa, b = c dt kappa_s and
                                        J' = (J* + a eps) / (1 + a) the angle mean
                                        of the update (J* that of I*): a per-step
-                                       pre-pass computes J* from the cores.  Needs
-                                       paper_step_order 0; such a problem advances
+                                       pre-pass computes J* from the cores (from
+                                       the rounded state after transport with
+                                       paper_step_order 1).  Such a problem advances
                                        only through solve / step_batch / solve_batch
                                        (apply_op returns TT_ERR_STATE).  Adds 2 N_X
                                        N_nu doubles of workspace (3 without a

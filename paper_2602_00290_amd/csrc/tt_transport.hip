@@ -180,8 +180,6 @@ tt_status validate(const tt_problem* p) {
     if (p->paper_step_order < 0 || p->paper_step_order > 1) return fail(TT_ERR_INVALID_ARG, "paper_step_order must be 0 or 1");
     if (!(p->heat_capacity >= 0.0) || !std::isfinite(p->heat_capacity))
         return fail(TT_ERR_INVALID_ARG, "heat_capacity must be finite and >= 0");
-    if (p->heat_capacity > 0.0 && p->paper_step_order != 0)
-        return fail(TT_ERR_INVALID_ARG, "the coupled medium temperature needs paper_step_order == 0");
     if (p->flux != TT_FLUX_UPWIND && p->flux != TT_FLUX_RUSANOV && p->flux != TT_FLUX_HLL)
         return fail(TT_ERR_INVALID_ARG, "unknown flux");
     if (p->flux == TT_FLUX_HLL) {
@@ -194,8 +192,6 @@ tt_status validate(const tt_problem* p) {
     }
     if (p->flux == TT_FLUX_RUSANOV && !(p->rusanov_s >= 0.0 && p->rusanov_s <= 1.0))
         return fail(TT_ERR_INVALID_ARG, "rusanov_s must lie in [0, 1]");
-    if (p->kappa_s_full && p->paper_step_order != 0)
-        return fail(TT_ERR_INVALID_ARG, "scattering needs paper_step_order == 0");
     return TT_OK;
 }
 
@@ -1247,13 +1243,21 @@ tt_status coupled_step(tt_handle* h, hipStream_t s) {
     const CoupleArgs a = couple_args(h);
     const size_t lds_pre = couple_lds_doubles(P.n_gather_max * P.ldzcap + P.n_r1_max, 1 + P.n_terms, P.r1cap, P.r2cap) *
                            sizeof(double);
+    const bool paper = h->step_order == 1;
+    tt_status r = TT_OK;
+    if (paper) {
+        // the paper's order (Sec. 3.1): transport and round, then the source
+        // stage on the rounded state, whose angle means are J*
+        r = round_dispatch(h, OP_TRANSPORT, h->tol, P.cap, s);
+        if (r != TT_OK) return r;
+    }
     size_t e = h->ev_begin(KC_COUPLE, s);
     hipLaunchKernelGGL(k_couple_pre<T>, dim3(couple_grid(P, 768)), dim3(kCoupleThreads), lds_pre, s, h->geom,
-                       h->ops[OP_TRANSPORT], h->rowdata(), (const DevState*)h->st(), (const T*)h->Zc(),
-                       (const double*)h->Thc(), (const double*)h->Phc(), a);
+                       h->ops[paper ? OP_NONE : OP_TRANSPORT], h->rowdata(), (const DevState*)h->st(),
+                       (const T*)h->Zc(), (const double*)h->Thc(), (const double*)h->Phc(), a);
     h->ev_end(e, s);
     HIP_TRY(hipGetLastError());
-    tt_status r = round_dispatch(h, OP_FULL, h->tol, P.cap, s);
+    r = round_dispatch(h, paper ? OP_SOURCE : OP_FULL, h->tol, P.cap, s);
     if (r != TT_OK) return r;
     if (!P.coupled) return TT_OK;
     const size_t lds_post = (size_t)(P.r1cap + P.r2cap + 8) * sizeof(double);

@@ -7,7 +7,12 @@ dense scheme up to rounding, so intensity and temperature agree to 1e-9 after
 tens of steps; FP32 (fused path, tol 1e-6): 5e-4 for the intensity, 1e-4 for
 the temperature.  Total energy (medium + radiation) is conserved by
 construction against the rounded state, so on a periodic domain it holds to
-round-off."""
+round-off.
+
+The paper's step order (Section 3.1: transport, round, source stage, round)
+takes the source stage's J* from the rounded state after transport.  The dense
+scheme has no rounding, so at tol 1e-13 both orders equal it to the same
+bounds."""
 import math
 import os
 
@@ -78,6 +83,40 @@ def test_coupled_fp32_fused_matches_dense_oracle(tt):
     I_ref, T_ref = dense.march_coupled(p, dense.initial_dense(p), p.T_cell, steps)
     assert rel(I, I_ref) < 5e-4
     np.testing.assert_allclose(T, T_ref, rtol=1e-4, atol=0.0)
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_coupled_paper_step_order_fp64_matches_dense_oracle(tt, dim):
+    p = _coupled(dim).copy(step_order=1)
+    steps = 12
+    print(f"couple: paper order fp64 dim={dim}", flush=True)
+    I, T, st = _run(tt, p, steps)
+    I_ref, T_ref = dense.march_coupled(p, dense.initial_dense(p), p.T_cell, steps)
+    assert rel(I, I_ref) < 1e-9
+    np.testing.assert_allclose(T, T_ref, rtol=1e-9, atol=0.0)
+    assert np.max(np.abs(T - p.T_cell) / p.T_cell) > 1e-3
+
+
+def test_coupled_paper_step_order_fp32_fused_matches_dense_oracle(tt):
+    p = _coupled(2, prec=ti.PREC_FP32, tol=1e-6, cap=16).copy(step_order=1)
+    steps = 10
+    I, T, st = _run(tt, p, steps)
+    I_ref, T_ref = dense.march_coupled(p, dense.initial_dense(p), p.T_cell, steps)
+    assert rel(I, I_ref) < 5e-4
+    np.testing.assert_allclose(T, T_ref, rtol=1e-4, atol=0.0)
+
+
+def test_coupled_paper_step_order_energy_on_periodic_domain(tt):
+    # the source stage conserves the total against the rounded states; the
+    # transport round in between is exact to the tolerance
+    p = _coupled(2).copy(bc=(2, 2, 2, 2, 0, 0), step_order=1)
+    s = tt.Solver(p)
+    st0 = s.get_stats()
+    U0 = st0["energy"] / p.c + st0["medium_energy"]
+    st = s.solve(20)
+    U = st["energy"] / p.c + st["medium_energy"]
+    assert U == pytest.approx(U0, rel=1e-10)
+    s.destroy()
 
 
 def test_coupled_energy_conserved_on_periodic_domain(tt):

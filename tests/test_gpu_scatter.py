@@ -132,6 +132,30 @@ def test_coupled_temperature_with_scattering_matches_dense_oracle(tt):
     s.destroy()
 
 
+@pytest.mark.parametrize("dim,coupled", [(1, False), (2, False), (1, True)])
+def test_paper_step_order_with_scattering_matches_dense_march(tt, dim, coupled):
+    # the paper's order (Section 3.1): transport, round, then the source stage
+    # with J* from the rounded state after transport, round; the dense scheme
+    # has no rounding, so at tol 1e-13 both orders equal it
+    p = _case(dim, s_rus=1.0).copy(step_order=1)
+    if coupled:
+        rng = np.random.default_rng(5)
+        p = p.copy(T_cell=rng.uniform(0.3, 1.2, p.n_x), T_rad0=rng.uniform(0.1, 0.8, p.n_x), heat_capacity=15.0)
+    steps = 10
+    print(f"scatter: paper order dim={dim} coupled={coupled}", flush=True)
+    s = tt.Solver(p)
+    s.solve(steps)
+    I = full(*s.get_cores())
+    if coupled:
+        T = s.get_temperature()
+        I_ref, T_ref = dense.march_coupled(p, dense.initial_dense(p), p.T_cell, steps)
+        np.testing.assert_allclose(T, T_ref, rtol=1e-9)
+    else:
+        I_ref = dense.march(p, dense.initial_dense(p), steps)
+    assert rel(I, I_ref) < 1e-9
+    s.destroy()
+
+
 def test_scattering_problem_rejects_apply_op_and_bad_inputs(tt):
     p = _case(1)
     s = tt.Solver(p)

@@ -100,11 +100,13 @@ def test_coupled_temperature_validation(tt):
     fixed = p.copy(heat_capacity=0.0, T_rad0=None)
     # the coupled problem carries T, its initial copy, J* per row, edges and weights
     assert tt.workspace_bytes(p) > tt.workspace_bytes(fixed)
-    for bad in (p.copy(heat_capacity=-1.0), p.copy(heat_capacity=float("inf")), p.copy(step_order=1)):
+    for bad in (p.copy(heat_capacity=-1.0), p.copy(heat_capacity=float("inf"))):
         with pytest.raises(tt.TTError) as e:
             tt.workspace_bytes(bad)
         assert e.value.status == tt.TT_ERR_INVALID_ARG
+    # both step orders are accepted, with or without the coupling
     assert tt.workspace_bytes(fixed.copy(step_order=1)) > 0
+    assert tt.workspace_bytes(p.copy(step_order=1)) == tt.workspace_bytes(p)
 
 
 def test_kappa_full_validation(tt):
@@ -125,6 +127,7 @@ def test_flux_and_scattering_validation(tt):
     # scattering: the opacity, J^{m+1} and the pre-pass rows (3 N_X N_nu doubles)
     assert tt.workspace_bytes(p.copy(kappa_s_full=ks)) >= base + 3 * 16 * 4 * 8
     assert tt.workspace_bytes(p.copy(flux=ti.FLUX_RUSANOV, rusanov_s=0.0)) > 0
+    assert tt.workspace_bytes(p.copy(kappa_s_full=ks, step_order=1)) == tt.workspace_bytes(p.copy(kappa_s_full=ks))
     # randomized rounding: sketch buffers, and its oversampling is checked
     assert tt.workspace_bytes(p.copy(round_method=ti.ROUND_RAND)) > tt.workspace_bytes(p.copy(round_method=ti.ROUND_GRAM))
     for bad in (p.copy(round_method=4), p.copy(round_method=ti.ROUND_RAND, rand_oversample=0),
@@ -137,7 +140,6 @@ def test_flux_and_scattering_validation(tt):
     assert tt.workspace_bytes(p.copy(flux=ti.FLUX_HLL, precision=ti.PREC_FP64)) > 0
     for bad in (p.copy(flux=3), p.copy(flux=ti.FLUX_RUSANOV, rusanov_s=1.5),
                 p.copy(flux=ti.FLUX_RUSANOV, rusanov_s=float("nan")),
-                p.copy(kappa_s_full=ks, step_order=1),
                 p.copy(flux=ti.FLUX_HLL, precision=ti.PREC_FP32),
                 p.copy(flux=ti.FLUX_HLL, precision=ti.PREC_FP64, kappa_s_full=ks),
                 p.copy(flux=ti.FLUX_HLL, precision=ti.PREC_FP64, hll_beta=0.0),
