@@ -222,7 +222,16 @@ __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const
                 const int k = 16 * t + 4 * q;
                 f64x2 v0 = (f64x2){0.0, 0.0}, v1 = v0;
                 if (rb < rb_end && row < g.M && k < K) {
-                    const double* ap = A + row * lda + k;
+                    // Y = Z W walks Y's group-major rows, reading Z's row of
+                    // the same (cell, grp)
+                    long long arow = row;
+                    if (MODE == MODE_ANGLE) {
+                        const int NXc = (int)(g.M / g.G);
+                        int cell = 0;
+                        const int grp = divmod_d((int)row, NXc, 1.0 / NXc, cell);
+                        arow = (long long)cell * g.G + grp;
+                    }
+                    const double* ap = A + arow * lda + k;
                     v0 = *reinterpret_cast<const f64x2*>(ap);
                     v1 = *reinterpret_cast<const f64x2*>(ap + 2);
                 }
@@ -281,11 +290,6 @@ __global__ __launch_bounds__(kF64Threads) void k_mm_f64(Geom g, OpDesc op, const
                     // Y is stored group-major (row grp N_X + cell), where the
                     // stencil's neighbours are 1, n_x and n_x n_y rows apart
                     long long orow = row;
-                    if (MODE == MODE_ANGLE && row < g.M) {
-                        int grp = 0;
-                        const int cell = divmod_d((int)row, g.G, rG, grp);
-                        orow = (long long)grp * (g.M / g.G) + cell;
-                    }
                     // a direction-space pass leaves B group-major too: the
                     // output reads it in that order and writes Z_out in the
                     // state's (cell G + grp)
@@ -539,11 +543,10 @@ __global__ __launch_bounds__(64 * kStWaves) void k_stencil_f64(Geom g, OpDesc op
     // dealt to the XCD's blocks in turn, are the next batch positions of the
     // plane (the y-neighbours when n_x = 64).  Each XCD sweeps a contiguous
     // region of tasks.  Otherwise the waves take consecutive batches in
-    // turn.  B is written group-major like Y: the Gram and the Householder
-    // QR of B do not depend on the row order, and the output contraction maps
-    // the rows back to the state's order (cell G + grp).  Written in the
-    // state's order, B's rows landed 64 KB apart and the stencil took 12.1
-    // against 11.2 ms.
+    // turn.  B is written group-major like Y, in whole contiguous rows: the
+    // Gram and the Householder QR of B do not depend on the row order, and
+    // the output contraction maps the rows back to the state's order
+    // (cell G + grp).
     const int nb = gridDim.x, b = blockIdx.x;
     const long long nbat = (g.M + kStRows - 1) / kStRows;
     const int NXc = g.nx * g.ny * g.nz;
@@ -626,40 +629,24 @@ __global__ __launch_bounds__(64 * kStWaves) void k_stencil_f64(Geom g, OpDesc op
             // them in program order across this barrier
             __builtin_amdgcn_wave_barrier();
             const int nrow = (int)((g.M - row0) < kStRows ? (g.M - row0) : kStRows);
-            // two rows at a time: both rows' neighbours load before either
-            // computes (twice the loads in flight per wave; at the 128 VGPRs a
-            // 1024-thread block allows this spills 44 bytes per lane and still
-            // measured 10 % faster than one row at a time)
-            for (int i = 0; i < nrow; i += 2) {
-                const bool two = i + 1 < nrow;
-                f64x2 y0[kStNG], y1[kStNG];
+            for (int i = 0; i < nrow; ++i) {
+                f64x2 y[kStNG];
 #pragma unroll
                 for (int j = 0; j < kStNG; ++j) {
-                    y0[j] = (f64x2){0.0, 0.0};
-                    y1[j] = (f64x2){0.0, 0.0};
+                    y[j] = (f64x2){0.0, 0.0};
                     if (j < ng) {
-                        const int s0 = s_nbr[w][j][i];
-                        if (s0 >= 0 && colok) y0[j] = *reinterpret_cast<const f64x2*>(Y + (size_t)s0 * ldb + c0);
-                        const int s1 = two ? s_nbr[w][j][i + 1] : -1;
-                        if (s1 >= 0 && colok) y1[j] = *reinterpret_cast<const f64x2*>(Y + (size_t)s1 * ldb + c0);
+                        const int src = s_nbr[w][j][i];
+                        if (src >= 0 && colok) y[j] = *reinterpret_cast<const f64x2*>(Y + (size_t)src * ldb + c0);
                     }
                 }
-                f64x2 a0 = (f64x2){0.0, 0.0}, a1 = a0;
+                f64x2 acc = (f64x2){0.0, 0.0};
 #pragma unroll
-                for (int j = 0; j < kStNG; ++j) {
-                    const f64x2 c = *reinterpret_cast<const f64x2*>(s_cf + j * 128 + c0);
-                    a0 += c * y0[j];
-                    a1 += c * y1[j];
-                }
+                for (int j = 0; j < kStNG; ++j) acc += *reinterpret_cast<const f64x2*>(s_cf + j * 128 + c0) * y[j];
                 for (int qq = 0; qq < nq; ++qq) {
-                    const f64x2 r = *reinterpret_cast<const f64x2*>(s_R + qq * 128 + c0);
-                    a0 += s_z[w][qq][i] * r;
-                    if (two) a1 += s_z[w][qq][i + 1] * r;
+                    const double z = s_z[w][qq][i];
+                    acc += z * *reinterpret_cast<const f64x2*>(s_R + qq * 128 + c0);
                 }
-                if (colok) {
-                    *reinterpret_cast<f64x2*>(B + (size_t)(row0 + i) * ldb + c0) = a0 * s_d[w][i];
-                    if (two) *reinterpret_cast<f64x2*>(B + (size_t)(row0 + i + 1) * ldb + c0) = a1 * s_d[w][i + 1];
-                }
+                if (colok) *reinterpret_cast<f64x2*>(B + (size_t)(row0 + i) * ldb + c0) = acc * s_d[w][i];
             }
             __builtin_amdgcn_wave_barrier();   // this batch's row data is read before the next overwrites it
         }
