@@ -294,6 +294,7 @@ def served_phase(args):
     dimension U{64..256}, groups U{16..64}, rank caps U{4..48}, FP32/FP64 split,
     64 steps each.  First all requests arrive at once (capacity = completed
     requests/s); then Poisson arrivals at 0.8 x capacity give p50/p99 latency."""
+    import numpy as np
     import tt_inputs as ti
     from paper_2602_00290_amd.serve import Server, make_requests
 
@@ -305,12 +306,26 @@ def served_phase(args):
     arr = ti.poisson_arrivals(len(probs), rate, seed=0)
     live = srv.run(make_requests(probs, arr))
     keep = ("p50_ms", "p99_ms", "mean_ms", "throughput_rps", "makespan_s", "max_active", "peak_workspace_bytes")
+
+    # latency per request class (dimension, precision) and the slowest
+    # requests, to show where the tail comes from
+    def cls(p):
+        return f"{p.dim}d_" + ("fp64" if p.precision == ti.PREC_FP64 else "fp32")
+
+    lat = live["latency_ms"]
+    by = {}
+    for i, p in enumerate(probs):
+        by.setdefault(cls(p), []).append(lat[i])
+    by_class = {c: {"n": len(v), "p50_ms": float(np.percentile(v, 50)), "p99_ms": float(np.percentile(v, 99)),
+                    "mean_ms": float(np.mean(v))} for c, v in sorted(by.items())}
+    slow = sorted(range(len(probs)), key=lambda i: -lat[i])[:5]
+    tail = [{"class": cls(probs[i]), "rows": probs[i].M, "cap": probs[i].rank_cap, "latency_ms": lat[i]} for i in slow]
     return {"requests": len(probs), "steps_per_request": 64,
             "mix": "1D (16 GL mu) / 2D (8x8) 50/50, cells/dim U{64..256}, groups U{16..64}, caps U{4..48}, "
                    "FP32 (Gram) / FP64 (QR) 50/50, seed 0",
             "budget_gb": args.served_budget_gb, "slots": args.served_slots,
             "capacity_rps": cap["throughput_rps"], "capacity_run": {k: cap[k] for k in keep},
-            "arrival_rate_rps": rate, **{k: live[k] for k in keep}}
+            "arrival_rate_rps": rate, **{k: live[k] for k in keep}, "by_class": by_class, "slowest": tail}
 
 
 def mode_copy(args):
