@@ -202,15 +202,18 @@ __global__ __launch_bounds__(256) void k_gather_gemm(Geom g, OpDesc op, const De
 // ---------------------------------------------------------------------------
 //
 // Each block owns a contiguous range of rows and keeps an upper-triangular R
-// (KP x KP, FP64) in LDS.  Rows arrive in chunks of NG*BR; thread (rg, c)
-// holds BR rows of column c of the chunk in registers.  For every column j the
-// reflector that zeroes the chunk's column j against R[j][j] is formed
-// (LAPACK dlarfg convention: beta = -sign(alpha) ||(alpha, x)||,
+// (KP x KP, FP64, packed) in LDS.  Rows arrive in chunks of NG*BR; the NG threads of
+// column c (adjacent lanes of one wave) hold BR rows each of the chunk's
+// column c in registers (thread rg holds chunk rows i*NG + rg).  For every
+// column j the reflector that zeroes the chunk's column j against R[j][j] is
+// formed (LAPACK dlarfg convention: beta = -sign(alpha) ||(alpha, x)||,
 // tau = (beta - alpha) / beta, v = x / (alpha - beta)) and applied to the
-// columns c > j of R and of the chunk.  Column-parallel: the dot products
-// v^T T[:, c] run down each thread's own registers and across row groups
-// through LDS.  The block writes its final R (KP x KP, zeros below the
-// diagonal) to Rout[blockIdx.x].
+// columns c > j of R and of the chunk.  A column's dot product v^T T[:, c]
+// runs down its threads' registers and across their lanes with shuffles, so
+// only the reflector crosses waves: the threads of column j + 1 form it as
+// soon as their own update by reflector j is done, and one block barrier per
+// column step publishes it.  The block writes its final R (KP x KP, zeros
+// below the diagonal) to Rout[blk].
 // ncols = k1 from the state; lda is the state's ldb when lda_from_state.
 // rows_per_R > 0 (tree levels): the input is a stack of KP x KP R factors of
 // which only the first rows_per_R rows can be non-zero (k1 <= rows_per_R);
@@ -221,79 +224,82 @@ template <typename TS, int KP, int NG, int BR>
 __device__ __forceinline__ void tsqr_body(const TS* __restrict__ A, int lda_static, int lda_from_state, int rows_per_R,
                                           long long nrows, long long rows_per_block, const DevState* __restrict__ st,
                                           double* __restrict__ Rout, int blk) {
-    __shared__ double R[KP][KP];
-    __shared__ double vbuf[2][NG * BR];
-    __shared__ double pdot[2][NG][KP];
-    __shared__ double red[2][NG];
+    static_assert(NG <= 64 && (64 % NG) == 0, "the row groups of a column share one wave");
+    // R's upper triangle, packed by rows (KP (KP + 1) / 2 entries: two
+    // 128-column blocks fit one CU's LDS)
+    __shared__ double R[KP * (KP + 1) / 2];
+    __shared__ double vbuf[2][NG * BR];   // reflector of the current column, chunk row order
+    __shared__ double tbuf[2];            // its tau; 0 when the column has nothing to annihilate
     const int tid = threadIdx.x;
-    const int c = tid % KP, rg = tid / KP;
+    const int c = tid / NG, rg = tid % NG;
     const int ncols = st->k1;
     const int lda = lda_from_state ? st->ldb : lda_static;
-    for (int idx = tid; idx < KP * KP; idx += KP * NG) R[idx / KP][idx % KP] = 0.0;
+    // entry (j, c), c >= j
+    auto ri = [](int j, int c) __attribute__((always_inline)) { return j * (2 * KP - j + 1) / 2 + (c - j); };
+    for (int idx = tid; idx < KP * (KP + 1) / 2; idx += KP * NG) R[idx] = 0.0;
     __syncthreads();
     const long long begin = (long long)blk * rows_per_block;
     long long end = begin + rows_per_block;
     if (end > nrows) end = nrows;
     double T[BR];
+    // sum over the NG lanes of one column; the butterfly leaves the same
+    // bits in every lane
+    auto colsum = [&](double x) __attribute__((always_inline)) {
+#pragma unroll
+        for (int o = 1; o < NG; o <<= 1) x += __shfl_xor(x, o, NG);
+        return x;
+    };
+    // run by the NG threads of column col once every earlier reflector has
+    // been applied to their values
+    auto form = [&](int col, int p) __attribute__((always_inline)) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < BR; ++i) s += T[i] * T[i];
+        const double xn2 = colsum(s);
+        double tau = 0.0;
+        if (xn2 != xn2) {
+            if (rg == 0) R[ri(col, col)] = xn2;   // NaN in the data: poison R so it reaches the SVD
+        } else if (xn2 > 0.0) {
+            const double alpha = R[ri(col, col)];
+            const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+            tau = (beta - alpha) / beta;
+            const double scal = 1.0 / (alpha - beta);
+#pragma unroll
+            for (int i = 0; i < BR; ++i) vbuf[p][i * NG + rg] = T[i] * scal;
+            if (rg == 0) R[ri(col, col)] = beta;
+        }
+        if (rg == 0) tbuf[p] = tau;
+    };
     for (long long k0 = begin; k0 < end; k0 += NG * BR) {
 #pragma unroll
         for (int i = 0; i < BR; ++i) {
-            const long long row = k0 + rg * BR + i;
+            const long long row = k0 + i * NG + rg;
             const long long src = rows_per_R > 0 ? (row / rows_per_R) * KP + row % rows_per_R : row;
             T[i] = (row < end && c < ncols) ? (double)A[src * lda + c] : 0.0;
         }
+        if (c == 0 && ncols > 0) form(0, 0);
+        __syncthreads();
         for (int j = 0; j < ncols; ++j) {
             const int p = j & 1;
-            if (c == j) {
-                double s = 0.0;
-#pragma unroll
-                for (int i = 0; i < BR; ++i) s += T[i] * T[i];
-                red[p][rg] = s;
-            }
-            __syncthreads();
-            double xn2 = 0.0;
-#pragma unroll
-            for (int q = 0; q < NG; ++q) xn2 += red[p][q];
-            if (xn2 != xn2) {             // NaN in the data: poison R so it reaches the SVD
-                if (c == j && rg == 0) R[j][j] = xn2;
-                continue;
-            }
-            if (!(xn2 > 0.0)) continue;   // uniform: nothing to annihilate in this column
-            const double alpha = R[j][j];
-            const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-            const double tau = (beta - alpha) / beta;
-            const double scal = 1.0 / (alpha - beta);
-            if (c == j) {
-#pragma unroll
-                for (int i = 0; i < BR; ++i) vbuf[p][rg * BR + i] = T[i] * scal;
-            }
-            __syncthreads();
-            double rjc = 0.0;
-            if (c > j && c < ncols) {
+            const double tau = tbuf[p];
+            if (tau != 0.0 && c > j && c < ncols) {
                 double d = 0.0;
 #pragma unroll
-                for (int i = 0; i < BR; ++i) d += vbuf[p][rg * BR + i] * T[i];
-                pdot[p][rg][c] = d;
-                rjc = R[j][c];
+                for (int i = 0; i < BR; ++i) d += vbuf[p][i * NG + rg] * T[i];
+                const double rjc = R[ri(j, c)];
+                const double f = tau * (rjc + colsum(d));
+#pragma unroll
+                for (int i = 0; i < BR; ++i) T[i] -= f * vbuf[p][i * NG + rg];
+                if (rg == 0) R[ri(j, c)] = rjc - f;
             }
-            if (c == j && rg == 0) R[j][j] = beta;
+            if (c == j + 1 && c < ncols) form(j + 1, p ^ 1);
             __syncthreads();
-            if (c > j && c < ncols) {
-                double w = rjc;
-#pragma unroll
-                for (int q = 0; q < NG; ++q) w += pdot[p][q][c];
-                const double f = tau * w;
-#pragma unroll
-                for (int i = 0; i < BR; ++i) T[i] -= f * vbuf[p][rg * BR + i];
-                if (rg == 0) R[j][c] = rjc - f;
-            }
         }
     }
-    __syncthreads();
     double* out = Rout + (size_t)blk * KP * KP;
     for (int idx = tid; idx < KP * KP; idx += KP * NG) {
         const int i = idx / KP, j = idx % KP;
-        out[idx] = (j >= i) ? R[i][j] : 0.0;
+        out[idx] = (j >= i) ? R[ri(i, j)] : 0.0;
     }
 }
 

@@ -63,6 +63,12 @@ enum KClass {
 // kernels (four blocks per CU); the partial buffers are sized for it.
 constexpr int kTuneMaxBlocks = 1024;
 
+// Rows per thread in the 128-column TSQR leaf (chunks of 4 x this many rows):
+// longer chunks mean fewer column steps per block over the tall first core,
+// and 24 still fits two blocks per CU (122 VGPRs; 32 takes 154, one block).
+// Tree levels and the narrower tiles take 16.
+constexpr int kTsqrBrLeaf128 = 24;
+
 struct Plan {
     int dim = 1, nx = 1, ny = 1, nz = 1;
     long long NX = 0, M = 0;
@@ -70,7 +76,8 @@ struct Plan {
     int n_terms = 0, n_bc = 0, cap = 1;
     int r1cap = 1, r2cap = 1, R1cap = 1, R2cap = 1, k1cap = 1, k2cap = 1, ldzcap = 8, ldbcap = 8;
     int n_gather_max = 1, n_r1_max = 1;
-    int KP = 64, chunk = 128;
+    int KP = 64, chunk = 128;      // rows per chunk of a TSQR leaf block
+    int chunk_t = 128;              // and of a tree-level block
     int KPt = 64;                   // column tile of the TSQR (16 for QR-route cores of k1cap <= 16)
     std::vector<int> levP;          // blocks per TSQR level
     std::vector<long long> levRows; // rows per block per level
@@ -252,7 +259,8 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
                                  : p->round_method;
         P.KPt = (method_q == TT_ROUND_QR && P.k1cap <= 16) ? 16 : P.KP;
     }
-    P.chunk = P.KPt == 16 ? 32 * 16 : (P.KP == 64 ? 8 * 16 : 4 * 16);
+    P.chunk = P.KPt == 16 ? 32 * 16 : (P.KP == 64 ? 8 * 16 : 4 * kTsqrBrLeaf128);
+    P.chunk_t = P.KPt == 16 ? 32 * 16 : (P.KP == 64 ? 8 * 16 : 4 * 16);
     P.elem = p->precision == TT_PREC_FP64 ? 8 : 4;
     {
         const int method = p->round_method == TT_ROUND_AUTO
@@ -308,7 +316,7 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         while (prev > 1) {
             // only the first k1 <= k1cap rows of each R factor can be non-zero
             long long nn = (long long)prev * P.k1cap;
-            long long rr = 4LL * P.chunk;
+            long long rr = 4LL * P.chunk_t;
             int Pn = (int)((nn + rr - 1) / rr);
             P.levP.push_back(Pn); P.levRows.push_back(rr); P.levN.push_back(nn);
             prev = Pn;
@@ -1082,7 +1090,7 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
                                        P.levN[L], P.levRows[L], (const DevState*)st, out);
             } else {
                 if (L == 0)
-                    hipLaunchKernelGGL((k_tsqr<T, 128, 4, 16>), dim3(P.levP[L]), dim3(512), 0, s, (const T*)B, 0, 1, 0,
+                    hipLaunchKernelGGL((k_tsqr<T, 128, 4, kTsqrBrLeaf128>), dim3(P.levP[L]), dim3(512), 0, s, (const T*)B, 0, 1, 0,
                                        P.levN[L], P.levRows[L], (const DevState*)st, out);
                 else
                     hipLaunchKernelGGL((k_tsqr<double, 128, 4, 16>), dim3(P.levP[L]), dim3(512), 0, s, in, 128, 0, P.k1cap,

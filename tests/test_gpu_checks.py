@@ -12,8 +12,9 @@ against the CPU oracle.
   fresh handle, solve(K - k) (1e-12 FP64; the warm-started Jacobi of the
   first step after a restore starts cold, which changes only rounding noise).
 * The Householder TSQR tree: QR-route cores of 16 columns with several
-  leaf blocks and one tree level, and of 64 columns with two tree levels,
-  against the oracle at the FP64 bounds (1e-12 per step, 1e-10 per solve).
+  leaf blocks and one tree level, of 64 columns with two tree levels, and of
+  128 columns whose last leaf block ends inside a row chunk, against the
+  oracle at the FP64 bounds (1e-12 per step, 1e-10 per solve).
 * Full sizes: the 128 x 128 x 32-group workload in FP64 (five TSQR levels),
   and the 3D workload's angular shape (8 x 16 directions, rank 64, so the
   sum has R1 = 450 and the projected core k1 = 128) on 24^3 cells x 16
@@ -157,6 +158,32 @@ def test_tsqr_64_column_cores_with_two_tree_levels(tt):
     assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 1e-12
     st = s.solve(6)
     (Zs, Ts, Ps), infos = ott.solve(p, 6, cores=(Zo, To, Po))
+    assert (st["r1"], st["r2"]) == (infos[-1]["r1"], infos[-1]["r2"])
+    assert rel(full(*s.get_cores()), full(Zs, Ts, Ps)) < 1e-10
+    s.destroy()
+
+
+def test_tsqr_128_column_cores_with_a_ragged_leaf(tt):
+    # 3D, 7 x 6 x 5 cells x 8 groups, 8 x 16 directions, from a rank-(64, 16)
+    # state: k1 = 128, M = 1680 rows in five leaf blocks of four 96-row
+    # chunks, the last holding 144 rows (one and a half chunks), then tree
+    # levels of three blocks, two and one
+    rng = np.random.default_rng(6)
+    p = ti.clumps3d(n=8, n_groups=8, n_theta=8, n_phi=16, tol=1e-9, rank_cap=64, precision=ti.PREC_FP64, T=0.3)
+    p.n_cells = (7, 6, 5)
+    p.kappa0 = rng.uniform(0.3, 3.0, 210)
+    p.T_cell = np.full(210, 0.3)
+    print(f"tsqr 128-column ragged leaf M={p.M}", flush=True)
+    s = tt.Solver(p, round_method=tt.TT_ROUND_QR)
+    Z, Th, Ph = ti.random_tt(p.M, 8, 16, 64, 16, seed=21, decay=0.9)
+    s.set_cores(Z, Th, Ph)
+    st = s.solve(1)
+    Zo, To, Po, info = ott.step(p, Z, Th, Ph)
+    assert (info["R1"], st["max_R1"]) == (450, 450)
+    assert s.get_ranks() == (info["r1"], info["r2"])
+    assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 1e-12
+    st = s.solve(4)
+    (Zs, Ts, Ps), infos = ott.solve(p, 4, cores=(Zo, To, Po))
     assert (st["r1"], st["r2"]) == (infos[-1]["r1"], infos[-1]["r2"])
     assert rel(full(*s.get_cores()), full(Zs, Ts, Ps)) < 1e-10
     s.destroy()
