@@ -197,6 +197,16 @@ __global__ __launch_bounds__(256) void k_gather_gemm(Geom g, OpDesc op, const De
     }
 }
 
+// Value of x in another lane of the same 16-lane row, chosen by the DPP
+// control CTRL (both halves of the double moved by one DPP move each).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
 // ---------------------------------------------------------------------------
 // Householder TSQR: R factor of a tall matrix
 // ---------------------------------------------------------------------------
@@ -242,20 +252,30 @@ __device__ __forceinline__ void tsqr_body(const TS* __restrict__ A, int lda_stat
     long long end = begin + rows_per_block;
     if (end > nrows) end = nrows;
     double T[BR];
-    // sum over the NG lanes of one column; the butterfly leaves the same
-    // bits in every lane
+    // sum over the NG lanes of one column: lane swaps within quads, then the
+    // mirror images within 8 and 16 lanes (DPP moves, no LDS round trip),
+    // then shuffles; every pairing adds the same two values, so every lane
+    // ends with the same bits
     auto colsum = [&](double x) __attribute__((always_inline)) {
+        if constexpr (NG >= 2) x += dpp_f64<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+        if constexpr (NG >= 4) x += dpp_f64<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+        if constexpr (NG >= 8) x += dpp_f64<0x141>(x);   // row_half_mirror
+        if constexpr (NG >= 16) x += dpp_f64<0x140>(x);  // row_mirror
 #pragma unroll
-        for (int o = 1; o < NG; o <<= 1) x += __shfl_xor(x, o, NG);
+        for (int o = 16; o < NG; o <<= 1) x += __shfl_xor(x, o, NG);
         return x;
+    };
+    // sums of BR terms in four interleaved chains
+    auto sum4 = [&](auto term) __attribute__((always_inline)) {
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < BR; ++i) a[i & 3] += term(i);
+        return (a[0] + a[1]) + (a[2] + a[3]);
     };
     // run by the NG threads of column col once every earlier reflector has
     // been applied to their values
     auto form = [&](int col, int p) __attribute__((always_inline)) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < BR; ++i) s += T[i] * T[i];
-        const double xn2 = colsum(s);
+        const double xn2 = colsum(sum4([&](int i) { return T[i] * T[i]; }));
         double tau = 0.0;
         if (xn2 != xn2) {
             if (rg == 0) R[ri(col, col)] = xn2;   // NaN in the data: poison R so it reaches the SVD
@@ -283,9 +303,7 @@ __device__ __forceinline__ void tsqr_body(const TS* __restrict__ A, int lda_stat
             const int p = j & 1;
             const double tau = tbuf[p];
             if (tau != 0.0 && c > j && c < ncols) {
-                double d = 0.0;
-#pragma unroll
-                for (int i = 0; i < BR; ++i) d += vbuf[p][i * NG + rg] * T[i];
+                const double d = sum4([&](int i) { return vbuf[p][i * NG + rg] * T[i]; });
                 const double rjc = R[ri(j, c)];
                 const double f = tau * (rjc + colsum(d));
 #pragma unroll

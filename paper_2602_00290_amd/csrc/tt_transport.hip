@@ -66,8 +66,14 @@ constexpr int kTuneMaxBlocks = 1024;
 // Rows per thread in the 128-column TSQR leaf (chunks of 4 x this many rows):
 // longer chunks mean fewer column steps per block over the tall first core,
 // and 24 still fits two blocks per CU (122 VGPRs; 32 takes 154, one block).
-// Tree levels and the narrower tiles take 16.
 constexpr int kTsqrBrLeaf128 = 24;
+// Tree levels of the 64- and 128-column tiles (few blocks, each one chain of
+// column steps) take 32 rows per thread; the 16-column tile takes 16.
+constexpr int kTsqrBrTree = 32;
+// Leaf blocks of the TSQR at most: two resident blocks per CU on 256 CUs,
+// so the whole first core is one wave of blocks and the tree starts from as
+// few R factors as that allows.
+constexpr int kTsqrMaxLeaves = 512;
 
 struct Plan {
     int dim = 1, nx = 1, ny = 1, nz = 1;
@@ -260,7 +266,7 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         P.KPt = (method_q == TT_ROUND_QR && P.k1cap <= 16) ? 16 : P.KP;
     }
     P.chunk = P.KPt == 16 ? 32 * 16 : (P.KP == 64 ? 8 * 16 : 4 * kTsqrBrLeaf128);
-    P.chunk_t = P.KPt == 16 ? 32 * 16 : (P.KP == 64 ? 8 * 16 : 4 * 16);
+    P.chunk_t = P.KPt == 16 ? 32 * 16 : (P.KP == 64 ? 8 * kTsqrBrTree : 4 * kTsqrBrTree);
     P.elem = p->precision == TT_PREC_FP64 ? 8 : 4;
     {
         const int method = p->round_method == TT_ROUND_AUTO
@@ -303,11 +309,12 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
     // TSQR levels
     {
         long long n = P.M;
-        // four chunks per leaf block; a small core (fewer than four such
-        // blocks) gets one chunk per block, and its tree stays short
+        // four chunks per leaf block, more once the blocks would exceed the
+        // cap; a small core (fewer than four such blocks) gets one chunk per
+        // block, and its tree stays short
         long long want = (n + 4 * P.chunk - 1) / (4 * P.chunk);
         if (want < 4) want = (n + P.chunk - 1) / P.chunk;
-        int P1 = (int)std::min<long long>(2048, std::max<long long>(1, want));
+        int P1 = (int)std::min<long long>(kTsqrMaxLeaves, std::max<long long>(1, want));
         long long rows = (n + P1 - 1) / P1;
         rows = (rows + P.chunk - 1) / P.chunk * P.chunk;
         P1 = (int)((n + rows - 1) / rows);
@@ -316,7 +323,10 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         while (prev > 1) {
             // only the first k1 <= k1cap rows of each R factor can be non-zero
             long long nn = (long long)prev * P.k1cap;
-            long long rr = 4LL * P.chunk_t;
+            // one chunk per block (at least two factors): the levels have
+            // few blocks, so the chain of column steps per block is the time
+            long long rr = std::max<long long>(P.chunk_t, 2LL * P.k1cap);
+            rr = (rr + P.chunk_t - 1) / P.chunk_t * P.chunk_t;
             int Pn = (int)((nn + rr - 1) / rr);
             P.levP.push_back(Pn); P.levRows.push_back(rr); P.levN.push_back(nn);
             prev = Pn;
@@ -1086,14 +1096,14 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
                     hipLaunchKernelGGL((k_tsqr<T, 64, 8, 16>), dim3(P.levP[L]), dim3(512), 0, s, (const T*)B, 0, 1, 0,
                                        P.levN[L], P.levRows[L], (const DevState*)st, out);
                 else
-                    hipLaunchKernelGGL((k_tsqr<double, 64, 8, 16>), dim3(P.levP[L]), dim3(512), 0, s, in, 64, 0, P.k1cap,
+                    hipLaunchKernelGGL((k_tsqr<double, 64, 8, kTsqrBrTree>), dim3(P.levP[L]), dim3(512), 0, s, in, 64, 0, P.k1cap,
                                        P.levN[L], P.levRows[L], (const DevState*)st, out);
             } else {
                 if (L == 0)
                     hipLaunchKernelGGL((k_tsqr<T, 128, 4, kTsqrBrLeaf128>), dim3(P.levP[L]), dim3(512), 0, s, (const T*)B, 0, 1, 0,
                                        P.levN[L], P.levRows[L], (const DevState*)st, out);
                 else
-                    hipLaunchKernelGGL((k_tsqr<double, 128, 4, 16>), dim3(P.levP[L]), dim3(512), 0, s, in, 128, 0, P.k1cap,
+                    hipLaunchKernelGGL((k_tsqr<double, 128, 4, kTsqrBrTree>), dim3(P.levP[L]), dim3(512), 0, s, in, 128, 0, P.k1cap,
                                        P.levN[L], P.levRows[L], (const DevState*)st, out);
             }
             h->ev_end(e, s);

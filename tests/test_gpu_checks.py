@@ -12,10 +12,10 @@ against the CPU oracle.
   fresh handle, solve(K - k) (1e-12 FP64; the warm-started Jacobi of the
   first step after a restore starts cold, which changes only rounding noise).
 * The Householder TSQR tree: QR-route cores of 16 columns with several
-  leaf blocks and one tree level, of 64 columns with two tree levels, and of
+  leaf blocks and one tree level, of 64 columns with three tree levels, and of
   128 columns whose last leaf block ends inside a row chunk, against the
   oracle at the FP64 bounds (1e-12 per step, 1e-10 per solve).
-* Full sizes: the 128 x 128 x 32-group workload in FP64 (five TSQR levels),
+* Full sizes: the 128 x 128 x 32-group workload in FP64 (six TSQR levels),
   and the 3D workload's angular shape (8 x 16 directions, rank 64, so the
   sum has R1 = 450 and the projected core k1 = 128) on 24^3 cells x 16
   groups in FP64, FP32 and split BF16 at their bounds (1e-12, 2e-6, 5e-5 per
@@ -144,10 +144,11 @@ def test_tsqr_16_column_cores_with_a_tree_level(tt):
     s.destroy()
 
 
-def test_tsqr_64_column_cores_with_two_tree_levels(tt):
-    # 2D, 32 x 32 cells x 8 groups, 8 x 8 directions: k1 = 64, M = 8192 rows in
-    # 16 leaf blocks, then tree levels of two blocks and one
-    p = _plane(n=(32, 32), G=8, nt=8, nphi=8, tol=1e-7, cap=32, seed=5)
+def test_tsqr_64_column_cores_with_three_tree_levels(tt):
+    # 2D, 44 x 44 cells x 8 groups, 8 x 8 directions: k1 = 64, M = 15488 rows
+    # in 31 leaf blocks of four 128-row chunks (the last holds one), then tree
+    # levels of eight blocks (the last with 192 rows), two and one
+    p = _plane(n=(44, 44), G=8, nt=8, nphi=8, tol=1e-7, cap=32, seed=5)
     print("tsqr 64-column two levels", flush=True)
     s = tt.Solver(p, round_method=tt.TT_ROUND_QR)
     Z, Th, Ph = ti.random_tt(p.M, 8, 8, 20, 8, seed=8, decay=0.75)
@@ -167,7 +168,7 @@ def test_tsqr_128_column_cores_with_a_ragged_leaf(tt):
     # 3D, 7 x 6 x 5 cells x 8 groups, 8 x 16 directions, from a rank-(64, 16)
     # state: k1 = 128, M = 1680 rows in five leaf blocks of four 96-row
     # chunks, the last holding 144 rows (one and a half chunks), then tree
-    # levels of three blocks, two and one
+    # levels of three blocks (the last with 128 rows), two and one
     rng = np.random.default_rng(6)
     p = ti.clumps3d(n=8, n_groups=8, n_theta=8, n_phi=16, tol=1e-9, rank_cap=64, precision=ti.PREC_FP64, T=0.3)
     p.n_cells = (7, 6, 5)
@@ -191,7 +192,7 @@ def test_tsqr_128_column_cores_with_a_ragged_leaf(tt):
 
 def test_plane2d_full_size_one_step_fp64(tt):
     # the 2D workload at full size in FP64 (Householder TSQR over 524288 rows:
-    # 1024 leaf blocks and four tree levels), one step from a rank-(32, 8) state
+    # 512 leaf blocks and five tree levels), one step from a rank-(32, 8) state
     p = ti.plane2d(precision=ti.PREC_FP64)
     print("plane2d full size fp64", flush=True)
     s = tt.Solver(p, round_method=tt.TT_ROUND_QR)
