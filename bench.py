@@ -22,10 +22,10 @@ rounding), each compared with the dense FP64 oracle march; the 1D slab as
 top-level p50_ms / p99_ms); and `cpu_baseline`, the dense FP64 CPU oracle
 timed on z-slabs of the same 64^3 cube and scaled to the whole cube.
 
-Prints one JSON line.  `roofline` covers the dominant kernel, the FP64 MFMA
-gather projection of the 3D headline, from its HIP-event times; `traffic` its
-HBM bytes per launch from the committed counter summary (null when the kernel
-source has changed since).
+Prints one JSON line.  `roofline` covers the dominant kernel, the
+direction-space stencil of the 3D headline's FP64 projection, from its
+HIP-event times; `traffic` its HBM bytes per launch from the committed counter
+summary (null when the kernel source has changed since).
 
 Other modes (for profiling runs; they print one line and exit):
   --mode probe        one solve of `--probe-workload` for `--probe-steps` steps (clumps3d_fp64 first
@@ -377,9 +377,11 @@ def mode_probe(args):
         prob = rusanov_scatter_problem(ti)
     elif args.probe_workload == "plane2d_randomized":
         prob = ti.plane2d().copy(round_method=ti.ROUND_RAND, rand_oversample=4, rand_seed=0)
+    elif args.probe_workload == "plane2d_fp64_qr":
+        prob = ti.plane2d(precision=ti.PREC_FP64)
     else:
         prob = ti.plane2d()
-    s = tt.Solver(prob)
+    s = tt.Solver(prob, round_method=tt.TT_ROUND_QR) if args.probe_workload == "plane2d_fp64_qr" else tt.Solver(prob)
     st = s.solve(args.probe_steps)
     torch.cuda.synchronize()
     print(json.dumps({"mode": "probe", "workload": args.probe_workload, "steps": args.probe_steps,
@@ -755,12 +757,13 @@ def main():
     ap.add_argument("--probe-steps", type=int, default=64)
     ap.add_argument("--probe-workload", default="plane2d",
                     choices=["plane2d", "clumps3d", "clumps3d_fp64", "plane2d_coupled", "plane2d_rusanov_scatter",
-                             "plane2d_randomized"],
+                             "plane2d_randomized", "plane2d_fp64_qr"],
                     help="probe workload: plane2d (FP32), clumps3d (64^3 cells, 64 groups, split BF16), "
                          "clumps3d_fp64 (the headline: FP64, Gram rounding, ranks at the cap first), "
                          "plane2d_coupled (plane2d with the coupled medium temperature, heat capacity 8 a), "
                          "plane2d_rusanov_scatter (plane2d with the Rusanov flux and scattering kappa_s = kappa_a), "
-                         "or plane2d_randomized (plane2d with randomized rounding, sketch ranks = ranks + 4)")
+                         "plane2d_randomized (plane2d with randomized rounding, sketch ranks = ranks + 4), "
+                         "or plane2d_fp64_qr (plane2d in FP64 with Householder TSQR rounding)")
     ap.add_argument("--tune", type=int, default=1,
                     help="tune the launch shapes of the 3D solves once their ranks reach the cap (untimed)")
     ap.add_argument("--tune-cache", default=None, help="tuning cache file (default: none, always time)")
