@@ -14,7 +14,9 @@ against the CPU oracle.
 * The Householder TSQR tree: QR-route cores of 16 columns with several
   leaf blocks and one tree level, of 64 columns with three tree levels, and of
   128 columns whose last leaf block ends inside a row chunk, against the
-  oracle at the FP64 bounds (1e-12 per step, 1e-10 per solve).
+  oracle at the FP64 bounds (1e-12 per step, 1e-10 per solve); and at tol
+  1e-14 a 2D solve with TSQR rounding equals the dense march to 1e-10 (Gram
+  rounding to 1e-5).
 * Full sizes: the 128 x 128 x 32-group workload in FP64 (six TSQR levels),
   and the 3D workload's angular shape (8 x 16 directions, rank 64, so the
   sum has R1 = 450 and the projected core k1 = 128) on 24^3 cells x 16
@@ -25,7 +27,7 @@ import numpy as np
 import pytest
 
 import tt_inputs as ti
-from oracle import tt as ott
+from oracle import dense, tt as ott
 
 pytestmark = pytest.mark.gpu
 
@@ -188,6 +190,26 @@ def test_tsqr_128_column_cores_with_a_ragged_leaf(tt):
     assert (st["r1"], st["r2"]) == (infos[-1]["r1"], infos[-1]["r2"])
     assert rel(full(*s.get_cores()), full(Zs, Ts, Ps)) < 1e-10
     s.destroy()
+
+
+def test_tsqr_rounding_at_tol_1e14_matches_the_dense_march(tt):
+    # 2D, 12 x 10 cells x 4 groups, 8 x 8 directions, tol 1e-14 and a cap above
+    # the solution's rank: with Householder TSQR rounding (64-column tile, four
+    # leaf blocks and one tree level) the TT solve equals the dense FP64 march
+    # to 1e-10 after 24 steps; Gram rounding, which resolves singular values
+    # only down to ~1e-8 of the norm, stays within 1e-5
+    p = _plane(n=(12, 10), G=4, nt=8, nphi=8, tol=1e-14, cap=64, seed=2)
+    print(f"tol 1e-14 against the dense march M={p.M}", flush=True)
+    ref = dense.march(p, dense.initial_dense(p), 24)
+    errs = {}
+    for name, method in (("qr", tt.TT_ROUND_QR), ("gram", tt.TT_ROUND_GRAM)):
+        s = tt.Solver(p, round_method=method)
+        s.solve(24)
+        errs[name] = rel(full(*s.get_cores()), ref)
+        s.destroy()
+    print(f"rel-L2 against the dense march: {errs}", flush=True)
+    assert errs["qr"] < 1e-10
+    assert errs["gram"] < 1e-5
 
 
 def test_plane2d_full_size_one_step_fp64(tt):
