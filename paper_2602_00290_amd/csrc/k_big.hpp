@@ -212,14 +212,15 @@ __device__ __forceinline__ double dpp_f64(double x) {
 // ---------------------------------------------------------------------------
 //
 // Each block owns a contiguous range of rows and keeps an upper-triangular R
-// (KP x KP, FP64, packed) in LDS.  Rows arrive in chunks of NG*BR; the NG threads of
-// column c (adjacent lanes of one wave) hold BR rows each of the chunk's
-// column c in registers (thread rg holds chunk rows i*NG + rg).  For every
-// column j the reflector that zeroes the chunk's column j against R[j][j] is
-// formed (LAPACK dlarfg convention: beta = -sign(alpha) ||(alpha, x)||,
-// tau = (beta - alpha) / beta, v = x / (alpha - beta)) and applied to the
-// columns c > j of R and of the chunk.  A column's dot product v^T T[:, c]
-// runs down its threads' registers and across their lanes with shuffles, so
+// (KP x KP, FP64, packed by rows) in LDS.  Rows arrive in chunks of NG*BR;
+// the NG threads of column c (adjacent lanes of one wave) hold BR rows each
+// of the chunk's column c in registers (thread rg holds chunk rows
+// i*NG + rg).  For every column j the reflector that zeroes the chunk's
+// column j against R[j][j] is formed (LAPACK dlarfg convention:
+// beta = -sign(alpha) ||(alpha, x)||, tau = (beta - alpha) / beta,
+// v = x / (alpha - beta)) and applied to the columns c > j of R and of the
+// chunk.  A column's dot product v^T T[:, c] runs down its threads'
+// registers and across their lanes (DPP moves, shuffles beyond 16 lanes), so
 // only the reflector crosses waves: the threads of column j + 1 form it as
 // soon as their own update by reflector j is done, and one block barrier per
 // column step publishes it.  The block writes its final R (KP x KP, zeros
