@@ -265,7 +265,8 @@ typedef struct tt_handle tt_handle;
 
 /* Bytes of device workspace needed for `p` at its rank cap.  FP64 problems
  * whose projected first core can exceed 64 columns also hold Y = Z W
- * (M x 128 doubles) for the direction-space projection.  Returns 0 for an
+ * (M rows of up to 128 doubles, 32 doubles of padding each) for the
+ * direction-space projection.  Returns 0 for an
  * invalid problem (see tt_transport_last_error). */
 size_t tt_transport_workspace_bytes(const tt_problem* p);
 

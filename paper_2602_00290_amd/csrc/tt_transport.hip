@@ -354,7 +354,7 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         P.B_bytes = std::min<size_t>(P.B_bytes, std::max<size_t>((size_t)16 << 20, (size_t)P.R1cap * sizeof(double)));
     P.o_B = take(P.B_bytes);
     if (P.stencil) {
-        P.o_Y = take((size_t)P.M * P.ldbcap * sizeof(double));
+        P.o_Y = take((size_t)P.M * (P.ldbcap + kYPad) * sizeof(double));
         P.o_Wst = take((size_t)P.ldzcap * P.ldbcap * sizeof(double));
         P.o_Cst = take((size_t)(kStNG + kStZ) * P.ldbcap * sizeof(double));
     }
