@@ -263,10 +263,11 @@ typedef struct tt_internal_ranks {
 
 typedef struct tt_handle tt_handle;
 
-/* Bytes of device workspace needed for `p` at its rank cap.  FP64 problems
- * whose projected first core can exceed 64 columns also hold Y = Z W
- * (M rows of up to 128 doubles, 32 doubles of padding each) for the
- * direction-space projection.  Returns 0 for an
+/* Bytes of device workspace needed for `p` at its rank cap.  FP64 and FP32
+ * problems whose projected first core can exceed 64 columns also hold
+ * Y = Z W (M rows of up to 128 elements of the data type, 32 elements of
+ * padding each; FP32 also an FP32 copy of W) for the direction-space
+ * projection.  Returns 0 for an
  * invalid problem (see tt_transport_last_error). */
 size_t tt_transport_workspace_bytes(const tt_problem* p);
 

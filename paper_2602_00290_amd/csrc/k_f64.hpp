@@ -34,12 +34,6 @@
 
 namespace ttrt {
 
-// Y's rows are ldb + kYPad doubles apart (two extra 128-byte lines per row),
-// so that the stencil's taps, whole rows 1, n_x and n_x n_y rows apart, do
-// not all start at the same offset of a power-of-two address stride: over
-// twelve allocations the 3D stencil took 11.0 ms on average against 12.1
-// unpadded (11.3 with four lines)
-constexpr int kYPad = 32;
 constexpr int kF64Waves = 8;
 constexpr int kF64Threads = 64 * kF64Waves;
 constexpr int kF64Rows = 32 * kF64Waves;   // rows per row block (two row tiles per wave)
@@ -48,6 +42,7 @@ constexpr int kF64LdK = kF64KC + 2;        // LDS column stride (doubles) of the
 constexpr int kF64Z = kMaxBC + 4;          // rank-1 value rows (read four at a time)
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 // Gather blocks whose rows the row data holds: the identity and the shifted
 // copies (upwind, Rusanov), or up to kMaxBlocks with the HLL flux's
@@ -659,5 +654,161 @@ __global__ __launch_bounds__(64 * kStWaves) void k_stencil_f64(Geom g, OpDesc op
         __syncthreads();   // the block's waves start each task together
     }
 }
+
+// The same stencil for FP32 data (FP32 Y and B, rows of Y ldb + kYPadF
+// floats apart), with FP32 sums as the gathered FP32 contraction forms B.
+__global__ __launch_bounds__(64 * kStWaves) void k_stencil_f32(Geom g, OpDesc op, const DevState* __restrict__ st,
+                                                              const float* __restrict__ Y,
+                                                              const double* __restrict__ Cst, float* __restrict__ B,
+                                                              RowData rd) {
+    if (!st->stencil) return;
+    __shared__ double s_R[kStZ * 128];                       // rank-1 direction rows
+    __shared__ double s_cf[kStNG * 128];                     // gather blocks' direction factors
+    __shared__ int s_nbr[kStWaves][kStNG][kStRows];          // gather rows (-1: none)
+    __shared__ double s_d[kStWaves][kStRows];                // absorption factor
+    __shared__ double s_z[kStWaves][kStZ][kStRows];          // rank-1 values
+    const int ldb = st->ldb, ng = op.n_gather, nq = op.n_r1;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    for (int i = tid; i < nq * ldb; i += 64 * kStWaves) {
+        const int q = i / ldb, c = i - q * ldb;
+        s_R[q * 128 + c] = Cst[(size_t)(ng + q) * ldb + c];
+    }
+    for (int i = tid; i < kStNG * 128; i += 64 * kStWaves) {
+        const int j = i >> 7, c = i & 127;
+        s_cf[i] = (j < ng && c < ldb) ? Cst[(size_t)j * ldb + c] : 0.0;
+    }
+    const int c0 = 2 * l;
+    const bool colok = c0 < ldb;   // ldb is a multiple of 8, so c0 + 1 < ldb too
+    __syncthreads();
+    f32x2 cf32[kStNG];   // this lane's direction factors
+#pragma unroll
+    for (int j = 0; j < kStNG; ++j) cf32[j] = (f32x2){(float)s_cf[j * 128 + c0], (float)s_cf[j * 128 + c0 + 1]};
+
+    // Rows are taken in Y's group-major order (grp N_X + cell), in batches of
+    // 64.  When an x-y plane is a whole number of batches, a block's task is
+    // one batch position pb of the plane in kStWaves consecutive planes of one
+    // group: wave w takes plane iz0 + w, so most z-neighbours of a wave's
+    // rows are the rows its neighbouring waves load at the same time (the
+    // block's waves keep step by a barrier per task), and consecutive tasks,
+    // dealt to the XCD's blocks in turn, are the next batch positions of the
+    // plane (the y-neighbours when n_x = 64).  Each XCD sweeps a contiguous
+    // region of tasks.  Otherwise the waves take consecutive batches in
+    // turn.  B is written group-major like Y, in whole contiguous rows: the
+    // Gram and the Householder QR of B do not depend on the row order, and
+    // the output contraction maps the rows back to the state's order
+    // (cell G + grp).
+    const int nb = gridDim.x, b = blockIdx.x;
+    const long long nbat = (g.M + kStRows - 1) / kStRows;
+    const int NXc = g.nx * g.ny * g.nz;
+    const int plane = g.nx * g.ny;
+    const int PB = (plane % kStRows == 0) ? plane / kStRows : 0;   // batches per plane (0: no tiling)
+    const int nzb = (g.nz + kStWaves - 1) / kStWaves;                // plane blocks per group
+    const long long ntask = PB ? (long long)g.G * nzb * PB : (nbat + kStWaves - 1) / kStWaves;
+    int nbx = nb, bx = b;            // blocks of this XCD, this block's index there
+    long long reg0 = 0, reg1 = ntask;
+    if (nb % 8 == 0) {
+        const int xcd = b % 8;
+        nbx = nb / 8;
+        bx = b / 8;
+        reg0 = xcd * ntask / 8;
+        reg1 = (xcd + 1) * ntask / 8;
+    }
+    const double rNX = 1.0 / NXc, rnx = 1.0 / g.nx, rny = 1.0 / g.ny;
+    for (long long task = reg0 + bx; task < reg1; task += nbx) {
+        long long bt;
+        bool have;
+        if (PB) {
+            const int pb = (int)(task % PB);
+            const long long t2 = task / PB;
+            const int zb = (int)(t2 % nzb), grp0 = (int)(t2 / nzb);
+            const int iz = zb * kStWaves + w;
+            have = iz < g.nz;
+            bt = ((long long)grp0 * g.nz + iz) * PB + pb;
+        } else {
+            bt = task * kStWaves + w;
+            have = bt < nbat;
+        }
+        const long long row0 = bt * kStRows;   // group-major
+        if (have) {
+            {
+                // lane l: row data of group-major row row0 + l (row k of Z and B)
+                const long long kg = row0 + l;
+                const bool ok = kg < g.M;
+                int cell = 0, ix = 0, iy = 0, iz = 0;
+                const int grp = ok ? divmod_d((int)kg, NXc, rNX, cell) : 0;
+                const long long k = (long long)cell * g.G + grp;
+                iy = divmod_d(cell, g.nx, rnx, ix);
+                iz = divmod_d(iy, g.ny, rny, iy);
+                const int idx3[3] = {ix, iy, iz}, n3[3] = {g.nx, g.ny, g.nz};
+                const int st3[3] = {1, g.nx, g.nx * g.ny};
+                for (int j = 0; j < ng; ++j) {
+                    int src = ok ? (int)kg : -1;
+                    if (j > 0 && ok) {
+                        const int ax = op.gaxis[j], dir = op.gdir[j];
+                        int jj = idx3[ax] + dir;
+                        const bool out = jj < 0 || jj >= n3[ax];
+                        if (out && !g.periodic[ax]) src = -1;
+                        else {
+                            jj = out ? (jj + n3[ax]) % n3[ax] : jj;
+                            src = (int)kg + (jj - idx3[ax]) * st3[ax];
+                        }
+                    }
+                    s_nbr[w][j][l] = src;
+                }
+                double kap = 0.0;
+                if (ok) kap = rd.kfull ? rd.kfull[k] : rd.kappa0[cell] * rd.kscale[grp];
+                const double ktot = (ok && rd.kscat) ? kap + rd.kscat[k] : kap;
+                s_d[w][l] = (ok && op.scale_d) ? 1.0 / (1.0 + g.cdt * ktot) : 1.0;
+                for (int qq = 0; qq < nq; ++qq) {
+                    double v = 0.0;
+                    if (ok) {
+                        if (op.r1kind[qq] == 0) {
+                            v = g.cdt * kap * rd.eps[k];
+                            if (rd.kscat) v += g.cdt * rd.kscat[k] * rd.jn[k];
+                        } else {
+                            const int face = op.r1face[qq], ax = face >> 1;
+                            const int edge = (face & 1) ? n3[ax] - 1 : 0;
+                            if (idx3[ax] == edge) v = op.r1coef[qq] * rd.ghost[face * g.G + grp];
+                        }
+                    }
+                    s_z[w][qq][l] = v;
+                }
+            }
+            // the row data is read by the other lanes of this wave: LDS
+            // operations of a wave complete in order, and the compiler keeps
+            // them in program order across this barrier
+            __builtin_amdgcn_wave_barrier();
+            const int nrow = (int)((g.M - row0) < kStRows ? (g.M - row0) : kStRows);
+            {
+                for (int i = 0; i < nrow; ++i) {
+                    // all taps' loads first, then the sums
+                    f32x2 y[kStNG];
+#pragma unroll
+                    for (int j = 0; j < kStNG; ++j) {
+                        y[j] = (f32x2){0.0f, 0.0f};
+                        if (j < ng) {
+                            const int src = s_nbr[w][j][i];
+                            if (src >= 0 && colok)
+                                y[j] = *reinterpret_cast<const f32x2*>(Y + (size_t)src * (ldb + kYPadF) + c0);
+                        }
+                    }
+                    f32x2 acc = (f32x2){0.0f, 0.0f};
+#pragma unroll
+                    for (int j = 0; j < kStNG; ++j) acc += cf32[j] * y[j];
+                    for (int qq = 0; qq < nq; ++qq) {
+                        const float z = (float)s_z[w][qq][i];
+                        acc += z * (f32x2){(float)s_R[qq * 128 + c0], (float)s_R[qq * 128 + c0 + 1]};
+                    }
+                    if (colok)
+                        *reinterpret_cast<f32x2*>(B + (size_t)(row0 + i) * ldb + c0) = acc * (float)s_d[w][i];
+                }
+            }
+            __builtin_amdgcn_wave_barrier();   // this batch's row data is read before the next overwrites it
+        }
+        __syncthreads();   // the block's waves start each task together
+    }
+}
+
+
 
 }  // namespace ttrt

@@ -14,9 +14,21 @@ namespace ttrt {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+// out[i] = (float)in[i], i < n.
+__global__ __launch_bounds__(256) void k_f64_to_f32(const double* __restrict__ in, float* __restrict__ out, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
+
 // FP32 gather contraction on MFMA (same operation as k_gather_gemm<float, MODE>):
 //   MODE_PROJECT: B[k,:] = d_k (sum_j Z[nbr_j(k),:] G_j + sum_q z_q(k) G_rank1[q])
 //   MODE_OUTPUT:  Z_out = B V_r
+//   MODE_ANGLE:   Y = Z W for the direction-space projection: Y's group-major
+//                 row grp N_X + cell from Z's row cell G + grp, rows ldb + kYPad
+//                 apart (Gop = W, N_r1 x ldb)
+// A pass in direction space leaves B group-major: the gathered projection
+// then stands aside, and the output writes row grp N_X + cell of B V_r to
+// the state's row cell G + grp.
 // Block: 128 rows x BN columns, 4 waves of 32 rows each; K staged in chunks of
 // 32 through LDS (row stride 33 floats: conflict-free column reads).
 template <int MODE, int BN>
@@ -32,18 +44,31 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(Geom g, OpDesc op, const 
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const long long row0 = (long long)blockIdx.x * BM;
     const int col0 = blockIdx.y * BN;
+    if (MODE == MODE_PROJECT && st->stencil) return;
+    if (MODE == MODE_ANGLE && !st->stencil) return;
     int lda, ldg, ldo, nblk, kper;
     if (MODE == MODE_PROJECT) {
         lda = st->ldz; kper = st->ldz; ldg = st->ldb; ldo = st->ldb; nblk = op.n_gather;
+    } else if (MODE == MODE_ANGLE) {
+        lda = st->ldz; kper = st->ldz; ldg = st->ldb; ldo = st->ldb + kYPadF; nblk = 1;
     } else {
         lda = st->ldb; kper = st->ldb; ldg = st->ldzn; ldo = st->ldzn; nblk = 1;
     }
-    if (col0 >= ldo) return;
+    const int ncol = MODE == MODE_ANGLE ? st->ldb : ldo;   // columns formed
+    if (col0 >= ncol) return;
+    const int NXc = (int)(g.M / g.G);
     for (int idx = tid; idx < nblk * BM; idx += 256) {
         const int j = idx / BM, i = idx % BM;
         const long long k = row0 + i;
         long long src = -1;
-        if (k < g.M) src = (MODE == MODE_OUTPUT || j == 0) ? k : neighbour_row(g, k, op.gaxis[j], op.gdir[j]);
+        if (k < g.M) {
+            if (MODE == MODE_ANGLE) {
+                const int grp = (int)(k / NXc), cell = (int)(k - (long long)grp * NXc);
+                src = (long long)cell * g.G + grp;
+            } else {
+                src = (MODE == MODE_OUTPUT || j == 0) ? k : neighbour_row(g, k, op.gaxis[j], op.gdir[j]);
+            }
+        }
         nbr[j][i] = src;
     }
     if (MODE == MODE_PROJECT && tid < BM) {
@@ -108,10 +133,11 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(Geom g, OpDesc op, const 
         }
     }
     // epilogue: D[i][j] of wave w sits in lane j + 32*((i/4)%2), register 4*(i/8) + i%4
+    const bool gm_out = MODE == MODE_OUTPUT && st->stencil;
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
         const int col = col0 + 32 * c + (l & 31);
-        if (col >= ldo) continue;
+        if (col >= ncol) continue;
         float g1[kMaxBC + 1];
         if (MODE == MODE_PROJECT) {
             const int base = op.n_gather * kper;
@@ -128,7 +154,12 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(Geom g, OpDesc op, const 
                 for (int q = 0; q < op.n_r1; ++q) v += rowz[q][il] * g1[q];
                 v *= rowd[il];
             }
-            Out[k * ldo + col] = v;
+            long long orow = k;
+            if (gm_out) {
+                const int grp = (int)(k / NXc), cell = (int)(k - (long long)grp * NXc);
+                orow = (long long)cell * g.G + grp;
+            }
+            Out[orow * ldo + col] = v;
         }
     }
 }

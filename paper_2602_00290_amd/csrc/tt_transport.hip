@@ -125,8 +125,9 @@ struct Plan {
     // direction-space projection (Y = Z W, then the operator's stencil on Y)
     // for 128-column FP64 cores once both small-core factors are square
     bool stencil = false;
+    bool stencil32 = false;         // ... on FP32 data (FP32 MFMA Y = Z W, FP32 Y and B)
     int st_blocks = 1;              // blocks of the stencil kernel
-    size_t o_Y = 0, o_Wst = 0, o_Cst = 0;
+    size_t o_Y = 0, o_Wst = 0, o_Cst = 0, o_WstF = 0;
     size_t o_state, o_Z0, o_Z1, o_B, o_Th0, o_Th1, o_Ph0, o_Ph1, o_LTh, o_QTh, o_QPh, o_G, o_V, o_RA, o_RB, o_small,
         o_k0, o_ks, o_kfull = 0, o_eps, o_ghost, o_gtab, o_htab, o_ThN, o_PhN, o_sv, o_colsum;
     size_t small_bytes = 0, n_parts_max = 1;
@@ -300,6 +301,10 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         if (P.f64_blocks > 8) P.f64_blocks = P.f64_blocks / 8 * 8;
         P.f64_blocks_o = P.f64_blocks;
         P.stencil = P.f64mm && P.nct_f == 8;
+        // FP32 data with a stored B of more than 64 columns: the same pass
+        P.stencil32 = p->precision == TT_PREC_FP32 && !P.fused && P.ldbcap > 64 && P.ldbcap <= 128 &&
+                      P.M < (1LL << 31);
+        P.stencil = P.stencil || P.stencil32;
         P.st_blocks = (int)std::max<long long>(1, std::min<long long>(256, (P.M + kStRows - 1) / kStRows / kStWaves));
         if (P.st_blocks > 8) P.st_blocks = P.st_blocks / 8 * 8;
         // launch-shape tuning may take up to four blocks per CU
@@ -354,9 +359,10 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         P.B_bytes = std::min<size_t>(P.B_bytes, std::max<size_t>((size_t)16 << 20, (size_t)P.R1cap * sizeof(double)));
     P.o_B = take(P.B_bytes);
     if (P.stencil) {
-        P.o_Y = take((size_t)P.M * (P.ldbcap + kYPad) * sizeof(double));
+        P.o_Y = take((size_t)P.M * (P.ldbcap + (P.stencil32 ? kYPadF : kYPad)) * P.elem);
         P.o_Wst = take((size_t)P.ldzcap * P.ldbcap * sizeof(double));
         P.o_Cst = take((size_t)(kStNG + kStZ) * P.ldbcap * sizeof(double));
+        if (P.stencil32) P.o_WstF = take((size_t)P.ldzcap * P.ldbcap * sizeof(float));
     }
     P.bf16x = p->precision == TT_PREC_BF16X;
     if (P.bf16x && P.M >= (1LL << 31))
@@ -940,7 +946,7 @@ void launch_prep(tt_handle* h, int opkind, hipStream_t s) {
     const Plan& P = h->P;
     constexpr bool f32 = std::is_same<T, float>::value;
     const bool fused = f32 && P.fused;
-    const bool sten = !f32 && stencil_op(h, opkind);
+    const bool sten = stencil_op(h, opkind);
     hipLaunchKernelGGL(k_prep<T>, dim3(1), dim3(kSmallThreads), kSmallLdsBytes, s, h->geom, h->ops[opkind], h->st(),
                        h->Thc(), h->Phc(), h->at<double>(P.o_gtab), h->at<double>(P.o_htab), h->scratch(),
                        h->at<double>(P.o_LTh), P.k1cap, h->at<double>(P.o_QTh), h->at<double>(P.o_QPh),
@@ -977,6 +983,27 @@ tt_status launch_project(tt_handle* h, int opkind, hipStream_t s) {
             hipLaunchKernelGGL(k_stencil_f64, dim3(P.st_blocks), dim3(64 * kStWaves), 0, s, h->geom, op,
                                (const DevState*)st, (const double*)Yb, (const double*)h->at<double>(P.o_Cst),
                                (double*)B, h->rowdata());
+            h->ev_end(e, s);
+        }
+    }
+    if constexpr (f32) {
+        if (P.stencil32 && stencil_op(h, opkind)) {
+            // the same on FP32 data: W to FP32, Y = Z W on FP32 MFMA, the
+            // stencil with FP64 sums into the FP32 B
+            float* Yf = h->at<float>(P.o_Y);
+            float* Wf = h->at<float>(P.o_WstF);
+            size_t e = h->ev_begin(KC_ANGLE, s);
+            const int nw = P.ldzcap * P.ldbcap;
+            hipLaunchKernelGGL(k_f64_to_f32, dim3((nw + 255) / 256), dim3(256), 0, s,
+                               (const double*)h->at<double>(P.o_Wst), Wf, nw);
+            hipLaunchKernelGGL((k_gemm_f32_mfma<MODE_ANGLE, 128>), dim3(gx128, 1), dim3(256), 0, s,
+                               h->geom, op, (const DevState*)st, (const float*)h->Zc(), (const float*)Wf, Yf,
+                               h->rowdata());
+            h->ev_end(e, s);
+            e = h->ev_begin(KC_STENCIL, s);
+            hipLaunchKernelGGL(k_stencil_f32, dim3(P.st_blocks), dim3(64 * kStWaves), 0, s, h->geom, op,
+                               (const DevState*)st, (const float*)Yf, (const double*)h->at<double>(P.o_Cst),
+                               (float*)B, h->rowdata());
             h->ev_end(e, s);
         }
     }

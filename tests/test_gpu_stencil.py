@@ -31,7 +31,11 @@ result with the oracle:
   64-row batches and each stencil block takes one batch position in up to 16
   consecutive planes (five here, so most of its waves idle), with z periodic
   or with inflow on both z faces: against the oracle's step (1e-12, equal
-  ranks).
+  ranks);
+* FP32 data (Y = Z W on FP32 MFMA, FP32 Y and B, FP64 sums in the stencil):
+  one step of the 3D shape at the cap and of the plane-tiled cube against
+  the oracle's step (2e-6, the FP32 bound), and a 12-step Gram solve on the
+  cube against the oracle's TT solve (1e-4).
 """
 import numpy as np
 import pytest
@@ -192,4 +196,42 @@ def test_one_step_with_plane_tiles(tt, zbc):
     assert st["direction_space_rounds"] == 1
     assert s.get_ranks() == (info["r1"], info["r2"])
     assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 1e-12
+    s.destroy()
+
+
+@pytest.mark.parametrize("case", ["3d_shape", "plane_tiles"])
+def test_fp32_one_step(tt, case):
+    if case == "3d_shape":
+        p = ti.clumps3d(n=12, n_groups=8, n_theta=8, n_phi=16, tol=1e-5, rank_cap=64, precision=ti.PREC_FP32)
+        Z, Th, Ph = ti.random_tt(p.M, 8, 16, 64, 16, seed=31, decay=0.9)
+    else:
+        p = ti.clumps3d(n=8, n_groups=4, n_theta=8, n_phi=16, tol=1e-5, rank_cap=48, precision=ti.PREC_FP32, T=0.3)
+        p.n_cells = (8, 8, 5)
+        rng = np.random.default_rng(9)
+        p.kappa0 = rng.uniform(0.3, 3.0, 320)
+        p.T_cell = np.full(320, 0.3)
+        p.bc = (ti.BC_INFLOW_PLANCK, 0, 0, 0, ti.BC_PERIODIC, ti.BC_PERIODIC)
+        p.bc_T = (1.0, 0.0, 0.0, 0.0, 0.0, 0.0)
+        Z, Th, Ph = ti.random_tt(p.M, 8, 16, 24, 16, seed=41, decay=0.8)
+    print(f"stencil: fp32 one step {case} M={p.M}", flush=True)
+    s = tt.Solver(p)
+    s.set_cores(Z, Th, Ph)
+    st = s.solve(1)
+    Zo, To, Po, info = ott.step(p, Z, Th, Ph)
+    assert st["direction_space_rounds"] == 1
+    r1, r2 = s.get_ranks()
+    assert abs(r1 - info["r1"]) <= 1 and abs(r2 - info["r2"]) <= 1
+    slack = 2 * p.tol * ((r1, r2) != (info["r1"], info["r2"]))
+    assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 2e-6 + slack
+    s.destroy()
+
+
+def test_fp32_gram_solve_matches_oracle_tt_solve(tt):
+    p = _cube(tol=1e-6, cap=40, precision=ti.PREC_FP32)
+    print(f"stencil: fp32 gram solve M={p.M}", flush=True)
+    s = tt.Solver(p, round_method=tt.TT_ROUND_GRAM)
+    st = s.solve(STEPS)
+    (Zo, To, Po), infos = ott.solve(p, STEPS)
+    assert st["direction_space_rounds"] > 0
+    assert rel(full(*s.get_cores()), full(Zo, To, Po)) < 1e-4
     s.destroy()
