@@ -43,6 +43,7 @@ constexpr int kF64Z = kMaxBC + 4;          // rank-1 value rows (read four at a 
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Gather blocks whose rows the row data holds: the identity and the shifted
 // copies (upwind, Rusanov), or up to kMaxBlocks with the HLL flux's
@@ -677,12 +678,15 @@ __global__ __launch_bounds__(64 * kStWaves) void k_stencil_f32(Geom g, OpDesc op
         const int j = i >> 7, c = i & 127;
         s_cf[i] = (j < ng && c < ldb) ? Cst[(size_t)j * ldb + c] : 0.0;
     }
-    const int c0 = 2 * l;
-    const bool colok = c0 < ldb;   // ldb is a multiple of 8, so c0 + 1 < ldb too
+    // four columns per lane: the two half-waves take two rows at a time
+    const int c0 = 4 * (l & 31), half = l >> 5;
+    const bool colok = c0 < ldb;   // ldb is a multiple of 8, so c0 + 3 < ldb too
     __syncthreads();
-    f32x2 cf32[kStNG];   // this lane's direction factors
+    f32x4 cf32[kStNG];   // this lane's direction factors
 #pragma unroll
-    for (int j = 0; j < kStNG; ++j) cf32[j] = (f32x2){(float)s_cf[j * 128 + c0], (float)s_cf[j * 128 + c0 + 1]};
+    for (int j = 0; j < kStNG; ++j)
+        cf32[j] = (f32x4){(float)s_cf[j * 128 + c0], (float)s_cf[j * 128 + c0 + 1], (float)s_cf[j * 128 + c0 + 2],
+                          (float)s_cf[j * 128 + c0 + 3]};
 
     // Rows are taken in Y's group-major order (grp N_X + cell), in batches of
     // 64.  When an x-y plane is a whole number of batches, a block's task is
@@ -780,27 +784,30 @@ __global__ __launch_bounds__(64 * kStWaves) void k_stencil_f32(Geom g, OpDesc op
             __builtin_amdgcn_wave_barrier();
             const int nrow = (int)((g.M - row0) < kStRows ? (g.M - row0) : kStRows);
             {
-                for (int i = 0; i < nrow; ++i) {
+                for (int i0 = 0; i0 < nrow; i0 += 2) {
+                    const int i = i0 + half;
+                    const bool rok = i < nrow && colok;
                     // all taps' loads first, then the sums
-                    f32x2 y[kStNG];
+                    f32x4 y[kStNG];
 #pragma unroll
                     for (int j = 0; j < kStNG; ++j) {
-                        y[j] = (f32x2){0.0f, 0.0f};
-                        if (j < ng) {
+                        y[j] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+                        if (j < ng && rok) {
                             const int src = s_nbr[w][j][i];
-                            if (src >= 0 && colok)
-                                y[j] = *reinterpret_cast<const f32x2*>(Y + (size_t)src * (ldb + kYPadF) + c0);
+                            if (src >= 0) y[j] = *reinterpret_cast<const f32x4*>(Y + (size_t)src * (ldb + kYPadF) + c0);
                         }
                     }
-                    f32x2 acc = (f32x2){0.0f, 0.0f};
+                    f32x4 acc = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                     for (int j = 0; j < kStNG; ++j) acc += cf32[j] * y[j];
-                    for (int qq = 0; qq < nq; ++qq) {
-                        const float z = (float)s_z[w][qq][i];
-                        acc += z * (f32x2){(float)s_R[qq * 128 + c0], (float)s_R[qq * 128 + c0 + 1]};
+                    if (rok) {
+                        for (int qq = 0; qq < nq; ++qq) {
+                            const float z = (float)s_z[w][qq][i];
+                            acc += z * (f32x4){(float)s_R[qq * 128 + c0], (float)s_R[qq * 128 + c0 + 1],
+                                               (float)s_R[qq * 128 + c0 + 2], (float)s_R[qq * 128 + c0 + 3]};
+                        }
+                        *reinterpret_cast<f32x4*>(B + (size_t)(row0 + i) * ldb + c0) = acc * (float)s_d[w][i];
                     }
-                    if (colok)
-                        *reinterpret_cast<f32x2*>(B + (size_t)(row0 + i) * ldb + c0) = acc * (float)s_d[w][i];
                 }
             }
             __builtin_amdgcn_wave_barrier();   // this batch's row data is read before the next overwrites it
