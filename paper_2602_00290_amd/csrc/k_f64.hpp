@@ -528,9 +528,31 @@ __global__ __launch_bounds__(64 * kStWaves) void k_stencil_f64(Geom g, OpDesc op
         const int q = i / ldb, c = i - q * ldb;
         s_R[q * 128 + c] = Cst[(size_t)(ng + q) * ldb + c];
     }
+    // tap slots: the centre 0, then (when the operator has both) x- in 1 and
+    // x+ in 2, the other gather blocks after them in order; gather block
+    // jslot[s] sits in slot s
+    int jxm = -1, jxp = -1;
+    for (int j = 1; j < ng; ++j)
+        if (op.gaxis[j] == 0) {
+            if (op.gdir[j] < 0) jxm = j;
+            else jxp = j;
+        }
+    const bool xwin = jxm > 0 && jxp > 0;
+    int jslot[kStNG], slotj[kStNG];
+#pragma unroll
+    for (int t = 0; t < kStNG; ++t) jslot[t] = t;
+    if (xwin) {
+        jslot[1] = jxm;
+        jslot[2] = jxp;
+        int t = 3;
+        for (int j = 1; j < ng; ++j)
+            if (j != jxm && j != jxp) jslot[t++] = j;
+    }
+#pragma unroll
+    for (int t = 0; t < kStNG; ++t) slotj[jslot[t]] = t;
     for (int i = tid; i < kStNG * 128; i += 64 * kStWaves) {
-        const int j = i >> 7, c = i & 127;
-        s_cf[i] = (j < ng && c < ldb) ? Cst[(size_t)j * ldb + c] : 0.0;
+        const int t = i >> 7, c = i & 127, j = jslot[t];
+        s_cf[i] = (t < ng && c < ldb) ? Cst[(size_t)j * ldb + c] : 0.0;
     }
     const int c0 = 2 * l;
     const bool colok = c0 < ldb;   // ldb is a multiple of 8, so c0 + 1 < ldb too
@@ -605,7 +627,7 @@ __global__ __launch_bounds__(64 * kStWaves) void k_stencil_f64(Geom g, OpDesc op
                             src = (int)kg + (jj - idx3[ax]) * st3[ax];
                         }
                     }
-                    s_nbr[w][j][l] = src;
+                    s_nbr[w][slotj[j]][l] = src;
                 }
                 double kap = 0.0;
                 if (ok) kap = rd.kfull ? rd.kfull[k] : rd.kappa0[cell] * rd.kscale[grp];
@@ -631,16 +653,42 @@ __global__ __launch_bounds__(64 * kStWaves) void k_stencil_f64(Geom g, OpDesc op
             // them in program order across this barrier
             __builtin_amdgcn_wave_barrier();
             const int nrow = (int)((g.M - row0) < kStRows ? (g.M - row0) : kStRows);
+            // the previous row's centre and x+ taps, and their rows (uniform):
+            // along an x-line the centre of row i is row i - 1's x+ tap and
+            // its x- tap is row i - 1's centre, so two of the loads are reused
+            f64x2 pc = (f64x2){0.0, 0.0}, pxp = pc;
+            int pc_row = -1, pxp_row = -1;
             for (int i = 0; i < nrow; ++i) {
                 f64x2 y[kStNG];
+                const int s0 = __builtin_amdgcn_readfirstlane(s_nbr[w][0][i]);
+                const int s1 = __builtin_amdgcn_readfirstlane(s_nbr[w][1][i]);
+                if (xwin && s0 >= 0 && s0 == pxp_row && s1 >= 0 && s1 == pc_row) {
+                    y[0] = pxp;
+                    y[1] = pc;
 #pragma unroll
-                for (int j = 0; j < kStNG; ++j) {
-                    y[j] = (f64x2){0.0, 0.0};
-                    if (j < ng) {
-                        const int src = s_nbr[w][j][i];
-                        if (src >= 0 && colok) y[j] = *reinterpret_cast<const f64x2*>(Y + (size_t)src * (ldb + kYPad) + c0);
+                    for (int j = 2; j < kStNG; ++j) {
+                        y[j] = (f64x2){0.0, 0.0};
+                        if (j < ng) {
+                            const int src = s_nbr[w][j][i];
+                            if (src >= 0 && colok)
+                                y[j] = *reinterpret_cast<const f64x2*>(Y + (size_t)src * (ldb + kYPad) + c0);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kStNG; ++j) {
+                        y[j] = (f64x2){0.0, 0.0};
+                        if (j < ng) {
+                            const int src = s_nbr[w][j][i];
+                            if (src >= 0 && colok)
+                                y[j] = *reinterpret_cast<const f64x2*>(Y + (size_t)src * (ldb + kYPad) + c0);
+                        }
                     }
                 }
+                pc = y[0];
+                pc_row = s0;
+                pxp = y[2];
+                pxp_row = xwin ? __builtin_amdgcn_readfirstlane(s_nbr[w][2][i]) : -1;
                 f64x2 acc = (f64x2){0.0, 0.0};
 #pragma unroll
                 for (int j = 0; j < kStNG; ++j) acc += *reinterpret_cast<const f64x2*>(s_cf + j * 128 + c0) * y[j];
