@@ -469,10 +469,21 @@ def mode_pmc_summary(args):
         vals = sorted(v for _, _, v in rows)[-4:]          # the large copies
         return nbytes / (sum(vals) / len(vals) * 1024.0)
 
+    def probe_steps(sub):
+        # the steps the probe timed at the cap (its JSON line on stdout); the
+        # dispatches before them include passes on which the kernel exits at once
+        try:
+            for line in open(os.path.join(d, sub + ".log")):
+                if line.startswith("{") and '"probe"' in line:
+                    return int(json.loads(line)["steps"])
+        except (OSError, ValueError, KeyError):
+            pass
+        return args.probe_steps
+
     def kernel(sub, counter):
         key = HEAD_KERNEL.replace(" ", "")
         rows = [v for _, k, v in _pmc_rows(os.path.join(d, sub), counter) if key in k.replace(" ", "")]
-        steady = rows[-args.probe_steps:]
+        steady = rows[-probe_steps(sub):]
         return sum(steady) / len(steady) * 1024.0, len(steady)
 
     def probe_grid(sub):
@@ -495,7 +506,7 @@ def mode_pmc_summary(args):
     out = {
         "kernel": HEAD_KERNEL,
         "workload": "clumps3d 64^3 FP64 at the rank cap (R1 = 450, k1 = 128, r1 = 64), direction-space "
-                    f"projection, last {args.probe_steps} steps of a probe",
+                    f"projection, last {nf} steps of a probe",
         "source_hash": kernel_source_hash(),
         "fetch_bytes": fetch * ff,
         "write_bytes": write * fw,
