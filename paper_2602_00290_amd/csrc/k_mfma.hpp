@@ -27,8 +27,9 @@ __global__ __launch_bounds__(256) void k_f64_to_f32(const double* __restrict__ i
 //                 row grp N_X + cell from Z's row cell G + grp, rows ldb + kYPad
 //                 apart (Gop = W, N_r1 x ldb)
 // A pass in direction space leaves B group-major: the gathered projection
-// then stands aside, and the output writes row grp N_X + cell of B V_r to
-// the state's row cell G + grp.
+// then stands aside, and the output forms the state's row cell G + grp from
+// B's row grp N_X + cell (gathered reads, contiguous writes: 4.55 -> 4.26 ms
+// on the 3D workload against the other way round).
 // Block: 128 rows x BN columns, 4 waves of 32 rows each; K staged in chunks of
 // 32 through LDS (row stride 33 floats: conflict-free column reads).
 template <int MODE, int BN>
@@ -65,6 +66,10 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(Geom g, OpDesc op, const 
             if (MODE == MODE_ANGLE) {
                 const int grp = (int)(k / NXc), cell = (int)(k - (long long)grp * NXc);
                 src = (long long)cell * g.G + grp;
+            } else if (MODE == MODE_OUTPUT && st->stencil) {
+                // state row k = cell G + grp reads B's group-major row grp N_X + cell
+                const int cell = (int)(k / g.G), grp = (int)(k - (long long)cell * g.G);
+                src = (long long)grp * NXc + cell;
             } else {
                 src = (MODE == MODE_OUTPUT || j == 0) ? k : neighbour_row(g, k, op.gaxis[j], op.gdir[j]);
             }
@@ -133,7 +138,6 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(Geom g, OpDesc op, const 
         }
     }
     // epilogue: D[i][j] of wave w sits in lane j + 32*((i/4)%2), register 4*(i/8) + i%4
-    const bool gm_out = MODE == MODE_OUTPUT && st->stencil;
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
         const int col = col0 + 32 * c + (l & 31);
@@ -154,12 +158,7 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(Geom g, OpDesc op, const 
                 for (int q = 0; q < op.n_r1; ++q) v += rowz[q][il] * g1[q];
                 v *= rowd[il];
             }
-            long long orow = k;
-            if (gm_out) {
-                const int grp = (int)(k / NXc), cell = (int)(k - (long long)grp * NXc);
-                orow = (long long)cell * g.G + grp;
-            }
-            Out[orow * ldo + col] = v;
+            Out[k * ldo + col] = v;
         }
     }
 }
