@@ -29,8 +29,9 @@ result with the oracle:
   (R1 = 450), QR route, against the oracle's step (1e-12, equal ranks);
 * one step on 8 x 8 x 5 cells, where an x-y plane is a whole number of
   64-row batches and each stencil block takes one batch position in up to 16
-  consecutive planes (five here, so most of its waves idle), with z periodic
-  or with inflow on both z faces: against the oracle's step (1e-12, equal
+  consecutive planes (five here, so most of its waves idle), with z periodic,
+  with inflow on both z faces, or with x periodic (the taps reused along an
+  x-line stop at its wrapped ends): against the oracle's step (1e-12, equal
   ranks);
 * FP32 data (Y = Z W on FP32 MFMA, FP32 Y and B, FP64 sums in the stencil):
   one step of the 3D shape at the cap and of the plane-tiled cube against
@@ -174,7 +175,7 @@ def test_one_step_of_the_3d_shape_at_the_cap(tt):
     s.destroy()
 
 
-@pytest.mark.parametrize("zbc", ["periodic", "inflow"])
+@pytest.mark.parametrize("zbc", ["periodic", "inflow", "x_periodic"])
 def test_one_step_with_plane_tiles(tt, zbc):
     p = ti.clumps3d(n=8, n_groups=4, n_theta=8, n_phi=16, tol=1e-9, rank_cap=48, precision=ti.PREC_FP64, T=0.3)
     p.n_cells = (8, 8, 5)
@@ -184,6 +185,11 @@ def test_one_step_with_plane_tiles(tt, zbc):
     if zbc == "periodic":
         p.bc = (ti.BC_INFLOW_PLANCK, 0, 0, 0, ti.BC_PERIODIC, ti.BC_PERIODIC)
         p.bc_T = (1.0, 0.0, 0.0, 0.0, 0.0, 0.0)
+    elif zbc == "x_periodic":
+        # x-lines wrap: the stencil's reuse of the previous row's taps must
+        # stop at each line's ends
+        p.bc = (ti.BC_PERIODIC, ti.BC_PERIODIC, ti.BC_INFLOW_PLANCK, 0, 0, ti.BC_INFLOW_PLANCK)
+        p.bc_T = (0.0, 0.0, 1.0, 0.0, 0.0, 0.6)
     else:
         p.bc = (ti.BC_INFLOW_PLANCK, 0, 0, 0, ti.BC_INFLOW_PLANCK, ti.BC_INFLOW_PLANCK)
         p.bc_T = (1.0, 0.0, 0.0, 0.0, 0.7, 0.4)
