@@ -352,9 +352,11 @@ def mode_probe(args):
     import torch
     import paper_2602_00290_amd as tt
     import tt_inputs as ti
-    if args.probe_workload == "clumps3d_fp64":
-        # the headline: ranks brought to the cap, then --probe-steps steps
-        prob = ti.clumps3d(precision=ti.PREC_FP64)
+    if args.probe_workload in ("clumps3d_fp64", "clumps3d_fp32"):
+        # the headline (or the same in FP32): ranks brought to the cap, then
+        # --probe-steps steps
+        fp64 = args.probe_workload == "clumps3d_fp64"
+        prob = ti.clumps3d(precision=ti.PREC_FP64 if fp64 else ti.PREC_FP32)
         s = tt.Solver(prob, round_method=tt.TT_ROUND_GRAM)
         warm = 0
         while warm < 48:
@@ -768,9 +770,10 @@ def main():
     ap.add_argument("--probe-steps", type=int, default=64)
     ap.add_argument("--probe-workload", default="plane2d",
                     choices=["plane2d", "clumps3d", "clumps3d_fp64", "plane2d_coupled", "plane2d_rusanov_scatter",
-                             "plane2d_randomized", "plane2d_fp64_qr"],
+                             "plane2d_randomized", "plane2d_fp64_qr", "clumps3d_fp32"],
                     help="probe workload: plane2d (FP32), clumps3d (64^3 cells, 64 groups, split BF16), "
                          "clumps3d_fp64 (the headline: FP64, Gram rounding, ranks at the cap first), "
+                         "clumps3d_fp32 (the same in FP32), "
                          "plane2d_coupled (plane2d with the coupled medium temperature, heat capacity 8 a), "
                          "plane2d_rusanov_scatter (plane2d with the Rusanov flux and scattering kappa_s = kappa_a), "
                          "plane2d_randomized (plane2d with randomized rounding, sketch ranks = ranks + 4), "
