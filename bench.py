@@ -798,7 +798,7 @@ def main():
     ap.add_argument("--served-slots", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     if args.mode == "pmc-summary":
         return mode_pmc_summary(args)

@@ -200,7 +200,7 @@ tt_status validate(const tt_problem* p) {
         if (!(p->hll_beta > 0.0) || !std::isfinite(p->hll_beta))
             return fail(TT_ERR_INVALID_ARG, "hll_beta must be finite and > 0");
         if (p->precision != TT_PREC_FP64)
-            return fail(TT_ERR_INVALID_ARG, "the HLL flux needs FP64 data (TT_PREC_FP64) in this build");
+            return fail(TT_ERR_INVALID_ARG, "the HLL flux needs FP64 data (TT_PREC_FP64)");
         if (p->kappa_s_full || p->heat_capacity > 0.0)
             return fail(TT_ERR_INVALID_ARG, "the HLL flux is provided without scattering or a coupled temperature");
     }
@@ -242,7 +242,7 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
     P.k1cap = std::min(P.R1cap, P.nt * P.k2cap);
     P.ldzcap = ld_for_rank(P.r1cap);
     P.ldbcap = ld_for_rank(P.k1cap);
-    if (P.k1cap > 128) return fail(TT_ERR_INVALID_ARG, "projected first-core rank above 128 is not supported by this build");
+    if (P.k1cap > 128) return fail(TT_ERR_INVALID_ARG, "projected first-core rank above 128 is not supported");
     P.KP = P.k1cap <= 64 ? 64 : 128;
     {
         // fixed LDS layout of the SVD chain: 64 x 64 matrices (ld 65) and a
