@@ -34,9 +34,10 @@ result with the oracle:
   x-line stop at its wrapped ends): against the oracle's step (1e-12, equal
   ranks);
 * FP32 data (Y = Z W on FP32 MFMA, FP32 Y and B, FP64 sums in the stencil):
-  one step of the 3D shape at the cap and of the plane-tiled cube against
-  the oracle's step (2e-6, the FP32 bound), and a 12-step Gram solve on the
-  cube against the oracle's TT solve (1e-4).
+  one step of the 3D shape at the cap (Gram and Householder TSQR rounding)
+  and of the plane-tiled cube against the oracle's step (2e-6, the FP32
+  bound), and a 12-step Gram solve on the cube against the oracle's TT solve
+  (1e-4).
 """
 import numpy as np
 import pytest
@@ -205,9 +206,9 @@ def test_one_step_with_plane_tiles(tt, zbc):
     s.destroy()
 
 
-@pytest.mark.parametrize("case", ["3d_shape", "plane_tiles"])
+@pytest.mark.parametrize("case", ["3d_shape", "3d_shape_qr", "plane_tiles"])
 def test_fp32_one_step(tt, case):
-    if case == "3d_shape":
+    if case.startswith("3d_shape"):
         p = ti.clumps3d(n=12, n_groups=8, n_theta=8, n_phi=16, tol=1e-5, rank_cap=64, precision=ti.PREC_FP32)
         Z, Th, Ph = ti.random_tt(p.M, 8, 16, 64, 16, seed=31, decay=0.9)
     else:
@@ -220,7 +221,7 @@ def test_fp32_one_step(tt, case):
         p.bc_T = (1.0, 0.0, 0.0, 0.0, 0.0, 0.0)
         Z, Th, Ph = ti.random_tt(p.M, 8, 16, 24, 16, seed=41, decay=0.8)
     print(f"stencil: fp32 one step {case} M={p.M}", flush=True)
-    s = tt.Solver(p)
+    s = tt.Solver(p, round_method=tt.TT_ROUND_QR) if case.endswith("_qr") else tt.Solver(p)
     s.set_cores(Z, Th, Ph)
     st = s.solve(1)
     Zo, To, Po, info = ott.step(p, Z, Th, Ph)
