@@ -67,6 +67,8 @@ constexpr int kTuneMaxBlocks = 1024;
 // longer chunks mean fewer column steps per block over the tall first core,
 // and 24 still fits two blocks per CU (122 VGPRs; 32 takes 154, one block).
 constexpr int kTsqrBrLeaf128 = 24;
+// and in the 64-column leaf (chunks of 8 x this many rows)
+constexpr int kTsqrBrLeaf64 = 24;
 // Tree levels of the 64- and 128-column tiles (few blocks, each one chain of
 // column steps) take 32 rows per thread; the 16-column tile takes 16.
 constexpr int kTsqrBrTree = 32;
@@ -266,7 +268,7 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
                                  : p->round_method;
         P.KPt = (method_q == TT_ROUND_QR && P.k1cap <= 16) ? 16 : P.KP;
     }
-    P.chunk = P.KPt == 16 ? 32 * 16 : (P.KP == 64 ? 8 * 16 : 4 * kTsqrBrLeaf128);
+    P.chunk = P.KPt == 16 ? 32 * 16 : (P.KP == 64 ? 8 * kTsqrBrLeaf64 : 4 * kTsqrBrLeaf128);
     P.chunk_t = P.KPt == 16 ? 32 * 16 : (P.KP == 64 ? 8 * kTsqrBrTree : 4 * kTsqrBrTree);
     P.elem = p->precision == TT_PREC_FP64 ? 8 : 4;
     {
@@ -1120,7 +1122,7 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
                                        P.levN[L], P.levRows[L], (const DevState*)st, out);
             } else if (P.KP == 64) {
                 if (L == 0)
-                    hipLaunchKernelGGL((k_tsqr<T, 64, 8, 16>), dim3(P.levP[L]), dim3(512), 0, s, (const T*)B, 0, 1, 0,
+                    hipLaunchKernelGGL((k_tsqr<T, 64, 8, kTsqrBrLeaf64>), dim3(P.levP[L]), dim3(512), 0, s, (const T*)B, 0, 1, 0,
                                        P.levN[L], P.levRows[L], (const DevState*)st, out);
                 else
                     hipLaunchKernelGGL((k_tsqr<double, 64, 8, kTsqrBrTree>), dim3(P.levP[L]), dim3(512), 0, s, in, 64, 0, P.k1cap,

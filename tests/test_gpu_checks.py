@@ -148,8 +148,8 @@ def test_tsqr_16_column_cores_with_a_tree_level(tt):
 
 def test_tsqr_64_column_cores_with_three_tree_levels(tt):
     # 2D, 44 x 44 cells x 8 groups, 8 x 8 directions: k1 = 64, M = 15488 rows
-    # in 31 leaf blocks of four 128-row chunks (the last holds one), then tree
-    # levels of eight blocks (the last with 192 rows), two and one
+    # in 21 leaf blocks of four 192-row chunks (the last holds 128 rows), then
+    # tree levels of six blocks (the last with 64 rows), two and one
     p = _plane(n=(44, 44), G=8, nt=8, nphi=8, tol=1e-7, cap=32, seed=5)
     print("tsqr 64-column two levels", flush=True)
     s = tt.Solver(p, round_method=tt.TT_ROUND_QR)
@@ -214,7 +214,7 @@ def test_tsqr_rounding_at_tol_1e14_matches_the_dense_march(tt):
 
 def test_plane2d_full_size_one_step_fp64(tt):
     # the 2D workload at full size in FP64 (Householder TSQR over 524288 rows:
-    # 512 leaf blocks and five tree levels), one step from a rank-(32, 8) state
+    # 456 leaf blocks and five tree levels), one step from a rank-(32, 8) state
     p = ti.plane2d(precision=ti.PREC_FP64)
     print("plane2d full size fp64", flush=True)
     s = tt.Solver(p, round_method=tt.TT_ROUND_QR)
