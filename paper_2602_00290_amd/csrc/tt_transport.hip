@@ -69,9 +69,10 @@ constexpr int kTuneMaxBlocks = 1024;
 constexpr int kTsqrBrLeaf128 = 24;
 // and in the 64-column leaf (chunks of 8 x this many rows)
 constexpr int kTsqrBrLeaf64 = 24;
-// Tree levels of the 64- and 128-column tiles (few blocks, each one chain of
-// column steps) take 32 rows per thread; the 16-column tile takes 16.
-constexpr int kTsqrBrTree = 32;
+// Tree levels of the 64- and 128-column tiles have few blocks, each one chain
+// of column steps: they take 1024 threads (16 and 8 row groups) of 16 rows,
+// so a column step is short (plane2d: 83 -> 66 us per level against 512
+// threads of 32 rows); the 16-column tile takes 512 threads of 16 rows.
 // Leaf blocks of the TSQR at most: two resident blocks per CU on 256 CUs,
 // so the whole first core is one wave of blocks and the tree starts from as
 // few R factors as that allows.
@@ -269,7 +270,7 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         P.KPt = (method_q == TT_ROUND_QR && P.k1cap <= 16) ? 16 : P.KP;
     }
     P.chunk = P.KPt == 16 ? 32 * 16 : (P.KP == 64 ? 8 * kTsqrBrLeaf64 : 4 * kTsqrBrLeaf128);
-    P.chunk_t = P.KPt == 16 ? 32 * 16 : (P.KP == 64 ? 8 * kTsqrBrTree : 4 * kTsqrBrTree);
+    P.chunk_t = P.KPt == 16 ? 32 * 16 : (P.KP == 64 ? 16 * 16 : 8 * 16);
     P.elem = p->precision == TT_PREC_FP64 ? 8 : 4;
     {
         const int method = p->round_method == TT_ROUND_AUTO
@@ -1125,14 +1126,14 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
                     hipLaunchKernelGGL((k_tsqr<T, 64, 8, kTsqrBrLeaf64>), dim3(P.levP[L]), dim3(512), 0, s, (const T*)B, 0, 1, 0,
                                        P.levN[L], P.levRows[L], (const DevState*)st, out);
                 else
-                    hipLaunchKernelGGL((k_tsqr<double, 64, 8, kTsqrBrTree>), dim3(P.levP[L]), dim3(512), 0, s, in, 64, 0, P.k1cap,
+                    hipLaunchKernelGGL((k_tsqr<double, 64, 16, 16>), dim3(P.levP[L]), dim3(1024), 0, s, in, 64, 0, P.k1cap,
                                        P.levN[L], P.levRows[L], (const DevState*)st, out);
             } else {
                 if (L == 0)
                     hipLaunchKernelGGL((k_tsqr<T, 128, 4, kTsqrBrLeaf128>), dim3(P.levP[L]), dim3(512), 0, s, (const T*)B, 0, 1, 0,
                                        P.levN[L], P.levRows[L], (const DevState*)st, out);
                 else
-                    hipLaunchKernelGGL((k_tsqr<double, 128, 4, kTsqrBrTree>), dim3(P.levP[L]), dim3(512), 0, s, in, 128, 0, P.k1cap,
+                    hipLaunchKernelGGL((k_tsqr<double, 128, 8, 16>), dim3(P.levP[L]), dim3(1024), 0, s, in, 128, 0, P.k1cap,
                                        P.levN[L], P.levRows[L], (const DevState*)st, out);
             }
             h->ev_end(e, s);
