@@ -197,16 +197,6 @@ __global__ __launch_bounds__(256) void k_gather_gemm(Geom g, OpDesc op, const De
     }
 }
 
-// Value of x in another lane of the same 16-lane row, chosen by the DPP
-// control CTRL (both halves of the double moved by one DPP move each).
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double x) {
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
-}
-
 // ---------------------------------------------------------------------------
 // Householder TSQR: R factor of a tall matrix
 // ---------------------------------------------------------------------------
@@ -258,12 +248,8 @@ __device__ __forceinline__ void tsqr_body(const TS* __restrict__ A, int lda_stat
     // then shuffles; every pairing adds the same two values, so every lane
     // ends with the same bits
     auto colsum = [&](double x) __attribute__((always_inline)) {
-        if constexpr (NG >= 2) x += dpp_f64<0xB1>(x);    // quad_perm [1, 0, 3, 2]
-        if constexpr (NG >= 4) x += dpp_f64<0x4E>(x);    // quad_perm [2, 3, 0, 1]
-        if constexpr (NG >= 8) x += dpp_f64<0x141>(x);   // row_half_mirror
-        if constexpr (NG >= 16) x += dpp_f64<0x140>(x);  // row_mirror
-#pragma unroll
-        for (int o = 16; o < NG; o <<= 1) x += __shfl_xor(x, o, NG);
+        x = group_sum(x, NG < 32 ? NG : 32);
+        if constexpr (NG == 64) x += __shfl_xor(x, 32, 64);
         return x;
     };
     // sums of BR terms in four interleaved chains
