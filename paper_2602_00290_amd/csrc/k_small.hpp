@@ -1155,11 +1155,11 @@ __device__ __forceinline__ void svd_chain_body(const Geom& g, DevState* st, cons
         // J = R_B W has non-zero rows only below k1 (R_B is k1 x k1 upper
         // triangular): for k1 <= 16 (32) the rotations run over 16 (32) rows
         if (FAST && k1 <= 16)
-            sw1 = block_jacobi_1s_fixed<2, 8, 2>(J, ld, k1, W, ld, &sh_flag, red);
+            sw1 = block_jacobi_1s_fixed<1, 16, 1>(J, ld, k1, W, ld, &sh_flag, red);
         else if (FAST && k1 <= 32)
-            sw1 = block_jacobi_1s_fixed<4, 8, 4>(J, ld, k1, W, ld, &sh_flag, red);
+            sw1 = block_jacobi_1s_fixed<2, 16, 2>(J, ld, k1, W, ld, &sh_flag, red);
         else if (FAST)
-            sw1 = block_jacobi_1s_fixed<8, 8, 8>(J, ld, k1, W, ld, &sh_flag, red);
+            sw1 = block_jacobi_1s_fixed<4, 16, 4>(J, ld, k1, W, ld, &sh_flag, red);
         else
             sw1 = block_jacobi_1s(J, ld, k1, k1, W, ld, nrm, &sh_flag, red);
         tph[2] = wall_clock64();
