@@ -69,9 +69,14 @@ constexpr int kTuneMaxBlocks = 1024;
 constexpr int kTsqrBrLeaf128 = 24;
 // and in the 64-column leaf (chunks of 8 x this many rows)
 constexpr int kTsqrBrLeaf64 = 24;
+// Rows per thread in the 64-column tree levels (1024 threads, blocks of 16 x
+// this many rows): 320-row blocks reduce five R factors each, so plane2d
+// takes four tree levels of 73 us instead of five of 66 us with 16 rows (24
+// rows: four of 80 us)
+constexpr int kTsqrBrTree64 = 20;
 // Tree levels of the 64- and 128-column tiles have few blocks, each one chain
-// of column steps: they take 1024 threads (16 and 8 row groups) of 16 rows,
-// so a column step is short (plane2d: 83 -> 66 us per level against 512
+// of column steps: they take 1024 threads (16 and 8 row groups) of 20 and 16
+// rows, so a column step is short (plane2d: 83 -> 66 us per level against 512
 // threads of 32 rows); the 16-column tile takes 512 threads of 16 rows.
 // Leaf blocks of the TSQR at most: two resident blocks per CU on 256 CUs,
 // so the whole first core is one wave of blocks and the tree starts from as
@@ -270,7 +275,7 @@ tt_status make_plan_impl(const tt_problem* p, Plan& P, bool allow_fused) {
         P.KPt = (method_q == TT_ROUND_QR && P.k1cap <= 16) ? 16 : P.KP;
     }
     P.chunk = P.KPt == 16 ? 32 * 16 : (P.KP == 64 ? 8 * kTsqrBrLeaf64 : 4 * kTsqrBrLeaf128);
-    P.chunk_t = P.KPt == 16 ? 32 * 16 : (P.KP == 64 ? 16 * 16 : 8 * 16);
+    P.chunk_t = P.KPt == 16 ? 32 * 16 : (P.KP == 64 ? 16 * kTsqrBrTree64 : 8 * 16);
     P.elem = p->precision == TT_PREC_FP64 ? 8 : 4;
     {
         const int method = p->round_method == TT_ROUND_AUTO
@@ -1126,7 +1131,7 @@ tt_status round_impl(tt_handle* h, int opkind, double tol, int cap, hipStream_t 
                     hipLaunchKernelGGL((k_tsqr<T, 64, 8, kTsqrBrLeaf64>), dim3(P.levP[L]), dim3(512), 0, s, (const T*)B, 0, 1, 0,
                                        P.levN[L], P.levRows[L], (const DevState*)st, out);
                 else
-                    hipLaunchKernelGGL((k_tsqr<double, 64, 16, 16>), dim3(P.levP[L]), dim3(1024), 0, s, in, 64, 0, P.k1cap,
+                    hipLaunchKernelGGL((k_tsqr<double, 64, 16, kTsqrBrTree64>), dim3(P.levP[L]), dim3(1024), 0, s, in, 64, 0, P.k1cap,
                                        P.levN[L], P.levRows[L], (const DevState*)st, out);
             } else {
                 if (L == 0)

@@ -17,7 +17,7 @@ against the CPU oracle.
   oracle at the FP64 bounds (1e-12 per step, 1e-10 per solve); and at tol
   1e-14 a 2D solve with TSQR rounding equals the dense march to 1e-10 (Gram
   rounding to 1e-5).
-* Full sizes: the 128 x 128 x 32-group workload in FP64 (six TSQR levels),
+* Full sizes: the 128 x 128 x 32-group workload in FP64 (five TSQR levels),
   and the 3D workload's angular shape (8 x 16 directions, rank 64, so the
   sum has R1 = 450 and the projected core k1 = 128) on 24^3 cells x 16
   groups in FP64, FP32 and split BF16 at their bounds (1e-12, 2e-6, 5e-5 per
@@ -147,11 +147,12 @@ def test_tsqr_16_column_cores_with_a_tree_level(tt):
 
 
 def test_tsqr_64_column_cores_with_three_tree_levels(tt):
-    # 2D, 44 x 44 cells x 8 groups, 8 x 8 directions: k1 = 64, M = 15488 rows
-    # in 21 leaf blocks of four 192-row chunks (the last holds 128 rows), then
-    # tree levels of six blocks (the last with 64 rows), two and one
-    p = _plane(n=(44, 44), G=8, nt=8, nphi=8, tol=1e-7, cap=32, seed=5)
-    print("tsqr 64-column two levels", flush=True)
+    # 2D, 50 x 50 cells x 8 groups, 8 x 8 directions: k1 = 64, M = 20000 rows
+    # in 27 leaf blocks of four 192-row chunks (the last holds 32 rows), then
+    # tree levels of 320-row blocks: six (the last with 128 rows), two (the
+    # last with 64 rows) and one
+    p = _plane(n=(50, 50), G=8, nt=8, nphi=8, tol=1e-7, cap=32, seed=5)
+    print("tsqr 64-column three tree levels", flush=True)
     s = tt.Solver(p, round_method=tt.TT_ROUND_QR)
     Z, Th, Ph = ti.random_tt(p.M, 8, 8, 20, 8, seed=8, decay=0.75)
     s.set_cores(Z, Th, Ph)
@@ -214,7 +215,7 @@ def test_tsqr_rounding_at_tol_1e14_matches_the_dense_march(tt):
 
 def test_plane2d_full_size_one_step_fp64(tt):
     # the 2D workload at full size in FP64 (Householder TSQR over 524288 rows:
-    # 456 leaf blocks and five tree levels), one step from a rank-(32, 8) state
+    # 456 leaf blocks and four tree levels), one step from a rank-(32, 8) state
     p = ti.plane2d(precision=ti.PREC_FP64)
     print("plane2d full size fp64", flush=True)
     s = tt.Solver(p, round_method=tt.TT_ROUND_QR)
