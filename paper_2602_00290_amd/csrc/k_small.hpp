@@ -236,11 +236,15 @@ __device__ __forceinline__ void jacobi_rotation(double a, double b, double g, do
 }
 
 // Pair (a, b) of round `round` in the round-robin tournament over np players
-// (player 0 fixed, the others rotating); a < b.
+// (player 0 fixed, the others rotating); a < b.  For 0 <= pp < np and
+// 0 <= round < np - 1 the rotated index is below 2 (np - 1), so one
+// conditional subtraction takes it mod np - 1 (an integer division by the
+// run-time np costs tens of instructions on the round's critical path).
 __device__ __forceinline__ void tournament_pair(int pp, int round, int np, int* a, int* b) {
-    const int pa = pp, pb = np - 1 - pp;
-    int x = pa == 0 ? 0 : ((pa - 1 + round) % (np - 1)) + 1;
-    int y = pb == 0 ? 0 : ((pb - 1 + round) % (np - 1)) + 1;
+    const int pa = pp, pb = np - 1 - pp, m = np - 1;
+    int x = pa - 1 + round, y = pb - 1 + round;
+    x = pa == 0 ? 0 : (x >= m ? x - m : x) + 1;
+    y = pb == 0 ? 0 : (y >= m ? y - m : y) + 1;
     if (x > y) { const int t = x; x = y; y = t; }
     *a = x;
     *b = y;
@@ -380,7 +384,9 @@ __device__ __forceinline__ int block_jacobi_1s_fixed(double* A, int lda, int n, 
                     al = group_sum(al, GS);
                     be = group_sum(be, GS);
                     ga = group_sum(ga, GS);
-                    if (fabs(ga) > 1e-15 * sqrt(al * be) && fabs(ga) > floor_abs) {
+                    // |ga| > 1e-15 sqrt(al be), squared (no FP64 square root on
+                    // the round's critical path)
+                    if (ga * ga > 1e-30 * (al * be) && fabs(ga) > floor_abs) {
                         double c, s, t;
                         jacobi_rotation(al, be, ga, &c, &s, &t);
 #pragma unroll
