@@ -508,7 +508,8 @@ __device__ __forceinline__ int block_jacobi_sym64(double* S, int ld, double* W, 
                 tournament_pair(threadIdx.x, round, np, &a, &b);
                 double c = 1.0, sn = 0.0;
                 const double app = S[a + (size_t)a * ld], aqq = S[b + (size_t)b * ld], apq = S[a + (size_t)b * ld];
-                if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs) {
+                // |apq| > 1e-15 sqrt(|app aqq|), squared
+                if (apq * apq > 1e-30 * fabs(app * aqq) && fabs(apq) > floor_abs) {
                     double t;
                     jacobi_rotation(app, aqq, apq, &c, &sn, &t);
                     if (fabs(t) > tconv) *flag = 1;
